@@ -1,0 +1,359 @@
+"""Pins for the FP64 oracle: closed forms, textbook cases, invariants and brute force.
+
+None of these re-types the oracle's own formulas: each compares it with an
+independent statement of the same physics (a closed form, scipy's rotations,
+the textbook double pendulum, energy and power identities, finite differences
+of kinematics, or a different algorithm).
+"""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+from scipy.spatial.transform import Rotation
+
+import oracle as O
+import workloads as W
+from oracle import euler_lagrange as EL
+from oracle import paper_vectorized as PV
+from tests._helpers import base_rotation, com_world, inertia_matrix, rel_err, retract
+
+G = 9.81
+
+
+def _single_body(seed, floating=False, com_zero=False):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    d = W.random_tree([-1], floating, seed)
+    d.origin[0, :9] = Rotation.random(random_state=seed).as_matrix().reshape(-1)
+    if com_zero:
+        d.com[0] = 0.0
+    return d, rng
+
+
+# ---------------------------------------------------------------- closed forms
+@pytest.mark.parametrize("seed", [0, 1, 2, 3])
+def test_single_pendulum_closed_form(seed):
+    """One revolute joint: M = a^T Ic a + m |a x c|^2, h = g(q) = dV/dq, qdd = (tau - g)/M."""
+    d, rng = _single_body(seed)
+    a = d.axis[0] / np.linalg.norm(d.axis[0])
+    c, m = d.com[0], d.mass[0]
+    Ic = inertia_matrix(d, 0)
+    Rf = d.origin[0, :9].reshape(3, 3)
+    B = 16
+    q = rng.uniform(-np.pi, np.pi, size=(B, 1))
+    qd = rng.normal(size=(B, 1))
+    tau = rng.normal(0, 5, size=(B, 1))
+    M_ref = a @ Ic @ a + m * np.dot(np.cross(a, c), np.cross(a, c))
+    Rq = Rotation.from_rotvec(a[None, :] * q).as_matrix()
+    lever = np.einsum("bij,j->bi", Rq, c)
+    dVdq = -m * np.einsum("i,ij,bj->b", d.gravity, Rf, np.cross(a[None, :], lever))
+    assert np.allclose(O.crba(d, q)[:, 0, 0], M_ref, rtol=1e-13, atol=0)
+    assert np.allclose(O.rnea(d, q, qd)[:, 0], dVdq, rtol=1e-12, atol=1e-13)
+    for method in (O.METHOD_LLT, O.METHOD_LTL, O.METHOD_ABA):
+        qdd = O.fwd_dyn(d, q, qd, tau, method)
+        assert np.allclose(qdd[:, 0], (tau[:, 0] - dVdq) / M_ref, rtol=1e-12, atol=1e-13)
+
+
+def _spong_double_pendulum(m1, m2, l1, lc1, lc2, I1, I2):
+    parent = np.array([-1, 0], dtype=np.int32)
+    d = W.TreeDesc(
+        parent=parent, joint_type=np.zeros(2, dtype=np.int32),
+        axis=np.array([[0.0, 0, 1], [0, 0, 1]]),
+        origin=np.array([[1.0, 0, 0, 0, 1, 0, 0, 0, 1, 0, 0, 0], [1.0, 0, 0, 0, 1, 0, 0, 0, 1, l1, 0, 0]]),
+        mass=np.array([m1, m2]), com=np.array([[lc1, 0, 0], [lc2, 0, 0]]),
+        inertia=np.array([[0.7 * I1, 0.9 * I1, I1, 0, 0, 0], [0.6 * I2, 0.8 * I2, I2, 0, 0, 0]]),
+        gravity=np.array([0.0, -G, 0.0]), name="spong")
+    return d
+
+
+def test_planar_double_pendulum_textbook():
+    """Spong, Robot Modeling and Control, planar elbow manipulator: M, C, g in closed form."""
+    m1, m2, l1, lc1, lc2, I1, I2 = 1.3, 0.8, 0.9, 0.4, 0.35, 0.11, 0.07
+    d = _spong_double_pendulum(m1, m2, l1, lc1, lc2, I1, I2)
+    rng = np.random.Generator(np.random.PCG64(7))
+    B = 32
+    q = rng.uniform(-np.pi, np.pi, size=(B, 2))
+    qd = rng.normal(size=(B, 2))
+    qdd = rng.normal(size=(B, 2))
+    c2 = np.cos(q[:, 1])
+    d11 = m1 * lc1 ** 2 + m2 * (l1 ** 2 + lc2 ** 2 + 2 * l1 * lc2 * c2) + I1 + I2
+    d12 = m2 * (lc2 ** 2 + l1 * lc2 * c2) + I2
+    d22 = np.full(B, m2 * lc2 ** 2 + I2)
+    h = -m2 * l1 * lc2 * np.sin(q[:, 1])
+    phi1 = (m1 * lc1 + m2 * l1) * G * np.cos(q[:, 0]) + m2 * lc2 * G * np.cos(q[:, 0] + q[:, 1])
+    phi2 = m2 * lc2 * G * np.cos(q[:, 0] + q[:, 1])
+    tau1 = d11 * qdd[:, 0] + d12 * qdd[:, 1] + 2 * h * qd[:, 0] * qd[:, 1] + h * qd[:, 1] ** 2 + phi1
+    tau2 = d12 * qdd[:, 0] + d22 * qdd[:, 1] - h * qd[:, 0] ** 2 + phi2
+    M = O.crba(d, q)
+    assert np.allclose(M[:, 0, 0], d11, rtol=1e-13) and np.allclose(M[:, 0, 1], d12, rtol=1e-13)
+    assert np.allclose(M[:, 1, 0], d12, rtol=1e-13) and np.allclose(M[:, 1, 1], d22, rtol=1e-13)
+    tau = O.rnea(d, q, qd, qdd)
+    assert np.allclose(tau, np.stack([tau1, tau2], 1), rtol=1e-12, atol=1e-12)
+
+
+@pytest.mark.parametrize("seed", [11, 12, 13])
+def test_euler_lagrange_random_2link(seed):
+    """Random 3-D 2-link chain: M and h from symbolic differentiation of the Lagrangian."""
+    d = W.random_tree([-1, 0], False, seed)
+    d.origin[1, :9] = Rotation.random(random_state=seed).as_matrix().reshape(-1)
+    M_fn, h_fn = EL.chain_dynamics(d)
+    st = W.states(d, 6, seed + 100)
+    M = O.crba(d, st.q)
+    h = O.rnea(d, st.q, st.qd)
+    for b in range(6):
+        assert np.allclose(M[b], M_fn(st.q[b], st.qd[b]), rtol=1e-12, atol=1e-14)
+        assert np.allclose(h[b], h_fn(st.q[b], st.qd[b]), rtol=1e-11, atol=1e-13)
+
+
+def test_free_body_newton_euler():
+    """A free rigid body with its origin at the CoM obeys Newton and Euler in body axes."""
+    d, rng = _single_body(21, floating=True, com_zero=True)
+    B = 16
+    st = W.states(d, B, 5)
+    m = d.mass[0]
+    Ic = inertia_matrix(d, 0)
+    v, w = st.qd[:, 0:3], st.qd[:, 3:6]
+    f, n = st.tau[:, 0:3], st.tau[:, 3:6]
+    R = base_rotation(st.q[:, 3:7])
+    g_body = np.einsum("bji,j->bi", R, d.gravity)
+    vdot = f / m + g_body - np.cross(w, v)
+    wdot = np.linalg.solve(Ic[None], (n - np.cross(w, np.einsum("ij,bj->bi", Ic, w)))[..., None])[..., 0]
+    for method in (O.METHOD_LLT, O.METHOD_LTL, O.METHOD_ABA):
+        qdd = O.fwd_dyn(d, st.q, st.qd, st.tau, method)
+        assert rel_err(qdd, np.concatenate([vdot, wdot], 1)) < 1e-12
+
+
+def test_free_body_mass_matrix_offset_com():
+    """Body-twist mass matrix of a free body: [[m 1, m [c]x^T], [m [c]x, Ic + m [c]x [c]x^T]]."""
+    d, _ = _single_body(22, floating=True)
+    m, c = d.mass[0], d.com[0]
+    C = np.array([[0, -c[2], c[1]], [c[2], 0, -c[0]], [-c[1], c[0], 0]])
+    ref = np.block([[m * np.eye(3), m * C.T], [m * C, inertia_matrix(d, 0) + m * C @ C.T]])
+    st = W.states(d, 4, 3)
+    assert np.allclose(O.crba(d, st.q), ref[None], rtol=1e-13, atol=1e-15)
+
+
+def test_tree_free_fall():
+    """At rest with no torques the humanoid falls as one body: joints stay, base accel = R^T g."""
+    d = W.humanoid()
+    st = W.states(d, 32, 9)
+    zero = np.zeros_like(st.qd)
+    R = base_rotation(st.q[:, 3:7])
+    ref = np.zeros_like(st.qd)
+    ref[:, 0:3] = np.einsum("bji,j->bi", R, d.gravity)
+    for method in (O.METHOD_LLT, O.METHOD_LTL, O.METHOD_ABA):
+        qdd = O.fwd_dyn(d, st.q, zero, zero, method)
+        assert np.abs(qdd - ref).max() < 1e-11
+
+
+# ---------------------------------------------------------------- invariants
+@pytest.mark.parametrize("name", ["chain7", "humanoid30"])
+def test_mass_matrix_symmetric_positive_definite(name):
+    d = W.chain(7) if name == "chain7" else W.humanoid()
+    st = W.states(d, 128, 1)
+    M = O.crba(d, st.q)
+    assert np.abs(M - np.swapaxes(M, 1, 2)).max() <= 1e-13 * np.abs(M).max()
+    assert np.linalg.eigvalsh(M).min() > 0
+    np.linalg.cholesky(M)
+
+
+@pytest.mark.parametrize("name", ["chain7", "humanoid30"])
+def test_kinetic_energy_from_kinematics(name):
+    """1/2 qd^T M qd equals the kinetic energy of body velocities taken from FK alone."""
+    d = W.chain(7) if name == "chain7" else W.humanoid()
+    st = W.states(d, 16, 2)
+    eps = 1e-6
+    Tp = O.fk(d, retract(d, st.q, st.qd, eps))
+    Tm = O.fk(d, retract(d, st.q, st.qd, -eps))
+    T0 = O.fk(d, st.q)
+    cdot = (com_world(d, Tp) - com_world(d, Tm)) / (2 * eps)
+    Rdot = (Tp[..., :3] - Tm[..., :3]) / (2 * eps)
+    Wx = np.einsum("bnij,bnkj->bnik", Rdot, T0[..., :3])
+    w = np.stack([Wx[..., 2, 1], Wx[..., 0, 2], Wx[..., 1, 0]], -1)
+    KE = 0.5 * np.einsum("n,bni,bni->b", d.mass, cdot, cdot)
+    for i in range(d.n_bodies):
+        Iw = np.einsum("bij,jk,blk->bil", T0[:, i, :, :3], inertia_matrix(d, i), T0[:, i, :, :3])
+        KE += 0.5 * np.einsum("bi,bij,bj->b", w[:, i], Iw, w[:, i])
+    M = O.crba(d, st.q)
+    ke = 0.5 * np.einsum("bi,bij,bj->b", st.qd, M, st.qd)
+    assert np.allclose(ke, KE, rtol=1e-7)
+
+
+@pytest.mark.parametrize("name", ["chain7", "humanoid30"])
+def test_gravity_is_potential_gradient(name):
+    """rnea(q, 0, 0) = dV/dq with V = -sum m g . c(q) (central differences along each DoF)."""
+    d = W.chain(7) if name == "chain7" else W.humanoid()
+    st = W.states(d, 8, 3)
+    zero = np.zeros_like(st.qd)
+    grav = O.rnea(d, st.q, zero)
+
+    def V(q):
+        return -np.einsum("n,bni,i->b", d.mass, com_world(d, O.fk(d, q)), d.gravity)
+
+    eps = 1e-6
+    num = np.zeros_like(grav)
+    for k in range(d.nv):
+        e = np.zeros_like(st.qd)
+        e[:, k] = 1.0
+        num[:, k] = (V(retract(d, st.q, e, eps)) - V(retract(d, st.q, e, -eps))) / (2 * eps)
+    assert np.abs(num - grav).max() < 1e-6 * np.abs(grav).max()
+
+
+def test_christoffel_skew_symmetry_fixed_base():
+    """Fixed base: Mdot - 2C is skew, and C(q, qd) qd is the Coriolis/centrifugal force c."""
+    d = W.chain(7)
+    st = W.states(d, 6, 4)
+    eps = 1e-5
+    n = d.nv
+    dM = np.zeros((6, n, n, n))                     # dM[b, k] = dM/dq_k
+    for k in range(n):
+        e = np.zeros_like(st.q)
+        e[:, k] = eps
+        dM[:, k] = (O.crba(d, st.q + e) - O.crba(d, st.q - e)) / (2 * eps)
+    qd = st.qd
+    Mdot = np.einsum("bkij,bk->bij", dM, qd)
+    # C_ij = sum_k 1/2 (dM_ij/dq_k + dM_ik/dq_j - dM_jk/dq_i) qd_k
+    Cm = 0.5 * (np.einsum("bkij,bk->bij", dM, qd) + np.einsum("bjik,bk->bij", dM, qd)
+                - np.einsum("bijk,bk->bij", dM, qd))
+    S = Mdot - 2 * Cm
+    assert np.abs(S + np.swapaxes(S, 1, 2)).max() < 1e-7 * np.abs(Mdot).max()
+    c = O.rnea(d, st.q, qd, gravity=False)
+    assert np.abs(np.einsum("bij,bj->bi", Cm, qd) - c).max() < 1e-7 * np.abs(c).max()
+
+
+@pytest.mark.parametrize("name", ["chain7", "humanoid30"])
+def test_power_balance(name):
+    """qd^T Mdot qd = 2 qd^T c for any base (c without gravity; Mdot along the motion)."""
+    d = W.chain(7) if name == "chain7" else W.humanoid()
+    st = W.states(d, 8, 5)
+    eps = 1e-6
+    Mdot = (O.crba(d, retract(d, st.q, st.qd, eps)) - O.crba(d, retract(d, st.q, st.qd, -eps))) / (2 * eps)
+    lhs = np.einsum("bi,bij,bj->b", st.qd, Mdot, st.qd)
+    c = O.rnea(d, st.q, st.qd, gravity=False)
+    rhs = 2 * np.einsum("bi,bi->b", st.qd, c)
+    assert np.allclose(lhs, rhs, rtol=1e-6, atol=1e-7 * np.abs(rhs).max())
+
+
+# ---------------------------------------------------------------- algorithms agree
+@pytest.mark.parametrize("name", ["chain7", "humanoid30", "tree12"])
+def test_forward_dynamics_round_trip_and_three_methods(name):
+    d = {"chain7": W.chain(7), "humanoid30": W.humanoid(),
+         "tree12": W.random_tree([-1, 0, 1, 1, 0, 4, 5, 5, 7, 0, 9, 10], True, 5)}[name]
+    st = W.states(d, 64, 6)
+    q_llt = O.fwd_dyn(d, st.q, st.qd, st.tau, O.METHOD_LLT)
+    q_ltl = O.fwd_dyn(d, st.q, st.qd, st.tau, O.METHOD_LTL)
+    q_aba = O.fwd_dyn(d, st.q, st.qd, st.tau, O.METHOD_ABA)
+    assert rel_err(q_ltl, q_llt) < 1e-11 and rel_err(q_aba, q_llt) < 1e-11
+    assert rel_err(O.rnea(d, st.q, st.qd, q_ltl), st.tau) < 1e-11
+    M = O.crba(d, st.q)
+    h = O.rnea(d, st.q, st.qd)
+    ref = np.linalg.solve(M, (st.tau - h)[..., None])[..., 0]
+    assert rel_err(q_ltl, ref) < 1e-11
+
+
+@pytest.mark.parametrize("name", ["chain7", "humanoid30", "tree12"])
+def test_paper_literal_vectorized_forms_match_recursive(name):
+    """Alg. 1 and Alg. 2 (ancestor mask U, root frame) agree with the recursive oracle."""
+    d = {"chain7": W.chain(7), "humanoid30": W.humanoid(),
+         "tree12": W.random_tree([-1, 0, 1, 1, 0, 4, 5, 5, 7, 0, 9, 10], True, 5)}[name]
+    st = W.states(d, 32, 7)
+    rng = np.random.Generator(np.random.PCG64(3))
+    qdd = rng.normal(size=st.qd.shape)
+    assert rel_err(PV.crba(d, st.q), O.crba(d, st.q)) < 1e-12
+    assert rel_err(PV.rnea(d, st.q, st.qd, qdd), O.rnea(d, st.q, st.qd, qdd)) < 1e-12
+    assert rel_err(PV.rnea(d, st.q, st.qd), O.rnea(d, st.q, st.qd)) < 1e-12
+
+
+# ---------------------------------------------------------------- kinematics
+def test_fk_at_zero_and_orthonormality():
+    d = W.chain(7)
+    T = O.fk(d, np.zeros((1, 7)))[0]
+    assert np.allclose(T[:, :, 3], np.cumsum(d.origin[:, 9:12], axis=0), atol=1e-15)
+    assert np.allclose(T[:, :, :3], np.eye(3)[None], atol=1e-15)
+    for dd in (W.chain(7), W.humanoid()):
+        st = W.states(dd, 64, 8)
+        R = O.fk(dd, st.q)[..., :3]
+        assert np.abs(np.einsum("bnij,bnkj->bnik", R, R) - np.eye(3)).max() < 1e-13
+        assert np.allclose(np.linalg.det(R), 1.0, atol=1e-13)
+
+
+def test_fk_base_pose_is_the_free_joint_state():
+    d = W.humanoid()
+    st = W.states(d, 8, 10)
+    T = O.fk(d, st.q)
+    assert np.allclose(T[:, 0, :, 3], st.q[:, 0:3], atol=1e-15)
+    assert np.allclose(T[:, 0, :, :3], base_rotation(st.q[:, 3:7]), atol=1e-14)
+    q2 = st.q.copy()
+    q2[:, 3:7] *= 3.7                                  # a scaled quaternion is the same rotation
+    assert np.allclose(O.fk(d, q2), T, atol=1e-14)
+
+
+@pytest.mark.parametrize("name", ["chain7", "humanoid30"])
+def test_jacobian_is_the_derivative_of_fk(name):
+    """J(q) qd = [d p / dt; w] of every frame, with both sides from FK alone."""
+    d = W.chain(7) if name == "chain7" else W.humanoid()
+    st = W.states(d, 4, 11)
+    J = O.jacobian(d, st.q)
+    eps = 1e-6
+    T0 = O.fk(d, st.q)
+    for k in range(d.nv):
+        e = np.zeros_like(st.qd)
+        e[:, k] = 1.0
+        Tp, Tm = O.fk(d, retract(d, st.q, e, eps)), O.fk(d, retract(d, st.q, e, -eps))
+        pdot = (Tp[..., :, 3] - Tm[..., :, 3]) / (2 * eps)
+        Wx = np.einsum("bnij,bnkj->bnik", (Tp[..., :3] - Tm[..., :3]) / (2 * eps), T0[..., :3])
+        w = np.stack([Wx[..., 2, 1], Wx[..., 0, 2], Wx[..., 1, 0]], -1)
+        assert np.abs(J[:, :, 0:3, k] - pdot).max() < 1e-8
+        assert np.abs(J[:, :, 3:6, k] - w).max() < 1e-8
+
+
+# ---------------------------------------------------------------- derivatives
+@pytest.mark.parametrize("name", ["chain7", "humanoid30"])
+def test_vjp_tau_block_is_the_inverse_mass_matrix(name):
+    """d qdd / d tau = M^-1, so gbar^T M^-1 is the tau cotangent exactly."""
+    d = W.chain(7) if name == "chain7" else W.humanoid()
+    st = W.states(d, 8, 12)
+    gbar = W.cotangent(d.nv, 8, 13)
+    _, _, gtau = O.fwd_dyn_vjp_fd(d, st.q, st.qd, st.tau, gbar)
+    ref = np.linalg.solve(O.crba(d, st.q), gbar[..., None])[..., 0]
+    assert rel_err(gtau, ref) < 1e-7
+
+
+def test_vjp_dot_product_with_directional_difference():
+    """<gbar, D qdd [dq, dqd, dtau]> = <vjp(gbar), [dq, dqd, dtau]> for random directions."""
+    d = W.humanoid()
+    st = W.states(d, 8, 14)
+    gbar = W.cotangent(d.nv, 8, 15)
+    gq, gqd, gtau = O.fwd_dyn_vjp_fd(d, st.q, st.qd, st.tau, gbar)
+    rng = np.random.Generator(np.random.PCG64(16))
+    dq, dqd, dtau = rng.normal(size=st.q.shape), rng.normal(size=st.qd.shape), rng.normal(size=st.tau.shape)
+    eps = 1e-6
+    fp = O.fwd_dyn(d, st.q + eps * dq, st.qd + eps * dqd, st.tau + eps * dtau)
+    fm = O.fwd_dyn(d, st.q - eps * dq, st.qd - eps * dqd, st.tau - eps * dtau)
+    lhs = np.einsum("bi,bi->b", gbar, (fp - fm) / (2 * eps))
+    rhs = np.einsum("bi,bi->b", gq, dq) + np.einsum("bi,bi->b", gqd, dqd) + np.einsum("bi,bi->b", gtau, dtau)
+    assert np.allclose(lhs, rhs, rtol=1e-5, atol=1e-6 * np.abs(lhs).max())
+
+
+def test_vjp_position_is_invariant_to_base_translation():
+    """Dynamics in body coordinates do not depend on the base position."""
+    d = W.humanoid()
+    st = W.states(d, 4, 17)
+    gbar = W.cotangent(d.nv, 4, 18)
+    gq, _, _ = O.fwd_dyn_vjp_fd(d, st.q, st.qd, st.tau, gbar)
+    assert np.abs(gq[:, 0:3]).max() < 1e-6
+
+
+# ---------------------------------------------------------------- operation counts
+def test_operation_counts_are_consistent():
+    for d in (W.chain(7), W.humanoid()):
+        nrev = int((d.joint_type == W.REVOLUTE).sum())
+        fk = O.count_ops(d, "fk")
+        assert fk["trig"] == 2 * nrev
+        ltl, llt = O.count_ops(d, "fwd_dyn_ltl"), O.count_ops(d, "fwd_dyn_llt")
+        assert ltl["sqrt"] == llt["sqrt"] == d.nv
+        if d.floating:
+            assert ltl["flops"] < llt["flops"]         # branch sparsity saves work
+        else:
+            assert ltl["flops"] == llt["flops"]        # a chain has none
+        rb, cr = O.count_ops(d, "rnea_bias"), O.count_ops(d, "crba")
+        assert ltl["flops"] > rb["flops"] + cr["flops"]
