@@ -1,0 +1,196 @@
+/*
+ * rbd.h - batched rigid-body kinematics and dynamics on one MI355X (gfx950).
+ *
+ * C ABI of librbd.so. Every hot entry point evaluates one operation for a
+ * whole batch of robot states, one instance per GPU lane, in FP32.
+ *
+ * Operations (arxiv 2604.04310):
+ *   rbd_fk           forward kinematics 0T_i(q) of every body (Sec. II)
+ *   rbd_jacobian     world-aligned geometric Jacobians of chosen body frames
+ *                    (Sec. IV, the library's analytical Jacobians)
+ *   rbd_rnea         inverse dynamics tau = M qdd + c + g, Eq. (1); with
+ *                    qdd == NULL the bias force h(q, qd) = c + g (Alg. 1)
+ *   rbd_crba         joint-space mass matrix M(q) (Alg. 2)
+ *   rbd_fwd_dyn      forward dynamics qdd = M^-1 (tau - h), Eq. (2), by a
+ *                    per-instance Cholesky-type solve (Sec. V, footnote)
+ *   rbd_fwd_dyn_vjp  reverse-mode derivative of rbd_fwd_dyn (Sec. I, AD)
+ *   rbd_server_*     continuous-batching service for the above (host API)
+ *
+ * Conventions
+ *   Bodies are numbered 0..n-1 with parent[i] < i (-1 = world), depth-first
+ *   (every subtree is a contiguous range of bodies). Body 0 may be a free
+ *   joint. A revolute body frame sits at origin p in its parent frame, is
+ *   turned by the fixed rotation R and then by q about the unit axis.
+ *   Generalised coordinates: revolute q, qd, qdd, tau are scalars. A free base
+ *   has q = [p_world(3); quaternion w,x,y,z (4)], qd = [v; w] (the body-frame
+ *   twist of the base origin, linear first), qdd its time derivative, and tau
+ *   the body-frame wrench [force; moment]. Base rotation = Hamilton rotation of
+ *   the quaternion divided by its squared norm. nq = n (+6 with a free base),
+ *   nv = n (+5 with a free base).
+ *   Gravity enters as a fictitious base acceleration -g, so tau contains the
+ *   holding torque +g(q).
+ *
+ * Data layout of every batched array: device memory, FP32, structure of
+ *   arrays. Element (coordinate c, instance b) lives at ptr[c * ld + b] with
+ *   ld >= batch. Inputs are never written. Outputs must not overlap inputs.
+ *
+ * Calls are asynchronous on the given HIP stream (0 = the null stream). They
+ *   never allocate device memory and never synchronise. Argument errors are
+ *   reported synchronously by the status code, with a message from
+ *   rbd_last_error() (thread-local). A numerically failed instance (a
+ *   non-positive pivot, a zero quaternion) yields NaN in that instance's
+ *   outputs and never fails the call.
+ */
+#ifndef RBD_H
+#define RBD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  RBD_OK = 0,
+  RBD_E_INVAL = 1,       /* bad argument (message in rbd_last_error)          */
+  RBD_E_NOMEM = 2,       /* device or host allocation failed                  */
+  RBD_E_NODEVICE = 3,    /* no usable GPU, or the device id is out of range   */
+  RBD_E_LAUNCH = 4,      /* a HIP call or kernel launch failed                */
+  RBD_E_UNSUPPORTED = 5, /* valid model whose topology has no compiled kernel */
+  RBD_E_TIMEOUT = 6,     /* rbd_server_wait: the request did not finish       */
+  RBD_E_SHUTDOWN = 7     /* rbd_server_*: the server is shutting down         */
+} rbd_status;
+
+typedef enum { RBD_JOINT_REVOLUTE = 0, RBD_JOINT_FREE = 1 } rbd_joint;
+
+/* Kinematic tree description, host memory, FP64 (paper Sec. II: a kinematic
+ * tree with generalised coordinates q). Copied by rbd_model_create; the caller
+ * keeps ownership. */
+typedef struct {
+  int32_t n_bodies;          /* 1 .. 64                                        */
+  const int32_t* parent;     /* [n]  parent[i] < i, -1 = world                 */
+  const int32_t* joint_type; /* [n]  rbd_joint; FREE only for body 0           */
+  const double* axis;        /* [n][3] joint axis in the joint frame (revolute;
+                                normalised on creation, must be non-zero)      */
+  const double* origin;      /* [n][12] fixed parent->joint transform: rotation
+                                R row-major (9) then p (3); unused for FREE    */
+  const double* mass;        /* [n]  > 0                                       */
+  const double* com;         /* [n][3] centre of mass in the body frame        */
+  const double* inertia;     /* [n][6] about the CoM in body axes:
+                                xx yy zz xy xz yz; positive definite           */
+  double gravity[3];         /* world gravity, e.g. {0, 0, -9.81}              */
+} rbd_tree_desc;
+
+typedef struct rbd_model rbd_model; /* opaque: device-resident tables */
+
+/* Validate the tree, precompute FP32 tables and upload them to `device`.
+ * Errors: RBD_E_INVAL (null pointer, n out of range, parent[i] >= i, a
+ * subtree that is not a contiguous range, FREE joint not at body 0, unknown
+ * joint type, zero axis, R not a rotation, mass <= 0, inertia not positive
+ * definite or violating the triangle inequality), RBD_E_UNSUPPORTED (no
+ * compiled kernel for this topology), RBD_E_NODEVICE, RBD_E_NOMEM. */
+rbd_status rbd_model_create(const rbd_tree_desc* desc, int device, rbd_model** out);
+rbd_status rbd_model_destroy(rbd_model* model);
+rbd_status rbd_model_dims(const rbd_model* model, int* nq, int* nv, int* n_bodies);
+/* Name of the compiled topology serving this model (static string). */
+const char* rbd_model_topology(const rbd_model* model);
+
+/* Forward kinematics (Sec. II): T[(i*12 + e) * ld + b] holds the world pose
+ * of body i as a 3x4 row-major [R | p] (e = 4*row + col). q: [nq][ld]. */
+rbd_status rbd_fk(const rbd_model* model, int64_t batch, int64_t ld, const float* q, float* T,
+                  hipStream_t stream);
+
+/* Geometric Jacobians (Sec. IV): for each of the n_frames body ids in
+ * `frames` (host array, 1..256 entries, repeats allowed), the 6 x nv matrix
+ * mapping qd to the world-aligned twist [v; w] of that body frame at its
+ * origin. J[((f*6 + r) * nv + c) * ld + b]; columns of non-ancestor joints
+ * are zero. */
+rbd_status rbd_jacobian(const rbd_model* model, int64_t batch, int64_t ld, const float* q, int32_t n_frames,
+                        const int32_t* frames, float* J, hipStream_t stream);
+
+/* Inverse dynamics, Eq. (1) with f = 0, by the recursive Newton-Euler
+ * algorithm (the recursive form of Alg. 1): tau = M(q) qdd + c(q, qd) + g(q).
+ * qdd == NULL computes the bias force h(q, qd). q: [nq][ld]; qd, qdd, tau:
+ * [nv][ld]. */
+rbd_status rbd_rnea(const rbd_model* model, int64_t batch, int64_t ld, const float* q, const float* qd,
+                    const float* qdd, float* tau, hipStream_t stream);
+
+/* Joint-space mass matrix by the composite-rigid-body algorithm (the
+ * recursive form of Alg. 2), dense and symmetric: M[(r*nv + c) * ld + b]. */
+rbd_status rbd_crba(const rbd_model* model, int64_t batch, int64_t ld, const float* q, float* M,
+                    hipStream_t stream);
+
+/* Forward dynamics, Eq. (2) with f = 0: qdd = M(q)^-1 (tau - h(q, qd)).
+ * One fused kernel: bias force, mass matrix and its branch-sparse L^T L
+ * factorisation never leave the lane. q: [nq][ld]; qd, tau, qdd: [nv][ld]. */
+rbd_status rbd_fwd_dyn(const rbd_model* model, int64_t batch, int64_t ld, const float* q, const float* qd,
+                       const float* tau, float* qdd, hipStream_t stream);
+
+/* Vector-Jacobian product of rbd_fwd_dyn for the cotangent g_qdd [nv][ld]:
+ * g_q = g_qdd^T dqdd/dq [nq][ld] (raw quaternion components included),
+ * g_qd = g_qdd^T dqdd/dqd [nv][ld], g_tau = g_qdd^T dqdd/dtau = M^-1 g_qdd
+ * [nv][ld]. Any of the three outputs may be NULL (not computed). */
+rbd_status rbd_fwd_dyn_vjp(const rbd_model* model, int64_t batch, int64_t ld, const float* q, const float* qd,
+                           const float* tau, const float* g_qdd, float* g_q, float* g_qd, float* g_tau,
+                           hipStream_t stream);
+
+const char* rbd_status_str(rbd_status s);
+const char* rbd_last_error(void); /* message of this thread's last failed call */
+int rbd_device_count(void);       /* number of visible GPUs (0 without one)    */
+
+/* ------------------------------------------------------------------ serving
+ * Continuous batching of dynamics requests (spec: requests of mixed
+ * robots and batch sizes are admitted as device memory frees up, packed into
+ * one persistent launch per operation and robot, replayed as a captured HIP
+ * graph, and overlapped on several streams).
+ *
+ * A request names a model, an operation and a batch size, and points at host
+ * buffers, instance-major FP32 ([batch][n], rows of one instance contiguous):
+ *   RBD_OP_FWD_DYN:     in = {q, qd, tau},          out = {qdd}
+ *   RBD_OP_RNEA:        in = {q, qd, qdd},          out = {tau}
+ *   RBD_OP_FWD_DYN_VJP: in = {q, qd, tau, g_qdd},   out = {g_q, g_qd, g_tau}
+ * The buffers must stay valid until rbd_server_wait reports completion. The
+ * server copies inputs into its device arena, runs the batch and copies the
+ * results back. */
+typedef enum { RBD_OP_FWD_DYN = 0, RBD_OP_RNEA = 1, RBD_OP_FWD_DYN_VJP = 2 } rbd_op;
+
+typedef struct rbd_server rbd_server;
+
+typedef struct {
+  int device;            /* GPU id                                                  */
+  size_t arena_bytes;    /* device memory for staged requests (admission budget)    */
+  int n_streams;         /* concurrent launch streams, 1..8                         */
+  int max_batch_requests;/* most requests packed into one launch (1..4096)          */
+  double max_wait_us;    /* how long a launch may wait to gather more requests      */
+  int use_graphs;        /* 1: replay captured HIP graphs, 0: plain launches        */
+  int per_request;       /* 1: one launch per request (baseline mode, no packing)   */
+} rbd_server_config;
+
+rbd_status rbd_server_create(const rbd_server_config* cfg, rbd_server** out);
+/* Queue one request; returns a ticket immediately. RBD_E_INVAL if it can never
+ * fit the arena or names a bad op, size or pointer. */
+rbd_status rbd_server_submit(rbd_server* s, const rbd_model* model, int op, int64_t batch,
+                             const float* const* host_in, float* const* host_out, uint64_t* ticket);
+/* Wait until the request finishes (timeout_s < 0: forever). On RBD_OK,
+ * *req_status holds the request's own result. A ticket can be waited once. */
+rbd_status rbd_server_wait(rbd_server* s, uint64_t ticket, double timeout_s, rbd_status* req_status);
+/* Latency (submit -> results in host memory) and throughput counters since
+ * the last reset. */
+typedef struct {
+  uint64_t requests, instances, launches;
+  double p50_us, p99_us, max_us, mean_us;
+  double busy_s; /* wall time with at least one launch in flight */
+} rbd_server_stats;
+rbd_status rbd_server_get_stats(rbd_server* s, rbd_server_stats* out);
+rbd_status rbd_server_reset_stats(rbd_server* s);
+/* Drain outstanding requests, then free everything. */
+rbd_status rbd_server_destroy(rbd_server* s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RBD_H */

@@ -1,0 +1,76 @@
+// Internal declarations shared by the host API, the kernel dispatch and the
+// serving runtime of librbd.so.
+#pragma once
+
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "rbd.h"
+#include "rbd_shared.hpp"
+
+struct rbd_model {
+  int device = 0;
+  int topo = -1;               // index into the compiled topology list
+  int n = 0, nq = 0, nv = 0;
+  bool floating = false;
+  float* d_tab = nullptr;      // device tables (see rbd_lane.hpp)
+  size_t tab_floats = 0;
+};
+
+namespace rbd {
+
+// FP32 device tables of a validated tree (layout in rbd_lane.hpp)
+std::vector<float> make_tables(const rbd_tree_desc* d);
+
+// error reporting (thread-local message)
+rbd_status fail(rbd_status s, const char* fmt, ...);
+void clear_error();
+
+// ---- compiled topologies
+struct TopoInfo {
+  const char* name;
+  bool floating;
+  int n;
+  const int* parent;
+};
+int n_topologies();
+const TopoInfo& topology(int id);
+int find_topology(bool floating, int n, const int32_t* parent);
+
+// ---- kernel dispatch (rbd_kernels.hip); arguments are already validated
+rbd_status launch_fk(const rbd_model* m, int64_t batch, int64_t ld, const float* q, float* T, hipStream_t s);
+rbd_status launch_jacobian(const rbd_model* m, int64_t batch, int64_t ld, const float* q, int32_t n_frames,
+                           const int32_t* frames, float* J, hipStream_t s);
+rbd_status launch_rnea(const rbd_model* m, int64_t batch, int64_t ld, const float* q, const float* qd,
+                       const float* qdd, float* tau, hipStream_t s);
+rbd_status launch_crba(const rbd_model* m, int64_t batch, int64_t ld, const float* q, float* M, hipStream_t s);
+rbd_status launch_fwd_dyn(const rbd_model* m, int64_t batch, int64_t ld, const float* q, const float* qd,
+                          const float* tau, float* qdd, hipStream_t s);
+rbd_status launch_fwd_dyn_vjp(const rbd_model* m, int64_t batch, int64_t ld, const float* q, const float* qd,
+                              const float* tau, const float* gqdd, float* gq, float* gqd, float* gtau,
+                              hipStream_t s);
+
+
+// Host launch wrappers of one compiled topology (see rbd_kernels.hpp).
+struct LaunchTable {
+  rbd_status (*fk)(const float* tab, int64_t batch, int64_t ld, const float* q, float* T, hipStream_t s);
+  rbd_status (*jacobian)(const float* tab, int64_t batch, int64_t ld, const float* q, const JacSlots& js, float* J,
+                         hipStream_t s);
+  rbd_status (*rnea)(const float* tab, int64_t batch, int64_t ld, const float* q, const float* qd, const float* qdd,
+                     float* tau, hipStream_t s);
+  rbd_status (*crba)(const float* tab, int64_t batch, int64_t ld, const float* q, float* M, hipStream_t s);
+  rbd_status (*fwd_dyn)(const float* tab, int64_t batch, int64_t ld, const float* q, const float* qd,
+                        const float* tau, float* qdd, hipStream_t s);
+  rbd_status (*vjp)(const float* tab, int64_t batch, int64_t ld, const float* q, const float* qd, const float* tau,
+                    const float* gqdd, float* gq, float* gqd, float* gtau, hipStream_t s);
+  rbd_status (*packed)(int op, const float* tab, const void* table, int grid, hipStream_t s);
+};
+
+// Packed serving launch of one (model, op): d_table holds a PackedHdr-led
+// descriptor table in device memory; grid blocks of 256 threads stride over it.
+constexpr int kMaxPacked = 4096;
+rbd_status launch_packed(const rbd_model* m, int op, const void* d_table, int grid, hipStream_t s);
+
+}  // namespace rbd

@@ -1,0 +1,826 @@
+// Per-lane rigid-body algorithms for gfx950: one robot instance per lane.
+//
+// Everything a lane holds lives in registers: the tree is a compile-time
+// type, every body loop is unrolled by template recursion, so the per-body
+// transforms, velocities, forces, composite inertias and the mass-matrix factor
+// are named registers and never indexed memory. Model constants are read from
+// a small read-only table with uniform addresses (scalar loads, SGPR operands).
+//
+// Frames. Each revolute body is computed in a joint-aligned copy of its frame
+// whose z axis is the joint axis, so the motion subspace is S = [e_z; 0], the
+// joint rotation is Rz(q), and S^T f is just f.n.z. The constant part of the
+// parent-to-child rotation, K = C_parent^T R_fix C_child, is precomputed on the
+// host; R(q) = K Rz(q) costs 12 multiply-adds. Body-fixed frames keep spatial
+// quantities near the bodies they describe, which matters in FP32: the root
+// frame form of Alg. 1 and Alg. 2 subtracts large m|p|^2 terms for distal
+// bodies.
+//
+// Spatial vectors are [angular; linear] (motion [w; v], force [n; f]).
+// Algorithms follow the paper's problem statement (Eq. (1), Eq. (2)) in their
+// recursive O(n) form, the one Alg. 1 and Alg. 2 vectorise with the ancestor
+// mask U: on a GPU the parallelism is across instances, so the per-instance
+// work should be the smallest, not the most parallel.
+#pragma once
+
+#include <stdint.h>
+
+#include <type_traits>
+#include <utility>
+
+#include "rbd_shared.hpp"
+
+#ifndef RBD_DI
+#define RBD_DI __device__ __forceinline__
+#endif
+
+namespace rbd {
+
+// =================================================================== topology
+// A kinematic tree as a type: FREE says body 0 is a floating base, P... are
+// the parents (depth-first order, parent[i] < i, -1 = world).
+template <bool FREE, int... P>
+struct Tree {
+  static constexpr int N = sizeof...(P);
+  static constexpr bool kFree = FREE;
+  static constexpr int NV = N + (FREE ? 5 : 0);
+  static constexpr int NQ = N + (FREE ? 6 : 0);
+  struct Arr {
+    int v[sizeof...(P)];
+  };
+  static constexpr Arr par_ = {{P...}};
+
+  static constexpr int parent(int i) { return par_.v[i]; }
+  static constexpr bool free_body(int i) { return FREE && i == 0; }
+  static constexpr int nvb(int i) { return free_body(i) ? 6 : 1; }
+  static constexpr int vofs(int i) { return (FREE && i > 0) ? i + 5 : i; }
+  static constexpr int qofs(int i) { return (FREE && i > 0) ? i + 6 : i; }
+  // j is i or an ancestor of i
+  static constexpr bool is_anc(int j, int i) {
+    for (int k = i; k >= 0; k = parent(k))
+      if (k == j) return true;
+    return false;
+  }
+  // last body of the subtree rooted at i (depth-first numbering)
+  static constexpr int last(int i) {
+    int m = i;
+    for (int k = i + 1; k < N; ++k)
+      if (is_anc(i, k)) m = k;
+    return m;
+  }
+  static constexpr bool depth_first() {
+    for (int i = 0; i < N; ++i) {
+      if (parent(i) >= i || parent(i) < -1) return false;
+      for (int k = i + 1; k <= last(i); ++k)
+        if (!is_anc(i, k)) return false;
+    }
+    return true;
+  }
+  // ---- DoF-level tree (a free base is a chain of 6 DoFs)
+  static constexpr int body_of(int k) { return FREE ? (k < 6 ? 0 : k - 5) : k; }
+  static constexpr int dpar(int k) {
+    if (FREE && k < 6) return k - 1;
+    const int p = parent(body_of(k));
+    return p < 0 ? -1 : vofs(p) + nvb(p) - 1;
+  }
+  static constexpr int ddepth(int k) {
+    int d = 0;
+    for (int j = dpar(k); j >= 0; j = dpar(j)) ++d;
+    return d;
+  }
+  // j is a strict ancestor DoF of k
+  static constexpr bool is_danc(int j, int k) {
+    for (int t = dpar(k); t >= 0; t = dpar(t))
+      if (t == j) return true;
+    return false;
+  }
+  static constexpr int loff(int k) {
+    int o = 0;
+    for (int t = 0; t < k; ++t) o += ddepth(t);
+    return o;
+  }
+  static constexpr int nnz() { return loff(NV); }  // off-diagonal entries of L
+  // position of L[k][j] (j a strict ancestor of k) in the packed factor
+  static constexpr int lidx(int k, int j) { return loff(k) + ddepth(k) - 1 - ddepth(j); }
+  static_assert(N >= 1 && N <= 64, "1..64 bodies");
+};
+
+template <int I>
+using ic = std::integral_constant<int, I>;
+// Forces a constexpr index to be folded by the front end (an array index is not
+// a constant-expression context, so a plain call would be a run-time call).
+template <int V>
+inline constexpr int cidx = V;
+
+// f(ic<B>), f(ic<B+1>), ..., f(ic<E-1>). A fold over an index sequence, not a
+// recursion: a recursive helper makes every level a function that holds all the
+// later iterations, which is quadratic work for the optimiser.
+template <int B, class F, int... Is>
+RBD_DI void sfor_impl(F& f, std::integer_sequence<int, Is...>) {
+  (f(ic<B + Is>{}), ...);
+}
+template <int B, int E, class F>
+RBD_DI void sfor(F&& f) {
+  if constexpr (B < E) sfor_impl<B>(f, std::make_integer_sequence<int, E - B>{});
+}
+// f(ic<E-1>), ..., f(ic<B>)
+template <int E, class F, int... Is>
+RBD_DI void sfor_rev_impl(F& f, std::integer_sequence<int, Is...>) {
+  (f(ic<E - 1 - Is>{}), ...);
+}
+template <int B, int E, class F>
+RBD_DI void sfor_rev(F&& f) {
+  if constexpr (B < E) sfor_rev_impl<E>(f, std::make_integer_sequence<int, E - B>{});
+}
+
+// Runs fn(ic<J>) for J = I, parent(I), ... while the subtree of J ends at I.
+template <class TP, int J, int I, class F>
+RBD_DI void close_subtrees(F& fn) {
+  if constexpr (J >= 0) {
+    if constexpr (TP::last(J) == I) {
+      fn(ic<J>{});
+      close_subtrees<TP, TP::parent(J), I>(fn);
+    }
+  }
+}
+
+// =================================================================== algebra
+struct V3 {
+  float x, y, z;
+};
+RBD_DI V3 operator+(V3 a, V3 b) { return {a.x + b.x, a.y + b.y, a.z + b.z}; }
+RBD_DI V3 operator-(V3 a, V3 b) { return {a.x - b.x, a.y - b.y, a.z - b.z}; }
+RBD_DI V3 operator*(float s, V3 a) { return {s * a.x, s * a.y, s * a.z}; }
+RBD_DI float dot(V3 a, V3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+RBD_DI V3 cross(V3 a, V3 b) { return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x}; }
+
+struct M3 {  // row-major
+  float a[9];
+};
+RBD_DI V3 mul(const M3& R, V3 x) {
+  return {R.a[0] * x.x + R.a[1] * x.y + R.a[2] * x.z, R.a[3] * x.x + R.a[4] * x.y + R.a[5] * x.z,
+          R.a[6] * x.x + R.a[7] * x.y + R.a[8] * x.z};
+}
+RBD_DI V3 mulT(const M3& R, V3 x) {
+  return {R.a[0] * x.x + R.a[3] * x.y + R.a[6] * x.z, R.a[1] * x.x + R.a[4] * x.y + R.a[7] * x.z,
+          R.a[2] * x.x + R.a[5] * x.y + R.a[8] * x.z};
+}
+RBD_DI M3 mulMM(const M3& A, const M3& B) {
+  M3 C;
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) C.a[3 * i + j] = A.a[3 * i] * B.a[j] + A.a[3 * i + 1] * B.a[3 + j] + A.a[3 * i + 2] * B.a[6 + j];
+  return C;
+}
+RBD_DI M3 mulMMT(const M3& A, const M3& B) {  // A B^T
+  M3 C;
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+      C.a[3 * i + j] = A.a[3 * i] * B.a[3 * j] + A.a[3 * i + 1] * B.a[3 * j + 1] + A.a[3 * i + 2] * B.a[3 * j + 2];
+  return C;
+}
+
+struct Mot {  // motion vector [w; v]
+  V3 w, v;
+};
+struct Frc {  // force vector [n; f]
+  V3 n, f;
+};
+RBD_DI Mot operator+(const Mot& a, const Mot& b) { return {a.w + b.w, a.v + b.v}; }
+RBD_DI Frc operator+(const Frc& a, const Frc& b) { return {a.n + b.n, a.f + b.f}; }
+RBD_DI Frc operator-(const Frc& a, const Frc& b) { return {a.n - b.n, a.f - b.f}; }
+
+// Rigid-body inertia about the frame origin: mass, first moment h = m c and
+// the rotational inertia about the origin (symmetric, 6 numbers).
+struct Inr {
+  float m;
+  V3 h;
+  float xx, yy, zz, xy, xz, yz;
+};
+RBD_DI V3 isym(const Inr& I, V3 w) {
+  return {I.xx * w.x + I.xy * w.y + I.xz * w.z, I.xy * w.x + I.yy * w.y + I.yz * w.z,
+          I.xz * w.x + I.yz * w.y + I.zz * w.z};
+}
+// I x = [Ibar w + h x v; m v - h x w]
+RBD_DI Frc imul(const Inr& I, const Mot& x) { return {isym(I, x.w) + cross(I.h, x.v), I.m * x.v - cross(I.h, x.w)}; }
+RBD_DI Inr operator+(const Inr& A, const Inr& B) {
+  return {A.m + B.m, A.h + B.h, A.xx + B.xx, A.yy + B.yy, A.zz + B.zz, A.xy + B.xy, A.xz + B.xz, A.yz + B.yz};
+}
+// v x* f = [w x n + v x f; w x f]
+RBD_DI Frc crf(const Mot& v, const Frc& f) { return {cross(v.w, f.n) + cross(v.v, f.f), cross(v.w, f.f)}; }
+// v x m = [w x w2; w x v2 + v x w2]
+RBD_DI Mot crm(const Mot& v, const Mot& m) { return {cross(v.w, m.w), cross(v.w, m.v) + cross(v.v, m.w)}; }
+RBD_DI float pair(const Frc& f, const Mot& m) { return dot(f.n, m.w) + dot(f.f, m.v); }
+
+// Child frame at r (parent coords) with axes R (columns, parent coords).
+// motion parent -> child: w' = R^T w, v' = R^T (v + w x r)
+RBD_DI Mot xmot(const M3& R, V3 r, const Mot& m) { return {mulT(R, m.w), mulT(R, m.v + cross(m.w, r))}; }
+// force child -> parent: f' = R f, n' = R n + r x f'
+RBD_DI Frc xfrc(const M3& R, V3 r, const Frc& f) {
+  const V3 fp = mul(R, f.f);
+  return {mul(R, f.n) + cross(r, fp), fp};
+}
+// inertia child -> parent (X^T I X): h' = R h + m r,
+// Ibar' = R Ibar R^T - (u r^T + r u^T - 2 (r.u) 1) - m (r r^T - |r|^2 1), u = R h
+RBD_DI Inr xinr(const M3& R, V3 r, const Inr& I) {
+  const V3 u = mul(R, I.h);
+  // T = R * Ibar (Ibar symmetric)
+  const V3 c0 = {I.xx, I.xy, I.xz}, c1 = {I.xy, I.yy, I.yz}, c2 = {I.xz, I.yz, I.zz};
+  const V3 r0 = {R.a[0], R.a[1], R.a[2]}, r1 = {R.a[3], R.a[4], R.a[5]}, r2 = {R.a[6], R.a[7], R.a[8]};
+  const V3 t0 = {dot(r0, c0), dot(r0, c1), dot(r0, c2)};
+  const V3 t1 = {dot(r1, c0), dot(r1, c1), dot(r1, c2)};
+  const V3 t2 = {dot(r2, c0), dot(r2, c1), dot(r2, c2)};
+  const float ru = dot(r, u), rr = dot(r, r);
+  const float d = 2.0f * ru + I.m * rr;
+  Inr o;
+  o.m = I.m;
+  o.h = u + I.m * r;
+  o.xx = dot(t0, r0) - 2.0f * u.x * r.x - I.m * r.x * r.x + d;
+  o.yy = dot(t1, r1) - 2.0f * u.y * r.y - I.m * r.y * r.y + d;
+  o.zz = dot(t2, r2) - 2.0f * u.z * r.z - I.m * r.z * r.z + d;
+  o.xy = dot(t0, r1) - (u.x * r.y + r.x * u.y) - I.m * r.x * r.y;
+  o.xz = dot(t0, r2) - (u.x * r.z + r.x * u.z) - I.m * r.x * r.z;
+  o.yz = dot(t1, r2) - (u.y * r.z + r.y * u.z) - I.m * r.y * r.z;
+  return o;
+}
+
+RBD_DI void fsincos(float q, float& s, float& c) {
+  // hardware sin/cos take revolutions
+  const float t = q * 0.15915494309189535f;
+  s = __builtin_amdgcn_sinf(t);
+  c = __builtin_amdgcn_cosf(t);
+}
+RBD_DI float frsq(float x) { return __builtin_amdgcn_rsqf(x); }
+RBD_DI float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
+
+// =================================================================== tables
+// Per body, 32 floats: K (9, row-major), r (3), m, h (3), Ibar about the origin
+// in joint-aligned axes (xx yy zz xy xz yz), C (9, row-major; joint-aligned ->
+// user body axes), pad. After the bodies: gravity (3).
+constexpr int kBodyStride = 32;
+constexpr int kOffK = 0, kOffR = 9, kOffM = 12, kOffH = 13, kOffI = 16, kOffC = 22;
+
+template <int I>
+RBD_DI Inr load_inr(const float* __restrict__ t) {
+  const float* b = t + I * kBodyStride;
+  return {b[kOffM], {b[kOffH], b[kOffH + 1], b[kOffH + 2]}, b[kOffI], b[kOffI + 1], b[kOffI + 2],
+          b[kOffI + 3], b[kOffI + 4], b[kOffI + 5]};
+}
+template <int I>
+RBD_DI V3 load_r(const float* __restrict__ t) {
+  const float* b = t + I * kBodyStride + kOffR;
+  return {b[0], b[1], b[2]};
+}
+template <class TP>
+RBD_DI V3 load_g(const float* __restrict__ t) {
+  const float* b = t + TP::N * kBodyStride;
+  return {b[0], b[1], b[2]};
+}
+// R = K Rz(q): columns c K0 + s K1, -s K0 + c K1, K2
+template <int I>
+RBD_DI M3 joint_rot(const float* __restrict__ t, float q) {
+  const float* K = t + I * kBodyStride + kOffK;
+  float s, c;
+  fsincos(q, s, c);
+  M3 R;
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    R.a[3 * r + 0] = c * K[3 * r] + s * K[3 * r + 1];
+    R.a[3 * r + 1] = c * K[3 * r + 1] - s * K[3 * r];
+    R.a[3 * r + 2] = K[3 * r + 2];
+  }
+  return R;
+}
+// Rotation of a quaternion (w,x,y,z) divided by its squared norm.
+RBD_DI M3 quat_rot(float w, float x, float y, float z) {
+  const float s = frcp(w * w + x * x + y * y + z * z);
+  const float ww = w * w, xx = x * x, yy = y * y, zz = z * z;
+  M3 R;
+  R.a[0] = (ww + xx - yy - zz) * s;
+  R.a[1] = 2.0f * (x * y - w * z) * s;
+  R.a[2] = 2.0f * (x * z + w * y) * s;
+  R.a[3] = 2.0f * (x * y + w * z) * s;
+  R.a[4] = (ww - xx + yy - zz) * s;
+  R.a[5] = 2.0f * (y * z - w * x) * s;
+  R.a[6] = 2.0f * (x * z - w * y) * s;
+  R.a[7] = 2.0f * (y * z + w * x) * s;
+  R.a[8] = (ww - xx - yy + zz) * s;
+  return R;
+}
+
+// Column of a composite inertia for S = [e_z; 0]: I S = [Ibar e_z; -h x e_z]
+RBD_DI Frc inr_col_z(const Inr& I) { return {{I.xz, I.yz, I.zz}, {-I.h.y, I.h.x, 0.0f}}; }
+
+// =================================================================== lane I/O
+// One lane's view of a structure-of-arrays batch: element c at p[c * ld].
+struct In {
+  const float* __restrict__ p;
+  int64_t ld;
+  RBD_DI float operator()(int c) const { return p[c * ld]; }
+};
+struct Out {
+  float* __restrict__ p;
+  int64_t ld;
+  RBD_DI void operator()(int c, float v) const { p[c * ld] = v; }
+};
+
+// =================================================================== FK
+// World pose of every body in the user's body axes: [R | p] row-major.
+template <class TP>
+RBD_DI void fk_lane(const float* __restrict__ t, const In& q, const Out& T) {
+  constexpr int N = TP::N;
+  M3 Rw[N];
+  V3 pw[N];
+  sfor<0, N>([&](auto I_) __attribute__((always_inline)) {
+    constexpr int I = decltype(I_)::value;
+    constexpr int P = TP::parent(I);
+    if constexpr (TP::free_body(I)) {
+      Rw[I] = quat_rot(q(3), q(4), q(5), q(6));
+      pw[I] = {q(0), q(1), q(2)};
+    } else {
+      const M3 R = joint_rot<I>(t, q(cidx<TP::qofs(I)>));
+      const V3 r = load_r<I>(t);
+      if constexpr (P < 0) {
+        Rw[I] = R;
+        pw[I] = r;
+      } else {
+        Rw[I] = mulMM(Rw[P], R);
+        pw[I] = pw[P] + mul(Rw[P], r);
+      }
+    }
+    // user body axes: Rw C^T
+    const float* C = t + I * kBodyStride + kOffC;
+    M3 Cm;
+#pragma unroll
+    for (int e = 0; e < 9; ++e) Cm.a[e] = C[e];
+    const M3 Ro = cidx<TP::free_body(I) ? 1 : 0> ? Rw[I] : mulMMT(Rw[I], Cm);
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) T(12 * I + 4 * r + c, Ro.a[3 * r + c]);
+      T(12 * I + 4 * r + 3, r == 0 ? pw[I].x : (r == 1 ? pw[I].y : pw[I].z));
+    }
+  });
+}
+
+// =================================================================== Jacobian
+template <class TP>
+RBD_DI void jac_lane(const float* __restrict__ t, const In& q, const JacSlots& js, float* __restrict__ J,
+                     int64_t ld) {
+  constexpr int N = TP::N, NV = TP::NV;
+  M3 Rw[N];
+  V3 pw[N];
+  sfor<0, N>([&](auto K_) __attribute__((always_inline)) {
+    constexpr int K = decltype(K_)::value;
+    constexpr int P = TP::parent(K);
+    if constexpr (TP::free_body(K)) {
+      Rw[K] = quat_rot(q(3), q(4), q(5), q(6));
+      pw[K] = {q(0), q(1), q(2)};
+    } else {
+      const M3 R = joint_rot<K>(t, q(cidx<TP::qofs(K)>));
+      const V3 r = load_r<K>(t);
+      if constexpr (P < 0) {
+        Rw[K] = R;
+        pw[K] = r;
+      } else {
+        Rw[K] = mulMM(Rw[P], R);
+        pw[K] = pw[P] + mul(Rw[P], r);
+      }
+    }
+    const int beg = js.beg[K], end = js.beg[K + 1];
+    for (int s = beg; s < end; ++s) {
+      float* __restrict__ Jf = J + (int64_t)js.slot[s] * 6 * NV * ld;
+      auto put = [&](int r, int c, float v) __attribute__((always_inline)) { Jf[(int64_t)(r * NV + c) * ld] = v; };
+      sfor<0, N>([&](auto A_) __attribute__((always_inline)) {
+        constexpr int A = decltype(A_)::value;
+        constexpr int c0 = TP::vofs(A);
+        if constexpr (TP::is_anc(A, K)) {
+          const V3 d = pw[K] - pw[A];
+          if constexpr (TP::free_body(A)) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+              const V3 col = {Rw[A].a[c], Rw[A].a[3 + c], Rw[A].a[6 + c]};
+              const V3 lin = cross(col, d);
+              put(0, c0 + c, col.x); put(1, c0 + c, col.y); put(2, c0 + c, col.z);
+              put(3, c0 + c, 0.0f); put(4, c0 + c, 0.0f); put(5, c0 + c, 0.0f);
+              put(0, c0 + 3 + c, lin.x); put(1, c0 + 3 + c, lin.y); put(2, c0 + 3 + c, lin.z);
+              put(3, c0 + 3 + c, col.x); put(4, c0 + 3 + c, col.y); put(5, c0 + 3 + c, col.z);
+            }
+          } else {
+            const V3 z = {Rw[A].a[2], Rw[A].a[5], Rw[A].a[8]};
+            const V3 lin = cross(z, d);
+            put(0, c0, lin.x); put(1, c0, lin.y); put(2, c0, lin.z);
+            put(3, c0, z.x); put(4, c0, z.y); put(5, c0, z.z);
+          }
+        } else {
+#pragma unroll
+          for (int c = 0; c < cidx<TP::nvb(A)>; ++c)
+#pragma unroll
+            for (int r = 0; r < 6; ++r) put(r, c0 + c, 0.0f);
+        }
+      });
+    }
+  });
+}
+
+// =================================================================== RNEA
+// tau = ID(q, qd, qdd); qdd may be absent (bias force). Depth-first: the
+// backward step of a body runs as soon as its subtree is done, so only the
+// current root path is live.
+template <class TP, bool HAS_QDD>
+RBD_DI void rnea_lane(const float* __restrict__ t, const In& q, const In& qd, const In& qdd, const Out& tau) {
+  constexpr int N = TP::N;
+  M3 R[N];
+  Mot v[N], a[N];
+  Frc f[N];
+  const V3 g = load_g<TP>(t);
+  const V3 mg = {-g.x, -g.y, -g.z};
+
+  auto backward = [&](auto J_) __attribute__((always_inline)) {
+    constexpr int J = decltype(J_)::value;
+    constexpr int P = TP::parent(J);
+    if constexpr (TP::free_body(J)) {
+      tau(0, f[J].f.x); tau(1, f[J].f.y); tau(2, f[J].f.z);
+      tau(3, f[J].n.x); tau(4, f[J].n.y); tau(5, f[J].n.z);
+    } else {
+      tau(cidx<TP::vofs(J)>, f[J].n.z);
+      if constexpr (P >= 0) f[P] = f[P] + xfrc(R[J], load_r<J>(t), f[J]);
+    }
+  };
+
+  sfor<0, N>([&](auto I_) __attribute__((always_inline)) {
+    constexpr int I = decltype(I_)::value;
+    constexpr int P = TP::parent(I);
+    if constexpr (TP::free_body(I)) {
+      R[I] = quat_rot(q(3), q(4), q(5), q(6));
+      v[I] = {{qd(3), qd(4), qd(5)}, {qd(0), qd(1), qd(2)}};
+      a[I] = {{0.0f, 0.0f, 0.0f}, mulT(R[I], mg)};
+      if constexpr (HAS_QDD) a[I] = a[I] + Mot{{qdd(3), qdd(4), qdd(5)}, {qdd(0), qdd(1), qdd(2)}};
+    } else {
+      R[I] = joint_rot<I>(t, q(cidx<TP::qofs(I)>));
+      const float w = qd(cidx<TP::vofs(I)>);
+      if constexpr (P < 0) {
+        v[I] = {{0.0f, 0.0f, w}, {0.0f, 0.0f, 0.0f}};
+        a[I] = {{0.0f, 0.0f, 0.0f}, mulT(R[I], mg)};
+      } else {
+        const V3 r = load_r<I>(t);
+        v[I] = xmot(R[I], r, v[P]);
+        v[I].w.z = v[I].w.z + w;
+        a[I] = xmot(R[I], r, a[P]);
+        // + v x (S qd) = w * [wy, -wx, 0; vy, -vx, 0]
+        a[I].w.x = a[I].w.x + w * v[I].w.y;
+        a[I].w.y = a[I].w.y - w * v[I].w.x;
+        a[I].v.x = a[I].v.x + w * v[I].v.y;
+        a[I].v.y = a[I].v.y - w * v[I].v.x;
+      }
+      if constexpr (HAS_QDD) a[I].w.z = a[I].w.z + qdd(cidx<TP::vofs(I)>);
+    }
+    const Inr Ib = load_inr<I>(t);
+    f[I] = imul(Ib, a[I]) + crf(v[I], imul(Ib, v[I]));
+    // close every subtree that ends at I, deepest first
+    close_subtrees<TP, I, I>(backward);
+  });
+}
+
+
+// =================================================================== mass matrix rows
+// Row of M for revolute body J: M[k][k] and M[k][j] for every ancestor DoF j
+// (k = vofs(J)). F = Ic S is carried up the tree: F <- X^T F at each hop.
+template <class TP, int C, class EMIT>
+RBD_DI void walk_up(const float* __restrict__ t, const M3* R, Frc F, EMIT& emit) {
+  constexpr int A = TP::parent(C);
+  if constexpr (A >= 0) {
+    F = xfrc(R[C], load_r<C>(t), F);
+    emit(ic<A>{}, F);
+    walk_up<TP, A>(t, R, F, emit);
+  }
+}
+
+// Base block of M in [v; w] DoF order: [[m 1, [h]x^T], [[h]x, Ibar]].
+RBD_DI float base_block(const Inr& I, int r, int c) {
+  if (r < 3 && c < 3) return r == c ? I.m : 0.0f;
+  const float hx[9] = {0.0f, -I.h.z, I.h.y, I.h.z, 0.0f, -I.h.x, -I.h.y, I.h.x, 0.0f};
+  if (r >= 3 && c < 3) return hx[3 * (r - 3) + c];
+  if (r < 3 && c >= 3) return hx[3 * (c - 3) + r];
+  const float Ib[9] = {I.xx, I.xy, I.xz, I.xy, I.yy, I.yz, I.xz, I.yz, I.zz};
+  return Ib[3 * (r - 3) + (c - 3)];
+}
+
+// =================================================================== CRBA
+template <class TP>
+RBD_DI void crba_lane(const float* __restrict__ t, const In& q, float* __restrict__ Mp, int64_t ld) {
+  constexpr int N = TP::N, NV = TP::NV;
+  M3 R[N];
+  Inr Ic[N];
+  auto put = [&](int r, int c, float v) __attribute__((always_inline)) { Mp[(int64_t)(r * NV + c) * ld] = v; };
+
+  auto backward = [&](auto J_) __attribute__((always_inline)) {
+    constexpr int J = decltype(J_)::value;
+    constexpr int P = TP::parent(J);
+    if constexpr (TP::free_body(J)) {
+#pragma unroll
+      for (int r = 0; r < 6; ++r)
+#pragma unroll
+        for (int c = 0; c < 6; ++c) put(r, c, base_block(Ic[J], r, c));
+    } else {
+      constexpr int k = TP::vofs(J);
+      put(k, k, Ic[J].zz);
+      auto emit = [&](auto A_, const Frc& F) __attribute__((always_inline)) {
+        constexpr int A = decltype(A_)::value;
+        if constexpr (TP::free_body(A)) {
+          const float e[6] = {F.f.x, F.f.y, F.f.z, F.n.x, F.n.y, F.n.z};
+#pragma unroll
+          for (int c = 0; c < 6; ++c) { put(k, c, e[c]); put(c, k, e[c]); }
+        } else {
+          put(k, cidx<TP::vofs(A)>, F.n.z);
+          put(cidx<TP::vofs(A)>, k, F.n.z);
+        }
+      };
+      walk_up<TP, J>(t, R, inr_col_z(Ic[J]), emit);
+      if constexpr (P >= 0) Ic[P] = Ic[P] + xinr(R[J], load_r<J>(t), Ic[J]);
+    }
+  };
+
+  sfor<0, N>([&](auto I_) __attribute__((always_inline)) {
+    constexpr int I = decltype(I_)::value;
+    if constexpr (TP::free_body(I)) {
+      R[I] = quat_rot(q(3), q(4), q(5), q(6));  // unused by M; kept for uniformity
+    } else {
+      R[I] = joint_rot<I>(t, q(cidx<TP::qofs(I)>));
+    }
+    Ic[I] = load_inr<I>(t);
+    close_subtrees<TP, I, I>(backward);
+  });
+  // entries between DoFs of which neither is an ancestor of the other are zero
+  sfor<0, NV>([&](auto K_) __attribute__((always_inline)) {
+    constexpr int K = decltype(K_)::value;
+    sfor<0, NV>([&](auto L_) __attribute__((always_inline)) {
+      constexpr int L = decltype(L_)::value;
+      if constexpr (L != K && !TP::is_danc(L, K) && !TP::is_danc(K, L)) put(K, L, 0.0f);
+    });
+  });
+}
+
+// =================================================================== forward dynamics
+// qdd = M^-1 (tau - h) for NRHS right-hand sides (the second one, when asked,
+// is an extra vector solved with the same factor). One depth-first sweep runs
+// the RNEA forward step (bias accelerations and forces) on the way down; each
+// closed subtree then does, leaves to root:
+//   h_k = S^T f, f_parent += X^T f                       (RNEA backward)
+//   row k of M from F = Ic S carried up, Ic_parent += X^T Ic X   (CRBA)
+//   row k of the factor M = L^T L (left-looking, branch-sparse: entries only
+//   for ancestors, no fill-in), and y_k of L^T y = b      (sparse Cholesky)
+// and a final root-to-leaves sweep solves L x = y.
+template <class TP, int NRHS, class RHS, class SINK>
+RBD_DI void fwd_dyn_lane(const float* __restrict__ t, const In& q, const In& qd, const RHS& rhs, const SINK& sink) {
+  constexpr int N = TP::N, NV = TP::NV;
+  constexpr int NNZ = TP::nnz() > 0 ? TP::nnz() : 1;
+  M3 R[N];
+  Mot v[N], a[N];
+  Frc f[N];
+  Inr Ic[N];
+  float L[NNZ];
+  float Linv[NV];
+  float y[NRHS][NV];
+  const V3 g = load_g<TP>(t);
+  const V3 mg = {-g.x, -g.y, -g.z};
+
+  // Row k of L^T L given row k of M (Mr[j] for ancestors j, Mkk) and b_k.
+  auto factor_row = [&](auto K_, const float* Mr, float Mkk, const float* bk) __attribute__((always_inline)) {
+    constexpr int K = decltype(K_)::value;
+    float D = Mkk;
+    sfor<K + 1, NV>([&](auto D_) __attribute__((always_inline)) {
+      constexpr int Dd = decltype(D_)::value;
+      if constexpr (TP::is_danc(K, Dd)) D = D - L[cidx<TP::lidx(Dd, K)>] * L[cidx<TP::lidx(Dd, K)>];
+    });
+    const float inv = frsq(D);
+    Linv[K] = inv;
+    sfor<0, K>([&](auto J_) __attribute__((always_inline)) {
+      constexpr int Jd = decltype(J_)::value;
+      if constexpr (TP::is_danc(Jd, K)) {
+        float acc = Mr[Jd];
+        sfor<K + 1, NV>([&](auto D_) __attribute__((always_inline)) {
+          constexpr int Dd = decltype(D_)::value;
+          if constexpr (TP::is_danc(K, Dd)) acc = acc - L[cidx<TP::lidx(Dd, K)>] * L[cidx<TP::lidx(Dd, Jd)>];
+        });
+        L[cidx<TP::lidx(K, Jd)>] = acc * inv;
+      }
+    });
+    sfor<0, NRHS>([&](auto R_) __attribute__((always_inline)) {
+      constexpr int r = decltype(R_)::value;
+      float acc = bk[r];
+      sfor<K + 1, NV>([&](auto D_) __attribute__((always_inline)) {
+        constexpr int Dd = decltype(D_)::value;
+        if constexpr (TP::is_danc(K, Dd)) acc = acc - L[cidx<TP::lidx(Dd, K)>] * y[r][Dd];
+      });
+      y[r][K] = acc * inv;
+    });
+  };
+
+  auto backward = [&](auto J_) __attribute__((always_inline)) {
+    constexpr int J = decltype(J_)::value;
+    constexpr int P = TP::parent(J);
+    if constexpr (TP::free_body(J)) {
+      const float hb[6] = {f[J].f.x, f[J].f.y, f[J].f.z, f[J].n.x, f[J].n.y, f[J].n.z};
+      sfor_rev<0, 6>([&](auto K_) __attribute__((always_inline)) {
+        constexpr int K = decltype(K_)::value;
+        float Mr[6];
+#pragma unroll
+        for (int j = 0; j < K; ++j) Mr[j] = base_block(Ic[J], K, j);
+        float bk[NRHS];
+#pragma unroll
+        for (int r = 0; r < NRHS; ++r) bk[r] = rhs(r, K) - (r == 0 ? hb[K] : 0.0f);
+        factor_row(K_, Mr, base_block(Ic[J], K, K), bk);
+      });
+    } else {
+      constexpr int k = TP::vofs(J);
+      float Mr[NV > 1 ? NV : 1];
+      auto emit = [&](auto A_, const Frc& F) __attribute__((always_inline)) {
+        constexpr int A = decltype(A_)::value;
+        if constexpr (TP::free_body(A)) {
+          Mr[0] = F.f.x; Mr[1] = F.f.y; Mr[2] = F.f.z;
+          Mr[3] = F.n.x; Mr[4] = F.n.y; Mr[5] = F.n.z;
+        } else {
+          Mr[cidx<TP::vofs(A)>] = F.n.z;
+        }
+      };
+      walk_up<TP, J>(t, R, inr_col_z(Ic[J]), emit);
+      float bk[NRHS];
+#pragma unroll
+      for (int r = 0; r < NRHS; ++r) bk[r] = rhs(r, k) - (r == 0 ? f[J].n.z : 0.0f);
+      factor_row(ic<k>{}, Mr, Ic[J].zz, bk);
+      if constexpr (P >= 0) {
+        const V3 r = load_r<J>(t);
+        f[P] = f[P] + xfrc(R[J], r, f[J]);
+        Ic[P] = Ic[P] + xinr(R[J], r, Ic[J]);
+      }
+    }
+  };
+
+  sfor<0, N>([&](auto I_) __attribute__((always_inline)) {
+    constexpr int I = decltype(I_)::value;
+    constexpr int P = TP::parent(I);
+    if constexpr (TP::free_body(I)) {
+      R[I] = quat_rot(q(3), q(4), q(5), q(6));
+      v[I] = {{qd(3), qd(4), qd(5)}, {qd(0), qd(1), qd(2)}};
+      a[I] = {{0.0f, 0.0f, 0.0f}, mulT(R[I], mg)};
+    } else {
+      R[I] = joint_rot<I>(t, q(cidx<TP::qofs(I)>));
+      const float w = qd(cidx<TP::vofs(I)>);
+      if constexpr (P < 0) {
+        v[I] = {{0.0f, 0.0f, w}, {0.0f, 0.0f, 0.0f}};
+        a[I] = {{0.0f, 0.0f, 0.0f}, mulT(R[I], mg)};
+      } else {
+        const V3 r = load_r<I>(t);
+        v[I] = xmot(R[I], r, v[P]);
+        v[I].w.z = v[I].w.z + w;
+        a[I] = xmot(R[I], r, a[P]);
+        a[I].w.x = a[I].w.x + w * v[I].w.y;
+        a[I].w.y = a[I].w.y - w * v[I].w.x;
+        a[I].v.x = a[I].v.x + w * v[I].v.y;
+        a[I].v.y = a[I].v.y - w * v[I].v.x;
+      }
+    }
+    const Inr Ib = load_inr<I>(t);
+    f[I] = imul(Ib, a[I]) + crf(v[I], imul(Ib, v[I]));
+    Ic[I] = Ib;
+    close_subtrees<TP, I, I>(backward);
+  });
+
+  // L x = y, root to leaves
+  sfor<0, NRHS>([&](auto R_) __attribute__((always_inline)) {
+    constexpr int r = decltype(R_)::value;
+    float x[NV];
+    sfor<0, NV>([&](auto K_) __attribute__((always_inline)) {
+      constexpr int K = decltype(K_)::value;
+      float acc = y[r][K];
+      sfor<0, K>([&](auto J_) __attribute__((always_inline)) {
+        constexpr int Jd = decltype(J_)::value;
+        if constexpr (TP::is_danc(Jd, K)) acc = acc - L[cidx<TP::lidx(K, Jd)>] * x[Jd];
+      });
+      x[K] = acc * Linv[K];
+      sink(r, K, x[K]);
+    });
+  });
+}
+
+// =================================================================== fwd_dyn adjoint
+// Reverse-mode derivative of inverse dynamics: given (q, qd, qdd) and the
+// cotangent lam of tau, accumulate dq = (dID/dq)^T lam and dqd = (dID/dqd)^T
+// lam. With lam = M^-1 gbar and qdd = FD(q, qd, tau), -dq and -dqd are the
+// fwd_dyn cotangents (implicit differentiation of ID(q, qd, FD) = tau).
+//
+// Forward (root to leaves), besides v, a, f:
+//   mu_i = X_i mu_parent + S_i lam_i   (cotangent of the total force of body i)
+// Backward (subtree closed), with totals f, abar = I mu + sum X^T abar_child,
+//   vbar = I (mu x v) - mu x* (I v) + (S qd) x* abar + sum X^T vbar_child:
+//   dq_i  = <vbar, dX/dq v_parent> + <abar, dX/dq a_parent> + <X mu_parent, S x* f>
+//         with dX/dq = -(S x) X,
+//   dqd_i = S^T vbar - S^T (v x* abar).
+// For a free base only gravity a_0 = R^T (-g) depends on q (through the
+// quaternion); its position never enters body-frame dynamics.
+template <class TP, class QDD, class LAM, class GQ, class GQD>
+RBD_DI void id_adjoint_lane(const float* __restrict__ t, const In& q, const In& qd, const QDD& qdd, const LAM& lam,
+                            const GQ& gq, const GQD& gqd) {
+  constexpr int N = TP::N;
+  M3 R[N];
+  Mot v[N], a[N], mu[N];
+  float ap[N][4];  // (X a_parent) w.x, w.y, v.x, v.y
+  Frc f[N], ab[N], vb[N];
+  const V3 g = load_g<TP>(t);
+  const V3 mg = {-g.x, -g.y, -g.z};
+
+  auto backward = [&](auto J_) __attribute__((always_inline)) {
+    constexpr int J = decltype(J_)::value;
+    constexpr int P = TP::parent(J);
+    const Inr Ib = load_inr<J>(t);
+    const Frc abar = imul(Ib, mu[J]) + ab[J];
+    Frc vbar = imul(Ib, crm(mu[J], v[J])) - crf(mu[J], imul(Ib, v[J])) + vb[J];
+    if constexpr (TP::free_body(J)) {
+      gqd(0, -vbar.f.x); gqd(1, -vbar.f.y); gqd(2, -vbar.f.z);
+      gqd(3, -vbar.n.x); gqd(4, -vbar.n.y); gqd(5, -vbar.n.z);
+      // d/dquat of <abar.f, R^T(-g)> = -g^T R abar, with R = N(quat) / |quat|^2
+      const float w = q(3), x = q(4), y = q(5), z = q(6);
+      const float s = frcp(w * w + x * x + y * y + z * z);
+      const V3 u = {x, y, z}, A = abar.f;
+      const float gA = dot(g, A), uA = dot(u, A), gu = dot(g, u);
+      const V3 axg = cross(A, g);
+      const float gRA = dot(g, mul(R[J], A));  // g^T R abar
+      const float dw = 2.0f * w * gA + 2.0f * dot(u, axg);
+      const float dx = -2.0f * x * gA + 2.0f * g.x * uA + 2.0f * gu * A.x + 2.0f * w * axg.x;
+      const float dy = -2.0f * y * gA + 2.0f * g.y * uA + 2.0f * gu * A.y + 2.0f * w * axg.y;
+      const float dz = -2.0f * z * gA + 2.0f * g.z * uA + 2.0f * gu * A.z + 2.0f * w * axg.z;
+      // dPhi/dquat_k = -(g^T dN/dquat_k abar - 2 quat_k g^T R abar) / |quat|^2; output -dPhi
+      gq(0, 0.0f); gq(1, 0.0f); gq(2, 0.0f);
+      gq(3, (dw - 2.0f * w * gRA) * s);
+      gq(4, (dx - 2.0f * x * gRA) * s);
+      gq(5, (dy - 2.0f * y * gRA) * s);
+      gq(6, (dz - 2.0f * z * gRA) * s);
+    } else {
+      const float w = qd(cidx<TP::vofs(J)>);
+      // (S qd) x* abar = w [(-n_y, n_x, 0); (-f_y, f_x, 0)]
+      vbar.n.x = vbar.n.x - w * abar.n.y;
+      vbar.n.y = vbar.n.y + w * abar.n.x;
+      vbar.f.x = vbar.f.x - w * abar.f.y;
+      vbar.f.y = vbar.f.y + w * abar.f.x;
+      // S^T (v x* abar) = z of (w x n + v x f)
+      const float vxa = v[J].w.x * abar.n.y - v[J].w.y * abar.n.x + v[J].v.x * abar.f.y - v[J].v.y * abar.f.x;
+      gqd(cidx<TP::vofs(J)>, -(vbar.n.z - vxa));
+      // <vbar, -S x (X v_p)>: (X v_p) has the x, y parts of v
+      float dq = vbar.n.x * v[J].w.y - vbar.n.y * v[J].w.x + vbar.f.x * v[J].v.y - vbar.f.y * v[J].v.x;
+      dq = dq + abar.n.x * ap[J][1] - abar.n.y * ap[J][0] + abar.f.x * ap[J][3] - abar.f.y * ap[J][2];
+      if constexpr (P >= 0) {
+        // <X mu_p, S x* f>: (X mu_p) has the x, y parts of mu
+        dq = dq - mu[J].w.x * f[J].n.y + mu[J].w.y * f[J].n.x - mu[J].v.x * f[J].f.y + mu[J].v.y * f[J].f.x;
+        const V3 r = load_r<J>(t);
+        f[P] = f[P] + xfrc(R[J], r, f[J]);
+        ab[P] = ab[P] + xfrc(R[J], r, abar);
+        vb[P] = vb[P] + xfrc(R[J], r, vbar);
+      }
+      gq(cidx<TP::qofs(J)>, -dq);
+    }
+  };
+
+  sfor<0, N>([&](auto I_) __attribute__((always_inline)) {
+    constexpr int I = decltype(I_)::value;
+    constexpr int P = TP::parent(I);
+    if constexpr (TP::free_body(I)) {
+      R[I] = quat_rot(q(3), q(4), q(5), q(6));
+      v[I] = {{qd(3), qd(4), qd(5)}, {qd(0), qd(1), qd(2)}};
+      a[I] = {{qdd(3), qdd(4), qdd(5)}, mulT(R[I], mg) + V3{qdd(0), qdd(1), qdd(2)}};
+      mu[I] = {{lam(3), lam(4), lam(5)}, {lam(0), lam(1), lam(2)}};
+    } else {
+      R[I] = joint_rot<I>(t, q(cidx<TP::qofs(I)>));
+      const float w = qd(cidx<TP::vofs(I)>);
+      Mot apI;
+      if constexpr (P < 0) {
+        v[I] = {{0.0f, 0.0f, w}, {0.0f, 0.0f, 0.0f}};
+        apI = {{0.0f, 0.0f, 0.0f}, mulT(R[I], mg)};
+        mu[I] = {{0.0f, 0.0f, 0.0f}, {0.0f, 0.0f, 0.0f}};
+      } else {
+        const V3 r = load_r<I>(t);
+        v[I] = xmot(R[I], r, v[P]);
+        v[I].w.z = v[I].w.z + w;
+        apI = xmot(R[I], r, a[P]);
+        mu[I] = xmot(R[I], r, mu[P]);
+      }
+      ap[I][0] = apI.w.x; ap[I][1] = apI.w.y; ap[I][2] = apI.v.x; ap[I][3] = apI.v.y;
+      a[I] = apI;
+      a[I].w.z = a[I].w.z + qdd(cidx<TP::vofs(I)>);
+      a[I].w.x = a[I].w.x + w * v[I].w.y;
+      a[I].w.y = a[I].w.y - w * v[I].w.x;
+      a[I].v.x = a[I].v.x + w * v[I].v.y;
+      a[I].v.y = a[I].v.y - w * v[I].v.x;
+      mu[I].w.z = mu[I].w.z + lam(cidx<TP::vofs(I)>);
+    }
+    const Inr Ib = load_inr<I>(t);
+    f[I] = imul(Ib, a[I]) + crf(v[I], imul(Ib, v[I]));
+    ab[I] = Frc{{0.0f, 0.0f, 0.0f}, {0.0f, 0.0f, 0.0f}};
+    vb[I] = Frc{{0.0f, 0.0f, 0.0f}, {0.0f, 0.0f, 0.0f}};
+    close_subtrees<TP, I, I>(backward);
+  });
+}
+
+}  // namespace rbd

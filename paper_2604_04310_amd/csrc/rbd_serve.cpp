@@ -1,0 +1,554 @@
+// Continuous-batching service for dynamics requests.
+//
+// Requests (model, operation, batch, host buffers) queue in arrival order. A
+// dispatcher thread forms a launch group from the oldest request's (model,
+// operation) class: as many queued requests of that class as fit the largest
+// free block of the device arena (admission by device memory) and the free
+// launch slots. A group is one block of the arena holding all of its inputs,
+// then all of its outputs; it costs one host-to-device copy, one packed launch
+// (every request of the group at once, tiles of 64 instances) and one
+// device-to-host copy. The packed launch has a fixed grid of persistent waves
+// that read the tile table from device memory, so one captured HIP graph per
+// (slot, class, grid size) replays it for any group. Up to n_streams groups
+// are in flight on their own streams, so requests that arrive while others run
+// are admitted as memory and slots free up, and their work overlaps on the GPU.
+// A completion thread polls the groups' events, copies the results into the
+// clients' buffers, frees the arena block and records each request's latency
+// (submit to results in host memory).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <thread>
+#include <tuple>
+#include <unordered_map>
+#include <vector>
+
+#include "rbd_internal.hpp"
+
+namespace rbd {
+namespace {
+
+using Clock = std::chrono::steady_clock;
+constexpr size_t kAlign = 256;
+constexpr int kMaxTilesPerGroup = 16384;  // 1 M instances per launch
+constexpr int kGridClasses[] = {4, 32, 256, 1024};
+inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+struct Request {
+  uint64_t ticket = 0;
+  const rbd_model* model = nullptr;
+  int op = 0;
+  int64_t batch = 0;
+  int n_in = 0, n_out = 0;
+  const float* in[4] = {nullptr, nullptr, nullptr, nullptr};
+  float* out[3] = {nullptr, nullptr, nullptr};
+  size_t in_n[4] = {0, 0, 0, 0};  // floats per array
+  size_t out_n[3] = {0, 0, 0};
+  size_t in_bytes = 0, out_bytes = 0;
+  Clock::time_point t_submit;
+  bool done = false;
+  rbd_status status = RBD_OK;
+};
+
+// The rows per instance of every array of an operation.
+void shape_of(const rbd_model* m, int op, int* n_in, int in_rows[4], int* n_out, int out_rows[3]) {
+  if (op == RBD_OP_FWD_DYN || op == RBD_OP_RNEA) {
+    *n_in = 3; in_rows[0] = m->nq; in_rows[1] = m->nv; in_rows[2] = m->nv;
+    *n_out = 1; out_rows[0] = m->nv;
+  } else {
+    *n_in = 4; in_rows[0] = m->nq; in_rows[1] = m->nv; in_rows[2] = m->nv; in_rows[3] = m->nv;
+    *n_out = 3; out_rows[0] = m->nq; out_rows[1] = m->nv; out_rows[2] = m->nv;
+  }
+}
+
+// First-fit allocator over [0, size) with coalescing of neighbours.
+class Arena {
+ public:
+  void init(size_t size) {
+    free_.clear();
+    free_[0] = size;
+  }
+  bool alloc(size_t bytes, size_t* off) {
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+      if (it->second >= bytes) {
+        *off = it->first;
+        const size_t rest = it->second - bytes;
+        const size_t noff = it->first + bytes;
+        free_.erase(it);
+        if (rest) free_[noff] = rest;
+        return true;
+      }
+    }
+    return false;
+  }
+  void release(size_t off, size_t bytes) {
+    auto it = free_.emplace(off, bytes).first;
+    auto next = std::next(it);
+    if (next != free_.end() && it->first + it->second == next->first) {
+      it->second += next->second;
+      free_.erase(next);
+    }
+    if (it != free_.begin()) {
+      auto prev = std::prev(it);
+      if (prev->first + prev->second == it->first) {
+        prev->second += it->second;
+        free_.erase(it);
+      }
+    }
+  }
+  size_t largest() const {
+    size_t m = 0;
+    for (auto& kv : free_) m = std::max(m, kv.second);
+    return m;
+  }
+
+ private:
+  std::map<size_t, size_t> free_;
+};
+
+struct Group {
+  int slot = -1;
+  const rbd_model* model = nullptr;
+  int op = 0;
+  std::vector<std::shared_ptr<Request>> reqs;
+  size_t off = 0, bytes = 0, in_bytes = 0, out_off = 0, out_bytes = 0;
+  std::vector<size_t> in_pos, out_pos;  // per request, offsets inside the block
+  int n_tiles = 0;
+  rbd_status status = RBD_OK;
+};
+
+struct Slot {
+  hipStream_t stream = nullptr;
+  hipEvent_t done = nullptr;
+  uint8_t* d_table = nullptr;
+  uint8_t* h_table = nullptr;
+  bool busy = false;
+  std::map<std::tuple<const rbd_model*, int, int>, hipGraphExec_t> graphs;
+};
+
+size_t table_capacity(int max_req) {
+  return align_up(sizeof(PackedHdr) + sizeof(int32_t) * kMaxTilesPerGroup) + sizeof(PackedReq) * (size_t)max_req;
+}
+
+}  // namespace
+}  // namespace rbd
+
+using namespace rbd;
+
+struct rbd_server {
+  rbd_server_config cfg{};
+  uint8_t* d_arena = nullptr;
+  uint8_t* h_stage = nullptr;
+  Arena arena;
+  std::vector<Slot> slots;
+  std::mutex mu;
+  std::condition_variable cv_work, cv_done;
+  std::deque<std::shared_ptr<Request>> pending;
+  std::unordered_map<uint64_t, std::shared_ptr<Request>> tickets;
+  std::vector<Group*> inflight;
+  uint64_t next_ticket = 1;
+  bool stop = false, dispatcher_done = false;
+  std::thread dispatcher, completer;
+  // statistics
+  std::vector<double> lat_us;
+  uint64_t n_req = 0, n_inst = 0, n_launch = 0;
+  double busy_s = 0.0;
+  Clock::time_point busy_since;
+};
+
+namespace rbd {
+namespace {
+
+int free_slot(rbd_server* s) {
+  for (size_t i = 0; i < s->slots.size(); ++i)
+    if (!s->slots[i].busy) return (int)i;
+  return -1;
+}
+
+// Takes the oldest request's class and every queued request of that class that
+// fits; returns nullptr when the head cannot be admitted yet. Caller holds mu.
+Group* form_group(rbd_server* s) {
+  if (s->pending.empty()) return nullptr;
+  const auto head = s->pending.front();
+  const size_t budget = s->arena.largest();
+  const int max_req = s->cfg.per_request ? 1 : s->cfg.max_batch_requests;
+  auto* g = new Group;
+  g->model = head->model;
+  g->op = head->op;
+  size_t in_total = 0, out_total = 0;
+  int tiles = 0;
+  for (auto it = s->pending.begin(); it != s->pending.end() && (int)g->reqs.size() < max_req;) {
+    const auto& r = *it;
+    if (r->model != g->model || r->op != g->op) { ++it; continue; }
+    const int rt = (int)((r->batch + kTileLanes - 1) / kTileLanes);
+    if (tiles + rt > kMaxTilesPerGroup) break;
+    if (align_up(in_total + r->in_bytes) + out_total + r->out_bytes > budget) break;
+    in_total += r->in_bytes;
+    out_total += r->out_bytes;
+    tiles += rt;
+    g->reqs.push_back(r);
+    it = s->pending.erase(it);
+  }
+  if (g->reqs.empty()) {
+    delete g;
+    return nullptr;
+  }
+  g->in_bytes = in_total;
+  g->out_off = align_up(in_total);
+  g->out_bytes = out_total;
+  g->bytes = g->out_off + out_total;
+  g->n_tiles = tiles;
+  if (!s->arena.alloc(g->bytes, &g->off)) {  // cannot happen: budget is the largest block
+    for (auto rit = g->reqs.rbegin(); rit != g->reqs.rend(); ++rit) s->pending.push_front(*rit);
+    delete g;
+    return nullptr;
+  }
+  return g;
+}
+
+int grid_class(int n_tiles) {
+  const int blocks_needed = (n_tiles * kTileLanes + 255) / 256;
+  for (int g : kGridClasses)
+    if (g >= blocks_needed) return g;
+  return kGridClasses[sizeof(kGridClasses) / sizeof(int) - 1];
+}
+
+// Stage, launch and queue the copy-back of one group (dispatcher thread, no lock).
+rbd_status launch_group(rbd_server* s, Group* g) {
+  Slot& sl = s->slots[g->slot];
+  uint8_t* hb = s->h_stage + g->off;
+  uint8_t* db = s->d_arena + g->off;
+  // pack inputs (instance-major, as given) and the tile table
+  PackedHdr* hdr = reinterpret_cast<PackedHdr*>(sl.h_table);
+  int32_t* tile_req = reinterpret_cast<int32_t*>(sl.h_table + sizeof(PackedHdr));
+  const int32_t req_off = (int32_t)align_up(sizeof(PackedHdr) + sizeof(int32_t) * g->n_tiles);
+  PackedReq* reqs = reinterpret_cast<PackedReq*>(sl.h_table + req_off);
+  size_t ipos = 0, opos = g->out_off;
+  int tile = 0;
+  for (size_t k = 0; k < g->reqs.size(); ++k) {
+    const Request& r = *g->reqs[k];
+    PackedReq pr{};
+    for (int a = 0; a < r.n_in; ++a) {
+      std::memcpy(hb + ipos, r.in[a], r.in_n[a] * sizeof(float));
+      pr.in[a] = reinterpret_cast<const float*>(db + ipos);
+      ipos += r.in_n[a] * sizeof(float);
+    }
+    for (int a = 0; a < r.n_out; ++a) {
+      pr.out[a] = reinterpret_cast<float*>(db + opos);
+      opos += r.out_n[a] * sizeof(float);
+    }
+    pr.batch = (int32_t)r.batch;
+    pr.first_tile = tile;
+    const int rt = (int)((r.batch + kTileLanes - 1) / kTileLanes);
+    for (int t = 0; t < rt; ++t) tile_req[tile++] = (int32_t)k;
+    reqs[k] = pr;
+  }
+  hdr->n_tiles = g->n_tiles;
+  hdr->n_req = (int32_t)g->reqs.size();
+  hdr->req_offset = req_off;
+  hdr->pad = 0;
+  const size_t table_bytes = req_off + sizeof(PackedReq) * g->reqs.size();
+  hipStream_t st = sl.stream;
+  if (hipMemcpyAsync(db, hb, g->in_bytes, hipMemcpyHostToDevice, st) != hipSuccess ||
+      hipMemcpyAsync(sl.d_table, sl.h_table, table_bytes, hipMemcpyHostToDevice, st) != hipSuccess)
+    return fail(RBD_E_LAUNCH, "server: input copy failed");
+  const int grid = s->cfg.per_request ? std::max(1, (g->n_tiles * kTileLanes + 255) / 256) : grid_class(g->n_tiles);
+  rbd_status rs = RBD_OK;
+  if (s->cfg.use_graphs && !s->cfg.per_request) {
+    auto key = std::make_tuple(g->model, g->op, grid);
+    auto it = sl.graphs.find(key);
+    if (it == sl.graphs.end()) {
+      hipGraph_t graph = nullptr;
+      hipGraphExec_t exec = nullptr;
+      if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess)
+        return fail(RBD_E_LAUNCH, "server: stream capture failed");
+      rs = launch_packed(g->model, g->op, sl.d_table, grid, st);
+      const hipError_t ce = hipStreamEndCapture(st, &graph);
+      if (rs != RBD_OK || ce != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return rs != RBD_OK ? rs : fail(RBD_E_LAUNCH, "server: stream capture failed");
+      }
+      const hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(graph);
+      if (ie != hipSuccess) return fail(RBD_E_LAUNCH, "server: graph instantiation failed");
+      it = sl.graphs.emplace(key, exec).first;
+    }
+    if (hipGraphLaunch(it->second, st) != hipSuccess) return fail(RBD_E_LAUNCH, "server: graph launch failed");
+  } else {
+    rs = launch_packed(g->model, g->op, sl.d_table, grid, st);
+    if (rs != RBD_OK) return rs;
+  }
+  if (hipMemcpyAsync(hb + g->out_off, db + g->out_off, g->out_bytes, hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipEventRecord(sl.done, st) != hipSuccess)
+    return fail(RBD_E_LAUNCH, "server: result copy failed");
+  return RBD_OK;
+}
+
+void finish_group(rbd_server* s, Group* g, const Clock::time_point now) {
+  // results -> client buffers (instance-major, as requested)
+  if (g->status == RBD_OK) {
+    const uint8_t* hb = s->h_stage + g->off;
+    size_t opos = g->out_off;
+    for (auto& rp : g->reqs) {
+      Request& r = *rp;
+      for (int a = 0; a < r.n_out; ++a) {
+        std::memcpy(r.out[a], hb + opos, r.out_n[a] * sizeof(float));
+        opos += r.out_n[a] * sizeof(float);
+      }
+    }
+  }
+  std::lock_guard<std::mutex> lk(s->mu);
+  s->arena.release(g->off, g->bytes);
+  s->slots[g->slot].busy = false;
+  for (auto& rp : g->reqs) {
+    rp->status = g->status;
+    rp->done = true;
+    s->lat_us.push_back(std::chrono::duration<double, std::micro>(now - rp->t_submit).count());
+    s->n_req++;
+    s->n_inst += (uint64_t)rp->batch;
+  }
+  s->n_launch++;
+  s->inflight.erase(std::find(s->inflight.begin(), s->inflight.end(), g));
+  if (s->inflight.empty()) s->busy_s += std::chrono::duration<double>(now - s->busy_since).count();
+  delete g;
+  s->cv_done.notify_all();
+  s->cv_work.notify_all();
+}
+
+void dispatcher_main(rbd_server* s) {
+  (void)hipSetDevice(s->cfg.device);
+  std::unique_lock<std::mutex> lk(s->mu);
+  for (;;) {
+    if (s->pending.empty()) {
+      if (s->stop) break;
+      s->cv_work.wait(lk);
+      continue;
+    }
+    if (free_slot(s) < 0) {
+      s->cv_work.wait(lk);
+      continue;
+    }
+    // gather window: give a young head a moment to collect company
+    if (s->cfg.max_wait_us > 0 && !s->cfg.per_request && !s->stop) {
+      const auto ready = s->pending.front()->t_submit +
+                         std::chrono::duration_cast<Clock::duration>(std::chrono::duration<double, std::micro>(s->cfg.max_wait_us));
+      if (Clock::now() < ready && (int)s->pending.size() < s->cfg.max_batch_requests) {
+        s->cv_work.wait_until(lk, ready);
+        continue;
+      }
+    }
+    Group* g = form_group(s);
+    if (!g) {  // the head does not fit the free memory yet: wait for a completion
+      s->cv_work.wait(lk);
+      continue;
+    }
+    g->slot = free_slot(s);
+    s->slots[g->slot].busy = true;
+    lk.unlock();
+    g->status = launch_group(s, g);
+    lk.lock();
+    if (s->inflight.empty()) s->busy_since = Clock::now();
+    s->inflight.push_back(g);
+    if (g->status != RBD_OK) {
+      lk.unlock();
+      finish_group(s, g, Clock::now());
+      lk.lock();
+    }
+  }
+  s->dispatcher_done = true;
+  s->cv_work.notify_all();
+}
+
+void completer_main(rbd_server* s) {
+  (void)hipSetDevice(s->cfg.device);
+  std::unique_lock<std::mutex> lk(s->mu);
+  for (;;) {
+    if (s->inflight.empty()) {
+      if (s->dispatcher_done) break;
+      s->cv_work.wait_for(lk, std::chrono::milliseconds(1));
+      continue;
+    }
+    std::vector<Group*> look(s->inflight.begin(), s->inflight.end());
+    lk.unlock();
+    bool any = false;
+    for (Group* g : look) {
+      if (g->status != RBD_OK) continue;  // failed groups are finished by the dispatcher
+      const hipError_t e = hipEventQuery(s->slots[g->slot].done);
+      if (e == hipErrorNotReady) continue;
+      if (e != hipSuccess) g->status = fail(RBD_E_LAUNCH, "server: launch failed on the device");
+      finish_group(s, g, Clock::now());
+      any = true;
+    }
+    if (!any) std::this_thread::yield();
+    lk.lock();
+  }
+}
+
+}  // namespace
+}  // namespace rbd
+
+extern "C" {
+
+rbd_status rbd_server_create(const rbd_server_config* cfg, rbd_server** out) {
+  if (!out) return fail(RBD_E_INVAL, "out is NULL");
+  *out = nullptr;
+  if (!cfg) return fail(RBD_E_INVAL, "config is NULL");
+  if (cfg->n_streams < 1 || cfg->n_streams > 8) return fail(RBD_E_INVAL, "n_streams = %d, expected 1..8", cfg->n_streams);
+  if (cfg->max_batch_requests < 1 || cfg->max_batch_requests > kMaxPacked)
+    return fail(RBD_E_INVAL, "max_batch_requests = %d, expected 1..%d", cfg->max_batch_requests, kMaxPacked);
+  if (cfg->arena_bytes < (1u << 16)) return fail(RBD_E_INVAL, "arena_bytes must be at least 64 KiB");
+  if (!(cfg->max_wait_us >= 0.0)) return fail(RBD_E_INVAL, "max_wait_us must be >= 0");
+  const int ndev = rbd_device_count();
+  if (cfg->device < 0 || cfg->device >= ndev) return fail(RBD_E_NODEVICE, "device %d is not available", cfg->device);
+  if (hipSetDevice(cfg->device) != hipSuccess) return fail(RBD_E_NODEVICE, "cannot select device %d", cfg->device);
+  auto* s = new (std::nothrow) rbd_server;
+  if (!s) return fail(RBD_E_NOMEM, "host allocation failed");
+  s->cfg = *cfg;
+  s->arena.init(cfg->arena_bytes);
+  bool ok = hipMalloc(&s->d_arena, cfg->arena_bytes) == hipSuccess &&
+            hipHostMalloc(&s->h_stage, cfg->arena_bytes, hipHostMallocDefault) == hipSuccess;
+  s->slots.resize(cfg->n_streams);
+  const size_t tcap = table_capacity(cfg->max_batch_requests);
+  for (auto& sl : s->slots) {
+    ok = ok && hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) == hipSuccess &&
+         hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) == hipSuccess &&
+         hipMalloc(&sl.d_table, tcap) == hipSuccess &&
+         hipHostMalloc(&sl.h_table, tcap, hipHostMallocDefault) == hipSuccess;
+  }
+  if (!ok) {
+    rbd_server_destroy(s);
+    return fail(RBD_E_NOMEM, "server: allocation of %zu arena bytes failed", cfg->arena_bytes);
+  }
+  s->dispatcher = std::thread(dispatcher_main, s);
+  s->completer = std::thread(completer_main, s);
+  *out = s;
+  return RBD_OK;
+}
+
+rbd_status rbd_server_submit(rbd_server* s, const rbd_model* m, int op, int64_t batch, const float* const* host_in,
+                             float* const* host_out, uint64_t* ticket) {
+  if (!s || !m || !host_in || !host_out || !ticket) return fail(RBD_E_INVAL, "rbd_server_submit: NULL argument");
+  if (op < RBD_OP_FWD_DYN || op > RBD_OP_FWD_DYN_VJP) return fail(RBD_E_INVAL, "rbd_server_submit: unknown op %d", op);
+  if (batch < 1 || batch > (int64_t)kMaxTilesPerGroup * kTileLanes)
+    return fail(RBD_E_INVAL, "rbd_server_submit: batch = %lld out of range", (long long)batch);
+  if (m->device != s->cfg.device) return fail(RBD_E_INVAL, "rbd_server_submit: model lives on another device");
+  auto r = std::make_shared<Request>();
+  int in_rows[4], out_rows[3];
+  shape_of(m, op, &r->n_in, in_rows, &r->n_out, out_rows);
+  for (int a = 0; a < r->n_in; ++a) {
+    if (!host_in[a]) return fail(RBD_E_INVAL, "rbd_server_submit: input %d is NULL", a);
+    r->in[a] = host_in[a];
+    r->in_n[a] = (size_t)in_rows[a] * (size_t)batch;
+    r->in_bytes += r->in_n[a] * sizeof(float);
+  }
+  for (int a = 0; a < r->n_out; ++a) {
+    if (!host_out[a]) return fail(RBD_E_INVAL, "rbd_server_submit: output %d is NULL", a);
+    r->out[a] = host_out[a];
+    r->out_n[a] = (size_t)out_rows[a] * (size_t)batch;
+    r->out_bytes += r->out_n[a] * sizeof(float);
+  }
+  if (align_up(r->in_bytes) + r->out_bytes > s->cfg.arena_bytes)
+    return fail(RBD_E_INVAL, "rbd_server_submit: request needs %zu bytes, more than the arena holds",
+                align_up(r->in_bytes) + r->out_bytes);
+  r->model = m;
+  r->op = op;
+  r->batch = batch;
+  std::lock_guard<std::mutex> lk(s->mu);
+  if (s->stop) return fail(RBD_E_SHUTDOWN, "rbd_server_submit: server is shutting down");
+  r->ticket = s->next_ticket++;
+  r->t_submit = Clock::now();
+  s->tickets[r->ticket] = r;
+  s->pending.push_back(r);
+  *ticket = r->ticket;
+  s->cv_work.notify_all();
+  return RBD_OK;
+}
+
+rbd_status rbd_server_wait(rbd_server* s, uint64_t ticket, double timeout_s, rbd_status* req_status) {
+  if (!s) return fail(RBD_E_INVAL, "rbd_server_wait: server is NULL");
+  std::unique_lock<std::mutex> lk(s->mu);
+  auto it = s->tickets.find(ticket);
+  if (it == s->tickets.end()) return fail(RBD_E_INVAL, "rbd_server_wait: unknown ticket %llu", (unsigned long long)ticket);
+  auto r = it->second;
+  if (timeout_s < 0) {
+    s->cv_done.wait(lk, [&] { return r->done; });
+  } else if (!s->cv_done.wait_for(lk, std::chrono::duration<double>(timeout_s), [&] { return r->done; })) {
+    return fail(RBD_E_TIMEOUT, "rbd_server_wait: ticket %llu not done", (unsigned long long)ticket);
+  }
+  if (req_status) *req_status = r->status;
+  s->tickets.erase(ticket);
+  return RBD_OK;
+}
+
+rbd_status rbd_server_get_stats(rbd_server* s, rbd_server_stats* out) {
+  if (!s || !out) return fail(RBD_E_INVAL, "rbd_server_get_stats: NULL argument");
+  std::lock_guard<std::mutex> lk(s->mu);
+  *out = rbd_server_stats{};
+  out->requests = s->n_req;
+  out->instances = s->n_inst;
+  out->launches = s->n_launch;
+  out->busy_s = s->busy_s;
+  if (!s->lat_us.empty()) {
+    std::vector<double> v(s->lat_us);
+    auto pct = [&](double p) {
+      const size_t k = std::min(v.size() - 1, (size_t)(p * (double)(v.size() - 1) + 0.5));
+      std::nth_element(v.begin(), v.begin() + (ptrdiff_t)k, v.end());
+      return v[k];
+    };
+    out->p50_us = pct(0.50);
+    out->p99_us = pct(0.99);
+    out->max_us = *std::max_element(v.begin(), v.end());
+    double sum = 0.0;
+    for (double x : s->lat_us) sum += x;
+    out->mean_us = sum / (double)s->lat_us.size();
+  }
+  return RBD_OK;
+}
+
+rbd_status rbd_server_reset_stats(rbd_server* s) {
+  if (!s) return fail(RBD_E_INVAL, "rbd_server_reset_stats: server is NULL");
+  std::lock_guard<std::mutex> lk(s->mu);
+  s->lat_us.clear();
+  s->n_req = s->n_inst = s->n_launch = 0;
+  s->busy_s = 0.0;
+  s->busy_since = Clock::now();
+  return RBD_OK;
+}
+
+rbd_status rbd_server_destroy(rbd_server* s) {
+  if (!s) return RBD_OK;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->stop = true;
+    s->cv_work.notify_all();
+  }
+  if (s->dispatcher.joinable()) s->dispatcher.join();
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->dispatcher_done = true;
+    s->cv_work.notify_all();
+  }
+  if (s->completer.joinable()) s->completer.join();
+  (void)hipSetDevice(s->cfg.device);
+  for (auto& sl : s->slots) {
+    for (auto& kv : sl.graphs) (void)hipGraphExecDestroy(kv.second);
+    if (sl.stream) (void)hipStreamSynchronize(sl.stream);
+    if (sl.done) (void)hipEventDestroy(sl.done);
+    if (sl.stream) (void)hipStreamDestroy(sl.stream);
+    if (sl.d_table) (void)hipFree(sl.d_table);
+    if (sl.h_table) (void)hipHostFree(sl.h_table);
+  }
+  if (s->d_arena) (void)hipFree(s->d_arena);
+  if (s->h_stage) (void)hipHostFree(s->h_stage);
+  delete s;
+  return RBD_OK;
+}
+
+}  // extern "C"

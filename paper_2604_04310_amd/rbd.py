@@ -1,0 +1,382 @@
+"""Python binding of librbd.so (ctypes): argument marshalling only.
+
+Every batched array is a torch CUDA float32 tensor in structure-of-arrays
+layout [rows, batch] with unit stride along the batch (ld = stride(0)); the
+call is enqueued on torch's current stream. PyTorch supplies device memory and
+streams; all arithmetic runs in the HIP kernels of librbd.so. There is no CPU
+fallback: a missing library raises.
+
+Operations (arxiv 2604.04310): fk and jacobian (Sec. II, Sec. IV), rnea
+(Eq. (1), Alg. 1), crba (Alg. 2), fwd_dyn (Eq. (2)), fwd_dyn_vjp and the
+autograd function FwdDyn (reverse-mode AD, Sec. I).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "librbd.so")
+
+RBD_OK = 0
+STATUS = {0: "RBD_OK", 1: "RBD_E_INVAL", 2: "RBD_E_NOMEM", 3: "RBD_E_NODEVICE", 4: "RBD_E_LAUNCH",
+          5: "RBD_E_UNSUPPORTED", 6: "RBD_E_TIMEOUT", 7: "RBD_E_SHUTDOWN"}
+OP_FWD_DYN, OP_RNEA, OP_FWD_DYN_VJP = 0, 1, 2
+
+# Every symbol include/rbd.h declares.
+EXPORTS = ["rbd_model_create", "rbd_model_destroy", "rbd_model_dims", "rbd_model_topology", "rbd_fk",
+           "rbd_jacobian", "rbd_rnea", "rbd_crba", "rbd_fwd_dyn", "rbd_fwd_dyn_vjp", "rbd_status_str",
+           "rbd_last_error", "rbd_device_count", "rbd_server_create", "rbd_server_submit", "rbd_server_wait",
+           "rbd_server_get_stats", "rbd_server_reset_stats", "rbd_server_destroy"]
+
+
+class RbdError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS.get(status, status)}: {message}")
+        self.status = status
+
+
+class TreeDescC(C.Structure):
+    _fields_ = [
+        ("n_bodies", C.c_int32),
+        ("parent", C.POINTER(C.c_int32)),
+        ("joint_type", C.POINTER(C.c_int32)),
+        ("axis", C.POINTER(C.c_double)),
+        ("origin", C.POINTER(C.c_double)),
+        ("mass", C.POINTER(C.c_double)),
+        ("com", C.POINTER(C.c_double)),
+        ("inertia", C.POINTER(C.c_double)),
+        ("gravity", C.c_double * 3),
+    ]
+
+
+class ServerConfigC(C.Structure):
+    _fields_ = [("device", C.c_int), ("arena_bytes", C.c_size_t), ("n_streams", C.c_int),
+                ("max_batch_requests", C.c_int), ("max_wait_us", C.c_double), ("use_graphs", C.c_int),
+                ("per_request", C.c_int)]
+
+
+class ServerStatsC(C.Structure):
+    _fields_ = [("requests", C.c_uint64), ("instances", C.c_uint64), ("launches", C.c_uint64),
+                ("p50_us", C.c_double), ("p99_us", C.c_double), ("max_us", C.c_double), ("mean_us", C.c_double),
+                ("busy_s", C.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    """Load librbd.so (built in-tree by __graft_entry__.build())."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built: run __graft_entry__.build() first")
+        L = C.CDLL(LIB_PATH)
+        P, vp, i64, i32 = C.POINTER, C.c_void_p, C.c_int64, C.c_int32
+        L.rbd_model_create.argtypes = [P(TreeDescC), C.c_int, P(vp)]
+        L.rbd_model_destroy.argtypes = [vp]
+        L.rbd_model_dims.argtypes = [vp, P(C.c_int), P(C.c_int), P(C.c_int)]
+        L.rbd_model_topology.argtypes = [vp]
+        L.rbd_model_topology.restype = C.c_char_p
+        L.rbd_fk.argtypes = [vp, i64, i64, vp, vp, vp]
+        L.rbd_jacobian.argtypes = [vp, i64, i64, vp, i32, P(C.c_int32), vp, vp]
+        L.rbd_rnea.argtypes = [vp, i64, i64, vp, vp, vp, vp, vp]
+        L.rbd_crba.argtypes = [vp, i64, i64, vp, vp, vp]
+        L.rbd_fwd_dyn.argtypes = [vp, i64, i64, vp, vp, vp, vp, vp]
+        L.rbd_fwd_dyn_vjp.argtypes = [vp, i64, i64, vp, vp, vp, vp, vp, vp, vp, vp]
+        L.rbd_status_str.argtypes = [C.c_int]
+        L.rbd_status_str.restype = C.c_char_p
+        L.rbd_last_error.argtypes = []
+        L.rbd_last_error.restype = C.c_char_p
+        L.rbd_device_count.argtypes = []
+        L.rbd_server_create.argtypes = [P(ServerConfigC), P(vp)]
+        L.rbd_server_submit.argtypes = [vp, vp, C.c_int, i64, P(vp), P(vp), P(C.c_uint64)]
+        L.rbd_server_wait.argtypes = [vp, C.c_uint64, C.c_double, P(C.c_int)]
+        L.rbd_server_get_stats.argtypes = [vp, P(ServerStatsC)]
+        L.rbd_server_reset_stats.argtypes = [vp]
+        L.rbd_server_destroy.argtypes = [vp]
+        _lib = L
+    return _lib
+
+
+def check(status: int) -> None:
+    if status != RBD_OK:
+        raise RbdError(status, lib().rbd_last_error().decode())
+
+
+def device_count() -> int:
+    return int(lib().rbd_device_count())
+
+
+def desc_struct(desc) -> TreeDescC:
+    """rbd_tree_desc view of any object with the tree fields (arrays kept alive)."""
+    get = (lambda k: desc[k]) if isinstance(desc, dict) else (lambda k: getattr(desc, k))
+    keep = {
+        "parent": np.ascontiguousarray(get("parent"), dtype=np.int32),
+        "joint_type": np.ascontiguousarray(get("joint_type"), dtype=np.int32),
+        "axis": np.ascontiguousarray(get("axis"), dtype=np.float64),
+        "origin": np.ascontiguousarray(get("origin"), dtype=np.float64),
+        "mass": np.ascontiguousarray(get("mass"), dtype=np.float64),
+        "com": np.ascontiguousarray(get("com"), dtype=np.float64),
+        "inertia": np.ascontiguousarray(get("inertia"), dtype=np.float64),
+    }
+    s = TreeDescC()
+    s.n_bodies = int(keep["parent"].shape[0])
+    s.parent = keep["parent"].ctypes.data_as(C.POINTER(C.c_int32))
+    s.joint_type = keep["joint_type"].ctypes.data_as(C.POINTER(C.c_int32))
+    for k in ("axis", "origin", "mass", "com", "inertia"):
+        setattr(s, k, keep[k].ctypes.data_as(C.POINTER(C.c_double)))
+    g = np.asarray(get("gravity"), dtype=np.float64)
+    for k in range(3):
+        s.gravity[k] = float(g[k])
+    s._keep = keep
+    return s
+
+
+class Model:
+    """A kinematic tree resident on one GPU (owns the device tables)."""
+
+    def __init__(self, desc, device: int = 0):
+        self._h = C.c_void_p()
+        self._desc = desc_struct(desc)
+        check(lib().rbd_model_create(C.byref(self._desc), int(device), C.byref(self._h)))
+        nq, nv, n = C.c_int(), C.c_int(), C.c_int()
+        check(lib().rbd_model_dims(self._h, C.byref(nq), C.byref(nv), C.byref(n)))
+        self.nq, self.nv, self.n_bodies, self.device = nq.value, nv.value, n.value, int(device)
+        self.topology = lib().rbd_model_topology(self._h).decode()
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if self._h:
+            lib().rbd_model_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream():
+    torch = _torch()
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _soa(x, rows: int, name: str, batch: Optional[int] = None):
+    """Checks a [rows, batch] SoA tensor and returns (ptr, batch, ld)."""
+    torch = _torch()
+    if not isinstance(x, torch.Tensor) or not x.is_cuda or x.dtype != torch.float32:
+        raise TypeError(f"{name}: expected a CUDA float32 tensor")
+    if x.dim() != 2 or x.shape[0] != rows:
+        raise ValueError(f"{name}: expected shape [{rows}, batch], got {tuple(x.shape)}")
+    if x.stride(1) != 1 and x.shape[1] > 1:
+        raise ValueError(f"{name}: the batch dimension must have unit stride")
+    if batch is not None and x.shape[1] != batch:
+        raise ValueError(f"{name}: batch {x.shape[1]} != {batch}")
+    ld = x.stride(0) if x.shape[0] > 1 else max(x.shape[1], 1)
+    return C.c_void_p(x.data_ptr()), int(x.shape[1]), int(ld)
+
+
+def _out(rows: int, batch: int, like):
+    torch = _torch()
+    return torch.empty((rows, batch), dtype=torch.float32, device=like.device)
+
+
+def _same_ld(*lds):
+    if len(set(lds)) != 1:
+        raise ValueError("all arrays of one call must share the leading dimension (ld)")
+    return lds[0]
+
+
+def fk(model: Model, q):
+    """World pose of every body: [n_bodies * 12, B], rows (i, 3x4 row-major [R | p])."""
+    qp, B, ld = _soa(q, model.nq, "q")
+    T = _out(model.n_bodies * 12, B, q)
+    if ld != B:
+        raise ValueError("fk: q must be contiguous (ld = batch) so that outputs share its ld")
+    check(lib().rbd_fk(model.handle, B, ld, qp, C.c_void_p(T.data_ptr()), _stream()))
+    return T
+
+
+def jacobian(model: Model, q, frames: Optional[Sequence[int]] = None):
+    """Geometric Jacobians [n_frames * 6 * nv, B] of the given body frames (all by default)."""
+    qp, B, ld = _soa(q, model.nq, "q")
+    if ld != B:
+        raise ValueError("jacobian: q must be contiguous")
+    fr = np.arange(model.n_bodies, dtype=np.int32) if frames is None else np.asarray(frames, dtype=np.int32)
+    fr = np.ascontiguousarray(fr)
+    J = _out(len(fr) * 6 * model.nv, B, q)
+    check(lib().rbd_jacobian(model.handle, B, ld, qp, len(fr), fr.ctypes.data_as(C.POINTER(C.c_int32)),
+                             C.c_void_p(J.data_ptr()), _stream()))
+    return J
+
+
+def rnea(model: Model, q, qd, qdd=None, out=None):
+    """Inverse dynamics tau [nv, B] (Eq. (1)); qdd=None gives the bias force h(q, qd)."""
+    qp, B, l1 = _soa(q, model.nq, "q")
+    qdp, _, l2 = _soa(qd, model.nv, "qd", B)
+    lds = [l1, l2]
+    qddp = None
+    if qdd is not None:
+        qddp, _, l3 = _soa(qdd, model.nv, "qdd", B)
+        lds.append(l3)
+    tau = _out(model.nv, B, q) if out is None else out
+    tp, _, l4 = _soa(tau, model.nv, "tau", B)
+    ld = _same_ld(*lds, l4)
+    check(lib().rbd_rnea(model.handle, B, ld, qp, qdp, qddp, tp, _stream()))
+    return tau
+
+
+def crba(model: Model, q):
+    """Mass matrix [nv * nv, B], row-major per instance."""
+    qp, B, ld = _soa(q, model.nq, "q")
+    if ld != B:
+        raise ValueError("crba: q must be contiguous")
+    M = _out(model.nv * model.nv, B, q)
+    check(lib().rbd_crba(model.handle, B, ld, qp, C.c_void_p(M.data_ptr()), _stream()))
+    return M
+
+
+def fwd_dyn(model: Model, q, qd, tau, out=None):
+    """Forward dynamics qdd [nv, B] (Eq. (2))."""
+    qp, B, l1 = _soa(q, model.nq, "q")
+    qdp, _, l2 = _soa(qd, model.nv, "qd", B)
+    taup, _, l3 = _soa(tau, model.nv, "tau", B)
+    qdd = _out(model.nv, B, q) if out is None else out
+    op, _, l4 = _soa(qdd, model.nv, "qdd", B)
+    ld = _same_ld(l1, l2, l3, l4)
+    check(lib().rbd_fwd_dyn(model.handle, B, ld, qp, qdp, taup, op, _stream()))
+    return qdd
+
+
+def fwd_dyn_vjp(model: Model, q, qd, tau, g_qdd, want=(True, True, True)):
+    """(g_q [nq, B], g_qd [nv, B], g_tau [nv, B]) = g_qdd^T d qdd / d(q, qd, tau); None where not wanted."""
+    qp, B, l1 = _soa(q, model.nq, "q")
+    qdp, _, l2 = _soa(qd, model.nv, "qd", B)
+    taup, _, l3 = _soa(tau, model.nv, "tau", B)
+    gp, _, l4 = _soa(g_qdd, model.nv, "g_qdd", B)
+    ld = _same_ld(l1, l2, l3, l4)
+    if ld != B:
+        raise ValueError("fwd_dyn_vjp: inputs must be contiguous")
+    outs = [_out(model.nq, B, q) if want[0] else None, _out(model.nv, B, q) if want[1] else None,
+            _out(model.nv, B, q) if want[2] else None]
+    ptrs = [C.c_void_p(o.data_ptr()) if o is not None else None for o in outs]
+    check(lib().rbd_fwd_dyn_vjp(model.handle, B, ld, qp, qdp, taup, gp, ptrs[0], ptrs[1], ptrs[2], _stream()))
+    return tuple(outs)
+
+
+def _make_autograd():
+    torch = _torch()
+
+    class FwdDyn(torch.autograd.Function):
+        """qdd = FD(q, qd, tau) with the hand-written adjoint kernel as backward."""
+
+        @staticmethod
+        def forward(ctx, model, q, qd, tau):
+            ctx.model = model
+            q, qd, tau = q.contiguous(), qd.contiguous(), tau.contiguous()
+            ctx.save_for_backward(q, qd, tau)
+            return fwd_dyn(model, q, qd, tau)
+
+        @staticmethod
+        def backward(ctx, g):
+            q, qd, tau = ctx.saved_tensors
+            want = ctx.needs_input_grad[1:4]
+            gq, gqd, gtau = fwd_dyn_vjp(ctx.model, q, qd, tau, g.contiguous(), want=tuple(bool(w) for w in want))
+            return None, gq, gqd, gtau
+
+    return FwdDyn
+
+
+_FwdDyn = None
+
+
+def fwd_dyn_autograd(model: Model, q, qd, tau):
+    """Differentiable forward dynamics: backward runs rbd_fwd_dyn_vjp."""
+    global _FwdDyn
+    if _FwdDyn is None:
+        _FwdDyn = _make_autograd()
+    return _FwdDyn.apply(model, q, qd, tau)
+
+
+# ---------------------------------------------------------------- serving
+def op_shapes(model: Model, op: int):
+    """Rows per instance of the inputs and outputs of a served operation."""
+    nq, nv = model.nq, model.nv
+    if op in (OP_FWD_DYN, OP_RNEA):
+        return [nq, nv, nv], [nv]
+    if op == OP_FWD_DYN_VJP:
+        return [nq, nv, nv, nv], [nq, nv, nv]
+    raise ValueError(f"unknown op {op}")
+
+
+class Server:
+    """Continuous-batching service (rbd_server_*). Requests carry host arrays,
+    instance-major float32 [batch, rows]; results land in host arrays."""
+
+    def __init__(self, device: int = 0, arena_bytes: int = 256 << 20, n_streams: int = 4,
+                 max_batch_requests: int = 1024, max_wait_us: float = 0.0, use_graphs: bool = True,
+                 per_request: bool = False):
+        cfg = ServerConfigC(int(device), int(arena_bytes), int(n_streams), int(max_batch_requests),
+                            float(max_wait_us), int(bool(use_graphs)), int(bool(per_request)))
+        self._h = C.c_void_p()
+        check(lib().rbd_server_create(C.byref(cfg), C.byref(self._h)))
+        self._live = {}
+
+    def submit(self, model: Model, op: int, inputs: Sequence[np.ndarray]):
+        """Queue one request; returns (ticket, outputs) with outputs filled once waited."""
+        in_rows, out_rows = op_shapes(model, op)
+        if len(inputs) != len(in_rows):
+            raise ValueError(f"op {op} takes {len(in_rows)} inputs")
+        batch = int(inputs[0].shape[0])
+        ins = []
+        for x, r in zip(inputs, in_rows):
+            x = np.ascontiguousarray(x, dtype=np.float32)
+            if x.shape != (batch, r):
+                raise ValueError(f"input of shape {x.shape}, expected {(batch, r)}")
+            ins.append(x)
+        outs = [np.empty((batch, r), dtype=np.float32) for r in out_rows]
+        pin = (C.c_void_p * 4)(*[C.c_void_p(x.ctypes.data) for x in ins] + [None] * (4 - len(ins)))
+        pout = (C.c_void_p * 3)(*[C.c_void_p(x.ctypes.data) for x in outs] + [None] * (3 - len(outs)))
+        t = C.c_uint64()
+        check(lib().rbd_server_submit(self._h, model.handle, int(op), batch, pin, pout, C.byref(t)))
+        self._live[t.value] = (ins, outs)
+        return t.value, outs
+
+    def wait(self, ticket: int, timeout: float = -1.0) -> int:
+        st = C.c_int()
+        check(lib().rbd_server_wait(self._h, C.c_uint64(ticket), float(timeout), C.byref(st)))
+        self._live.pop(ticket, None)
+        return st.value
+
+    def stats(self) -> dict:
+        s = ServerStatsC()
+        check(lib().rbd_server_get_stats(self._h, C.byref(s)))
+        return {k: getattr(s, k) for k, _ in ServerStatsC._fields_}
+
+    def reset_stats(self) -> None:
+        check(lib().rbd_server_reset_stats(self._h))
+
+    def close(self) -> None:
+        if self._h:
+            lib().rbd_server_destroy(self._h)
+            self._h = C.c_void_p()
+            self._live.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -54,3 +54,19 @@ def rel_err(x, ref, axis=None):
     num = np.abs(x - ref).max(axis=1)
     den = np.abs(ref).max(axis=1)
     return float((num / np.maximum(den, 1e-300)).max())
+
+
+def vjp_err(got, ref, floor=1e-4):
+    """Max over instances and over the blocks (g_q, g_qd, g_tau) of
+    ||x_b - ref_b||_inf / max(||ref_b||_inf, floor * ||ref||_inf): a block whose true
+    value vanishes (a single pendulum has no velocity dependence) is held to an
+    absolute bar set by the scale of the whole gradient, not to its FD noise."""
+    B = len(ref[0])
+    flat = [np.asarray(r, dtype=np.float64).reshape(B, -1) for r in ref]
+    scale = np.max([np.abs(r).max(axis=1) for r in flat], axis=0)
+    worst = 0.0
+    for x, r in zip(got, flat):
+        x = np.asarray(x, dtype=np.float64).reshape(B, -1)
+        den = np.maximum(np.abs(r).max(axis=1), floor * scale)
+        worst = max(worst, float((np.abs(x - r).max(axis=1) / den).max()))
+    return worst

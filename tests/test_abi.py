@@ -1,0 +1,105 @@
+"""The C ABI on the CPU: the library loads without a GPU, exports every symbol
+include/rbd.h declares, and rejects bad models with the documented status."""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def rbd():
+    import paper_2604_04310_amd as rbd
+    if not os.path.exists(rbd.LIB_PATH):
+        pytest.skip("librbd.so not built")
+    rbd.lib()
+    return rbd
+
+
+def test_header_declarations_are_exported(rbd):
+    header = open(os.path.join(ROOT, "include", "rbd.h")).read()
+    declared = set(re.findall(r"\b(rbd_[a-z_]+)\s*\(", header))
+    assert declared == set(rbd.EXPORTS)
+    for name in declared:
+        assert hasattr(rbd.lib(), name), name
+
+
+def test_status_strings(rbd):
+    L = rbd.lib()
+    assert L.rbd_status_str(0) == b"ok"
+    assert L.rbd_status_str(1) == b"invalid argument"
+    assert L.rbd_status_str(5) == b"unsupported topology"
+
+
+def _create(rbd, desc):
+    h = C.c_void_p()
+    s = rbd.desc_struct(desc) if desc is not None else None
+    st = rbd.lib().rbd_model_create(C.byref(s) if s is not None else None, 0, C.byref(h))
+    if st == 0:
+        rbd.lib().rbd_model_destroy(h)
+    return st, rbd.lib().rbd_last_error().decode()
+
+
+def _mutated(**kw):
+    d = W.chain(7)
+    for k, fn in kw.items():
+        arr = getattr(d, k).copy()
+        fn(arr)
+        setattr(d, k, arr)
+    return d
+
+
+@pytest.mark.parametrize("case,msg", [
+    ("parent_order", "parent"), ("free_not_root", "free joint"), ("zero_axis", "axis"),
+    ("bad_rotation", "rotation"), ("mass", "mass"), ("not_pd", "positive definite"),
+    ("triangle", "triangle"), ("not_dfs", "contiguous"), ("bad_joint", "joint_type"),
+])
+def test_invalid_models_are_rejected(rbd, case, msg):
+    muts = {
+        "parent_order": dict(parent=lambda a: a.__setitem__(3, 5)),
+        "free_not_root": dict(joint_type=lambda a: a.__setitem__(2, 1)),
+        "zero_axis": dict(axis=lambda a: a.__setitem__(1, 0.0)),
+        "bad_rotation": dict(origin=lambda a: a.__setitem__((2, 0), 2.0)),
+        "mass": dict(mass=lambda a: a.__setitem__(4, -1.0)),
+        "not_pd": dict(inertia=lambda a: a.__setitem__(0, [-1.0, 1, 1, 0, 0, 0])),
+        "triangle": dict(inertia=lambda a: a.__setitem__(0, [1.0, 1.0, 5.0, 0, 0, 0])),
+        "bad_joint": dict(joint_type=lambda a: a.__setitem__(3, 7)),
+    }
+    if case == "not_dfs":
+        d = W.random_tree([-1, 0, 0, 1], False, 3)  # body 3 hangs under 1 after 2: not depth-first
+    else:
+        d = _mutated(**muts[case])
+    st, err = _create(rbd, d)
+    assert st == 1, (st, err)
+    assert msg in err
+
+
+def test_null_desc(rbd):
+    st, err = _create(rbd, None)
+    assert st == 1 and "NULL" in err
+
+
+def test_unsupported_topology(rbd):
+    st, err = _create(rbd, W.random_tree([-1, 0, 0], False, 4))
+    assert st == 5 and "no compiled kernel" in err
+
+
+def test_valid_model_without_device(rbd):
+    st, err = _create(rbd, W.chain(7))
+    if rbd.device_count() == 0:
+        assert st == 3, err
+    else:
+        assert st == 0, err
+
+
+def test_null_model_calls(rbd):
+    L = rbd.lib()
+    assert L.rbd_fwd_dyn(None, 1, 1, None, None, None, None, None) == 1
+    assert b"model is NULL" in L.rbd_last_error()

@@ -1,0 +1,91 @@
+"""Parity at the benchmark sizes, in the launch configuration the benchmark times.
+
+Chain of 7 at batch 2^20 (fwd_dyn, rnea: first 4096 states against the oracle,
+all outputs finite), the 35-DoF humanoid at batch 65536 (fwd_dyn on every
+instance; crba, fk and jacobian on a strided sample), and the adjoint at 2^18
+(chain) and 32768 (humanoid) against central differences on 256 states.
+"""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+from tests._helpers import rel_err, vjp_err
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def rbd():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2604_04310_amd as rbd
+    rbd.lib()
+    return rbd
+
+
+def gpu(x):
+    return torch.tensor(np.ascontiguousarray(x.T), dtype=torch.float32, device="cuda")
+
+
+def cols(t, idx):
+    """Instances idx of a [rows, B] tensor as a float64 [len(idx), rows] array."""
+    torch.cuda.synchronize()
+    return t[:, torch.as_tensor(idx, device=t.device)].double().cpu().numpy().T
+
+
+def test_chain7_batch_2p20(rbd):
+    desc = W.chain(7)
+    m = rbd.Model(desc, 0)
+    st = W.states(desc, 1 << 20, 102)
+    q, qd, tau = gpu(st.q), gpu(st.qd), gpu(st.tau)
+    qdd = rbd.fwd_dyn(m, q, qd, tau)
+    h = rbd.rnea(m, q, qd)
+    torch.cuda.synchronize()
+    assert torch.isfinite(qdd).all() and torch.isfinite(h).all()
+    idx = np.arange(4096)
+    assert rel_err(cols(qdd, idx), O.fwd_dyn(desc, st.q[idx], st.qd[idx], st.tau[idx])) < 1e-4
+    assert rel_err(cols(h, idx), O.rnea(desc, st.q[idx], st.qd[idx])) < 1e-4
+
+
+def test_humanoid_batch_65536(rbd):
+    desc = W.humanoid()
+    m = rbd.Model(desc, 0)
+    B = 65536
+    st = W.states(desc, B, 103)
+    q, qd, tau = gpu(st.q), gpu(st.qd), gpu(st.tau)
+    qdd = rbd.fwd_dyn(m, q, qd, tau)
+    h = rbd.rnea(m, q, qd)
+    torch.cuda.synchronize()
+    all_idx = np.arange(B)
+    assert rel_err(cols(qdd, all_idx), O.fwd_dyn(desc, st.q, st.qd, st.tau)) < 1e-4
+    assert rel_err(cols(h, all_idx), O.rnea(desc, st.q, st.qd)) < 1e-4
+    idx = np.arange(0, B, 61)
+    M = rbd.crba(m, q)
+    Mh = cols(M, idx).reshape(len(idx), -1)
+    Mr = O.crba(desc, st.q[idx]).reshape(len(idx), -1)
+    assert (np.abs(Mh - Mr).max(1) / np.abs(Mr).max(1)).max() < 1e-5
+    del M
+    T = rbd.fk(m, q)
+    assert rel_err(cols(T, idx), O.fk(desc, st.q[idx]).reshape(len(idx), -1)) < 1e-5
+    del T
+    J = rbd.jacobian(m, q)
+    assert rel_err(cols(J, idx), O.jacobian(desc, st.q[idx]).reshape(len(idx), -1)) < 1e-5
+    del J
+
+
+@pytest.mark.parametrize("name,B", [("chain7", 1 << 18), ("humanoid30", 32768)])
+def test_vjp_full_batch(rbd, name, B):
+    desc = W.chain(7) if name == "chain7" else W.humanoid()
+    m = rbd.Model(desc, 0)
+    st = W.states(desc, B, 104)
+    gbar = W.cotangent(desc.nv, B, 105)
+    gq, gqd, gtau = rbd.fwd_dyn_vjp(m, gpu(st.q), gpu(st.qd), gpu(st.tau), gpu(gbar))
+    torch.cuda.synchronize()
+    assert torch.isfinite(gq).all() and torch.isfinite(gqd).all() and torch.isfinite(gtau).all()
+    idx = np.linspace(0, B - 1, 256).astype(int)
+    rq, rqd, rtau = O.fwd_dyn_vjp_fd(desc, st.q[idx], st.qd[idx], st.tau[idx], gbar[idx])
+    assert vjp_err([cols(gq, idx), cols(gqd, idx), cols(gtau, idx)], [rq, rqd, rtau]) < 1e-3

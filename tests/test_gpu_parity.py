@@ -1,0 +1,213 @@
+"""GPU parity: every entry point of librbd.so against the FP64 oracle.
+
+Inputs are seeded, FP32-rounded synthetic robots and states (workloads); the
+oracle runs on exactly those values in FP64. The error of an instance is
+normwise, ||x - ref||_inf / ||ref||_inf, and the bar is its maximum over
+instances: 1e-4 for qdd and tau, 1e-5 for M, T and J, 1e-3 for the VJP
+(against central differences of the oracle).
+"""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+from tests._helpers import rel_err, vjp_err
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL_QDD, TOL_TAU, TOL_M, TOL_KIN, TOL_VJP = 1e-4, 1e-4, 1e-5, 1e-5, 1e-3
+
+TREE12 = [-1, 0, 1, 1, 0, 4, 5, 5, 7, 0, 9, 10]
+MODELS = {
+    "chain1": lambda: W.random_tree([-1], False, 31),
+    "chain2": lambda: W.random_tree([-1, 0], False, 32),
+    "chain7": lambda: W.chain(7),
+    "free1": lambda: W.random_tree([-1], True, 33),
+    "tree12f": lambda: W.random_tree(TREE12, True, 34),
+    "humanoid30": lambda: W.humanoid(),
+}
+
+
+@pytest.fixture(scope="module")
+def rbd():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2604_04310_amd as rbd
+    rbd.lib()
+    return rbd
+
+
+_models = {}
+
+
+def model_of(rbd, name):
+    if name not in _models:
+        desc = MODELS[name]()
+        _models[name] = (desc, rbd.Model(desc, 0))
+    return _models[name]
+
+
+def gpu(x, ld=None):
+    """[B, n] float64 -> CUDA float32 [n, B] (or a [n, ld] buffer viewed as [n, B])."""
+    B, n = x.shape
+    if ld is None:
+        return torch.tensor(np.ascontiguousarray(x.T), dtype=torch.float32, device="cuda")
+    buf = torch.full((n, ld), float("nan"), dtype=torch.float32, device="cuda")
+    buf[:, :B] = torch.tensor(np.ascontiguousarray(x.T), dtype=torch.float32, device="cuda")
+    return buf[:, :B]
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.double().cpu().numpy().T
+
+
+# ---------------------------------------------------------------- small batches, every op
+BATCH = 1000  # four 256-lane blocks, the last one ragged
+
+
+@pytest.mark.parametrize("name", list(MODELS))
+def test_fwd_dyn_parity(rbd, name):
+    desc, m = model_of(rbd, name)
+    st = W.states(desc, BATCH, 201)
+    qdd = rbd.fwd_dyn(m, gpu(st.q), gpu(st.qd), gpu(st.tau))
+    assert rel_err(host(qdd), O.fwd_dyn(desc, st.q, st.qd, st.tau)) < TOL_QDD
+
+
+@pytest.mark.parametrize("name", list(MODELS))
+def test_rnea_parity(rbd, name):
+    desc, m = model_of(rbd, name)
+    st = W.states(desc, BATCH, 202)
+    qdd_in = W.cotangent(desc.nv, BATCH, 203) * 3.0
+    tau = rbd.rnea(m, gpu(st.q), gpu(st.qd), gpu(qdd_in))
+    assert rel_err(host(tau), O.rnea(desc, st.q, st.qd, qdd_in)) < TOL_TAU
+    h = rbd.rnea(m, gpu(st.q), gpu(st.qd))
+    assert rel_err(host(h), O.rnea(desc, st.q, st.qd)) < TOL_TAU
+
+
+@pytest.mark.parametrize("name", list(MODELS))
+def test_crba_parity(rbd, name):
+    desc, m = model_of(rbd, name)
+    st = W.states(desc, BATCH, 204)
+    M = host(rbd.crba(m, gpu(st.q))).reshape(BATCH, desc.nv, desc.nv)
+    ref = O.crba(desc, st.q)
+    err = (np.abs(M - ref).reshape(BATCH, -1).max(1) / np.abs(ref).reshape(BATCH, -1).max(1)).max()
+    assert err < TOL_M
+    assert np.array_equal(M, np.swapaxes(M, 1, 2))  # written symmetric, bit for bit
+
+
+@pytest.mark.parametrize("name", list(MODELS))
+def test_fk_parity(rbd, name):
+    desc, m = model_of(rbd, name)
+    st = W.states(desc, BATCH, 205)
+    T = host(rbd.fk(m, gpu(st.q)))
+    assert rel_err(T, O.fk(desc, st.q).reshape(BATCH, -1)) < TOL_KIN
+
+
+@pytest.mark.parametrize("name", list(MODELS))
+def test_jacobian_parity(rbd, name):
+    desc, m = model_of(rbd, name)
+    st = W.states(desc, BATCH, 206)
+    rng = np.random.Generator(np.random.PCG64(7))
+    frames = np.concatenate([np.arange(desc.n_bodies), rng.integers(0, desc.n_bodies, 3)]).astype(np.int32)
+    J = host(rbd.jacobian(m, gpu(st.q), frames))
+    ref = O.jacobian(desc, st.q, frames).reshape(BATCH, -1)
+    assert rel_err(J, ref) < TOL_KIN
+    assert np.all(J[ref == 0.0] == 0.0)  # non-ancestor columns are exact zeros
+
+
+@pytest.mark.parametrize("name", list(MODELS))
+def test_fwd_dyn_vjp_parity(rbd, name):
+    desc, m = model_of(rbd, name)
+    B = 256
+    st = W.states(desc, B, 207)
+    gbar = W.cotangent(desc.nv, B, 208)
+    gq, gqd, gtau = rbd.fwd_dyn_vjp(m, gpu(st.q), gpu(st.qd), gpu(st.tau), gpu(gbar))
+    rq, rqd, rtau = O.fwd_dyn_vjp_fd(desc, st.q, st.qd, st.tau, gbar, h=1e-6)
+    assert vjp_err([host(gq), host(gqd), host(gtau)], [rq, rqd, rtau]) < TOL_VJP
+    # any output may be skipped; the others are unchanged
+    _, gqd2, gtau2 = rbd.fwd_dyn_vjp(m, gpu(st.q), gpu(st.qd), gpu(st.tau), gpu(gbar), want=(False, True, True))
+    assert np.array_equal(host(gqd2), host(gqd)) and np.array_equal(host(gtau2), host(gtau))
+
+
+# ---------------------------------------------------------------- layout and edge cases
+def test_leading_dimension_larger_than_batch(rbd):
+    desc, m = model_of(rbd, "humanoid30")
+    B, ld = 300, 512
+    st = W.states(desc, B, 210)
+    out = torch.full((desc.nv, ld), 7.0, dtype=torch.float32, device="cuda")
+    rbd.fwd_dyn(m, gpu(st.q, ld), gpu(st.qd, ld), gpu(st.tau, ld), out=out[:, :B])
+    o = out.cpu().numpy()
+    assert np.all(o[:, B:] == 7.0)  # padding untouched
+    assert rel_err(o[:, :B].T.astype(np.float64), O.fwd_dyn(desc, st.q, st.qd, st.tau)) < TOL_QDD
+
+
+@pytest.mark.parametrize("B", [0, 1, 255, 257])
+def test_batch_edges(rbd, B):
+    desc, m = model_of(rbd, "humanoid30")
+    st = W.states(desc, max(B, 1), 211)
+    if B == 0:
+        z = torch.zeros((desc.nq, 0), dtype=torch.float32, device="cuda")
+        zv = torch.zeros((desc.nv, 0), dtype=torch.float32, device="cuda")
+        assert rbd.fwd_dyn(m, z, zv, zv).shape == (desc.nv, 0)
+        return
+    qdd = rbd.fwd_dyn(m, gpu(st.q), gpu(st.qd), gpu(st.tau))
+    assert rel_err(host(qdd), O.fwd_dyn(desc, st.q, st.qd, st.tau)) < TOL_QDD
+
+
+def test_special_states(rbd):
+    """q = 0, q = +-pi, qd = 0, large qd, and a scaled (non-unit) quaternion."""
+    desc, m = model_of(rbd, "humanoid30")
+    st = W.states(desc, 64, 212)
+    q, qd, tau = st.q.copy(), st.qd.copy(), st.tau.copy()
+    q[0:8, 7:] = 0.0
+    q[8:16, 7:] = np.pi
+    q[16:24, 7:] = -np.pi
+    qd[24:32] = 0.0
+    qd[32:40] *= 20.0
+    q = W._f32(q)
+    qd = W._f32(qd)
+    qdd = host(rbd.fwd_dyn(m, gpu(q), gpu(qd), gpu(tau)))
+    assert rel_err(qdd, O.fwd_dyn(desc, q, qd, tau)) < TOL_QDD
+    q2 = q.copy()
+    q2[:, 3:7] *= 2.5  # same rotation
+    qdd2 = host(rbd.fwd_dyn(m, gpu(q2), gpu(qd), gpu(tau)))
+    assert rel_err(qdd2, O.fwd_dyn(desc, q, qd, tau)) < TOL_QDD
+
+
+def test_zero_quaternion_poisons_only_its_instance(rbd):
+    desc, m = model_of(rbd, "humanoid30")
+    st = W.states(desc, 64, 213)
+    q = st.q.copy()
+    q[5, 3:7] = 0.0
+    qdd = host(rbd.fwd_dyn(m, gpu(q), gpu(st.qd), gpu(st.tau)))
+    assert np.isnan(qdd[5]).any()
+    keep = np.arange(64) != 5
+    assert np.isfinite(qdd[keep]).all()
+    assert rel_err(qdd[keep], O.fwd_dyn(desc, q[keep], st.qd[keep], st.tau[keep])) < TOL_QDD
+
+
+def test_autograd_function(rbd):
+    desc, m = model_of(rbd, "chain7")
+    B = 128
+    st = W.states(desc, B, 214)
+    q = gpu(st.q).requires_grad_(True)
+    qd = gpu(st.qd).requires_grad_(True)
+    tau = gpu(st.tau).requires_grad_(True)
+    gbar = W.cotangent(desc.nv, B, 215)
+    qdd = rbd.fwd_dyn_autograd(m, q, qd, tau)
+    (qdd * gpu(gbar)).sum().backward()
+    rq, rqd, rtau = O.fwd_dyn_vjp_fd(desc, st.q, st.qd, st.tau, gbar)
+    assert vjp_err([host(q.grad), host(qd.grad), host(tau.grad)], [rq, rqd, rtau]) < TOL_VJP
+
+
+def test_invalid_arguments_raise(rbd):
+    desc, m = model_of(rbd, "chain7")
+    st = W.states(desc, 8, 216)
+    with pytest.raises(ValueError):
+        rbd.fwd_dyn(m, gpu(st.q)[:5], gpu(st.qd), gpu(st.tau))
+    with pytest.raises(rbd.RbdError):
+        rbd.jacobian(m, gpu(st.q), [0, 99])
