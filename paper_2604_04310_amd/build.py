@@ -34,24 +34,39 @@ def _jobs():
     return max(1, min(16, cpus, int(os.environ.get("MAX_JOBS", cpus))))
 
 
-def build(verbose: bool = False, jobs: int = 0, resource_usage: bool = False) -> str:
-    """Compile one object per topology plus the host sources in parallel, then link librbd.so."""
+def _newest_source() -> float:
+    paths = [os.path.join(CSRC, f) for f in os.listdir(CSRC)] + [os.path.join(INCLUDE, f) for f in os.listdir(INCLUDE)]
+    return max(os.path.getmtime(p) for p in paths)
+
+
+def build(verbose: bool = False, jobs: int = 0, resource_usage: bool = False, incremental: bool = False) -> str:
+    """Compile one object per topology part plus the host sources in parallel, then link librbd.so.
+
+    incremental=True skips objects newer than every source and header (a
+    development convenience; the default always recompiles everything)."""
     out_dir = os.path.join(PKG, "_build")
     os.makedirs(out_dir, exist_ok=True)
     jobs = jobs or _jobs()
     work = []
     # the largest topologies first, so the longest compiles start early
     for name in reversed(topologies()):
-        obj = os.path.join(out_dir, f"kern_{name}.o")
-        cmd = [HIPCC, *DEVICE, *COMMON, f"-DRBD_TOPO={name}", "-c", os.path.join(CSRC, TOPO_SOURCE), "-o", obj]
-        if resource_usage:
-            cmd.append("-Rpass-analysis=kernel-resource-usage")
-        work.append((obj, cmd))
+        for part in (2, 3, 1):
+            obj = os.path.join(out_dir, f"kern_{name}_p{part}.o")
+            cmd = [HIPCC, *DEVICE, *COMMON, f"-DRBD_TOPO={name}", f"-DRBD_PART={part}", "-c",
+                   os.path.join(CSRC, TOPO_SOURCE), "-o", obj]
+            if resource_usage:
+                cmd.append("-Rpass-analysis=kernel-resource-usage")
+            work.append((obj, cmd))
     for src in HOST_SOURCES:
         obj = os.path.join(out_dir, src + ".o")
         work.append((obj, [HIPCC, *COMMON, "-c", os.path.join(CSRC, src), "-o", obj]))
     t0 = time.time()
     running, logs, objs = [], [], []
+    if incremental and not resource_usage:
+        newest = _newest_source()
+        fresh = [(o, c) for o, c in work if os.path.exists(o) and os.path.getmtime(o) > newest]
+        objs = [o for o, _ in fresh]
+        work = [(o, c) for o, c in work if (o, c) not in fresh]
     pending = list(work)
     while pending or running:
         while pending and len(running) < jobs:
@@ -88,6 +103,6 @@ def build(verbose: bool = False, jobs: int = 0, resource_usage: bool = False) ->
 
 if __name__ == "__main__":
     ru = "--resource-usage" in sys.argv
-    out = build(verbose=True, resource_usage=ru)
+    out = build(verbose=True, resource_usage=ru, incremental="--incremental" in sys.argv)
     if ru:
         print(out)

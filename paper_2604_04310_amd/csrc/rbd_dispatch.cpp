@@ -2,12 +2,17 @@
 // model's compiled topology.
 #include <hip/hip_runtime.h>
 
+#include <cstdlib>
+#include <cstring>
+#include <vector>
+
 #include "rbd_internal.hpp"
 #include "rbd_topologies.hpp"
 
 namespace rbd {
 
-#define RBD_DECL(name, fr, ...) extern const LaunchTable launch_table_##name;
+#define RBD_DECL(name, fr, ...) \
+  extern const LaunchTable launch_table_##name##_p1, launch_table_##name##_p2, launch_table_##name##_p3;
 RBD_TOPOLOGIES(RBD_DECL)
 #undef RBD_DECL
 
@@ -21,11 +26,24 @@ static const TopoInfo k_topos[] = {
 #undef RBD_INFO
 };
 
-static const LaunchTable* const k_tables[] = {
-#define RBD_TAB(name, fr, ...) &launch_table_##name,
+static const LaunchTable* const k_parts[][3] = {
+#define RBD_TAB(name, fr, ...) {&launch_table_##name##_p1, &launch_table_##name##_p2, &launch_table_##name##_p3},
     RBD_TOPOLOGIES(RBD_TAB)
 #undef RBD_TAB
 };
+
+// The three parts of a topology merged into one table (built on first use).
+static const LaunchTable* merged(int id) {
+  static const std::vector<LaunchTable> all = [] {
+    std::vector<LaunchTable> v(sizeof(k_parts) / sizeof(k_parts[0]));
+    for (size_t i = 0; i < v.size(); ++i) {
+      const LaunchTable &a = *k_parts[i][0], &b = *k_parts[i][1], &c = *k_parts[i][2];
+      v[i] = LaunchTable{a.fk, a.jacobian, a.rnea, a.crba, b.fwd_dyn, c.vjp, b.packed, c.packed_vjp};
+    }
+    return v;
+  }();
+  return &all[id];
+}
 
 int n_topologies() { return (int)(sizeof(k_topos) / sizeof(k_topos[0])); }
 const TopoInfo& topology(int id) { return k_topos[id]; }
@@ -40,8 +58,16 @@ int find_topology(bool floating, int n, const int32_t* parent) {
   return -1;
 }
 
+bool tables_in_lds() {
+  static const bool lds = [] {
+    const char* e = std::getenv("RBD_TABLES");
+    return e && std::strcmp(e, "lds") == 0;
+  }();
+  return lds;
+}
+
 static const LaunchTable* table_of(const rbd_model* m) {
-  return (m->topo >= 0 && m->topo < n_topologies()) ? k_tables[m->topo] : nullptr;
+  return (m->topo >= 0 && m->topo < n_topologies()) ? merged(m->topo) : nullptr;
 }
 
 #define RBD_TABLE_OR_FAIL(m)                                                     \
@@ -102,6 +128,7 @@ rbd_status launch_fwd_dyn_vjp(const rbd_model* m, int64_t batch, int64_t ld, con
 
 rbd_status launch_packed(const rbd_model* m, int op, const void* d_table, int grid, hipStream_t s) {
   RBD_TABLE_OR_FAIL(m);
+  if (op == RBD_OP_FWD_DYN_VJP) return lt->packed_vjp(op, m->d_tab, d_table, grid, s);
   return lt->packed(op, m->d_tab, d_table, grid, s);
 }
 

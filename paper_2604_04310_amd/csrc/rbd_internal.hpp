@@ -24,6 +24,11 @@ namespace rbd {
 // FP32 device tables of a validated tree (layout in rbd_lane.hpp)
 std::vector<float> make_tables(const rbd_tree_desc* d);
 
+// Model constants read through the scalar cache (default) or staged in LDS
+// per block (environment variable RBD_TABLES=lds; slower on gfx950 for the
+// large trees, whose extra vector registers then spill).
+bool tables_in_lds();
+
 // error reporting (thread-local message)
 rbd_status fail(rbd_status s, const char* fmt, ...);
 void clear_error();
@@ -66,6 +71,7 @@ struct LaunchTable {
   rbd_status (*vjp)(const float* tab, int64_t batch, int64_t ld, const float* q, const float* qd, const float* tau,
                     const float* gqdd, float* gq, float* gqd, float* gtau, hipStream_t s);
   rbd_status (*packed)(int op, const float* tab, const void* table, int grid, hipStream_t s);
+  rbd_status (*packed_vjp)(int op, const float* tab, const void* table, int grid, hipStream_t s);
 };
 
 // Packed serving launch of one (model, op): d_table holds a PackedHdr-led

@@ -1,10 +1,10 @@
 // Kernels of one compiled topology. Built once per entry of RBD_TOPOLOGIES
-// with -DRBD_TOPO=<name>, so the topologies compile in parallel.
+// and part (-DRBD_TOPO=<name> -DRBD_PART=1|2|3), so they compile in parallel.
 #include "rbd_kernels.hpp"
 #include "rbd_topologies.hpp"
 
-#ifndef RBD_TOPO
-#error "RBD_TOPO must name a topology"
+#if !defined(RBD_TOPO) || !defined(RBD_PART)
+#error "RBD_TOPO must name a topology and RBD_PART a part (1..3)"
 #endif
 
 #define RBD_CAT2(a, b) a##b
@@ -19,7 +19,8 @@ using TP = RBD_CAT(T_, RBD_TOPO);
 static_assert(TP::depth_first(), "topology is not depth-first");
 }  // namespace
 
-extern const LaunchTable RBD_CAT(launch_table_, RBD_TOPO);
-const LaunchTable RBD_CAT(launch_table_, RBD_TOPO) = Launch<TP>::table();
+#define RBD_NAME RBD_CAT(RBD_CAT(RBD_CAT(launch_table_, RBD_TOPO), _p), RBD_PART)
+extern const LaunchTable RBD_NAME;
+const LaunchTable RBD_NAME = Launch<TP>::part(RBD_PART);
 
 }  // namespace rbd

@@ -12,67 +12,86 @@ namespace rbd {
 
 constexpr int kBlock = 256;
 
-RBD_DI int64_t lane_id() { return (int64_t)blockIdx.x * blockDim.x + threadIdx.x; }
+RBD_DI uint32_t lane_id() { return blockIdx.x * blockDim.x + threadIdx.x; }
+
+// Stages the model tables in LDS; every thread of the block must call it
+// (before any early exit), since it ends with a barrier.
+template <class TP>
+RBD_DI const float* stage_tables(const float* __restrict__ tab, float* lds) {
+  constexpr int n = TP::N * kBodyStride + 4;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) lds[i] = tab[i];
+  __syncthreads();
+  return lds;
+}
 
 template <class TP>
 __global__ __launch_bounds__(kBlock) void k_fk(const float* __restrict__ tab, int64_t batch, int64_t ld,
                                                const float* __restrict__ q, float* __restrict__ T) {
-  const int64_t b = lane_id();
+  const uint32_t b = lane_id();
   if (b >= batch) return;
-  fk_lane<TP>(tab, In{q + b, ld}, Out{T + b, ld});
+  fk_lane<TP>(tab, In{q, ld, b}, Out{T, ld, b});
 }
 
 template <class TP>
 __global__ __launch_bounds__(kBlock) void k_jacobian(const float* __restrict__ tab, int64_t batch, int64_t ld,
                                                      const float* __restrict__ q, JacSlots js,
                                                      float* __restrict__ J) {
-  const int64_t b = lane_id();
+  const uint32_t b = lane_id();
   if (b >= batch) return;
-  jac_lane<TP>(tab, In{q + b, ld}, js, J + b, ld);
+  jac_lane<TP>(tab, In{q, ld, b}, js, J, ld, b);
 }
 
 template <class TP, bool HAS_QDD>
 __global__ __launch_bounds__(kBlock) void k_rnea(const float* __restrict__ tab, int64_t batch, int64_t ld,
                                                  const float* __restrict__ q, const float* __restrict__ qd,
                                                  const float* __restrict__ qdd, float* __restrict__ tau) {
-  const int64_t b = lane_id();
+  const uint32_t b = lane_id();
   if (b >= batch) return;
-  rnea_lane<TP, HAS_QDD>(tab, In{q + b, ld}, In{qd + b, ld}, In{HAS_QDD ? qdd + b : q + b, ld}, Out{tau + b, ld});
+  rnea_lane<TP, HAS_QDD>(tab, In{q, ld, b}, In{qd, ld, b}, In{HAS_QDD ? qdd : q, ld, b}, Out{tau, ld, b});
 }
 
 template <class TP>
 __global__ __launch_bounds__(kBlock) void k_crba(const float* __restrict__ tab, int64_t batch, int64_t ld,
                                                  const float* __restrict__ q, float* __restrict__ M) {
-  const int64_t b = lane_id();
+  const uint32_t b = lane_id();
   if (b >= batch) return;
-  crba_lane<TP>(tab, In{q + b, ld}, M + b, ld);
+  crba_lane<TP>(tab, In{q, ld, b}, M, ld, b);
 }
 
-struct RhsTau {
-  In tau;
+template <class X>
+struct RhsOne {
+  X tau;
   RBD_DI float operator()(int, int k) const { return tau(k); }
 };
-struct SinkOut {
-  Out x;
+template <class Y>
+struct SinkOne {
+  Y x;
   RBD_DI void operator()(int, int k, float v) const { x(k, v); }
 };
 
-template <class TP>
+// LDS = true reads the model constants from LDS, false through the scalar cache.
+template <class TP, bool LDS>
 __global__ __launch_bounds__(kBlock) void k_fwd_dyn(const float* __restrict__ tab, int64_t batch, int64_t ld,
                                                     const float* __restrict__ q, const float* __restrict__ qd,
                                                     const float* __restrict__ tau, float* __restrict__ qdd) {
-  const int64_t b = lane_id();
+  const float* t = tab;
+  if constexpr (LDS) {
+    __shared__ float lds[TP::N * kBodyStride + 4];
+    t = stage_tables<TP>(tab, lds);
+  }
+  const uint32_t b = lane_id();
   if (b >= batch) return;
-  fwd_dyn_lane<TP, 1>(tab, In{q + b, ld}, In{qd + b, ld}, RhsTau{In{tau + b, ld}}, SinkOut{Out{qdd + b, ld}});
+  fwd_dyn_lane<TP, 1>(t, In{q, ld, b}, In{qd, ld, b}, RhsOne<In>{In{tau, ld, b}}, SinkOne<Out>{Out{qdd, ld, b}});
 }
 
 // ---- fwd_dyn adjoint: solve M [qdd, lam] = [tau - h, gbar] with one factor,
 // write g_tau = lam, then run the inverse-dynamics adjoint at (q, qd, qdd).
+template <class X>
 struct RhsTwo {
-  In tau, gbar;
+  X tau, gbar;
   RBD_DI float operator()(int r, int k) const { return r == 0 ? tau(k) : gbar(k); }
 };
-struct SinkTwo {
+struct SinkRegs {
   float* qdd;
   float* lam;
   RBD_DI void operator()(int r, int k, float v) const {
@@ -83,20 +102,44 @@ struct RegView {
   const float* x;
   RBD_DI float operator()(int k) const { return x[k]; }
 };
+// An output that may be absent (null base).
+template <class Y>
 struct OutOpt {
-  float* __restrict__ p;
-  int64_t ld;
+  Y y;
+  bool on;
   RBD_DI void operator()(int c, float v) const {
-    if (p) p[c * ld] = v;
+    if (on) y(c, v);
+  }
+};
+// Views of q-double-dot and lam parked in the g_qd and g_tau outputs: not
+// restrict-qualified, so the compiler keeps every load before the store that
+// later overwrites the same element.
+struct InAlias {
+  const float* base;
+  int64_t ld;
+  uint32_t lane;
+  RBD_DI float operator()(int c) const { return (base + c * ld)[lane]; }
+};
+struct OutAlias {
+  float* base;
+  int64_t ld;
+  uint32_t lane;
+  RBD_DI void operator()(int c, float v) const { (base + c * ld)[lane] = v; }
+};
+template <class Y>
+struct SinkTwo {
+  Y qdd, lam;
+  RBD_DI void operator()(int r, int k, float v) const {
+    if (r == 0) qdd(k, v); else lam(k, v);
   }
 };
 
-template <class TP, bool ADJ>
-RBD_DI void vjp_lane(const float* __restrict__ tab, const In& q, const In& qd, const In& tau, const In& gqdd,
-                     const OutOpt& gq, const OutOpt& gqd, const OutOpt& gtau) {
+template <class TP, bool ADJ, class QI, class X, class GQ, class GQD, class GT>
+RBD_DI void vjp_lane(const float* __restrict__ tab, const QI& q, const X& qd, const X& tau, const X& gqdd,
+                     const GQ& gq, const GQD& gqd, const GT& gtau) {
   constexpr int NV = TP::NV;
   float qddv[NV], lam[NV];
-  fwd_dyn_lane<TP, 2>(tab, q, qd, RhsTwo{tau, gqdd}, SinkTwo{qddv, lam});
+  fwd_dyn_lane<TP, 2>(tab, q, qd, RhsTwo<X>{tau, gqdd}, SinkRegs{qddv, lam});
   sfor<0, NV>([&](auto K_) __attribute__((always_inline)) {
     constexpr int K = decltype(K_)::value;
     gtau(K, lam[K]);
@@ -104,17 +147,48 @@ RBD_DI void vjp_lane(const float* __restrict__ tab, const In& q, const In& qd, c
   if constexpr (ADJ) id_adjoint_lane<TP>(tab, q, qd, RegView{qddv}, RegView{lam}, gq, gqd);
 }
 
-template <class TP, bool ADJ>
+// q-double-dot parked in g_qd and lam in g_tau between the solve and the
+// adjoint sweep, instead of 2 nv registers held across it. Every element is
+// read by its body's forward step before that body's backward step
+// overwrites g_qd.
+template <class TP, class QI, class X, class GQ, class P>
+RBD_DI void vjp_lane_parked(const float* __restrict__ tab, const QI& q, const X& qd, const X& tau, const X& gqdd,
+                            const GQ& gq, const P& gqd_out, const P& gtau_out, const typename P::In& gqd_in,
+                            const typename P::In& gtau_in) {
+  fwd_dyn_lane<TP, 2>(tab, q, qd, RhsTwo<X>{tau, gqdd}, SinkTwo<P>{gqd_out, gtau_out});
+  id_adjoint_lane<TP>(tab, q, qd, gqd_in, gtau_in, gq, gqd_out);
+}
+struct OutAliasP : OutAlias {
+  using In = InAlias;
+};
+struct RowAlias {
+  float* p;
+  RBD_DI void operator()(int c, float v) const { p[c] = v; }
+  struct In {
+    const float* p;
+    RBD_DI float operator()(int c) const { return p[c]; }
+  };
+};
+
+// MODE 0: g_tau only; 1: adjoint with q-double-dot and lam in registers (some
+// output absent); 2: adjoint with both parked in g_qd and g_tau.
+template <class TP, int MODE>
 __global__ __launch_bounds__(kBlock) void k_fwd_dyn_vjp(const float* __restrict__ tab, int64_t batch, int64_t ld,
                                                         const float* __restrict__ q, const float* __restrict__ qd,
                                                         const float* __restrict__ tau,
-                                                        const float* __restrict__ gqdd, float* __restrict__ gq,
-                                                        float* __restrict__ gqd, float* __restrict__ gtau) {
-  const int64_t b = lane_id();
+                                                        const float* __restrict__ gqdd, float* gq, float* gqd,
+                                                        float* gtau) {
+  const uint32_t b = lane_id();
   if (b >= batch) return;
-  vjp_lane<TP, ADJ>(tab, In{q + b, ld}, In{qd + b, ld}, In{tau + b, ld}, In{gqdd + b, ld},
-                    OutOpt{gq ? gq + b : nullptr, ld}, OutOpt{gqd ? gqd + b : nullptr, ld},
-                    OutOpt{gtau ? gtau + b : nullptr, ld});
+  const In qi{q, ld, b}, qdi{qd, ld, b}, ti{tau, ld, b}, gi{gqdd, ld, b};
+  const OutOpt<OutAlias> gqo{OutAlias{gq, ld, b}, gq != nullptr};
+  if constexpr (MODE == 2) {
+    const OutAliasP pd{{gqd, ld, b}}, pt{{gtau, ld, b}};
+    vjp_lane_parked<TP>(tab, qi, qdi, ti, gi, gqo, pd, pt, InAlias{gqd, ld, b}, InAlias{gtau, ld, b});
+  } else {
+    vjp_lane<TP, MODE == 1>(tab, qi, qdi, ti, gi, gqo, OutOpt<OutAlias>{OutAlias{gqd, ld, b}, gqd != nullptr},
+                            OutOpt<OutAlias>{OutAlias{gtau, ld, b}, gtau != nullptr});
+  }
 }
 
 // ---- packed launch for the serving runtime. One launch serves many requests
@@ -139,14 +213,16 @@ __global__ __launch_bounds__(kBlock) void k_packed(const float* __restrict__ tab
     const PackedReq& R = reqs[r];
     const int64_t i = (int64_t)(t - R.first_tile) * kTileLanes + lane;
     if (i >= R.batch) continue;
-    const In q{R.in[0] + i * NQ, 1}, qd{R.in[1] + i * NV, 1}, x2{R.in[2] + i * NV, 1};
+    const InRow q{R.in[0] + i * NQ}, qd{R.in[1] + i * NV}, x2{R.in[2] + i * NV};
     if constexpr (OP == RBD_OP_FWD_DYN) {
-      fwd_dyn_lane<TP, 1>(tab, q, qd, RhsTau{x2}, SinkOut{Out{R.out[0] + i * NV, 1}});
+      fwd_dyn_lane<TP, 1>(tab, q, qd, RhsOne<InRow>{x2}, SinkOne<OutRow>{OutRow{R.out[0] + i * NV}});
     } else if constexpr (OP == RBD_OP_RNEA) {
-      rnea_lane<TP, true>(tab, q, qd, x2, Out{R.out[0] + i * NV, 1});
+      rnea_lane<TP, true>(tab, q, qd, x2, OutRow{R.out[0] + i * NV});
     } else {
-      vjp_lane<TP, true>(tab, q, qd, x2, In{R.in[3] + i * NV, 1}, OutOpt{R.out[0] + i * NQ, 1},
-                         OutOpt{R.out[1] + i * NV, 1}, OutOpt{R.out[2] + i * NV, 1});
+      float* gqd = R.out[1] + i * NV;
+      float* gtau = R.out[2] + i * NV;
+      vjp_lane_parked<TP>(tab, q, qd, x2, InRow{R.in[3] + i * NV}, OutRow{R.out[0] + i * NQ}, RowAlias{gqd},
+                          RowAlias{gtau}, RowAlias::In{gqd}, RowAlias::In{gtau});
     }
   }
 }
@@ -189,39 +265,58 @@ struct Launch {
   }
   static rbd_status fwd_dyn(const float* tab, int64_t batch, int64_t ld, const float* q, const float* qd,
                             const float* tau, float* qdd, hipStream_t s) {
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_fwd_dyn<TP>), dim3(grid_for(batch)), dim3(kBlock), 0, s, tab, batch, ld,
-                       q, qd, tau, qdd);
+    if (tables_in_lds())
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_fwd_dyn<TP, true>), dim3(grid_for(batch)), dim3(kBlock), 0, s, tab,
+                         batch, ld, q, qd, tau, qdd);
+    else
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_fwd_dyn<TP, false>), dim3(grid_for(batch)), dim3(kBlock), 0, s, tab,
+                         batch, ld, q, qd, tau, qdd);
     return check_launch("rbd_fwd_dyn");
   }
   static rbd_status vjp(const float* tab, int64_t batch, int64_t ld, const float* q, const float* qd,
                         const float* tau, const float* gqdd, float* gq, float* gqd, float* gtau, hipStream_t s) {
-    if (gq || gqd)
-      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_fwd_dyn_vjp<TP, true>), dim3(grid_for(batch)), dim3(kBlock), 0, s, tab,
+    if (gqd && gtau)
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_fwd_dyn_vjp<TP, 2>), dim3(grid_for(batch)), dim3(kBlock), 0, s, tab,
+                         batch, ld, q, qd, tau, gqdd, gq, gqd, gtau);
+    else if (gq || gqd)
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_fwd_dyn_vjp<TP, 1>), dim3(grid_for(batch)), dim3(kBlock), 0, s, tab,
                          batch, ld, q, qd, tau, gqdd, gq, gqd, gtau);
     else
-      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_fwd_dyn_vjp<TP, false>), dim3(grid_for(batch)), dim3(kBlock), 0, s, tab,
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_fwd_dyn_vjp<TP, 0>), dim3(grid_for(batch)), dim3(kBlock), 0, s, tab,
                          batch, ld, q, qd, tau, gqdd, gq, gqd, gtau);
     return check_launch("rbd_fwd_dyn_vjp");
   }
   static rbd_status packed(int op, const float* tab, const void* table, int grid, hipStream_t s) {
     const uint8_t* t = static_cast<const uint8_t*>(table);
-    switch (op) {
-      case RBD_OP_FWD_DYN:
-        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_packed<TP, RBD_OP_FWD_DYN>), dim3(grid), dim3(kBlock), 0, s, tab, t);
-        break;
-      case RBD_OP_RNEA:
-        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_packed<TP, RBD_OP_RNEA>), dim3(grid), dim3(kBlock), 0, s, tab, t);
-        break;
-      default:
-        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_packed<TP, RBD_OP_FWD_DYN_VJP>), dim3(grid), dim3(kBlock), 0, s, tab,
-                           t);
-        break;
-    }
+    if (op == RBD_OP_FWD_DYN)
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_packed<TP, RBD_OP_FWD_DYN>), dim3(grid), dim3(kBlock), 0, s, tab, t);
+    else
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_packed<TP, RBD_OP_RNEA>), dim3(grid), dim3(kBlock), 0, s, tab, t);
     return check_launch("packed launch");
   }
-  static LaunchTable table() {
-    return LaunchTable{&Launch::fk, &Launch::jacobian, &Launch::rnea, &Launch::crba,
-                       &Launch::fwd_dyn, &Launch::vjp, &Launch::packed};
+  static rbd_status packed_vjp(int, const float* tab, const void* table, int grid, hipStream_t s) {
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_packed<TP, RBD_OP_FWD_DYN_VJP>), dim3(grid), dim3(kBlock), 0, s, tab,
+                       static_cast<const uint8_t*>(table));
+    return check_launch("packed launch");
+  }
+  // Part 1: kinematics, inverse dynamics, mass matrix. Part 2: forward dynamics
+  // and the packed forward-dynamics and inverse-dynamics launches. Part 3: the
+  // adjoint and its packed launch. Each part is its own translation unit.
+  static LaunchTable part(int k) {
+    LaunchTable t{};
+    if (k == 1) {
+      t.fk = &Launch::fk;
+      t.jacobian = &Launch::jacobian;
+      t.rnea = &Launch::rnea;
+      t.crba = &Launch::crba;
+    } else if (k == 2) {
+      t.fwd_dyn = &Launch::fwd_dyn;
+      t.packed = &Launch::packed;
+    } else {
+      t.vjp = &Launch::vjp;
+      t.packed_vjp = &Launch::packed_vjp;
+    }
+    return t;
   }
 };
 

@@ -214,17 +214,35 @@ RBD_DI Frc crf(const Mot& v, const Frc& f) { return {cross(v.w, f.n) + cross(v.v
 RBD_DI Mot crm(const Mot& v, const Mot& m) { return {cross(v.w, m.w), cross(v.w, m.v) + cross(v.v, m.w)}; }
 RBD_DI float pair(const Frc& f, const Mot& m) { return dot(f.n, m.w) + dot(f.f, m.v); }
 
+// Fused forms: c + a x b and c + R x as chains of fused multiply-adds (the
+// compiler does not reassociate a separately written sum into them).
+RBD_DI V3 cross_add(V3 a, V3 b, V3 c) {
+  return {__builtin_fmaf(a.y, b.z, __builtin_fmaf(-a.z, b.y, c.x)), __builtin_fmaf(a.z, b.x, __builtin_fmaf(-a.x, b.z, c.y)),
+          __builtin_fmaf(a.x, b.y, __builtin_fmaf(-a.y, b.x, c.z))};
+}
+RBD_DI V3 mul_add(const M3& R, V3 x, V3 c) {
+  return {__builtin_fmaf(R.a[0], x.x, __builtin_fmaf(R.a[1], x.y, __builtin_fmaf(R.a[2], x.z, c.x))),
+          __builtin_fmaf(R.a[3], x.x, __builtin_fmaf(R.a[4], x.y, __builtin_fmaf(R.a[5], x.z, c.y))),
+          __builtin_fmaf(R.a[6], x.x, __builtin_fmaf(R.a[7], x.y, __builtin_fmaf(R.a[8], x.z, c.z)))};
+}
+
 // Child frame at r (parent coords) with axes R (columns, parent coords).
 // motion parent -> child: w' = R^T w, v' = R^T (v + w x r)
-RBD_DI Mot xmot(const M3& R, V3 r, const Mot& m) { return {mulT(R, m.w), mulT(R, m.v + cross(m.w, r))}; }
+RBD_DI Mot xmot(const M3& R, V3 r, const Mot& m) { return {mulT(R, m.w), mulT(R, cross_add(m.w, r, m.v))}; }
 // force child -> parent: f' = R f, n' = R n + r x f'
 RBD_DI Frc xfrc(const M3& R, V3 r, const Frc& f) {
   const V3 fp = mul(R, f.f);
-  return {mul(R, f.n) + cross(r, fp), fp};
+  return {mul_add(R, f.n, cross(r, fp)), fp};
 }
-// inertia child -> parent (X^T I X): h' = R h + m r,
+// acc += X^T f
+RBD_DI void xfrc_acc(const M3& R, V3 r, const Frc& f, Frc& acc) {
+  const V3 fp = mul(R, f.f);
+  acc.n = mul_add(R, f.n, cross_add(r, fp, acc.n));
+  acc.f = acc.f + fp;
+}
+// acc += X^T I X (inertia child -> parent): h' = R h + m r,
 // Ibar' = R Ibar R^T - (u r^T + r u^T - 2 (r.u) 1) - m (r r^T - |r|^2 1), u = R h
-RBD_DI Inr xinr(const M3& R, V3 r, const Inr& I) {
+RBD_DI void xinr_acc(const M3& R, V3 r, const Inr& I, Inr& acc) {
   const V3 u = mul(R, I.h);
   // T = R * Ibar (Ibar symmetric)
   const V3 c0 = {I.xx, I.xy, I.xz}, c1 = {I.xy, I.yy, I.yz}, c2 = {I.xz, I.yz, I.zz};
@@ -232,18 +250,21 @@ RBD_DI Inr xinr(const M3& R, V3 r, const Inr& I) {
   const V3 t0 = {dot(r0, c0), dot(r0, c1), dot(r0, c2)};
   const V3 t1 = {dot(r1, c0), dot(r1, c1), dot(r1, c2)};
   const V3 t2 = {dot(r2, c0), dot(r2, c1), dot(r2, c2)};
-  const float ru = dot(r, u), rr = dot(r, r);
-  const float d = 2.0f * ru + I.m * rr;
-  Inr o;
-  o.m = I.m;
-  o.h = u + I.m * r;
-  o.xx = dot(t0, r0) - 2.0f * u.x * r.x - I.m * r.x * r.x + d;
-  o.yy = dot(t1, r1) - 2.0f * u.y * r.y - I.m * r.y * r.y + d;
-  o.zz = dot(t2, r2) - 2.0f * u.z * r.z - I.m * r.z * r.z + d;
-  o.xy = dot(t0, r1) - (u.x * r.y + r.x * u.y) - I.m * r.x * r.y;
-  o.xz = dot(t0, r2) - (u.x * r.z + r.x * u.z) - I.m * r.x * r.z;
-  o.yz = dot(t1, r2) - (u.y * r.z + r.y * u.z) - I.m * r.y * r.z;
-  return o;
+  const float ru = dot(r, u);
+  const float d = __builtin_fmaf(I.m, dot(r, r), 2.0f * ru);
+  const V3 mr = I.m * r;  // m r
+  const V3 w = u + mr;    // u + m r, so that u r^T + r u^T + m r r^T = w r^T + r u^T on the diagonal terms below
+  acc.m = acc.m + I.m;
+  acc.h = acc.h + w;
+  auto fdot = [](V3 a, V3 b, float c) __attribute__((always_inline)) {
+    return __builtin_fmaf(a.x, b.x, __builtin_fmaf(a.y, b.y, __builtin_fmaf(a.z, b.z, c)));
+  };
+  acc.xx = fdot(t0, r0, __builtin_fmaf(-(u.x + w.x), r.x, acc.xx + d));
+  acc.yy = fdot(t1, r1, __builtin_fmaf(-(u.y + w.y), r.y, acc.yy + d));
+  acc.zz = fdot(t2, r2, __builtin_fmaf(-(u.z + w.z), r.z, acc.zz + d));
+  acc.xy = fdot(t0, r1, __builtin_fmaf(-w.x, r.y, __builtin_fmaf(-r.x, u.y, acc.xy)));
+  acc.xz = fdot(t0, r2, __builtin_fmaf(-w.x, r.z, __builtin_fmaf(-r.x, u.z, acc.xz)));
+  acc.yz = fdot(t1, r2, __builtin_fmaf(-w.y, r.z, __builtin_fmaf(-r.y, u.z, acc.yz)));
 }
 
 RBD_DI void fsincos(float q, float& s, float& c) {
@@ -280,10 +301,8 @@ RBD_DI V3 load_g(const float* __restrict__ t) {
 }
 // R = K Rz(q): columns c K0 + s K1, -s K0 + c K1, K2
 template <int I>
-RBD_DI M3 joint_rot(const float* __restrict__ t, float q) {
+RBD_DI M3 joint_rot_cs(const float* __restrict__ t, float c, float s) {
   const float* K = t + I * kBodyStride + kOffK;
-  float s, c;
-  fsincos(q, s, c);
   M3 R;
 #pragma unroll
   for (int r = 0; r < 3; ++r) {
@@ -292,6 +311,12 @@ RBD_DI M3 joint_rot(const float* __restrict__ t, float q) {
     R.a[3 * r + 2] = K[3 * r + 2];
   }
   return R;
+}
+template <int I>
+RBD_DI M3 joint_rot(const float* __restrict__ t, float q) {
+  float s, c;
+  fsincos(q, s, c);
+  return joint_rot_cs<I>(t, c, s);
 }
 // Rotation of a quaternion (w,x,y,z) divided by its squared norm.
 RBD_DI M3 quat_rot(float w, float x, float y, float z) {
@@ -314,22 +339,38 @@ RBD_DI M3 quat_rot(float w, float x, float y, float z) {
 RBD_DI Frc inr_col_z(const Inr& I) { return {{I.xz, I.yz, I.zz}, {-I.h.y, I.h.x, 0.0f}}; }
 
 // =================================================================== lane I/O
-// One lane's view of a structure-of-arrays batch: element c at p[c * ld].
+// A lane's view of a structure-of-arrays batch: element c of the lane's
+// instance is row(c)[lane], with row(c) = base + c * ld the same for the whole
+// wave. The row pointer lives in scalar registers and the lane offset is one
+// 32-bit register shared by every access (global loads and stores take an
+// SGPR base plus a 32-bit VGPR offset), so no per-access 64-bit address has
+// to be kept in vector registers.
 struct In {
-  const float* __restrict__ p;
+  const float* __restrict__ base;
   int64_t ld;
-  RBD_DI float operator()(int c) const { return p[c * ld]; }
+  uint32_t lane;
+  RBD_DI float operator()(int c) const { return (base + c * ld)[lane]; }
 };
 struct Out {
-  float* __restrict__ p;
+  float* __restrict__ base;
   int64_t ld;
-  RBD_DI void operator()(int c, float v) const { p[c * ld] = v; }
+  uint32_t lane;
+  RBD_DI void operator()(int c, float v) const { (base + c * ld)[lane] = v; }
+};
+// A lane's own row of an instance-major array (coordinate c at p[c]).
+struct InRow {
+  const float* __restrict__ p;
+  RBD_DI float operator()(int c) const { return p[c]; }
+};
+struct OutRow {
+  float* __restrict__ p;
+  RBD_DI void operator()(int c, float v) const { p[c] = v; }
 };
 
 // =================================================================== FK
 // World pose of every body in the user's body axes: [R | p] row-major.
-template <class TP>
-RBD_DI void fk_lane(const float* __restrict__ t, const In& q, const Out& T) {
+template <class TP, class QI, class TO>
+RBD_DI void fk_lane(const float* __restrict__ t, const QI& q, const TO& T) {
   constexpr int N = TP::N;
   M3 Rw[N];
   V3 pw[N];
@@ -366,9 +407,9 @@ RBD_DI void fk_lane(const float* __restrict__ t, const In& q, const Out& T) {
 }
 
 // =================================================================== Jacobian
-template <class TP>
-RBD_DI void jac_lane(const float* __restrict__ t, const In& q, const JacSlots& js, float* __restrict__ J,
-                     int64_t ld) {
+template <class TP, class QI>
+RBD_DI void jac_lane(const float* __restrict__ t, const QI& q, const JacSlots& js, float* __restrict__ J, int64_t ld,
+                     uint32_t lane) {
   constexpr int N = TP::N, NV = TP::NV;
   M3 Rw[N];
   V3 pw[N];
@@ -392,7 +433,7 @@ RBD_DI void jac_lane(const float* __restrict__ t, const In& q, const JacSlots& j
     const int beg = js.beg[K], end = js.beg[K + 1];
     for (int s = beg; s < end; ++s) {
       float* __restrict__ Jf = J + (int64_t)js.slot[s] * 6 * NV * ld;
-      auto put = [&](int r, int c, float v) __attribute__((always_inline)) { Jf[(int64_t)(r * NV + c) * ld] = v; };
+      auto put = [&](int r, int c, float v) __attribute__((always_inline)) { (Jf + (int64_t)(r * NV + c) * ld)[lane] = v; };
       sfor<0, N>([&](auto A_) __attribute__((always_inline)) {
         constexpr int A = decltype(A_)::value;
         constexpr int c0 = TP::vofs(A);
@@ -429,8 +470,8 @@ RBD_DI void jac_lane(const float* __restrict__ t, const In& q, const JacSlots& j
 // tau = ID(q, qd, qdd); qdd may be absent (bias force). Depth-first: the
 // backward step of a body runs as soon as its subtree is done, so only the
 // current root path is live.
-template <class TP, bool HAS_QDD>
-RBD_DI void rnea_lane(const float* __restrict__ t, const In& q, const In& qd, const In& qdd, const Out& tau) {
+template <class TP, bool HAS_QDD, class QI, class QDI, class QDDI, class TO>
+RBD_DI void rnea_lane(const float* __restrict__ t, const QI& q, const QDI& qd, const QDDI& qdd, const TO& tau) {
   constexpr int N = TP::N;
   M3 R[N];
   Mot v[N], a[N];
@@ -446,7 +487,7 @@ RBD_DI void rnea_lane(const float* __restrict__ t, const In& q, const In& qd, co
       tau(3, f[J].n.x); tau(4, f[J].n.y); tau(5, f[J].n.z);
     } else {
       tau(cidx<TP::vofs(J)>, f[J].n.z);
-      if constexpr (P >= 0) f[P] = f[P] + xfrc(R[J], load_r<J>(t), f[J]);
+      if constexpr (P >= 0) xfrc_acc(R[J], load_r<J>(t), f[J], f[P]);
     }
   };
 
@@ -509,12 +550,12 @@ RBD_DI float base_block(const Inr& I, int r, int c) {
 }
 
 // =================================================================== CRBA
-template <class TP>
-RBD_DI void crba_lane(const float* __restrict__ t, const In& q, float* __restrict__ Mp, int64_t ld) {
+template <class TP, class QI>
+RBD_DI void crba_lane(const float* __restrict__ t, const QI& q, float* __restrict__ Mp, int64_t ld, uint32_t lane) {
   constexpr int N = TP::N, NV = TP::NV;
   M3 R[N];
   Inr Ic[N];
-  auto put = [&](int r, int c, float v) __attribute__((always_inline)) { Mp[(int64_t)(r * NV + c) * ld] = v; };
+  auto put = [&](int r, int c, float v) __attribute__((always_inline)) { (Mp + (int64_t)(r * NV + c) * ld)[lane] = v; };
 
   auto backward = [&](auto J_) __attribute__((always_inline)) {
     constexpr int J = decltype(J_)::value;
@@ -539,7 +580,7 @@ RBD_DI void crba_lane(const float* __restrict__ t, const In& q, float* __restric
         }
       };
       walk_up<TP, J>(t, R, inr_col_z(Ic[J]), emit);
-      if constexpr (P >= 0) Ic[P] = Ic[P] + xinr(R[J], load_r<J>(t), Ic[J]);
+      if constexpr (P >= 0) xinr_acc(R[J], load_r<J>(t), Ic[J], Ic[P]);
     }
   };
 
@@ -573,8 +614,8 @@ RBD_DI void crba_lane(const float* __restrict__ t, const In& q, float* __restric
 //   row k of the factor M = L^T L (left-looking, branch-sparse: entries only
 //   for ancestors, no fill-in), and y_k of L^T y = b      (sparse Cholesky)
 // and a final root-to-leaves sweep solves L x = y.
-template <class TP, int NRHS, class RHS, class SINK>
-RBD_DI void fwd_dyn_lane(const float* __restrict__ t, const In& q, const In& qd, const RHS& rhs, const SINK& sink) {
+template <class TP, int NRHS, class QI, class QDI, class RHS, class SINK>
+RBD_DI void fwd_dyn_lane(const float* __restrict__ t, const QI& q, const QDI& qd, const RHS& rhs, const SINK& sink) {
   constexpr int N = TP::N, NV = TP::NV;
   constexpr int NNZ = TP::nnz() > 0 ? TP::nnz() : 1;
   M3 R[N];
@@ -653,8 +694,8 @@ RBD_DI void fwd_dyn_lane(const float* __restrict__ t, const In& q, const In& qd,
       factor_row(ic<k>{}, Mr, Ic[J].zz, bk);
       if constexpr (P >= 0) {
         const V3 r = load_r<J>(t);
-        f[P] = f[P] + xfrc(R[J], r, f[J]);
-        Ic[P] = Ic[P] + xinr(R[J], r, Ic[J]);
+        xfrc_acc(R[J], r, f[J], f[P]);
+        xinr_acc(R[J], r, Ic[J], Ic[P]);
       }
     }
   };
@@ -721,11 +762,14 @@ RBD_DI void fwd_dyn_lane(const float* __restrict__ t, const In& q, const In& qd,
 //   dqd_i = S^T vbar - S^T (v x* abar).
 // For a free base only gravity a_0 = R^T (-g) depends on q (through the
 // quaternion); its position never enters body-frame dynamics.
-template <class TP, class QDD, class LAM, class GQ, class GQD>
-RBD_DI void id_adjoint_lane(const float* __restrict__ t, const In& q, const In& qd, const QDD& qdd, const LAM& lam,
+template <class TP, class QI, class QDI, class QDD, class LAM, class GQ, class GQD>
+RBD_DI void id_adjoint_lane(const float* __restrict__ t, const QI& q, const QDI& qd, const QDD& qdd, const LAM& lam,
                             const GQ& gq, const GQD& gqd) {
   constexpr int N = TP::N;
-  M3 R[N];
+  // Only (cos q, sin q) of a body is kept between its forward and backward
+  // step; R is rebuilt when needed, which keeps the live root path small.
+  float cq[N], sq[N];
+  M3 R0;  // base rotation (free base only)
   Mot v[N], a[N], mu[N];
   float ap[N][4];  // (X a_parent) w.x, w.y, v.x, v.y
   Frc f[N], ab[N], vb[N];
@@ -747,7 +791,7 @@ RBD_DI void id_adjoint_lane(const float* __restrict__ t, const In& q, const In& 
       const V3 u = {x, y, z}, A = abar.f;
       const float gA = dot(g, A), uA = dot(u, A), gu = dot(g, u);
       const V3 axg = cross(A, g);
-      const float gRA = dot(g, mul(R[J], A));  // g^T R abar
+      const float gRA = dot(g, mul(R0, A));  // g^T R abar
       const float dw = 2.0f * w * gA + 2.0f * dot(u, axg);
       const float dx = -2.0f * x * gA + 2.0f * g.x * uA + 2.0f * gu * A.x + 2.0f * w * axg.x;
       const float dy = -2.0f * y * gA + 2.0f * g.y * uA + 2.0f * gu * A.y + 2.0f * w * axg.y;
@@ -775,9 +819,10 @@ RBD_DI void id_adjoint_lane(const float* __restrict__ t, const In& q, const In& 
         // <X mu_p, S x* f>: (X mu_p) has the x, y parts of mu
         dq = dq - mu[J].w.x * f[J].n.y + mu[J].w.y * f[J].n.x - mu[J].v.x * f[J].f.y + mu[J].v.y * f[J].f.x;
         const V3 r = load_r<J>(t);
-        f[P] = f[P] + xfrc(R[J], r, f[J]);
-        ab[P] = ab[P] + xfrc(R[J], r, abar);
-        vb[P] = vb[P] + xfrc(R[J], r, vbar);
+        const M3 RJ = joint_rot_cs<J>(t, cq[J], sq[J]);
+        xfrc_acc(RJ, r, f[J], f[P]);
+        xfrc_acc(RJ, r, abar, ab[P]);
+        xfrc_acc(RJ, r, vbar, vb[P]);
       }
       gq(cidx<TP::qofs(J)>, -dq);
     }
@@ -787,24 +832,25 @@ RBD_DI void id_adjoint_lane(const float* __restrict__ t, const In& q, const In& 
     constexpr int I = decltype(I_)::value;
     constexpr int P = TP::parent(I);
     if constexpr (TP::free_body(I)) {
-      R[I] = quat_rot(q(3), q(4), q(5), q(6));
+      R0 = quat_rot(q(3), q(4), q(5), q(6));
       v[I] = {{qd(3), qd(4), qd(5)}, {qd(0), qd(1), qd(2)}};
-      a[I] = {{qdd(3), qdd(4), qdd(5)}, mulT(R[I], mg) + V3{qdd(0), qdd(1), qdd(2)}};
+      a[I] = {{qdd(3), qdd(4), qdd(5)}, mulT(R0, mg) + V3{qdd(0), qdd(1), qdd(2)}};
       mu[I] = {{lam(3), lam(4), lam(5)}, {lam(0), lam(1), lam(2)}};
     } else {
-      R[I] = joint_rot<I>(t, q(cidx<TP::qofs(I)>));
+      fsincos(q(cidx<TP::qofs(I)>), sq[I], cq[I]);
+      const M3 RI = joint_rot_cs<I>(t, cq[I], sq[I]);
       const float w = qd(cidx<TP::vofs(I)>);
       Mot apI;
       if constexpr (P < 0) {
         v[I] = {{0.0f, 0.0f, w}, {0.0f, 0.0f, 0.0f}};
-        apI = {{0.0f, 0.0f, 0.0f}, mulT(R[I], mg)};
+        apI = {{0.0f, 0.0f, 0.0f}, mulT(RI, mg)};
         mu[I] = {{0.0f, 0.0f, 0.0f}, {0.0f, 0.0f, 0.0f}};
       } else {
         const V3 r = load_r<I>(t);
-        v[I] = xmot(R[I], r, v[P]);
+        v[I] = xmot(RI, r, v[P]);
         v[I].w.z = v[I].w.z + w;
-        apI = xmot(R[I], r, a[P]);
-        mu[I] = xmot(R[I], r, mu[P]);
+        apI = xmot(RI, r, a[P]);
+        mu[I] = xmot(RI, r, mu[P]);
       }
       ap[I][0] = apI.w.x; ap[I][1] = apI.w.y; ap[I][2] = apI.v.x; ap[I][3] = apI.v.y;
       a[I] = apI;

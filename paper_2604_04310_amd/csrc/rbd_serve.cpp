@@ -149,7 +149,7 @@ struct rbd_server {
   Arena arena;
   std::vector<Slot> slots;
   std::mutex mu;
-  std::condition_variable cv_work, cv_done;
+  std::condition_variable cv_work, cv_done, cv_inflight;
   std::deque<std::shared_ptr<Request>> pending;
   std::unordered_map<uint64_t, std::shared_ptr<Request>> tickets;
   std::vector<Group*> inflight;
@@ -356,6 +356,7 @@ void dispatcher_main(rbd_server* s) {
     lk.lock();
     if (s->inflight.empty()) s->busy_since = Clock::now();
     s->inflight.push_back(g);
+    s->cv_inflight.notify_all();
     if (g->status != RBD_OK) {
       lk.unlock();
       finish_group(s, g, Clock::now());
@@ -364,6 +365,7 @@ void dispatcher_main(rbd_server* s) {
   }
   s->dispatcher_done = true;
   s->cv_work.notify_all();
+  s->cv_inflight.notify_all();
 }
 
 void completer_main(rbd_server* s) {
@@ -372,7 +374,7 @@ void completer_main(rbd_server* s) {
   for (;;) {
     if (s->inflight.empty()) {
       if (s->dispatcher_done) break;
-      s->cv_work.wait_for(lk, std::chrono::milliseconds(1));
+      s->cv_inflight.wait(lk);
       continue;
     }
     std::vector<Group*> look(s->inflight.begin(), s->inflight.end());
@@ -534,6 +536,7 @@ rbd_status rbd_server_destroy(rbd_server* s) {
     std::lock_guard<std::mutex> lk(s->mu);
     s->dispatcher_done = true;
     s->cv_work.notify_all();
+    s->cv_inflight.notify_all();
   }
   if (s->completer.joinable()) s->completer.join();
   (void)hipSetDevice(s->cfg.device);

@@ -103,3 +103,43 @@ def test_null_model_calls(rbd):
     L = rbd.lib()
     assert L.rbd_fwd_dyn(None, 1, 1, None, None, None, None, None) == 1
     assert b"model is NULL" in L.rbd_last_error()
+
+
+def _server_create(rbd, **kw):
+    cfg = dict(device=0, arena_bytes=1 << 24, n_streams=2, max_batch_requests=64, max_wait_us=0.0,
+               use_graphs=1, per_request=0)
+    cfg.update(kw)
+    from paper_2604_04310_amd import rbd as R
+    c = R.ServerConfigC(cfg["device"], cfg["arena_bytes"], cfg["n_streams"], cfg["max_batch_requests"],
+                              cfg["max_wait_us"], cfg["use_graphs"], cfg["per_request"])
+    h = C.c_void_p()
+    st = rbd.lib().rbd_server_create(C.byref(c), C.byref(h))
+    if st == 0:
+        rbd.lib().rbd_server_destroy(h)
+    return st, rbd.lib().rbd_last_error().decode()
+
+
+@pytest.mark.parametrize("kw,msg", [
+    (dict(n_streams=0), "n_streams"), (dict(n_streams=9), "n_streams"),
+    (dict(max_batch_requests=0), "max_batch_requests"), (dict(max_batch_requests=5000), "max_batch_requests"),
+    (dict(arena_bytes=1024), "arena_bytes"), (dict(max_wait_us=-1.0), "max_wait_us"),
+])
+def test_server_config_validation(rbd, kw, msg):
+    st, err = _server_create(rbd, **kw)
+    assert st == 1 and msg in err
+
+
+def test_server_needs_a_device(rbd):
+    st, err = _server_create(rbd)
+    if rbd.device_count() == 0:
+        assert st == 3, err
+    else:
+        assert st == 0, err
+
+
+def test_server_null_handles(rbd):
+    L = rbd.lib()
+    t = C.c_uint64()
+    assert L.rbd_server_submit(None, None, 0, 1, None, None, C.byref(t)) == 1
+    assert L.rbd_server_wait(None, 1, 0.0, None) == 1
+    assert L.rbd_server_destroy(None) == 0
