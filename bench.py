@@ -36,30 +36,61 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "fwd_dyn_humanoid30_b65536_traffic
 CSRC = os.path.join(ROOT, "paper_2604_04310_amd", "csrc")
 
 
+KERNEL_SOURCES = ["rbd_lane.hpp", "rbd_kernels.hpp", "rbd_kern_topo.hip", "rbd_shared.hpp", "rbd_topologies.hpp"]
+
+
 def kernel_source_hash() -> str:
+    """Hash of the device-code sources: the counter figures hold while it is unchanged."""
     h = hashlib.sha256()
-    for f in sorted(os.listdir(CSRC)):
+    for f in KERNEL_SOURCES:
         with open(os.path.join(CSRC, f), "rb") as fh:
             h.update(f.encode() + fh.read())
     return h.hexdigest()[:16]
 
 
-def read_traffic():
-    """HBM bytes per launch from the committed counter summary, or None when the
-    kernels changed after the counters were taken."""
+def read_counters():
+    """Figures from the committed counter summary (HBM bytes per launch, executed
+    FP32 FLOPs per evaluation), or {} when the kernels changed after the
+    counters were taken."""
     if not os.path.exists(TRAFFIC_FILE):
-        return None
+        return {}
     vals = {}
     for line in open(TRAFFIC_FILE):
         if "=" in line and not line.startswith("#"):
             k, v = line.split("=", 1)
             vals[k.strip()] = v.strip()
     if vals.get("source_hash") != kernel_source_hash():
-        return None
-    try:
-        return float(vals["hbm_bytes_per_launch"])
-    except (KeyError, ValueError):
-        return None
+        return {}
+    out = {}
+    for k in ("hbm_bytes_per_launch", "executed_fp32_flops_per_eval"):
+        try:
+            out[k] = float(vals[k])
+        except (KeyError, ValueError):
+            pass
+    return out
+
+
+def counters_driver():
+    """The run the counter summaries are taken from: five humanoid fwd_dyn
+    launches at batch 65536, then three plain 512 MiB device copies (the
+    calibration kernel for FETCH_SIZE / WRITE_SIZE)."""
+    import torch
+
+    import paper_2604_04310_amd as rbd
+    import workloads as W
+    desc = W.humanoid()
+    m = rbd.Model(desc, 0)
+    st = W.states(desc, BATCH, 103)
+    q, qd, tau = soa(st.q, torch), soa(st.qd, torch), soa(st.tau, torch)
+    out = torch.empty((desc.nv, BATCH), dtype=torch.float32, device="cuda")
+    for _ in range(5):
+        rbd.fwd_dyn(m, q, qd, tau, out=out)
+    a = torch.empty(128 << 20, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print("counters driver done", flush=True)
 
 
 def soa(x, torch):
@@ -192,7 +223,11 @@ def main():
     ap.add_argument("--serve-seconds", type=float, default=6.0)
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--counters", action="store_true", help="only run the counter-collection driver")
     args = ap.parse_args()
+    if args.counters:
+        counters_driver()
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU: the dynamics of independent robot instances need no "
               f"cross-GPU exchange, and this build runs on a single MI355X (asked for --gpus {args.gpus}).",
@@ -240,13 +275,19 @@ def main():
     flops = O.count_ops(desc, "fwd_dyn_ltl")
     per_eval = flops["flops"]
     achieved = per_eval * BATCH / (kernel_ms * 1e-3) / 1e12
-    traffic = read_traffic()
+    cnt = read_counters()
+    traffic = cnt.get("hbm_bytes_per_launch")
+    ceiling = rbd.fma_rate(256, 16)  # measured FMA issue ceiling at this launch shape
     roofline = {"bound": "alu", "achieved": round(achieved, 2), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": traffic,
                 "kernel": "k_fwd_dyn<humanoid30>", "kernel_ms": round(kernel_ms, 5),
                 "flops_per_eval": per_eval, "flops_source": "oracle count of the same algorithm (FP64 counting scalar)",
                 "peak_unpacked_fp32": round(PEAK_FP32_UNPACKED_TFLOPS, 1),
                 "frac_of_unpacked_peak": round(achieved / PEAK_FP32_UNPACKED_TFLOPS, 4),
+                "measured_fma_ceiling_at_this_launch_shape": round(ceiling, 1),
+                "executed_fp32_flops_per_eval": cnt.get("executed_fp32_flops_per_eval"),
+                "executed_tflops": (round(cnt["executed_fp32_flops_per_eval"] * BATCH / (kernel_ms * 1e-3) / 1e12, 2)
+                                    if "executed_fp32_flops_per_eval" in cnt else None),
                 "algorithmic_bytes_per_eval": 4 * (desc.nq + 3 * desc.nv),
                 "hbm_gbs_algorithmic": round(4 * (desc.nq + 3 * desc.nv) * BATCH / (kernel_ms * 1e-3) / 1e9, 1)}
 

@@ -137,6 +137,15 @@ rbd_status rbd_fwd_dyn_vjp(const rbd_model* model, int64_t batch, int64_t ld, co
                            const float* tau, const float* g_qdd, float* g_q, float* g_qd, float* g_tau,
                            hipStream_t stream);
 
+/* Diagnostic (not on the hot path): measured FP32 FMA rate in TFLOP/s of a
+ * kernel issuing ilp (1, 4 or 16) independent FMA chains per lane, launched as
+ * `blocks` blocks of 256 threads with no memory traffic. At 256 blocks (one
+ * wave per SIMD, the launch shape of the 35-DoF forward dynamics at batch
+ * 65536) it gives the issue ceiling that shape can reach; the published FP32
+ * peak assumes packed FP32, which this library does not use. Synchronous;
+ * allocates and frees a small buffer. */
+rbd_status rbd_diag_fma_rate(int device, int blocks, int ilp, double* tflops);
+
 const char* rbd_status_str(rbd_status s);
 const char* rbd_last_error(void); /* message of this thread's last failed call */
 int rbd_device_count(void);       /* number of visible GPUs (0 without one)    */

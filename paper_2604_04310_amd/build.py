@@ -15,6 +15,7 @@ LIB = os.path.join(PKG, "librbd.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 HOST_SOURCES = ["rbd_api.cpp", "rbd_dispatch.cpp", "rbd_serve.cpp"]
+DEVICE_SOURCES = ["rbd_diag.hip"]
 TOPO_SOURCE = "rbd_kern_topo.hip"
 
 # Packed FP32 (v_pk_*_f32) is switched off for every HIP translation unit.
@@ -57,6 +58,9 @@ def build(verbose: bool = False, jobs: int = 0, resource_usage: bool = False, in
             if resource_usage:
                 cmd.append("-Rpass-analysis=kernel-resource-usage")
             work.append((obj, cmd))
+    for src in DEVICE_SOURCES:
+        obj = os.path.join(out_dir, src + ".o")
+        work.append((obj, [HIPCC, *DEVICE, *COMMON, "-c", os.path.join(CSRC, src), "-o", obj]))
     for src in HOST_SOURCES:
         obj = os.path.join(out_dir, src + ".o")
         work.append((obj, [HIPCC, *COMMON, "-c", os.path.join(CSRC, src), "-o", obj]))

@@ -1,0 +1,73 @@
+// Diagnostic: the FP32 fused-multiply-add issue rate of the device at a given
+// launch shape, the measured ceiling beside the published FP32 peak.
+#include <hip/hip_runtime.h>
+
+#include "rbd_internal.hpp"
+
+namespace rbd {
+namespace {
+
+// ILP independent chains of 16 * iters FMAs per lane (no memory traffic in the
+// loop); one store per lane keeps the work alive.
+template <int ILP>
+__global__ __launch_bounds__(256) void k_fma_rate(float* __restrict__ out, int iters, float a, float b) {
+  float x[ILP];
+#pragma unroll
+  for (int k = 0; k < ILP; ++k) x[k] = threadIdx.x * 1e-3f + k;
+  for (int i = 0; i < iters; ++i) {
+#pragma unroll
+    for (int r = 0; r < 16; ++r)
+#pragma unroll
+      for (int k = 0; k < ILP; ++k) x[k] = __builtin_fmaf(x[k], a, b);
+  }
+  float s = 0.0f;
+#pragma unroll
+  for (int k = 0; k < ILP; ++k) s += x[k];
+  out[(int64_t)blockIdx.x * blockDim.x + threadIdx.x] = s;
+}
+
+template <int ILP>
+rbd_status time_rate(float* buf, int blocks, int fma_per_lane, hipStream_t s, hipEvent_t e0, hipEvent_t e1,
+                     float* ms) {
+  const int iters = fma_per_lane / (16 * ILP);
+  for (int w = 0; w < 3; ++w)
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_fma_rate<ILP>), dim3(blocks), dim3(256), 0, s, buf, iters, 0.999f, 0.001f);
+  const int n = 10;
+  if (hipEventRecord(e0, s) != hipSuccess) return fail(RBD_E_LAUNCH, "event record failed");
+  for (int w = 0; w < n; ++w)
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_fma_rate<ILP>), dim3(blocks), dim3(256), 0, s, buf, iters, 0.999f, 0.001f);
+  if (hipGetLastError() != hipSuccess) return fail(RBD_E_LAUNCH, "launch failed");
+  if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess)
+    return fail(RBD_E_LAUNCH, "event failed");
+  if (hipEventElapsedTime(ms, e0, e1) != hipSuccess) return fail(RBD_E_LAUNCH, "event timing failed");
+  *ms /= n;
+  return RBD_OK;
+}
+
+}  // namespace
+}  // namespace rbd
+
+extern "C" rbd_status rbd_diag_fma_rate(int device, int blocks, int ilp, double* tflops) {
+  using namespace rbd;
+  if (!tflops) return fail(RBD_E_INVAL, "tflops is NULL");
+  if (blocks < 1 || blocks > 65536) return fail(RBD_E_INVAL, "blocks = %d, expected 1..65536", blocks);
+  if (ilp != 1 && ilp != 4 && ilp != 16) return fail(RBD_E_INVAL, "ilp = %d, expected 1, 4 or 16", ilp);
+  if (device < 0 || device >= rbd_device_count()) return fail(RBD_E_NODEVICE, "device %d is not available", device);
+  if (hipSetDevice(device) != hipSuccess) return fail(RBD_E_NODEVICE, "cannot select device %d", device);
+  float* buf = nullptr;
+  if (hipMalloc(&buf, (size_t)blocks * 256 * sizeof(float)) != hipSuccess) return fail(RBD_E_NOMEM, "allocation failed");
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  (void)hipEventCreate(&e0);
+  (void)hipEventCreate(&e1);
+  const int fma_per_lane = 16384;
+  float ms = 0.0f;
+  rbd_status st = ilp == 1 ? time_rate<1>(buf, blocks, fma_per_lane, nullptr, e0, e1, &ms)
+                : ilp == 4 ? time_rate<4>(buf, blocks, fma_per_lane, nullptr, e0, e1, &ms)
+                           : time_rate<16>(buf, blocks, fma_per_lane, nullptr, e0, e1, &ms);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)hipFree(buf);
+  if (st != RBD_OK) return st;
+  *tflops = 2.0 * fma_per_lane * (double)blocks * 256 / (ms * 1e-3) / 1e12;
+  return RBD_OK;
+}

@@ -58,12 +58,13 @@ int find_topology(bool floating, int n, const int32_t* parent) {
   return -1;
 }
 
-bool tables_in_lds() {
-  static const bool lds = [] {
-    const char* e = std::getenv("RBD_TABLES");
-    return e && std::strcmp(e, "lds") == 0;
+bool preload_inputs(bool topology_default) {
+  static const int env = [] {
+    const char* e = std::getenv("RBD_PRELOAD");
+    if (!e) return -1;
+    return std::strcmp(e, "0") == 0 ? 0 : 1;
   }();
-  return lds;
+  return env < 0 ? topology_default : env == 1;
 }
 
 static const LaunchTable* table_of(const rbd_model* m) {

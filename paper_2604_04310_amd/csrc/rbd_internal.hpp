@@ -24,10 +24,10 @@ namespace rbd {
 // FP32 device tables of a validated tree (layout in rbd_lane.hpp)
 std::vector<float> make_tables(const rbd_tree_desc* d);
 
-// Model constants read through the scalar cache (default) or staged in LDS
-// per block (environment variable RBD_TABLES=lds; slower on gfx950 for the
-// large trees, whose extra vector registers then spill).
-bool tables_in_lds();
+// Whether forward dynamics issues all input loads at kernel entry: the
+// topology's compiled default, unless the environment variable RBD_PRELOAD
+// (0 or 1) overrides it for measurement.
+bool preload_inputs(bool topology_default);
 
 // error reporting (thread-local message)
 rbd_status fail(rbd_status s, const char* fmt, ...);

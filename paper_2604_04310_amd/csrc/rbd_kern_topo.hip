@@ -21,6 +21,6 @@ static_assert(TP::depth_first(), "topology is not depth-first");
 
 #define RBD_NAME RBD_CAT(RBD_CAT(RBD_CAT(launch_table_, RBD_TOPO), _p), RBD_PART)
 extern const LaunchTable RBD_NAME;
-const LaunchTable RBD_NAME = Launch<TP>::part(RBD_PART);
+const LaunchTable RBD_NAME = Launch<TP>::part<RBD_PART>();
 
 }  // namespace rbd

@@ -14,16 +14,6 @@ constexpr int kBlock = 256;
 
 RBD_DI uint32_t lane_id() { return blockIdx.x * blockDim.x + threadIdx.x; }
 
-// Stages the model tables in LDS; every thread of the block must call it
-// (before any early exit), since it ends with a barrier.
-template <class TP>
-RBD_DI const float* stage_tables(const float* __restrict__ tab, float* lds) {
-  constexpr int n = TP::N * kBodyStride + 4;
-  for (int i = threadIdx.x; i < n; i += blockDim.x) lds[i] = tab[i];
-  __syncthreads();
-  return lds;
-}
-
 template <class TP>
 __global__ __launch_bounds__(kBlock) void k_fk(const float* __restrict__ tab, int64_t batch, int64_t ld,
                                                const float* __restrict__ q, float* __restrict__ T) {
@@ -69,19 +59,34 @@ struct SinkOne {
   RBD_DI void operator()(int, int k, float v) const { x(k, v); }
 };
 
-// LDS = true reads the model constants from LDS, false through the scalar cache.
-template <class TP, bool LDS>
+// Registers of one lane holding a preloaded input vector.
+struct RegView {
+  const float* x;
+  RBD_DI float operator()(int k) const { return x[k]; }
+};
+
+// PRE = true issues every input load of the lane at entry (106 for the
+// humanoid), so their latency overlaps the first bodies' arithmetic instead of
+// stalling the single wave of each SIMD at every body.
+template <class TP, bool PRE>
 __global__ __launch_bounds__(kBlock) void k_fwd_dyn(const float* __restrict__ tab, int64_t batch, int64_t ld,
                                                     const float* __restrict__ q, const float* __restrict__ qd,
                                                     const float* __restrict__ tau, float* __restrict__ qdd) {
-  const float* t = tab;
-  if constexpr (LDS) {
-    __shared__ float lds[TP::N * kBodyStride + 4];
-    t = stage_tables<TP>(tab, lds);
-  }
   const uint32_t b = lane_id();
   if (b >= batch) return;
-  fwd_dyn_lane<TP, 1>(t, In{q, ld, b}, In{qd, ld, b}, RhsOne<In>{In{tau, ld, b}}, SinkOne<Out>{Out{qdd, ld, b}});
+  if constexpr (PRE) {
+    constexpr int NQ = TP::NQ, NV = TP::NV;
+    float qv[NQ], qdv[NV], tv[NV];
+    const In qi{q, ld, b}, qdi{qd, ld, b}, ti{tau, ld, b};
+    sfor<0, NQ>([&](auto K_) __attribute__((always_inline)) { qv[decltype(K_)::value] = qi(decltype(K_)::value); });
+    sfor<0, NV>([&](auto K_) __attribute__((always_inline)) {
+      qdv[decltype(K_)::value] = qdi(decltype(K_)::value);
+      tv[decltype(K_)::value] = ti(decltype(K_)::value);
+    });
+    fwd_dyn_lane<TP, 1>(tab, RegView{qv}, RegView{qdv}, RhsOne<RegView>{RegView{tv}}, SinkOne<Out>{Out{qdd, ld, b}});
+  } else {
+    fwd_dyn_lane<TP, 1>(tab, In{q, ld, b}, In{qd, ld, b}, RhsOne<In>{In{tau, ld, b}}, SinkOne<Out>{Out{qdd, ld, b}});
+  }
 }
 
 // ---- fwd_dyn adjoint: solve M [qdd, lam] = [tau - h, gbar] with one factor,
@@ -97,10 +102,6 @@ struct SinkRegs {
   RBD_DI void operator()(int r, int k, float v) const {
     if (r == 0) qdd[k] = v; else lam[k] = v;
   }
-};
-struct RegView {
-  const float* x;
-  RBD_DI float operator()(int k) const { return x[k]; }
 };
 // An output that may be absent (null base).
 template <class Y>
@@ -265,7 +266,10 @@ struct Launch {
   }
   static rbd_status fwd_dyn(const float* tab, int64_t batch, int64_t ld, const float* q, const float* qd,
                             const float* tau, float* qdd, hipStream_t s) {
-    if (tables_in_lds())
+    // Large trees run one wave per SIMD and gain from issuing all input loads
+    // up front; small ones keep their occupancy instead (measured).
+    constexpr bool kPre = TP::NV > 16;
+    if (preload_inputs(kPre))
       hipLaunchKernelGGL(HIP_KERNEL_NAME(k_fwd_dyn<TP, true>), dim3(grid_for(batch)), dim3(kBlock), 0, s, tab,
                          batch, ld, q, qd, tau, qdd);
     else
@@ -301,15 +305,17 @@ struct Launch {
   }
   // Part 1: kinematics, inverse dynamics, mass matrix. Part 2: forward dynamics
   // and the packed forward-dynamics and inverse-dynamics launches. Part 3: the
-  // adjoint and its packed launch. Each part is its own translation unit.
-  static LaunchTable part(int k) {
+  // adjoint and its packed launch. Each part is its own translation unit and
+  // instantiates only its own kernels.
+  template <int K>
+  static LaunchTable part() {
     LaunchTable t{};
-    if (k == 1) {
+    if constexpr (K == 1) {
       t.fk = &Launch::fk;
       t.jacobian = &Launch::jacobian;
       t.rnea = &Launch::rnea;
       t.crba = &Launch::crba;
-    } else if (k == 2) {
+    } else if constexpr (K == 2) {
       t.fwd_dyn = &Launch::fwd_dyn;
       t.packed = &Launch::packed;
     } else {

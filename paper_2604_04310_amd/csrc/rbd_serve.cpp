@@ -220,6 +220,24 @@ int grid_class(int n_tiles) {
   return kGridClasses[sizeof(kGridClasses) / sizeof(int) - 1];
 }
 
+// Captures the packed launch of (model, op) with `grid` blocks on `st` as a graph.
+rbd_status capture_packed(const rbd_model* m, int op, const void* d_table, int grid, hipStream_t st,
+                          hipGraphExec_t* out) {
+  hipGraph_t graph = nullptr;
+  if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess)
+    return fail(RBD_E_LAUNCH, "server: stream capture failed");
+  const rbd_status rs = launch_packed(m, op, d_table, grid, st);
+  const hipError_t ce = hipStreamEndCapture(st, &graph);
+  if (rs != RBD_OK || ce != hipSuccess) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return rs != RBD_OK ? rs : fail(RBD_E_LAUNCH, "server: stream capture failed");
+  }
+  const hipError_t ie = hipGraphInstantiate(out, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (ie != hipSuccess) return fail(RBD_E_LAUNCH, "server: graph instantiation failed");
+  return RBD_OK;
+}
+
 // Stage, launch and queue the copy-back of one group (dispatcher thread, no lock).
 rbd_status launch_group(rbd_server* s, Group* g) {
   Slot& sl = s->slots[g->slot];
@@ -265,19 +283,22 @@ rbd_status launch_group(rbd_server* s, Group* g) {
     auto key = std::make_tuple(g->model, g->op, grid);
     auto it = sl.graphs.find(key);
     if (it == sl.graphs.end()) {
-      hipGraph_t graph = nullptr;
+      // first request of this model: capture its graphs for every slot,
+      // operation and grid size now, so that none is captured mid-stream later
+      // (a capture costs about a millisecond of dispatcher time)
+      for (auto& other : s->slots)
+        for (int op = RBD_OP_FWD_DYN; op <= RBD_OP_FWD_DYN_VJP; ++op)
+          for (int gc : kGridClasses) {
+            if (&other == &sl && op == g->op && gc == grid) continue;
+            auto k2 = std::make_tuple(g->model, op, gc);
+            if (other.graphs.count(k2)) continue;
+            hipGraphExec_t e2 = nullptr;
+            if (capture_packed(g->model, op, other.d_table, gc, other.stream, &e2) == RBD_OK)
+              other.graphs.emplace(k2, e2);
+          }
       hipGraphExec_t exec = nullptr;
-      if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess)
-        return fail(RBD_E_LAUNCH, "server: stream capture failed");
-      rs = launch_packed(g->model, g->op, sl.d_table, grid, st);
-      const hipError_t ce = hipStreamEndCapture(st, &graph);
-      if (rs != RBD_OK || ce != hipSuccess) {
-        if (graph) (void)hipGraphDestroy(graph);
-        return rs != RBD_OK ? rs : fail(RBD_E_LAUNCH, "server: stream capture failed");
-      }
-      const hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-      (void)hipGraphDestroy(graph);
-      if (ie != hipSuccess) return fail(RBD_E_LAUNCH, "server: graph instantiation failed");
+      rs = capture_packed(g->model, g->op, sl.d_table, grid, st, &exec);
+      if (rs != RBD_OK) return rs;
       it = sl.graphs.emplace(key, exec).first;
     }
     if (hipGraphLaunch(it->second, st) != hipSuccess) return fail(RBD_E_LAUNCH, "server: graph launch failed");

@@ -29,7 +29,7 @@ OP_FWD_DYN, OP_RNEA, OP_FWD_DYN_VJP = 0, 1, 2
 # Every symbol include/rbd.h declares.
 EXPORTS = ["rbd_model_create", "rbd_model_destroy", "rbd_model_dims", "rbd_model_topology", "rbd_fk",
            "rbd_jacobian", "rbd_rnea", "rbd_crba", "rbd_fwd_dyn", "rbd_fwd_dyn_vjp", "rbd_status_str",
-           "rbd_last_error", "rbd_device_count", "rbd_server_create", "rbd_server_submit", "rbd_server_wait",
+           "rbd_last_error", "rbd_device_count", "rbd_diag_fma_rate", "rbd_server_create", "rbd_server_submit", "rbd_server_wait",
            "rbd_server_get_stats", "rbd_server_reset_stats", "rbd_server_destroy"]
 
 
@@ -92,6 +92,7 @@ def lib():
         L.rbd_last_error.argtypes = []
         L.rbd_last_error.restype = C.c_char_p
         L.rbd_device_count.argtypes = []
+        L.rbd_diag_fma_rate.argtypes = [C.c_int, C.c_int, C.c_int, P(C.c_double)]
         L.rbd_server_create.argtypes = [P(ServerConfigC), P(vp)]
         L.rbd_server_submit.argtypes = [vp, vp, C.c_int, i64, P(vp), P(vp), P(C.c_uint64)]
         L.rbd_server_wait.argtypes = [vp, C.c_uint64, C.c_double, P(C.c_int)]
@@ -109,6 +110,13 @@ def check(status: int) -> None:
 
 def device_count() -> int:
     return int(lib().rbd_device_count())
+
+
+def fma_rate(blocks: int = 256, ilp: int = 16, device: int = 0) -> float:
+    """Measured FP32 FMA TFLOP/s at a launch of `blocks` x 256 threads (diagnostic)."""
+    out = C.c_double()
+    check(lib().rbd_diag_fma_rate(int(device), int(blocks), int(ilp), C.byref(out)))
+    return out.value
 
 
 def desc_struct(desc) -> TreeDescC:
