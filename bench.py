@@ -294,6 +294,7 @@ def main():
     # the other hot-path kernels at their benchmark shapes
     ops = {}
     n_t = max(5, args.steps // 10)
+    ops["aba_humanoid30_b65536_us"] = 1e3 * time_launches(lambda: rbd.aba(model, q, qd, tau), n_t, torch)
     ops["rnea_bias_humanoid30_b65536_us"] = 1e3 * time_launches(lambda: rbd.rnea(model, q, qd), n_t, torch)
     ops["crba_humanoid30_b65536_us"] = 1e3 * time_launches(lambda: rbd.crba(model, q), n_t, torch)
     ops["fk_humanoid30_b65536_us"] = 1e3 * time_launches(lambda: rbd.fk(model, q), n_t, torch)
@@ -309,6 +310,7 @@ def main():
     cs = W.states(chain, 1 << 20, 102)
     cq, cqd, ctau = soa(cs.q, torch), soa(cs.qd, torch), soa(cs.tau, torch)
     ops["fwd_dyn_chain7_b1048576_us"] = 1e3 * time_launches(lambda: rbd.fwd_dyn(cm, cq, cqd, ctau), n_t, torch)
+    ops["aba_chain7_b1048576_us"] = 1e3 * time_launches(lambda: rbd.aba(cm, cq, cqd, ctau), n_t, torch)
     ops["rnea_bias_chain7_b1048576_us"] = 1e3 * time_launches(lambda: rbd.rnea(cm, cq, cqd), n_t, torch)
     Bc = 1 << 18
     cg = soa(W.cotangent(chain.nv, Bc, 3), torch)

@@ -13,6 +13,9 @@
  *   rbd_crba         joint-space mass matrix M(q) (Alg. 2)
  *   rbd_fwd_dyn      forward dynamics qdd = M^-1 (tau - h), Eq. (2), by a
  *                    per-instance Cholesky-type solve (Sec. V, footnote)
+ *   rbd_aba          the same forward dynamics by the articulated-body
+ *                    algorithm, O(n), no mass matrix (Sec. III, named there as
+ *                    a Featherstone algorithm; Sec. VI, future work)
  *   rbd_fwd_dyn_vjp  reverse-mode derivative of rbd_fwd_dyn (Sec. I, AD)
  *   rbd_server_*     continuous-batching service for the above (host API)
  *
@@ -128,6 +131,14 @@ rbd_status rbd_crba(const rbd_model* model, int64_t batch, int64_t ld, const flo
  * factorisation never leave the lane. q: [nq][ld]; qd, tau, qdd: [nv][ld]. */
 rbd_status rbd_fwd_dyn(const rbd_model* model, int64_t batch, int64_t ld, const float* q, const float* qd,
                        const float* tau, float* qdd, hipStream_t stream);
+
+/* Forward dynamics, Eq. (2) with f = 0, by the articulated-body algorithm:
+ * the same qdd as rbd_fwd_dyn (up to rounding), computed in three O(n) sweeps
+ * over the tree (velocities; articulated inertias and bias forces, leaves to
+ * root; accelerations) without forming M. Same arguments and layout as
+ * rbd_fwd_dyn. A non-positive articulated pivot yields NaN in that instance. */
+rbd_status rbd_aba(const rbd_model* model, int64_t batch, int64_t ld, const float* q, const float* qd,
+                   const float* tau, float* qdd, hipStream_t stream);
 
 /* Vector-Jacobian product of rbd_fwd_dyn for the cotangent g_qdd [nv][ld]:
  * g_q = g_qdd^T dqdd/dq [nq][ld] (raw quaternion components included),

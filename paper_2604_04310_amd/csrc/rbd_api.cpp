@@ -325,6 +325,15 @@ rbd_status rbd_fwd_dyn(const rbd_model* m, int64_t batch, int64_t ld, const floa
   return launch_fwd_dyn(m, batch, ld, q, qd, tau, qdd, s);
 }
 
+rbd_status rbd_aba(const rbd_model* m, int64_t batch, int64_t ld, const float* q, const float* qd, const float* tau,
+                   float* qdd, hipStream_t s) {
+  rbd_status st = check_batch(m, batch, ld, "rbd_aba");
+  if (st != RBD_OK) return st;
+  if (batch > 0 && (!q || !qd || !tau || !qdd)) return fail(RBD_E_INVAL, "rbd_aba: NULL array");
+  if ((st = use_device(m->device)) != RBD_OK) return st;
+  return launch_aba(m, batch, ld, q, qd, tau, qdd, s);
+}
+
 rbd_status rbd_fwd_dyn_vjp(const rbd_model* m, int64_t batch, int64_t ld, const float* q, const float* qd,
                            const float* tau, const float* g_qdd, float* g_q, float* g_qd, float* g_tau,
                            hipStream_t s) {

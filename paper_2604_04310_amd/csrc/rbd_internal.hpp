@@ -53,6 +53,8 @@ rbd_status launch_rnea(const rbd_model* m, int64_t batch, int64_t ld, const floa
 rbd_status launch_crba(const rbd_model* m, int64_t batch, int64_t ld, const float* q, float* M, hipStream_t s);
 rbd_status launch_fwd_dyn(const rbd_model* m, int64_t batch, int64_t ld, const float* q, const float* qd,
                           const float* tau, float* qdd, hipStream_t s);
+rbd_status launch_aba(const rbd_model* m, int64_t batch, int64_t ld, const float* q, const float* qd,
+                      const float* tau, float* qdd, hipStream_t s);
 rbd_status launch_fwd_dyn_vjp(const rbd_model* m, int64_t batch, int64_t ld, const float* q, const float* qd,
                               const float* tau, const float* gqdd, float* gq, float* gqd, float* gtau,
                               hipStream_t s);
@@ -70,6 +72,8 @@ struct LaunchTable {
                         const float* tau, float* qdd, hipStream_t s);
   rbd_status (*vjp)(const float* tab, int64_t batch, int64_t ld, const float* q, const float* qd, const float* tau,
                     const float* gqdd, float* gq, float* gqd, float* gtau, hipStream_t s);
+  rbd_status (*aba)(const float* tab, int64_t batch, int64_t ld, const float* q, const float* qd, const float* tau,
+                    float* qdd, hipStream_t s);
   rbd_status (*packed)(int op, const float* tab, const void* table, int grid, hipStream_t s);
   rbd_status (*packed_vjp)(int op, const float* tab, const void* table, int grid, hipStream_t s);
 };

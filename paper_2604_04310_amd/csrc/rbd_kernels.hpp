@@ -89,6 +89,28 @@ __global__ __launch_bounds__(kBlock) void k_fwd_dyn(const float* __restrict__ ta
   }
 }
 
+// Forward dynamics by the articulated-body algorithm; PRE as for k_fwd_dyn.
+template <class TP, bool PRE>
+__global__ __launch_bounds__(kBlock) void k_aba(const float* __restrict__ tab, int64_t batch, int64_t ld,
+                                                const float* __restrict__ q, const float* __restrict__ qd,
+                                                const float* __restrict__ tau, float* __restrict__ qdd) {
+  const uint32_t b = lane_id();
+  if (b >= batch) return;
+  if constexpr (PRE) {
+    constexpr int NQ = TP::NQ, NV = TP::NV;
+    float qv[NQ], qdv[NV], tv[NV];
+    const In qi{q, ld, b}, qdi{qd, ld, b}, ti{tau, ld, b};
+    sfor<0, NQ>([&](auto K_) __attribute__((always_inline)) { qv[decltype(K_)::value] = qi(decltype(K_)::value); });
+    sfor<0, NV>([&](auto K_) __attribute__((always_inline)) {
+      qdv[decltype(K_)::value] = qdi(decltype(K_)::value);
+      tv[decltype(K_)::value] = ti(decltype(K_)::value);
+    });
+    aba_lane<TP>(tab, RegView{qv}, RegView{qdv}, RegView{tv}, Out{qdd, ld, b});
+  } else {
+    aba_lane<TP>(tab, In{q, ld, b}, In{qd, ld, b}, In{tau, ld, b}, Out{qdd, ld, b});
+  }
+}
+
 // ---- fwd_dyn adjoint: solve M [qdd, lam] = [tau - h, gbar] with one factor,
 // write g_tau = lam, then run the inverse-dynamics adjoint at (q, qd, qdd).
 template <class X>
@@ -277,6 +299,17 @@ struct Launch {
                          batch, ld, q, qd, tau, qdd);
     return check_launch("rbd_fwd_dyn");
   }
+  static rbd_status aba(const float* tab, int64_t batch, int64_t ld, const float* q, const float* qd,
+                        const float* tau, float* qdd, hipStream_t s) {
+    constexpr bool kPre = TP::NV > 16;
+    if (preload_inputs(kPre))
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_aba<TP, true>), dim3(grid_for(batch)), dim3(kBlock), 0, s, tab, batch,
+                         ld, q, qd, tau, qdd);
+    else
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_aba<TP, false>), dim3(grid_for(batch)), dim3(kBlock), 0, s, tab, batch,
+                         ld, q, qd, tau, qdd);
+    return check_launch("rbd_aba");
+  }
   static rbd_status vjp(const float* tab, int64_t batch, int64_t ld, const float* q, const float* qd,
                         const float* tau, const float* gqdd, float* gq, float* gqd, float* gtau, hipStream_t s) {
     if (gqd && gtau)
@@ -305,8 +338,9 @@ struct Launch {
   }
   // Part 1: kinematics, inverse dynamics, mass matrix. Part 2: forward dynamics
   // and the packed forward-dynamics and inverse-dynamics launches. Part 3: the
-  // adjoint and its packed launch. Each part is its own translation unit and
-  // instantiates only its own kernels.
+  // adjoint and its packed launch. Part 4: the articulated-body algorithm.
+  // Each part is its own translation unit and instantiates only its own
+  // kernels.
   template <int K>
   static LaunchTable part() {
     LaunchTable t{};
@@ -318,9 +352,11 @@ struct Launch {
     } else if constexpr (K == 2) {
       t.fwd_dyn = &Launch::fwd_dyn;
       t.packed = &Launch::packed;
-    } else {
+    } else if constexpr (K == 3) {
       t.vjp = &Launch::vjp;
       t.packed_vjp = &Launch::packed_vjp;
+    } else {
+      t.aba = &Launch::aba;
     }
     return t;
   }

@@ -869,4 +869,320 @@ RBD_DI void id_adjoint_lane(const float* __restrict__ t, const QI& q, const QDI&
   });
 }
 
+// =================================================================== ABA
+// Articulated-body inertia: symmetric 6x6 [[A, B], [B^T, C]] acting on a
+// motion [w; v] as n = A w + B v, f = B^T w + C v. A and C are symmetric (6
+// numbers each), B is general (row-major).
+struct AInr {
+  float a00, a11, a22, a01, a02, a12;
+  float b[9];
+  float c00, c11, c22, c01, c02, c12;
+};
+// A rigid body: A = Ibar, B = [h]x, C = m 1.
+RBD_DI AInr ainr_rigid(const Inr& I) {
+  return {I.xx,  I.yy, I.zz,  I.xy, I.xz, I.yz, {0.0f, -I.h.z, I.h.y, I.h.z, 0.0f, -I.h.x, -I.h.y, I.h.x, 0.0f},
+          I.m,   I.m,  I.m,   0.0f, 0.0f, 0.0f};
+}
+RBD_DI void ainr_add_rigid(AInr& A, const Inr& I) {
+  A.a00 = A.a00 + I.xx; A.a11 = A.a11 + I.yy; A.a22 = A.a22 + I.zz;
+  A.a01 = A.a01 + I.xy; A.a02 = A.a02 + I.xz; A.a12 = A.a12 + I.yz;
+  A.b[1] = A.b[1] - I.h.z; A.b[2] = A.b[2] + I.h.y; A.b[3] = A.b[3] + I.h.z;
+  A.b[5] = A.b[5] - I.h.x; A.b[6] = A.b[6] - I.h.y; A.b[7] = A.b[7] + I.h.x;
+  A.c00 = A.c00 + I.m; A.c11 = A.c11 + I.m; A.c22 = A.c22 + I.m;
+}
+
+// Articulated inertia of a revolute body after its joint is projected out,
+// Ia = IA - U U^T / D with U = IA S. For S = [e_z; 0] its angular-z row and
+// column vanish, so only A's upper-left 2x2 block, the first two rows of B
+// and all of C remain.
+struct AInrP {
+  float a00, a11, a01;
+  float b[6];
+  float c00, c11, c22, c01, c02, c12;
+};
+
+// acc (= or +=) X^T Ia X for the child frame at r with axes R (parent
+// coordinates). X = rot(R^T) * [[1, 0], [-[r]x, 1]]: the rotation acts
+// first, blockwise R M R^T, then the shift to the parent origin gives
+//   A_p = A' - (B' [r]x) - (B' [r]x)^T - [r]x C' [r]x,  B_p = B' + [r]x C',
+//   C_p = C'.
+template <bool INIT>
+RBD_DI void xainr_acc(const M3& R, V3 r, const AInrP& I, AInr& acc) {
+  const float* Ra = R.a;
+  // A' = P A2 P^T with P = the first two columns of R
+  float wa[3][2];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    wa[i][0] = __builtin_fmaf(Ra[3 * i], I.a00, Ra[3 * i + 1] * I.a01);
+    wa[i][1] = __builtin_fmaf(Ra[3 * i], I.a01, Ra[3 * i + 1] * I.a11);
+  }
+  float Ap[3][3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = i; j < 3; ++j) Ap[i][j] = __builtin_fmaf(wa[i][0], Ra[3 * j], wa[i][1] * Ra[3 * j + 1]);
+  // B' = (P B2) R^T, B2 = the first two rows of B
+  float wb[3][3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int k = 0; k < 3; ++k) wb[i][k] = __builtin_fmaf(Ra[3 * i], I.b[k], Ra[3 * i + 1] * I.b[3 + k]);
+  float Bp[3][3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+      Bp[i][j] = __builtin_fmaf(wb[i][0], Ra[3 * j], __builtin_fmaf(wb[i][1], Ra[3 * j + 1], wb[i][2] * Ra[3 * j + 2]));
+  // C' = R C R^T
+  const float Cm[3][3] = {{I.c00, I.c01, I.c02}, {I.c01, I.c11, I.c12}, {I.c02, I.c12, I.c22}};
+  float wc[3][3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+      wc[i][k] = __builtin_fmaf(Ra[3 * i], Cm[0][k], __builtin_fmaf(Ra[3 * i + 1], Cm[1][k], Ra[3 * i + 2] * Cm[2][k]));
+  float Cp[3][3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = i; j < 3; ++j)
+      Cp[i][j] = __builtin_fmaf(wc[i][0], Ra[3 * j], __builtin_fmaf(wc[i][1], Ra[3 * j + 1], wc[i][2] * Ra[3 * j + 2]));
+  Cp[1][0] = Cp[0][1]; Cp[2][0] = Cp[0][2]; Cp[2][1] = Cp[1][2];
+  // [r]x C' (row i of [r]x times C')
+  float rc[3][3];
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    rc[0][j] = __builtin_fmaf(r.y, Cp[2][j], -r.z * Cp[1][j]);
+    rc[1][j] = __builtin_fmaf(r.z, Cp[0][j], -r.x * Cp[2][j]);
+    rc[2][j] = __builtin_fmaf(r.x, Cp[1][j], -r.y * Cp[0][j]);
+  }
+  // T = B' [r]x and Q = ([r]x C') [r]x (symmetric), column j of [r]x:
+  // (0, rz, -ry), (-rz, 0, rx), (ry, -rx, 0)
+  auto times_rx = [&](const float (&M)[3][3], int i, int j) __attribute__((always_inline)) {
+    return j == 0 ? __builtin_fmaf(M[i][1], r.z, -M[i][2] * r.y)
+                  : (j == 1 ? __builtin_fmaf(M[i][2], r.x, -M[i][0] * r.z) : __builtin_fmaf(M[i][0], r.y, -M[i][1] * r.x));
+  };
+  float T[3][3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) T[i][j] = times_rx(Bp, i, j);
+  float An[6], Bn[9], Cn[6];
+  const int ii[6] = {0, 1, 2, 0, 0, 1}, jj[6] = {0, 1, 2, 1, 2, 2};
+#pragma unroll
+  for (int e = 0; e < 6; ++e) {
+    const int i = ii[e], j = jj[e];
+    An[e] = Ap[i][j] - T[i][j] - T[j][i] - times_rx(rc, i, j);
+    Cn[e] = Cp[i][j];
+  }
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) Bn[3 * i + j] = Bp[i][j] + rc[i][j];
+  if constexpr (INIT) {
+    acc.a00 = An[0]; acc.a11 = An[1]; acc.a22 = An[2]; acc.a01 = An[3]; acc.a02 = An[4]; acc.a12 = An[5];
+#pragma unroll
+    for (int e = 0; e < 9; ++e) acc.b[e] = Bn[e];
+    acc.c00 = Cn[0]; acc.c11 = Cn[1]; acc.c22 = Cn[2]; acc.c01 = Cn[3]; acc.c02 = Cn[4]; acc.c12 = Cn[5];
+  } else {
+    acc.a00 = acc.a00 + An[0]; acc.a11 = acc.a11 + An[1]; acc.a22 = acc.a22 + An[2];
+    acc.a01 = acc.a01 + An[3]; acc.a02 = acc.a02 + An[4]; acc.a12 = acc.a12 + An[5];
+#pragma unroll
+    for (int e = 0; e < 9; ++e) acc.b[e] = acc.b[e] + Bn[e];
+    acc.c00 = acc.c00 + Cn[0]; acc.c11 = acc.c11 + Cn[1]; acc.c22 = acc.c22 + Cn[2];
+    acc.c01 = acc.c01 + Cn[3]; acc.c02 = acc.c02 + Cn[4]; acc.c12 = acc.c12 + Cn[5];
+  }
+}
+
+// Solves IA x = b for a symmetric positive definite 6x6 articulated inertia
+// (unpivoted Cholesky), motion x from force b.
+RBD_DI Mot ainr_solve(const AInr& I, const Frc& rhs) {
+  float M[6][6] = {{I.a00, I.a01, I.a02, I.b[0], I.b[1], I.b[2]},
+                   {I.a01, I.a11, I.a12, I.b[3], I.b[4], I.b[5]},
+                   {I.a02, I.a12, I.a22, I.b[6], I.b[7], I.b[8]},
+                   {I.b[0], I.b[3], I.b[6], I.c00, I.c01, I.c02},
+                   {I.b[1], I.b[4], I.b[7], I.c01, I.c11, I.c12},
+                   {I.b[2], I.b[5], I.b[8], I.c02, I.c12, I.c22}};
+  const float b[6] = {rhs.n.x, rhs.n.y, rhs.n.z, rhs.f.x, rhs.f.y, rhs.f.z};
+  float L[6][6], inv[6], y[6], x[6];
+#pragma unroll
+  for (int j = 0; j < 6; ++j) {
+    float d = M[j][j];
+#pragma unroll
+    for (int k = 0; k < j; ++k) d = __builtin_fmaf(-L[j][k], L[j][k], d);
+    inv[j] = frsq(d);
+#pragma unroll
+    for (int i = j + 1; i < 6; ++i) {
+      float s = M[i][j];
+#pragma unroll
+      for (int k = 0; k < j; ++k) s = __builtin_fmaf(-L[i][k], L[j][k], s);
+      L[i][j] = s * inv[j];
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < 6; ++j) {
+    float s = b[j];
+#pragma unroll
+    for (int k = 0; k < j; ++k) s = __builtin_fmaf(-L[j][k], y[k], s);
+    y[j] = s * inv[j];
+  }
+#pragma unroll
+  for (int j = 5; j >= 0; --j) {
+    float s = y[j];
+#pragma unroll
+    for (int k = j + 1; k < 6; ++k) s = __builtin_fmaf(-L[k][j], x[k], s);
+    x[j] = s * inv[j];
+  }
+  return {{x[0], x[1], x[2]}, {x[3], x[4], x[5]}};
+}
+
+// Forward dynamics by the articulated-body algorithm: qdd = FD(q, qd, tau),
+// the O(n) alternative to forming and factoring M. One depth-first sweep does
+// the velocity pass on the way down and, as each subtree closes, the
+// articulated-inertia pass (leaves to root):
+//   IA_i = I_i + sum X^T Ia_c X,  pA_i = v_i x* I_i v_i + sum X^T pa_c,
+//   U = IA_i S, D = S^T U, u = tau_i - S^T pA_i,
+//   Ia_i = IA_i - U U^T / D,  pa_i = pA_i + Ia_i c_i + U u / D,
+// with c_i = v_i x S qd_i. Only U/D and u/D outlive a body's subtree; the
+// acceleration pass (root to leaves) rebuilds X and v from q and qd, which is
+// cheaper than holding them for every body:
+//   a' = X a_parent + c_i,  qdd_i = u/D - (U/D)^T a',  a_i = a' + S qdd_i.
+// Gravity is the fictitious base acceleration -g; a free base solves its 6x6
+// articulated inertia directly. A parent's accumulators start at its first
+// child's contribution, so a chain body holds none while its subtree runs.
+template <class TP, class QI, class QDI, class TI, class QDDO>
+RBD_DI void aba_lane(const float* __restrict__ t, const QI& q, const QDI& qd, const TI& tau, const QDDO& qdd) {
+  constexpr int N = TP::N;
+  float cq[N], sq[N];
+  Mot v[N];
+  Frc Ud[N];
+  float ud[N];
+  AInr acc[N];
+  Frc accp[N];
+  Mot a0;  // free base: total spatial acceleration (gravity included)
+  const V3 g = load_g<TP>(t);
+  const V3 mg = {-g.x, -g.y, -g.z};
+
+  auto close = [&](auto J_) __attribute__((always_inline)) {
+    constexpr int J = decltype(J_)::value;
+    constexpr int P = TP::parent(J);
+    constexpr bool kKids = TP::last(J) > J;
+    const Inr Ib = load_inr<J>(t);
+    const Frc bias = crf(v[J], imul(Ib, v[J]));
+    AInr IA;
+    Frc pA;
+    if constexpr (kKids) {
+      IA = acc[J];
+      ainr_add_rigid(IA, Ib);
+      pA = accp[J] + bias;
+    } else {
+      IA = ainr_rigid(Ib);
+      pA = bias;
+    }
+    if constexpr (TP::free_body(J)) {
+      const Frc b = {{tau(3) - pA.n.x, tau(4) - pA.n.y, tau(5) - pA.n.z}, {tau(0) - pA.f.x, tau(1) - pA.f.y, tau(2) - pA.f.z}};
+      a0 = ainr_solve(IA, b);
+    } else {
+      const Frc U = {{IA.a02, IA.a12, IA.a22}, {IA.b[6], IA.b[7], IA.b[8]}};
+      const float invD = frcp(IA.a22);
+      const float u = tau(cidx<TP::vofs(J)>) - pA.n.z;
+      const Frc W = {invD * U.n, invD * U.f};
+      Ud[J] = W;
+      ud[J] = u * invD;
+      if constexpr (P >= 0) {
+        AInrP Ia;
+        Ia.a00 = __builtin_fmaf(-U.n.x, W.n.x, IA.a00);
+        Ia.a11 = __builtin_fmaf(-U.n.y, W.n.y, IA.a11);
+        Ia.a01 = __builtin_fmaf(-U.n.x, W.n.y, IA.a01);
+        const float uf[3] = {W.f.x, W.f.y, W.f.z};
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          Ia.b[k] = __builtin_fmaf(-U.n.x, uf[k], IA.b[k]);
+          Ia.b[3 + k] = __builtin_fmaf(-U.n.y, uf[k], IA.b[3 + k]);
+        }
+        Ia.c00 = __builtin_fmaf(-U.f.x, W.f.x, IA.c00);
+        Ia.c11 = __builtin_fmaf(-U.f.y, W.f.y, IA.c11);
+        Ia.c22 = __builtin_fmaf(-U.f.z, W.f.z, IA.c22);
+        Ia.c01 = __builtin_fmaf(-U.f.x, W.f.y, IA.c01);
+        Ia.c02 = __builtin_fmaf(-U.f.x, W.f.z, IA.c02);
+        Ia.c12 = __builtin_fmaf(-U.f.y, W.f.z, IA.c12);
+        // pa = pA + Ia c + U u / D; c = w [wy, -wx, 0; vy, -vx, 0]
+        const float w = qd(cidx<TP::vofs(J)>);
+        const float cwx = w * v[J].w.y, cwy = -w * v[J].w.x, cvx = w * v[J].v.y, cvy = -w * v[J].v.x;
+        const float ud_ = ud[J];
+        Frc pa;
+        pa.n.x = pA.n.x + Ia.a00 * cwx + Ia.a01 * cwy + Ia.b[0] * cvx + Ia.b[1] * cvy + U.n.x * ud_;
+        pa.n.y = pA.n.y + Ia.a01 * cwx + Ia.a11 * cwy + Ia.b[3] * cvx + Ia.b[4] * cvy + U.n.y * ud_;
+        pa.n.z = pA.n.z + U.n.z * ud_;
+        pa.f.x = pA.f.x + Ia.b[0] * cwx + Ia.b[3] * cwy + Ia.c00 * cvx + Ia.c01 * cvy + U.f.x * ud_;
+        pa.f.y = pA.f.y + Ia.b[1] * cwx + Ia.b[4] * cwy + Ia.c01 * cvx + Ia.c11 * cvy + U.f.y * ud_;
+        pa.f.z = pA.f.z + Ia.b[2] * cwx + Ia.b[5] * cwy + Ia.c02 * cvx + Ia.c12 * cvy + U.f.z * ud_;
+        const V3 r = load_r<J>(t);
+        const M3 RJ = joint_rot_cs<J>(t, cq[J], sq[J]);
+        constexpr bool kFirst = (J == P + 1);
+        xainr_acc<kFirst>(RJ, r, Ia, acc[P]);
+        if constexpr (kFirst) accp[P] = xfrc(RJ, r, pa);
+        else xfrc_acc(RJ, r, pa, accp[P]);
+      }
+    }
+  };
+
+  // velocity pass (root to leaves) with the articulated pass on subtree close
+  sfor<0, N>([&](auto I_) __attribute__((always_inline)) {
+    constexpr int I = decltype(I_)::value;
+    constexpr int P = TP::parent(I);
+    if constexpr (TP::free_body(I)) {
+      v[I] = {{qd(3), qd(4), qd(5)}, {qd(0), qd(1), qd(2)}};
+    } else {
+      fsincos(q(cidx<TP::qofs(I)>), sq[I], cq[I]);
+      const float w = qd(cidx<TP::vofs(I)>);
+      if constexpr (P < 0) {
+        v[I] = {{0.0f, 0.0f, w}, {0.0f, 0.0f, 0.0f}};
+      } else {
+        const M3 RI = joint_rot_cs<I>(t, cq[I], sq[I]);
+        v[I] = xmot(RI, load_r<I>(t), v[P]);
+        v[I].w.z = v[I].w.z + w;
+      }
+    }
+    close_subtrees<TP, I, I>(close);
+  });
+
+  // acceleration pass (root to leaves), velocities rebuilt on the way
+  Mot a[N], vv[N];
+  sfor<0, N>([&](auto I_) __attribute__((always_inline)) {
+    constexpr int I = decltype(I_)::value;
+    constexpr int P = TP::parent(I);
+    if constexpr (TP::free_body(I)) {
+      const V3 ag = mulT(quat_rot(q(3), q(4), q(5), q(6)), mg);
+      a[I] = a0;
+      vv[I] = {{qd(3), qd(4), qd(5)}, {qd(0), qd(1), qd(2)}};
+      qdd(0, a0.v.x - ag.x); qdd(1, a0.v.y - ag.y); qdd(2, a0.v.z - ag.z);
+      qdd(3, a0.w.x); qdd(4, a0.w.y); qdd(5, a0.w.z);
+    } else {
+      float s, c;
+      fsincos(q(cidx<TP::qofs(I)>), s, c);
+      const M3 RI = joint_rot_cs<I>(t, c, s);
+      const float w = qd(cidx<TP::vofs(I)>);
+      Mot ap;
+      if constexpr (P < 0) {
+        vv[I] = {{0.0f, 0.0f, w}, {0.0f, 0.0f, 0.0f}};
+        ap = {{0.0f, 0.0f, 0.0f}, mulT(RI, mg)};
+      } else {
+        const V3 r = load_r<I>(t);
+        vv[I] = xmot(RI, r, vv[P]);
+        vv[I].w.z = vv[I].w.z + w;
+        ap = xmot(RI, r, a[P]);
+        ap.w.x = __builtin_fmaf(w, vv[I].w.y, ap.w.x);
+        ap.w.y = __builtin_fmaf(-w, vv[I].w.x, ap.w.y);
+        ap.v.x = __builtin_fmaf(w, vv[I].v.y, ap.v.x);
+        ap.v.y = __builtin_fmaf(-w, vv[I].v.x, ap.v.y);
+      }
+      const float x = ud[I] - pair(Ud[I], ap);
+      qdd(cidx<TP::vofs(I)>, x);
+      ap.w.z = ap.w.z + x;
+      a[I] = ap;
+    }
+  });
+}
+
 }  // namespace rbd

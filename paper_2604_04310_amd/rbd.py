@@ -28,7 +28,7 @@ OP_FWD_DYN, OP_RNEA, OP_FWD_DYN_VJP = 0, 1, 2
 
 # Every symbol include/rbd.h declares.
 EXPORTS = ["rbd_model_create", "rbd_model_destroy", "rbd_model_dims", "rbd_model_topology", "rbd_fk",
-           "rbd_jacobian", "rbd_rnea", "rbd_crba", "rbd_fwd_dyn", "rbd_fwd_dyn_vjp", "rbd_status_str",
+           "rbd_jacobian", "rbd_rnea", "rbd_crba", "rbd_fwd_dyn", "rbd_aba", "rbd_fwd_dyn_vjp", "rbd_status_str",
            "rbd_last_error", "rbd_device_count", "rbd_diag_fma_rate", "rbd_server_create", "rbd_server_submit", "rbd_server_wait",
            "rbd_server_get_stats", "rbd_server_reset_stats", "rbd_server_destroy"]
 
@@ -86,6 +86,7 @@ def lib():
         L.rbd_rnea.argtypes = [vp, i64, i64, vp, vp, vp, vp, vp]
         L.rbd_crba.argtypes = [vp, i64, i64, vp, vp, vp]
         L.rbd_fwd_dyn.argtypes = [vp, i64, i64, vp, vp, vp, vp, vp]
+        L.rbd_aba.argtypes = [vp, i64, i64, vp, vp, vp, vp, vp]
         L.rbd_fwd_dyn_vjp.argtypes = [vp, i64, i64, vp, vp, vp, vp, vp, vp, vp, vp]
         L.rbd_status_str.argtypes = [C.c_int]
         L.rbd_status_str.restype = C.c_char_p
@@ -266,6 +267,18 @@ def fwd_dyn(model: Model, q, qd, tau, out=None):
     op, _, l4 = _soa(qdd, model.nv, "qdd", B)
     ld = _same_ld(l1, l2, l3, l4)
     check(lib().rbd_fwd_dyn(model.handle, B, ld, qp, qdp, taup, op, _stream()))
+    return qdd
+
+
+def aba(model: Model, q, qd, tau, out=None):
+    """Forward dynamics qdd [nv, B] by the articulated-body algorithm (same result as fwd_dyn)."""
+    qp, B, l1 = _soa(q, model.nq, "q")
+    qdp, _, l2 = _soa(qd, model.nv, "qd", B)
+    taup, _, l3 = _soa(tau, model.nv, "tau", B)
+    qdd = _out(model.nv, B, q) if out is None else out
+    op, _, l4 = _soa(qdd, model.nv, "qdd", B)
+    ld = _same_ld(l1, l2, l3, l4)
+    check(lib().rbd_aba(model.handle, B, ld, qp, qdp, taup, op, _stream()))
     return qdd
 
 

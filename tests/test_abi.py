@@ -103,6 +103,8 @@ def test_null_model_calls(rbd):
     L = rbd.lib()
     assert L.rbd_fwd_dyn(None, 1, 1, None, None, None, None, None) == 1
     assert b"model is NULL" in L.rbd_last_error()
+    assert L.rbd_aba(None, 1, 1, None, None, None, None, None) == 1
+    assert b"model is NULL" in L.rbd_last_error()
 
 
 def _server_create(rbd, **kw):

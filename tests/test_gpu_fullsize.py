@@ -1,8 +1,9 @@
 """Parity at the benchmark sizes, in the launch configuration the benchmark times.
 
 Chain of 7 at batch 2^20 (fwd_dyn, rnea: first 4096 states against the oracle,
-all outputs finite), the 35-DoF humanoid at batch 65536 (fwd_dyn on every
-instance; crba, fk and jacobian on a strided sample), and the adjoint at 2^18
+all outputs finite), the 35-DoF humanoid at batch 65536 (fwd_dyn by both the
+factorised solve and the articulated-body algorithm on every instance; crba,
+fk and jacobian on a strided sample), and the adjoint at 2^18
 (chain) and 32768 (humanoid) against central differences on 256 states.
 """
 from __future__ import annotations
@@ -61,7 +62,12 @@ def test_humanoid_batch_65536(rbd):
     h = rbd.rnea(m, q, qd)
     torch.cuda.synchronize()
     all_idx = np.arange(B)
-    assert rel_err(cols(qdd, all_idx), O.fwd_dyn(desc, st.q, st.qd, st.tau)) < 1e-4
+    ref = O.fwd_dyn(desc, st.q, st.qd, st.tau)
+    assert rel_err(cols(qdd, all_idx), ref) < 1e-4
+    del qdd
+    qdd_aba = rbd.aba(m, q, qd, tau)
+    assert rel_err(cols(qdd_aba, all_idx), ref) < 1e-4
+    del qdd_aba
     assert rel_err(cols(h, all_idx), O.rnea(desc, st.q, st.qd)) < 1e-4
     idx = np.arange(0, B, 61)
     M = rbd.crba(m, q)

@@ -78,6 +78,16 @@ def test_fwd_dyn_parity(rbd, name):
 
 
 @pytest.mark.parametrize("name", list(MODELS))
+def test_aba_parity(rbd, name):
+    """Articulated-body forward dynamics against the oracle's own ABA and its LTL solve."""
+    desc, m = model_of(rbd, name)
+    st = W.states(desc, BATCH, 201)
+    qdd = host(rbd.aba(m, gpu(st.q), gpu(st.qd), gpu(st.tau)))
+    assert rel_err(qdd, O.fwd_dyn(desc, st.q, st.qd, st.tau, method=O.METHOD_ABA)) < TOL_QDD
+    assert rel_err(qdd, O.fwd_dyn(desc, st.q, st.qd, st.tau)) < TOL_QDD
+
+
+@pytest.mark.parametrize("name", list(MODELS))
 def test_rnea_parity(rbd, name):
     desc, m = model_of(rbd, name)
     st = W.states(desc, BATCH, 202)
@@ -176,6 +186,26 @@ def test_special_states(rbd):
     q2[:, 3:7] *= 2.5  # same rotation
     qdd2 = host(rbd.fwd_dyn(m, gpu(q2), gpu(qd), gpu(tau)))
     assert rel_err(qdd2, O.fwd_dyn(desc, q, qd, tau)) < TOL_QDD
+
+
+def test_aba_special_states_and_layout(rbd):
+    """ABA on q = 0, +-pi, qd = 0, large qd, a scaled quaternion, with ld > batch."""
+    desc, m = model_of(rbd, "humanoid30")
+    B, ld = 64, 96
+    st = W.states(desc, B, 212)
+    q, qd = st.q.copy(), st.qd.copy()
+    q[0:8, 7:] = 0.0
+    q[8:16, 7:] = np.pi
+    q[16:24, 7:] = -np.pi
+    qd[24:32] = 0.0
+    qd[32:40] *= 20.0
+    q[40:48, 3:7] *= 0.3
+    q, qd = W._f32(q), W._f32(qd)
+    out = torch.full((desc.nv, ld), 7.0, dtype=torch.float32, device="cuda")
+    rbd.aba(m, gpu(q, ld), gpu(qd, ld), gpu(st.tau, ld), out=out[:, :B])
+    o = out.cpu().numpy()
+    assert np.all(o[:, B:] == 7.0)
+    assert rel_err(o[:, :B].T.astype(np.float64), O.fwd_dyn(desc, q, qd, st.tau, method=O.METHOD_ABA)) < TOL_QDD
 
 
 def test_zero_quaternion_poisons_only_its_instance(rbd):
