@@ -58,6 +58,8 @@ def lib():
         L.orc_jacobian.argtypes = [m, i64, d, i32, P(C.c_int32), d]
         L.orc_rnea.argtypes = [m, i64, d, d, d, d]
         L.orc_rnea_nograv.argtypes = [m, i64, d, d, d, d]
+        L.orc_rnea_ext.argtypes = [m, i64, d, d, d, d, d]
+        L.orc_fwd_dyn_ext.argtypes = [m, i64, d, d, d, d, d, C.c_int]
         L.orc_crba.argtypes = [m, i64, d, d]
         L.orc_fwd_dyn.argtypes = [m, i64, d, d, d, d, C.c_int]
         L.orc_fwd_dyn_vjp_fd.argtypes = [m, i64, d, d, d, d, d, d, d, C.c_double, C.c_int]
@@ -127,11 +129,21 @@ def jacobian(desc, q, frames=None):
     return J
 
 
-def rnea(desc, q, qd, qdd=None, gravity=True):
-    """Inverse dynamics tau = M qdd + c + g, Eq. (1); qdd=None gives h(q, qd)."""
+def rnea(desc, q, qd, qdd=None, gravity=True, fext=None):
+    """Inverse dynamics tau = M qdd + c + g - sum_i J_i^T F_i, Eq. (1); qdd=None gives h(q, qd).
+
+    fext: [B, n_bodies, 6] external spatial forces in world axes, [force; moment
+    about the world origin] (the F_ext input of Alg. 1)."""
     q, qd = _c(q), _c(qd)
     qdd = None if qdd is None else _c(qdd)
     tau = np.empty_like(qd)
+    if fext is not None:
+        if not gravity:
+            raise ValueError("oracle rnea: fext with gravity=False is not provided")
+        fext = _c(fext)
+        _check(lib().orc_rnea_ext(C.byref(_model(desc)), q.shape[0], _dp(q), _dp(qd), _dp(qdd), _dp(fext),
+                                  _dp(tau)), "rnea")
+        return tau
     fn = lib().orc_rnea if gravity else lib().orc_rnea_nograv
     _check(fn(C.byref(_model(desc)), q.shape[0], _dp(q), _dp(qd), _dp(qdd), _dp(tau)), "rnea")
     return tau
@@ -145,10 +157,15 @@ def crba(desc, q):
     return H
 
 
-def fwd_dyn(desc, q, qd, tau, method=METHOD_LTL):
-    """Forward dynamics qdd = M^-1 (tau - h), Eq. (2)."""
+def fwd_dyn(desc, q, qd, tau, method=METHOD_LTL, fext=None):
+    """Forward dynamics qdd = M^-1 (tau - h + sum_i J_i^T F_i), Eq. (2); fext as for rnea."""
     q, qd, tau = _c(q), _c(qd), _c(tau)
     qdd = np.empty_like(qd)
+    if fext is not None:
+        fext = _c(fext)
+        _check(lib().orc_fwd_dyn_ext(C.byref(_model(desc)), q.shape[0], _dp(q), _dp(qd), _dp(tau), _dp(fext),
+                                     _dp(qdd), method), "fwd_dyn")
+        return qdd
     _check(lib().orc_fwd_dyn(C.byref(_model(desc)), q.shape[0], _dp(q), _dp(qd), _dp(tau), _dp(qdd), method),
            "fwd_dyn")
     return qdd

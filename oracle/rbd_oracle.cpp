@@ -317,12 +317,28 @@ template <class T> void jacobian(const Model& M, const T* q, int k, T* J /*6 x n
   }
 }
 
+// ---------------------------------------------------------------- external forces
+// External spatial force on body i, given in world axes as [force f; moment n
+// about the world origin] (fext + 6 i), expressed in body i's coordinates:
+// [R^T (n - p x f); R^T f] with (R, p) the body's world pose (Alg. 1 takes
+// the forces in the root frame; the recursion here works in body frames).
+template <class T> SV<T> fext_body(const M3<T>& Rw, const V3<T>& pw, const T* fe) {
+  const V3<T> f = {fe[0], fe[1], fe[2]}, n = {fe[3], fe[4], fe[5]};
+  return {mtv(Rw, sub(n, cross(pw, f))), mtv(Rw, f)};
+}
+
 // ---------------------------------------------------------------- RNEA
-// tau = ID(q, qd, qdd); qdd == nullptr means qdd = 0 (bias force h(q, qd)).
-template <class T> void rnea(const Model& M, const T* q, const T* qd, const T* qdd, T* tau) {
+// tau = ID(q, qd, qdd) - sum_i J_i^T F_ext,i; qdd == nullptr means qdd = 0
+// (bias force h(q, qd)), fext == nullptr means no external forces. Body i's
+// force balance subtracts the external force, as in Alg. 1.
+template <class T> void rnea(const Model& M, const T* q, const T* qd, const T* qdd, T* tau,
+                             const T* fext = nullptr) {
   const int n = M.n;
   std::vector<PX<T>> X(n);
   std::vector<SV<T>> v(n), a(n), f(n);
+  std::vector<M3<T>> Rw;
+  std::vector<V3<T>> pw;
+  if (fext) fk(M, q, Rw, pw);
   const SV<T> a0 = gravity_acc<T>(M);
   for (int i = 0; i < n; ++i) {
     X[i] = jcalc(M, i, q);
@@ -335,6 +351,7 @@ template <class T> void rnea(const Model& M, const T* q, const T* qd, const T* q
     if (qdd) a[i] = sadd(a[i], smul(M, i, qdd + M.vofs[i]));
     RBI<T> I = cvt<T>(M.I[i]);
     f[i] = sadd(imul(I, a[i]), crf(v[i], imul(I, v[i])));
+    if (fext) f[i] = ssub(f[i], fext_body(Rw[i], pw[i], fext + 6 * i));
   }
   for (int i = n - 1; i >= 0; --i) {
     stmul(M, i, f[i], tau + M.vofs[i]);
@@ -492,10 +509,13 @@ template <class T> M6<T> xtax(const PX<T>& X, const M6<T>& A) {  // X^T A X
 // Solve the small dense SPD system D x = b (size m <= 6) by L L^T.
 template <class T> void small_spd_solve(int m, T* D, T* b) { chol_llt_solve(m, D, b); }
 
-template <class T> void aba(const Model& M, const T* q, const T* qd, const T* tau, T* qdd) {
+template <class T> void aba(const Model& M, const T* q, const T* qd, const T* tau, T* qdd, const T* fext = nullptr) {
   const int n = M.n;
   std::vector<PX<T>> X(n);
   std::vector<SV<T>> v(n), c(n), pA(n), a(n);
+  std::vector<M3<T>> Rw;
+  std::vector<V3<T>> pw;
+  if (fext) fk(M, q, Rw, pw);
   std::vector<M6<T>> IA(n);
   std::vector<std::vector<SV<T>>> U(n);
   std::vector<std::vector<T>> D(n), u(n);
@@ -508,6 +528,7 @@ template <class T> void aba(const Model& M, const T* q, const T* qd, const T* ta
     RBI<T> I = cvt<T>(M.I[i]);
     IA[i] = rbi_dense(I);
     pA[i] = crf(v[i], imul(I, v[i]));
+    if (fext) pA[i] = ssub(pA[i], fext_body(Rw[i], pw[i], fext + 6 * i));
   }
   for (int i = n - 1; i >= 0; --i) {
     const int m = M.nvi[i];
@@ -563,11 +584,13 @@ template <class T> void aba(const Model& M, const T* q, const T* qd, const T* ta
 }
 
 // qdd = M^-1 (tau - h); method 0: dense L L^T, 1: branch-sparse L^T L, 2: ABA.
-template <class T> void fwd_dyn(const Model& M, const T* q, const T* qd, const T* tau, T* qdd, int method) {
+// With external forces (fext non-null) h includes -sum_i J_i^T F_ext,i.
+template <class T> void fwd_dyn(const Model& M, const T* q, const T* qd, const T* tau, T* qdd, int method,
+                                const T* fext = nullptr) {
   const int nv = M.nv;
-  if (method == 2) { aba(M, q, qd, tau, qdd); return; }
+  if (method == 2) { aba(M, q, qd, tau, qdd, fext); return; }
   std::vector<T> h(nv), H(nv * nv);
-  rnea(M, q, qd, (const T*)nullptr, h.data());
+  rnea(M, q, qd, (const T*)nullptr, h.data(), fext);
   crba(M, q, H.data());
   for (int k = 0; k < nv; ++k) qdd[k] = tau[k] - h[k];
   if (method == 0) chol_llt_solve(nv, H.data(), qdd);
@@ -694,6 +717,19 @@ int orc_rnea(const orc_model* d, int64_t B, const double* q, const double* qd, c
   return 0;
 }
 
+// orc_rnea with external forces fext [B][n][6] (world axes: force, then
+// moment about the world origin).
+int orc_rnea_ext(const orc_model* d, int64_t B, const double* q, const double* qd, const double* qdd,
+                 const double* fext, double* tau) {
+  Model M;
+  if (build_model(d, M) || !fext) return 1;
+#pragma omp parallel for schedule(static)
+  for (int64_t b = 0; b < B; ++b)
+    rnea(M, q + b * M.nq, qd + b * M.nv, qdd ? qdd + b * M.nv : (const double*)nullptr, tau + b * M.nv,
+         fext + b * 6 * M.n);
+  return 0;
+}
+
 // Like orc_rnea with gravity switched off (c(q, qd) alone when qdd is null).
 int orc_rnea_nograv(const orc_model* d, int64_t B, const double* q, const double* qd, const double* qdd,
                     double* tau) {
@@ -721,6 +757,16 @@ int orc_fwd_dyn(const orc_model* d, int64_t B, const double* q, const double* qd
 #pragma omp parallel for schedule(static)
   for (int64_t b = 0; b < B; ++b)
     fwd_dyn(M, q + b * M.nq, qd + b * M.nv, tau + b * M.nv, qdd + b * M.nv, method);
+  return 0;
+}
+
+int orc_fwd_dyn_ext(const orc_model* d, int64_t B, const double* q, const double* qd, const double* tau,
+                    const double* fext, double* qdd, int method) {
+  Model M;
+  if (build_model(d, M) || method < 0 || method > 2 || !fext) return 1;
+#pragma omp parallel for schedule(static)
+  for (int64_t b = 0; b < B; ++b)
+    fwd_dyn(M, q + b * M.nq, qd + b * M.nv, tau + b * M.nv, qdd + b * M.nv, method, fext + b * 6 * M.n);
   return 0;
 }
 

@@ -357,3 +357,68 @@ def test_operation_counts_are_consistent():
             assert ltl["flops"] == llt["flops"]        # a chain has none
         rb, cr = O.count_ops(d, "rnea_bias"), O.count_ops(d, "crba")
         assert ltl["flops"] > rb["flops"] + cr["flops"]
+
+
+# ---------------------------------------------------------------- external forces (Eq. (1) J^T f, Alg. 1 F_ext)
+def _random_fext(desc, B, seed):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return rng.normal(0.0, 5.0, size=(B, desc.n_bodies, 6))
+
+
+@pytest.mark.parametrize("name", ["chain7", "tree12f", "humanoid30"])
+def test_external_weight_support_cancels_gravity(name):
+    """Each body held up at its CoM by a force equal to its weight: at rest no joint torque is
+    needed, and with zero torque nothing accelerates (every method)."""
+    desc = {"chain7": W.chain(7), "tree12f": W.random_tree([-1, 0, 1, 1, 0, 4, 5, 5, 7, 0, 9, 10], True, 34),
+            "humanoid30": W.humanoid()}[name]
+    B = 16
+    st = W.states(desc, B, 41)
+    zero = np.zeros((B, desc.nv))
+    c = com_world(desc, O.fk(desc, st.q))
+    f = -desc.mass[None, :, None] * np.asarray(desc.gravity)[None, None, :]
+    fext = np.concatenate([np.broadcast_to(f, c.shape), np.cross(c, f)], axis=2)
+    scale = np.abs(O.rnea(desc, st.q, zero)).max()
+    assert scale > 1.0
+    assert np.abs(O.rnea(desc, st.q, zero, fext=fext)).max() < 1e-11 * scale
+    for method in (O.METHOD_LLT, O.METHOD_LTL, O.METHOD_ABA):
+        assert np.abs(O.fwd_dyn(desc, st.q, zero, zero, method, fext=fext)).max() < 1e-9
+
+
+@pytest.mark.parametrize("name", ["chain7", "tree12f", "humanoid30"])
+def test_external_force_is_virtual_work_through_jacobians(name):
+    """tau(F) - tau(0) = -sum_i J_i^T [f_i; n_i - p_i x f_i] with the kinematic Jacobians of the body
+    origins p_i (the moment moved from the world origin to p_i)."""
+    desc = {"chain7": W.chain(7), "tree12f": W.random_tree([-1, 0, 1, 1, 0, 4, 5, 5, 7, 0, 9, 10], True, 34),
+            "humanoid30": W.humanoid()}[name]
+    B = 8
+    st = W.states(desc, B, 42)
+    qdd = W.cotangent(desc.nv, B, 43)
+    fext = _random_fext(desc, B, 44)
+    dtau = O.rnea(desc, st.q, st.qd, qdd, fext=fext) - O.rnea(desc, st.q, st.qd, qdd)
+    p = O.fk(desc, st.q)[..., :, 3]
+    J = O.jacobian(desc, st.q)  # [B, n, 6, nv], rows [v; w]
+    wrench = np.concatenate([fext[..., :3], fext[..., 3:] - np.cross(p, fext[..., :3])], axis=2)
+    ref = -np.einsum("bnrc,bnr->bc", J, wrench)
+    assert rel_err(dtau, ref) < 1e-12
+    # forward dynamics moves by M^-1 of the same generalised force
+    M = O.crba(desc, st.q)
+    for method in (O.METHOD_LLT, O.METHOD_LTL, O.METHOD_ABA):
+        d_qdd = O.fwd_dyn(desc, st.q, st.qd, st.tau, method, fext=fext) - O.fwd_dyn(desc, st.q, st.qd, st.tau, method)
+        assert rel_err(d_qdd, np.linalg.solve(M, -ref[..., None])[..., 0]) < 1e-10
+
+
+def test_free_body_force_through_com_closed_form():
+    """A free body at rest pushed by F through its CoM: the origin accelerates by R^T (F/m + g) in
+    body axes and nothing turns."""
+    d, rng = _single_body(11, floating=True)
+    B = 8
+    st = W.states(d, B, 45)
+    R = base_rotation(st.q[:, 3:7] / np.linalg.norm(st.q[:, 3:7], axis=1, keepdims=True))
+    cw = st.q[:, :3] + np.einsum("bij,j->bi", R, d.com[0])
+    F = rng.normal(0, 10, size=(B, 3))
+    fext = np.concatenate([F, np.cross(cw, F)], axis=1)[:, None, :]
+    lin = np.einsum("bji,bj->bi", R, F / d.mass[0] + np.asarray(d.gravity))
+    ref = np.concatenate([lin, np.zeros((B, 3))], axis=1)
+    zero = np.zeros((B, 6))
+    for method in (O.METHOD_LLT, O.METHOD_LTL, O.METHOD_ABA):
+        assert np.allclose(O.fwd_dyn(d, st.q, zero, zero, method, fext=fext), ref, rtol=1e-11, atol=1e-11)
