@@ -8,10 +8,10 @@
  *   rbd_fk           forward kinematics 0T_i(q) of every body (Sec. II)
  *   rbd_jacobian     world-aligned geometric Jacobians of chosen body frames
  *                    (Sec. IV, the library's analytical Jacobians)
- *   rbd_rnea         inverse dynamics tau = M qdd + c + g, Eq. (1); with
- *                    qdd == NULL the bias force h(q, qd) = c + g (Alg. 1)
+ *   rbd_rnea         inverse dynamics tau = M qdd + c + g - J^T F_ext,
+ *                    Eq. (1); with qdd == NULL the bias force h(q, qd) (Alg. 1)
  *   rbd_crba         joint-space mass matrix M(q) (Alg. 2)
- *   rbd_fwd_dyn      forward dynamics qdd = M^-1 (tau - h), Eq. (2), by a
+ *   rbd_fwd_dyn      forward dynamics qdd = M^-1 (tau - h + J^T F_ext), Eq. (2), by a
  *                    per-instance Cholesky-type solve (Sec. V, footnote)
  *   rbd_aba          the same forward dynamics by the articulated-body
  *                    algorithm, O(n), no mass matrix (Sec. III, named there as
@@ -114,33 +114,43 @@ rbd_status rbd_fk(const rbd_model* model, int64_t batch, int64_t ld, const float
 rbd_status rbd_jacobian(const rbd_model* model, int64_t batch, int64_t ld, const float* q, int32_t n_frames,
                         const int32_t* frames, float* J, hipStream_t stream);
 
-/* Inverse dynamics, Eq. (1) with f = 0, by the recursive Newton-Euler
- * algorithm (the recursive form of Alg. 1): tau = M(q) qdd + c(q, qd) + g(q).
- * qdd == NULL computes the bias force h(q, qd). q: [nq][ld]; qd, qdd, tau:
- * [nv][ld]. */
+/* External forces (Eq. (1)'s J^T f term; the F_ext input of Alg. 1). f_ext,
+ * where an entry point takes it, is NULL (no external forces) or a device
+ * array [n_bodies * 6][ld]: element ((i*6 + c) * ld + b) is the spatial force
+ * the environment applies to body i, in world axes, c = 0..2 the force and
+ * c = 3..5 the moment about the world origin. It enters the joint torques as
+ * -sum_i J_i^T F_i (J_i the body's Jacobian in the same world frame), so a
+ * force holding a body up lowers the torque its joints need. */
+
+/* Inverse dynamics, Eq. (1), by the recursive Newton-Euler algorithm (the
+ * recursive form of Alg. 1): tau = M(q) qdd + c(q, qd) + g(q) - sum_i J_i^T
+ * F_i. qdd == NULL computes the bias force h(q, qd) (with the external-force
+ * term when f_ext is given). q: [nq][ld]; qd, qdd, tau: [nv][ld]. */
 rbd_status rbd_rnea(const rbd_model* model, int64_t batch, int64_t ld, const float* q, const float* qd,
-                    const float* qdd, float* tau, hipStream_t stream);
+                    const float* qdd, const float* f_ext, float* tau, hipStream_t stream);
 
 /* Joint-space mass matrix by the composite-rigid-body algorithm (the
  * recursive form of Alg. 2), dense and symmetric: M[(r*nv + c) * ld + b]. */
 rbd_status rbd_crba(const rbd_model* model, int64_t batch, int64_t ld, const float* q, float* M,
                     hipStream_t stream);
 
-/* Forward dynamics, Eq. (2) with f = 0: qdd = M(q)^-1 (tau - h(q, qd)).
- * One fused kernel: bias force, mass matrix and its branch-sparse L^T L
- * factorisation never leave the lane. q: [nq][ld]; qd, tau, qdd: [nv][ld]. */
+/* Forward dynamics, Eq. (2): qdd = M(q)^-1 (tau - h(q, qd) + sum_i J_i^T F_i),
+ * f_ext as above (NULL: none). One fused kernel: bias force, mass matrix and
+ * its branch-sparse L^T L factorisation never leave the lane. q: [nq][ld];
+ * qd, tau, qdd: [nv][ld]. */
 rbd_status rbd_fwd_dyn(const rbd_model* model, int64_t batch, int64_t ld, const float* q, const float* qd,
-                       const float* tau, float* qdd, hipStream_t stream);
+                       const float* tau, const float* f_ext, float* qdd, hipStream_t stream);
 
-/* Forward dynamics, Eq. (2) with f = 0, by the articulated-body algorithm:
- * the same qdd as rbd_fwd_dyn (up to rounding), computed in three O(n) sweeps
- * over the tree (velocities; articulated inertias and bias forces, leaves to
- * root; accelerations) without forming M. Same arguments and layout as
- * rbd_fwd_dyn. A non-positive articulated pivot yields NaN in that instance. */
+/* Forward dynamics, Eq. (2), by the articulated-body algorithm: the same qdd
+ * as rbd_fwd_dyn (up to rounding), computed in three O(n) sweeps over the
+ * tree (velocities; articulated inertias and bias forces, leaves to root;
+ * accelerations) without forming M. Same arguments and layout as rbd_fwd_dyn.
+ * A non-positive articulated pivot yields NaN in that instance. */
 rbd_status rbd_aba(const rbd_model* model, int64_t batch, int64_t ld, const float* q, const float* qd,
-                   const float* tau, float* qdd, hipStream_t stream);
+                   const float* tau, const float* f_ext, float* qdd, hipStream_t stream);
 
-/* Vector-Jacobian product of rbd_fwd_dyn for the cotangent g_qdd [nv][ld]:
+/* Vector-Jacobian product of rbd_fwd_dyn without external forces, for the
+ * cotangent g_qdd [nv][ld]:
  * g_q = g_qdd^T dqdd/dq [nq][ld] (raw quaternion components included),
  * g_qd = g_qdd^T dqdd/dqd [nv][ld], g_tau = g_qdd^T dqdd/dtau = M^-1 g_qdd
  * [nv][ld]. Any of the three outputs may be NULL (not computed). */

@@ -300,12 +300,12 @@ rbd_status rbd_jacobian(const rbd_model* m, int64_t batch, int64_t ld, const flo
 }
 
 rbd_status rbd_rnea(const rbd_model* m, int64_t batch, int64_t ld, const float* q, const float* qd,
-                    const float* qdd, float* tau, hipStream_t s) {
+                    const float* qdd, const float* f_ext, float* tau, hipStream_t s) {
   rbd_status st = check_batch(m, batch, ld, "rbd_rnea");
   if (st != RBD_OK) return st;
   if (batch > 0 && (!q || !qd || !tau)) return fail(RBD_E_INVAL, "rbd_rnea: NULL array");
   if ((st = use_device(m->device)) != RBD_OK) return st;
-  return launch_rnea(m, batch, ld, q, qd, qdd, tau, s);
+  return launch_rnea(m, batch, ld, q, qd, qdd, f_ext, tau, s);
 }
 
 rbd_status rbd_crba(const rbd_model* m, int64_t batch, int64_t ld, const float* q, float* M, hipStream_t s) {
@@ -317,21 +317,21 @@ rbd_status rbd_crba(const rbd_model* m, int64_t batch, int64_t ld, const float* 
 }
 
 rbd_status rbd_fwd_dyn(const rbd_model* m, int64_t batch, int64_t ld, const float* q, const float* qd,
-                       const float* tau, float* qdd, hipStream_t s) {
+                       const float* tau, const float* f_ext, float* qdd, hipStream_t s) {
   rbd_status st = check_batch(m, batch, ld, "rbd_fwd_dyn");
   if (st != RBD_OK) return st;
   if (batch > 0 && (!q || !qd || !tau || !qdd)) return fail(RBD_E_INVAL, "rbd_fwd_dyn: NULL array");
   if ((st = use_device(m->device)) != RBD_OK) return st;
-  return launch_fwd_dyn(m, batch, ld, q, qd, tau, qdd, s);
+  return launch_fwd_dyn(m, batch, ld, q, qd, tau, f_ext, qdd, s);
 }
 
 rbd_status rbd_aba(const rbd_model* m, int64_t batch, int64_t ld, const float* q, const float* qd, const float* tau,
-                   float* qdd, hipStream_t s) {
+                   const float* f_ext, float* qdd, hipStream_t s) {
   rbd_status st = check_batch(m, batch, ld, "rbd_aba");
   if (st != RBD_OK) return st;
   if (batch > 0 && (!q || !qd || !tau || !qdd)) return fail(RBD_E_INVAL, "rbd_aba: NULL array");
   if ((st = use_device(m->device)) != RBD_OK) return st;
-  return launch_aba(m, batch, ld, q, qd, tau, qdd, s);
+  return launch_aba(m, batch, ld, q, qd, tau, f_ext, qdd, s);
 }
 
 rbd_status rbd_fwd_dyn_vjp(const rbd_model* m, int64_t batch, int64_t ld, const float* q, const float* qd,

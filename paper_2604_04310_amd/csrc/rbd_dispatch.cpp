@@ -13,7 +13,7 @@ namespace rbd {
 
 #define RBD_DECL(name, fr, ...) \
   extern const LaunchTable launch_table_##name##_p1, launch_table_##name##_p2, launch_table_##name##_p3, \
-      launch_table_##name##_p4;
+      launch_table_##name##_p4, launch_table_##name##_p5;
 RBD_TOPOLOGIES(RBD_DECL)
 #undef RBD_DECL
 
@@ -27,20 +27,23 @@ static const TopoInfo k_topos[] = {
 #undef RBD_INFO
 };
 
-static const LaunchTable* const k_parts[][4] = {
-#define RBD_TAB(name, fr, ...) \
-  {&launch_table_##name##_p1, &launch_table_##name##_p2, &launch_table_##name##_p3, &launch_table_##name##_p4},
+static const LaunchTable* const k_parts[][5] = {
+#define RBD_TAB(name, fr, ...)                                                                                  \
+  {&launch_table_##name##_p1, &launch_table_##name##_p2, &launch_table_##name##_p3, &launch_table_##name##_p4, \
+   &launch_table_##name##_p5},
     RBD_TOPOLOGIES(RBD_TAB)
 #undef RBD_TAB
 };
 
-// The four parts of a topology merged into one table (built on first use).
+// The five parts of a topology merged into one table (built on first use).
 static const LaunchTable* merged(int id) {
   static const std::vector<LaunchTable> all = [] {
     std::vector<LaunchTable> v(sizeof(k_parts) / sizeof(k_parts[0]));
     for (size_t i = 0; i < v.size(); ++i) {
-      const LaunchTable &a = *k_parts[i][0], &b = *k_parts[i][1], &c = *k_parts[i][2], &d = *k_parts[i][3];
-      v[i] = LaunchTable{a.fk, a.jacobian, a.rnea, a.crba, b.fwd_dyn, c.vjp, d.aba, b.packed, c.packed_vjp};
+      const LaunchTable &a = *k_parts[i][0], &b = *k_parts[i][1], &c = *k_parts[i][2], &d = *k_parts[i][3],
+                        &e = *k_parts[i][4];
+      v[i] = LaunchTable{a.fk,   a.jacobian,   a.rnea,        a.crba,        b.fwd_dyn,  c.vjp,
+                         d.aba,  b.packed,     c.packed_vjp,  e.rnea_ext,    e.fwd_dyn_ext, e.aba_ext};
     }
     return v;
   }();
@@ -102,10 +105,10 @@ rbd_status launch_jacobian(const rbd_model* m, int64_t batch, int64_t ld, const 
 }
 
 rbd_status launch_rnea(const rbd_model* m, int64_t batch, int64_t ld, const float* q, const float* qd,
-                       const float* qdd, float* tau, hipStream_t s) {
+                       const float* qdd, const float* fext, float* tau, hipStream_t s) {
   if (batch == 0) return RBD_OK;
   RBD_TABLE_OR_FAIL(m);
-  return lt->rnea(m->d_tab, batch, ld, q, qd, qdd, tau, s);
+  return (fext ? lt->rnea_ext : lt->rnea)(m->d_tab, batch, ld, q, qd, qdd, fext, tau, s);
 }
 
 rbd_status launch_crba(const rbd_model* m, int64_t batch, int64_t ld, const float* q, float* M, hipStream_t s) {
@@ -115,17 +118,17 @@ rbd_status launch_crba(const rbd_model* m, int64_t batch, int64_t ld, const floa
 }
 
 rbd_status launch_fwd_dyn(const rbd_model* m, int64_t batch, int64_t ld, const float* q, const float* qd,
-                          const float* tau, float* qdd, hipStream_t s) {
+                          const float* tau, const float* fext, float* qdd, hipStream_t s) {
   if (batch == 0) return RBD_OK;
   RBD_TABLE_OR_FAIL(m);
-  return lt->fwd_dyn(m->d_tab, batch, ld, q, qd, tau, qdd, s);
+  return (fext ? lt->fwd_dyn_ext : lt->fwd_dyn)(m->d_tab, batch, ld, q, qd, tau, fext, qdd, s);
 }
 
 rbd_status launch_aba(const rbd_model* m, int64_t batch, int64_t ld, const float* q, const float* qd,
-                      const float* tau, float* qdd, hipStream_t s) {
+                      const float* tau, const float* fext, float* qdd, hipStream_t s) {
   if (batch == 0) return RBD_OK;
   RBD_TABLE_OR_FAIL(m);
-  return lt->aba(m->d_tab, batch, ld, q, qd, tau, qdd, s);
+  return (fext ? lt->aba_ext : lt->aba)(m->d_tab, batch, ld, q, qd, tau, fext, qdd, s);
 }
 
 rbd_status launch_fwd_dyn_vjp(const rbd_model* m, int64_t batch, int64_t ld, const float* q, const float* qd,

@@ -49,12 +49,12 @@ rbd_status launch_fk(const rbd_model* m, int64_t batch, int64_t ld, const float*
 rbd_status launch_jacobian(const rbd_model* m, int64_t batch, int64_t ld, const float* q, int32_t n_frames,
                            const int32_t* frames, float* J, hipStream_t s);
 rbd_status launch_rnea(const rbd_model* m, int64_t batch, int64_t ld, const float* q, const float* qd,
-                       const float* qdd, float* tau, hipStream_t s);
+                       const float* qdd, const float* fext, float* tau, hipStream_t s);
 rbd_status launch_crba(const rbd_model* m, int64_t batch, int64_t ld, const float* q, float* M, hipStream_t s);
 rbd_status launch_fwd_dyn(const rbd_model* m, int64_t batch, int64_t ld, const float* q, const float* qd,
-                          const float* tau, float* qdd, hipStream_t s);
+                          const float* tau, const float* fext, float* qdd, hipStream_t s);
 rbd_status launch_aba(const rbd_model* m, int64_t batch, int64_t ld, const float* q, const float* qd,
-                      const float* tau, float* qdd, hipStream_t s);
+                      const float* tau, const float* fext, float* qdd, hipStream_t s);
 rbd_status launch_fwd_dyn_vjp(const rbd_model* m, int64_t batch, int64_t ld, const float* q, const float* qd,
                               const float* tau, const float* gqdd, float* gq, float* gqd, float* gtau,
                               hipStream_t s);
@@ -62,20 +62,24 @@ rbd_status launch_fwd_dyn_vjp(const rbd_model* m, int64_t batch, int64_t ld, con
 
 // Host launch wrappers of one compiled topology (see rbd_kernels.hpp).
 struct LaunchTable {
+  using RneaFn = rbd_status (*)(const float* tab, int64_t batch, int64_t ld, const float* q, const float* qd,
+                                const float* qdd, const float* fext, float* tau, hipStream_t s);
+  using FdFn = rbd_status (*)(const float* tab, int64_t batch, int64_t ld, const float* q, const float* qd,
+                              const float* tau, const float* fext, float* qdd, hipStream_t s);
   rbd_status (*fk)(const float* tab, int64_t batch, int64_t ld, const float* q, float* T, hipStream_t s);
   rbd_status (*jacobian)(const float* tab, int64_t batch, int64_t ld, const float* q, const JacSlots& js, float* J,
                          hipStream_t s);
-  rbd_status (*rnea)(const float* tab, int64_t batch, int64_t ld, const float* q, const float* qd, const float* qdd,
-                     float* tau, hipStream_t s);
+  RneaFn rnea;
   rbd_status (*crba)(const float* tab, int64_t batch, int64_t ld, const float* q, float* M, hipStream_t s);
-  rbd_status (*fwd_dyn)(const float* tab, int64_t batch, int64_t ld, const float* q, const float* qd,
-                        const float* tau, float* qdd, hipStream_t s);
+  FdFn fwd_dyn;
   rbd_status (*vjp)(const float* tab, int64_t batch, int64_t ld, const float* q, const float* qd, const float* tau,
                     const float* gqdd, float* gq, float* gqd, float* gtau, hipStream_t s);
-  rbd_status (*aba)(const float* tab, int64_t batch, int64_t ld, const float* q, const float* qd, const float* tau,
-                    float* qdd, hipStream_t s);
+  FdFn aba;
   rbd_status (*packed)(int op, const float* tab, const void* table, int grid, hipStream_t s);
   rbd_status (*packed_vjp)(int op, const float* tab, const void* table, int grid, hipStream_t s);
+  RneaFn rnea_ext;  // with external forces (fext non-null)
+  FdFn fwd_dyn_ext;
+  FdFn aba_ext;
 };
 
 // Packed serving launch of one (model, op): d_table holds a PackedHdr-led

@@ -31,13 +31,19 @@ __global__ __launch_bounds__(kBlock) void k_jacobian(const float* __restrict__ t
   jac_lane<TP>(tab, In{q, ld, b}, js, J, ld, b);
 }
 
-template <class TP, bool HAS_QDD>
+// EXT: per-body external forces (fext, [6 n][ld]) enter the force balance.
+template <class TP, bool HAS_QDD, bool EXT>
 __global__ __launch_bounds__(kBlock) void k_rnea(const float* __restrict__ tab, int64_t batch, int64_t ld,
                                                  const float* __restrict__ q, const float* __restrict__ qd,
-                                                 const float* __restrict__ qdd, float* __restrict__ tau) {
+                                                 const float* __restrict__ qdd, const float* __restrict__ fext,
+                                                 float* __restrict__ tau) {
   const uint32_t b = lane_id();
   if (b >= batch) return;
-  rnea_lane<TP, HAS_QDD>(tab, In{q, ld, b}, In{qd, ld, b}, In{HAS_QDD ? qdd : q, ld, b}, Out{tau, ld, b});
+  if constexpr (EXT)
+    rnea_lane<TP, HAS_QDD>(tab, In{q, ld, b}, In{qd, ld, b}, In{HAS_QDD ? qdd : q, ld, b}, Out{tau, ld, b},
+                           FextIn{{fext, ld, b}});
+  else
+    rnea_lane<TP, HAS_QDD>(tab, In{q, ld, b}, In{qd, ld, b}, In{HAS_QDD ? qdd : q, ld, b}, Out{tau, ld, b});
 }
 
 template <class TP>
@@ -68,12 +74,22 @@ struct RegView {
 // PRE = true issues every input load of the lane at entry (106 for the
 // humanoid), so their latency overlaps the first bodies' arithmetic instead of
 // stalling the single wave of each SIMD at every body.
-template <class TP, bool PRE>
+// The external-force view of a kernel: FextIn over fext, or nothing.
+template <bool EXT>
+RBD_DI auto fext_view(const float* fext, int64_t ld, uint32_t b) {
+  if constexpr (EXT) return FextIn{{fext, ld, b}};
+  else return NoFext{};
+}
+
+// EXT as for k_rnea.
+template <class TP, bool PRE, bool EXT>
 __global__ __launch_bounds__(kBlock) void k_fwd_dyn(const float* __restrict__ tab, int64_t batch, int64_t ld,
                                                     const float* __restrict__ q, const float* __restrict__ qd,
-                                                    const float* __restrict__ tau, float* __restrict__ qdd) {
+                                                    const float* __restrict__ tau, const float* __restrict__ fext,
+                                                    float* __restrict__ qdd) {
   const uint32_t b = lane_id();
   if (b >= batch) return;
+  const auto fx = fext_view<EXT>(fext, ld, b);
   if constexpr (PRE) {
     constexpr int NQ = TP::NQ, NV = TP::NV;
     float qv[NQ], qdv[NV], tv[NV];
@@ -83,19 +99,24 @@ __global__ __launch_bounds__(kBlock) void k_fwd_dyn(const float* __restrict__ ta
       qdv[decltype(K_)::value] = qdi(decltype(K_)::value);
       tv[decltype(K_)::value] = ti(decltype(K_)::value);
     });
-    fwd_dyn_lane<TP, 1>(tab, RegView{qv}, RegView{qdv}, RhsOne<RegView>{RegView{tv}}, SinkOne<Out>{Out{qdd, ld, b}});
+    fwd_dyn_lane<TP, 1>(tab, RegView{qv}, RegView{qdv}, RhsOne<RegView>{RegView{tv}}, SinkOne<Out>{Out{qdd, ld, b}},
+                        fx);
   } else {
-    fwd_dyn_lane<TP, 1>(tab, In{q, ld, b}, In{qd, ld, b}, RhsOne<In>{In{tau, ld, b}}, SinkOne<Out>{Out{qdd, ld, b}});
+    fwd_dyn_lane<TP, 1>(tab, In{q, ld, b}, In{qd, ld, b}, RhsOne<In>{In{tau, ld, b}}, SinkOne<Out>{Out{qdd, ld, b}},
+                        fx);
   }
 }
 
-// Forward dynamics by the articulated-body algorithm; PRE as for k_fwd_dyn.
-template <class TP, bool PRE>
+// Forward dynamics by the articulated-body algorithm; PRE as for k_fwd_dyn,
+// EXT as for k_rnea.
+template <class TP, bool PRE, bool EXT>
 __global__ __launch_bounds__(kBlock) void k_aba(const float* __restrict__ tab, int64_t batch, int64_t ld,
                                                 const float* __restrict__ q, const float* __restrict__ qd,
-                                                const float* __restrict__ tau, float* __restrict__ qdd) {
+                                                const float* __restrict__ tau, const float* __restrict__ fext,
+                                                float* __restrict__ qdd) {
   const uint32_t b = lane_id();
   if (b >= batch) return;
+  const auto fx = fext_view<EXT>(fext, ld, b);
   if constexpr (PRE) {
     constexpr int NQ = TP::NQ, NV = TP::NV;
     float qv[NQ], qdv[NV], tv[NV];
@@ -105,9 +126,9 @@ __global__ __launch_bounds__(kBlock) void k_aba(const float* __restrict__ tab, i
       qdv[decltype(K_)::value] = qdi(decltype(K_)::value);
       tv[decltype(K_)::value] = ti(decltype(K_)::value);
     });
-    aba_lane<TP>(tab, RegView{qv}, RegView{qdv}, RegView{tv}, Out{qdd, ld, b});
+    aba_lane<TP>(tab, RegView{qv}, RegView{qdv}, RegView{tv}, Out{qdd, ld, b}, fx);
   } else {
-    aba_lane<TP>(tab, In{q, ld, b}, In{qd, ld, b}, In{tau, ld, b}, Out{qdd, ld, b});
+    aba_lane<TP>(tab, In{q, ld, b}, In{qd, ld, b}, In{tau, ld, b}, Out{qdd, ld, b}, fx);
   }
 }
 
@@ -271,14 +292,15 @@ struct Launch {
                        q, js, J);
     return check_launch("rbd_jacobian");
   }
-  static rbd_status rnea(const float* tab, int64_t batch, int64_t ld, const float* q, const float* qd,
-                         const float* qdd, float* tau, hipStream_t s) {
+  template <bool EXT>
+  static rbd_status rnea_t(const float* tab, int64_t batch, int64_t ld, const float* q, const float* qd,
+                           const float* qdd, const float* fext, float* tau, hipStream_t s) {
     if (qdd)
-      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_rnea<TP, true>), dim3(grid_for(batch)), dim3(kBlock), 0, s, tab, batch,
-                         ld, q, qd, qdd, tau);
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_rnea<TP, true, EXT>), dim3(grid_for(batch)), dim3(kBlock), 0, s, tab,
+                         batch, ld, q, qd, qdd, fext, tau);
     else
-      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_rnea<TP, false>), dim3(grid_for(batch)), dim3(kBlock), 0, s, tab, batch,
-                         ld, q, qd, qdd, tau);
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_rnea<TP, false, EXT>), dim3(grid_for(batch)), dim3(kBlock), 0, s, tab,
+                         batch, ld, q, qd, qdd, fext, tau);
     return check_launch("rbd_rnea");
   }
   static rbd_status crba(const float* tab, int64_t batch, int64_t ld, const float* q, float* M, hipStream_t s) {
@@ -286,28 +308,30 @@ struct Launch {
                        M);
     return check_launch("rbd_crba");
   }
-  static rbd_status fwd_dyn(const float* tab, int64_t batch, int64_t ld, const float* q, const float* qd,
-                            const float* tau, float* qdd, hipStream_t s) {
-    // Large trees run one wave per SIMD and gain from issuing all input loads
-    // up front; small ones keep their occupancy instead (measured).
+  // Large trees run one wave per SIMD and gain from issuing all input loads up
+  // front; small ones keep their occupancy instead (measured).
+  template <bool EXT>
+  static rbd_status fwd_dyn_t(const float* tab, int64_t batch, int64_t ld, const float* q, const float* qd,
+                              const float* tau, const float* fext, float* qdd, hipStream_t s) {
     constexpr bool kPre = TP::NV > 16;
     if (preload_inputs(kPre))
-      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_fwd_dyn<TP, true>), dim3(grid_for(batch)), dim3(kBlock), 0, s, tab,
-                         batch, ld, q, qd, tau, qdd);
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_fwd_dyn<TP, true, EXT>), dim3(grid_for(batch)), dim3(kBlock), 0, s, tab,
+                         batch, ld, q, qd, tau, fext, qdd);
     else
-      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_fwd_dyn<TP, false>), dim3(grid_for(batch)), dim3(kBlock), 0, s, tab,
-                         batch, ld, q, qd, tau, qdd);
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_fwd_dyn<TP, false, EXT>), dim3(grid_for(batch)), dim3(kBlock), 0, s,
+                         tab, batch, ld, q, qd, tau, fext, qdd);
     return check_launch("rbd_fwd_dyn");
   }
-  static rbd_status aba(const float* tab, int64_t batch, int64_t ld, const float* q, const float* qd,
-                        const float* tau, float* qdd, hipStream_t s) {
+  template <bool EXT>
+  static rbd_status aba_t(const float* tab, int64_t batch, int64_t ld, const float* q, const float* qd,
+                          const float* tau, const float* fext, float* qdd, hipStream_t s) {
     constexpr bool kPre = TP::NV > 16;
     if (preload_inputs(kPre))
-      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_aba<TP, true>), dim3(grid_for(batch)), dim3(kBlock), 0, s, tab, batch,
-                         ld, q, qd, tau, qdd);
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_aba<TP, true, EXT>), dim3(grid_for(batch)), dim3(kBlock), 0, s, tab,
+                         batch, ld, q, qd, tau, fext, qdd);
     else
-      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_aba<TP, false>), dim3(grid_for(batch)), dim3(kBlock), 0, s, tab, batch,
-                         ld, q, qd, tau, qdd);
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_aba<TP, false, EXT>), dim3(grid_for(batch)), dim3(kBlock), 0, s, tab,
+                         batch, ld, q, qd, tau, fext, qdd);
     return check_launch("rbd_aba");
   }
   static rbd_status vjp(const float* tab, int64_t batch, int64_t ld, const float* q, const float* qd,
@@ -339,24 +363,28 @@ struct Launch {
   // Part 1: kinematics, inverse dynamics, mass matrix. Part 2: forward dynamics
   // and the packed forward-dynamics and inverse-dynamics launches. Part 3: the
   // adjoint and its packed launch. Part 4: the articulated-body algorithm.
-  // Each part is its own translation unit and instantiates only its own
-  // kernels.
+  // Part 5: the external-force variants of inverse and forward dynamics. Each
+  // part is its own translation unit and instantiates only its own kernels.
   template <int K>
   static LaunchTable part() {
     LaunchTable t{};
     if constexpr (K == 1) {
       t.fk = &Launch::fk;
       t.jacobian = &Launch::jacobian;
-      t.rnea = &Launch::rnea;
+      t.rnea = &Launch::rnea_t<false>;
       t.crba = &Launch::crba;
     } else if constexpr (K == 2) {
-      t.fwd_dyn = &Launch::fwd_dyn;
+      t.fwd_dyn = &Launch::fwd_dyn_t<false>;
       t.packed = &Launch::packed;
     } else if constexpr (K == 3) {
       t.vjp = &Launch::vjp;
       t.packed_vjp = &Launch::packed_vjp;
+    } else if constexpr (K == 4) {
+      t.aba = &Launch::aba_t<false>;
     } else {
-      t.aba = &Launch::aba;
+      t.rnea_ext = &Launch::rnea_t<true>;
+      t.fwd_dyn_ext = &Launch::fwd_dyn_t<true>;
+      t.aba_ext = &Launch::aba_t<true>;
     }
     return t;
   }

@@ -367,6 +367,42 @@ struct OutRow {
   RBD_DI void operator()(int c, float v) const { p[c] = v; }
 };
 
+// =================================================================== external forces
+// Per-body external spatial forces (the F_ext input of Alg. 1), given in world
+// axes as [force f; moment n about the world origin], coordinate 6 i + c of
+// the lane's instance. NoFext compiles every use away.
+struct NoFext {
+  static constexpr bool kOn = false;
+  RBD_DI float operator()(int) const { return 0.0f; }
+};
+struct FextIn : In {
+  static constexpr bool kOn = true;
+};
+
+// World pose of body I's joint-aligned frame from its parent's (Rw, pw) and
+// the joint rotation RI (the base rotation for a free base).
+template <class TP, int I, class QI>
+RBD_DI void world_pose(const float* __restrict__ t, const QI& q, const M3& RI, M3* Rw, V3* pw) {
+  constexpr int P = TP::parent(I);
+  if constexpr (TP::free_body(I)) {
+    Rw[I] = RI;
+    pw[I] = {q(0), q(1), q(2)};
+  } else if constexpr (P < 0) {
+    Rw[I] = RI;
+    pw[I] = load_r<I>(t);
+  } else {
+    Rw[I] = mulMM(Rw[P], RI);
+    pw[I] = mul_add(Rw[P], load_r<I>(t), pw[P]);
+  }
+}
+// Body I's external force in its own frame: [R^T (n - p x f); R^T f].
+template <int I, class FX>
+RBD_DI Frc fext_body(const FX& fx, const M3& Rw, V3 pw) {
+  const V3 f = {fx(6 * I), fx(6 * I + 1), fx(6 * I + 2)};
+  const V3 n = {fx(6 * I + 3), fx(6 * I + 4), fx(6 * I + 5)};
+  return {mulT(Rw, cross_add(f, pw, n)), mulT(Rw, f)};
+}
+
 // =================================================================== FK
 // World pose of every body in the user's body axes: [R | p] row-major.
 template <class TP, class QI, class TO>
@@ -467,12 +503,16 @@ RBD_DI void jac_lane(const float* __restrict__ t, const QI& q, const JacSlots& j
 }
 
 // =================================================================== RNEA
-// tau = ID(q, qd, qdd); qdd may be absent (bias force). Depth-first: the
-// backward step of a body runs as soon as its subtree is done, so only the
-// current root path is live.
-template <class TP, bool HAS_QDD, class QI, class QDI, class QDDI, class TO>
-RBD_DI void rnea_lane(const float* __restrict__ t, const QI& q, const QDI& qd, const QDDI& qdd, const TO& tau) {
+// tau = ID(q, qd, qdd) - sum_i J_i^T F_ext,i; qdd may be absent (bias force),
+// external forces too (NoFext). Depth-first: the backward step of a body runs
+// as soon as its subtree is done, so only the current root path is live.
+template <class TP, bool HAS_QDD, class QI, class QDI, class QDDI, class TO, class FX = NoFext>
+RBD_DI void rnea_lane(const float* __restrict__ t, const QI& q, const QDI& qd, const QDDI& qdd, const TO& tau,
+                      const FX& fx = FX{}) {
   constexpr int N = TP::N;
+  constexpr int NW = FX::kOn ? N : 1;
+  M3 Rw[NW];
+  V3 pw[NW];
   M3 R[N];
   Mot v[N], a[N];
   Frc f[N];
@@ -520,6 +560,10 @@ RBD_DI void rnea_lane(const float* __restrict__ t, const QI& q, const QDI& qd, c
     }
     const Inr Ib = load_inr<I>(t);
     f[I] = imul(Ib, a[I]) + crf(v[I], imul(Ib, v[I]));
+    if constexpr (FX::kOn) {
+      world_pose<TP, I>(t, q, R[I], Rw, pw);
+      f[I] = f[I] - fext_body<I>(fx, Rw[I], pw[I]);
+    }
     // close every subtree that ends at I, deepest first
     close_subtrees<TP, I, I>(backward);
   });
@@ -606,7 +650,8 @@ RBD_DI void crba_lane(const float* __restrict__ t, const QI& q, float* __restric
 
 // =================================================================== forward dynamics
 // qdd = M^-1 (tau - h) for NRHS right-hand sides (the second one, when asked,
-// is an extra vector solved with the same factor). One depth-first sweep runs
+// is an extra vector solved with the same factor); with external forces h
+// includes -sum_i J_i^T F_ext,i. One depth-first sweep runs
 // the RNEA forward step (bias accelerations and forces) on the way down; each
 // closed subtree then does, leaves to root:
 //   h_k = S^T f, f_parent += X^T f                       (RNEA backward)
@@ -614,9 +659,13 @@ RBD_DI void crba_lane(const float* __restrict__ t, const QI& q, float* __restric
 //   row k of the factor M = L^T L (left-looking, branch-sparse: entries only
 //   for ancestors, no fill-in), and y_k of L^T y = b      (sparse Cholesky)
 // and a final root-to-leaves sweep solves L x = y.
-template <class TP, int NRHS, class QI, class QDI, class RHS, class SINK>
-RBD_DI void fwd_dyn_lane(const float* __restrict__ t, const QI& q, const QDI& qd, const RHS& rhs, const SINK& sink) {
+template <class TP, int NRHS, class QI, class QDI, class RHS, class SINK, class FX = NoFext>
+RBD_DI void fwd_dyn_lane(const float* __restrict__ t, const QI& q, const QDI& qd, const RHS& rhs, const SINK& sink,
+                         const FX& fx = FX{}) {
   constexpr int N = TP::N, NV = TP::NV;
+  constexpr int NW = FX::kOn ? N : 1;
+  M3 Rw[NW];
+  V3 pw[NW];
   constexpr int NNZ = TP::nnz() > 0 ? TP::nnz() : 1;
   M3 R[N];
   Mot v[N], a[N];
@@ -726,6 +775,10 @@ RBD_DI void fwd_dyn_lane(const float* __restrict__ t, const QI& q, const QDI& qd
     }
     const Inr Ib = load_inr<I>(t);
     f[I] = imul(Ib, a[I]) + crf(v[I], imul(Ib, v[I]));
+    if constexpr (FX::kOn) {
+      world_pose<TP, I>(t, q, R[I], Rw, pw);
+      f[I] = f[I] - fext_body<I>(fx, Rw[I], pw[I]);
+    }
     Ic[I] = Ib;
     close_subtrees<TP, I, I>(backward);
   });
@@ -1047,12 +1100,18 @@ RBD_DI Mot ainr_solve(const AInr& I, const Frc& rhs) {
 // acceleration pass (root to leaves) rebuilds X and v from q and qd, which is
 // cheaper than holding them for every body:
 //   a' = X a_parent + c_i,  qdd_i = u/D - (U/D)^T a',  a_i = a' + S qdd_i.
-// Gravity is the fictitious base acceleration -g; a free base solves its 6x6
-// articulated inertia directly. A parent's accumulators start at its first
-// child's contribution, so a chain body holds none while its subtree runs.
-template <class TP, class QI, class QDI, class TI, class QDDO>
-RBD_DI void aba_lane(const float* __restrict__ t, const QI& q, const QDI& qd, const TI& tau, const QDDO& qdd) {
+// Gravity is the fictitious base acceleration -g; external forces are
+// subtracted from pA; a free base solves its 6x6 articulated inertia
+// directly. A parent's accumulators start at its first child's contribution,
+// so a chain body holds none while its subtree runs.
+template <class TP, class QI, class QDI, class TI, class QDDO, class FX = NoFext>
+RBD_DI void aba_lane(const float* __restrict__ t, const QI& q, const QDI& qd, const TI& tau, const QDDO& qdd,
+                     const FX& fx = FX{}) {
   constexpr int N = TP::N;
+  constexpr int NW = FX::kOn ? N : 1;
+  M3 Rw[NW];
+  V3 pw[NW];
+  Frc fe[NW];  // external force in body coordinates, subtracted from pA
   float cq[N], sq[N];
   Mot v[N];
   Frc Ud[N];
@@ -1068,7 +1127,8 @@ RBD_DI void aba_lane(const float* __restrict__ t, const QI& q, const QDI& qd, co
     constexpr int P = TP::parent(J);
     constexpr bool kKids = TP::last(J) > J;
     const Inr Ib = load_inr<J>(t);
-    const Frc bias = crf(v[J], imul(Ib, v[J]));
+    Frc bias = crf(v[J], imul(Ib, v[J]));
+    if constexpr (FX::kOn) bias = bias - fe[J];
     AInr IA;
     Frc pA;
     if constexpr (kKids) {
@@ -1133,17 +1193,20 @@ RBD_DI void aba_lane(const float* __restrict__ t, const QI& q, const QDI& qd, co
     constexpr int P = TP::parent(I);
     if constexpr (TP::free_body(I)) {
       v[I] = {{qd(3), qd(4), qd(5)}, {qd(0), qd(1), qd(2)}};
+      if constexpr (FX::kOn) world_pose<TP, I>(t, q, quat_rot(q(3), q(4), q(5), q(6)), Rw, pw);
     } else {
       fsincos(q(cidx<TP::qofs(I)>), sq[I], cq[I]);
       const float w = qd(cidx<TP::vofs(I)>);
+      const M3 RI = joint_rot_cs<I>(t, cq[I], sq[I]);
       if constexpr (P < 0) {
         v[I] = {{0.0f, 0.0f, w}, {0.0f, 0.0f, 0.0f}};
       } else {
-        const M3 RI = joint_rot_cs<I>(t, cq[I], sq[I]);
         v[I] = xmot(RI, load_r<I>(t), v[P]);
         v[I].w.z = v[I].w.z + w;
       }
+      if constexpr (FX::kOn) world_pose<TP, I>(t, q, RI, Rw, pw);
     }
+    if constexpr (FX::kOn) fe[I] = fext_body<I>(fx, Rw[I], pw[I]);
     close_subtrees<TP, I, I>(close);
   });
 

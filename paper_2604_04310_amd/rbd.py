@@ -83,10 +83,10 @@ def lib():
         L.rbd_model_topology.restype = C.c_char_p
         L.rbd_fk.argtypes = [vp, i64, i64, vp, vp, vp]
         L.rbd_jacobian.argtypes = [vp, i64, i64, vp, i32, P(C.c_int32), vp, vp]
-        L.rbd_rnea.argtypes = [vp, i64, i64, vp, vp, vp, vp, vp]
+        L.rbd_rnea.argtypes = [vp, i64, i64, vp, vp, vp, vp, vp, vp]
         L.rbd_crba.argtypes = [vp, i64, i64, vp, vp, vp]
-        L.rbd_fwd_dyn.argtypes = [vp, i64, i64, vp, vp, vp, vp, vp]
-        L.rbd_aba.argtypes = [vp, i64, i64, vp, vp, vp, vp, vp]
+        L.rbd_fwd_dyn.argtypes = [vp, i64, i64, vp, vp, vp, vp, vp, vp]
+        L.rbd_aba.argtypes = [vp, i64, i64, vp, vp, vp, vp, vp, vp]
         L.rbd_fwd_dyn_vjp.argtypes = [vp, i64, i64, vp, vp, vp, vp, vp, vp, vp, vp]
         L.rbd_status_str.argtypes = [C.c_int]
         L.rbd_status_str.restype = C.c_char_p
@@ -232,8 +232,11 @@ def jacobian(model: Model, q, frames: Optional[Sequence[int]] = None):
     return J
 
 
-def rnea(model: Model, q, qd, qdd=None, out=None):
-    """Inverse dynamics tau [nv, B] (Eq. (1)); qdd=None gives the bias force h(q, qd)."""
+def rnea(model: Model, q, qd, qdd=None, out=None, fext=None):
+    """Inverse dynamics tau [nv, B] (Eq. (1)); qdd=None gives the bias force h(q, qd).
+
+    fext: optional [6 * n_bodies, B] external spatial forces, world axes, rows
+    6 i .. 6 i + 5 = force on body i, then its moment about the world origin."""
     qp, B, l1 = _soa(q, model.nq, "q")
     qdp, _, l2 = _soa(qd, model.nv, "qd", B)
     lds = [l1, l2]
@@ -241,10 +244,14 @@ def rnea(model: Model, q, qd, qdd=None, out=None):
     if qdd is not None:
         qddp, _, l3 = _soa(qdd, model.nv, "qdd", B)
         lds.append(l3)
+    fp = None
+    if fext is not None:
+        fp, _, l5 = _soa(fext, 6 * model.n_bodies, "fext", B)
+        lds.append(l5)
     tau = _out(model.nv, B, q) if out is None else out
     tp, _, l4 = _soa(tau, model.nv, "tau", B)
     ld = _same_ld(*lds, l4)
-    check(lib().rbd_rnea(model.handle, B, ld, qp, qdp, qddp, tp, _stream()))
+    check(lib().rbd_rnea(model.handle, B, ld, qp, qdp, qddp, fp, tp, _stream()))
     return tau
 
 
@@ -258,28 +265,30 @@ def crba(model: Model, q):
     return M
 
 
-def fwd_dyn(model: Model, q, qd, tau, out=None):
-    """Forward dynamics qdd [nv, B] (Eq. (2))."""
+def _fd(fn, model: Model, q, qd, tau, out, fext):
     qp, B, l1 = _soa(q, model.nq, "q")
     qdp, _, l2 = _soa(qd, model.nv, "qd", B)
     taup, _, l3 = _soa(tau, model.nv, "tau", B)
+    lds = [l1, l2, l3]
+    fp = None
+    if fext is not None:
+        fp, _, l5 = _soa(fext, 6 * model.n_bodies, "fext", B)
+        lds.append(l5)
     qdd = _out(model.nv, B, q) if out is None else out
     op, _, l4 = _soa(qdd, model.nv, "qdd", B)
-    ld = _same_ld(l1, l2, l3, l4)
-    check(lib().rbd_fwd_dyn(model.handle, B, ld, qp, qdp, taup, op, _stream()))
+    ld = _same_ld(*lds, l4)
+    check(fn(model.handle, B, ld, qp, qdp, taup, fp, op, _stream()))
     return qdd
 
 
-def aba(model: Model, q, qd, tau, out=None):
+def fwd_dyn(model: Model, q, qd, tau, out=None, fext=None):
+    """Forward dynamics qdd [nv, B] (Eq. (2)); fext as for rnea."""
+    return _fd(lib().rbd_fwd_dyn, model, q, qd, tau, out, fext)
+
+
+def aba(model: Model, q, qd, tau, out=None, fext=None):
     """Forward dynamics qdd [nv, B] by the articulated-body algorithm (same result as fwd_dyn)."""
-    qp, B, l1 = _soa(q, model.nq, "q")
-    qdp, _, l2 = _soa(qd, model.nv, "qd", B)
-    taup, _, l3 = _soa(tau, model.nv, "tau", B)
-    qdd = _out(model.nv, B, q) if out is None else out
-    op, _, l4 = _soa(qdd, model.nv, "qdd", B)
-    ld = _same_ld(l1, l2, l3, l4)
-    check(lib().rbd_aba(model.handle, B, ld, qp, qdp, taup, op, _stream()))
-    return qdd
+    return _fd(lib().rbd_aba, model, q, qd, tau, out, fext)
 
 
 def fwd_dyn_vjp(model: Model, q, qd, tau, g_qdd, want=(True, True, True)):

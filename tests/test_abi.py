@@ -101,9 +101,10 @@ def test_valid_model_without_device(rbd):
 
 def test_null_model_calls(rbd):
     L = rbd.lib()
-    assert L.rbd_fwd_dyn(None, 1, 1, None, None, None, None, None) == 1
+    assert L.rbd_fwd_dyn(None, 1, 1, None, None, None, None, None, None) == 1
     assert b"model is NULL" in L.rbd_last_error()
-    assert L.rbd_aba(None, 1, 1, None, None, None, None, None) == 1
+    assert L.rbd_aba(None, 1, 1, None, None, None, None, None, None) == 1
+    assert L.rbd_rnea(None, 1, 1, None, None, None, None, None, None) == 1
     assert b"model is NULL" in L.rbd_last_error()
 
 

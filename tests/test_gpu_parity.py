@@ -143,6 +143,47 @@ def test_fwd_dyn_vjp_parity(rbd, name):
     assert np.array_equal(host(gqd2), host(gqd)) and np.array_equal(host(gtau2), host(gtau))
 
 
+@pytest.mark.parametrize("name", list(MODELS))
+def test_external_force_parity(rbd, name):
+    """rnea, fwd_dyn and aba with per-body external forces (world axes) against the oracle."""
+    desc, m = model_of(rbd, name)
+    st = W.states(desc, BATCH, 220)
+    rng = np.random.Generator(np.random.PCG64(221))
+    fext = W._f32(rng.normal(0.0, 5.0, size=(BATCH, desc.n_bodies, 6)))
+    fx = gpu(fext.reshape(BATCH, -1))
+    qdd_in = W.cotangent(desc.nv, BATCH, 222) * 3.0
+    tau = host(rbd.rnea(m, gpu(st.q), gpu(st.qd), gpu(qdd_in), fext=fx))
+    assert rel_err(tau, O.rnea(desc, st.q, st.qd, qdd_in, fext=fext)) < TOL_TAU
+    h = host(rbd.rnea(m, gpu(st.q), gpu(st.qd), fext=fx))
+    assert rel_err(h, O.rnea(desc, st.q, st.qd, fext=fext)) < TOL_TAU
+    ref = O.fwd_dyn(desc, st.q, st.qd, st.tau, fext=fext)
+    assert rel_err(host(rbd.fwd_dyn(m, gpu(st.q), gpu(st.qd), gpu(st.tau), fext=fx)), ref) < TOL_QDD
+    assert rel_err(host(rbd.aba(m, gpu(st.q), gpu(st.qd), gpu(st.tau), fext=fx)), ref) < TOL_QDD
+
+
+def test_external_weight_support_on_gpu(rbd):
+    """Weight-supporting external forces at every CoM: zero holding torque and, with zero torque and
+    velocity, zero acceleration by both forward-dynamics kernels."""
+    desc, m = model_of(rbd, "humanoid30")
+    B = 256
+    st = W.states(desc, B, 223)
+    T = O.fk(desc, st.q)
+    c = T[..., :, 3] + np.einsum("bnij,nj->bni", T[..., :, :3], desc.com)
+    f = -desc.mass[None, :, None] * np.asarray(desc.gravity)[None, None, :]
+    fext = np.concatenate([np.broadcast_to(f, c.shape), np.cross(c, f)], axis=2)
+    fx = gpu(fext.reshape(B, -1))
+    zero = np.zeros((B, desc.nv))
+    g_scale = np.abs(O.rnea(desc, st.q, zero)).max()
+    tau = host(rbd.rnea(m, gpu(st.q), gpu(zero), fext=fx))
+    assert np.abs(tau).max() < 1e-4 * g_scale
+    # the accelerations that cancel are those of the unsupported robot; they vanish to the tolerance
+    # of the parity tests relative to that scale
+    a_scale = np.abs(O.fwd_dyn(desc, st.q, zero, zero)).max()
+    for fn in (rbd.fwd_dyn, rbd.aba):
+        qdd = host(fn(m, gpu(st.q), gpu(zero), gpu(zero), fext=fx))
+        assert np.abs(qdd).max() < TOL_QDD * a_scale
+
+
 # ---------------------------------------------------------------- layout and edge cases
 def test_leading_dimension_larger_than_batch(rbd):
     desc, m = model_of(rbd, "humanoid30")
