@@ -63,6 +63,7 @@ def lib():
         L.orc_crba.argtypes = [m, i64, d, d]
         L.orc_fwd_dyn.argtypes = [m, i64, d, d, d, d, C.c_int]
         L.orc_fwd_dyn_vjp_fd.argtypes = [m, i64, d, d, d, d, d, d, d, C.c_double, C.c_int]
+        L.orc_fwd_dyn_jvp_fd.argtypes = [m, i64, d, d, d, d, d, d, d, C.c_double, C.c_int]
         L.orc_count_ops.argtypes = [m, C.c_int, P(C.c_longlong)]
         L.orc_max_threads.argtypes = []
         _lib = L
@@ -178,6 +179,15 @@ def fwd_dyn_vjp_fd(desc, q, qd, tau, gbar, h=1e-6, method=METHOD_LTL):
     _check(lib().orc_fwd_dyn_vjp_fd(C.byref(_model(desc)), q.shape[0], _dp(q), _dp(qd), _dp(tau), _dp(gbar),
                                     _dp(gq), _dp(gqd), _dp(gtau), h, method), "vjp")
     return gq, gqd, gtau
+
+
+def fwd_dyn_jvp_fd(desc, q, qd, tau, dq, dqd, dtau, h=1e-6, method=METHOD_LTL):
+    """d qdd along (dq, dqd, dtau): one central difference of step h of forward dynamics."""
+    q, qd, tau, dq, dqd, dtau = _c(q), _c(qd), _c(tau), _c(dq), _c(dqd), _c(dtau)
+    dqdd = np.empty_like(qd)
+    _check(lib().orc_fwd_dyn_jvp_fd(C.byref(_model(desc)), q.shape[0], _dp(q), _dp(qd), _dp(tau), _dp(dq),
+                                    _dp(dqd), _dp(dtau), _dp(dqdd), h, method), "jvp")
+    return dqdd
 
 
 OPS = {"fk": 0, "jacobian": 1, "rnea": 2, "rnea_bias": 3, "crba": 4, "fwd_dyn_llt": 5, "fwd_dyn_ltl": 6, "aba": 7}

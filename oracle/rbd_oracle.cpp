@@ -770,6 +770,35 @@ int orc_fwd_dyn_ext(const orc_model* d, int64_t B, const double* q, const double
   return 0;
 }
 
+// Jacobian-vector product of qdd = FD(q, qd, tau) along the tangent (dq, dqd,
+// dtau), the directional derivative by one central difference of step h:
+// [FD(x + h dx) - FD(x - h dx)] / 2h (raw quaternion components are moved
+// like any other coordinate).
+int orc_fwd_dyn_jvp_fd(const orc_model* d, int64_t B, const double* q, const double* qd, const double* tau,
+                       const double* dq, const double* dqd, const double* dtau, double* dqdd, double h, int method) {
+  Model M;
+  if (build_model(d, M) || method < 0 || method > 2) return 1;
+  const int nq = M.nq, nv = M.nv;
+#pragma omp parallel for schedule(static)
+  for (int64_t b = 0; b < B; ++b) {
+    std::vector<double> xp(nq), xm(nq), yp(nv), ym(nv), zp(nv), zm(nv), ap(nv), am(nv);
+    for (int k = 0; k < nq; ++k) {
+      xp[k] = q[b * nq + k] + h * dq[b * nq + k];
+      xm[k] = q[b * nq + k] - h * dq[b * nq + k];
+    }
+    for (int k = 0; k < nv; ++k) {
+      yp[k] = qd[b * nv + k] + h * dqd[b * nv + k];
+      ym[k] = qd[b * nv + k] - h * dqd[b * nv + k];
+      zp[k] = tau[b * nv + k] + h * dtau[b * nv + k];
+      zm[k] = tau[b * nv + k] - h * dtau[b * nv + k];
+    }
+    fwd_dyn(M, xp.data(), yp.data(), zp.data(), ap.data(), method);
+    fwd_dyn(M, xm.data(), ym.data(), zm.data(), am.data(), method);
+    for (int k = 0; k < nv; ++k) dqdd[b * nv + k] = (ap[k] - am[k]) / (2.0 * h);
+  }
+  return 0;
+}
+
 // Vector-Jacobian product of qdd = FD(q, qd, tau) with cotangent gbar, by
 // central differences of step h on every coordinate (raw quaternion
 // components included). Any output may be null.

@@ -422,3 +422,51 @@ def test_free_body_force_through_com_closed_form():
     zero = np.zeros((B, 6))
     for method in (O.METHOD_LLT, O.METHOD_LTL, O.METHOD_ABA):
         assert np.allclose(O.fwd_dyn(d, st.q, zero, zero, method, fext=fext), ref, rtol=1e-11, atol=1e-11)
+
+
+# ---------------------------------------------------------------- forward-mode derivative (jax.jvp, Sec. IV-A)
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_jvp_single_pendulum_closed_form(seed):
+    """qdd = (tau - G(q)) / M with constant M and G(q) = dV/dq: d qdd = (dtau - G'(q) dq) / M, where
+    G'(q) follows from d/dq R(q) c = a x R(q) c; qd does not enter."""
+    d, rng = _single_body(seed)
+    a = d.axis[0] / np.linalg.norm(d.axis[0])
+    c, m = d.com[0], d.mass[0]
+    Rf = d.origin[0, :9].reshape(3, 3)
+    M_ref = a @ inertia_matrix(d, 0) @ a + m * np.dot(np.cross(a, c), np.cross(a, c))
+    B = 16
+    q, qd, tau = rng.uniform(-np.pi, np.pi, (B, 1)), rng.normal(size=(B, 1)), rng.normal(0, 5, (B, 1))
+    dq, dqd, dtau = rng.normal(size=(B, 1)), rng.normal(size=(B, 1)), rng.normal(size=(B, 1))
+    lever = np.einsum("bij,j->bi", Rotation.from_rotvec(a[None, :] * q).as_matrix(), c)
+    dG = -m * np.einsum("i,ij,bj->b", d.gravity, Rf, np.cross(a[None, :], np.cross(a[None, :], lever)))
+    ref = (dtau[:, 0] - dG * dq[:, 0]) / M_ref
+    # a central difference of step 1e-6 carries rounding of about eps |qdd| / h ~ 1e-9 |qdd|
+    for method in (O.METHOD_LLT, O.METHOD_LTL, O.METHOD_ABA):
+        assert np.allclose(O.fwd_dyn_jvp_fd(d, q, qd, tau, dq, dqd, dtau, method=method)[:, 0], ref,
+                           rtol=1e-7, atol=1e-7)
+
+
+@pytest.mark.parametrize("name", ["chain7", "humanoid30"])
+def test_jvp_is_dual_to_vjp(name):
+    """<gbar, J dx> = <J^T gbar, dx> between the two difference formulas (each to O(h^2))."""
+    desc = W.chain(7) if name == "chain7" else W.humanoid()
+    B = 8
+    st = W.states(desc, B, 46)
+    rng = np.random.Generator(np.random.PCG64(47))
+    dq, dqd, dtau = rng.normal(size=st.q.shape), rng.normal(size=st.qd.shape), rng.normal(size=st.tau.shape)
+    gbar = W.cotangent(desc.nv, B, 48)
+    jv = O.fwd_dyn_jvp_fd(desc, st.q, st.qd, st.tau, dq, dqd, dtau)
+    gq, gqd, gtau = O.fwd_dyn_vjp_fd(desc, st.q, st.qd, st.tau, gbar)
+    lhs = np.einsum("bk,bk->b", gbar, jv)
+    rhs = np.einsum("bk,bk->b", gq, dq) + np.einsum("bk,bk->b", gqd, dqd) + np.einsum("bk,bk->b", gtau, dtau)
+    assert np.allclose(lhs, rhs, rtol=1e-6, atol=1e-6 * np.abs(rhs).max())
+
+
+def test_jvp_tau_direction_is_inverse_mass_matrix():
+    """Along (0, 0, dtau) the derivative is M^-1 dtau exactly (forward dynamics is affine in tau)."""
+    desc = W.humanoid()
+    B = 8
+    st = W.states(desc, B, 49)
+    dtau = W.cotangent(desc.nv, B, 50)
+    jv = O.fwd_dyn_jvp_fd(desc, st.q, st.qd, st.tau, np.zeros_like(st.q), np.zeros_like(st.qd), dtau)
+    assert rel_err(jv, np.linalg.solve(O.crba(desc, st.q), dtau[..., None])[..., 0]) < 1e-7
