@@ -305,6 +305,15 @@ def main():
     vq, vqd, vtau = q[:, :Bv].contiguous(), qd[:, :Bv].contiguous(), tau[:, :Bv].contiguous()
     ops["fwd_dyn_vjp_humanoid30_b32768_us"] = 1e3 * time_launches(
         lambda: rbd.fwd_dyn_vjp(model, vq, vqd, vtau, gq), n_t, torch)
+    tq, tqd, ttau = (soa(W._f32(np.random.default_rng(s).normal(size=(Bv, r))), torch)
+                     for s, r in ((11, desc.nq), (12, desc.nv), (13, desc.nv)))
+    ops["fwd_dyn_jvp_humanoid30_b32768_us"] = 1e3 * time_launches(
+        lambda: rbd.fwd_dyn_jvp(model, vq, vqd, vtau, tq, tqd, ttau), n_t, torch)
+    del tq, tqd, ttau
+    fx = soa(W._f32(np.random.default_rng(14).normal(0.0, 5.0, size=(BATCH, 6 * desc.n_bodies))), torch)
+    ops["fwd_dyn_fext_humanoid30_b65536_us"] = 1e3 * time_launches(
+        lambda: rbd.fwd_dyn(model, q, qd, tau, fext=fx), n_t, torch)
+    del fx
     chain = W.chain(7)
     cm = rbd.Model(chain, 0)
     cs = W.states(chain, 1 << 20, 102)

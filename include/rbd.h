@@ -14,8 +14,9 @@
  *   rbd_fwd_dyn      forward dynamics qdd = M^-1 (tau - h + J^T F_ext), Eq. (2), by a
  *                    per-instance Cholesky-type solve (Sec. V, footnote)
  *   rbd_aba          the same forward dynamics by the articulated-body
- *                    algorithm, O(n), no mass matrix (Sec. III, named there as
- *                    a Featherstone algorithm; Sec. VI, future work)
+ *                    algorithm, O(n), no mass matrix (Sec. II names it among
+ *                    Featherstone's algorithms; Sec. VI-A, future work)
+ *   rbd_fwd_dyn_jvp  forward-mode derivative of rbd_fwd_dyn (Sec. IV-A, Fig. 2)
  *   rbd_fwd_dyn_vjp  reverse-mode derivative of rbd_fwd_dyn (Sec. I, AD)
  *   rbd_server_*     continuous-batching service for the above (host API)
  *
@@ -148,6 +149,18 @@ rbd_status rbd_fwd_dyn(const rbd_model* model, int64_t batch, int64_t ld, const 
  * A non-positive articulated pivot yields NaN in that instance. */
 rbd_status rbd_aba(const rbd_model* model, int64_t batch, int64_t ld, const float* q, const float* qd,
                    const float* tau, const float* f_ext, float* qdd, hipStream_t stream);
+
+/* Jacobian-vector product of rbd_fwd_dyn without external forces (forward-mode
+ * AD, Sec. IV-A and Fig. 2): for tangents dq [nq][ld] (raw quaternion
+ * components included; a free base's position does not change qdd), dqd and
+ * dtau [nv][ld], dqdd = dqdd/dq dq + dqdd/dqd dqd + M^-1 dtau [nv][ld]. Computed
+ * as M^-1 (dtau - dID/dq dq - dID/dqd dqd) at qdd = FD(q, qd, tau): the fused
+ * forward dynamics, then one sweep of tangent inverse dynamics feeding the
+ * same factorisation. qdd (nullable) also receives the forward dynamics. All
+ * inputs are required. */
+rbd_status rbd_fwd_dyn_jvp(const rbd_model* model, int64_t batch, int64_t ld, const float* q, const float* qd,
+                           const float* tau, const float* dq, const float* dqd, const float* dtau, float* qdd,
+                           float* dqdd, hipStream_t stream);
 
 /* Vector-Jacobian product of rbd_fwd_dyn without external forces, for the
  * cotangent g_qdd [nv][ld]:

@@ -334,6 +334,17 @@ rbd_status rbd_aba(const rbd_model* m, int64_t batch, int64_t ld, const float* q
   return launch_aba(m, batch, ld, q, qd, tau, f_ext, qdd, s);
 }
 
+rbd_status rbd_fwd_dyn_jvp(const rbd_model* m, int64_t batch, int64_t ld, const float* q, const float* qd,
+                           const float* tau, const float* dq, const float* dqd, const float* dtau, float* qdd,
+                           float* dqdd, hipStream_t s) {
+  rbd_status st = check_batch(m, batch, ld, "rbd_fwd_dyn_jvp");
+  if (st != RBD_OK) return st;
+  if (batch > 0 && (!q || !qd || !tau || !dq || !dqd || !dtau || !dqdd))
+    return fail(RBD_E_INVAL, "rbd_fwd_dyn_jvp: NULL array");
+  if ((st = use_device(m->device)) != RBD_OK) return st;
+  return launch_fwd_dyn_jvp(m, batch, ld, q, qd, tau, dq, dqd, dtau, qdd, dqdd, s);
+}
+
 rbd_status rbd_fwd_dyn_vjp(const rbd_model* m, int64_t batch, int64_t ld, const float* q, const float* qd,
                            const float* tau, const float* g_qdd, float* g_q, float* g_qd, float* g_tau,
                            hipStream_t s) {

@@ -13,7 +13,7 @@ namespace rbd {
 
 #define RBD_DECL(name, fr, ...) \
   extern const LaunchTable launch_table_##name##_p1, launch_table_##name##_p2, launch_table_##name##_p3, \
-      launch_table_##name##_p4, launch_table_##name##_p5;
+      launch_table_##name##_p4, launch_table_##name##_p5, launch_table_##name##_p6;
 RBD_TOPOLOGIES(RBD_DECL)
 #undef RBD_DECL
 
@@ -27,23 +27,23 @@ static const TopoInfo k_topos[] = {
 #undef RBD_INFO
 };
 
-static const LaunchTable* const k_parts[][5] = {
+static const LaunchTable* const k_parts[][6] = {
 #define RBD_TAB(name, fr, ...)                                                                                  \
   {&launch_table_##name##_p1, &launch_table_##name##_p2, &launch_table_##name##_p3, &launch_table_##name##_p4, \
-   &launch_table_##name##_p5},
+   &launch_table_##name##_p5, &launch_table_##name##_p6},
     RBD_TOPOLOGIES(RBD_TAB)
 #undef RBD_TAB
 };
 
-// The five parts of a topology merged into one table (built on first use).
+// The six parts of a topology merged into one table (built on first use).
 static const LaunchTable* merged(int id) {
   static const std::vector<LaunchTable> all = [] {
     std::vector<LaunchTable> v(sizeof(k_parts) / sizeof(k_parts[0]));
     for (size_t i = 0; i < v.size(); ++i) {
       const LaunchTable &a = *k_parts[i][0], &b = *k_parts[i][1], &c = *k_parts[i][2], &d = *k_parts[i][3],
-                        &e = *k_parts[i][4];
-      v[i] = LaunchTable{a.fk,   a.jacobian,   a.rnea,        a.crba,        b.fwd_dyn,  c.vjp,
-                         d.aba,  b.packed,     c.packed_vjp,  e.rnea_ext,    e.fwd_dyn_ext, e.aba_ext};
+                        &e = *k_parts[i][4], &f = *k_parts[i][5];
+      v[i] = LaunchTable{a.fk,  a.jacobian, a.rnea,       a.crba,     b.fwd_dyn,     c.vjp,     d.aba,
+                         b.packed, c.packed_vjp, e.rnea_ext, e.fwd_dyn_ext, e.aba_ext, f.jvp};
     }
     return v;
   }();
@@ -129,6 +129,14 @@ rbd_status launch_aba(const rbd_model* m, int64_t batch, int64_t ld, const float
   if (batch == 0) return RBD_OK;
   RBD_TABLE_OR_FAIL(m);
   return (fext ? lt->aba_ext : lt->aba)(m->d_tab, batch, ld, q, qd, tau, fext, qdd, s);
+}
+
+rbd_status launch_fwd_dyn_jvp(const rbd_model* m, int64_t batch, int64_t ld, const float* q, const float* qd,
+                              const float* tau, const float* dq, const float* dqd, const float* dtau, float* qdd,
+                              float* dqdd, hipStream_t s) {
+  if (batch == 0) return RBD_OK;
+  RBD_TABLE_OR_FAIL(m);
+  return lt->jvp(m->d_tab, batch, ld, q, qd, tau, dq, dqd, dtau, qdd, dqdd, s);
 }
 
 rbd_status launch_fwd_dyn_vjp(const rbd_model* m, int64_t batch, int64_t ld, const float* q, const float* qd,

@@ -55,6 +55,9 @@ rbd_status launch_fwd_dyn(const rbd_model* m, int64_t batch, int64_t ld, const f
                           const float* tau, const float* fext, float* qdd, hipStream_t s);
 rbd_status launch_aba(const rbd_model* m, int64_t batch, int64_t ld, const float* q, const float* qd,
                       const float* tau, const float* fext, float* qdd, hipStream_t s);
+rbd_status launch_fwd_dyn_jvp(const rbd_model* m, int64_t batch, int64_t ld, const float* q, const float* qd,
+                              const float* tau, const float* dq, const float* dqd, const float* dtau, float* qdd,
+                              float* dqdd, hipStream_t s);
 rbd_status launch_fwd_dyn_vjp(const rbd_model* m, int64_t batch, int64_t ld, const float* q, const float* qd,
                               const float* tau, const float* gqdd, float* gq, float* gqd, float* gtau,
                               hipStream_t s);
@@ -80,6 +83,8 @@ struct LaunchTable {
   RneaFn rnea_ext;  // with external forces (fext non-null)
   FdFn fwd_dyn_ext;
   FdFn aba_ext;
+  rbd_status (*jvp)(const float* tab, int64_t batch, int64_t ld, const float* q, const float* qd, const float* tau,
+                    const float* dq, const float* dqd, const float* dtau, float* qdd, float* dqdd, hipStream_t s);
 };
 
 // Packed serving launch of one (model, op): d_table holds a PackedHdr-led

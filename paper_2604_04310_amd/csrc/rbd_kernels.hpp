@@ -235,6 +235,25 @@ __global__ __launch_bounds__(kBlock) void k_fwd_dyn_vjp(const float* __restrict_
   }
 }
 
+// ---- fwd_dyn tangent: qdd by the fused solve, parked in the qdd output when
+// one is given (else in dqdd, which the tangent sweep overwrites only after its
+// last read), then the tangent sweep. Neither output is restrict-qualified, so
+// the loads of the parked values stay ordered with the stores.
+template <class TP>
+__global__ __launch_bounds__(kBlock) void k_fwd_dyn_jvp(const float* __restrict__ tab, int64_t batch, int64_t ld,
+                                                        const float* __restrict__ q, const float* __restrict__ qd,
+                                                        const float* __restrict__ tau, const float* __restrict__ dq,
+                                                        const float* __restrict__ dqd,
+                                                        const float* __restrict__ dtau, float* qdd, float* dqdd) {
+  const uint32_t b = lane_id();
+  if (b >= batch) return;
+  float* park = qdd ? qdd : dqdd;
+  const In qi{q, ld, b}, qdi{qd, ld, b};
+  fwd_dyn_lane<TP, 1>(tab, qi, qdi, RhsOne<In>{In{tau, ld, b}}, SinkOne<OutAlias>{OutAlias{park, ld, b}});
+  fwd_dyn_tangent_lane<TP>(tab, qi, qdi, InAlias{park, ld, b}, In{dq, ld, b}, In{dqd, ld, b}, In{dtau, ld, b},
+                           SinkOne<OutAlias>{OutAlias{dqdd, ld, b}});
+}
+
 // ---- packed launch for the serving runtime. One launch serves many requests
 // of one (model, operation): the work is cut into tiles of 64 instances (one
 // wave), every tile belongs to one request, and a fixed grid of waves strides
@@ -347,6 +366,13 @@ struct Launch {
                          batch, ld, q, qd, tau, gqdd, gq, gqd, gtau);
     return check_launch("rbd_fwd_dyn_vjp");
   }
+  static rbd_status jvp(const float* tab, int64_t batch, int64_t ld, const float* q, const float* qd,
+                        const float* tau, const float* dq, const float* dqd, const float* dtau, float* qdd,
+                        float* dqdd, hipStream_t s) {
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_fwd_dyn_jvp<TP>), dim3(grid_for(batch)), dim3(kBlock), 0, s, tab, batch, ld,
+                       q, qd, tau, dq, dqd, dtau, qdd, dqdd);
+    return check_launch("rbd_fwd_dyn_jvp");
+  }
   static rbd_status packed(int op, const float* tab, const void* table, int grid, hipStream_t s) {
     const uint8_t* t = static_cast<const uint8_t*>(table);
     if (op == RBD_OP_FWD_DYN)
@@ -363,8 +389,9 @@ struct Launch {
   // Part 1: kinematics, inverse dynamics, mass matrix. Part 2: forward dynamics
   // and the packed forward-dynamics and inverse-dynamics launches. Part 3: the
   // adjoint and its packed launch. Part 4: the articulated-body algorithm.
-  // Part 5: the external-force variants of inverse and forward dynamics. Each
-  // part is its own translation unit and instantiates only its own kernels.
+  // Part 5: the external-force variants of inverse and forward dynamics. Part
+  // 6: the forward-mode derivative. Each part is its own translation unit and
+  // instantiates only its own kernels.
   template <int K>
   static LaunchTable part() {
     LaunchTable t{};
@@ -381,10 +408,12 @@ struct Launch {
       t.packed_vjp = &Launch::packed_vjp;
     } else if constexpr (K == 4) {
       t.aba = &Launch::aba_t<false>;
-    } else {
+    } else if constexpr (K == 5) {
       t.rnea_ext = &Launch::rnea_t<true>;
       t.fwd_dyn_ext = &Launch::fwd_dyn_t<true>;
       t.aba_ext = &Launch::aba_t<true>;
+    } else {
+      t.jvp = &Launch::jvp;
     }
     return t;
   }

@@ -648,16 +648,114 @@ RBD_DI void crba_lane(const float* __restrict__ t, const QI& q, float* __restric
   });
 }
 
+// =================================================================== branch-sparse L^T L
+// M = L^T L with L lower triangular and, in a depth-first DoF order, nonzero
+// only where M is (an entry per DoF and each of its ancestors: no fill-in).
+// Rows are produced leaves to root, as subtrees close, and the first solve
+// L^T y = b runs alongside for NRHS right-hand sides; a root-to-leaves sweep
+// then solves L x = y.
+template <class TP, int NRHS>
+struct Ltl {
+  static constexpr int NNZ = TP::nnz() > 0 ? TP::nnz() : 1;
+  float L[NNZ];
+  float Linv[TP::NV];
+  float y[NRHS][TP::NV];
+};
+
+// Row K given row K of M (Mr[j] for ancestors j, Mkk) and b_K.
+template <class TP, int K, int NRHS>
+RBD_DI void ltl_row(Ltl<TP, NRHS>& F, const float* Mr, float Mkk, const float* bk) {
+  constexpr int NV = TP::NV;
+  float D = Mkk;
+  sfor<K + 1, NV>([&](auto D_) __attribute__((always_inline)) {
+    constexpr int Dd = decltype(D_)::value;
+    if constexpr (TP::is_danc(K, Dd)) D = D - F.L[cidx<TP::lidx(Dd, K)>] * F.L[cidx<TP::lidx(Dd, K)>];
+  });
+  const float inv = frsq(D);
+  F.Linv[K] = inv;
+  sfor<0, K>([&](auto J_) __attribute__((always_inline)) {
+    constexpr int Jd = decltype(J_)::value;
+    if constexpr (TP::is_danc(Jd, K)) {
+      float acc = Mr[Jd];
+      sfor<K + 1, NV>([&](auto D_) __attribute__((always_inline)) {
+        constexpr int Dd = decltype(D_)::value;
+        if constexpr (TP::is_danc(K, Dd)) acc = acc - F.L[cidx<TP::lidx(Dd, K)>] * F.L[cidx<TP::lidx(Dd, Jd)>];
+      });
+      F.L[cidx<TP::lidx(K, Jd)>] = acc * inv;
+    }
+  });
+  sfor<0, NRHS>([&](auto R_) __attribute__((always_inline)) {
+    constexpr int r = decltype(R_)::value;
+    float acc = bk[r];
+    sfor<K + 1, NV>([&](auto D_) __attribute__((always_inline)) {
+      constexpr int Dd = decltype(D_)::value;
+      if constexpr (TP::is_danc(K, Dd)) acc = acc - F.L[cidx<TP::lidx(Dd, K)>] * F.y[r][Dd];
+    });
+    F.y[r][K] = acc * inv;
+  });
+}
+
+// The six rows of a free base from its composite inertia; bk(r, K) gives the
+// right-hand sides (base DoFs in [v; w] order).
+template <class TP, int NRHS, class BK>
+RBD_DI void ltl_base_rows(Ltl<TP, NRHS>& F, const Inr& Ic, const BK& bk) {
+  sfor_rev<0, 6>([&](auto K_) __attribute__((always_inline)) {
+    constexpr int K = decltype(K_)::value;
+    float Mr[6];
+#pragma unroll
+    for (int j = 0; j < K; ++j) Mr[j] = base_block(Ic, K, j);
+    float b[NRHS];
+#pragma unroll
+    for (int r = 0; r < NRHS; ++r) b[r] = bk(r, K);
+    ltl_row<TP, K, NRHS>(F, Mr, base_block(Ic, K, K), b);
+  });
+}
+
+// L x = y, root to leaves; sink(r, k, x_k).
+template <class TP, int NRHS, class SINK>
+RBD_DI void ltl_back(const Ltl<TP, NRHS>& F, const SINK& sink) {
+  constexpr int NV = TP::NV;
+  sfor<0, NRHS>([&](auto R_) __attribute__((always_inline)) {
+    constexpr int r = decltype(R_)::value;
+    float x[NV];
+    sfor<0, NV>([&](auto K_) __attribute__((always_inline)) {
+      constexpr int K = decltype(K_)::value;
+      float acc = F.y[r][K];
+      sfor<0, K>([&](auto J_) __attribute__((always_inline)) {
+        constexpr int Jd = decltype(J_)::value;
+        if constexpr (TP::is_danc(Jd, K)) acc = acc - F.L[cidx<TP::lidx(K, Jd)>] * x[Jd];
+      });
+      x[K] = acc * F.Linv[K];
+      sink(r, K, x[K]);
+    });
+  });
+}
+
+// Row of M for revolute body J against its ancestors, into Mr (CRBA: F = Ic S
+// carried up the tree).
+template <class TP, int J>
+RBD_DI void crba_row(const float* __restrict__ t, const M3* R, const Inr& IcJ, float* Mr) {
+  auto emit = [&](auto A_, const Frc& F) __attribute__((always_inline)) {
+    constexpr int A = decltype(A_)::value;
+    if constexpr (TP::free_body(A)) {
+      Mr[0] = F.f.x; Mr[1] = F.f.y; Mr[2] = F.f.z;
+      Mr[3] = F.n.x; Mr[4] = F.n.y; Mr[5] = F.n.z;
+    } else {
+      Mr[cidx<TP::vofs(A)>] = F.n.z;
+    }
+  };
+  walk_up<TP, J>(t, R, inr_col_z(IcJ), emit);
+}
+
 // =================================================================== forward dynamics
 // qdd = M^-1 (tau - h) for NRHS right-hand sides (the second one, when asked,
 // is an extra vector solved with the same factor); with external forces h
-// includes -sum_i J_i^T F_ext,i. One depth-first sweep runs
-// the RNEA forward step (bias accelerations and forces) on the way down; each
-// closed subtree then does, leaves to root:
+// includes -sum_i J_i^T F_ext,i. One depth-first sweep runs the RNEA forward
+// step (bias accelerations and forces) on the way down; each closed subtree
+// then does, leaves to root:
 //   h_k = S^T f, f_parent += X^T f                       (RNEA backward)
 //   row k of M from F = Ic S carried up, Ic_parent += X^T Ic X   (CRBA)
-//   row k of the factor M = L^T L (left-looking, branch-sparse: entries only
-//   for ancestors, no fill-in), and y_k of L^T y = b      (sparse Cholesky)
+//   row k of the factor M = L^T L and y_k of L^T y = b   (sparse Cholesky)
 // and a final root-to-leaves sweep solves L x = y.
 template <class TP, int NRHS, class QI, class QDI, class RHS, class SINK, class FX = NoFext>
 RBD_DI void fwd_dyn_lane(const float* __restrict__ t, const QI& q, const QDI& qd, const RHS& rhs, const SINK& sink,
@@ -666,81 +764,30 @@ RBD_DI void fwd_dyn_lane(const float* __restrict__ t, const QI& q, const QDI& qd
   constexpr int NW = FX::kOn ? N : 1;
   M3 Rw[NW];
   V3 pw[NW];
-  constexpr int NNZ = TP::nnz() > 0 ? TP::nnz() : 1;
   M3 R[N];
   Mot v[N], a[N];
   Frc f[N];
   Inr Ic[N];
-  float L[NNZ];
-  float Linv[NV];
-  float y[NRHS][NV];
+  Ltl<TP, NRHS> F;
   const V3 g = load_g<TP>(t);
   const V3 mg = {-g.x, -g.y, -g.z};
-
-  // Row k of L^T L given row k of M (Mr[j] for ancestors j, Mkk) and b_k.
-  auto factor_row = [&](auto K_, const float* Mr, float Mkk, const float* bk) __attribute__((always_inline)) {
-    constexpr int K = decltype(K_)::value;
-    float D = Mkk;
-    sfor<K + 1, NV>([&](auto D_) __attribute__((always_inline)) {
-      constexpr int Dd = decltype(D_)::value;
-      if constexpr (TP::is_danc(K, Dd)) D = D - L[cidx<TP::lidx(Dd, K)>] * L[cidx<TP::lidx(Dd, K)>];
-    });
-    const float inv = frsq(D);
-    Linv[K] = inv;
-    sfor<0, K>([&](auto J_) __attribute__((always_inline)) {
-      constexpr int Jd = decltype(J_)::value;
-      if constexpr (TP::is_danc(Jd, K)) {
-        float acc = Mr[Jd];
-        sfor<K + 1, NV>([&](auto D_) __attribute__((always_inline)) {
-          constexpr int Dd = decltype(D_)::value;
-          if constexpr (TP::is_danc(K, Dd)) acc = acc - L[cidx<TP::lidx(Dd, K)>] * L[cidx<TP::lidx(Dd, Jd)>];
-        });
-        L[cidx<TP::lidx(K, Jd)>] = acc * inv;
-      }
-    });
-    sfor<0, NRHS>([&](auto R_) __attribute__((always_inline)) {
-      constexpr int r = decltype(R_)::value;
-      float acc = bk[r];
-      sfor<K + 1, NV>([&](auto D_) __attribute__((always_inline)) {
-        constexpr int Dd = decltype(D_)::value;
-        if constexpr (TP::is_danc(K, Dd)) acc = acc - L[cidx<TP::lidx(Dd, K)>] * y[r][Dd];
-      });
-      y[r][K] = acc * inv;
-    });
-  };
 
   auto backward = [&](auto J_) __attribute__((always_inline)) {
     constexpr int J = decltype(J_)::value;
     constexpr int P = TP::parent(J);
     if constexpr (TP::free_body(J)) {
       const float hb[6] = {f[J].f.x, f[J].f.y, f[J].f.z, f[J].n.x, f[J].n.y, f[J].n.z};
-      sfor_rev<0, 6>([&](auto K_) __attribute__((always_inline)) {
-        constexpr int K = decltype(K_)::value;
-        float Mr[6];
-#pragma unroll
-        for (int j = 0; j < K; ++j) Mr[j] = base_block(Ic[J], K, j);
-        float bk[NRHS];
-#pragma unroll
-        for (int r = 0; r < NRHS; ++r) bk[r] = rhs(r, K) - (r == 0 ? hb[K] : 0.0f);
-        factor_row(K_, Mr, base_block(Ic[J], K, K), bk);
+      ltl_base_rows<TP, NRHS>(F, Ic[J], [&](int r, int K) __attribute__((always_inline)) {
+        return rhs(r, K) - (r == 0 ? hb[K] : 0.0f);
       });
     } else {
       constexpr int k = TP::vofs(J);
       float Mr[NV > 1 ? NV : 1];
-      auto emit = [&](auto A_, const Frc& F) __attribute__((always_inline)) {
-        constexpr int A = decltype(A_)::value;
-        if constexpr (TP::free_body(A)) {
-          Mr[0] = F.f.x; Mr[1] = F.f.y; Mr[2] = F.f.z;
-          Mr[3] = F.n.x; Mr[4] = F.n.y; Mr[5] = F.n.z;
-        } else {
-          Mr[cidx<TP::vofs(A)>] = F.n.z;
-        }
-      };
-      walk_up<TP, J>(t, R, inr_col_z(Ic[J]), emit);
+      crba_row<TP, J>(t, R, Ic[J], Mr);
       float bk[NRHS];
 #pragma unroll
       for (int r = 0; r < NRHS; ++r) bk[r] = rhs(r, k) - (r == 0 ? f[J].n.z : 0.0f);
-      factor_row(ic<k>{}, Mr, Ic[J].zz, bk);
+      ltl_row<TP, k, NRHS>(F, Mr, Ic[J].zz, bk);
       if constexpr (P >= 0) {
         const V3 r = load_r<J>(t);
         xfrc_acc(R[J], r, f[J], f[P]);
@@ -783,21 +830,143 @@ RBD_DI void fwd_dyn_lane(const float* __restrict__ t, const QI& q, const QDI& qd
     close_subtrees<TP, I, I>(backward);
   });
 
-  // L x = y, root to leaves
-  sfor<0, NRHS>([&](auto R_) __attribute__((always_inline)) {
-    constexpr int r = decltype(R_)::value;
-    float x[NV];
-    sfor<0, NV>([&](auto K_) __attribute__((always_inline)) {
-      constexpr int K = decltype(K_)::value;
-      float acc = y[r][K];
-      sfor<0, K>([&](auto J_) __attribute__((always_inline)) {
-        constexpr int Jd = decltype(J_)::value;
-        if constexpr (TP::is_danc(Jd, K)) acc = acc - L[cidx<TP::lidx(K, Jd)>] * x[Jd];
-      });
-      x[K] = acc * Linv[K];
-      sink(r, K, x[K]);
-    });
+  ltl_back<TP, NRHS>(F, sink);
+}
+
+// =================================================================== fwd_dyn tangent
+// Forward-mode derivative of forward dynamics. With qdd = FD(q, qd, tau)
+// known, ID(q, qd, qdd) = tau gives
+//   dqdd = M^-1 (dtau - dID/dq dq - dID/dqd dqd),
+// so one sweep runs the tangent of inverse dynamics at (q, qd, qdd) and, as
+// each subtree closes, feeds dtau_k - d(ID)_k into the same CRBA row and L^T L
+// factor as fwd_dyn_lane; the final L x = y sweep gives dqdd.
+// Tangents through a revolute joint, with dX/dq = -(S x) X:
+//   dv_i = X dv_p - dq_i S x (X v_p) + S dqd_i
+//   da_i = X da_p - dq_i S x (X a_p) + dv_i x S qd_i + v_i x S dqd_i
+//   df_i = I da_i + dv_i x* I v_i + v_i x* I dv_i
+//   df_p += X^T (df_i + dq_i S x* f_i)      (f_i the total force of body i)
+//   d(ID)_i = S^T df_i.
+// A free base contributes only through gravity a_0 = R^T (-g), whose
+// quaternion derivative follows the normalised Hamilton rotation; its position
+// does not enter body-frame dynamics.
+template <class TP, class QI, class QDI, class QDDI, class DQI, class DQDI, class DTI, class SINK>
+RBD_DI void fwd_dyn_tangent_lane(const float* __restrict__ t, const QI& q, const QDI& qd, const QDDI& qdd,
+                                 const DQI& dq, const DQDI& dqd, const DTI& dtau, const SINK& sink) {
+  constexpr int N = TP::N, NV = TP::NV;
+  M3 R[N];
+  Mot v[N], a[N], dv[N], da[N];
+  Frc f[N], df[N];
+  Inr Ic[N];
+  Ltl<TP, 1> F;
+  const V3 g = load_g<TP>(t);
+  const V3 mg = {-g.x, -g.y, -g.z};
+
+  auto backward = [&](auto J_) __attribute__((always_inline)) {
+    constexpr int J = decltype(J_)::value;
+    constexpr int P = TP::parent(J);
+    if constexpr (TP::free_body(J)) {
+      const float hb[6] = {df[J].f.x, df[J].f.y, df[J].f.z, df[J].n.x, df[J].n.y, df[J].n.z};
+      ltl_base_rows<TP, 1>(F, Ic[J], [&](int, int K) __attribute__((always_inline)) { return dtau(K) - hb[K]; });
+    } else {
+      constexpr int k = TP::vofs(J);
+      float Mr[NV > 1 ? NV : 1];
+      crba_row<TP, J>(t, R, Ic[J], Mr);
+      const float bk[1] = {dtau(k) - df[J].n.z};
+      ltl_row<TP, k, 1>(F, Mr, Ic[J].zz, bk);
+      if constexpr (P >= 0) {
+        const V3 r = load_r<J>(t);
+        const float e = dq(cidx<TP::qofs(J)>);
+        // df + dq S x* f: S x* [n; f] = [(-n_y, n_x, 0); (-f_y, f_x, 0)]
+        Frc d = df[J];
+        d.n.x = __builtin_fmaf(-e, f[J].n.y, d.n.x);
+        d.n.y = __builtin_fmaf(e, f[J].n.x, d.n.y);
+        d.f.x = __builtin_fmaf(-e, f[J].f.y, d.f.x);
+        d.f.y = __builtin_fmaf(e, f[J].f.x, d.f.y);
+        xfrc_acc(R[J], r, d, df[P]);
+        xfrc_acc(R[J], r, f[J], f[P]);
+        xinr_acc(R[J], r, Ic[J], Ic[P]);
+      }
+    }
+  };
+
+  sfor<0, N>([&](auto I_) __attribute__((always_inline)) {
+    constexpr int I = decltype(I_)::value;
+    constexpr int P = TP::parent(I);
+    if constexpr (TP::free_body(I)) {
+      const float w = q(3), x = q(4), y = q(5), z = q(6);
+      const float dw = dq(3), dx = dq(4), dy = dq(5), dz = dq(6);
+      R[I] = quat_rot(w, x, y, z);
+      // d(R^T mg) with R = N(quat) / |quat|^2: dR = (dN - R ds) / s, ds = 2 quat . dquat
+      const float s = frcp(w * w + x * x + y * y + z * z);
+      const float ds = 2.0f * (w * dw + x * dx + y * dy + z * dz);
+      M3 dN;
+      dN.a[0] = 2.0f * (w * dw + x * dx - y * dy - z * dz);
+      dN.a[1] = 2.0f * (dx * y + x * dy - dw * z - w * dz);
+      dN.a[2] = 2.0f * (dx * z + x * dz + dw * y + w * dy);
+      dN.a[3] = 2.0f * (dx * y + x * dy + dw * z + w * dz);
+      dN.a[4] = 2.0f * (w * dw - x * dx + y * dy - z * dz);
+      dN.a[5] = 2.0f * (dy * z + y * dz - dw * x - w * dx);
+      dN.a[6] = 2.0f * (dx * z + x * dz - dw * y - w * dy);
+      dN.a[7] = 2.0f * (dy * z + y * dz + dw * x + w * dx);
+      dN.a[8] = 2.0f * (w * dw - x * dx - y * dy + z * dz);
+      const V3 ag = mulT(R[I], mg);
+      const V3 dag = s * (mulT(dN, mg) - ds * ag);
+      v[I] = {{qd(3), qd(4), qd(5)}, {qd(0), qd(1), qd(2)}};
+      a[I] = {{qdd(3), qdd(4), qdd(5)}, ag + V3{qdd(0), qdd(1), qdd(2)}};
+      dv[I] = {{dqd(3), dqd(4), dqd(5)}, {dqd(0), dqd(1), dqd(2)}};
+      da[I] = {{0.0f, 0.0f, 0.0f}, dag};
+    } else {
+      R[I] = joint_rot<I>(t, q(cidx<TP::qofs(I)>));
+      const float w = qd(cidx<TP::vofs(I)>);
+      const float dw = dqd(cidx<TP::vofs(I)>);
+      const float e = dq(cidx<TP::qofs(I)>);
+      Mot ap, dap;
+      if constexpr (P < 0) {
+        v[I] = {{0.0f, 0.0f, w}, {0.0f, 0.0f, 0.0f}};
+        dv[I] = {{0.0f, 0.0f, dw}, {0.0f, 0.0f, 0.0f}};
+        ap = {{0.0f, 0.0f, 0.0f}, mulT(R[I], mg)};
+        dap = {{0.0f, 0.0f, 0.0f}, {0.0f, 0.0f, 0.0f}};
+      } else {
+        const V3 r = load_r<I>(t);
+        v[I] = xmot(R[I], r, v[P]);
+        v[I].w.z = v[I].w.z + w;
+        dv[I] = xmot(R[I], r, dv[P]);
+        // - e S x (X v_p): the x, y parts of v_i
+        dv[I].w.x = __builtin_fmaf(e, v[I].w.y, dv[I].w.x);
+        dv[I].w.y = __builtin_fmaf(-e, v[I].w.x, dv[I].w.y);
+        dv[I].v.x = __builtin_fmaf(e, v[I].v.y, dv[I].v.x);
+        dv[I].v.y = __builtin_fmaf(-e, v[I].v.x, dv[I].v.y);
+        dv[I].w.z = dv[I].w.z + dw;
+        ap = xmot(R[I], r, a[P]);
+        dap = xmot(R[I], r, da[P]);
+      }
+      // - e S x (X a_p)
+      dap.w.x = __builtin_fmaf(e, ap.w.y, dap.w.x);
+      dap.w.y = __builtin_fmaf(-e, ap.w.x, dap.w.y);
+      dap.v.x = __builtin_fmaf(e, ap.v.y, dap.v.x);
+      dap.v.y = __builtin_fmaf(-e, ap.v.x, dap.v.y);
+      // v x S w and its tangent dv x S w + v x S dw
+      a[I] = ap;
+      a[I].w.x = __builtin_fmaf(w, v[I].w.y, a[I].w.x);
+      a[I].w.y = __builtin_fmaf(-w, v[I].w.x, a[I].w.y);
+      a[I].v.x = __builtin_fmaf(w, v[I].v.y, a[I].v.x);
+      a[I].v.y = __builtin_fmaf(-w, v[I].v.x, a[I].v.y);
+      a[I].w.z = a[I].w.z + qdd(cidx<TP::vofs(I)>);
+      da[I] = dap;
+      da[I].w.x = __builtin_fmaf(w, dv[I].w.y, __builtin_fmaf(dw, v[I].w.y, da[I].w.x));
+      da[I].w.y = __builtin_fmaf(-w, dv[I].w.x, __builtin_fmaf(-dw, v[I].w.x, da[I].w.y));
+      da[I].v.x = __builtin_fmaf(w, dv[I].v.y, __builtin_fmaf(dw, v[I].v.y, da[I].v.x));
+      da[I].v.y = __builtin_fmaf(-w, dv[I].v.x, __builtin_fmaf(-dw, v[I].v.x, da[I].v.y));
+    }
+    const Inr Ib = load_inr<I>(t);
+    const Frc Iv = imul(Ib, v[I]);
+    f[I] = imul(Ib, a[I]) + crf(v[I], Iv);
+    df[I] = imul(Ib, da[I]) + crf(dv[I], Iv) + crf(v[I], imul(Ib, dv[I]));
+    Ic[I] = Ib;
+    close_subtrees<TP, I, I>(backward);
   });
+
+  ltl_back<TP, 1>(F, sink);
 }
 
 // =================================================================== fwd_dyn adjoint

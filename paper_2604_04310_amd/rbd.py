@@ -28,7 +28,7 @@ OP_FWD_DYN, OP_RNEA, OP_FWD_DYN_VJP = 0, 1, 2
 
 # Every symbol include/rbd.h declares.
 EXPORTS = ["rbd_model_create", "rbd_model_destroy", "rbd_model_dims", "rbd_model_topology", "rbd_fk",
-           "rbd_jacobian", "rbd_rnea", "rbd_crba", "rbd_fwd_dyn", "rbd_aba", "rbd_fwd_dyn_vjp", "rbd_status_str",
+           "rbd_jacobian", "rbd_rnea", "rbd_crba", "rbd_fwd_dyn", "rbd_aba", "rbd_fwd_dyn_jvp", "rbd_fwd_dyn_vjp", "rbd_status_str",
            "rbd_last_error", "rbd_device_count", "rbd_diag_fma_rate", "rbd_server_create", "rbd_server_submit", "rbd_server_wait",
            "rbd_server_get_stats", "rbd_server_reset_stats", "rbd_server_destroy"]
 
@@ -88,6 +88,7 @@ def lib():
         L.rbd_fwd_dyn.argtypes = [vp, i64, i64, vp, vp, vp, vp, vp, vp]
         L.rbd_aba.argtypes = [vp, i64, i64, vp, vp, vp, vp, vp, vp]
         L.rbd_fwd_dyn_vjp.argtypes = [vp, i64, i64, vp, vp, vp, vp, vp, vp, vp, vp]
+        L.rbd_fwd_dyn_jvp.argtypes = [vp, i64, i64, vp, vp, vp, vp, vp, vp, vp, vp]
         L.rbd_status_str.argtypes = [C.c_int]
         L.rbd_status_str.restype = C.c_char_p
         L.rbd_last_error.argtypes = []
@@ -307,18 +308,44 @@ def fwd_dyn_vjp(model: Model, q, qd, tau, g_qdd, want=(True, True, True)):
     return tuple(outs)
 
 
+def fwd_dyn_jvp(model: Model, q, qd, tau, dq, dqd, dtau, want_qdd=False):
+    """d qdd [nv, B] along the tangent (dq [nq, B], dqd, dtau [nv, B]); with want_qdd also returns qdd."""
+    ins = [_soa(x, r, n, None) for x, r, n in ((q, model.nq, "q"), (qd, model.nv, "qd"), (tau, model.nv, "tau"),
+                                               (dq, model.nq, "dq"), (dqd, model.nv, "dqd"),
+                                               (dtau, model.nv, "dtau"))]
+    B = ins[0][1]
+    if any(i[1] != B for i in ins):
+        raise ValueError("fwd_dyn_jvp: batch sizes differ")
+    ld = _same_ld(*[i[2] for i in ins])
+    if ld != B:
+        raise ValueError("fwd_dyn_jvp: inputs must be contiguous")
+    dqdd = _out(model.nv, B, q)
+    qdd = _out(model.nv, B, q) if want_qdd else None
+    check(lib().rbd_fwd_dyn_jvp(model.handle, B, ld, *[i[0] for i in ins],
+                                C.c_void_p(qdd.data_ptr()) if qdd is not None else None,
+                                C.c_void_p(dqdd.data_ptr()), _stream()))
+    return (qdd, dqdd) if want_qdd else dqdd
+
+
 def _make_autograd():
     torch = _torch()
 
     class FwdDyn(torch.autograd.Function):
-        """qdd = FD(q, qd, tau) with the hand-written adjoint kernel as backward."""
+        """qdd = FD(q, qd, tau) with the hand-written adjoint kernel as backward and the tangent
+        kernel as the forward-mode rule (torch.autograd.forward_ad dual tensors; torch.func
+        transforms hand the rules storage-less wrappers, which a kernel call cannot take).
+        Inputs must be contiguous [rows, B] tensors."""
 
         @staticmethod
-        def forward(ctx, model, q, qd, tau):
-            ctx.model = model
-            q, qd, tau = q.contiguous(), qd.contiguous(), tau.contiguous()
-            ctx.save_for_backward(q, qd, tau)
+        def forward(model, q, qd, tau):
             return fwd_dyn(model, q, qd, tau)
+
+        @staticmethod
+        def setup_context(ctx, inputs, output):
+            model, q, qd, tau = inputs
+            ctx.model = model
+            ctx.save_for_backward(q, qd, tau)
+            ctx.save_for_forward(q, qd, tau)
 
         @staticmethod
         def backward(ctx, g):
@@ -327,6 +354,13 @@ def _make_autograd():
             gq, gqd, gtau = fwd_dyn_vjp(ctx.model, q, qd, tau, g.contiguous(), want=tuple(bool(w) for w in want))
             return None, gq, gqd, gtau
 
+        @staticmethod
+        def jvp(ctx, _model_t, q_t, qd_t, tau_t):
+            q, qd, tau = ctx.saved_tensors
+            tangents = [torch.zeros_like(x) if t is None else t.contiguous()
+                        for x, t in ((q, q_t), (qd, qd_t), (tau, tau_t))]
+            return fwd_dyn_jvp(ctx.model, q, qd, tau, *tangents)
+
     return FwdDyn
 
 
@@ -334,11 +368,11 @@ _FwdDyn = None
 
 
 def fwd_dyn_autograd(model: Model, q, qd, tau):
-    """Differentiable forward dynamics: backward runs rbd_fwd_dyn_vjp."""
+    """Differentiable forward dynamics: backward runs rbd_fwd_dyn_vjp, forward-mode AD rbd_fwd_dyn_jvp."""
     global _FwdDyn
     if _FwdDyn is None:
         _FwdDyn = _make_autograd()
-    return _FwdDyn.apply(model, q, qd, tau)
+    return _FwdDyn.apply(model, q.contiguous(), qd.contiguous(), tau.contiguous())
 
 
 # ---------------------------------------------------------------- serving

@@ -105,6 +105,7 @@ def test_null_model_calls(rbd):
     assert b"model is NULL" in L.rbd_last_error()
     assert L.rbd_aba(None, 1, 1, None, None, None, None, None, None) == 1
     assert L.rbd_rnea(None, 1, 1, None, None, None, None, None, None) == 1
+    assert L.rbd_fwd_dyn_jvp(None, 1, 1, None, None, None, None, None, None, None, None, None) == 1
     assert b"model is NULL" in L.rbd_last_error()
 
 

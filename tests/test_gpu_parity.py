@@ -184,6 +184,55 @@ def test_external_weight_support_on_gpu(rbd):
         assert np.abs(qdd).max() < TOL_QDD * a_scale
 
 
+@pytest.mark.parametrize("name", list(MODELS))
+def test_fwd_dyn_jvp_parity(rbd, name):
+    """Forward-mode derivative against the oracle's central differences along the same tangent."""
+    desc, m = model_of(rbd, name)
+    B = 256
+    st = W.states(desc, B, 230)
+    rng = np.random.Generator(np.random.PCG64(231))
+    dq, dqd, dtau = (W._f32(rng.normal(size=x.shape)) for x in (st.q, st.qd, st.tau))
+    args = [gpu(x) for x in (st.q, st.qd, st.tau, dq, dqd, dtau)]
+    qdd, dqdd = rbd.fwd_dyn_jvp(m, *args, want_qdd=True)
+    ref = O.fwd_dyn_jvp_fd(desc, st.q, st.qd, st.tau, dq, dqd, dtau)
+    assert vjp_err([host(dqdd)], [ref]) < TOL_VJP
+    assert rel_err(host(qdd), O.fwd_dyn(desc, st.q, st.qd, st.tau)) < TOL_QDD
+    # without the qdd output the tangent is parked in dqdd itself; same result bit for bit
+    assert np.array_equal(host(rbd.fwd_dyn_jvp(m, *args)), host(dqdd))
+
+
+def test_jvp_vjp_duality_on_gpu(rbd):
+    """<gbar, J dx> from the tangent kernel equals <J^T gbar, dx> from the adjoint kernel."""
+    desc, m = model_of(rbd, "humanoid30")
+    B = 512
+    st = W.states(desc, B, 232)
+    rng = np.random.Generator(np.random.PCG64(233))
+    dx = [W._f32(rng.normal(size=x.shape)) for x in (st.q, st.qd, st.tau)]
+    gbar = W.cotangent(desc.nv, B, 234)
+    dqdd = host(rbd.fwd_dyn_jvp(m, gpu(st.q), gpu(st.qd), gpu(st.tau), *[gpu(x) for x in dx]))
+    gs = [host(x) for x in rbd.fwd_dyn_vjp(m, gpu(st.q), gpu(st.qd), gpu(st.tau), gpu(gbar))]
+    lhs = np.einsum("bk,bk->b", gbar, dqdd)
+    rhs = sum(np.einsum("bk,bk->b", g, x) for g, x in zip(gs, dx))
+    scale = sum(np.einsum("bk,bk->b", np.abs(g), np.abs(x)) for g, x in zip(gs, dx))
+    assert (np.abs(lhs - rhs) / scale).max() < 1e-4
+
+
+def test_forward_mode_autograd(rbd):
+    """Forward-mode AD (dual tensors) through fwd_dyn_autograd runs the tangent kernel."""
+    from torch.autograd import forward_ad as fwAD
+    desc, m = model_of(rbd, "tree12f")
+    B = 128
+    st = W.states(desc, B, 235)
+    rng = np.random.Generator(np.random.PCG64(236))
+    dq = W._f32(rng.normal(size=st.q.shape))
+    qd, tau = gpu(st.qd), gpu(st.tau)
+    with fwAD.dual_level():
+        out = rbd.fwd_dyn_autograd(m, fwAD.make_dual(gpu(st.q), gpu(dq)), qd, tau)
+        t = fwAD.unpack_dual(out).tangent
+    ref = O.fwd_dyn_jvp_fd(desc, st.q, st.qd, st.tau, dq, np.zeros_like(st.qd), np.zeros_like(st.tau))
+    assert vjp_err([host(t)], [ref]) < TOL_VJP
+
+
 # ---------------------------------------------------------------- layout and edge cases
 def test_leading_dimension_larger_than_batch(rbd):
     desc, m = model_of(rbd, "humanoid30")
