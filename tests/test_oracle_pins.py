@@ -470,3 +470,66 @@ def test_jvp_tau_direction_is_inverse_mass_matrix():
     dtau = W.cotangent(desc.nv, B, 50)
     jv = O.fwd_dyn_jvp_fd(desc, st.q, st.qd, st.tau, np.zeros_like(st.q), np.zeros_like(st.qd), dtau)
     assert rel_err(jv, np.linalg.solve(O.crba(desc, st.q), dtau[..., None])[..., 0]) < 1e-7
+
+
+# ---------------------------------------------------------------- controller workloads (Sec. IV, Table II)
+from oracle import controllers as CT  # noqa: E402
+
+
+def _targets(desc, q, frame, seed, scale=0.2):
+    """Targets near the current pose of `frame`: [B, 3, 4]."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    T = O.fk(desc, q)[:, frame]
+    dR = Rotation.from_rotvec(rng.normal(0, scale, size=(len(q), 3))).as_matrix()
+    out = np.empty_like(T)
+    out[:, :, :3] = dR @ T[:, :, :3]
+    out[:, :, 3] = T[:, :, 3] + rng.normal(0, scale, size=(len(q), 3))
+    return out
+
+
+@pytest.mark.parametrize("name", ["chain7", "humanoid30"])
+def test_diff_ik_moves_the_frame_toward_its_target(name):
+    """With no damping the commanded velocity makes the frame's twist k err exactly (J has full row
+    rank), and a small step along it shrinks a finite pose error by about k dt."""
+    desc = W.chain(7) if name == "chain7" else W.humanoid()
+    B = 8
+    st = W.states(desc, B, 51)
+    e = desc.n_bodies - 1
+    tgt = _targets(desc, st.q, e, 52)
+    k = 2.0
+    qd = CT.diff_ik(desc, st.q, e, tgt, k, 0.0)
+    J = O.jacobian(desc, st.q, [e])[:, 0]
+    err = CT.pose_error(desc, st.q, e, tgt)
+    assert rel_err(np.einsum("brc,bc->br", J, qd), k * err) < 1e-9
+    dt = 1e-4
+    err2 = CT.pose_error(desc, retract(desc, st.q, qd, dt), e, tgt)
+    # first order: d err / dt = -J qd for the position part; the rotation part follows the same
+    # rate up to O(|err|^2) terms of the small-angle vector, so compare norms
+    assert np.all(np.linalg.norm(err2, axis=1) < np.linalg.norm(err, axis=1))
+    lin = err[:, :3] - dt * k * err[:, :3]
+    assert np.allclose(err2[:, :3], lin, atol=1e-7)
+    # at the target nothing moves
+    T = O.fk(desc, st.q)[:, e]
+    assert np.abs(CT.diff_ik(desc, st.q, e, T, k, 0.1)).max() < 1e-12
+
+
+@pytest.mark.parametrize("name", ["chain7", "tree12f", "humanoid30"])
+def test_osc_commands_exactly_the_task_acceleration(name):
+    """Forward dynamics under the OSC torques gives J qdd = a* (every solver), and with no
+    null-space damping tau - h lies in the range of J^T."""
+    desc = {"chain7": W.chain(7), "tree12f": W.random_tree([-1, 0, 1, 1, 0, 4, 5, 5, 7, 0, 9, 10], True, 34),
+            "humanoid30": W.humanoid()}[name]
+    B = 8
+    st = W.states(desc, B, 53)
+    e = desc.n_bodies - 1
+    tgt = _targets(desc, st.q, e, 54)
+    kp, kd, kn = 50.0, 10.0, 2.0
+    tau = CT.osc(desc, st.q, st.qd, e, tgt, kp, kd, kn)
+    J = O.jacobian(desc, st.q, [e])[:, 0]
+    a_star = kp * CT.pose_error(desc, st.q, e, tgt) - kd * np.einsum("brc,bc->br", J, st.qd)
+    for method in (O.METHOD_LLT, O.METHOD_LTL, O.METHOD_ABA):
+        qdd = O.fwd_dyn(desc, st.q, st.qd, tau, method)
+        assert rel_err(np.einsum("brc,bc->br", J, qdd), a_star) < 1e-8
+    tau0 = CT.osc(desc, st.q, st.qd, e, tgt, kp, kd, 0.0) - O.rnea(desc, st.q, st.qd)
+    F, *_ = np.linalg.lstsq(np.swapaxes(J[0], 0, 1), tau0[0], rcond=None)
+    assert np.allclose(np.swapaxes(J[0], 0, 1) @ F, tau0[0], rtol=1e-9, atol=1e-9 * np.abs(tau0[0]).max())
