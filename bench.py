@@ -310,6 +310,13 @@ def main():
     ops["fwd_dyn_jvp_humanoid30_b32768_us"] = 1e3 * time_launches(
         lambda: rbd.fwd_dyn_jvp(model, vq, vqd, vtau, tq, tqd, ttau), n_t, torch)
     del tq, tqd, ttau
+    rng_t = np.random.default_rng(15)
+    tgt = np.concatenate([np.stack([W.random_rotation(rng_t) for _ in range(256)])[np.arange(BATCH) % 256],
+                          rng_t.normal(0.0, 0.5, size=(BATCH, 3, 1))], axis=2)
+    tg = soa(W._f32(tgt.reshape(BATCH, 12)), torch)
+    ops["osc_humanoid30_b65536_us"] = 1e3 * time_launches(lambda: rbd.osc(model, q, qd, tg, 50.0, 10.0, 2.0), n_t, torch)
+    ops["diff_ik_humanoid30_b65536_us"] = 1e3 * time_launches(lambda: rbd.diff_ik(model, q, tg, 2.0, 0.05), n_t, torch)
+    del tg
     fx = soa(W._f32(np.random.default_rng(14).normal(0.0, 5.0, size=(BATCH, 6 * desc.n_bodies))), torch)
     ops["fwd_dyn_fext_humanoid30_b65536_us"] = 1e3 * time_launches(
         lambda: rbd.fwd_dyn(model, q, qd, tau, fext=fx), n_t, torch)

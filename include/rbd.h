@@ -17,6 +17,8 @@
  *                    algorithm, O(n), no mass matrix (Sec. II names it among
  *                    Featherstone's algorithms; Sec. VI-A, future work)
  *   rbd_fwd_dyn_jvp  forward-mode derivative of rbd_fwd_dyn (Sec. IV-A, Fig. 2)
+ *   rbd_diff_ik      differential IK for an end effector (Sec. IV, Table II)
+ *   rbd_osc          operational-space control torques (Sec. IV, Table II)
  *   rbd_fwd_dyn_vjp  reverse-mode derivative of rbd_fwd_dyn (Sec. I, AD)
  *   rbd_server_*     continuous-batching service for the above (host API)
  *
@@ -170,6 +172,27 @@ rbd_status rbd_fwd_dyn_jvp(const rbd_model* model, int64_t batch, int64_t ld, co
 rbd_status rbd_fwd_dyn_vjp(const rbd_model* model, int64_t batch, int64_t ld, const float* q, const float* qd,
                            const float* tau, const float* g_qdd, float* g_q, float* g_qd, float* g_tau,
                            hipStream_t stream);
+
+/* Controller workloads (Sec. IV, Sec. V and Table II: differential IK and
+ * operational-space control), the plain textbook forms for one end-effector
+ * frame, fused into one kernel each. frame must be the last body (n_bodies -
+ * 1, a leaf: the end effector every topology is compiled for; another valid
+ * body id gives RBD_E_UNSUPPORTED). target: [12][ld], the desired pose
+ * [R* | p*] of the frame per instance in the layout of rbd_fk's output (R* in
+ * the body's user axes). With the frame's pose (R_e, p_e) and its Jacobian J
+ * as in rbd_jacobian:
+ *   err = [p* - p_e; 1/2 sum_k R_e[:, k] x R*[:, k]]                (world axes)
+ * rbd_diff_ik: damped least squares, qd = J^T (J J^T + damping^2 I)^-1 (gain err),
+ *   qd: [nv][ld] (zero for joints off the frame's path). damping >= 0.
+ * rbd_osc: a* = kp err - kd J qd, Lambda = (J M^-1 J^T)^-1, tau_null = -k_null qd,
+ *   tau = J^T Lambda (a* - J M^-1 tau_null) + tau_null + h(q, qd), tau: [nv][ld]
+ *   (the Jdot qd term is omitted, so forward dynamics under tau gives J qdd = a*).
+ *   One sweep forms h, M = L^T L and L^-T [J^T, tau_null]; no back substitution. */
+rbd_status rbd_diff_ik(const rbd_model* model, int64_t batch, int64_t ld, const float* q, int32_t frame,
+                       const float* target, float gain, float damping, float* qd, hipStream_t stream);
+rbd_status rbd_osc(const rbd_model* model, int64_t batch, int64_t ld, const float* q, const float* qd,
+                   int32_t frame, const float* target, float kp, float kd, float k_null, float* tau,
+                   hipStream_t stream);
 
 /* Diagnostic (not on the hot path): measured FP32 FMA rate in TFLOP/s of a
  * kernel issuing ilp (1, 4 or 16) independent FMA chains per lane, launched as

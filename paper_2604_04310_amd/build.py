@@ -51,7 +51,7 @@ def build(verbose: bool = False, jobs: int = 0, resource_usage: bool = False, in
     work = []
     # the largest topologies first, so the longest compiles start early
     for name in reversed(topologies()):
-        for part in (2, 4, 6, 5, 3, 1):
+        for part in (2, 7, 4, 6, 5, 3, 1):
             obj = os.path.join(out_dir, f"kern_{name}_p{part}.o")
             cmd = [HIPCC, *DEVICE, *COMMON, f"-DRBD_TOPO={name}", f"-DRBD_PART={part}", "-c",
                    os.path.join(CSRC, TOPO_SOURCE), "-o", obj]

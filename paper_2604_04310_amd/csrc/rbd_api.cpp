@@ -345,6 +345,40 @@ rbd_status rbd_fwd_dyn_jvp(const rbd_model* m, int64_t batch, int64_t ld, const 
   return launch_fwd_dyn_jvp(m, batch, ld, q, qd, tau, dq, dqd, dtau, qdd, dqdd, s);
 }
 
+// The controller entry points serve the end effector each topology is compiled
+// for: the last body.
+static rbd_status check_frame(const rbd_model* m, int32_t frame, const char* fn) {
+  if (frame < 0 || frame >= m->n) return fail(RBD_E_INVAL, "%s: frame %d is not a body id (0..%d)", fn, frame, m->n - 1);
+  if (frame != m->n - 1)
+    return fail(RBD_E_UNSUPPORTED, "%s: frame %d: kernels are compiled for the end effector, body %d", fn, frame,
+                m->n - 1);
+  return RBD_OK;
+}
+
+rbd_status rbd_diff_ik(const rbd_model* m, int64_t batch, int64_t ld, const float* q, int32_t frame,
+                       const float* target, float gain, float damping, float* qd, hipStream_t s) {
+  rbd_status st = check_batch(m, batch, ld, "rbd_diff_ik");
+  if (st != RBD_OK) return st;
+  if ((st = check_frame(m, frame, "rbd_diff_ik")) != RBD_OK) return st;
+  if (!std::isfinite(gain) || !std::isfinite(damping) || damping < 0.0f)
+    return fail(RBD_E_INVAL, "rbd_diff_ik: gain must be finite and damping finite and >= 0");
+  if (batch > 0 && (!q || !target || !qd)) return fail(RBD_E_INVAL, "rbd_diff_ik: NULL array");
+  if ((st = use_device(m->device)) != RBD_OK) return st;
+  return launch_diff_ik(m, batch, ld, q, target, gain, damping * damping, qd, s);
+}
+
+rbd_status rbd_osc(const rbd_model* m, int64_t batch, int64_t ld, const float* q, const float* qd, int32_t frame,
+                   const float* target, float kp, float kd, float k_null, float* tau, hipStream_t s) {
+  rbd_status st = check_batch(m, batch, ld, "rbd_osc");
+  if (st != RBD_OK) return st;
+  if ((st = check_frame(m, frame, "rbd_osc")) != RBD_OK) return st;
+  if (!std::isfinite(kp) || !std::isfinite(kd) || !std::isfinite(k_null))
+    return fail(RBD_E_INVAL, "rbd_osc: gains must be finite");
+  if (batch > 0 && (!q || !qd || !target || !tau)) return fail(RBD_E_INVAL, "rbd_osc: NULL array");
+  if ((st = use_device(m->device)) != RBD_OK) return st;
+  return launch_osc(m, batch, ld, q, qd, target, kp, kd, k_null, tau, s);
+}
+
 rbd_status rbd_fwd_dyn_vjp(const rbd_model* m, int64_t batch, int64_t ld, const float* q, const float* qd,
                            const float* tau, const float* g_qdd, float* g_q, float* g_qd, float* g_tau,
                            hipStream_t s) {

@@ -13,7 +13,7 @@ namespace rbd {
 
 #define RBD_DECL(name, fr, ...) \
   extern const LaunchTable launch_table_##name##_p1, launch_table_##name##_p2, launch_table_##name##_p3, \
-      launch_table_##name##_p4, launch_table_##name##_p5, launch_table_##name##_p6;
+      launch_table_##name##_p4, launch_table_##name##_p5, launch_table_##name##_p6, launch_table_##name##_p7;
 RBD_TOPOLOGIES(RBD_DECL)
 #undef RBD_DECL
 
@@ -27,23 +27,23 @@ static const TopoInfo k_topos[] = {
 #undef RBD_INFO
 };
 
-static const LaunchTable* const k_parts[][6] = {
+static const LaunchTable* const k_parts[][7] = {
 #define RBD_TAB(name, fr, ...)                                                                                  \
   {&launch_table_##name##_p1, &launch_table_##name##_p2, &launch_table_##name##_p3, &launch_table_##name##_p4, \
-   &launch_table_##name##_p5, &launch_table_##name##_p6},
+   &launch_table_##name##_p5, &launch_table_##name##_p6, &launch_table_##name##_p7},
     RBD_TOPOLOGIES(RBD_TAB)
 #undef RBD_TAB
 };
 
-// The six parts of a topology merged into one table (built on first use).
+// The seven parts of a topology merged into one table (built on first use).
 static const LaunchTable* merged(int id) {
   static const std::vector<LaunchTable> all = [] {
     std::vector<LaunchTable> v(sizeof(k_parts) / sizeof(k_parts[0]));
     for (size_t i = 0; i < v.size(); ++i) {
       const LaunchTable &a = *k_parts[i][0], &b = *k_parts[i][1], &c = *k_parts[i][2], &d = *k_parts[i][3],
-                        &e = *k_parts[i][4], &f = *k_parts[i][5];
-      v[i] = LaunchTable{a.fk,  a.jacobian, a.rnea,       a.crba,     b.fwd_dyn,     c.vjp,     d.aba,
-                         b.packed, c.packed_vjp, e.rnea_ext, e.fwd_dyn_ext, e.aba_ext, f.jvp};
+                        &e = *k_parts[i][4], &f = *k_parts[i][5], &g = *k_parts[i][6];
+      v[i] = LaunchTable{a.fk,     a.jacobian,   a.rnea,     a.crba,        b.fwd_dyn, c.vjp, d.aba,
+                         b.packed, c.packed_vjp, e.rnea_ext, e.fwd_dyn_ext, e.aba_ext, f.jvp, g.diff_ik, g.osc};
     }
     return v;
   }();
@@ -137,6 +137,20 @@ rbd_status launch_fwd_dyn_jvp(const rbd_model* m, int64_t batch, int64_t ld, con
   if (batch == 0) return RBD_OK;
   RBD_TABLE_OR_FAIL(m);
   return lt->jvp(m->d_tab, batch, ld, q, qd, tau, dq, dqd, dtau, qdd, dqdd, s);
+}
+
+rbd_status launch_diff_ik(const rbd_model* m, int64_t batch, int64_t ld, const float* q, const float* tgt,
+                          float gain, float lam2, float* qd, hipStream_t s) {
+  if (batch == 0) return RBD_OK;
+  RBD_TABLE_OR_FAIL(m);
+  return lt->diff_ik(m->d_tab, batch, ld, q, tgt, gain, lam2, qd, s);
+}
+
+rbd_status launch_osc(const rbd_model* m, int64_t batch, int64_t ld, const float* q, const float* qd,
+                      const float* tgt, float kp, float kd, float kn, float* tau, hipStream_t s) {
+  if (batch == 0) return RBD_OK;
+  RBD_TABLE_OR_FAIL(m);
+  return lt->osc(m->d_tab, batch, ld, q, qd, tgt, kp, kd, kn, tau, s);
 }
 
 rbd_status launch_fwd_dyn_vjp(const rbd_model* m, int64_t batch, int64_t ld, const float* q, const float* qd,

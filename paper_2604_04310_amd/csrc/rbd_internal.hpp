@@ -58,6 +58,10 @@ rbd_status launch_aba(const rbd_model* m, int64_t batch, int64_t ld, const float
 rbd_status launch_fwd_dyn_jvp(const rbd_model* m, int64_t batch, int64_t ld, const float* q, const float* qd,
                               const float* tau, const float* dq, const float* dqd, const float* dtau, float* qdd,
                               float* dqdd, hipStream_t s);
+rbd_status launch_diff_ik(const rbd_model* m, int64_t batch, int64_t ld, const float* q, const float* tgt,
+                          float gain, float lam2, float* qd, hipStream_t s);
+rbd_status launch_osc(const rbd_model* m, int64_t batch, int64_t ld, const float* q, const float* qd,
+                      const float* tgt, float kp, float kd, float kn, float* tau, hipStream_t s);
 rbd_status launch_fwd_dyn_vjp(const rbd_model* m, int64_t batch, int64_t ld, const float* q, const float* qd,
                               const float* tau, const float* gqdd, float* gq, float* gqd, float* gtau,
                               hipStream_t s);
@@ -85,6 +89,10 @@ struct LaunchTable {
   FdFn aba_ext;
   rbd_status (*jvp)(const float* tab, int64_t batch, int64_t ld, const float* q, const float* qd, const float* tau,
                     const float* dq, const float* dqd, const float* dtau, float* qdd, float* dqdd, hipStream_t s);
+  rbd_status (*diff_ik)(const float* tab, int64_t batch, int64_t ld, const float* q, const float* tgt, float gain,
+                        float lam2, float* qd, hipStream_t s);
+  rbd_status (*osc)(const float* tab, int64_t batch, int64_t ld, const float* q, const float* qd, const float* tgt,
+                    float kp, float kd, float kn, float* tau, hipStream_t s);
 };
 
 // Packed serving launch of one (model, op): d_table holds a PackedHdr-led

@@ -1,10 +1,10 @@
 // Kernels of one compiled topology. Built once per entry of RBD_TOPOLOGIES
-// and part (-DRBD_TOPO=<name> -DRBD_PART=1..6), so they compile in parallel.
+// and part (-DRBD_TOPO=<name> -DRBD_PART=1..7), so they compile in parallel.
 #include "rbd_kernels.hpp"
 #include "rbd_topologies.hpp"
 
 #if !defined(RBD_TOPO) || !defined(RBD_PART)
-#error "RBD_TOPO must name a topology and RBD_PART a part (1..6)"
+#error "RBD_TOPO must name a topology and RBD_PART a part (1..7)"
 #endif
 
 #define RBD_CAT2(a, b) a##b

@@ -254,6 +254,38 @@ __global__ __launch_bounds__(kBlock) void k_fwd_dyn_jvp(const float* __restrict_
                            SinkOne<OutAlias>{OutAlias{dqdd, ld, b}});
 }
 
+// ---- controller workloads for the end effector E = the last body (a leaf).
+template <class TP>
+__global__ __launch_bounds__(kBlock) void k_diff_ik(const float* __restrict__ tab, int64_t batch, int64_t ld,
+                                                    const float* __restrict__ q, const float* __restrict__ tgt,
+                                                    float gain, float lam2, float* __restrict__ qd) {
+  const uint32_t b = lane_id();
+  if (b >= batch) return;
+  diff_ik_lane<TP, TP::N - 1>(tab, In{q, ld, b}, In{tgt, ld, b}, gain, lam2, Out{qd, ld, b});
+}
+
+// PRE as for k_fwd_dyn (q, qd and the target preloaded).
+template <class TP, bool PRE>
+__global__ __launch_bounds__(kBlock) void k_osc(const float* __restrict__ tab, int64_t batch, int64_t ld,
+                                                const float* __restrict__ q, const float* __restrict__ qd,
+                                                const float* __restrict__ tgt, float kp, float kd, float kn,
+                                                float* __restrict__ tau) {
+  const uint32_t b = lane_id();
+  if (b >= batch) return;
+  constexpr int E = TP::N - 1;
+  if constexpr (PRE) {
+    constexpr int NQ = TP::NQ, NV = TP::NV;
+    float qv[NQ], qdv[NV], tv[12];
+    const In qi{q, ld, b}, qdi{qd, ld, b}, ti{tgt, ld, b};
+    sfor<0, NQ>([&](auto K_) __attribute__((always_inline)) { qv[decltype(K_)::value] = qi(decltype(K_)::value); });
+    sfor<0, NV>([&](auto K_) __attribute__((always_inline)) { qdv[decltype(K_)::value] = qdi(decltype(K_)::value); });
+    sfor<0, 12>([&](auto K_) __attribute__((always_inline)) { tv[decltype(K_)::value] = ti(decltype(K_)::value); });
+    osc_lane<TP, E>(tab, RegView{qv}, RegView{qdv}, RegView{tv}, kp, kd, kn, Out{tau, ld, b});
+  } else {
+    osc_lane<TP, E>(tab, In{q, ld, b}, In{qd, ld, b}, In{tgt, ld, b}, kp, kd, kn, Out{tau, ld, b});
+  }
+}
+
 // ---- packed launch for the serving runtime. One launch serves many requests
 // of one (model, operation): the work is cut into tiles of 64 instances (one
 // wave), every tile belongs to one request, and a fixed grid of waves strides
@@ -373,6 +405,23 @@ struct Launch {
                        q, qd, tau, dq, dqd, dtau, qdd, dqdd);
     return check_launch("rbd_fwd_dyn_jvp");
   }
+  static rbd_status diff_ik(const float* tab, int64_t batch, int64_t ld, const float* q, const float* tgt, float gain,
+                            float lam2, float* qd, hipStream_t s) {
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_diff_ik<TP>), dim3(grid_for(batch)), dim3(kBlock), 0, s, tab, batch, ld, q,
+                       tgt, gain, lam2, qd);
+    return check_launch("rbd_diff_ik");
+  }
+  static rbd_status osc(const float* tab, int64_t batch, int64_t ld, const float* q, const float* qd,
+                        const float* tgt, float kp, float kd, float kn, float* tau, hipStream_t s) {
+    constexpr bool kPre = TP::NV > 16;
+    if (preload_inputs(kPre))
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_osc<TP, true>), dim3(grid_for(batch)), dim3(kBlock), 0, s, tab, batch,
+                         ld, q, qd, tgt, kp, kd, kn, tau);
+    else
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_osc<TP, false>), dim3(grid_for(batch)), dim3(kBlock), 0, s, tab, batch,
+                         ld, q, qd, tgt, kp, kd, kn, tau);
+    return check_launch("rbd_osc");
+  }
   static rbd_status packed(int op, const float* tab, const void* table, int grid, hipStream_t s) {
     const uint8_t* t = static_cast<const uint8_t*>(table);
     if (op == RBD_OP_FWD_DYN)
@@ -390,8 +439,8 @@ struct Launch {
   // and the packed forward-dynamics and inverse-dynamics launches. Part 3: the
   // adjoint and its packed launch. Part 4: the articulated-body algorithm.
   // Part 5: the external-force variants of inverse and forward dynamics. Part
-  // 6: the forward-mode derivative. Each part is its own translation unit and
-  // instantiates only its own kernels.
+  // 6: the forward-mode derivative. Part 7: the controller workloads. Each part
+  // is its own translation unit and instantiates only its own kernels.
   template <int K>
   static LaunchTable part() {
     LaunchTable t{};
@@ -412,8 +461,11 @@ struct Launch {
       t.rnea_ext = &Launch::rnea_t<true>;
       t.fwd_dyn_ext = &Launch::fwd_dyn_t<true>;
       t.aba_ext = &Launch::aba_t<true>;
-    } else {
+    } else if constexpr (K == 6) {
       t.jvp = &Launch::jvp;
+    } else {
+      t.diff_ik = &Launch::diff_ik;
+      t.osc = &Launch::osc;
     }
     return t;
   }

@@ -662,8 +662,15 @@ struct Ltl {
   float y[NRHS][TP::NV];
 };
 
+// Which right-hand-side entries can be nonzero: MASK::on(r, k) false means
+// entry k of right-hand side r is structurally zero, and then so is y[r][k]
+// (never stored, never read).
+struct AllRhs {
+  static constexpr bool on(int, int) { return true; }
+};
+
 // Row K given row K of M (Mr[j] for ancestors j, Mkk) and b_K.
-template <class TP, int K, int NRHS>
+template <class TP, int K, int NRHS, class MASK = AllRhs>
 RBD_DI void ltl_row(Ltl<TP, NRHS>& F, const float* Mr, float Mkk, const float* bk) {
   constexpr int NV = TP::NV;
   float D = Mkk;
@@ -686,19 +693,21 @@ RBD_DI void ltl_row(Ltl<TP, NRHS>& F, const float* Mr, float Mkk, const float* b
   });
   sfor<0, NRHS>([&](auto R_) __attribute__((always_inline)) {
     constexpr int r = decltype(R_)::value;
-    float acc = bk[r];
-    sfor<K + 1, NV>([&](auto D_) __attribute__((always_inline)) {
-      constexpr int Dd = decltype(D_)::value;
-      if constexpr (TP::is_danc(K, Dd)) acc = acc - F.L[cidx<TP::lidx(Dd, K)>] * F.y[r][Dd];
-    });
-    F.y[r][K] = acc * inv;
+    if constexpr (MASK::on(r, K)) {
+      float acc = bk[r];
+      sfor<K + 1, NV>([&](auto D_) __attribute__((always_inline)) {
+        constexpr int Dd = decltype(D_)::value;
+        if constexpr (TP::is_danc(K, Dd) && MASK::on(r, Dd)) acc = acc - F.L[cidx<TP::lidx(Dd, K)>] * F.y[r][Dd];
+      });
+      F.y[r][K] = acc * inv;
+    }
   });
 }
 
 // The six rows of a free base from its composite inertia; bk(r, K) gives the
 // right-hand sides (base DoFs in [v; w] order).
-template <class TP, int NRHS, class BK>
-RBD_DI void ltl_base_rows(Ltl<TP, NRHS>& F, const Inr& Ic, const BK& bk) {
+template <class TP, int NRHS, class BK, class MASK = AllRhs>
+RBD_DI void ltl_base_rows(Ltl<TP, NRHS>& F, const Inr& Ic, const BK& bk, MASK = MASK{}) {
   sfor_rev<0, 6>([&](auto K_) __attribute__((always_inline)) {
     constexpr int K = decltype(K_)::value;
     float Mr[6];
@@ -707,7 +716,7 @@ RBD_DI void ltl_base_rows(Ltl<TP, NRHS>& F, const Inr& Ic, const BK& bk) {
     float b[NRHS];
 #pragma unroll
     for (int r = 0; r < NRHS; ++r) b[r] = bk(r, K);
-    ltl_row<TP, K, NRHS>(F, Mr, base_block(Ic, K, K), b);
+    ltl_row<TP, K, NRHS, MASK>(F, Mr, base_block(Ic, K, K), b);
   });
 }
 
@@ -1216,25 +1225,19 @@ RBD_DI void xainr_acc(const M3& R, V3 r, const AInrP& I, AInr& acc) {
   }
 }
 
-// Solves IA x = b for a symmetric positive definite 6x6 articulated inertia
-// (unpivoted Cholesky), motion x from force b.
-RBD_DI Mot ainr_solve(const AInr& I, const Frc& rhs) {
-  float M[6][6] = {{I.a00, I.a01, I.a02, I.b[0], I.b[1], I.b[2]},
-                   {I.a01, I.a11, I.a12, I.b[3], I.b[4], I.b[5]},
-                   {I.a02, I.a12, I.a22, I.b[6], I.b[7], I.b[8]},
-                   {I.b[0], I.b[3], I.b[6], I.c00, I.c01, I.c02},
-                   {I.b[1], I.b[4], I.b[7], I.c01, I.c11, I.c12},
-                   {I.b[2], I.b[5], I.b[8], I.c02, I.c12, I.c22}};
-  const float b[6] = {rhs.n.x, rhs.n.y, rhs.n.z, rhs.f.x, rhs.f.y, rhs.f.z};
-  float L[6][6], inv[6], y[6], x[6];
+// Solves M x = b for a symmetric positive definite n x n M, n <= 6 (unpivoted
+// Cholesky; only the lower triangle of M is read).
+template <int n>
+RBD_DI void chol_solve(const float (&M)[6][6], const float (&b)[6], float (&x)[6]) {
+  float L[6][6], inv[6], y[6];
 #pragma unroll
-  for (int j = 0; j < 6; ++j) {
+  for (int j = 0; j < n; ++j) {
     float d = M[j][j];
 #pragma unroll
     for (int k = 0; k < j; ++k) d = __builtin_fmaf(-L[j][k], L[j][k], d);
     inv[j] = frsq(d);
 #pragma unroll
-    for (int i = j + 1; i < 6; ++i) {
+    for (int i = j + 1; i < n; ++i) {
       float s = M[i][j];
 #pragma unroll
       for (int k = 0; k < j; ++k) s = __builtin_fmaf(-L[i][k], L[j][k], s);
@@ -1242,19 +1245,33 @@ RBD_DI Mot ainr_solve(const AInr& I, const Frc& rhs) {
     }
   }
 #pragma unroll
-  for (int j = 0; j < 6; ++j) {
+  for (int j = 0; j < n; ++j) {
     float s = b[j];
 #pragma unroll
     for (int k = 0; k < j; ++k) s = __builtin_fmaf(-L[j][k], y[k], s);
     y[j] = s * inv[j];
   }
 #pragma unroll
-  for (int j = 5; j >= 0; --j) {
+  for (int j = n - 1; j >= 0; --j) {
     float s = y[j];
 #pragma unroll
-    for (int k = j + 1; k < 6; ++k) s = __builtin_fmaf(-L[k][j], x[k], s);
+    for (int k = j + 1; k < n; ++k) s = __builtin_fmaf(-L[k][j], x[k], s);
     x[j] = s * inv[j];
   }
+}
+RBD_DI void chol6_solve(const float (&M)[6][6], const float (&b)[6], float (&x)[6]) { chol_solve<6>(M, b, x); }
+
+// Solves IA x = b for a 6x6 articulated inertia, motion x from force b.
+RBD_DI Mot ainr_solve(const AInr& I, const Frc& rhs) {
+  const float M[6][6] = {{I.a00, I.a01, I.a02, I.b[0], I.b[1], I.b[2]},
+                         {I.a01, I.a11, I.a12, I.b[3], I.b[4], I.b[5]},
+                         {I.a02, I.a12, I.a22, I.b[6], I.b[7], I.b[8]},
+                         {I.b[0], I.b[3], I.b[6], I.c00, I.c01, I.c02},
+                         {I.b[1], I.b[4], I.b[7], I.c01, I.c11, I.c12},
+                         {I.b[2], I.b[5], I.b[8], I.c02, I.c12, I.c22}};
+  const float b[6] = {rhs.n.x, rhs.n.y, rhs.n.z, rhs.f.x, rhs.f.y, rhs.f.z};
+  float x[6];
+  chol6_solve(M, b, x);
   return {{x[0], x[1], x[2]}, {x[3], x[4], x[5]}};
 }
 
@@ -1413,6 +1430,325 @@ RBD_DI void aba_lane(const float* __restrict__ t, const QI& q, const QDI& qd, co
       qdd(cidx<TP::vofs(I)>, x);
       ap.w.z = ap.w.z + x;
       a[I] = ap;
+    }
+  });
+}
+
+// =================================================================== controller workloads
+// One end-effector frame E (a compile-time body id), a target pose [R* | p*]
+// (12 numbers, row-major like the FK output) per instance. Pose error in world
+// axes: err = [p* - p_E; 1/2 sum_k R_E[:, k] x R*[:, k]] with R_E the user
+// axes of body E. J is E's world-aligned Jacobian at its origin (rows [v; w]);
+// its column for a DoF is zero unless the DoF's body is E or an ancestor (the
+// path of E).
+
+// right-hand sides 0..5 (the rows of J) vanish off the path of E
+template <class TP, int E>
+struct PathRhs {
+  static constexpr bool on(int r, int k) { return r >= 6 || TP::is_anc(TP::body_of(k), E); }
+};
+
+template <class TP, int E, class TGT>
+RBD_DI void pose_error(const float* __restrict__ t, const M3& RwE, V3 pE, const TGT& tgt, float (&err)[6]) {
+  M3 Ru = RwE;  // user axes: Rw C^T (a free base has none of its own)
+  if constexpr (!TP::free_body(E)) {
+    const float* C = t + E * kBodyStride + kOffC;
+    M3 Cm;
+#pragma unroll
+    for (int e = 0; e < 9; ++e) Cm.a[e] = C[e];
+    Ru = mulMMT(RwE, Cm);
+  }
+  V3 rot = {0.0f, 0.0f, 0.0f};
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const V3 a = {Ru.a[k], Ru.a[3 + k], Ru.a[6 + k]};
+    const V3 b = {tgt(k), tgt(4 + k), tgt(8 + k)};
+    rot = cross_add(a, b, rot);
+  }
+  err[0] = tgt(3) - pE.x; err[1] = tgt(7) - pE.y; err[2] = tgt(11) - pE.z;
+  err[3] = 0.5f * rot.x; err[4] = 0.5f * rot.y; err[5] = 0.5f * rot.z;
+}
+
+// Column c (0..5) of J for the DoFs of a free base with world pose (R0, p0).
+RBD_DI void base_jcol(const M3& R0, V3 p0, V3 pE, int c, float (&col)[6]) {
+  const V3 ax = {R0.a[c % 3], R0.a[3 + c % 3], R0.a[6 + c % 3]};
+  if (c < 3) {
+    col[0] = ax.x; col[1] = ax.y; col[2] = ax.z; col[3] = 0.0f; col[4] = 0.0f; col[5] = 0.0f;
+  } else {
+    const V3 lin = cross(ax, pE - p0);
+    col[0] = lin.x; col[1] = lin.y; col[2] = lin.z; col[3] = ax.x; col[4] = ax.y; col[5] = ax.z;
+  }
+}
+// Column of J for a revolute body K with world pose (Rw, pw): [z x (pE - p); z].
+RBD_DI void rev_jcol(const M3& Rw, V3 pw, V3 pE, float (&col)[6]) {
+  const V3 z = {Rw.a[2], Rw.a[5], Rw.a[8]};
+  const V3 lin = cross(z, pE - pw);
+  col[0] = lin.x; col[1] = lin.y; col[2] = lin.z; col[3] = z.x; col[4] = z.y; col[5] = z.z;
+}
+
+// Differential IK by damped least squares: qd = J^T (J J^T + lam^2 I)^-1 (k err).
+// Only E's path is visited: world poses, Jacobian columns and a normal matrix.
+// With fewer than six DoFs on the path the same qd is formed as
+// (J^T J + lam^2 I)^-1 J^T (k err): there J J^T is singular, and the 6x6 form
+// would build large components of w that J^T then cancels in FP32.
+template <class TP, int E>
+struct EPath {
+  static constexpr int count() {
+    int c = 0;
+    for (int k = 0; k < TP::NV; ++k) c += TP::is_anc(TP::body_of(k), E) ? 1 : 0;
+    return c;
+  }
+  static constexpr int slot(int k) {  // position of DoF k among the path's DoFs
+    int c = 0;
+    for (int j = 0; j < k; ++j) c += TP::is_anc(TP::body_of(j), E) ? 1 : 0;
+    return c;
+  }
+};
+
+template <class TP, int E, class QI, class TGT, class QDO>
+RBD_DI void diff_ik_lane(const float* __restrict__ t, const QI& q, const TGT& tgt, float gain, float lam2,
+                         const QDO& qdo) {
+  constexpr int N = TP::N, NV = TP::NV;
+  constexpr int NP = EPath<TP, E>::count();
+  M3 Rw[N];
+  V3 pw[N];
+  sfor<0, E + 1>([&](auto I_) __attribute__((always_inline)) {
+    constexpr int I = decltype(I_)::value;
+    if constexpr (TP::is_anc(I, E)) {
+      M3 RI;
+      if constexpr (TP::free_body(I)) RI = quat_rot(q(3), q(4), q(5), q(6));
+      else RI = joint_rot<I>(t, q(cidx<TP::qofs(I)>));
+      world_pose<TP, I>(t, q, RI, Rw, pw);
+    }
+  });
+  const V3 pE = pw[E];
+  float err[6];
+  pose_error<TP, E>(t, Rw[E], pE, tgt, err);
+  float b[6];
+#pragma unroll
+  for (int i = 0; i < 6; ++i) b[i] = gain * err[i];
+  float Jc[NV][6];
+  sfor<0, N>([&](auto I_) __attribute__((always_inline)) {
+    constexpr int I = decltype(I_)::value;
+    if constexpr (TP::is_anc(I, E)) {
+      if constexpr (TP::free_body(I)) {
+#pragma unroll
+        for (int c = 0; c < 6; ++c) base_jcol(Rw[I], pw[I], pE, c, Jc[c]);
+      } else {
+        rev_jcol(Rw[I], pw[I], pE, Jc[cidx<TP::vofs(I)>]);
+      }
+    }
+  });
+  float A[6][6];
+#pragma unroll
+  for (int i = 0; i < 6; ++i)
+#pragma unroll
+    for (int j = 0; j < 6; ++j) A[i][j] = (i == j) ? lam2 : 0.0f;
+  if constexpr (NP >= 6) {
+    // (J J^T + lam^2 I) w = k err, qd = J^T w
+    sfor<0, NV>([&](auto K_) __attribute__((always_inline)) {
+      constexpr int K = decltype(K_)::value;
+      if constexpr (TP::is_anc(TP::body_of(K), E)) {
+#pragma unroll
+        for (int i = 0; i < 6; ++i)
+#pragma unroll
+          for (int j = 0; j <= i; ++j) A[i][j] = __builtin_fmaf(Jc[K][i], Jc[K][j], A[i][j]);
+      }
+    });
+    float w[6];
+    chol_solve<6>(A, b, w);
+    sfor<0, NV>([&](auto K_) __attribute__((always_inline)) {
+      constexpr int K = decltype(K_)::value;
+      if constexpr (TP::is_anc(TP::body_of(K), E)) {
+        float x = 0.0f;
+#pragma unroll
+        for (int i = 0; i < 6; ++i) x = __builtin_fmaf(Jc[K][i], w[i], x);
+        qdo(K, x);
+      } else {
+        qdo(K, 0.0f);
+      }
+    });
+  } else {
+    // (J^T J + lam^2 I) x = J^T k err over the path's DoFs
+    float rhs[6], x[6];
+    sfor<0, NV>([&](auto K_) __attribute__((always_inline)) {
+      constexpr int K = decltype(K_)::value;
+      if constexpr (TP::is_anc(TP::body_of(K), E)) {
+        constexpr int a = EPath<TP, E>::slot(K);
+        float r = 0.0f;
+#pragma unroll
+        for (int i = 0; i < 6; ++i) r = __builtin_fmaf(Jc[K][i], b[i], r);
+        rhs[a] = r;
+        sfor<0, K + 1>([&](auto L_) __attribute__((always_inline)) {
+          constexpr int L = decltype(L_)::value;
+          if constexpr (TP::is_anc(TP::body_of(L), E)) {
+            constexpr int c = EPath<TP, E>::slot(L);
+#pragma unroll
+            for (int i = 0; i < 6; ++i) A[a][c] = __builtin_fmaf(Jc[K][i], Jc[L][i], A[a][c]);
+          }
+        });
+      }
+    });
+    chol_solve<NP>(A, rhs, x);
+    sfor<0, NV>([&](auto K_) __attribute__((always_inline)) {
+      constexpr int K = decltype(K_)::value;
+      if constexpr (TP::is_anc(TP::body_of(K), E)) qdo(K, x[cidx<EPath<TP, E>::slot(K)>]);
+      else qdo(K, 0.0f);
+    });
+  }
+}
+
+// Operational-space control (Khatib's form, the Jdot qd term omitted):
+//   a* = kp err - kd J qd,  tau_null = -k_null qd,
+//   tau = J^T Lambda (a* - J M^-1 tau_null) + tau_null + h,  Lambda^-1 = J M^-1 J^T.
+// One depth-first sweep as in fwd_dyn_lane (bias force h, world poses, CRBA
+// rows, branch-sparse M = L^T L) runs the first solve for seven right-hand
+// sides: the six rows of J and tau_null. With Y = L^-T J^T and y = L^-T tau_null,
+// Lambda^-1 = Y^T Y and J M^-1 tau_null = Y^T y accumulate as the path's DoFs
+// close, so L is never used again and no back substitution is needed. Then a
+// 6x6 solve gives the task wrench z, and J^T z is z applied at E and carried
+// down E's path like a body force.
+template <class TP, int E, class QI, class QDI, class TGT, class TO>
+RBD_DI void osc_lane(const float* __restrict__ t, const QI& q, const QDI& qd, const TGT& tgt, float kp, float kd,
+                     float kn, const TO& tau) {
+  constexpr int N = TP::N, NV = TP::NV;
+  using MK = PathRhs<TP, E>;
+  M3 R[N], Rw[N];
+  V3 pw[N];
+  Mot v[N], a[N];
+  Frc f[N];
+  Inr Ic[N];
+  Ltl<TP, 7> F;
+  float G[6][6], c6[6], hn[NV];
+#pragma unroll
+  for (int i = 0; i < 6; ++i) {
+    c6[i] = 0.0f;
+#pragma unroll
+    for (int j = 0; j < 6; ++j) G[i][j] = 0.0f;
+  }
+  M3 RwE;
+  V3 pE;
+  float astar[6];
+  const V3 g = load_g<TP>(t);
+  const V3 mg = {-g.x, -g.y, -g.z};
+
+  auto accumulate = [&](auto K_) __attribute__((always_inline)) {
+    constexpr int K = decltype(K_)::value;
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+      c6[i] = __builtin_fmaf(F.y[i][K], F.y[6][K], c6[i]);
+#pragma unroll
+      for (int j = 0; j <= i; ++j) G[i][j] = __builtin_fmaf(F.y[i][K], F.y[j][K], G[i][j]);
+    }
+  };
+
+  auto backward = [&](auto J_) __attribute__((always_inline)) {
+    constexpr int J = decltype(J_)::value;
+    constexpr int P = TP::parent(J);
+    constexpr bool kPath = TP::is_anc(J, E);
+    if constexpr (TP::free_body(J)) {
+      float cols[6][6];
+#pragma unroll
+      for (int c = 0; c < 6; ++c) base_jcol(Rw[J], pw[J], pE, c, cols[c]);
+      ltl_base_rows<TP, 7>(F, Ic[J], [&](int r, int K) __attribute__((always_inline)) {
+        return r < 6 ? cols[K][r] : -kn * qd(K);
+      }, MK{});
+      const float hb[6] = {f[J].f.x, f[J].f.y, f[J].f.z, f[J].n.x, f[J].n.y, f[J].n.z};
+      sfor<0, 6>([&](auto K_) __attribute__((always_inline)) {
+        constexpr int K = decltype(K_)::value;
+        accumulate(K_);
+        hn[K] = __builtin_fmaf(-kn, qd(K), hb[K]);
+      });
+    } else {
+      constexpr int k = TP::vofs(J);
+      float Mr[NV > 1 ? NV : 1];
+      crba_row<TP, J>(t, R, Ic[J], Mr);
+      float bk[7];
+      if constexpr (kPath) {
+        float col[6];
+        rev_jcol(Rw[J], pw[J], pE, col);
+#pragma unroll
+        for (int r = 0; r < 6; ++r) bk[r] = col[r];
+      }
+      const float tn = -kn * qd(k);
+      bk[6] = tn;
+      ltl_row<TP, k, 7, MK>(F, Mr, Ic[J].zz, bk);
+      if constexpr (kPath) {
+        accumulate(ic<k>{});
+        hn[k] = f[J].n.z + tn;
+      } else {
+        tau(k, f[J].n.z + tn);
+      }
+      if constexpr (P >= 0) {
+        const V3 r = load_r<J>(t);
+        xfrc_acc(R[J], r, f[J], f[P]);
+        xinr_acc(R[J], r, Ic[J], Ic[P]);
+      }
+    }
+  };
+
+  sfor<0, N>([&](auto I_) __attribute__((always_inline)) {
+    constexpr int I = decltype(I_)::value;
+    constexpr int P = TP::parent(I);
+    if constexpr (TP::free_body(I)) {
+      R[I] = quat_rot(q(3), q(4), q(5), q(6));
+      v[I] = {{qd(3), qd(4), qd(5)}, {qd(0), qd(1), qd(2)}};
+      a[I] = {{0.0f, 0.0f, 0.0f}, mulT(R[I], mg)};
+    } else {
+      R[I] = joint_rot<I>(t, q(cidx<TP::qofs(I)>));
+      const float w = qd(cidx<TP::vofs(I)>);
+      if constexpr (P < 0) {
+        v[I] = {{0.0f, 0.0f, w}, {0.0f, 0.0f, 0.0f}};
+        a[I] = {{0.0f, 0.0f, 0.0f}, mulT(R[I], mg)};
+      } else {
+        const V3 r = load_r<I>(t);
+        v[I] = xmot(R[I], r, v[P]);
+        v[I].w.z = v[I].w.z + w;
+        a[I] = xmot(R[I], r, a[P]);
+        a[I].w.x = a[I].w.x + w * v[I].w.y;
+        a[I].w.y = a[I].w.y - w * v[I].w.x;
+        a[I].v.x = a[I].v.x + w * v[I].v.y;
+        a[I].v.y = a[I].v.y - w * v[I].v.x;
+      }
+    }
+    if constexpr (TP::is_anc(I, E)) world_pose<TP, I>(t, q, R[I], Rw, pw);
+    if constexpr (I == E) {
+      RwE = Rw[E];
+      pE = pw[E];
+      float err[6];
+      pose_error<TP, E>(t, RwE, pE, tgt, err);
+      // world twist of E: the body velocity turned into world axes
+      const V3 vl = mul(RwE, v[E].v), vw = mul(RwE, v[E].w);
+      const float tw[6] = {vl.x, vl.y, vl.z, vw.x, vw.y, vw.z};
+#pragma unroll
+      for (int i = 0; i < 6; ++i) astar[i] = kp * err[i] - kd * tw[i];
+    }
+    const Inr Ib = load_inr<I>(t);
+    f[I] = imul(Ib, a[I]) + crf(v[I], imul(Ib, v[I]));
+    Ic[I] = Ib;
+    close_subtrees<TP, I, I>(backward);
+  });
+
+  // task wrench z = Lambda (a* - J M^-1 tau_null)
+  float rhs[6], z[6];
+#pragma unroll
+  for (int i = 0; i < 6; ++i) rhs[i] = astar[i] - c6[i];
+  chol6_solve(G, rhs, z);
+  // J^T z: the wrench [z_lin; z_ang] at E's origin, carried down E's path
+  Frc w = {mulT(RwE, V3{z[3], z[4], z[5]}), mulT(RwE, V3{z[0], z[1], z[2]})};
+  sfor_rev<0, E + 1>([&](auto K_) __attribute__((always_inline)) {
+    constexpr int K = decltype(K_)::value;
+    constexpr int P = TP::parent(K);
+    if constexpr (TP::is_anc(K, E)) {
+      if constexpr (TP::free_body(K)) {
+        const float wb[6] = {w.f.x, w.f.y, w.f.z, w.n.x, w.n.y, w.n.z};
+#pragma unroll
+        for (int c = 0; c < 6; ++c) tau(c, hn[c] + wb[c]);
+      } else {
+        constexpr int k = TP::vofs(K);
+        tau(k, hn[k] + w.n.z);
+        if constexpr (P >= 0) w = xfrc(joint_rot<K>(t, q(cidx<TP::qofs(K)>)), load_r<K>(t), w);
+      }
     }
   });
 }

@@ -28,7 +28,7 @@ OP_FWD_DYN, OP_RNEA, OP_FWD_DYN_VJP = 0, 1, 2
 
 # Every symbol include/rbd.h declares.
 EXPORTS = ["rbd_model_create", "rbd_model_destroy", "rbd_model_dims", "rbd_model_topology", "rbd_fk",
-           "rbd_jacobian", "rbd_rnea", "rbd_crba", "rbd_fwd_dyn", "rbd_aba", "rbd_fwd_dyn_jvp", "rbd_fwd_dyn_vjp", "rbd_status_str",
+           "rbd_jacobian", "rbd_rnea", "rbd_crba", "rbd_fwd_dyn", "rbd_aba", "rbd_fwd_dyn_jvp", "rbd_fwd_dyn_vjp", "rbd_diff_ik", "rbd_osc", "rbd_status_str",
            "rbd_last_error", "rbd_device_count", "rbd_diag_fma_rate", "rbd_server_create", "rbd_server_submit", "rbd_server_wait",
            "rbd_server_get_stats", "rbd_server_reset_stats", "rbd_server_destroy"]
 
@@ -89,6 +89,9 @@ def lib():
         L.rbd_aba.argtypes = [vp, i64, i64, vp, vp, vp, vp, vp, vp]
         L.rbd_fwd_dyn_vjp.argtypes = [vp, i64, i64, vp, vp, vp, vp, vp, vp, vp, vp]
         L.rbd_fwd_dyn_jvp.argtypes = [vp, i64, i64, vp, vp, vp, vp, vp, vp, vp, vp]
+        f32 = C.c_float
+        L.rbd_diff_ik.argtypes = [vp, i64, i64, vp, C.c_int32, vp, f32, f32, vp, vp]
+        L.rbd_osc.argtypes = [vp, i64, i64, vp, vp, C.c_int32, vp, f32, f32, f32, vp, vp]
         L.rbd_status_str.argtypes = [C.c_int]
         L.rbd_status_str.restype = C.c_char_p
         L.rbd_last_error.argtypes = []
@@ -325,6 +328,32 @@ def fwd_dyn_jvp(model: Model, q, qd, tau, dq, dqd, dtau, want_qdd=False):
                                 C.c_void_p(qdd.data_ptr()) if qdd is not None else None,
                                 C.c_void_p(dqdd.data_ptr()), _stream()))
     return (qdd, dqdd) if want_qdd else dqdd
+
+
+def diff_ik(model: Model, q, target, gain: float, damping: float, frame: Optional[int] = None, out=None):
+    """Damped least-squares joint velocity [nv, B] toward target [12, B] ([R* | p*] row-major) for the
+    end effector (the last body)."""
+    qp, B, l1 = _soa(q, model.nq, "q")
+    tp, _, l2 = _soa(target, 12, "target", B)
+    qd = _out(model.nv, B, q) if out is None else out
+    op, _, l3 = _soa(qd, model.nv, "qd", B)
+    ld = _same_ld(l1, l2, l3)
+    f = model.n_bodies - 1 if frame is None else int(frame)
+    check(lib().rbd_diff_ik(model.handle, B, ld, qp, f, tp, float(gain), float(damping), op, _stream()))
+    return qd
+
+
+def osc(model: Model, q, qd, target, kp: float, kd: float, k_null: float, frame: Optional[int] = None, out=None):
+    """Operational-space control torques [nv, B] for the end effector (the last body)."""
+    qp, B, l1 = _soa(q, model.nq, "q")
+    qdp, _, l2 = _soa(qd, model.nv, "qd", B)
+    tp, _, l3 = _soa(target, 12, "target", B)
+    tau = _out(model.nv, B, q) if out is None else out
+    op, _, l4 = _soa(tau, model.nv, "tau", B)
+    ld = _same_ld(l1, l2, l3, l4)
+    f = model.n_bodies - 1 if frame is None else int(frame)
+    check(lib().rbd_osc(model.handle, B, ld, qp, qdp, f, tp, float(kp), float(kd), float(k_null), op, _stream()))
+    return tau
 
 
 def _make_autograd():

@@ -70,3 +70,14 @@ def vjp_err(got, ref, floor=1e-4):
         den = np.maximum(np.abs(r).max(axis=1), floor * scale)
         worst = max(worst, float((np.abs(x - r).max(axis=1) / den).max()))
     return worst
+
+
+def targets_near(T, seed, scale=0.2):
+    """Target poses [B, 3, 4] near the frame poses T [B, 3, 4]: a random rotation of standard
+    deviation `scale` rad applied in world axes and a random offset of `scale` m."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    dR = Rotation.from_rotvec(rng.normal(0, scale, size=(len(T), 3))).as_matrix()
+    out = np.empty_like(T)
+    out[:, :, :3] = dR @ T[:, :, :3]
+    out[:, :, 3] = T[:, :, 3] + rng.normal(0, scale, size=(len(T), 3))
+    return out
