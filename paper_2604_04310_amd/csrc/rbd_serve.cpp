@@ -38,6 +38,12 @@ namespace {
 using Clock = std::chrono::steady_clock;
 constexpr size_t kAlign = 256;
 constexpr int kMaxTilesPerGroup = 16384;  // 1 M instances per launch
+// A launch group stops growing at this many bytes of staged inputs and outputs
+// (a single request larger than it still forms a group of its own). Host
+// staging and the two copies dominate a group's latency, so a cap keeps a
+// small request from waiting behind hundreds of megabytes; 16 MiB is about
+// 40 000 humanoid or 140 000 seven-joint instances, enough to fill the GPU.
+constexpr size_t kMaxGroupBytes = size_t(16) << 20;
 constexpr int kGridClasses[] = {4, 32, 256, 1024};
 inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
@@ -189,7 +195,9 @@ Group* form_group(rbd_server* s) {
     if (r->model != g->model || r->op != g->op) { ++it; continue; }
     const int rt = (int)((r->batch + kTileLanes - 1) / kTileLanes);
     if (tiles + rt > kMaxTilesPerGroup) break;
-    if (align_up(in_total + r->in_bytes) + out_total + r->out_bytes > budget) break;
+    const size_t grown = align_up(in_total + r->in_bytes) + out_total + r->out_bytes;
+    if (grown > budget) break;
+    if (!g->reqs.empty() && grown > kMaxGroupBytes) break;
     in_total += r->in_bytes;
     out_total += r->out_bytes;
     tiles += rt;
