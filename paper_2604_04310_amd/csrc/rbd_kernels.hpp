@@ -14,6 +14,21 @@ constexpr int kBlock = 256;
 
 RBD_DI uint32_t lane_id() { return blockIdx.x * blockDim.x + threadIdx.x; }
 
+// The same pointer value, hidden from the optimiser (an empty asm on its
+// scalar register, no instruction). A kernel that runs several sweeps gives
+// each its own copies of the table and input pointers and of the row stride,
+// so model constants, inputs, row addresses and what is computed from them
+// (joint sines and cosines) are reloaded and recomputed in each sweep instead
+// of being held in registers across all of them.
+RBD_DI const float* opaque(const float* p) {
+  asm volatile("" : "+s"(p));
+  return p;
+}
+RBD_DI int64_t opaque(int64_t x) {
+  asm volatile("" : "+s"(x));
+  return x;
+}
+
 template <class TP>
 __global__ __launch_bounds__(kBlock) void k_fk(const float* __restrict__ tab, int64_t batch, int64_t ld,
                                                const float* __restrict__ q, float* __restrict__ T) {
@@ -235,10 +250,12 @@ __global__ __launch_bounds__(kBlock) void k_fwd_dyn_vjp(const float* __restrict_
   }
 }
 
-// ---- fwd_dyn tangent: qdd by the fused solve, parked in the qdd output when
-// one is given (else in dqdd, which the tangent sweep overwrites only after its
-// last read), then the tangent sweep. Neither output is restrict-qualified, so
-// the loads of the parked values stay ordered with the stores.
+// ---- fwd_dyn tangent, three sweeps of one lane: qdd by the fused solve
+// (parked in the qdd output when one is given, else in dqdd), the tangent of
+// inverse dynamics writing dtau - d(ID) into dqdd, and the solve with M in
+// place (each right-hand-side entry is read when its subtree closes, every
+// result written after the sweep). Neither output is restrict-qualified, so
+// loads of parked values stay ordered with the stores.
 template <class TP>
 __global__ __launch_bounds__(kBlock) void k_fwd_dyn_jvp(const float* __restrict__ tab, int64_t batch, int64_t ld,
                                                         const float* __restrict__ q, const float* __restrict__ qd,
@@ -248,10 +265,15 @@ __global__ __launch_bounds__(kBlock) void k_fwd_dyn_jvp(const float* __restrict_
   const uint32_t b = lane_id();
   if (b >= batch) return;
   float* park = qdd ? qdd : dqdd;
-  const In qi{q, ld, b}, qdi{qd, ld, b};
-  fwd_dyn_lane<TP, 1>(tab, qi, qdi, RhsOne<In>{In{tau, ld, b}}, SinkOne<OutAlias>{OutAlias{park, ld, b}});
-  fwd_dyn_tangent_lane<TP>(tab, qi, qdi, InAlias{park, ld, b}, In{dq, ld, b}, In{dqd, ld, b}, In{dtau, ld, b},
-                           SinkOne<OutAlias>{OutAlias{dqdd, ld, b}});
+  fwd_dyn_lane<TP, 1>(tab, In{q, ld, b}, In{qd, ld, b}, RhsOne<In>{In{tau, ld, b}},
+                      SinkOne<OutAlias>{OutAlias{park, ld, b}});
+  const int64_t ld2 = opaque(ld);
+  id_tangent_lane<TP>(opaque(tab), In{opaque(q), ld2, b}, In{opaque(qd), ld2, b}, InAlias{park, ld2, b},
+                      In{dq, ld2, b}, In{dqd, ld2, b}, In{dtau, ld2, b}, OutAlias{dqdd, ld2, b});
+  const int64_t ld3 = opaque(ld2);
+  fwd_dyn_lane<TP, 1, In, In, RhsOne<InAlias>, SinkOne<OutAlias>, NoFext, false>(
+      opaque(tab), In{opaque(q), ld3, b}, In{qd, ld3, b}, RhsOne<InAlias>{InAlias{dqdd, ld3, b}},
+      SinkOne<OutAlias>{OutAlias{dqdd, ld3, b}});
 }
 
 // ---- controller workloads for the end effector E = the last body (a leaf).

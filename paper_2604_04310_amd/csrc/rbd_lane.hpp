@@ -766,7 +766,8 @@ RBD_DI void crba_row(const float* __restrict__ t, const M3* R, const Inr& IcJ, f
 //   row k of M from F = Ic S carried up, Ic_parent += X^T Ic X   (CRBA)
 //   row k of the factor M = L^T L and y_k of L^T y = b   (sparse Cholesky)
 // and a final root-to-leaves sweep solves L x = y.
-template <class TP, int NRHS, class QI, class QDI, class RHS, class SINK, class FX = NoFext>
+// BIAS = false solves M x = rhs alone (no bias force, qd unused).
+template <class TP, int NRHS, class QI, class QDI, class RHS, class SINK, class FX = NoFext, bool BIAS = true>
 RBD_DI void fwd_dyn_lane(const float* __restrict__ t, const QI& q, const QDI& qd, const RHS& rhs, const SINK& sink,
                          const FX& fx = FX{}) {
   constexpr int N = TP::N, NV = TP::NV;
@@ -785,21 +786,25 @@ RBD_DI void fwd_dyn_lane(const float* __restrict__ t, const QI& q, const QDI& qd
     constexpr int J = decltype(J_)::value;
     constexpr int P = TP::parent(J);
     if constexpr (TP::free_body(J)) {
-      const float hb[6] = {f[J].f.x, f[J].f.y, f[J].f.z, f[J].n.x, f[J].n.y, f[J].n.z};
-      ltl_base_rows<TP, NRHS>(F, Ic[J], [&](int r, int K) __attribute__((always_inline)) {
-        return rhs(r, K) - (r == 0 ? hb[K] : 0.0f);
-      });
+      if constexpr (BIAS) {
+        const float hb[6] = {f[J].f.x, f[J].f.y, f[J].f.z, f[J].n.x, f[J].n.y, f[J].n.z};
+        ltl_base_rows<TP, NRHS>(F, Ic[J], [&](int r, int K) __attribute__((always_inline)) {
+          return rhs(r, K) - (r == 0 ? hb[K] : 0.0f);
+        });
+      } else {
+        ltl_base_rows<TP, NRHS>(F, Ic[J], [&](int r, int K) __attribute__((always_inline)) { return rhs(r, K); });
+      }
     } else {
       constexpr int k = TP::vofs(J);
       float Mr[NV > 1 ? NV : 1];
       crba_row<TP, J>(t, R, Ic[J], Mr);
       float bk[NRHS];
 #pragma unroll
-      for (int r = 0; r < NRHS; ++r) bk[r] = rhs(r, k) - (r == 0 ? f[J].n.z : 0.0f);
+      for (int r = 0; r < NRHS; ++r) bk[r] = (BIAS && r == 0) ? rhs(r, k) - f[J].n.z : rhs(r, k);
       ltl_row<TP, k, NRHS>(F, Mr, Ic[J].zz, bk);
       if constexpr (P >= 0) {
         const V3 r = load_r<J>(t);
-        xfrc_acc(R[J], r, f[J], f[P]);
+        if constexpr (BIAS) xfrc_acc(R[J], r, f[J], f[P]);
         xinr_acc(R[J], r, Ic[J], Ic[P]);
       }
     }
@@ -808,7 +813,10 @@ RBD_DI void fwd_dyn_lane(const float* __restrict__ t, const QI& q, const QDI& qd
   sfor<0, N>([&](auto I_) __attribute__((always_inline)) {
     constexpr int I = decltype(I_)::value;
     constexpr int P = TP::parent(I);
-    if constexpr (TP::free_body(I)) {
+    if constexpr (!BIAS) {
+      if constexpr (TP::free_body(I)) R[I] = quat_rot(q(3), q(4), q(5), q(6));
+      else R[I] = joint_rot<I>(t, q(cidx<TP::qofs(I)>));
+    } else if constexpr (TP::free_body(I)) {
       R[I] = quat_rot(q(3), q(4), q(5), q(6));
       v[I] = {{qd(3), qd(4), qd(5)}, {qd(0), qd(1), qd(2)}};
       a[I] = {{0.0f, 0.0f, 0.0f}, mulT(R[I], mg)};
@@ -830,10 +838,12 @@ RBD_DI void fwd_dyn_lane(const float* __restrict__ t, const QI& q, const QDI& qd
       }
     }
     const Inr Ib = load_inr<I>(t);
-    f[I] = imul(Ib, a[I]) + crf(v[I], imul(Ib, v[I]));
-    if constexpr (FX::kOn) {
-      world_pose<TP, I>(t, q, R[I], Rw, pw);
-      f[I] = f[I] - fext_body<I>(fx, Rw[I], pw[I]);
+    if constexpr (BIAS) {
+      f[I] = imul(Ib, a[I]) + crf(v[I], imul(Ib, v[I]));
+      if constexpr (FX::kOn) {
+        world_pose<TP, I>(t, q, R[I], Rw, pw);
+        f[I] = f[I] - fext_body<I>(fx, Rw[I], pw[I]);
+      }
     }
     Ic[I] = Ib;
     close_subtrees<TP, I, I>(backward);
@@ -845,10 +855,11 @@ RBD_DI void fwd_dyn_lane(const float* __restrict__ t, const QI& q, const QDI& qd
 // =================================================================== fwd_dyn tangent
 // Forward-mode derivative of forward dynamics. With qdd = FD(q, qd, tau)
 // known, ID(q, qd, qdd) = tau gives
-//   dqdd = M^-1 (dtau - dID/dq dq - dID/dqd dqd),
-// so one sweep runs the tangent of inverse dynamics at (q, qd, qdd) and, as
-// each subtree closes, feeds dtau_k - d(ID)_k into the same CRBA row and L^T L
-// factor as fwd_dyn_lane; the final L x = y sweep gives dqdd.
+//   dqdd = M^-1 (dtau - dID/dq dq - dID/dqd dqd).
+// id_tangent_lane runs the tangent of inverse dynamics at (q, qd, qdd) and
+// writes the right-hand side dtau - d(ID); fwd_dyn_lane without bias then
+// solves with M. (One sweep doing both held the tangent state and the factor
+// at once and spilled; two light sweeps are faster.)
 // Tangents through a revolute joint, with dX/dq = -(S x) X:
 //   dv_i = X dv_p - dq_i S x (X v_p) + S dqd_i
 //   da_i = X da_p - dq_i S x (X a_p) + dv_i x S qd_i + v_i x S dqd_i
@@ -858,15 +869,13 @@ RBD_DI void fwd_dyn_lane(const float* __restrict__ t, const QI& q, const QDI& qd
 // A free base contributes only through gravity a_0 = R^T (-g), whose
 // quaternion derivative follows the normalised Hamilton rotation; its position
 // does not enter body-frame dynamics.
-template <class TP, class QI, class QDI, class QDDI, class DQI, class DQDI, class DTI, class SINK>
-RBD_DI void fwd_dyn_tangent_lane(const float* __restrict__ t, const QI& q, const QDI& qd, const QDDI& qdd,
-                                 const DQI& dq, const DQDI& dqd, const DTI& dtau, const SINK& sink) {
-  constexpr int N = TP::N, NV = TP::NV;
+template <class TP, class QI, class QDI, class QDDI, class DQI, class DQDI, class DTI, class OUT>
+RBD_DI void id_tangent_lane(const float* __restrict__ t, const QI& q, const QDI& qd, const QDDI& qdd,
+                            const DQI& dq, const DQDI& dqd, const DTI& dtau, const OUT& out) {
+  constexpr int N = TP::N;
   M3 R[N];
   Mot v[N], a[N], dv[N], da[N];
   Frc f[N], df[N];
-  Inr Ic[N];
-  Ltl<TP, 1> F;
   const V3 g = load_g<TP>(t);
   const V3 mg = {-g.x, -g.y, -g.z};
 
@@ -875,13 +884,11 @@ RBD_DI void fwd_dyn_tangent_lane(const float* __restrict__ t, const QI& q, const
     constexpr int P = TP::parent(J);
     if constexpr (TP::free_body(J)) {
       const float hb[6] = {df[J].f.x, df[J].f.y, df[J].f.z, df[J].n.x, df[J].n.y, df[J].n.z};
-      ltl_base_rows<TP, 1>(F, Ic[J], [&](int, int K) __attribute__((always_inline)) { return dtau(K) - hb[K]; });
+#pragma unroll
+      for (int c = 0; c < 6; ++c) out(c, dtau(c) - hb[c]);
     } else {
       constexpr int k = TP::vofs(J);
-      float Mr[NV > 1 ? NV : 1];
-      crba_row<TP, J>(t, R, Ic[J], Mr);
-      const float bk[1] = {dtau(k) - df[J].n.z};
-      ltl_row<TP, k, 1>(F, Mr, Ic[J].zz, bk);
+      out(k, dtau(k) - df[J].n.z);
       if constexpr (P >= 0) {
         const V3 r = load_r<J>(t);
         const float e = dq(cidx<TP::qofs(J)>);
@@ -893,7 +900,6 @@ RBD_DI void fwd_dyn_tangent_lane(const float* __restrict__ t, const QI& q, const
         d.f.y = __builtin_fmaf(e, f[J].f.x, d.f.y);
         xfrc_acc(R[J], r, d, df[P]);
         xfrc_acc(R[J], r, f[J], f[P]);
-        xinr_acc(R[J], r, Ic[J], Ic[P]);
       }
     }
   };
@@ -971,11 +977,8 @@ RBD_DI void fwd_dyn_tangent_lane(const float* __restrict__ t, const QI& q, const
     const Frc Iv = imul(Ib, v[I]);
     f[I] = imul(Ib, a[I]) + crf(v[I], Iv);
     df[I] = imul(Ib, da[I]) + crf(dv[I], Iv) + crf(v[I], imul(Ib, dv[I]));
-    Ic[I] = Ib;
     close_subtrees<TP, I, I>(backward);
   });
-
-  ltl_back<TP, 1>(F, sink);
 }
 
 // =================================================================== fwd_dyn adjoint
