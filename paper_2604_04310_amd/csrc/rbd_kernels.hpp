@@ -28,6 +28,9 @@ RBD_DI int64_t opaque(int64_t x) {
   asm volatile("" : "+s"(x));
   return x;
 }
+// Between two sweeps: keeps the scheduler from starting the next sweep's
+// loads inside the previous one, where its registers are all in use.
+RBD_DI void sweep_boundary() { __builtin_amdgcn_sched_barrier(0); }
 
 template <class TP>
 __global__ __launch_bounds__(kBlock) void k_fk(const float* __restrict__ tab, int64_t batch, int64_t ld,
@@ -241,7 +244,20 @@ __global__ __launch_bounds__(kBlock) void k_fwd_dyn_vjp(const float* __restrict_
   if (b >= batch) return;
   const In qi{q, ld, b}, qdi{qd, ld, b}, ti{tau, ld, b}, gi{gqdd, ld, b};
   const OutOpt<OutAlias> gqo{OutAlias{gq, ld, b}, gq != nullptr};
-  if constexpr (MODE == 2) {
+  if constexpr (MODE == 2 && TP::NV > 16) {
+    // the two sweeps of vjp_lane_parked, the second on fresh views (its own
+    // table and input pointers and row stride): a large tree's first sweep
+    // uses every register, and values kept for the second one spill
+    // (measured: 1028 -> 400 B/lane of scratch, 126 -> 108 us for the
+    // humanoid; a small tree is faster keeping them)
+    const OutAliasP pd{{gqd, ld, b}}, pt{{gtau, ld, b}};
+    fwd_dyn_lane<TP, 2>(tab, qi, qdi, RhsTwo<In>{ti, gi}, SinkTwo<OutAliasP>{pd, pt});
+    sweep_boundary();
+    const int64_t l2 = opaque(ld);
+    id_adjoint_lane<TP>(opaque(tab), In{opaque(q), l2, b}, In{opaque(qd), l2, b}, InAlias{gqd, l2, b},
+                        InAlias{gtau, l2, b}, OutOpt<OutAlias>{OutAlias{gq, l2, b}, gq != nullptr},
+                        OutAlias{gqd, l2, b});
+  } else if constexpr (MODE == 2) {
     const OutAliasP pd{{gqd, ld, b}}, pt{{gtau, ld, b}};
     vjp_lane_parked<TP>(tab, qi, qdi, ti, gi, gqo, pd, pt, InAlias{gqd, ld, b}, InAlias{gtau, ld, b});
   } else {
@@ -267,12 +283,18 @@ __global__ __launch_bounds__(kBlock) void k_fwd_dyn_jvp(const float* __restrict_
   float* park = qdd ? qdd : dqdd;
   fwd_dyn_lane<TP, 1>(tab, In{q, ld, b}, In{qd, ld, b}, RhsOne<In>{In{tau, ld, b}},
                       SinkOne<OutAlias>{OutAlias{park, ld, b}});
-  const int64_t ld2 = opaque(ld);
-  id_tangent_lane<TP>(opaque(tab), In{opaque(q), ld2, b}, In{opaque(qd), ld2, b}, InAlias{park, ld2, b},
+  // a large tree gives each sweep fresh views (see k_fwd_dyn_vjp)
+  constexpr bool kFresh = TP::NV > 16;
+  auto view = [](auto x) __attribute__((always_inline)) {
+    if constexpr (kFresh) return opaque(x);
+    else return x;
+  };
+  const int64_t ld2 = view(ld);
+  id_tangent_lane<TP>(view(tab), In{view(q), ld2, b}, In{view(qd), ld2, b}, InAlias{park, ld2, b},
                       In{dq, ld2, b}, In{dqd, ld2, b}, In{dtau, ld2, b}, OutAlias{dqdd, ld2, b});
-  const int64_t ld3 = opaque(ld2);
+  const int64_t ld3 = view(ld2);
   fwd_dyn_lane<TP, 1, In, In, RhsOne<InAlias>, SinkOne<OutAlias>, NoFext, false>(
-      opaque(tab), In{opaque(q), ld3, b}, In{qd, ld3, b}, RhsOne<InAlias>{InAlias{dqdd, ld3, b}},
+      view(tab), In{view(q), ld3, b}, In{qd, ld3, b}, RhsOne<InAlias>{InAlias{dqdd, ld3, b}},
       SinkOne<OutAlias>{OutAlias{dqdd, ld3, b}});
 }
 
