@@ -217,7 +217,7 @@ def fk(model: Model, q):
     """World pose of every body: [n_bodies * 12, B], rows (i, 3x4 row-major [R | p])."""
     qp, B, ld = _soa(q, model.nq, "q")
     T = _out(model.n_bodies * 12, B, q)
-    if ld != B:
+    if B > 0 and ld != B:
         raise ValueError("fk: q must be contiguous (ld = batch) so that outputs share its ld")
     check(lib().rbd_fk(model.handle, B, ld, qp, C.c_void_p(T.data_ptr()), _stream()))
     return T
@@ -226,7 +226,7 @@ def fk(model: Model, q):
 def jacobian(model: Model, q, frames: Optional[Sequence[int]] = None):
     """Geometric Jacobians [n_frames * 6 * nv, B] of the given body frames (all by default)."""
     qp, B, ld = _soa(q, model.nq, "q")
-    if ld != B:
+    if B > 0 and ld != B:
         raise ValueError("jacobian: q must be contiguous")
     fr = np.arange(model.n_bodies, dtype=np.int32) if frames is None else np.asarray(frames, dtype=np.int32)
     fr = np.ascontiguousarray(fr)
@@ -262,7 +262,7 @@ def rnea(model: Model, q, qd, qdd=None, out=None, fext=None):
 def crba(model: Model, q):
     """Mass matrix [nv * nv, B], row-major per instance."""
     qp, B, ld = _soa(q, model.nq, "q")
-    if ld != B:
+    if B > 0 and ld != B:
         raise ValueError("crba: q must be contiguous")
     M = _out(model.nv * model.nv, B, q)
     check(lib().rbd_crba(model.handle, B, ld, qp, C.c_void_p(M.data_ptr()), _stream()))
@@ -302,7 +302,7 @@ def fwd_dyn_vjp(model: Model, q, qd, tau, g_qdd, want=(True, True, True)):
     taup, _, l3 = _soa(tau, model.nv, "tau", B)
     gp, _, l4 = _soa(g_qdd, model.nv, "g_qdd", B)
     ld = _same_ld(l1, l2, l3, l4)
-    if ld != B:
+    if B > 0 and ld != B:
         raise ValueError("fwd_dyn_vjp: inputs must be contiguous")
     outs = [_out(model.nq, B, q) if want[0] else None, _out(model.nv, B, q) if want[1] else None,
             _out(model.nv, B, q) if want[2] else None]
@@ -320,7 +320,7 @@ def fwd_dyn_jvp(model: Model, q, qd, tau, dq, dqd, dtau, want_qdd=False):
     if any(i[1] != B for i in ins):
         raise ValueError("fwd_dyn_jvp: batch sizes differ")
     ld = _same_ld(*[i[2] for i in ins])
-    if ld != B:
+    if B > 0 and ld != B:
         raise ValueError("fwd_dyn_jvp: inputs must be contiguous")
     dqdd = _out(model.nv, B, q)
     qdd = _out(model.nv, B, q) if want_qdd else None

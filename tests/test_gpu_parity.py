@@ -331,3 +331,55 @@ def test_invalid_arguments_raise(rbd):
         rbd.fwd_dyn(m, gpu(st.q)[:5], gpu(st.qd), gpu(st.tau))
     with pytest.raises(rbd.RbdError):
         rbd.jacobian(m, gpu(st.q), [0, 99])
+
+
+# ---------------------------------------------------------------- edge cases of the later entry points
+def test_new_entry_points_empty_batch(rbd):
+    desc, m = model_of(rbd, "humanoid30")
+    zq = torch.zeros((desc.nq, 0), dtype=torch.float32, device="cuda")
+    zv = torch.zeros((desc.nv, 0), dtype=torch.float32, device="cuda")
+    zf = torch.zeros((6 * desc.n_bodies, 0), dtype=torch.float32, device="cuda")
+    zt = torch.zeros((12, 0), dtype=torch.float32, device="cuda")
+    assert rbd.aba(m, zq, zv, zv).shape == (desc.nv, 0)
+    assert rbd.fwd_dyn(m, zq, zv, zv, fext=zf).shape == (desc.nv, 0)
+    assert rbd.rnea(m, zq, zv, fext=zf).shape == (desc.nv, 0)
+    assert rbd.fwd_dyn_jvp(m, zq, zv, zv, zq, zv, zv).shape == (desc.nv, 0)
+    assert rbd.osc(m, zq, zv, zt, 1.0, 1.0, 1.0).shape == (desc.nv, 0)
+    assert rbd.diff_ik(m, zq, zt, 1.0, 0.1).shape == (desc.nv, 0)
+
+
+def test_new_entry_points_with_padded_leading_dimension(rbd):
+    """ld > batch for every array (padding never read or written) on a ragged batch."""
+    desc, m = model_of(rbd, "tree12f")
+    B, ld = 300, 512
+    st = W.states(desc, B, 250)
+    rng = np.random.Generator(np.random.PCG64(251))
+    fext = W._f32(rng.normal(0.0, 5.0, size=(B, desc.n_bodies, 6)))
+    q, qd, tau = gpu(st.q, ld), gpu(st.qd, ld), gpu(st.tau, ld)
+    fx = gpu(fext.reshape(B, -1), ld)
+
+    def padded(rows):
+        return torch.full((rows, ld), 7.0, dtype=torch.float32, device="cuda")
+
+    out = padded(desc.nv)
+    rbd.aba(m, q, qd, tau, out=out[:, :B], fext=fx)
+    o = out.cpu().numpy()
+    assert np.all(o[:, B:] == 7.0)
+    assert rel_err(o[:, :B].T.astype(np.float64), O.fwd_dyn(desc, st.q, st.qd, st.tau, fext=fext)) < TOL_QDD
+    out = padded(desc.nv)
+    rbd.rnea(m, q, qd, out=out[:, :B], fext=fx)
+    o = out.cpu().numpy()
+    assert np.all(o[:, B:] == 7.0)
+    assert rel_err(o[:, :B].T.astype(np.float64), O.rnea(desc, st.q, st.qd, fext=fext)) < TOL_TAU
+
+
+def test_new_entry_points_reject_bad_arguments(rbd):
+    desc, m = model_of(rbd, "chain7")
+    st = W.states(desc, 8, 252)
+    q, qd, tau = gpu(st.q), gpu(st.qd), gpu(st.tau)
+    with pytest.raises(ValueError):  # f_ext rows must be 6 per body
+        rbd.fwd_dyn(m, q, qd, tau, fext=torch.zeros((5, 8), dtype=torch.float32, device="cuda"))
+    with pytest.raises(ValueError):  # tangent batch differs
+        rbd.fwd_dyn_jvp(m, q, qd, tau, gpu(st.q[:4]), qd, tau)
+    with pytest.raises(rbd.RbdError):  # non-finite gain
+        rbd.osc(m, q, qd, torch.zeros((12, 8), dtype=torch.float32, device="cuda"), float("nan"), 1.0, 1.0)
