@@ -124,14 +124,26 @@ def cpu_baseline(desc, st, budget_s):
         O.fwd_dyn(desc, q, qd, tau)
         done += n
     dt = time.perf_counter() - t0
-    return {"value": done / dt, "unit": "evals/s", "cores": O.max_threads(), "kind": "oracle",
+    cores = O.max_threads()
+    # the same on one core, over a quarter of the budget
+    m = 512
+    prev = O.set_threads(1)
+    done1, t1 = 0, time.perf_counter()
+    while time.perf_counter() - t1 < budget_s / 4:
+        O.fwd_dyn(desc, q[:m], qd[:m], tau[:m])
+        done1 += m
+    dt1 = time.perf_counter() - t1
+    O.set_threads(prev)
+    return {"value": done / dt, "unit": "evals/s", "cores": cores, "kind": "oracle",
             "sample": f"{done} humanoid30 fwd_dyn evals (FP64, branch-sparse L^T L) = {done // n} passes over "
-                      f"the first {n} states of the batch, {dt:.1f} s wall"}
+                      f"the first {n} states of the batch, {dt:.1f} s wall",
+            "one_core_evals_per_s": done1 / dt1}
 
 
 def serving_leg(rbd, torch, seconds, seed=7):
     """Poisson mix of chain7/humanoid30 requests (ops 60/25/15 fwd_dyn/rnea/vjp,
-    batch log-uniform in [1, 4096]) at half the measured closed-loop capacity."""
+    batch log-uniform in [1, 4096]) at half and at 80 % of the measured
+    closed-loop capacity."""
     import workloads as W
     descs = {"chain7": W.chain(7), "humanoid30": W.humanoid()}
     models = {k: rbd.Model(d, 0) for k, d in descs.items()}
@@ -192,12 +204,18 @@ def serving_leg(rbd, torch, seconds, seed=7):
     run(srv, 512, 0.0)  # warm: graphs, pools
     st, wall = run(srv, 2048, 0.0)
     cap = st["requests"] / wall
+    run(srv, 4000, 0.5 * cap)  # open-loop warm-up, not reported
     n_open = int(max(512, min(20000, cap * 0.5 * seconds)))
     st, wall = run(srv, n_open, 0.5 * cap)
     out["batched"] = {"offered_req_per_s": round(0.5 * cap, 1), "requests": st["requests"],
                       "launches": st["launches"], "evals_per_s": st["instances"] / wall,
                       "p50_us": st["p50_us"], "p99_us": st["p99_us"], "max_us": st["max_us"],
                       "closed_loop_capacity_req_per_s": round(cap, 1)}
+    n80 = int(max(512, min(20000, cap * 0.8 * seconds)))
+    st, wall = run(srv, n80, 0.8 * cap)
+    out["batched_at_80pct"] = {"offered_req_per_s": round(0.8 * cap, 1), "requests": st["requests"],
+                               "launches": st["launches"], "evals_per_s": st["instances"] / wall,
+                               "p50_us": st["p50_us"], "p99_us": st["p99_us"], "max_us": st["max_us"]}
     srv.close()
     base = rbd.Server(arena_bytes=1 << 30, n_streams=1, per_request=True, use_graphs=False)
     run(base, 256, 0.0)
@@ -265,6 +283,38 @@ def main():
     kernel_ms = e0.elapsed_time(e1) / args.steps
     ms_per_step = wall * 1e3 / args.steps
     value = BATCH * args.steps / wall
+
+    # the same launch replayed from a captured HIP graph, and one launch's latency
+    # (launch to completion seen by the host)
+    n_graph = 20
+    gs = torch.cuda.Stream()
+    gs.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(gs):
+        step()
+    torch.cuda.current_stream().wait_stream(gs)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        for _ in range(n_graph):
+            step()
+    graph.replay()
+    torch.cuda.synchronize()
+    g0, g1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = max(1, args.steps // n_graph)
+    g0.record(s)
+    for _ in range(reps):
+        graph.replay()
+    g1.record(s)
+    torch.cuda.synchronize()
+    graph_us = 1e3 * g0.elapsed_time(g1) / (reps * n_graph)
+    lat = []
+    for _ in range(21):
+        t = time.perf_counter()
+        step()
+        torch.cuda.synchronize()
+        lat.append(time.perf_counter() - t)
+    single_launch_us = 1e6 * float(np.median(lat))
+    del graph
 
     # parity of the timed output on a sample (the full check lives in tests/)
     idx = np.arange(0, BATCH, 257)
@@ -349,6 +399,8 @@ def main():
                                "batch 65536 resident states, one instance per lane",
                    "batch": BATCH, "nq": desc.nq, "nv": desc.nv, "parallelism": "none (1 GPU)"},
         "parity_max_rel_err_sample": max_rel,
+        "fwd_dyn_graph_replay_us": round(graph_us, 2),
+        "fwd_dyn_single_launch_latency_us": round(single_launch_us, 1),
         "roofline": roofline,
         "cpu_baseline": cpu,
         "ops": ops,

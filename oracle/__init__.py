@@ -66,6 +66,7 @@ def lib():
         L.orc_fwd_dyn_jvp_fd.argtypes = [m, i64, d, d, d, d, d, d, d, C.c_double, C.c_int]
         L.orc_count_ops.argtypes = [m, C.c_int, P(C.c_longlong)]
         L.orc_max_threads.argtypes = []
+        L.orc_set_threads.argtypes = [C.c_int]
         _lib = L
     return _lib
 
@@ -204,3 +205,8 @@ def count_ops(desc, op):
 
 def max_threads() -> int:
     return int(lib().orc_max_threads())
+
+
+def set_threads(n: int) -> int:
+    """Use n host threads from now on; returns the previous count."""
+    return int(lib().orc_set_threads(int(n)))

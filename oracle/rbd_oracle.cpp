@@ -677,6 +677,18 @@ int orc_max_threads(void) {
 #endif
 }
 
+// Threads for the following calls (n >= 1); returns the previous count.
+int orc_set_threads(int n) {
+#ifdef _OPENMP
+  const int old = omp_get_max_threads();
+  if (n >= 1) omp_set_num_threads(n);
+  return old;
+#else
+  (void)n;
+  return 1;
+#endif
+}
+
 // All arrays are instance-major double: q [B][nq], qd/qdd/tau [B][nv].
 int orc_fk(const orc_model* d, int64_t B, const double* q, double* T /*[B][n][12]*/) {
   Model M;
