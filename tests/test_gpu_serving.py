@@ -136,3 +136,25 @@ def test_server_rejects_bad_requests(env):
     with pytest.raises(rbd.RbdError):
         srv.wait(123456, 0.0)
     srv.close()
+
+
+def test_groups_split_at_the_byte_cap(env):
+    """Requests totalling far more than one launch group may hold (16 MiB of staged data) are
+    served in several packed launches, each bit-identical to the direct call."""
+    rbd, descs, models = env
+    d, m = descs["humanoid30"], models["humanoid30"]
+    B = 4096  # 4096 x (36 + 35 + 35 + 35) x 4 B = 2.3 MB staged per request
+    reqs = []
+    for k in range(16):
+        st = W.states(d, B, 300 + k)
+        reqs.append(("humanoid30", rbd.OP_FWD_DYN, [x.astype(np.float32) for x in (st.q, st.qd, st.tau)]))
+    srv = rbd.Server(arena_bytes=1 << 30, n_streams=2, max_batch_requests=1024)
+    outs = run_all(srv, models, reqs, together=True)
+    st = srv.stats()
+    srv.close()
+    assert st["requests"] == len(reqs)
+    assert 3 <= st["launches"] < len(reqs)  # 37 MB of staging: at least three groups, still packed
+    g = lambda x: torch.tensor(np.ascontiguousarray(x.T), dtype=torch.float32, device="cuda")  # noqa: E731
+    for (_, _, ins), o in zip(reqs, outs):
+        direct = rbd.fwd_dyn(m, *[g(x) for x in ins]).cpu().numpy().T
+        assert np.array_equal(o[0], direct)
