@@ -248,7 +248,7 @@ def main():
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU: the dynamics of independent robot instances need no "
-              f"cross-GPU exchange, and this build runs on a single MI355X (asked for --gpus {args.gpus}).",
+              f"cross-GPU exchange, so each GPU runs its own shard (asked for --gpus {args.gpus}).",
               file=sys.stderr)
         sys.exit(2)
 

@@ -12,7 +12,7 @@
  *                    Eq. (1); with qdd == NULL the bias force h(q, qd) (Alg. 1)
  *   rbd_crba         joint-space mass matrix M(q) (Alg. 2)
  *   rbd_fwd_dyn      forward dynamics qdd = M^-1 (tau - h + J^T F_ext), Eq. (2), by a
- *                    per-instance Cholesky-type solve (Sec. V, footnote)
+ *                    per-instance Cholesky-type solve (Sec. VI-A, footnote)
  *   rbd_aba          the same forward dynamics by the articulated-body
  *                    algorithm, O(n), no mass matrix (Sec. II names it among
  *                    Featherstone's algorithms; Sec. VI-A, future work)
@@ -157,8 +157,8 @@ rbd_status rbd_aba(const rbd_model* model, int64_t batch, int64_t ld, const floa
  * components included; a free base's position does not change qdd), dqd and
  * dtau [nv][ld], dqdd = dqdd/dq dq + dqdd/dqd dqd + M^-1 dtau [nv][ld]. Computed
  * as M^-1 (dtau - dID/dq dq - dID/dqd dqd) at qdd = FD(q, qd, tau): the fused
- * forward dynamics, then one sweep of tangent inverse dynamics feeding the
- * same factorisation. qdd (nullable) also receives the forward dynamics. All
+ * forward dynamics, a sweep of tangent inverse dynamics, then a solve with M,
+ * all in one kernel. qdd (nullable) also receives the forward dynamics. All
  * inputs are required. */
 rbd_status rbd_fwd_dyn_jvp(const rbd_model* model, int64_t batch, int64_t ld, const float* q, const float* qd,
                            const float* tau, const float* dq, const float* dqd, const float* dtau, float* qdd,
@@ -208,10 +208,12 @@ const char* rbd_last_error(void); /* message of this thread's last failed call *
 int rbd_device_count(void);       /* number of visible GPUs (0 without one)    */
 
 /* ------------------------------------------------------------------ serving
- * Continuous batching of dynamics requests (spec: requests of mixed
- * robots and batch sizes are admitted as device memory frees up, packed into
- * one persistent launch per operation and robot, replayed as a captured HIP
- * graph, and overlapped on several streams).
+ * Continuous batching of dynamics requests: requests of mixed robots and
+ * batch sizes are admitted as device memory frees up, packed into one
+ * persistent launch per operation and robot (at most 16 MiB of staged data per
+ * launch), replayed as a captured HIP graph, and overlapped on several
+ * streams. Per-request latency is the time the batching amortises (the paper
+ * finds GPU overhead dominant below about 64 instances, Sec. III-B).
  *
  * A request names a model, an operation and a batch size, and points at host
  * buffers, instance-major FP32 ([batch][n], rows of one instance contiguous):

@@ -19,9 +19,9 @@
 //     ways: dense Cholesky L L^T without pivoting, the branch-sparse L^T L
 //     factorisation of RBDA Sec. 6.5, and the articulated-body algorithm
 //     (RBDA Table 7.1) which never forms M (Sec. II names all three
-//     Featherstone algorithms; Sec. V, footnote, prefers a Cholesky solve);
+//     Featherstone algorithms; Sec. VI-A, footnote, prefers a Cholesky solve);
 //   * the vector-Jacobian product of forward dynamics by central finite
-//     differences (reverse-mode derivatives, Sec. I and Sec. V).
+//     differences (reverse-mode derivatives, Sec. I and Sec. VI-A).
 //
 // Conventions. Spatial vectors inside this file are Featherstone's
 // [angular; linear]. Generalised coordinates: a revolute joint has one q and

@@ -5,9 +5,9 @@ draws random numbers and lays them out: it holds none of the dynamics
 arithmetic, so neither the FP64 oracle nor the GPU path depends on the other
 through it.
 
-The paper measures on a Franka Panda arm and a Unitree G1 humanoid (Sec. I and
-Sec. IV); their model files are not available, so synthetic kinematic trees of
-the same shape stand in for them:
+The paper measures on a Franka Panda arm and a Unitree G1 humanoid (abstract,
+Fig. 1, Sec. V and Table II); their model files are not available, so synthetic
+kinematic trees of the same shape stand in for them:
 
 * a serial chain of revolute joints (the arm), and
 * a 30-body floating-base tree (the humanoid): a 6-DoF free base plus 29
