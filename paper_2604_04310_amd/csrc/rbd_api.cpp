@@ -186,6 +186,8 @@ static rbd_status use_device(int device) {
 static rbd_status check_batch(const rbd_model* m, int64_t batch, int64_t ld, const char* what) {
   if (!m) return fail(RBD_E_INVAL, "%s: model is NULL", what);
   if (batch < 0) return fail(RBD_E_INVAL, "%s: batch = %lld < 0", what, (long long)batch);
+  if (batch > (int64_t(1) << 30))
+    return fail(RBD_E_INVAL, "%s: batch = %lld exceeds 2^30 instances per call", what, (long long)batch);
   if (ld < batch || ld < 1) return fail(RBD_E_INVAL, "%s: ld = %lld < batch = %lld", what, (long long)ld, (long long)batch);
   if (ld > (int64_t(1) << 40)) return fail(RBD_E_INVAL, "%s: ld = %lld is too large", what, (long long)ld);
   return RBD_OK;

@@ -28,6 +28,47 @@ RBD_DI int64_t opaque(int64_t x) {
   asm volatile("" : "+s"(x));
   return x;
 }
+// Views of outputs that a later sweep of the same kernel reads back: not
+// restrict-qualified, so the compiler keeps every load before the store that
+// later overwrites the same element.
+template <bool SB>
+struct InAliasT {
+  const float* base;
+  int64_t ld;
+  uint32_t lane;
+  RBD_DI float operator()(int c) const {
+    if constexpr (SB) return *lane_ptr(base + c * ld, lane);
+    else return (base + c * ld)[lane];
+  }
+};
+template <bool SB>
+struct OutAliasT {
+  float* base;
+  int64_t ld;
+  uint32_t lane;
+  RBD_DI void operator()(int c, float v) const {
+    if constexpr (SB) *lane_ptr(base + c * ld, lane) = v;
+    else (base + c * ld)[lane] = v;
+  }
+};
+using InAlias = InAliasT<true>;
+using OutAlias = OutAliasT<true>;
+template <bool SB>
+struct OutAliasPT : OutAliasT<SB> {
+  using In = InAliasT<SB>;
+};
+using OutAliasP = OutAliasPT<true>;
+
+// The lane I/O views of a tree's kernels (kScalarBase picks the address form).
+#define RBD_LANE_IO(TP)                           \
+  constexpr bool kSB_ = kScalarBase<TP>;          \
+  using In = InT<kSB_>;                           \
+  using Out = OutT<kSB_>;                         \
+  using InAlias = InAliasT<kSB_>;                 \
+  using OutAlias = OutAliasT<kSB_>;               \
+  using OutAliasP = OutAliasPT<kSB_>;             \
+  (void)kSB_
+
 // Between two sweeps: keeps the scheduler from starting the next sweep's
 // loads inside the previous one, where its registers are all in use.
 RBD_DI void sweep_boundary() { __builtin_amdgcn_sched_barrier(0); }
@@ -35,15 +76,17 @@ RBD_DI void sweep_boundary() { __builtin_amdgcn_sched_barrier(0); }
 template <class TP>
 __global__ __launch_bounds__(kBlock) void k_fk(const float* __restrict__ tab, int64_t batch, int64_t ld,
                                                const float* __restrict__ q, float* __restrict__ T) {
+  RBD_LANE_IO(TP);
   const uint32_t b = lane_id();
   if (b >= batch) return;
-  fk_lane<TP>(tab, In{q, ld, b}, Out{T, ld, b});
+  fk_lane<TP>(tab, In{q, ld, b}, OutNT{T, ld, b});
 }
 
 template <class TP>
 __global__ __launch_bounds__(kBlock) void k_jacobian(const float* __restrict__ tab, int64_t batch, int64_t ld,
                                                      const float* __restrict__ q, JacSlots js,
                                                      float* __restrict__ J) {
+  RBD_LANE_IO(TP);
   const uint32_t b = lane_id();
   if (b >= batch) return;
   jac_lane<TP>(tab, In{q, ld, b}, js, J, ld, b);
@@ -55,6 +98,7 @@ __global__ __launch_bounds__(kBlock) void k_rnea(const float* __restrict__ tab, 
                                                  const float* __restrict__ q, const float* __restrict__ qd,
                                                  const float* __restrict__ qdd, const float* __restrict__ fext,
                                                  float* __restrict__ tau) {
+  RBD_LANE_IO(TP);
   const uint32_t b = lane_id();
   if (b >= batch) return;
   if constexpr (EXT)
@@ -67,6 +111,7 @@ __global__ __launch_bounds__(kBlock) void k_rnea(const float* __restrict__ tab, 
 template <class TP>
 __global__ __launch_bounds__(kBlock) void k_crba(const float* __restrict__ tab, int64_t batch, int64_t ld,
                                                  const float* __restrict__ q, float* __restrict__ M) {
+  RBD_LANE_IO(TP);
   const uint32_t b = lane_id();
   if (b >= batch) return;
   crba_lane<TP>(tab, In{q, ld, b}, M, ld, b);
@@ -105,6 +150,7 @@ __global__ __launch_bounds__(kBlock) void k_fwd_dyn(const float* __restrict__ ta
                                                     const float* __restrict__ q, const float* __restrict__ qd,
                                                     const float* __restrict__ tau, const float* __restrict__ fext,
                                                     float* __restrict__ qdd) {
+  RBD_LANE_IO(TP);
   const uint32_t b = lane_id();
   if (b >= batch) return;
   const auto fx = fext_view<EXT>(fext, ld, b);
@@ -132,6 +178,7 @@ __global__ __launch_bounds__(kBlock) void k_aba(const float* __restrict__ tab, i
                                                 const float* __restrict__ q, const float* __restrict__ qd,
                                                 const float* __restrict__ tau, const float* __restrict__ fext,
                                                 float* __restrict__ qdd) {
+  RBD_LANE_IO(TP);
   const uint32_t b = lane_id();
   if (b >= batch) return;
   const auto fx = fext_view<EXT>(fext, ld, b);
@@ -173,21 +220,8 @@ struct OutOpt {
     if (on) y(c, v);
   }
 };
-// Views of q-double-dot and lam parked in the g_qd and g_tau outputs: not
-// restrict-qualified, so the compiler keeps every load before the store that
-// later overwrites the same element.
-struct InAlias {
-  const float* base;
-  int64_t ld;
-  uint32_t lane;
-  RBD_DI float operator()(int c) const { return (base + c * ld)[lane]; }
-};
-struct OutAlias {
-  float* base;
-  int64_t ld;
-  uint32_t lane;
-  RBD_DI void operator()(int c, float v) const { (base + c * ld)[lane] = v; }
-};
+// q-double-dot and lam parked in the g_qd and g_tau outputs go through the
+// alias views above.
 template <class Y>
 struct SinkTwo {
   Y qdd, lam;
@@ -220,9 +254,7 @@ RBD_DI void vjp_lane_parked(const float* __restrict__ tab, const QI& q, const X&
   fwd_dyn_lane<TP, 2>(tab, q, qd, RhsTwo<X>{tau, gqdd}, SinkTwo<P>{gqd_out, gtau_out});
   id_adjoint_lane<TP>(tab, q, qd, gqd_in, gtau_in, gq, gqd_out);
 }
-struct OutAliasP : OutAlias {
-  using In = InAlias;
-};
+
 struct RowAlias {
   float* p;
   RBD_DI void operator()(int c, float v) const { p[c] = v; }
@@ -240,6 +272,7 @@ __global__ __launch_bounds__(kBlock) void k_fwd_dyn_vjp(const float* __restrict_
                                                         const float* __restrict__ tau,
                                                         const float* __restrict__ gqdd, float* gq, float* gqd,
                                                         float* gtau) {
+  RBD_LANE_IO(TP);
   const uint32_t b = lane_id();
   if (b >= batch) return;
   const In qi{q, ld, b}, qdi{qd, ld, b}, ti{tau, ld, b}, gi{gqdd, ld, b};
@@ -278,6 +311,7 @@ __global__ __launch_bounds__(kBlock) void k_fwd_dyn_jvp(const float* __restrict_
                                                         const float* __restrict__ tau, const float* __restrict__ dq,
                                                         const float* __restrict__ dqd,
                                                         const float* __restrict__ dtau, float* qdd, float* dqdd) {
+  RBD_LANE_IO(TP);
   const uint32_t b = lane_id();
   if (b >= batch) return;
   float* park = qdd ? qdd : dqdd;
@@ -303,6 +337,7 @@ template <class TP>
 __global__ __launch_bounds__(kBlock) void k_diff_ik(const float* __restrict__ tab, int64_t batch, int64_t ld,
                                                     const float* __restrict__ q, const float* __restrict__ tgt,
                                                     float gain, float lam2, float* __restrict__ qd) {
+  RBD_LANE_IO(TP);
   const uint32_t b = lane_id();
   if (b >= batch) return;
   diff_ik_lane<TP, TP::N - 1>(tab, In{q, ld, b}, In{tgt, ld, b}, gain, lam2, Out{qd, ld, b});
@@ -314,6 +349,7 @@ __global__ __launch_bounds__(kBlock) void k_osc(const float* __restrict__ tab, i
                                                 const float* __restrict__ q, const float* __restrict__ qd,
                                                 const float* __restrict__ tgt, float kp, float kd, float kn,
                                                 float* __restrict__ tau) {
+  RBD_LANE_IO(TP);
   const uint32_t b = lane_id();
   if (b >= batch) return;
   constexpr int E = TP::N - 1;

@@ -345,17 +345,50 @@ RBD_DI Frc inr_col_z(const Inr& I) { return {{I.xz, I.yz, I.zz}, {-I.h.y, I.h.x,
 // 32-bit register shared by every access (global loads and stores take an
 // SGPR base plus a 32-bit VGPR offset), so no per-access 64-bit address has
 // to be kept in vector registers.
-struct In {
+// Element `lane` of a row: the row address stays scalar and the lane's byte
+// offset is a 32-bit value (batches are limited to 2^30), which is what the
+// scalar-base form of global loads and stores takes; a 64-bit per-lane
+// address would cost three vector instructions per access.
+template <class T>
+RBD_DI T* lane_ptr(T* row, uint32_t lane) {
+  using B = std::conditional_t<std::is_const_v<T>, const char, char>;
+  return reinterpret_cast<T*>(reinterpret_cast<B*>(row) + (lane << 2));
+}
+// SB selects that form; without it the compiler forms a 64-bit address per
+// lane, which measured faster for small trees (more waves per SIMD hide the
+// extra instructions, and their kernels are short) and slower for large ones.
+template <bool SB>
+struct InT {
   const float* __restrict__ base;
   int64_t ld;
   uint32_t lane;
-  RBD_DI float operator()(int c) const { return (base + c * ld)[lane]; }
+  RBD_DI float operator()(int c) const {
+    if constexpr (SB) return *lane_ptr(base + c * ld, lane);
+    else return (base + c * ld)[lane];
+  }
 };
-struct Out {
+template <bool SB>
+struct OutT {
   float* __restrict__ base;
   int64_t ld;
   uint32_t lane;
-  RBD_DI void operator()(int c, float v) const { (base + c * ld)[lane] = v; }
+  RBD_DI void operator()(int c, float v) const {
+    if constexpr (SB) *lane_ptr(base + c * ld, lane) = v;
+    else (base + c * ld)[lane] = v;
+  }
+};
+using In = InT<true>;
+using Out = OutT<true>;
+// The form a tree's kernels use: the scalar-base form above 16 DoFs.
+template <class TP>
+inline constexpr bool kScalarBase = TP::NV > 16;
+// Streaming output: a non-temporal store, for the large outputs written once
+// (poses, mass matrices, Jacobians) that should not displace cached data.
+struct OutNT {
+  float* __restrict__ base;
+  int64_t ld;
+  uint32_t lane;
+  RBD_DI void operator()(int c, float v) const { __builtin_nontemporal_store(v, lane_ptr(base + c * ld, lane)); }
 };
 // A lane's own row of an instance-major array (coordinate c at p[c]).
 struct InRow {
@@ -469,7 +502,9 @@ RBD_DI void jac_lane(const float* __restrict__ t, const QI& q, const JacSlots& j
     const int beg = js.beg[K], end = js.beg[K + 1];
     for (int s = beg; s < end; ++s) {
       float* __restrict__ Jf = J + (int64_t)js.slot[s] * 6 * NV * ld;
-      auto put = [&](int r, int c, float v) __attribute__((always_inline)) { (Jf + (int64_t)(r * NV + c) * ld)[lane] = v; };
+      auto put = [&](int r, int c, float v) __attribute__((always_inline)) {
+        __builtin_nontemporal_store(v, lane_ptr(Jf + (int64_t)(r * NV + c) * ld, lane));
+      };
       sfor<0, N>([&](auto A_) __attribute__((always_inline)) {
         constexpr int A = decltype(A_)::value;
         constexpr int c0 = TP::vofs(A);
@@ -599,7 +634,9 @@ RBD_DI void crba_lane(const float* __restrict__ t, const QI& q, float* __restric
   constexpr int N = TP::N, NV = TP::NV;
   M3 R[N];
   Inr Ic[N];
-  auto put = [&](int r, int c, float v) __attribute__((always_inline)) { (Mp + (int64_t)(r * NV + c) * ld)[lane] = v; };
+  auto put = [&](int r, int c, float v) __attribute__((always_inline)) {
+    __builtin_nontemporal_store(v, lane_ptr(Mp + (int64_t)(r * NV + c) * ld, lane));
+  };
 
   auto backward = [&](auto J_) __attribute__((always_inline)) {
     constexpr int J = decltype(J_)::value;
