@@ -38,7 +38,8 @@
  *
  * Data layout of every batched array: device memory, FP32, structure of
  *   arrays. Element (coordinate c, instance b) lives at ptr[c * ld + b] with
- *   ld >= batch. Inputs are never written. Outputs must not overlap inputs.
+ *   ld >= batch; 0 <= batch <= 2^30 instances per call (RBD_E_INVAL beyond).
+ *   Inputs are never written. Outputs must not overlap inputs.
  *
  * Calls are asynchronous on the given HIP stream (0 = the null stream). They
  *   never allocate device memory and never synchronise. Argument errors are

@@ -324,6 +324,16 @@ def test_autograd_function(rbd):
     assert vjp_err([host(q.grad), host(qd.grad), host(tau.grad)], [rq, rqd, rtau]) < TOL_VJP
 
 
+def test_batch_limit_is_checked_before_launch(rbd):
+    """More than 2^30 instances in one call is an argument error (no pointer is touched)."""
+    import ctypes as C
+    desc, m = model_of(rbd, "chain7")
+    big = (1 << 30) + 1
+    p = C.c_void_p(16)  # never dereferenced: the host check fails first
+    assert rbd.lib().rbd_fwd_dyn(m.handle, big, big, p, p, p, None, p, None) == 1
+    assert b"2^30" in rbd.lib().rbd_last_error()
+
+
 def test_invalid_arguments_raise(rbd):
     desc, m = model_of(rbd, "chain7")
     st = W.states(desc, 8, 216)
