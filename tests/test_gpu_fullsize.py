@@ -3,8 +3,9 @@
 Chain of 7 at batch 2^20 (fwd_dyn, rnea: first 4096 states against the oracle,
 all outputs finite), the 35-DoF humanoid at batch 65536 (fwd_dyn by both the
 factorised solve and the articulated-body algorithm on every instance; crba,
-fk and jacobian on a strided sample), and the adjoint at 2^18
-(chain) and 32768 (humanoid) against central differences on 256 states.
+fk and jacobian on a strided sample; with external forces on a sample), and
+the adjoint and the forward-mode derivative at 2^18 (chain) and 32768
+(humanoid) against central differences on 256 states.
 """
 from __future__ import annotations
 
@@ -95,3 +96,38 @@ def test_vjp_full_batch(rbd, name, B):
     idx = np.linspace(0, B - 1, 256).astype(int)
     rq, rqd, rtau = O.fwd_dyn_vjp_fd(desc, st.q[idx], st.qd[idx], st.tau[idx], gbar[idx])
     assert vjp_err([cols(gq, idx), cols(gqd, idx), cols(gtau, idx)], [rq, rqd, rtau]) < 1e-3
+
+
+@pytest.mark.parametrize("name,B", [("chain7", 1 << 18), ("humanoid30", 32768)])
+def test_jvp_full_batch(rbd, name, B):
+    """The forward-mode derivative at the adjoint's benchmark sizes: finite everywhere, 256 states
+    against central differences of the oracle along the same tangent."""
+    desc = W.chain(7) if name == "chain7" else W.humanoid()
+    m = rbd.Model(desc, 0)
+    st = W.states(desc, B, 106)
+    rng = np.random.Generator(np.random.PCG64(107))
+    dq, dqd, dtau = (W._f32(rng.normal(size=x.shape)) for x in (st.q, st.qd, st.tau))
+    dqdd = rbd.fwd_dyn_jvp(m, gpu(st.q), gpu(st.qd), gpu(st.tau), gpu(dq), gpu(dqd), gpu(dtau))
+    torch.cuda.synchronize()
+    assert torch.isfinite(dqdd).all()
+    idx = np.linspace(0, B - 1, 256).astype(int)
+    ref = O.fwd_dyn_jvp_fd(desc, st.q[idx], st.qd[idx], st.tau[idx], dq[idx], dqd[idx], dtau[idx])
+    assert vjp_err([cols(dqdd, idx)], [ref]) < 1e-3
+
+
+def test_external_forces_at_batch_65536(rbd):
+    """fwd_dyn and rnea with external forces on the humanoid batch: a strided sample against the oracle."""
+    desc = W.humanoid()
+    m = rbd.Model(desc, 0)
+    B = 65536
+    st = W.states(desc, B, 108)
+    rng = np.random.Generator(np.random.PCG64(109))
+    fext = W._f32(rng.normal(0.0, 5.0, size=(B, desc.n_bodies, 6)))
+    q, qd, tau, fx = gpu(st.q), gpu(st.qd), gpu(st.tau), gpu(fext.reshape(B, -1))
+    qdd = rbd.fwd_dyn(m, q, qd, tau, fext=fx)
+    h = rbd.rnea(m, q, qd, fext=fx)
+    torch.cuda.synchronize()
+    assert torch.isfinite(qdd).all() and torch.isfinite(h).all()
+    idx = np.arange(0, B, 131)
+    assert rel_err(cols(qdd, idx), O.fwd_dyn(desc, st.q[idx], st.qd[idx], st.tau[idx], fext=fext[idx])) < 1e-4
+    assert rel_err(cols(h, idx), O.rnea(desc, st.q[idx], st.qd[idx], fext=fext[idx])) < 1e-4
