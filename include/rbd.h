@@ -221,9 +221,9 @@ int rbd_device_count(void);       /* number of visible GPUs (0 without one)    *
  *   RBD_OP_FWD_DYN:     in = {q, qd, tau},          out = {qdd}
  *   RBD_OP_RNEA:        in = {q, qd, qdd},          out = {tau}
  *   RBD_OP_FWD_DYN_VJP: in = {q, qd, tau, g_qdd},   out = {g_q, g_qd, g_tau}
- * The buffers must stay valid until rbd_server_wait reports completion. The
- * server copies inputs into its device arena, runs the batch and copies the
- * results back. */
+ * The buffers, and the model, must stay valid until rbd_server_wait reports
+ * completion. The server copies inputs into its device arena, runs the batch
+ * and copies the results back. */
 typedef enum { RBD_OP_FWD_DYN = 0, RBD_OP_RNEA = 1, RBD_OP_FWD_DYN_VJP = 2 } rbd_op;
 
 typedef struct rbd_server rbd_server;

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <array>
+#include <atomic>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -236,6 +237,8 @@ rbd_status rbd_model_create(const rbd_tree_desc* desc, int device, rbd_model** o
   std::vector<float> tab = make_tables(desc);
   rbd_model* m = new (std::nothrow) rbd_model;
   if (!m) return fail(RBD_E_NOMEM, "host allocation failed");
+  static std::atomic<uint64_t> next_uid{1};
+  m->uid = next_uid.fetch_add(1);
   m->device = device;
   m->topo = topo;
   m->n = n;

@@ -17,6 +17,7 @@ struct rbd_model {
   bool floating = false;
   float* d_tab = nullptr;      // device tables (see rbd_lane.hpp)
   size_t tab_floats = 0;
+  uint64_t uid = 0;            // unique over the process (a new model never reuses one)
 };
 
 namespace rbd {

@@ -136,7 +136,9 @@ struct Slot {
   uint8_t* d_table = nullptr;
   uint8_t* h_table = nullptr;
   bool busy = false;
-  std::map<std::tuple<const rbd_model*, int, int>, hipGraphExec_t> graphs;
+  // captured launches by (model uid, op, grid): a graph holds its model's
+  // table address, so the key must not be the model's (reusable) address
+  std::map<std::tuple<uint64_t, int, int>, hipGraphExec_t> graphs;
 };
 
 size_t table_capacity(int max_req) {
@@ -288,7 +290,7 @@ rbd_status launch_group(rbd_server* s, Group* g) {
   const int grid = s->cfg.per_request ? std::max(1, (g->n_tiles * kTileLanes + 255) / 256) : grid_class(g->n_tiles);
   rbd_status rs = RBD_OK;
   if (s->cfg.use_graphs && !s->cfg.per_request) {
-    auto key = std::make_tuple(g->model, g->op, grid);
+    auto key = std::make_tuple(g->model->uid, g->op, grid);
     auto it = sl.graphs.find(key);
     if (it == sl.graphs.end()) {
       // first request of this model: capture its graphs for every slot,
@@ -298,7 +300,7 @@ rbd_status launch_group(rbd_server* s, Group* g) {
         for (int op = RBD_OP_FWD_DYN; op <= RBD_OP_FWD_DYN_VJP; ++op)
           for (int gc : kGridClasses) {
             if (&other == &sl && op == g->op && gc == grid) continue;
-            auto k2 = std::make_tuple(g->model, op, gc);
+            auto k2 = std::make_tuple(g->model->uid, op, gc);
             if (other.graphs.count(k2)) continue;
             hipGraphExec_t e2 = nullptr;
             if (capture_packed(g->model, op, other.d_table, gc, other.stream, &e2) == RBD_OK)
@@ -388,6 +390,9 @@ void dispatcher_main(rbd_server* s) {
     s->cv_inflight.notify_all();
     if (g->status != RBD_OK) {
       lk.unlock();
+      // copies queued before the failure may still run: drain them before the
+      // block goes back to the arena
+      (void)hipStreamSynchronize(s->slots[g->slot].stream);
       finish_group(s, g, Clock::now());
       lk.lock();
     }

@@ -158,3 +158,22 @@ def test_groups_split_at_the_byte_cap(env):
     for (_, _, ins), o in zip(reqs, outs):
         direct = rbd.fwd_dyn(m, *[g(x) for x in ins]).cpu().numpy().T
         assert np.array_equal(o[0], direct)
+
+
+def test_a_new_model_never_replays_a_destroyed_models_graphs(env):
+    """Captured launches are cached per model; after a model is destroyed, a new model (possibly at
+    the same host address) gets its own, so its results match its direct calls bit for bit."""
+    rbd, descs, _ = env
+    srv = rbd.Server(arena_bytes=64 << 20, n_streams=1, use_graphs=True)
+    g = lambda x: torch.tensor(np.ascontiguousarray(x.T), dtype=torch.float32, device="cuda")  # noqa: E731
+    for seed in (61, 62, 63):
+        d = W.random_tree([-1, 0, 1, 2, 3, 4, 5], False, seed)  # same topology, new parameters
+        m = rbd.Model(d, 0)
+        st = W.states(d, 300, seed)
+        ins = [x.astype(np.float32) for x in (st.q, st.qd, st.tau)]
+        t, outs = srv.submit(m, rbd.OP_FWD_DYN, ins)
+        assert srv.wait(t, 60.0) == 0
+        direct = rbd.fwd_dyn(m, *[g(x) for x in ins]).cpu().numpy().T
+        assert np.array_equal(outs[0], direct)
+        m.close()
+    srv.close()
