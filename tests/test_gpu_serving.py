@@ -79,7 +79,8 @@ def check_oracle(rbd, descs, reqs, results, every=5):
 def test_alone_equals_mix(env):
     rbd, descs, models = env
     reqs = make_requests(rbd, descs, 48, 1)
-    srv = rbd.Server(arena_bytes=512 << 20, n_streams=4, max_batch_requests=256)
+    # a short gather window makes the packing of the mixed phase independent of thread timing
+    srv = rbd.Server(arena_bytes=512 << 20, n_streams=4, max_batch_requests=256, max_wait_us=2000.0)
     alone = run_all(srv, models, reqs, together=False)
     mixed = run_all(srv, models, reqs, together=True)
     st = srv.stats()
@@ -148,7 +149,8 @@ def test_groups_split_at_the_byte_cap(env):
     for k in range(16):
         st = W.states(d, B, 300 + k)
         reqs.append(("humanoid30", rbd.OP_FWD_DYN, [x.astype(np.float32) for x in (st.q, st.qd, st.tau)]))
-    srv = rbd.Server(arena_bytes=1 << 30, n_streams=2, max_batch_requests=1024)
+    # a gather window longer than the submission loop: packing then depends only on the cap
+    srv = rbd.Server(arena_bytes=1 << 30, n_streams=2, max_batch_requests=1024, max_wait_us=50000.0)
     outs = run_all(srv, models, reqs, together=True)
     st = srv.stats()
     srv.close()
