@@ -134,7 +134,13 @@ def cpu_baseline(desc, st, budget_s):
         done1 += m
     dt1 = time.perf_counter() - t1
     O.set_threads(prev)
-    return {"value": done / dt, "unit": "evals/s", "cores": cores, "kind": "oracle",
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            model = next((ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name")), model)
+    except OSError:
+        pass
+    return {"value": done / dt, "unit": "evals/s", "cores": cores, "kind": "oracle", "cpu_model": model,
             "sample": f"{done} humanoid30 fwd_dyn evals (FP64, branch-sparse L^T L) = {done // n} passes over "
                       f"the first {n} states of the batch, {dt:.1f} s wall",
             "one_core_evals_per_s": done1 / dt1}
