@@ -72,7 +72,8 @@ def read_counters():
 
 def counters_driver():
     """The run the counter summaries are taken from: five humanoid fwd_dyn
-    launches at batch 65536, then three plain 512 MiB device copies (the
+    launches at batch 65536, three each of crba, fk and jacobian (all 30
+    frames) on the same states, then three plain 512 MiB device copies (the
     calibration kernel for FETCH_SIZE / WRITE_SIZE)."""
     import torch
 
@@ -85,6 +86,12 @@ def counters_driver():
     out = torch.empty((desc.nv, BATCH), dtype=torch.float32, device="cuda")
     for _ in range(5):
         rbd.fwd_dyn(m, q, qd, tau, out=out)
+    # the HBM-bound kernels of the same batch, three launches each
+    for fn in (lambda: rbd.crba(m, q), lambda: rbd.fk(m, q), lambda: rbd.jacobian(m, q)):
+        for _ in range(3):
+            fn()
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
     a = torch.empty(128 << 20, dtype=torch.float32, device="cuda")
     b = torch.empty_like(a)
     for _ in range(3):
