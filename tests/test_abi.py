@@ -147,3 +147,11 @@ def test_server_null_handles(rbd):
     assert L.rbd_server_submit(None, None, 0, 1, None, None, C.byref(t)) == 1
     assert L.rbd_server_wait(None, 1, 0.0, None) == 1
     assert L.rbd_server_destroy(None) == 0
+
+
+def test_parity_tests_cover_every_compiled_topology():
+    """The GPU parity lists name every topology the library compiles, and nothing else."""
+    from paper_2604_04310_amd.build import topologies
+    from tests.test_gpu_parity import EXTRA_TOPOLOGIES, MODELS
+    assert set(MODELS) | set(EXTRA_TOPOLOGIES) == set(topologies())
+    assert not set(MODELS) & set(EXTRA_TOPOLOGIES)

@@ -201,6 +201,39 @@ def test_fwd_dyn_jvp_parity(rbd, name):
     assert np.array_equal(host(rbd.fwd_dyn_jvp(m, *args)), host(dqdd))
 
 
+# The remaining compiled chains, each with its own random inertial parameters. Together with MODELS
+# they cover every topology in the library (a CPU test checks that the two lists stay complete).
+EXTRA_TOPOLOGIES = {f"chain{n}": (n, 40 + n) for n in (3, 4, 5, 6, 8)}
+
+
+@pytest.mark.parametrize("name", list(EXTRA_TOPOLOGIES))
+def test_every_compiled_chain(rbd, name):
+    """Every row on a chain the per-op tests above do not visit, at a ragged batch of 300."""
+    n, seed = EXTRA_TOPOLOGIES[name]
+    desc = W.random_tree(list(range(-1, n - 1)), False, seed)
+    m = rbd.Model(desc, 0)
+    B = 300
+    st = W.states(desc, B, seed + 100)
+    q, qd, tau = gpu(st.q), gpu(st.qd), gpu(st.tau)
+    ref_qdd = O.fwd_dyn(desc, st.q, st.qd, st.tau)
+    assert rel_err(host(rbd.fwd_dyn(m, q, qd, tau)), ref_qdd) < TOL_QDD
+    assert rel_err(host(rbd.aba(m, q, qd, tau)), ref_qdd) < TOL_QDD
+    assert rel_err(host(rbd.rnea(m, q, qd, gpu(ref_qdd))), O.rnea(desc, st.q, st.qd, ref_qdd)) < TOL_TAU
+    M = host(rbd.crba(m, q)).reshape(B, n, n)
+    ref_M = O.crba(desc, st.q)
+    assert (np.abs(M - ref_M).reshape(B, -1).max(1) / np.abs(ref_M).reshape(B, -1).max(1)).max() < TOL_M
+    assert rel_err(host(rbd.fk(m, q)), O.fk(desc, st.q).reshape(B, -1)) < TOL_KIN
+    frames = np.arange(n, dtype=np.int32)
+    assert rel_err(host(rbd.jacobian(m, q, frames)), O.jacobian(desc, st.q, frames).reshape(B, -1)) < TOL_KIN
+    gbar = W.cotangent(n, B, seed + 101)
+    gs = rbd.fwd_dyn_vjp(m, q, qd, tau, gpu(gbar))
+    assert vjp_err([host(x) for x in gs], list(O.fwd_dyn_vjp_fd(desc, st.q, st.qd, st.tau, gbar, h=1e-6))) < TOL_VJP
+    rng = np.random.Generator(np.random.PCG64(seed + 102))
+    dx = [W._f32(rng.normal(size=x.shape)) for x in (st.q, st.qd, st.tau)]
+    dqdd = host(rbd.fwd_dyn_jvp(m, q, qd, tau, *[gpu(x) for x in dx]))
+    assert vjp_err([dqdd], [O.fwd_dyn_jvp_fd(desc, st.q, st.qd, st.tau, *dx)]) < TOL_VJP
+
+
 def test_jvp_vjp_duality_on_gpu(rbd):
     """<gbar, J dx> from the tangent kernel equals <J^T gbar, dx> from the adjoint kernel."""
     desc, m = model_of(rbd, "humanoid30")
