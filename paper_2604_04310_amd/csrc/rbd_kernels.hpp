@@ -265,31 +265,41 @@ struct RowAlias {
 };
 
 // MODE 0: g_tau only; 1: adjoint with q-double-dot and lam in registers (some
-// output absent); 2: adjoint with both parked in g_qd and g_tau.
+// output absent); 2: adjoint with both parked in g_qd and g_tau (passed again
+// as park_qdd and park_lam); 3 (large trees): as 2, parked where the launcher
+// chooses, g_qd optional.
 template <class TP, int MODE>
 __global__ __launch_bounds__(kBlock) void k_fwd_dyn_vjp(const float* __restrict__ tab, int64_t batch, int64_t ld,
                                                         const float* __restrict__ q, const float* __restrict__ qd,
                                                         const float* __restrict__ tau,
                                                         const float* __restrict__ gqdd, float* gq, float* gqd,
-                                                        float* gtau) {
+                                                        float* gtau, float* park_qdd, float* park_lam) {
   RBD_LANE_IO(TP);
   const uint32_t b = lane_id();
   if (b >= batch) return;
   const In qi{q, ld, b}, qdi{qd, ld, b}, ti{tau, ld, b}, gi{gqdd, ld, b};
   const OutOpt<OutAlias> gqo{OutAlias{gq, ld, b}, gq != nullptr};
-  if constexpr (MODE == 2 && TP::NV > 16) {
+  if constexpr (MODE >= 2 && TP::NV > 16) {
     // the two sweeps of vjp_lane_parked, the second on fresh views (its own
     // table and input pointers and row stride): a large tree's first sweep
     // uses every register, and values kept for the second one spill
     // (measured: 1028 -> 400 B/lane of scratch, 126 -> 108 us for the
     // humanoid; a small tree is faster keeping them)
-    const OutAliasP pd{{gqd, ld, b}}, pt{{gtau, ld, b}};
+    // q-double-dot and lam park in g_qd and g_tau (MODE 2) or in park_qdd and
+    // park_lam (MODE 3, see the launcher)
+    float* const pq = MODE == 2 ? gqd : park_qdd;
+    float* const pl = MODE == 2 ? gtau : park_lam;
+    const OutAliasP pd{{pq, ld, b}}, pt{{pl, ld, b}};
     fwd_dyn_lane<TP, 2>(tab, qi, qdi, RhsTwo<In>{ti, gi}, SinkTwo<OutAliasP>{pd, pt});
     sweep_boundary();
     const int64_t l2 = opaque(ld);
-    id_adjoint_lane<TP>(opaque(tab), In{opaque(q), l2, b}, In{opaque(qd), l2, b}, InAlias{gqd, l2, b},
-                        InAlias{gtau, l2, b}, OutOpt<OutAlias>{OutAlias{gq, l2, b}, gq != nullptr},
-                        OutAlias{gqd, l2, b});
+    const OutOpt<OutAlias> gqo2{OutAlias{gq, l2, b}, gq != nullptr};
+    if constexpr (MODE == 2)
+      id_adjoint_lane<TP>(opaque(tab), In{opaque(q), l2, b}, In{opaque(qd), l2, b}, InAlias{pq, l2, b},
+                          InAlias{pl, l2, b}, gqo2, OutAlias{gqd, l2, b});
+    else
+      id_adjoint_lane<TP>(opaque(tab), In{opaque(q), l2, b}, In{opaque(qd), l2, b}, InAlias{pq, l2, b},
+                          InAlias{pl, l2, b}, gqo2, OutOpt<OutAlias>{OutAlias{gqd, l2, b}, gqd != nullptr});
   } else if constexpr (MODE == 2) {
     const OutAliasP pd{{gqd, ld, b}}, pt{{gtau, ld, b}};
     vjp_lane_parked<TP>(tab, qi, qdi, ti, gi, gqo, pd, pt, InAlias{gqd, ld, b}, InAlias{gtau, ld, b});
@@ -405,6 +415,23 @@ __global__ __launch_bounds__(kBlock) void k_packed(const float* __restrict__ tab
 // ------------------------------------------------------------------ launchers
 static inline int grid_for(int64_t batch) { return (int)((batch + kBlock - 1) / kBlock); }
 
+// Launch shape of the heavy per-lane kernels (forward dynamics, ABA, the two
+// derivatives, OSC), which are register-bound to one wave per SIMD. Up to
+// 65536 lanes (one wave for each of the 256 CUs x 4 SIMDs) they run in 64-lane
+// blocks: below that size 256-lane blocks would leave whole CUs idle and stack
+// four waves on the others, while 64-lane blocks spread the waves over every
+// CU (the humanoid's VJP and JVP at batch 32768 measured 3-5 % faster; at
+// 65536 the two shapes are equal). Larger batches keep 256-lane blocks, which
+// are as fast or faster there.
+constexpr int64_t kOneWavePerSimd = 256 * 4 * 64;
+struct Shape {
+  dim3 grid, block;
+};
+static inline Shape heavy_shape(int64_t batch) {
+  const int blk = batch <= kOneWavePerSimd ? 64 : kBlock;
+  return {dim3((unsigned)((batch + blk - 1) / blk)), dim3(blk)};
+}
+
 static inline rbd_status check_launch(const char* what) {
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) return fail(RBD_E_LAUNCH, "%s: launch failed: %s", what, hipGetErrorString(e));
@@ -444,44 +471,59 @@ struct Launch {
   template <bool EXT>
   static rbd_status fwd_dyn_t(const float* tab, int64_t batch, int64_t ld, const float* q, const float* qd,
                               const float* tau, const float* fext, float* qdd, hipStream_t s) {
+    const Shape sh = heavy_shape(batch);
     constexpr bool kPre = TP::NV > 16;
     if (preload_inputs(kPre))
-      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_fwd_dyn<TP, true, EXT>), dim3(grid_for(batch)), dim3(kBlock), 0, s, tab,
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_fwd_dyn<TP, true, EXT>), sh.grid, sh.block, 0, s, tab,
                          batch, ld, q, qd, tau, fext, qdd);
     else
-      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_fwd_dyn<TP, false, EXT>), dim3(grid_for(batch)), dim3(kBlock), 0, s,
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_fwd_dyn<TP, false, EXT>), sh.grid, sh.block, 0, s,
                          tab, batch, ld, q, qd, tau, fext, qdd);
     return check_launch("rbd_fwd_dyn");
   }
   template <bool EXT>
   static rbd_status aba_t(const float* tab, int64_t batch, int64_t ld, const float* q, const float* qd,
                           const float* tau, const float* fext, float* qdd, hipStream_t s) {
+    const Shape sh = heavy_shape(batch);
     constexpr bool kPre = TP::NV > 16;
     if (preload_inputs(kPre))
-      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_aba<TP, true, EXT>), dim3(grid_for(batch)), dim3(kBlock), 0, s, tab,
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_aba<TP, true, EXT>), sh.grid, sh.block, 0, s, tab,
                          batch, ld, q, qd, tau, fext, qdd);
     else
-      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_aba<TP, false, EXT>), dim3(grid_for(batch)), dim3(kBlock), 0, s, tab,
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_aba<TP, false, EXT>), sh.grid, sh.block, 0, s, tab,
                          batch, ld, q, qd, tau, fext, qdd);
     return check_launch("rbd_aba");
   }
   static rbd_status vjp(const float* tab, int64_t batch, int64_t ld, const float* q, const float* qd,
                         const float* tau, const float* gqdd, float* gq, float* gqd, float* gtau, hipStream_t s) {
+    const Shape sh = heavy_shape(batch);
+    // Between the solve and the adjoint sweep, q-double-dot and lam park in
+    // output rows that the adjoint overwrites only after reading them: g_qd
+    // and g_tau, or, for a large tree missing one of those, g_q shifted by
+    // nq - nv rows, so that DoF k lands in the q slot of its own body (the
+    // adjoint reads a body's entries in its forward step and writes that
+    // body's g_q in its backward step).
+    constexpr bool kVjpParkInGq = TP::NV > 16;
+    float* const gq_shift = gq ? gq + (TP::NQ - TP::NV) * ld : nullptr;
     if (gqd && gtau)
-      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_fwd_dyn_vjp<TP, 2>), dim3(grid_for(batch)), dim3(kBlock), 0, s, tab,
-                         batch, ld, q, qd, tau, gqdd, gq, gqd, gtau);
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_fwd_dyn_vjp<TP, 2>), sh.grid, sh.block, 0, s, tab,
+                         batch, ld, q, qd, tau, gqdd, gq, gqd, gtau, gqd, gtau);
+    else if (kVjpParkInGq && gq && (gqd || gtau))
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_fwd_dyn_vjp<TP, kVjpParkInGq ? 3 : 2>), sh.grid, sh.block, 0, s, tab,
+                         batch, ld, q, qd, tau, gqdd, gq, gqd, gtau, gqd ? gqd : gq_shift, gtau ? gtau : gq_shift);
     else if (gq || gqd)
-      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_fwd_dyn_vjp<TP, 1>), dim3(grid_for(batch)), dim3(kBlock), 0, s, tab,
-                         batch, ld, q, qd, tau, gqdd, gq, gqd, gtau);
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_fwd_dyn_vjp<TP, 1>), sh.grid, sh.block, 0, s, tab,
+                         batch, ld, q, qd, tau, gqdd, gq, gqd, gtau, gqd, gtau);
     else
-      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_fwd_dyn_vjp<TP, 0>), dim3(grid_for(batch)), dim3(kBlock), 0, s, tab,
-                         batch, ld, q, qd, tau, gqdd, gq, gqd, gtau);
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_fwd_dyn_vjp<TP, 0>), sh.grid, sh.block, 0, s, tab,
+                         batch, ld, q, qd, tau, gqdd, gq, gqd, gtau, gqd, gtau);
     return check_launch("rbd_fwd_dyn_vjp");
   }
   static rbd_status jvp(const float* tab, int64_t batch, int64_t ld, const float* q, const float* qd,
                         const float* tau, const float* dq, const float* dqd, const float* dtau, float* qdd,
                         float* dqdd, hipStream_t s) {
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_fwd_dyn_jvp<TP>), dim3(grid_for(batch)), dim3(kBlock), 0, s, tab, batch, ld,
+    const Shape sh = heavy_shape(batch);
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_fwd_dyn_jvp<TP>), sh.grid, sh.block, 0, s, tab, batch, ld,
                        q, qd, tau, dq, dqd, dtau, qdd, dqdd);
     return check_launch("rbd_fwd_dyn_jvp");
   }
@@ -493,12 +535,13 @@ struct Launch {
   }
   static rbd_status osc(const float* tab, int64_t batch, int64_t ld, const float* q, const float* qd,
                         const float* tgt, float kp, float kd, float kn, float* tau, hipStream_t s) {
+    const Shape sh = heavy_shape(batch);
     constexpr bool kPre = TP::NV > 16;
     if (preload_inputs(kPre))
-      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_osc<TP, true>), dim3(grid_for(batch)), dim3(kBlock), 0, s, tab, batch,
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_osc<TP, true>), sh.grid, sh.block, 0, s, tab, batch,
                          ld, q, qd, tgt, kp, kd, kn, tau);
     else
-      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_osc<TP, false>), dim3(grid_for(batch)), dim3(kBlock), 0, s, tab, batch,
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_osc<TP, false>), sh.grid, sh.block, 0, s, tab, batch,
                          ld, q, qd, tgt, kp, kd, kn, tau);
     return check_launch("rbd_osc");
   }

@@ -143,6 +143,26 @@ def test_fwd_dyn_vjp_parity(rbd, name):
     assert np.array_equal(host(gqd2), host(gqd)) and np.array_equal(host(gtau2), host(gtau))
 
 
+@pytest.mark.parametrize("name", ["chain7", "tree12f", "humanoid30"])
+def test_fwd_dyn_vjp_output_subsets(rbd, name):
+    """Every non-empty choice of outputs: the kernel variant changes with the choice (values held in
+    registers, parked in g_qd and g_tau, or parked in rows of g_q), the results do not."""
+    desc, m = model_of(rbd, name)
+    B = 300
+    st = W.states(desc, B, 209)
+    gbar = W.cotangent(desc.nv, B, 210)
+    args = [gpu(x) for x in (st.q, st.qd, st.tau, gbar)]
+    full = [host(x) for x in rbd.fwd_dyn_vjp(m, *args)]
+    ref = O.fwd_dyn_vjp_fd(desc, st.q, st.qd, st.tau, gbar, h=1e-6)
+    assert vjp_err(full, list(ref)) < TOL_VJP
+    for want in [(a, b, c) for a in (0, 1) for b in (0, 1) for c in (0, 1) if a or b or c]:
+        outs = rbd.fwd_dyn_vjp(m, *args, want=tuple(bool(w) for w in want))
+        for w, o, f in zip(want, outs, full):
+            assert (o is not None) == bool(w)
+            if w:  # the same arithmetic; FP32 contraction may differ between variants
+                assert rel_err(host(o), f) < 1e-4, want
+
+
 @pytest.mark.parametrize("name", list(MODELS))
 def test_external_force_parity(rbd, name):
     """rnea, fwd_dyn and aba with per-body external forces (world axes) against the oracle."""
