@@ -160,7 +160,8 @@ rbd_status rbd_aba(const rbd_model* model, int64_t batch, int64_t ld, const floa
  * as M^-1 (dtau - dID/dq dq - dID/dqd dqd) at qdd = FD(q, qd, tau): the fused
  * forward dynamics, a sweep of tangent inverse dynamics, then a solve with M,
  * all in one kernel. qdd (nullable) also receives the forward dynamics. All
- * inputs are required. */
+ * inputs are required. The forward dynamics is kept in qdd (or in dqdd) between
+ * the sweeps, so qdd and dqdd must not overlap (RBD_E_INVAL). */
 rbd_status rbd_fwd_dyn_jvp(const rbd_model* model, int64_t batch, int64_t ld, const float* q, const float* qd,
                            const float* tau, const float* dq, const float* dqd, const float* dtau, float* qdd,
                            float* dqdd, hipStream_t stream);
@@ -169,7 +170,9 @@ rbd_status rbd_fwd_dyn_jvp(const rbd_model* model, int64_t batch, int64_t ld, co
  * cotangent g_qdd [nv][ld]:
  * g_q = g_qdd^T dqdd/dq [nq][ld] (raw quaternion components included),
  * g_qd = g_qdd^T dqdd/dqd [nv][ld], g_tau = g_qdd^T dqdd/dtau = M^-1 g_qdd
- * [nv][ld]. Any of the three outputs may be NULL (not computed). */
+ * [nv][ld]. Any of the three outputs may be NULL (not computed). Between the
+ * kernel's two sweeps the requested outputs hold the forward dynamics and
+ * M^-1 g_qdd, so they must not overlap one another (RBD_E_INVAL). */
 rbd_status rbd_fwd_dyn_vjp(const rbd_model* model, int64_t batch, int64_t ld, const float* q, const float* qd,
                            const float* tau, const float* g_qdd, float* g_q, float* g_qd, float* g_tau,
                            hipStream_t stream);

@@ -194,6 +194,19 @@ static rbd_status check_batch(const rbd_model* m, int64_t batch, int64_t ld, con
   return RBD_OK;
 }
 
+// Whether two arrays of the SoA layout, a [ra][ld] and b [rb][ld] with batch
+// columns used in each row, share an element. With the offset b - a = q ld + r
+// (0 <= r < ld), a shared element needs a row difference of q with a column
+// difference of r, or q + 1 with r - ld.
+static bool soa_overlap(const float* a, int64_t ra, const float* b, int64_t rb, int64_t ld, int64_t batch) {
+  if (!a || !b || batch == 0) return false;
+  const int64_t d = ((int64_t)(intptr_t)b - (int64_t)(intptr_t)a) / (int64_t)sizeof(float);
+  int64_t q = d / ld, r = d % ld;
+  if (r < 0) { r += ld; q -= 1; }
+  const bool rows_q = q > -rb && q < ra, rows_q1 = q + 1 > -rb && q + 1 < ra;
+  return (rows_q && r < batch) || (rows_q1 && ld - r < batch);
+}
+
 }  // namespace rbd
 
 using namespace rbd;
@@ -346,6 +359,9 @@ rbd_status rbd_fwd_dyn_jvp(const rbd_model* m, int64_t batch, int64_t ld, const 
   if (st != RBD_OK) return st;
   if (batch > 0 && (!q || !qd || !tau || !dq || !dqd || !dtau || !dqdd))
     return fail(RBD_E_INVAL, "rbd_fwd_dyn_jvp: NULL array");
+  // qdd is parked in one of the outputs between sweeps
+  if (soa_overlap(qdd, m->nv, dqdd, m->nv, ld, batch))
+    return fail(RBD_E_INVAL, "rbd_fwd_dyn_jvp: qdd and dqdd overlap");
   if ((st = use_device(m->device)) != RBD_OK) return st;
   return launch_fwd_dyn_jvp(m, batch, ld, q, qd, tau, dq, dqd, dtau, qdd, dqdd, s);
 }
@@ -390,6 +406,10 @@ rbd_status rbd_fwd_dyn_vjp(const rbd_model* m, int64_t batch, int64_t ld, const 
   rbd_status st = check_batch(m, batch, ld, "rbd_fwd_dyn_vjp");
   if (st != RBD_OK) return st;
   if (batch > 0 && (!q || !qd || !tau || !g_qdd)) return fail(RBD_E_INVAL, "rbd_fwd_dyn_vjp: NULL input array");
+  // the outputs hold intermediate values between the kernel's two sweeps
+  if (soa_overlap(g_q, m->nq, g_qd, m->nv, ld, batch) || soa_overlap(g_q, m->nq, g_tau, m->nv, ld, batch) ||
+      soa_overlap(g_qd, m->nv, g_tau, m->nv, ld, batch))
+    return fail(RBD_E_INVAL, "rbd_fwd_dyn_vjp: output arrays overlap");
   if ((st = use_device(m->device)) != RBD_OK) return st;
   return launch_fwd_dyn_vjp(m, batch, ld, q, qd, tau, g_qdd, g_q, g_qd, g_tau, s);
 }

@@ -387,6 +387,32 @@ def test_batch_limit_is_checked_before_launch(rbd):
     assert b"2^30" in rbd.lib().rbd_last_error()
 
 
+def test_overlapping_derivative_outputs_are_rejected(rbd):
+    """The VJP and JVP keep intermediate values in their outputs, so outputs that share an element are an
+    argument error (checked before launch: the addresses below are never dereferenced); outputs that
+    interleave in one strided buffer without sharing an element are accepted and exact."""
+    import ctypes as C
+    desc, m = model_of(rbd, "humanoid30")
+    L = rbd.lib()
+    p, o = C.c_void_p(1 << 20), C.c_void_p((1 << 20) + 4 * 3)
+    assert L.rbd_fwd_dyn_vjp(m.handle, 8, 8, p, p, p, p, None, p, o, None) == 1
+    assert b"overlap" in L.rbd_last_error()
+    assert L.rbd_fwd_dyn_vjp(m.handle, 8, 8, p, p, p, p, o, p, None, None) == 1
+    assert L.rbd_fwd_dyn_jvp(m.handle, 8, 8, p, p, p, p, p, p, o, o, None) == 1
+    B, ld = 8, 16
+    st = W.states(desc, B, 217)
+    gbar = W.cotangent(desc.nv, B, 218)
+    ins = [gpu(x, ld) for x in (st.q, st.qd, st.tau, gbar)]
+    buf = torch.full((desc.nv, ld), float("nan"), dtype=torch.float32, device="cuda")
+    ptr = buf.data_ptr()
+    rc = L.rbd_fwd_dyn_vjp(m.handle, B, ld, *[C.c_void_p(x.data_ptr()) for x in ins], None, C.c_void_p(ptr),
+                           C.c_void_p(ptr + 4 * B), C.c_void_p(torch.cuda.current_stream().cuda_stream))
+    assert rc == 0
+    _, gqd, gtau = rbd.fwd_dyn_vjp(m, *[gpu(x) for x in (st.q, st.qd, st.tau, gbar)], want=(False, True, True))
+    got = host(buf)  # [ld, nv]: rows 0..B-1 hold g_qd, rows B..2B-1 hold g_tau
+    assert np.array_equal(got[:B], host(gqd)) and np.array_equal(got[B:], host(gtau))
+
+
 def test_invalid_arguments_raise(rbd):
     desc, m = model_of(rbd, "chain7")
     st = W.states(desc, 8, 216)
