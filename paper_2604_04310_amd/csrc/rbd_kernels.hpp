@@ -354,7 +354,10 @@ __global__ __launch_bounds__(kBlock) void k_diff_ik(const float* __restrict__ ta
 }
 
 // PRE as for k_fwd_dyn (q, qd and the target preloaded).
-template <class TP, bool PRE>
+// Inputs are loaded where they are used: preloading them (as k_fwd_dyn does
+// for large trees) held 83 more registers across a sweep that already spills,
+// and measured 99 us against 81 us for the humanoid at batch 65536.
+template <class TP>
 __global__ __launch_bounds__(kBlock) void k_osc(const float* __restrict__ tab, int64_t batch, int64_t ld,
                                                 const float* __restrict__ q, const float* __restrict__ qd,
                                                 const float* __restrict__ tgt, float kp, float kd, float kn,
@@ -362,18 +365,7 @@ __global__ __launch_bounds__(kBlock) void k_osc(const float* __restrict__ tab, i
   RBD_LANE_IO(TP);
   const uint32_t b = lane_id();
   if (b >= batch) return;
-  constexpr int E = TP::N - 1;
-  if constexpr (PRE) {
-    constexpr int NQ = TP::NQ, NV = TP::NV;
-    float qv[NQ], qdv[NV], tv[12];
-    const In qi{q, ld, b}, qdi{qd, ld, b}, ti{tgt, ld, b};
-    sfor<0, NQ>([&](auto K_) __attribute__((always_inline)) { qv[decltype(K_)::value] = qi(decltype(K_)::value); });
-    sfor<0, NV>([&](auto K_) __attribute__((always_inline)) { qdv[decltype(K_)::value] = qdi(decltype(K_)::value); });
-    sfor<0, 12>([&](auto K_) __attribute__((always_inline)) { tv[decltype(K_)::value] = ti(decltype(K_)::value); });
-    osc_lane<TP, E>(tab, RegView{qv}, RegView{qdv}, RegView{tv}, kp, kd, kn, Out{tau, ld, b});
-  } else {
-    osc_lane<TP, E>(tab, In{q, ld, b}, In{qd, ld, b}, In{tgt, ld, b}, kp, kd, kn, Out{tau, ld, b});
-  }
+  osc_lane<TP, TP::N - 1>(tab, In{q, ld, b}, In{qd, ld, b}, In{tgt, ld, b}, kp, kd, kn, Out{tau, ld, b});
 }
 
 // ---- packed launch for the serving runtime. One launch serves many requests
@@ -485,7 +477,9 @@ struct Launch {
   static rbd_status aba_t(const float* tab, int64_t batch, int64_t ld, const float* q, const float* qd,
                           const float* tau, const float* fext, float* qdd, hipStream_t s) {
     const Shape sh = heavy_shape(batch);
-    constexpr bool kPre = TP::NV > 16;
+    // with external forces the articulated-body sweep is faster loading its
+    // inputs in place (humanoid: 77.8 vs 81.6 us)
+    constexpr bool kPre = TP::NV > 16 && !EXT;
     if (preload_inputs(kPre))
       hipLaunchKernelGGL(HIP_KERNEL_NAME(k_aba<TP, true, EXT>), sh.grid, sh.block, 0, s, tab,
                          batch, ld, q, qd, tau, fext, qdd);
@@ -536,13 +530,8 @@ struct Launch {
   static rbd_status osc(const float* tab, int64_t batch, int64_t ld, const float* q, const float* qd,
                         const float* tgt, float kp, float kd, float kn, float* tau, hipStream_t s) {
     const Shape sh = heavy_shape(batch);
-    constexpr bool kPre = TP::NV > 16;
-    if (preload_inputs(kPre))
-      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_osc<TP, true>), sh.grid, sh.block, 0, s, tab, batch,
-                         ld, q, qd, tgt, kp, kd, kn, tau);
-    else
-      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_osc<TP, false>), sh.grid, sh.block, 0, s, tab, batch,
-                         ld, q, qd, tgt, kp, kd, kn, tau);
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_osc<TP>), sh.grid, sh.block, 0, s, tab, batch, ld, q, qd, tgt, kp, kd, kn,
+                       tau);
     return check_launch("rbd_osc");
   }
   static rbd_status packed(int op, const float* tab, const void* table, int grid, hipStream_t s) {
