@@ -73,6 +73,12 @@ using OutAliasP = OutAliasPT<true>;
 // loads inside the previous one, where its registers are all in use.
 RBD_DI void sweep_boundary() { __builtin_amdgcn_sched_barrier(0); }
 
+// Registers of one lane holding a preloaded input vector.
+struct RegView {
+  const float* x;
+  RBD_DI float operator()(int k) const { return x[k]; }
+};
+
 template <class TP>
 __global__ __launch_bounds__(kBlock) void k_fk(const float* __restrict__ tab, int64_t batch, int64_t ld,
                                                const float* __restrict__ q, float* __restrict__ T) {
@@ -93,7 +99,9 @@ __global__ __launch_bounds__(kBlock) void k_jacobian(const float* __restrict__ t
 }
 
 // EXT: per-body external forces (fext, [6 n][ld]) enter the force balance.
-template <class TP, bool HAS_QDD, bool EXT>
+// PRE (no external forces): every input load is issued at entry, as in
+// k_fwd_dyn.
+template <class TP, bool HAS_QDD, bool EXT, bool PRE = false>
 __global__ __launch_bounds__(kBlock) void k_rnea(const float* __restrict__ tab, int64_t batch, int64_t ld,
                                                  const float* __restrict__ q, const float* __restrict__ qd,
                                                  const float* __restrict__ qdd, const float* __restrict__ fext,
@@ -101,7 +109,17 @@ __global__ __launch_bounds__(kBlock) void k_rnea(const float* __restrict__ tab, 
   RBD_LANE_IO(TP);
   const uint32_t b = lane_id();
   if (b >= batch) return;
-  if constexpr (EXT)
+  if constexpr (PRE && !EXT) {
+    constexpr int NQ = TP::NQ, NV = TP::NV;
+    float qv[NQ], qdv[NV], qddv[NV];
+    const In qi{q, ld, b}, qdi{qd, ld, b}, qddi{HAS_QDD ? qdd : qd, ld, b};
+    sfor<0, NQ>([&](auto K_) __attribute__((always_inline)) { qv[decltype(K_)::value] = qi(decltype(K_)::value); });
+    sfor<0, NV>([&](auto K_) __attribute__((always_inline)) {
+      qdv[decltype(K_)::value] = qdi(decltype(K_)::value);
+      if constexpr (HAS_QDD) qddv[decltype(K_)::value] = qddi(decltype(K_)::value);
+    });
+    rnea_lane<TP, HAS_QDD>(tab, RegView{qv}, RegView{qdv}, RegView{HAS_QDD ? qddv : qdv}, Out{tau, ld, b});
+  } else if constexpr (EXT)
     rnea_lane<TP, HAS_QDD>(tab, In{q, ld, b}, In{qd, ld, b}, In{HAS_QDD ? qdd : q, ld, b}, Out{tau, ld, b},
                            FextIn{{fext, ld, b}});
   else
@@ -126,12 +144,6 @@ template <class Y>
 struct SinkOne {
   Y x;
   RBD_DI void operator()(int, int k, float v) const { x(k, v); }
-};
-
-// Registers of one lane holding a preloaded input vector.
-struct RegView {
-  const float* x;
-  RBD_DI float operator()(int k) const { return x[k]; }
 };
 
 // PRE = true issues every input load of the lane at entry (106 for the
@@ -445,12 +457,21 @@ struct Launch {
   template <bool EXT>
   static rbd_status rnea_t(const float* tab, int64_t batch, int64_t ld, const float* q, const float* qd,
                            const float* qdd, const float* fext, float* tau, hipStream_t s) {
-    if (qdd)
+    constexpr bool kPre = TP::NV > 16 && !EXT;
+    if (kPre && preload_inputs(kPre)) {
+      if (qdd)
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_rnea<TP, true, EXT, kPre>), dim3(grid_for(batch)), dim3(kBlock), 0, s,
+                           tab, batch, ld, q, qd, qdd, fext, tau);
+      else
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_rnea<TP, false, EXT, kPre>), dim3(grid_for(batch)), dim3(kBlock), 0, s,
+                           tab, batch, ld, q, qd, qdd, fext, tau);
+    } else if (qdd) {
       hipLaunchKernelGGL(HIP_KERNEL_NAME(k_rnea<TP, true, EXT>), dim3(grid_for(batch)), dim3(kBlock), 0, s, tab,
                          batch, ld, q, qd, qdd, fext, tau);
-    else
+    } else {
       hipLaunchKernelGGL(HIP_KERNEL_NAME(k_rnea<TP, false, EXT>), dim3(grid_for(batch)), dim3(kBlock), 0, s, tab,
                          batch, ld, q, qd, qdd, fext, tau);
+    }
     return check_launch("rbd_rnea");
   }
   static rbd_status crba(const float* tab, int64_t batch, int64_t ld, const float* q, float* M, hipStream_t s) {
