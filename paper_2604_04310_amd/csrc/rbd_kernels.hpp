@@ -365,7 +365,6 @@ __global__ __launch_bounds__(kBlock) void k_diff_ik(const float* __restrict__ ta
   diff_ik_lane<TP, TP::N - 1>(tab, In{q, ld, b}, In{tgt, ld, b}, gain, lam2, Out{qd, ld, b});
 }
 
-// PRE as for k_fwd_dyn (q, qd and the target preloaded).
 // Inputs are loaded where they are used: preloading them (as k_fwd_dyn does
 // for large trees) held 83 more registers across a sweep that already spills,
 // and measured 99 us against 81 us for the humanoid at batch 65536.
