@@ -267,9 +267,23 @@ RBD_DI void xinr_acc(const M3& R, V3 r, const Inr& I, Inr& acc) {
   acc.yz = fdot(t1, r2, __builtin_fmaf(-w.y, r.z, __builtin_fmaf(-r.y, u.z, acc.yz)));
 }
 
+// sin and cos of a joint angle of any size (continuous joints accumulate
+// turns). The hardware instructions take revolutions and a bounded argument,
+// and q / 2 pi in FP32 would lose the angle's absolute accuracy as |q| grows,
+// so q is first reduced to r = q - k 2 pi, |r| <= pi, by Cody and Waite's
+// additive reduction (Software Manual for the Elementary Functions, 1980)
+// with 2 pi split into P1 + P2: P1 is 2 pi rounded to FP32, P2 the FP32
+// rounding of the remainder. fma(-k, P1, q) is exact (q and k P1 are
+// multiples of P1's ulp and their difference is below 8), so r carries one
+// rounding, about 2^-22 absolute, for |q| up to about 10^8. For |q| <= pi,
+// k = 0 and r = q exactly.
 RBD_DI void fsincos(float q, float& s, float& c) {
-  // hardware sin/cos take revolutions
-  const float t = q * 0.15915494309189535f;
+  constexpr float kInv2Pi = 0.15915494309189535f;
+  constexpr float kP1 = 6.28318548202514648f;     // 2 pi rounded to FP32
+  constexpr float kP2 = -1.74845553146951715e-7f;  // 2 pi - P1, rounded to FP32
+  const float k = __builtin_rintf(q * kInv2Pi);
+  const float r = __builtin_fmaf(-k, kP2, __builtin_fmaf(-k, kP1, q));
+  const float t = r * kInv2Pi;
   s = __builtin_amdgcn_sinf(t);
   c = __builtin_amdgcn_cosf(t);
 }

@@ -15,17 +15,9 @@ from tests._helpers import targets_near
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
-TREE12 = [-1, 0, 1, 1, 0, 4, 5, 5, 7, 0, 9, 10]
-MODELS = {
-    "chain1": lambda: W.random_tree([-1], False, 31),
-    "chain2": lambda: W.random_tree([-1, 0], False, 32),
-    "chain7": lambda: W.chain(7),
-    "free1": lambda: W.random_tree([-1], True, 33),
-    "tree12f": lambda: W.random_tree(TREE12, True, 34),
-    "humanoid30": lambda: W.humanoid(),
-}
+from tests._models import ALL, draw
 # OSC needs J of full row rank: at least six DoFs on the end effector's path
-OSC_MODELS = ["chain7", "free1", "tree12f", "humanoid30"]
+OSC_MODELS = ["chain7", "free1", "tree12f", "humanoid30", "chain7_rot", "tree12f_rot", "humanoid30_rot"]
 KP, KD, KN = 50.0, 10.0, 2.0
 GAIN, DAMP = 2.0, 0.05
 TOL = 1e-4
@@ -83,7 +75,7 @@ _models = {}
 
 def model_of(rbd, name):
     if name not in _models:
-        desc = MODELS[name]()
+        desc = ALL[name]()
         _models[name] = (desc, rbd.Model(desc, 0))
     return _models[name]
 
@@ -97,17 +89,17 @@ def host(t):
     return t.double().cpu().numpy().T
 
 
-def case(desc, B, seed):
-    st = W.states(desc, B, seed)
+def case(desc, B, seed, name=""):
+    st = draw(name, desc, B, seed)
     e = desc.n_bodies - 1
     tgt = W._f32(targets_near(O.fk(desc, st.q)[:, e], seed + 1))
     return st, e, tgt
 
 
-@pytest.mark.parametrize("name", list(MODELS))
+@pytest.mark.parametrize("name", list(ALL))
 def test_diff_ik_parity(rbd, name):
     desc, m = model_of(rbd, name)
-    st, e, tgt = case(desc, 1000, 240)
+    st, e, tgt = case(desc, 1000, 240, name)
     qd = host(rbd.diff_ik(m, gpu(st.q), gpu(tgt), GAIN, DAMP))
     assert within_bar(qd, CT.diff_ik(desc, st.q, e, tgt, GAIN, DAMP), floor_ik(desc, st.q, e, tgt)) < 1.0
 
@@ -115,7 +107,7 @@ def test_diff_ik_parity(rbd, name):
 @pytest.mark.parametrize("name", OSC_MODELS)
 def test_osc_parity(rbd, name):
     desc, m = model_of(rbd, name)
-    st, e, tgt = case(desc, 1000, 241)
+    st, e, tgt = case(desc, 1000, 241, name)
     tau = host(rbd.osc(m, gpu(st.q), gpu(st.qd), gpu(tgt), KP, KD, KN))
     ref = CT.osc(desc, st.q, st.qd, e, tgt, KP, KD, KN)
     assert within_bar(tau, ref, floor_osc(desc, st.q, e, ref)) < 1.0

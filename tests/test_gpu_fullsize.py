@@ -3,7 +3,8 @@
 Chain of 7 at batch 2^20 (fwd_dyn, rnea: first 4096 states against the oracle,
 all outputs finite), the 35-DoF humanoid at batch 65536 (fwd_dyn by both the
 factorised solve and the articulated-body algorithm on every instance; crba,
-fk and jacobian on a strided sample; with external forces on a sample), and
+fk and jacobian on a strided sample; with external forces on a sample; the
+same rows for a URDF-style humanoid with rotated joint origins), and
 the adjoint and the forward-mode derivative at 2^18 (chain) and 32768
 (humanoid) against central differences on 256 states.
 """
@@ -71,6 +72,36 @@ def test_humanoid_batch_65536(rbd):
     del qdd_aba
     assert rel_err(cols(h, all_idx), O.rnea(desc, st.q, st.qd)) < 1e-4
     idx = np.arange(0, B, 61)
+    M = rbd.crba(m, q)
+    Mh = cols(M, idx).reshape(len(idx), -1)
+    Mr = O.crba(desc, st.q[idx]).reshape(len(idx), -1)
+    assert (np.abs(Mh - Mr).max(1) / np.abs(Mr).max(1)).max() < 1e-5
+    del M
+    T = rbd.fk(m, q)
+    assert rel_err(cols(T, idx), O.fk(desc, st.q[idx]).reshape(len(idx), -1)) < 1e-5
+    del T
+    J = rbd.jacobian(m, q)
+    assert rel_err(cols(J, idx), O.jacobian(desc, st.q[idx]).reshape(len(idx), -1)) < 1e-5
+    del J
+
+
+def test_rotated_humanoid_batch_65536(rbd):
+    """The URDF-style humanoid (random joint-origin rotations, gravity in a random direction, joint
+    angles up to 1000 rad) at the benchmark size: fwd_dyn on every instance, rnea, crba, fk and
+    jacobian on a strided sample."""
+    desc = W.humanoid(64, rotated=True, gravity=W.tilted_gravity(65))
+    m = rbd.Model(desc, 0)
+    B = 65536
+    st = W.states(desc, B, 110, q_range=1000.0)
+    q, qd, tau = gpu(st.q), gpu(st.qd), gpu(st.tau)
+    qdd = rbd.fwd_dyn(m, q, qd, tau)
+    torch.cuda.synchronize()
+    assert torch.isfinite(qdd).all()
+    assert rel_err(cols(qdd, np.arange(B)), O.fwd_dyn(desc, st.q, st.qd, st.tau)) < 1e-4
+    del qdd
+    idx = np.arange(0, B, 61)
+    h = rbd.rnea(m, q, qd)
+    assert rel_err(cols(h, idx), O.rnea(desc, st.q[idx], st.qd[idx])) < 1e-4
     M = rbd.crba(m, q)
     Mh = cols(M, idx).reshape(len(idx), -1)
     Mr = O.crba(desc, st.q[idx]).reshape(len(idx), -1)

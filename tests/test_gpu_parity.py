@@ -14,21 +14,12 @@ import pytest
 import oracle as O
 import workloads as W
 from tests._helpers import rel_err, vjp_err
+from tests._models import ALL, MODELS, ROTATED, TREE12, draw  # noqa: F401 (MODELS: the topology list)
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 TOL_QDD, TOL_TAU, TOL_M, TOL_KIN, TOL_VJP = 1e-4, 1e-4, 1e-5, 1e-5, 1e-3
-
-TREE12 = [-1, 0, 1, 1, 0, 4, 5, 5, 7, 0, 9, 10]
-MODELS = {
-    "chain1": lambda: W.random_tree([-1], False, 31),
-    "chain2": lambda: W.random_tree([-1, 0], False, 32),
-    "chain7": lambda: W.chain(7),
-    "free1": lambda: W.random_tree([-1], True, 33),
-    "tree12f": lambda: W.random_tree(TREE12, True, 34),
-    "humanoid30": lambda: W.humanoid(),
-}
 
 
 @pytest.fixture(scope="module")
@@ -45,7 +36,7 @@ _models = {}
 
 def model_of(rbd, name):
     if name not in _models:
-        desc = MODELS[name]()
+        desc = ALL[name]()
         _models[name] = (desc, rbd.Model(desc, 0))
     return _models[name]
 
@@ -69,28 +60,28 @@ def host(t):
 BATCH = 1000  # four 256-lane blocks, the last one ragged
 
 
-@pytest.mark.parametrize("name", list(MODELS))
+@pytest.mark.parametrize("name", list(ALL))
 def test_fwd_dyn_parity(rbd, name):
     desc, m = model_of(rbd, name)
-    st = W.states(desc, BATCH, 201)
+    st = draw(name, desc, BATCH, 201)
     qdd = rbd.fwd_dyn(m, gpu(st.q), gpu(st.qd), gpu(st.tau))
     assert rel_err(host(qdd), O.fwd_dyn(desc, st.q, st.qd, st.tau)) < TOL_QDD
 
 
-@pytest.mark.parametrize("name", list(MODELS))
+@pytest.mark.parametrize("name", list(ALL))
 def test_aba_parity(rbd, name):
     """Articulated-body forward dynamics against the oracle's own ABA and its LTL solve."""
     desc, m = model_of(rbd, name)
-    st = W.states(desc, BATCH, 201)
+    st = draw(name, desc, BATCH, 201)
     qdd = host(rbd.aba(m, gpu(st.q), gpu(st.qd), gpu(st.tau)))
     assert rel_err(qdd, O.fwd_dyn(desc, st.q, st.qd, st.tau, method=O.METHOD_ABA)) < TOL_QDD
     assert rel_err(qdd, O.fwd_dyn(desc, st.q, st.qd, st.tau)) < TOL_QDD
 
 
-@pytest.mark.parametrize("name", list(MODELS))
+@pytest.mark.parametrize("name", list(ALL))
 def test_rnea_parity(rbd, name):
     desc, m = model_of(rbd, name)
-    st = W.states(desc, BATCH, 202)
+    st = draw(name, desc, BATCH, 202)
     qdd_in = W.cotangent(desc.nv, BATCH, 203) * 3.0
     tau = rbd.rnea(m, gpu(st.q), gpu(st.qd), gpu(qdd_in))
     assert rel_err(host(tau), O.rnea(desc, st.q, st.qd, qdd_in)) < TOL_TAU
@@ -98,10 +89,10 @@ def test_rnea_parity(rbd, name):
     assert rel_err(host(h), O.rnea(desc, st.q, st.qd)) < TOL_TAU
 
 
-@pytest.mark.parametrize("name", list(MODELS))
+@pytest.mark.parametrize("name", list(ALL))
 def test_crba_parity(rbd, name):
     desc, m = model_of(rbd, name)
-    st = W.states(desc, BATCH, 204)
+    st = draw(name, desc, BATCH, 204)
     M = host(rbd.crba(m, gpu(st.q))).reshape(BATCH, desc.nv, desc.nv)
     ref = O.crba(desc, st.q)
     err = (np.abs(M - ref).reshape(BATCH, -1).max(1) / np.abs(ref).reshape(BATCH, -1).max(1)).max()
@@ -109,18 +100,18 @@ def test_crba_parity(rbd, name):
     assert np.array_equal(M, np.swapaxes(M, 1, 2))  # written symmetric, bit for bit
 
 
-@pytest.mark.parametrize("name", list(MODELS))
+@pytest.mark.parametrize("name", list(ALL))
 def test_fk_parity(rbd, name):
     desc, m = model_of(rbd, name)
-    st = W.states(desc, BATCH, 205)
+    st = draw(name, desc, BATCH, 205)
     T = host(rbd.fk(m, gpu(st.q)))
     assert rel_err(T, O.fk(desc, st.q).reshape(BATCH, -1)) < TOL_KIN
 
 
-@pytest.mark.parametrize("name", list(MODELS))
+@pytest.mark.parametrize("name", list(ALL))
 def test_jacobian_parity(rbd, name):
     desc, m = model_of(rbd, name)
-    st = W.states(desc, BATCH, 206)
+    st = draw(name, desc, BATCH, 206)
     rng = np.random.Generator(np.random.PCG64(7))
     frames = np.concatenate([np.arange(desc.n_bodies), rng.integers(0, desc.n_bodies, 3)]).astype(np.int32)
     J = host(rbd.jacobian(m, gpu(st.q), frames))
@@ -129,11 +120,11 @@ def test_jacobian_parity(rbd, name):
     assert np.all(J[ref == 0.0] == 0.0)  # non-ancestor columns are exact zeros
 
 
-@pytest.mark.parametrize("name", list(MODELS))
+@pytest.mark.parametrize("name", list(ALL))
 def test_fwd_dyn_vjp_parity(rbd, name):
     desc, m = model_of(rbd, name)
     B = 256
-    st = W.states(desc, B, 207)
+    st = draw(name, desc, B, 207)
     gbar = W.cotangent(desc.nv, B, 208)
     gq, gqd, gtau = rbd.fwd_dyn_vjp(m, gpu(st.q), gpu(st.qd), gpu(st.tau), gpu(gbar))
     rq, rqd, rtau = O.fwd_dyn_vjp_fd(desc, st.q, st.qd, st.tau, gbar, h=1e-6)
@@ -143,13 +134,13 @@ def test_fwd_dyn_vjp_parity(rbd, name):
     assert np.array_equal(host(gqd2), host(gqd)) and np.array_equal(host(gtau2), host(gtau))
 
 
-@pytest.mark.parametrize("name", ["chain7", "tree12f", "humanoid30"])
+@pytest.mark.parametrize("name", ["chain7", "tree12f", "humanoid30", "humanoid30_rot"])
 def test_fwd_dyn_vjp_output_subsets(rbd, name):
     """Every non-empty choice of outputs: the kernel variant changes with the choice (values held in
     registers, parked in g_qd and g_tau, or parked in rows of g_q), the results do not."""
     desc, m = model_of(rbd, name)
     B = 300
-    st = W.states(desc, B, 209)
+    st = draw(name, desc, B, 209)
     gbar = W.cotangent(desc.nv, B, 210)
     args = [gpu(x) for x in (st.q, st.qd, st.tau, gbar)]
     full = [host(x) for x in rbd.fwd_dyn_vjp(m, *args)]
@@ -163,11 +154,11 @@ def test_fwd_dyn_vjp_output_subsets(rbd, name):
                 assert rel_err(host(o), f) < 1e-4, want
 
 
-@pytest.mark.parametrize("name", list(MODELS))
+@pytest.mark.parametrize("name", list(ALL))
 def test_external_force_parity(rbd, name):
     """rnea, fwd_dyn and aba with per-body external forces (world axes) against the oracle."""
     desc, m = model_of(rbd, name)
-    st = W.states(desc, BATCH, 220)
+    st = draw(name, desc, BATCH, 220)
     rng = np.random.Generator(np.random.PCG64(221))
     fext = W._f32(rng.normal(0.0, 5.0, size=(BATCH, desc.n_bodies, 6)))
     fx = gpu(fext.reshape(BATCH, -1))
@@ -204,12 +195,12 @@ def test_external_weight_support_on_gpu(rbd):
         assert np.abs(qdd).max() < TOL_QDD * a_scale
 
 
-@pytest.mark.parametrize("name", list(MODELS))
+@pytest.mark.parametrize("name", list(ALL))
 def test_fwd_dyn_jvp_parity(rbd, name):
     """Forward-mode derivative against the oracle's central differences along the same tangent."""
     desc, m = model_of(rbd, name)
     B = 256
-    st = W.states(desc, B, 230)
+    st = draw(name, desc, B, 230)
     rng = np.random.Generator(np.random.PCG64(231))
     dq, dqd, dtau = (W._f32(rng.normal(size=x.shape)) for x in (st.q, st.qd, st.tau))
     args = [gpu(x) for x in (st.q, st.qd, st.tau, dq, dqd, dtau)]
@@ -312,7 +303,8 @@ def test_batch_edges(rbd, B):
 
 
 def test_special_states(rbd):
-    """q = 0, q = +-pi, qd = 0, large qd, and a scaled (non-unit) quaternion."""
+    """q = 0, q = +-pi, qd = 0, large qd, joint angles of up to 10^6 rad and exact multiples of
+    pi / 2 far from zero, and a scaled (non-unit) quaternion."""
     desc, m = model_of(rbd, "humanoid30")
     st = W.states(desc, 64, 212)
     q, qd, tau = st.q.copy(), st.qd.copy(), st.tau.copy()
@@ -321,6 +313,9 @@ def test_special_states(rbd):
     q[16:24, 7:] = -np.pi
     qd[24:32] = 0.0
     qd[32:40] *= 20.0
+    rng = np.random.Generator(np.random.PCG64(219))
+    q[40:48, 7:] = rng.uniform(-1e6, 1e6, size=(8, desc.nq - 7))
+    q[48:56, 7:] = 0.5 * np.pi * rng.integers(-4000, 4000, size=(8, desc.nq - 7))
     q = W._f32(q)
     qd = W._f32(qd)
     qdd = host(rbd.fwd_dyn(m, gpu(q), gpu(qd), gpu(tau)))

@@ -120,7 +120,10 @@ def random_axis(rng: np.random.Generator) -> np.ndarray:
     return a / np.linalg.norm(a)
 
 
-def _random_bodies(rng, parent, joint_type, name):
+def _random_bodies(rng, parent, joint_type, name, rotated=False, gravity=None):
+    """rotated: each revolute joint frame gets a uniform random fixed rotation
+    (as URDF joint origins carry); otherwise the fixed rotation is identity.
+    gravity: the gravity vector (default (0, 0, -9.81))."""
     n = len(parent)
     axis = np.zeros((n, 3))
     origin = np.zeros((n, 12))
@@ -132,6 +135,8 @@ def _random_bodies(rng, parent, joint_type, name):
         if joint_type[i] == REVOLUTE:
             origin[i, 9:12] = rng.uniform(-0.3, 0.3, size=3)
             axis[i] = random_axis(rng)
+            if rotated:
+                origin[i, 0:9] = random_rotation(rng).reshape(-1)
         else:
             axis[i] = [0.0, 0.0, 1.0]                    # unused by a free joint
         mass[i] = rng.uniform(0.5, 4.0)
@@ -141,16 +146,16 @@ def _random_bodies(rng, parent, joint_type, name):
         parent=np.asarray(parent, dtype=np.int32),
         joint_type=np.asarray(joint_type, dtype=np.int32),
         axis=_f32(axis), origin=_f32(origin), mass=_f32(mass), com=_f32(com),
-        inertia=_f32(inertia), gravity=_f32([0.0, 0.0, -9.81]), name=name)
+        inertia=_f32(inertia), gravity=_f32([0.0, 0.0, -9.81] if gravity is None else gravity), name=name)
     # Renormalising after rounding would move the value off the FP32 grid; a
     # rounded unit vector is unit to ~6e-8, which both sides accept as given.
     return desc
 
 
-def chain(n: int = 7, seed: int = SEED_CHAIN_MODEL) -> TreeDesc:
+def chain(n: int = 7, seed: int = SEED_CHAIN_MODEL, rotated: bool = False, gravity=None) -> TreeDesc:
     """Serial chain of n revolute joints (the arm workload; 7 joints by default)."""
     rng = np.random.Generator(np.random.PCG64(seed))
-    return _random_bodies(rng, list(range(-1, n - 1)), [REVOLUTE] * n, f"chain{n}")
+    return _random_bodies(rng, list(range(-1, n - 1)), [REVOLUTE] * n, f"chain{n}", rotated, gravity)
 
 
 HUMANOID_PARENT = (
@@ -163,18 +168,24 @@ HUMANOID_PARENT = (
 )
 
 
-def humanoid(seed: int = SEED_TREE_MODEL) -> TreeDesc:
+def humanoid(seed: int = SEED_TREE_MODEL, rotated: bool = False, gravity=None) -> TreeDesc:
     """30-body floating-base tree: free pelvis, 2 legs x 6, waist 3, 2 arms x 7."""
     rng = np.random.Generator(np.random.PCG64(seed))
     jt = [FREE] + [REVOLUTE] * 29
-    return _random_bodies(rng, HUMANOID_PARENT, jt, "humanoid30")
+    return _random_bodies(rng, HUMANOID_PARENT, jt, "humanoid30", rotated, gravity)
 
 
-def random_tree(parent, floating: bool, seed: int) -> TreeDesc:
+def random_tree(parent, floating: bool, seed: int, rotated: bool = False, gravity=None) -> TreeDesc:
     """Any topologically sorted tree with the standard inertial sampling."""
     rng = np.random.Generator(np.random.PCG64(seed))
     jt = [FREE if (floating and i == 0) else REVOLUTE for i in range(len(parent))]
-    return _random_bodies(rng, list(parent), jt, f"tree{len(parent)}{'f' if floating else ''}")
+    return _random_bodies(rng, list(parent), jt, f"tree{len(parent)}{'f' if floating else ''}", rotated, gravity)
+
+
+def tilted_gravity(seed: int) -> np.ndarray:
+    """A gravity vector of magnitude 9.81 in a random direction (for models whose world z is not up)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return 9.81 * random_axis(rng)
 
 
 @dataclass
@@ -190,8 +201,10 @@ class States:
         return int(self.q.shape[0])
 
 
-def states(desc: TreeDesc, batch: int, seed: int) -> States:
-    """q ~ U(-pi, pi) per revolute joint, qd ~ N(0, 1), tau ~ N(0, 5) (sigma 5).
+def states(desc: TreeDesc, batch: int, seed: int, q_range: float = np.pi) -> States:
+    """q ~ U(-q_range, q_range) per revolute joint (pi by default; larger for
+    continuous joints that have turned many times), qd ~ N(0, 1), tau ~ N(0, 5)
+    (sigma 5).
 
     A free base takes its position from U(-1, 1)^3 and its orientation as a
     uniform unit quaternion (normalised Gaussian, w first).
@@ -204,9 +217,9 @@ def states(desc: TreeDesc, batch: int, seed: int) -> States:
         quat = rng.normal(size=(batch, 4))
         quat /= np.linalg.norm(quat, axis=1, keepdims=True)
         q[:, 3:7] = quat
-        q[:, 7:] = rng.uniform(-np.pi, np.pi, size=(batch, nq - 7))
+        q[:, 7:] = rng.uniform(-q_range, q_range, size=(batch, nq - 7))
     else:
-        q[:] = rng.uniform(-np.pi, np.pi, size=(batch, nq))
+        q[:] = rng.uniform(-q_range, q_range, size=(batch, nq))
     qd = rng.normal(0.0, 1.0, size=(batch, nv))
     tau = rng.normal(0.0, 5.0, size=(batch, nv))
     return States(q=_f32(q), qd=_f32(qd), tau=_f32(tau))
