@@ -48,6 +48,16 @@
 namespace orc {
 
 // ---------------------------------------------------------------- counting
+// The counting scalar tallies the arithmetic of one evaluation that depends
+// on the robot's state. A value is "known" when it follows from the model
+// alone (constants, model parameters and what is computed from them only):
+// that work can be done once per model, so it is not counted. An operation
+// with a known 0 operand (x + 0, x * 0) or a known +-1 factor (x * 1) is the
+// trivial form of the plain algorithm's general step (an identity joint-origin
+// rotation, a zero parent velocity at the root, the zero linear part of a
+// revolute motion subspace) and is not counted either. Everything else counts
+// once: add/sub, mul, div, sqrt and sin/cos separately. The values themselves
+// are ordinary FP64, so results are unchanged.
 struct Tally {
   long long addsub, mul, div, sqrt, trig;
 };
@@ -55,21 +65,60 @@ static thread_local Tally g_tally = {0, 0, 0, 0, 0};
 
 struct Cd {
   double v;
-  Cd() : v(0.0) {}
-  Cd(double x) : v(x) {}  // constants enter without being counted
+  bool known;  // determined by the model alone
+  Cd() : v(0.0), known(true) {}
+  Cd(double x) : v(x), known(true) {}  // constants and model parameters
+  static Cd var(double x) { Cd c(x); c.known = false; return c; }  // a state input
 };
-inline Cd operator+(Cd a, Cd b) { ++g_tally.addsub; return Cd(a.v + b.v); }
-inline Cd operator-(Cd a, Cd b) { ++g_tally.addsub; return Cd(a.v - b.v); }
-inline Cd operator*(Cd a, Cd b) { ++g_tally.mul; return Cd(a.v * b.v); }
-inline Cd operator/(Cd a, Cd b) { ++g_tally.div; return Cd(a.v / b.v); }
-inline Cd operator-(Cd a) { return Cd(-a.v); }
+inline Cd cd_res(double x, bool known) { Cd c(x); c.known = known; return c; }
+inline bool is0(const Cd& a) { return a.known && a.v == 0.0; }
+inline bool is1(const Cd& a) { return a.known && (a.v == 1.0 || a.v == -1.0); }
+inline Cd operator+(Cd a, Cd b) {
+  if (a.known && b.known) return Cd(a.v + b.v);
+  if (is0(a)) return b;
+  if (is0(b)) return a;
+  ++g_tally.addsub;
+  return cd_res(a.v + b.v, false);
+}
+inline Cd operator-(Cd a) { return cd_res(-a.v, a.known); }
+inline Cd operator-(Cd a, Cd b) {
+  if (a.known && b.known) return Cd(a.v - b.v);
+  if (is0(b)) return a;
+  if (is0(a)) return -b;
+  ++g_tally.addsub;
+  return cd_res(a.v - b.v, false);
+}
+inline Cd operator*(Cd a, Cd b) {
+  if (a.known && b.known) return Cd(a.v * b.v);
+  if (is0(a) || is0(b)) return Cd(0.0);
+  if (is1(a)) return cd_res(a.v * b.v, b.known);
+  if (is1(b)) return cd_res(a.v * b.v, a.known);
+  ++g_tally.mul;
+  return cd_res(a.v * b.v, false);
+}
+inline Cd operator/(Cd a, Cd b) {
+  if (a.known && b.known) return Cd(a.v / b.v);
+  if (is0(a)) return Cd(0.0);
+  if (is1(b)) return cd_res(a.v / b.v, a.known);
+  ++g_tally.div;
+  return cd_res(a.v / b.v, false);
+}
 inline Cd& operator+=(Cd& a, Cd b) { a = a + b; return a; }
 inline Cd& operator-=(Cd& a, Cd b) { a = a - b; return a; }
 inline Cd& operator*=(Cd& a, Cd b) { a = a * b; return a; }
 inline Cd& operator/=(Cd& a, Cd b) { a = a / b; return a; }
-inline Cd sqrt(Cd a) { ++g_tally.sqrt; return Cd(std::sqrt(a.v)); }
-inline Cd sin(Cd a) { ++g_tally.trig; return Cd(std::sin(a.v)); }
-inline Cd cos(Cd a) { ++g_tally.trig; return Cd(std::cos(a.v)); }
+inline Cd sqrt(Cd a) {
+  if (!a.known) ++g_tally.sqrt;
+  return cd_res(std::sqrt(a.v), a.known);
+}
+inline Cd sin(Cd a) {
+  if (!a.known) ++g_tally.trig;
+  return cd_res(std::sin(a.v), a.known);
+}
+inline Cd cos(Cd a) {
+  if (!a.known) ++g_tally.trig;
+  return cd_res(std::cos(a.v), a.known);
+}
 inline double val(Cd a) { return a.v; }
 inline double val(double a) { return a; }
 
@@ -331,8 +380,10 @@ template <class T> SV<T> fext_body(const M3<T>& Rw, const V3<T>& pw, const T* fe
 // tau = ID(q, qd, qdd) - sum_i J_i^T F_ext,i; qdd == nullptr means qdd = 0
 // (bias force h(q, qd)), fext == nullptr means no external forces. Body i's
 // force balance subtracts the external force, as in Alg. 1.
+// Xin, when given, holds every body's joint transform already built from q
+// (forward dynamics builds them once for RNEA and CRBA).
 template <class T> void rnea(const Model& M, const T* q, const T* qd, const T* qdd, T* tau,
-                             const T* fext = nullptr) {
+                             const T* fext = nullptr, const std::vector<PX<T>>* Xin = nullptr) {
   const int n = M.n;
   std::vector<PX<T>> X(n);
   std::vector<SV<T>> v(n), a(n), f(n);
@@ -341,7 +392,7 @@ template <class T> void rnea(const Model& M, const T* q, const T* qd, const T* q
   if (fext) fk(M, q, Rw, pw);
   const SV<T> a0 = gravity_acc<T>(M);
   for (int i = 0; i < n; ++i) {
-    X[i] = jcalc(M, i, q);
+    X[i] = Xin ? (*Xin)[i] : jcalc(M, i, q);
     int l = M.parent[i];
     SV<T> vJ = smul(M, i, qd + M.vofs[i]);
     SV<T> vp = l < 0 ? zero_sv<T>() : v[l];
@@ -361,11 +412,12 @@ template <class T> void rnea(const Model& M, const T* q, const T* qd, const T* q
 }
 
 // ---------------------------------------------------------------- CRBA
-template <class T> void crba(const Model& M, const T* q, T* H /*nv x nv row-major*/) {
+template <class T> void crba(const Model& M, const T* q, T* H /*nv x nv row-major*/,
+                             const std::vector<PX<T>>* Xin = nullptr) {
   const int n = M.n, nv = M.nv;
   std::vector<PX<T>> X(n);
   std::vector<RBI<T>> Ic(n);
-  for (int i = 0; i < n; ++i) { X[i] = jcalc(M, i, q); Ic[i] = cvt<T>(M.I[i]); }
+  for (int i = 0; i < n; ++i) { X[i] = Xin ? (*Xin)[i] : jcalc(M, i, q); Ic[i] = cvt<T>(M.I[i]); }
   for (int e = 0; e < nv * nv; ++e) H[e] = T(0.0);
   for (int i = n - 1; i >= 0; --i) {
     int l = M.parent[i];
@@ -590,8 +642,10 @@ template <class T> void fwd_dyn(const Model& M, const T* q, const T* qd, const T
   const int nv = M.nv;
   if (method == 2) { aba(M, q, qd, tau, qdd, fext); return; }
   std::vector<T> h(nv), H(nv * nv);
-  rnea(M, q, qd, (const T*)nullptr, h.data(), fext);
-  crba(M, q, H.data());
+  std::vector<PX<T>> X(M.n);  // joint transforms, built once for both passes
+  for (int i = 0; i < M.n; ++i) X[i] = jcalc(M, i, q);
+  rnea(M, q, qd, (const T*)nullptr, h.data(), fext, &X);
+  crba(M, q, H.data(), &X);
   for (int k = 0; k < nv; ++k) qdd[k] = tau[k] - h[k];
   if (method == 0) chol_llt_solve(nv, H.data(), qdd);
   else ltl_solve(nv, dof_parent(M), H.data(), qdd);
@@ -867,8 +921,9 @@ int orc_count_ops(const orc_model* d, int op, long long* out) {
   Model M;
   if (build_model(d, M)) return 1;
   const int nq = M.nq, nv = M.nv;
-  std::vector<Cd> q(nq, Cd(0.1)), qd(nv, Cd(0.2)), qdd(nv, Cd(0.3)), tau(nv, Cd(0.4)), o(nv);
-  if (M.floating) { q[3] = Cd(1.0); q[4] = Cd(0.0); q[5] = Cd(0.0); q[6] = Cd(0.0); }
+  // a generic state: every input is a variable with a value that is neither 0 nor 1
+  std::vector<Cd> q(nq, Cd::var(0.1)), qd(nv, Cd::var(0.2)), qdd(nv, Cd::var(0.3)), tau(nv, Cd::var(0.4)), o(nv);
+  if (M.floating) { q[3] = Cd::var(0.9); q[4] = Cd::var(0.3); q[5] = Cd::var(-0.2); q[6] = Cd::var(0.25); }
   g_tally = {0, 0, 0, 0, 0};
   switch (op) {
     case 0: { std::vector<M3<Cd>> R; std::vector<V3<Cd>> p; fk(M, q.data(), R, p); break; }

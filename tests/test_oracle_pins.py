@@ -350,13 +350,59 @@ def test_operation_counts_are_consistent():
         fk = O.count_ops(d, "fk")
         assert fk["trig"] == 2 * nrev
         ltl, llt = O.count_ops(d, "fwd_dyn_ltl"), O.count_ops(d, "fwd_dyn_llt")
-        assert ltl["sqrt"] == llt["sqrt"] == d.nv
+        # one square root per DoF; L^T L starts at the leaves, whose pivots are model constants
+        leaves = sum(1 for i in range(d.n_bodies) if i not in set(d.parent.tolist()))
+        assert ltl["sqrt"] == d.nv - leaves and llt["sqrt"] <= d.nv
         if d.floating:
             assert ltl["flops"] < llt["flops"]         # branch sparsity saves work
         else:
             assert ltl["flops"] == llt["flops"]        # a chain has none
+        # forward dynamics builds the joint transforms once for both passes
         rb, cr = O.count_ops(d, "rnea_bias"), O.count_ops(d, "crba")
-        assert ltl["flops"] > rb["flops"] + cr["flops"]
+        assert ltl["trig"] == rb["trig"] == cr["trig"] == 2 * nrev
+
+
+# Hand-derived counts of the counting scalar's rules (model-only arithmetic is folded, operations
+# with a known 0 operand or a known +-1 factor are free, everything else counts once) for revolute
+# joints with identity origin rotations and general axes, origins and inertias (no zero entries).
+# Per primitive: mv/mtv (variable matrix or vector) 9 mul 6 add; cross 6 mul 3 add; dot 3 mul 2 add;
+# 3x3 product 27 mul 18 add; skew_skew(a, b) = b a^T - (a.b) 1: 12 mul 5 add.
+#   joint transform: Rodrigues 2 trig, 1 - c (1 add), diagonal c + t a_k^2 (3 mul 3 add), six
+#     off-diagonal t a_j a_k +- s a_l (12 mul 6 add); the identity origin rotation is free: 15 mul 10 add.
+#   root body of RNEA (bias): S qd 3 mul; X a_0 with a_0 = (0, 0, 0; 0, 0, 9.81) 3 mul; v x S qd
+#     6 mul 3 add (v.l = 0); I a 24 mul 18 add; I v 15 mul 9 add (v.l = 0); v x* I v 12 mul 6 add;
+#     sum 6 add: 63 mul 42 add. S^T f: 3 mul 2 add.
+#   a child body: S qd 3 mul; X v_p 24 mul 15 add (v_p.l = 0 at the root) + S qd 3 add; X a_p 24 mul
+#     18 add; v x S qd 12 mul 6 add; + 6 add; I a 24 mul 18 add; I v 24 mul 18 add; v x* I v 18 mul
+#     12 add; + 6 add: 129 mul 102 add. Backward S^T f 3 mul 2 add; f_p += X^T f 24 mul 24 add.
+#   CRBA with the transforms given: X^T Ic X of the child 87 mul 73 add (E^T h 9m 6a, + m r 3a, E^T I E
+#     54m 36a, two skew_skew 24m 10a, two 3x3 subtractions 18a), Ic_p += 12 add; the root's
+#     F = Ic S 15 mul 9 add and S^T F 3 mul 2 add; the child's F = Ic S and S^T F are model constants;
+#     F <- X^T F 24 mul 18 add and S^T F 3 mul 2 add.
+#   L^T L of 2 DoFs: the leaf's pivot is a constant (its sqrt is free); L_10 = M_10 / L_11 1 div;
+#     M_00 -= L_10^2 1 mul 1 add; sqrt(M_00); the two triangular solves 2 mul 2 add 4 div.
+def test_operation_count_of_one_pendulum():
+    d = W.random_tree([-1], False, 31)
+    c = O.count_ops(d, "fwd_dyn_ltl")
+    # transform 15m 10a; RNEA root 63m 42a; S^T f 3m 2a; tau - h 1a; M is a model constant;
+    # L^T y = b and L x = y: one division each
+    assert (c["mul"], c["addsub"], c["div"], c["sqrt"], c["trig"]) == (15 + 63 + 3, 10 + 42 + 2 + 1, 2, 0, 2)
+    assert O.count_ops(d, "crba")["flops"] == 15 + 10  # only the transform; M itself is constant
+    assert O.count_ops(d, "rnea_bias")["flops"] == (15 + 10) + (63 + 42) + (3 + 2)
+
+
+def test_operation_count_of_a_two_link_chain():
+    d = W.random_tree([-1, 0], False, 32)
+    assert not np.any(d.axis == 0.0) and not np.any(d.origin[:, 9:12] == 0.0)
+    transforms = 2 * (15 + 10)
+    rnea = (63 + 42) + (129 + 102) + (3 + 2) + (24 + 24) + (3 + 2)
+    crba = (87 + 73) + 12 + (15 + 9) + (3 + 2) + (24 + 18) + (3 + 2)
+    solve = 2 + (1 + 1) + (2 + 2)  # tau - h (2 add), the factor update, the two solves (2 mul 2 add)
+    assert O.count_ops(d, "rnea_bias")["flops"] == transforms + rnea
+    assert O.count_ops(d, "crba")["flops"] == transforms + crba
+    c = O.count_ops(d, "fwd_dyn_ltl")
+    assert c["flops"] == transforms + rnea + crba + solve
+    assert (c["div"], c["sqrt"], c["trig"]) == (5, 1, 4)
 
 
 # ---------------------------------------------------------------- external forces (Eq. (1) J^T f, Alg. 1 F_ext)
