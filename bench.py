@@ -32,7 +32,7 @@ BATCH = 65536
 PEAK_FP32_TFLOPS = 157.3
 PEAK_FP32_UNPACKED_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 PEAK_HBM_GBS = 8000.0
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "fwd_dyn_humanoid30_b65536_traffic.txt")
+COUNTERS_FILE = os.path.join(ROOT, "profiles", "kernel_counters_humanoid30_chain7.txt")
 CSRC = os.path.join(ROOT, "paper_2604_04310_amd", "csrc")
 
 
@@ -49,55 +49,147 @@ def kernel_source_hash() -> str:
 
 
 def read_counters():
-    """Figures from the committed counter summary (HBM bytes per launch, executed
-    FP32 FLOPs per evaluation), or {} when the kernels changed after the
-    counters were taken."""
-    if not os.path.exists(TRAFFIC_FILE):
+    """Per-kernel figures from the committed counter summary: {key: {field: value}}
+    with executed FP32 FLOPs per evaluation and HBM bytes per launch, or {} when
+    the kernels changed after the counters were taken."""
+    if not os.path.exists(COUNTERS_FILE):
         return {}
-    vals = {}
-    for line in open(TRAFFIC_FILE):
-        if "=" in line and not line.startswith("#"):
-            k, v = line.split("=", 1)
-            vals[k.strip()] = v.strip()
-    if vals.get("source_hash") != kernel_source_hash():
-        return {}
-    out = {}
-    for k in ("hbm_bytes_per_launch", "executed_fp32_flops_per_eval"):
-        try:
-            out[k] = float(vals[k])
-        except (KeyError, ValueError):
-            pass
-    return out
+    out, src = {}, None
+    for line in open(COUNTERS_FILE):
+        line = line.strip()
+        if not line or line.startswith("#"):
+            continue
+        if line.startswith("source_hash"):
+            src = line.split("=", 1)[1].strip()
+            continue
+        fields = dict(f.split("=", 1) for f in line.split() if "=" in f)
+        if "kernel" in fields:
+            out[fields.pop("kernel")] = {k: float(v) for k, v in fields.items()}
+    return out if src == kernel_source_hash() else {}
 
 
 def counters_driver():
-    """The run the counter summaries are taken from: five humanoid fwd_dyn
-    launches at batch 65536, three each of crba, fk and jacobian (all 30
-    frames) on the same states, then three plain 512 MiB device copies (the
-    calibration kernel for FETCH_SIZE / WRITE_SIZE)."""
+    """The run the counter summaries are taken from: each hot kernel at its
+    benchmark shape on the seeded states (humanoid30 at batch 65536, its
+    derivatives at 32768, the 7-chain at 2^20 and its adjoint at 2^18), a few
+    launches each, then three plain 512 MiB device copies (the calibration
+    kernel for FETCH_SIZE / WRITE_SIZE). Each step prints its name first."""
     import torch
 
     import paper_2604_04310_amd as rbd
     import workloads as W
+
+    def step(name, fn, n=3):
+        print(f"counters: {name}", flush=True)
+        for _ in range(n):
+            fn()
+        torch.cuda.synchronize()
+
     desc = W.humanoid()
     m = rbd.Model(desc, 0)
     st = W.states(desc, BATCH, 103)
     q, qd, tau = soa(st.q, torch), soa(st.qd, torch), soa(st.tau, torch)
     out = torch.empty((desc.nv, BATCH), dtype=torch.float32, device="cuda")
-    for _ in range(5):
-        rbd.fwd_dyn(m, q, qd, tau, out=out)
-    # the HBM-bound kernels of the same batch, three launches each
-    for fn in (lambda: rbd.crba(m, q), lambda: rbd.fk(m, q), lambda: rbd.jacobian(m, q)):
-        for _ in range(3):
-            fn()
-        torch.cuda.synchronize()
+    step("fwd_dyn humanoid30 65536", lambda: rbd.fwd_dyn(m, q, qd, tau, out=out), 5)
+    step("rnea bias humanoid30 65536", lambda: rbd.rnea(m, q, qd, out=out))
+    step("aba humanoid30 65536", lambda: rbd.aba(m, q, qd, tau, out=out))
+    for name, fn in (("crba", lambda: rbd.crba(m, q)), ("fk", lambda: rbd.fk(m, q)),
+                     ("jacobian", lambda: rbd.jacobian(m, q))):
+        step(f"{name} humanoid30 65536", fn)
         torch.cuda.empty_cache()
+    tg = soa(W._f32(targets(W, BATCH)), torch)
+    step("osc humanoid30 65536", lambda: rbd.osc(m, q, qd, tg, 50.0, 10.0, 2.0))
+    step("diff_ik humanoid30 65536", lambda: rbd.diff_ik(m, q, tg, 2.0, 0.05))
+    del tg
+    Bv = 32768
+    vq, vqd, vtau = q[:, :Bv].contiguous(), qd[:, :Bv].contiguous(), tau[:, :Bv].contiguous()
+    gq = soa(W.cotangent(desc.nv, Bv, 9), torch)
+    step("fwd_dyn_vjp humanoid30 32768", lambda: rbd.fwd_dyn_vjp(m, vq, vqd, vtau, gq))
+    tq, tqd, ttau = (soa(W._f32(np.random.default_rng(s).normal(size=(Bv, r))), torch)
+                     for s, r in ((11, desc.nq), (12, desc.nv), (13, desc.nv)))
+    step("fwd_dyn_jvp humanoid30 32768", lambda: rbd.fwd_dyn_jvp(m, vq, vqd, vtau, tq, tqd, ttau))
+    del q, qd, tau, out, vq, vqd, vtau, gq, tq, tqd, ttau
+    torch.cuda.empty_cache()
+    chain = W.chain(7)
+    cm = rbd.Model(chain, 0)
+    cs = W.states(chain, 1 << 20, 102)
+    cq, cqd, ctau = soa(cs.q, torch), soa(cs.qd, torch), soa(cs.tau, torch)
+    step("fwd_dyn chain7 1048576", lambda: rbd.fwd_dyn(cm, cq, cqd, ctau))
+    step("rnea bias chain7 1048576", lambda: rbd.rnea(cm, cq, cqd))
+    Bc = 1 << 18
+    cg = soa(W.cotangent(chain.nv, Bc, 3), torch)
+    wq, wqd, wtau = cq[:, :Bc].contiguous(), cqd[:, :Bc].contiguous(), ctau[:, :Bc].contiguous()
+    step("fwd_dyn_vjp chain7 262144", lambda: rbd.fwd_dyn_vjp(cm, wq, wqd, wtau, cg))
+    del cq, cqd, ctau, wq, wqd, wtau, cg
+    torch.cuda.empty_cache()
     a = torch.empty(128 << 20, dtype=torch.float32, device="cuda")
     b = torch.empty_like(a)
-    for _ in range(3):
-        b.copy_(a)
-    torch.cuda.synchronize()
+    step("copy 512 MiB", lambda: b.copy_(a))
     print("counters driver done", flush=True)
+
+
+def targets(W, B):
+    """End-effector target poses [B, 12] for the controller kernels (256 distinct, tiled)."""
+    rng_t = np.random.default_rng(15)
+    tgt = np.concatenate([np.stack([W.random_rotation(rng_t) for _ in range(256)])[np.arange(B) % 256],
+                          rng_t.normal(0.0, 0.5, size=(B, 3, 1))], axis=2)
+    return tgt.reshape(B, 12)
+
+
+def kernel_rooflines(O, W, desc, chain, ops, cnt, hbm):
+    """Roofline of every other hot kernel at its benchmark shape: VALU-bound ones
+    against the FP32 peak (oracle count where the oracle counts the operation,
+    and the executed count from the hardware counters), memory-bound ones
+    against the measured streaming-write ceiling and the HBM spec."""
+    B, Bv, Bc, Bw = BATCH, 32768, 1 << 20, 1 << 18
+    nb = desc.n_bodies
+
+    def valu(key, us, batch, oracle_flops):
+        c = cnt.get(key, {})
+        exe = c.get("flops_per_eval")
+        r = {"kernel_us": us, "batch": batch, "bound": "alu", "peak_tflops": PEAK_FP32_TFLOPS,
+             "oracle_flops_per_eval": oracle_flops,
+             "achieved_tflops": round(oracle_flops * batch / (us * 1e-6) / 1e12, 2) if oracle_flops else None,
+             "executed_fp32_flops_per_eval": exe,
+             "executed_tflops": round(exe * batch / (us * 1e-6) / 1e12, 2) if exe else None}
+        basis = r["achieved_tflops"] if oracle_flops else r["executed_tflops"]
+        r["frac"] = round(basis / PEAK_FP32_TFLOPS, 4) if basis else None
+        r["frac_basis"] = "oracle count" if oracle_flops else ("executed (hardware counter)" if exe else None)
+        if exe:
+            r["executed_frac"] = round(r["executed_tflops"] / PEAK_FP32_TFLOPS, 4)
+        if "fetch_bytes" in c:
+            r["traffic"] = c["fetch_bytes"] + c["write_bytes"]
+        return r
+
+    def mem(key, us, batch, bytes_per_eval):
+        c = cnt.get(key, {})
+        gbs = bytes_per_eval * batch / (us * 1e-6) / 1e9
+        r = {"kernel_us": us, "batch": batch, "bound": "hbm", "algorithmic_bytes_per_eval": bytes_per_eval,
+             "achieved_gbs": round(gbs, 1), "frac_of_spec": round(gbs / PEAK_HBM_GBS, 4),
+             "frac_of_measured_write_ceiling": round(gbs / hbm["write_gbs"], 4)}
+        if "fetch_bytes" in c:
+            r["traffic"] = c["fetch_bytes"] + c["write_bytes"]
+        return r
+
+    f = lambda d, op: O.count_ops(d, op)["flops"]  # noqa: E731
+    nv = desc.nv
+    return {
+        "fwd_dyn_chain7": valu("fwd_dyn_chain7", ops["fwd_dyn_chain7_b1048576_us"], Bc, f(chain, "fwd_dyn_ltl")),
+        "rnea_bias_humanoid30": valu("rnea_bias_humanoid30", ops["rnea_bias_humanoid30_b65536_us"], B,
+                                     f(desc, "rnea_bias")),
+        "rnea_bias_chain7": valu("rnea_bias_chain7", ops["rnea_bias_chain7_b1048576_us"], Bc, f(chain, "rnea_bias")),
+        "aba_humanoid30": valu("aba_humanoid30", ops["aba_humanoid30_b65536_us"], B, f(desc, "aba")),
+        "fwd_dyn_vjp_humanoid30": valu("fwd_dyn_vjp_humanoid30", ops["fwd_dyn_vjp_humanoid30_b32768_us"], Bv, None),
+        "fwd_dyn_vjp_chain7": valu("fwd_dyn_vjp_chain7", ops["fwd_dyn_vjp_chain7_b262144_us"], Bw, None),
+        "fwd_dyn_jvp_humanoid30": valu("fwd_dyn_jvp_humanoid30", ops["fwd_dyn_jvp_humanoid30_b32768_us"], Bv, None),
+        "osc_humanoid30": valu("osc_humanoid30", ops["osc_humanoid30_b65536_us"], B, None),
+        "crba_humanoid30": mem("crba_humanoid30", ops["crba_humanoid30_b65536_us"], B, 4 * (desc.nq + nv * nv)),
+        "fk_humanoid30": mem("fk_humanoid30", ops["fk_humanoid30_b65536_us"], B, 4 * (desc.nq + 12 * nb)),
+        "jacobian30_humanoid30": mem("jacobian_humanoid30", ops["jacobian30_humanoid30_b65536_us"], B,
+                                     4 * (desc.nq + nb * 6 * nv)),
+        "note": "the oracle differentiates by central differences and its controllers are NumPy solves, so the "
+                "derivative and controller kernels are reported on the executed (hardware-counter) basis only",
+    }
 
 
 def soa(x, torch):
@@ -223,12 +315,14 @@ def serving_leg(rbd, torch, seconds, seed=7):
     out["batched"] = {"offered_req_per_s": round(0.5 * cap, 1), "requests": st["requests"],
                       "launches": st["launches"], "evals_per_s": st["instances"] / wall,
                       "p50_us": st["p50_us"], "p99_us": st["p99_us"], "max_us": st["max_us"],
-                      "closed_loop_capacity_req_per_s": round(cap, 1)}
+                      "closed_loop_capacity_req_per_s": round(cap, 1),
+                      "groups_in_flight_frac": round(st["busy_s"] / wall, 3)}
     n80 = int(max(512, min(20000, cap * 0.8 * seconds)))
     st, wall = run(srv, n80, 0.8 * cap)
     out["batched_at_80pct"] = {"offered_req_per_s": round(0.8 * cap, 1), "requests": st["requests"],
                                "launches": st["launches"], "evals_per_s": st["instances"] / wall,
-                               "p50_us": st["p50_us"], "p99_us": st["p99_us"], "max_us": st["max_us"]}
+                               "p50_us": st["p50_us"], "p99_us": st["p99_us"], "max_us": st["max_us"],
+                               "groups_in_flight_frac": round(st["busy_s"] / wall, 3)}
     srv.close()
     base = rbd.Server(arena_bytes=1 << 30, n_streams=1, per_request=True, use_graphs=False)
     run(base, 256, 0.0)
@@ -339,18 +433,22 @@ def main():
     per_eval = flops["flops"]
     achieved = per_eval * BATCH / (kernel_ms * 1e-3) / 1e12
     cnt = read_counters()
-    traffic = cnt.get("hbm_bytes_per_launch")
+    head = cnt.get("fwd_dyn_humanoid30", {})
+    traffic = (head["fetch_bytes"] + head["write_bytes"]) if "fetch_bytes" in head else None
     ceiling = rbd.fma_rate(256, 16)  # measured FMA issue ceiling at this launch shape
+    exe = head.get("flops_per_eval")
     roofline = {"bound": "alu", "achieved": round(achieved, 2), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": traffic,
                 "kernel": "k_fwd_dyn<humanoid30>", "kernel_ms": round(kernel_ms, 5),
-                "flops_per_eval": per_eval, "flops_source": "oracle count of the same algorithm (FP64 counting scalar)",
+                "flops_per_eval": per_eval,
+                "flops_source": "oracle count (FP64 counting scalar: state-dependent add/sub/mul, transforms shared "
+                                "by RNEA and CRBA, trivial operations not counted)",
                 "peak_unpacked_fp32": round(PEAK_FP32_UNPACKED_TFLOPS, 1),
                 "frac_of_unpacked_peak": round(achieved / PEAK_FP32_UNPACKED_TFLOPS, 4),
                 "measured_fma_ceiling_at_this_launch_shape": round(ceiling, 1),
-                "executed_fp32_flops_per_eval": cnt.get("executed_fp32_flops_per_eval"),
-                "executed_tflops": (round(cnt["executed_fp32_flops_per_eval"] * BATCH / (kernel_ms * 1e-3) / 1e12, 2)
-                                    if "executed_fp32_flops_per_eval" in cnt else None),
+                "executed_fp32_flops_per_eval": exe,
+                "executed_tflops": round(exe * BATCH / (kernel_ms * 1e-3) / 1e12, 2) if exe else None,
+                "executed_frac": round(exe * BATCH / (kernel_ms * 1e-3) / 1e12 / PEAK_FP32_TFLOPS, 4) if exe else None,
                 "algorithmic_bytes_per_eval": 4 * (desc.nq + 3 * desc.nv),
                 "hbm_gbs_algorithmic": round(4 * (desc.nq + 3 * desc.nv) * BATCH / (kernel_ms * 1e-3) / 1e9, 1)}
 
@@ -373,10 +471,7 @@ def main():
     ops["fwd_dyn_jvp_humanoid30_b32768_us"] = 1e3 * time_launches(
         lambda: rbd.fwd_dyn_jvp(model, vq, vqd, vtau, tq, tqd, ttau), n_t, torch)
     del tq, tqd, ttau
-    rng_t = np.random.default_rng(15)
-    tgt = np.concatenate([np.stack([W.random_rotation(rng_t) for _ in range(256)])[np.arange(BATCH) % 256],
-                          rng_t.normal(0.0, 0.5, size=(BATCH, 3, 1))], axis=2)
-    tg = soa(W._f32(tgt.reshape(BATCH, 12)), torch)
+    tg = soa(W._f32(targets(W, BATCH)), torch)
     ops["osc_humanoid30_b65536_us"] = 1e3 * time_launches(lambda: rbd.osc(model, q, qd, tg, 50.0, 10.0, 2.0), n_t, torch)
     ops["diff_ik_humanoid30_b65536_us"] = 1e3 * time_launches(lambda: rbd.diff_ik(model, q, tg, 2.0, 0.05), n_t, torch)
     del tg
@@ -400,6 +495,11 @@ def main():
     ops = {k: round(v, 2) if "us" in k else float(f"{v:.4g}") for k, v in ops.items()}
     del cq, cqd, ctau
     torch.cuda.empty_cache()
+    hbm = {"write_gbs": round(max(rbd.hbm_rate(1 << 30, 0, b) for b in (4096, 16384)), 1),
+           "copy_gbs": round(max(rbd.hbm_rate(1 << 30, 1, b) for b in (4096, 16384)), 1),
+           "spec_gbs": PEAK_HBM_GBS,
+           "how": "streaming kernel (16-byte non-temporal stores, grid-stride), best of 10 launches over 1 GiB"}
+    kernels = kernel_rooflines(O, W, desc, chain, ops, cnt, hbm)
 
     serving = None if args.no_serving else serving_leg(rbd, torch, args.serve_seconds)
     cpu = None if args.no_cpu else cpu_baseline(desc, st, args.cpu_seconds)
@@ -415,6 +515,8 @@ def main():
         "fwd_dyn_graph_replay_us": round(graph_us, 2),
         "fwd_dyn_single_launch_latency_us": round(single_launch_us, 1),
         "roofline": roofline,
+        "kernels": kernels,
+        "hbm_ceiling": hbm,
         "cpu_baseline": cpu,
         "ops": ops,
         "serving": serving,

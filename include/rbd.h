@@ -68,7 +68,8 @@ typedef enum {
   RBD_E_LAUNCH = 4,      /* a HIP call or kernel launch failed                */
   RBD_E_UNSUPPORTED = 5, /* valid model whose topology has no compiled kernel */
   RBD_E_TIMEOUT = 6,     /* rbd_server_wait: the request did not finish       */
-  RBD_E_SHUTDOWN = 7     /* rbd_server_*: the server is shutting down         */
+  RBD_E_SHUTDOWN = 7,    /* rbd_server_*: the server is shutting down         */
+  RBD_E_COMPILE = 8      /* run-time compilation of a new topology failed     */
 } rbd_status;
 
 typedef enum { RBD_JOINT_REVOLUTE = 0, RBD_JOINT_FREE = 1 } rbd_joint;
@@ -94,16 +95,45 @@ typedef struct {
 typedef struct rbd_model rbd_model; /* opaque: device-resident tables */
 
 /* Validate the tree, precompute FP32 tables and upload them to `device`.
+ * Any valid tree is accepted (Sec. II: a robot is a kinematic tree). The
+ * library carries kernels compiled ahead of time for a list of topologies
+ * (chains of 1-8 joints, a free body, a 12-body floating tree and the 30-body
+ * humanoid). For any other topology the same kernel templates are compiled
+ * for the tree with hiprtc at run time, one kernel at a time, the first time
+ * that kernel is launched on a device (so the first call of each operation on
+ * a new topology is host-synchronous and takes seconds for small trees, up to
+ * minutes for a 40-body tree; the first call must not be made during stream
+ * capture). Code objects are cached on disk and looked up in $RBD_JIT_CACHE
+ * (if set), then in "_jit" beside librbd.so (code objects installed with the
+ * library, see rbd_precompile_topology), then in $XDG_CACHE_HOME/rbd-jit or
+ * ~/.cache/rbd-jit; new ones are written to $RBD_JIT_CACHE, else the user
+ * cache. A kernel is loaded once per process and device and serves every
+ * model of its topology. Compute calls on such a model can then also return
+ * RBD_E_COMPILE (compilation failed; message in rbd_last_error).
  * Errors: RBD_E_INVAL (null pointer, n out of range, parent[i] >= i, a
  * subtree that is not a contiguous range, FREE joint not at body 0, unknown
  * joint type, zero axis, R not a rotation, mass <= 0, inertia not positive
- * definite or violating the triangle inequality), RBD_E_UNSUPPORTED (no
- * compiled kernel for this topology), RBD_E_NODEVICE, RBD_E_NOMEM. */
+ * definite or violating the triangle inequality), RBD_E_NODEVICE,
+ * RBD_E_NOMEM. */
 rbd_status rbd_model_create(const rbd_tree_desc* desc, int device, rbd_model** out);
 rbd_status rbd_model_destroy(rbd_model* model);
 rbd_status rbd_model_dims(const rbd_model* model, int* nq, int* nv, int* n_bodies);
-/* Name of the compiled topology serving this model (static string). */
+/* Name of the topology serving this model (static string): a compiled
+ * topology's name, or "jit_<n>[f]_<hash>" for one compiled at run time. */
 const char* rbd_model_topology(const rbd_model* model);
+
+/* Compile kernels of a topology (n_bodies in 1..64, parent[i] < i
+ * depth-first, floating != 0 for a free body 0) into the code-object cache
+ * directory cache_dir (created if missing; NULL = the default write directory
+ * described at rbd_model_create): kernel = -1 compiles all RBD_N_KERNELS of
+ * them, kernel in [0, RBD_N_KERNELS) that one only (separate processes can
+ * compile a topology's kernels in parallel: hiprtc compiles one program at a
+ * time per process). Kernels already in the directory are kept. Needs no GPU.
+ * Synchronous. Used to install a robot's kernels before its first use.
+ * Errors: RBD_E_INVAL, RBD_E_COMPILE. */
+#define RBD_N_KERNELS 27
+rbd_status rbd_precompile_topology(int32_t n_bodies, const int32_t* parent, int floating, const char* cache_dir,
+                                   int32_t kernel);
 
 /* Forward kinematics (Sec. II): T[(i*12 + e) * ld + b] holds the world pose
  * of body i as a 3x4 row-major [R | p] (e = 4*row + col). q: [nq][ld]. */
@@ -206,6 +236,17 @@ rbd_status rbd_osc(const rbd_model* model, int64_t batch, int64_t ld, const floa
  * peak assumes packed FP32, which this library does not use. Synchronous;
  * allocates and frees a small buffer. */
 rbd_status rbd_diag_fma_rate(int device, int blocks, int ilp, double* tflops);
+
+/* Diagnostic (not on the hot path): measured streaming HBM bandwidth in GB/s.
+ * mode 0 writes `bytes` bytes (16-byte non-temporal stores, the way the pose,
+ * mass-matrix and Jacobian outputs are written); mode 1 copies `bytes` bytes
+ * (GB/s counts read + written bytes). A grid-stride kernel of `blocks` blocks
+ * of 256 threads; the best of 10 timed launches after 3 warm-up launches.
+ * bytes in [1 MiB, 16 GiB], blocks in [1, 2^20]. Synchronous; allocates and
+ * frees its buffers (device memory of bytes, twice for a copy). It is the
+ * achievable ceiling the memory-bound kernels are compared with, beside the
+ * published 8 TB/s. */
+rbd_status rbd_diag_hbm_rate(int device, int64_t bytes, int mode, int blocks, double* gbs);
 
 const char* rbd_status_str(rbd_status s);
 const char* rbd_last_error(void); /* message of this thread's last failed call */

@@ -14,14 +14,69 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "librbd.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-HOST_SOURCES = ["rbd_api.cpp", "rbd_dispatch.cpp", "rbd_serve.cpp"]
+HOST_SOURCES = ["rbd_api.cpp", "rbd_dispatch.cpp", "rbd_serve.cpp", "rbd_jit.cpp"]
 DEVICE_SOURCES = ["rbd_diag.hip"]
 TOPO_SOURCE = "rbd_kern_topo.hip"
+# Device headers the run-time compiler instantiates for a new topology; their
+# text is embedded in the library.
+JIT_HEADERS = ["rbd_kernels.hpp", "rbd_kernel_ids.hpp", "rbd_lane.hpp", "rbd_shared.hpp"]
 
 # Packed FP32 (v_pk_*_f32) is switched off for every HIP translation unit.
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function", "-Wno-unused-variable",
           f"-I{INCLUDE}", f"-I{CSRC}", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 DEVICE = ["--offload-arch=gfx950", "-ffp-contract=fast"]
+
+
+# Topologies outside the compiled list whose run-time-compiled kernels are
+# installed with the library (the "_jit" cache beside librbd.so, built by
+# build()), so that their models load without compiling: a quadruped (free
+# trunk, four 3-joint legs), random depth-first trees of 9 and 20 bodies on a
+# fixed base and one of 40 bodies on a free base. Name: (floating, parents).
+PREBUILT = {
+    "quadruped13f": (True, [-1, 0, 1, 2, 0, 4, 5, 0, 7, 8, 0, 10, 11]),
+    "tree9": (False, [-1, 0, 1, 1, 3, 0, 5, 6, 7]),
+    "tree20": (False, [-1, 0, 1, 0, 3, 4, 3, 6, 7, 8, 9, 7, 0, 12, 12, 14, 14, 0, 17, 18]),
+    "tree40f": (True, [-1, 0, 1, 0, 0, 0, 0, 6, 7, 8, 9, 10, 9, 0, 13, 0, 15, 16, 0, 0, 0, 0, 21, 0, 23, 24, 25, 0,
+                       27, 28, 29, 30, 31, 32, 29, 34, 27, 0, 37, 38]),
+}
+JIT_DIR = os.path.join(PKG, "_jit")
+N_KERNELS = 27  # RBD_N_KERNELS
+
+
+def _precompile_one(args):
+    """One kernel of one topology into JIT_DIR (runs in a worker process)."""
+    import ctypes as C
+    name, floating, parent, kernel = args
+    lib = C.CDLL(LIB)
+    lib.rbd_precompile_topology.argtypes = [C.c_int32, C.POINTER(C.c_int32), C.c_int, C.c_char_p, C.c_int32]
+    lib.rbd_last_error.restype = C.c_char_p
+    par = (C.c_int32 * len(parent))(*parent)
+    st = lib.rbd_precompile_topology(len(parent), par, int(floating), JIT_DIR.encode(), kernel)
+    return name, kernel, st, (lib.rbd_last_error().decode() if st else "")
+
+
+def prebuild_jit(verbose: bool = False, jobs: int = 0) -> None:
+    """Compile every kernel of the PREBUILT topologies into the library's _jit
+    cache, one kernel per worker process (hiprtc compiles one program at a
+    time per process). Code objects already there are kept: the cache is keyed
+    by a hash of the sources, options, topology and kernel."""
+    from concurrent.futures import ProcessPoolExecutor
+    import multiprocessing as mp
+    t0 = time.time()
+    work = [(name, fl, par, k) for name, (fl, par) in PREBUILT.items() for k in range(N_KERNELS)]
+    work.sort(key=lambda w: -len(w[2]))  # the largest trees first
+    with ProcessPoolExecutor(max_workers=jobs or _jobs(), mp_context=mp.get_context("spawn")) as ex:
+        for name, kernel, st, err in ex.map(_precompile_one, work):
+            if st != 0:
+                raise RuntimeError(f"precompiling kernel {kernel} of {name} failed: {err}")
+    # every code object in use was just written or touched: the rest are stale
+    for f in os.listdir(JIT_DIR):
+        path = os.path.join(JIT_DIR, f)
+        if f.endswith(".hsaco") and os.path.getmtime(path) < t0 - 1.0:
+            os.remove(path)
+    if verbose:
+        print(f"jit cache: {len(work)} kernels of {len(PREBUILT)} topologies ready in {time.time() - t0:.1f}s",
+              flush=True)
 
 
 def topologies():
@@ -35,16 +90,50 @@ def _jobs():
     return max(1, min(16, cpus, int(os.environ.get("MAX_JOBS", cpus))))
 
 
-def _newest_source() -> float:
-    paths = [os.path.join(CSRC, f) for f in os.listdir(CSRC)] + [os.path.join(INCLUDE, f) for f in os.listdir(INCLUDE)]
+# What each kind of object is compiled from (for incremental builds).
+DEVICE_DEPS = [TOPO_SOURCE, "rbd_kernels.hpp", "rbd_kernel_ids.hpp", "rbd_lane.hpp", "rbd_shared.hpp",
+               "rbd_topologies.hpp"]
+HOST_HEADERS = ["rbd_internal.hpp", "rbd_shared.hpp", "rbd_kernel_ids.hpp", "rbd_topologies.hpp"]
+
+
+def _newest(paths) -> float:
     return max(os.path.getmtime(p) for p in paths)
+
+
+def _deps(obj: str, cmd) -> list:
+    """Sources and headers an object depends on."""
+    inc = [os.path.join(INCLUDE, "rbd.h")]
+    if os.path.basename(obj).startswith("kern_"):
+        return [os.path.join(CSRC, f) for f in DEVICE_DEPS]
+    src = cmd[-3]  # ... -c <source> -o <object>
+    return [src] + [os.path.join(CSRC, f) for f in HOST_HEADERS] + inc
+
+
+def write_jit_sources(out_dir: str) -> str:
+    """A C++ source holding the device headers' text (for hiprtc at run time)."""
+    path = os.path.join(out_dir, "rbd_jit_sources.cpp")
+    parts = ["// Generated by build.py: the device headers, compiled at run time for new topologies.",
+             "namespace rbd {", f"extern const int kJitNumHeaders = {len(JIT_HEADERS)};",
+             "extern const char* const kJitHeaderNames[] = {" + ", ".join(f'"{h}"' for h in JIT_HEADERS) + "};",
+             "extern const char* const kJitHeaderTexts[] = {"]
+    for h in JIT_HEADERS:
+        text = open(os.path.join(CSRC, h)).read()
+        assert ')rbdjit"' not in text
+        parts.append('R"rbdjit(' + text + ')rbdjit",')
+    parts += ["};", "}  // namespace rbd", ""]
+    new = "\n".join(parts)
+    if not os.path.exists(path) or open(path).read() != new:
+        with open(path, "w") as fh:
+            fh.write(new)
+    return path
 
 
 def build(verbose: bool = False, jobs: int = 0, resource_usage: bool = False, incremental: bool = False) -> str:
     """Compile one object per topology part plus the host sources in parallel, then link librbd.so.
 
-    incremental=True skips objects newer than every source and header (a
-    development convenience; the default always recompiles everything)."""
+    incremental=True skips objects newer than every source and header they
+    are compiled from (a development convenience; the default always
+    recompiles everything)."""
     out_dir = os.path.join(PKG, "_build")
     os.makedirs(out_dir, exist_ok=True)
     jobs = jobs or _jobs()
@@ -64,11 +153,13 @@ def build(verbose: bool = False, jobs: int = 0, resource_usage: bool = False, in
     for src in HOST_SOURCES:
         obj = os.path.join(out_dir, src + ".o")
         work.append((obj, [HIPCC, *COMMON, "-c", os.path.join(CSRC, src), "-o", obj]))
+    jit_src = write_jit_sources(out_dir)
+    obj = os.path.join(out_dir, "rbd_jit_sources.o")
+    work.append((obj, [HIPCC, *COMMON, "-c", jit_src, "-o", obj]))
     t0 = time.time()
     running, logs, objs = [], [], []
     if incremental and not resource_usage:
-        newest = _newest_source()
-        fresh = [(o, c) for o, c in work if os.path.exists(o) and os.path.getmtime(o) > newest]
+        fresh = [(o, c) for o, c in work if os.path.exists(o) and os.path.getmtime(o) > _newest(_deps(o, c))]
         objs = [o for o, _ in fresh]
         work = [(o, c) for o, c in work if (o, c) not in fresh]
     pending = list(work)
@@ -93,13 +184,15 @@ def build(verbose: bool = False, jobs: int = 0, resource_usage: bool = False, in
             logs.append(err)
             objs.append(obj)
     tmp = LIB + ".tmp"
-    link = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", *sorted(objs), "-o", tmp, "-lpthread"]
+    link = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", *sorted(objs), "-o", tmp, "-lpthread", "-lhiprtc",
+            "-ldl"]
     if verbose:
         print(" ".join(link), flush=True)
     subprocess.run(link, check=True)
     os.replace(tmp, LIB)
     if verbose:
         print(f"built {LIB} in {time.time() - t0:.1f}s", flush=True)
+    prebuild_jit(verbose, jobs)
     if resource_usage:
         return "\n".join(logs)
     return LIB

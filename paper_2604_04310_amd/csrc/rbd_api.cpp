@@ -81,6 +81,24 @@ static bool finite_all(const double* x, int n) {
   return true;
 }
 
+// parent[i] in [-1, i) and depth-first numbering: every subtree is a
+// contiguous range of bodies.
+static rbd_status validate_topology(int n, const int32_t* parent) {
+  for (int i = 0; i < n; ++i)
+    if (parent[i] < -1 || parent[i] >= i) return fail(RBD_E_INVAL, "parent[%d] = %d: need -1 <= parent[i] < i", i, parent[i]);
+  for (int i = 0; i < n; ++i) {
+    bool inside = true;
+    for (int k = i + 1; k < n; ++k) {
+      int j = k;
+      while (j > i) j = parent[j];
+      const bool desc = (j == i);
+      if (desc && !inside) return fail(RBD_E_INVAL, "subtree of body %d is not contiguous (need depth-first order)", i);
+      if (!desc) inside = false;
+    }
+  }
+  return RBD_OK;
+}
+
 static rbd_status validate(const rbd_tree_desc* d) {
   if (!d) return fail(RBD_E_INVAL, "desc is NULL");
   const int n = d->n_bodies;
@@ -117,18 +135,7 @@ static rbd_status validate(const rbd_tree_desc* d) {
     if (!(ev[0] > 0.0)) return fail(RBD_E_INVAL, "inertia of body %d is not positive definite", i);
     if (ev[0] + ev[1] < ev[2] - tol) return fail(RBD_E_INVAL, "inertia of body %d violates the triangle inequality", i);
   }
-  // depth-first numbering: every subtree is a contiguous range
-  for (int i = 0; i < n; ++i) {
-    bool inside = true;
-    for (int k = i + 1; k < n; ++k) {
-      int j = k;
-      while (j > i) j = d->parent[j];
-      const bool desc = (j == i);
-      if (desc && !inside) return fail(RBD_E_INVAL, "subtree of body %d is not contiguous (need depth-first order)", i);
-      if (!desc) inside = false;
-    }
-  }
-  return RBD_OK;
+  return validate_topology(n, d->parent);
 }
 
 // FP32 tables, see rbd_lane.hpp: 32 floats per body, then gravity.
@@ -223,6 +230,7 @@ const char* rbd_status_str(rbd_status s) {
     case RBD_E_UNSUPPORTED: return "unsupported topology";
     case RBD_E_TIMEOUT: return "timed out";
     case RBD_E_SHUTDOWN: return "shutting down";
+    case RBD_E_COMPILE: return "run-time compilation failed";
   }
   return "unknown status";
 }
@@ -243,10 +251,11 @@ rbd_status rbd_model_create(const rbd_tree_desc* desc, int device, rbd_model** o
   const int n = desc->n_bodies;
   const bool floating = desc->joint_type[0] == RBD_JOINT_FREE;
   const int topo = find_topology(floating, n, desc->parent);
-  if (topo < 0) return fail(RBD_E_UNSUPPORTED, "no compiled kernel for this tree (%d bodies%s)", n, floating ? ", free base" : "");
   const int ndev = rbd_device_count();
   if (device < 0 || device >= ndev) return fail(RBD_E_NODEVICE, "device %d is not available (%d visible)", device, ndev);
   if ((st = use_device(device)) != RBD_OK) return st;
+  const KernelSet* ks = topo >= 0 ? aot_kernels(topo) : nullptr;
+  if (!ks && (st = jit_kernels(floating, n, desc->parent, device, &ks)) != RBD_OK) return st;
   std::vector<float> tab = make_tables(desc);
   rbd_model* m = new (std::nothrow) rbd_model;
   if (!m) return fail(RBD_E_NOMEM, "host allocation failed");
@@ -254,6 +263,7 @@ rbd_status rbd_model_create(const rbd_tree_desc* desc, int device, rbd_model** o
   m->uid = next_uid.fetch_add(1);
   m->device = device;
   m->topo = topo;
+  m->ks = ks;
   m->n = n;
   m->floating = floating;
   m->nq = n + (floating ? 6 : 0);
@@ -291,8 +301,20 @@ rbd_status rbd_model_dims(const rbd_model* m, int* nq, int* nv, int* n_bodies) {
 }
 
 const char* rbd_model_topology(const rbd_model* m) {
-  if (!m || m->topo < 0) return "";
-  return topology(m->topo).name;
+  if (!m || !m->ks) return "";
+  return m->ks->name;
+}
+
+rbd_status rbd_precompile_topology(int32_t n_bodies, const int32_t* parent, int floating, const char* cache_dir,
+                                   int32_t kernel) {
+  static_assert(KID_COUNT == RBD_N_KERNELS, "RBD_N_KERNELS differs from the kernel list");
+  if (!parent) return fail(RBD_E_INVAL, "parent is NULL");
+  if (n_bodies < 1 || n_bodies > 64) return fail(RBD_E_INVAL, "n_bodies = %d, expected 1..64", n_bodies);
+  if (kernel < -1 || kernel >= KID_COUNT)
+    return fail(RBD_E_INVAL, "kernel = %d, expected -1 or 0..%d", kernel, KID_COUNT - 1);
+  rbd_status st = validate_topology(n_bodies, parent);
+  if (st != RBD_OK) return st;
+  return jit_precompile(floating != 0, n_bodies, parent, cache_dir, kernel);
 }
 
 rbd_status rbd_fk(const rbd_model* m, int64_t batch, int64_t ld, const float* q, float* T, hipStream_t s) {

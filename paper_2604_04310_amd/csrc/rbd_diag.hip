@@ -1,5 +1,6 @@
-// Diagnostic: the FP32 fused-multiply-add issue rate of the device at a given
-// launch shape, the measured ceiling beside the published FP32 peak.
+// Diagnostics: the FP32 fused-multiply-add issue rate of the device at a given
+// launch shape, and the streaming HBM bandwidth (write-only and copy), the
+// measured ceilings beside the published FP32 and HBM peaks.
 #include <hip/hip_runtime.h>
 
 #include "rbd_internal.hpp"
@@ -44,8 +45,80 @@ rbd_status time_rate(float* buf, int blocks, int fma_per_lane, hipStream_t s, hi
   return RBD_OK;
 }
 
+// Streaming HBM kernels over n float4 elements: a grid-stride loop of 16-byte
+// accesses, consecutive lanes on consecutive addresses. WRITE stores a value
+// with non-temporal stores (as the pose, mass-matrix and Jacobian outputs are
+// written); COPY reads src and writes dst.
+template <bool COPY>
+__global__ __launch_bounds__(256) void k_hbm_stream(const float4* __restrict__ src, float4* __restrict__ dst,
+                                                    int64_t n, float v) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    float4 x;
+    if constexpr (COPY) x = src[i];
+    else x = make_float4(v, v, v, v);
+    __builtin_nontemporal_store(x.x, &dst[i].x);
+    __builtin_nontemporal_store(x.y, &dst[i].y);
+    __builtin_nontemporal_store(x.z, &dst[i].z);
+    __builtin_nontemporal_store(x.w, &dst[i].w);
+  }
+}
+
 }  // namespace
 }  // namespace rbd
+
+// Best of 10 timed launches (after 3 warm-up launches) of the streaming kernel
+// over `bytes` bytes (rounded down to 16), with 256-thread blocks, `blocks` of
+// them; GB/s counts the bytes moved to and from HBM (copy: read + write).
+extern "C" rbd_status rbd_diag_hbm_rate(int device, int64_t bytes, int mode, int blocks, double* gbs) {
+  using namespace rbd;
+  if (!gbs) return fail(RBD_E_INVAL, "gbs is NULL");
+  if (mode != 0 && mode != 1) return fail(RBD_E_INVAL, "mode = %d, expected 0 (write) or 1 (copy)", mode);
+  if (bytes < (1 << 20) || bytes > (int64_t(16) << 30))
+    return fail(RBD_E_INVAL, "bytes = %lld, expected 1 MiB .. 16 GiB", (long long)bytes);
+  if (blocks < 1 || blocks > (1 << 20)) return fail(RBD_E_INVAL, "blocks = %d, expected 1..2^20", blocks);
+  if (device < 0 || device >= rbd_device_count()) return fail(RBD_E_NODEVICE, "device %d is not available", device);
+  if (hipSetDevice(device) != hipSuccess) return fail(RBD_E_NODEVICE, "cannot select device %d", device);
+  const int64_t n = bytes / 16;
+  float4 *src = nullptr, *dst = nullptr;
+  if (hipMalloc(&dst, n * 16) != hipSuccess) return fail(RBD_E_NOMEM, "allocation failed");
+  if (mode == 1 && hipMalloc(&src, n * 16) != hipSuccess) {
+    (void)hipFree(dst);
+    return fail(RBD_E_NOMEM, "allocation failed");
+  }
+  if (src) (void)hipMemset(src, 0, n * 16);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  (void)hipEventCreate(&e0);
+  (void)hipEventCreate(&e1);
+  auto launch = [&]() {
+    if (mode == 1)
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_hbm_stream<true>), dim3(blocks), dim3(256), 0, nullptr, src, dst, n, 0.0f);
+    else
+      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_hbm_stream<false>), dim3(blocks), dim3(256), 0, nullptr, src, dst, n,
+                         1.0f);
+  };
+  rbd_status st = RBD_OK;
+  float best = 0.0f;
+  for (int w = 0; w < 3; ++w) launch();
+  for (int r = 0; r < 10 && st == RBD_OK; ++r) {
+    float ms = 0.0f;
+    if (hipEventRecord(e0, nullptr) != hipSuccess) st = fail(RBD_E_LAUNCH, "event record failed");
+    launch();
+    if (st == RBD_OK && hipGetLastError() != hipSuccess) st = fail(RBD_E_LAUNCH, "launch failed");
+    if (st == RBD_OK && (hipEventRecord(e1, nullptr) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                         hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+      st = fail(RBD_E_LAUNCH, "event timing failed");
+    if (st == RBD_OK && (best == 0.0f || ms < best)) best = ms;
+  }
+  (void)hipDeviceSynchronize();
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)hipFree(dst);
+  if (src) (void)hipFree(src);
+  if (st != RBD_OK) return st;
+  *gbs = (mode == 1 ? 2.0 : 1.0) * (double)(n * 16) / (best * 1e-3) / 1e9;
+  return RBD_OK;
+}
 
 extern "C" rbd_status rbd_diag_fma_rate(int device, int blocks, int ilp, double* tflops) {
   using namespace rbd;

@@ -1,5 +1,6 @@
-// Topology registry and dispatch of the C entry points to the kernels of the
-// model's compiled topology.
+// Topology registry and dispatch of the C entry points: each launcher picks a
+// kernel of the model's kernel set (variant and launch shape from the model's
+// sizes) and launches it, ahead-of-time and run-time-compiled kernels alike.
 #include <hip/hip_runtime.h>
 
 #include <cstdlib>
@@ -11,9 +12,17 @@
 
 namespace rbd {
 
-#define RBD_DECL(name, fr, ...) \
-  extern const LaunchTable launch_table_##name##_p1, launch_table_##name##_p2, launch_table_##name##_p3, \
-      launch_table_##name##_p4, launch_table_##name##_p5, launch_table_##name##_p6, launch_table_##name##_p7;
+static_assert(kOpFwdDyn == RBD_OP_FWD_DYN && kOpRnea == RBD_OP_RNEA && kOpFwdDynVjp == RBD_OP_FWD_DYN_VJP,
+              "packed operation ids differ from rbd_op");
+
+#define RBD_DECL(name, fr, ...)                                                                              \
+  void kernels_##name##_p1(const void**);                                                                    \
+  void kernels_##name##_p2(const void**);                                                                    \
+  void kernels_##name##_p3(const void**);                                                                    \
+  void kernels_##name##_p4(const void**);                                                                    \
+  void kernels_##name##_p5(const void**);                                                                    \
+  void kernels_##name##_p6(const void**);                                                                    \
+  void kernels_##name##_p7(const void**);
 RBD_TOPOLOGIES(RBD_DECL)
 #undef RBD_DECL
 
@@ -27,31 +36,32 @@ static const TopoInfo k_topos[] = {
 #undef RBD_INFO
 };
 
-static const LaunchTable* const k_parts[][7] = {
-#define RBD_TAB(name, fr, ...)                                                                                  \
-  {&launch_table_##name##_p1, &launch_table_##name##_p2, &launch_table_##name##_p3, &launch_table_##name##_p4, \
-   &launch_table_##name##_p5, &launch_table_##name##_p6, &launch_table_##name##_p7},
+using FillFn = void (*)(const void**);
+static const FillFn k_fill[][kParts] = {
+#define RBD_TAB(name, fr, ...)                                                                            \
+  {&kernels_##name##_p1, &kernels_##name##_p2, &kernels_##name##_p3, &kernels_##name##_p4, \
+   &kernels_##name##_p5, &kernels_##name##_p6, &kernels_##name##_p7},
     RBD_TOPOLOGIES(RBD_TAB)
 #undef RBD_TAB
 };
 
-// The seven parts of a topology merged into one table (built on first use).
-static const LaunchTable* merged(int id) {
-  static const std::vector<LaunchTable> all = [] {
-    std::vector<LaunchTable> v(sizeof(k_parts) / sizeof(k_parts[0]));
-    for (size_t i = 0; i < v.size(); ++i) {
-      const LaunchTable &a = *k_parts[i][0], &b = *k_parts[i][1], &c = *k_parts[i][2], &d = *k_parts[i][3],
-                        &e = *k_parts[i][4], &f = *k_parts[i][5], &g = *k_parts[i][6];
-      v[i] = LaunchTable{a.fk,     a.jacobian,   a.rnea,     a.crba,        b.fwd_dyn, c.vjp, d.aba,
-                         b.packed, c.packed_vjp, e.rnea_ext, e.fwd_dyn_ext, e.aba_ext, f.jvp, g.diff_ik, g.osc};
+int n_topologies() { return (int)(sizeof(k_topos) / sizeof(k_topos[0])); }
+const TopoInfo& topology(int id) { return k_topos[id]; }
+
+// The kernel table of a compiled topology: its seven parts merged (built on
+// first use).
+const KernelSet* aot_kernels(int id) {
+  static const std::vector<KernelSet> all = [] {
+    std::vector<KernelSet> v(n_topologies());
+    for (int i = 0; i < n_topologies(); ++i) {
+      for (int p = 0; p < kParts; ++p) k_fill[i][p](v[i].aot);
+      v[i].name = k_topos[i].name;
     }
     return v;
   }();
-  return &all[id];
+  return (id >= 0 && id < n_topologies()) ? &all[id] : nullptr;
 }
 
-int n_topologies() { return (int)(sizeof(k_topos) / sizeof(k_topos[0])); }
-const TopoInfo& topology(int id) { return k_topos[id]; }
 int find_topology(bool floating, int n, const int32_t* parent) {
   for (int id = 0; id < n_topologies(); ++id) {
     const TopoInfo& t = k_topos[id];
@@ -72,24 +82,62 @@ bool preload_inputs(bool topology_default) {
   return env < 0 ? topology_default : env == 1;
 }
 
-static const LaunchTable* table_of(const rbd_model* m) {
-  return (m->topo >= 0 && m->topo < n_topologies()) ? merged(m->topo) : nullptr;
-}
+// ------------------------------------------------------------------ launch
+static inline unsigned grid_for(int64_t batch) { return (unsigned)((batch + kBlock - 1) / kBlock); }
 
-#define RBD_TABLE_OR_FAIL(m)                                                     \
-  const LaunchTable* lt = table_of(m);                                           \
-  if (!lt) return fail(RBD_E_UNSUPPORTED, "no compiled kernel for this model");
+// Launch shape of the heavy per-lane kernels (forward dynamics, ABA, the two
+// derivatives, OSC), which are register-bound to one wave per SIMD. Up to
+// 65536 lanes (one wave for each of the 256 CUs x 4 SIMDs) they run in 64-lane
+// blocks: below that size 256-lane blocks would leave whole CUs idle and stack
+// four waves on the others, while 64-lane blocks spread the waves over every
+// CU (the humanoid's VJP and JVP at batch 32768 measured 3-5 % faster; at
+// 65536 the two shapes are equal). Larger batches keep 256-lane blocks, which
+// are as fast or faster there.
+constexpr int64_t kOneWavePerSimd = 256 * 4 * 64;
+struct Shape {
+  dim3 grid, block;
+};
+static inline Shape heavy_shape(int64_t batch) {
+  const unsigned blk = batch <= kOneWavePerSimd ? 64 : kBlock;
+  return {dim3((unsigned)((batch + blk - 1) / blk)), dim3(blk)};
+}
+static inline Shape plain_shape(int64_t batch) { return {dim3(grid_for(batch)), dim3(kBlock)}; }
+
+// Trees above 16 DoFs: the large-tree choices the kernels are tuned for
+// (scalar-base addressing is chosen in the kernels themselves).
+static inline bool large(const rbd_model* m) { return m->nv > 16; }
+
+// Launches kernel `id` of the model's set; args point to the kernel's
+// arguments in order.
+static rbd_status launch(const rbd_model* m, KernelId id, Shape sh, void** args, hipStream_t s, const char* what) {
+  const KernelSet* ks = m->ks;
+  if (!ks) return fail(RBD_E_UNSUPPORTED, "%s: the model has no kernels", what);
+  hipError_t e;
+  if (ks->is_jit) {
+    hipFunction_t f = nullptr;
+    const rbd_status st = jit_function(ks, id, &f);
+    if (st != RBD_OK) return st;
+    e = hipModuleLaunchKernel(f, sh.grid.x, sh.grid.y, sh.grid.z, sh.block.x, sh.block.y, sh.block.z, 0, s, args,
+                              nullptr);
+  } else {
+    if (!ks->aot[id]) return fail(RBD_E_UNSUPPORTED, "%s: kernel %d was not compiled", what, (int)id);
+    e = hipLaunchKernel(ks->aot[id], sh.grid, sh.block, args, 0, s);
+  }
+  if (e == hipSuccess) e = hipGetLastError();
+  if (e != hipSuccess) return fail(RBD_E_LAUNCH, "%s: launch failed: %s", what, hipGetErrorString(e));
+  return RBD_OK;
+}
 
 rbd_status launch_fk(const rbd_model* m, int64_t batch, int64_t ld, const float* q, float* T, hipStream_t s) {
   if (batch == 0) return RBD_OK;
-  RBD_TABLE_OR_FAIL(m);
-  return lt->fk(m->d_tab, batch, ld, q, T, s);
+  const float* tab = m->d_tab;
+  void* a[] = {&tab, &batch, &ld, &q, &T};
+  return launch(m, KID_FK, plain_shape(batch), a, s, "rbd_fk");
 }
 
 rbd_status launch_jacobian(const rbd_model* m, int64_t batch, int64_t ld, const float* q, int32_t n_frames,
                            const int32_t* frames, float* J, hipStream_t s) {
   if (batch == 0) return RBD_OK;
-  RBD_TABLE_OR_FAIL(m);
   JacSlots js{};
   js.n_frames = n_frames;
   int count[65] = {0};
@@ -101,70 +149,114 @@ rbd_status launch_jacobian(const rbd_model* m, int64_t batch, int64_t ld, const 
     const int i = frames[f];
     js.slot[js.beg[i] + fill[i]++] = (int16_t)f;
   }
-  return lt->jacobian(m->d_tab, batch, ld, q, js, J, s);
+  const float* tab = m->d_tab;
+  void* a[] = {&tab, &batch, &ld, &q, &js, &J};
+  return launch(m, KID_JACOBIAN, plain_shape(batch), a, s, "rbd_jacobian");
 }
 
+// Large trees issue every input load at kernel entry (without external
+// forces); small ones keep their occupancy instead (measured).
 rbd_status launch_rnea(const rbd_model* m, int64_t batch, int64_t ld, const float* q, const float* qd,
                        const float* qdd, const float* fext, float* tau, hipStream_t s) {
   if (batch == 0) return RBD_OK;
-  RBD_TABLE_OR_FAIL(m);
-  return (fext ? lt->rnea_ext : lt->rnea)(m->d_tab, batch, ld, q, qd, qdd, fext, tau, s);
+  KernelId id;
+  if (fext) id = qdd ? KID_RNEA_EXT : KID_RNEA_BIAS_EXT;
+  else if (large(m) && preload_inputs(true)) id = qdd ? KID_RNEA_PRE : KID_RNEA_BIAS_PRE;
+  else id = qdd ? KID_RNEA : KID_RNEA_BIAS;
+  const float* tab = m->d_tab;
+  void* a[] = {&tab, &batch, &ld, &q, &qd, &qdd, &fext, &tau};
+  return launch(m, id, plain_shape(batch), a, s, "rbd_rnea");
 }
 
 rbd_status launch_crba(const rbd_model* m, int64_t batch, int64_t ld, const float* q, float* M, hipStream_t s) {
   if (batch == 0) return RBD_OK;
-  RBD_TABLE_OR_FAIL(m);
-  return lt->crba(m->d_tab, batch, ld, q, M, s);
+  const float* tab = m->d_tab;
+  void* a[] = {&tab, &batch, &ld, &q, &M};
+  return launch(m, KID_CRBA, plain_shape(batch), a, s, "rbd_crba");
 }
 
 rbd_status launch_fwd_dyn(const rbd_model* m, int64_t batch, int64_t ld, const float* q, const float* qd,
                           const float* tau, const float* fext, float* qdd, hipStream_t s) {
   if (batch == 0) return RBD_OK;
-  RBD_TABLE_OR_FAIL(m);
-  return (fext ? lt->fwd_dyn_ext : lt->fwd_dyn)(m->d_tab, batch, ld, q, qd, tau, fext, qdd, s);
+  const bool pre = preload_inputs(large(m));
+  const KernelId id = fext ? (pre ? KID_FWD_DYN_PRE_EXT : KID_FWD_DYN_EXT) : (pre ? KID_FWD_DYN_PRE : KID_FWD_DYN);
+  const float* tab = m->d_tab;
+  void* a[] = {&tab, &batch, &ld, &q, &qd, &tau, &fext, &qdd};
+  return launch(m, id, heavy_shape(batch), a, s, "rbd_fwd_dyn");
 }
 
+// With external forces the articulated-body sweep is faster loading its
+// inputs in place (humanoid: 77.8 vs 81.6 us).
 rbd_status launch_aba(const rbd_model* m, int64_t batch, int64_t ld, const float* q, const float* qd,
                       const float* tau, const float* fext, float* qdd, hipStream_t s) {
   if (batch == 0) return RBD_OK;
-  RBD_TABLE_OR_FAIL(m);
-  return (fext ? lt->aba_ext : lt->aba)(m->d_tab, batch, ld, q, qd, tau, fext, qdd, s);
+  const bool pre = preload_inputs(large(m) && !fext);
+  const KernelId id = fext ? (pre ? KID_ABA_PRE_EXT : KID_ABA_EXT) : (pre ? KID_ABA_PRE : KID_ABA);
+  const float* tab = m->d_tab;
+  void* a[] = {&tab, &batch, &ld, &q, &qd, &tau, &fext, &qdd};
+  return launch(m, id, heavy_shape(batch), a, s, "rbd_aba");
 }
 
 rbd_status launch_fwd_dyn_jvp(const rbd_model* m, int64_t batch, int64_t ld, const float* q, const float* qd,
                               const float* tau, const float* dq, const float* dqd, const float* dtau, float* qdd,
                               float* dqdd, hipStream_t s) {
   if (batch == 0) return RBD_OK;
-  RBD_TABLE_OR_FAIL(m);
-  return lt->jvp(m->d_tab, batch, ld, q, qd, tau, dq, dqd, dtau, qdd, dqdd, s);
+  const float* tab = m->d_tab;
+  void* a[] = {&tab, &batch, &ld, &q, &qd, &tau, &dq, &dqd, &dtau, &qdd, &dqdd};
+  return launch(m, KID_JVP, heavy_shape(batch), a, s, "rbd_fwd_dyn_jvp");
 }
 
 rbd_status launch_diff_ik(const rbd_model* m, int64_t batch, int64_t ld, const float* q, const float* tgt,
                           float gain, float lam2, float* qd, hipStream_t s) {
   if (batch == 0) return RBD_OK;
-  RBD_TABLE_OR_FAIL(m);
-  return lt->diff_ik(m->d_tab, batch, ld, q, tgt, gain, lam2, qd, s);
+  const float* tab = m->d_tab;
+  void* a[] = {&tab, &batch, &ld, &q, &tgt, &gain, &lam2, &qd};
+  return launch(m, KID_DIFF_IK, plain_shape(batch), a, s, "rbd_diff_ik");
 }
 
 rbd_status launch_osc(const rbd_model* m, int64_t batch, int64_t ld, const float* q, const float* qd,
                       const float* tgt, float kp, float kd, float kn, float* tau, hipStream_t s) {
   if (batch == 0) return RBD_OK;
-  RBD_TABLE_OR_FAIL(m);
-  return lt->osc(m->d_tab, batch, ld, q, qd, tgt, kp, kd, kn, tau, s);
+  const float* tab = m->d_tab;
+  void* a[] = {&tab, &batch, &ld, &q, &qd, &tgt, &kp, &kd, &kn, &tau};
+  return launch(m, KID_OSC, heavy_shape(batch), a, s, "rbd_osc");
 }
 
+// Between the solve and the adjoint sweep, q-double-dot and lam park in
+// output rows that the adjoint overwrites only after reading them: g_qd and
+// g_tau, or, for a large tree missing one of those, g_q shifted by nq - nv
+// rows, so that DoF k lands in the q slot of its own body (the adjoint reads a
+// body's entries in its forward step and writes that body's g_q in its
+// backward step).
 rbd_status launch_fwd_dyn_vjp(const rbd_model* m, int64_t batch, int64_t ld, const float* q, const float* qd,
                               const float* tau, const float* gqdd, float* gq, float* gqd, float* gtau,
                               hipStream_t s) {
   if (batch == 0 || (!gq && !gqd && !gtau)) return RBD_OK;
-  RBD_TABLE_OR_FAIL(m);
-  return lt->vjp(m->d_tab, batch, ld, q, qd, tau, gqdd, gq, gqd, gtau, s);
+  float* const gq_shift = gq ? gq + (int64_t)(m->nq - m->nv) * ld : nullptr;
+  KernelId id;
+  float *park_qdd = gqd, *park_lam = gtau;
+  if (gqd && gtau) {
+    id = KID_VJP_PARK;
+  } else if (large(m) && gq && (gqd || gtau)) {
+    id = KID_VJP_PARK_GQ;
+    park_qdd = gqd ? gqd : gq_shift;
+    park_lam = gtau ? gtau : gq_shift;
+  } else if (gq || gqd) {
+    id = KID_VJP_REGS;
+  } else {
+    id = KID_VJP_TAU;
+  }
+  const float* tab = m->d_tab;
+  void* a[] = {&tab, &batch, &ld, &q, &qd, &tau, &gqdd, &gq, &gqd, &gtau, &park_qdd, &park_lam};
+  return launch(m, id, heavy_shape(batch), a, s, "rbd_fwd_dyn_vjp");
 }
 
 rbd_status launch_packed(const rbd_model* m, int op, const void* d_table, int grid, hipStream_t s) {
-  RBD_TABLE_OR_FAIL(m);
-  if (op == RBD_OP_FWD_DYN_VJP) return lt->packed_vjp(op, m->d_tab, d_table, grid, s);
-  return lt->packed(op, m->d_tab, d_table, grid, s);
+  const KernelId id = op == kOpFwdDynVjp ? KID_PACKED_VJP : (op == kOpFwdDyn ? KID_PACKED_FWD_DYN : KID_PACKED_RNEA);
+  const float* tab = m->d_tab;
+  const uint8_t* t = static_cast<const uint8_t*>(d_table);
+  void* a[] = {&tab, &t};
+  return launch(m, id, Shape{dim3((unsigned)grid), dim3(kBlock)}, a, s, "packed launch");
 }
 
 }  // namespace rbd

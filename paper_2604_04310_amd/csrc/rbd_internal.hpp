@@ -4,15 +4,33 @@
 
 #include <stdint.h>
 
+#include <atomic>
 #include <string>
 #include <vector>
 
 #include "rbd.h"
+#include "rbd_kernel_ids.hpp"
 #include "rbd_shared.hpp"
+
+namespace rbd {
+// The kernels serving a model: those of a topology compiled ahead of time
+// (host stub addresses, launched with hipLaunchKernel), or those compiled at
+// run time for a new topology and loaded on one device (module functions,
+// launched with hipModuleLaunchKernel). A set lives until the process ends.
+struct KernelSet {
+  const void* aot[KID_COUNT] = {};
+  mutable std::atomic<hipFunction_t> jit[KID_COUNT] = {};  // filled on first launch
+  bool is_jit = false;
+  const char* name = "";
+  void* jit_owner = nullptr;  // the run-time topology (rbd_jit.cpp)
+  int device = 0;
+};
+}  // namespace rbd
 
 struct rbd_model {
   int device = 0;
-  int topo = -1;               // index into the compiled topology list
+  int topo = -1;               // index into the compiled topology list (-1: compiled at run time)
+  const rbd::KernelSet* ks = nullptr;
   int n = 0, nq = 0, nv = 0;
   bool floating = false;
   float* d_tab = nullptr;      // device tables (see rbd_lane.hpp)
@@ -44,6 +62,18 @@ struct TopoInfo {
 int n_topologies();
 const TopoInfo& topology(int id);
 int find_topology(bool floating, int n, const int32_t* parent);
+const KernelSet* aot_kernels(int id);
+
+// ---- run-time compilation of a topology that has no compiled kernels
+// (rbd_jit.cpp). jit_kernels returns the topology's kernel set for `device`
+// (shared by every model of the topology, alive until the process ends);
+// jit_function compiles (or reads from the code-object cache) and loads one of
+// its kernels on first use.
+rbd_status jit_kernels(bool floating, int n, const int32_t* parent, int device, const KernelSet** out);
+rbd_status jit_function(const KernelSet* ks, KernelId id, hipFunction_t* out);
+// Compiles kernel `kernel` of the topology (-1: every kernel) into the cache
+// directory (NULL: the default one); needs no device.
+rbd_status jit_precompile(bool floating, int n, const int32_t* parent, const char* cache_dir, int kernel);
 
 // ---- kernel dispatch (rbd_kernels.hip); arguments are already validated
 rbd_status launch_fk(const rbd_model* m, int64_t batch, int64_t ld, const float* q, float* T, hipStream_t s);
@@ -67,34 +97,6 @@ rbd_status launch_fwd_dyn_vjp(const rbd_model* m, int64_t batch, int64_t ld, con
                               const float* tau, const float* gqdd, float* gq, float* gqd, float* gtau,
                               hipStream_t s);
 
-
-// Host launch wrappers of one compiled topology (see rbd_kernels.hpp).
-struct LaunchTable {
-  using RneaFn = rbd_status (*)(const float* tab, int64_t batch, int64_t ld, const float* q, const float* qd,
-                                const float* qdd, const float* fext, float* tau, hipStream_t s);
-  using FdFn = rbd_status (*)(const float* tab, int64_t batch, int64_t ld, const float* q, const float* qd,
-                              const float* tau, const float* fext, float* qdd, hipStream_t s);
-  rbd_status (*fk)(const float* tab, int64_t batch, int64_t ld, const float* q, float* T, hipStream_t s);
-  rbd_status (*jacobian)(const float* tab, int64_t batch, int64_t ld, const float* q, const JacSlots& js, float* J,
-                         hipStream_t s);
-  RneaFn rnea;
-  rbd_status (*crba)(const float* tab, int64_t batch, int64_t ld, const float* q, float* M, hipStream_t s);
-  FdFn fwd_dyn;
-  rbd_status (*vjp)(const float* tab, int64_t batch, int64_t ld, const float* q, const float* qd, const float* tau,
-                    const float* gqdd, float* gq, float* gqd, float* gtau, hipStream_t s);
-  FdFn aba;
-  rbd_status (*packed)(int op, const float* tab, const void* table, int grid, hipStream_t s);
-  rbd_status (*packed_vjp)(int op, const float* tab, const void* table, int grid, hipStream_t s);
-  RneaFn rnea_ext;  // with external forces (fext non-null)
-  FdFn fwd_dyn_ext;
-  FdFn aba_ext;
-  rbd_status (*jvp)(const float* tab, int64_t batch, int64_t ld, const float* q, const float* qd, const float* tau,
-                    const float* dq, const float* dqd, const float* dtau, float* qdd, float* dqdd, hipStream_t s);
-  rbd_status (*diff_ik)(const float* tab, int64_t batch, int64_t ld, const float* q, const float* tgt, float gain,
-                        float lam2, float* qd, hipStream_t s);
-  rbd_status (*osc)(const float* tab, int64_t batch, int64_t ld, const float* q, const float* qd, const float* tgt,
-                    float kp, float kd, float kn, float* tau, hipStream_t s);
-};
 
 // Packed serving launch of one (model, op): d_table holds a PackedHdr-led
 // descriptor table in device memory; grid blocks of 256 threads stride over it.

@@ -1,5 +1,10 @@
 // Kernels of one compiled topology. Built once per entry of RBD_TOPOLOGIES
 // and part (-DRBD_TOPO=<name> -DRBD_PART=1..7), so they compile in parallel.
+// The part's function stores the address of each of its kernels in its slot
+// of the topology's kernel table.
+#include <hip/hip_runtime.h>
+
+#include "rbd_kernel_ids.hpp"
 #include "rbd_kernels.hpp"
 #include "rbd_topologies.hpp"
 
@@ -19,8 +24,12 @@ using TP = RBD_CAT(T_, RBD_TOPO);
 static_assert(TP::depth_first(), "topology is not depth-first");
 }  // namespace
 
-#define RBD_NAME RBD_CAT(RBD_CAT(RBD_CAT(launch_table_, RBD_TOPO), _p), RBD_PART)
-extern const LaunchTable RBD_NAME;
-const LaunchTable RBD_NAME = Launch<TP>::part<RBD_PART>();
+#define RBD_NAME RBD_CAT(RBD_CAT(RBD_CAT(kernels_, RBD_TOPO), _p), RBD_PART)
+void RBD_NAME(const void** fn) {
+#define RBD_FILL(id, part, ...) \
+  if constexpr (part == RBD_PART) fn[id] = reinterpret_cast<const void*>(&__VA_ARGS__);
+  RBD_KERNELS(RBD_FILL)
+#undef RBD_FILL
+}
 
 }  // namespace rbd

@@ -1,16 +1,15 @@
-// HIP kernels for gfx950, templated on the compiled tree type, and the host
-// launch wrappers each topology's translation unit instantiates. The per-lane
-// algorithms live in rbd_lane.hpp.
+// HIP kernels for gfx950, templated on the tree type. Device code only, with
+// no host headers: the ahead-of-time build instantiates it per compiled
+// topology (rbd_kern_topo.hip) and the runtime compiler per new topology
+// (rbd_jit.cpp), from the same text. The per-lane algorithms live in
+// rbd_lane.hpp; kernel ids and launch shapes are chosen on the host
+// (rbd_dispatch.cpp).
 #pragma once
 
-#include <hip/hip_runtime.h>
-
-#include "rbd_internal.hpp"
 #include "rbd_lane.hpp"
+#include "rbd_shared.hpp"
 
 namespace rbd {
-
-constexpr int kBlock = 256;
 
 RBD_DI uint32_t lane_id() { return blockIdx.x * blockDim.x + threadIdx.x; }
 
@@ -402,9 +401,9 @@ __global__ __launch_bounds__(kBlock) void k_packed(const float* __restrict__ tab
     const int64_t i = (int64_t)(t - R.first_tile) * kTileLanes + lane;
     if (i >= R.batch) continue;
     const InRow q{R.in[0] + i * NQ}, qd{R.in[1] + i * NV}, x2{R.in[2] + i * NV};
-    if constexpr (OP == RBD_OP_FWD_DYN) {
+    if constexpr (OP == kOpFwdDyn) {
       fwd_dyn_lane<TP, 1>(tab, q, qd, RhsOne<InRow>{x2}, SinkOne<OutRow>{OutRow{R.out[0] + i * NV}});
-    } else if constexpr (OP == RBD_OP_RNEA) {
+    } else if constexpr (OP == kOpRnea) {
       rnea_lane<TP, true>(tab, q, qd, x2, OutRow{R.out[0] + i * NV});
     } else {
       float* gqd = R.out[1] + i * NV;
@@ -414,193 +413,5 @@ __global__ __launch_bounds__(kBlock) void k_packed(const float* __restrict__ tab
     }
   }
 }
-
-// ------------------------------------------------------------------ launchers
-static inline int grid_for(int64_t batch) { return (int)((batch + kBlock - 1) / kBlock); }
-
-// Launch shape of the heavy per-lane kernels (forward dynamics, ABA, the two
-// derivatives, OSC), which are register-bound to one wave per SIMD. Up to
-// 65536 lanes (one wave for each of the 256 CUs x 4 SIMDs) they run in 64-lane
-// blocks: below that size 256-lane blocks would leave whole CUs idle and stack
-// four waves on the others, while 64-lane blocks spread the waves over every
-// CU (the humanoid's VJP and JVP at batch 32768 measured 3-5 % faster; at
-// 65536 the two shapes are equal). Larger batches keep 256-lane blocks, which
-// are as fast or faster there.
-constexpr int64_t kOneWavePerSimd = 256 * 4 * 64;
-struct Shape {
-  dim3 grid, block;
-};
-static inline Shape heavy_shape(int64_t batch) {
-  const int blk = batch <= kOneWavePerSimd ? 64 : kBlock;
-  return {dim3((unsigned)((batch + blk - 1) / blk)), dim3(blk)};
-}
-
-static inline rbd_status check_launch(const char* what) {
-  const hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return fail(RBD_E_LAUNCH, "%s: launch failed: %s", what, hipGetErrorString(e));
-  return RBD_OK;
-}
-
-template <class TP>
-struct Launch {
-  static rbd_status fk(const float* tab, int64_t batch, int64_t ld, const float* q, float* T, hipStream_t s) {
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_fk<TP>), dim3(grid_for(batch)), dim3(kBlock), 0, s, tab, batch, ld, q, T);
-    return check_launch("rbd_fk");
-  }
-  static rbd_status jacobian(const float* tab, int64_t batch, int64_t ld, const float* q, const JacSlots& js,
-                             float* J, hipStream_t s) {
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_jacobian<TP>), dim3(grid_for(batch)), dim3(kBlock), 0, s, tab, batch, ld,
-                       q, js, J);
-    return check_launch("rbd_jacobian");
-  }
-  template <bool EXT>
-  static rbd_status rnea_t(const float* tab, int64_t batch, int64_t ld, const float* q, const float* qd,
-                           const float* qdd, const float* fext, float* tau, hipStream_t s) {
-    constexpr bool kPre = TP::NV > 16 && !EXT;
-    if (kPre && preload_inputs(kPre)) {
-      if (qdd)
-        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_rnea<TP, true, EXT, kPre>), dim3(grid_for(batch)), dim3(kBlock), 0, s,
-                           tab, batch, ld, q, qd, qdd, fext, tau);
-      else
-        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_rnea<TP, false, EXT, kPre>), dim3(grid_for(batch)), dim3(kBlock), 0, s,
-                           tab, batch, ld, q, qd, qdd, fext, tau);
-    } else if (qdd) {
-      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_rnea<TP, true, EXT>), dim3(grid_for(batch)), dim3(kBlock), 0, s, tab,
-                         batch, ld, q, qd, qdd, fext, tau);
-    } else {
-      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_rnea<TP, false, EXT>), dim3(grid_for(batch)), dim3(kBlock), 0, s, tab,
-                         batch, ld, q, qd, qdd, fext, tau);
-    }
-    return check_launch("rbd_rnea");
-  }
-  static rbd_status crba(const float* tab, int64_t batch, int64_t ld, const float* q, float* M, hipStream_t s) {
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_crba<TP>), dim3(grid_for(batch)), dim3(kBlock), 0, s, tab, batch, ld, q,
-                       M);
-    return check_launch("rbd_crba");
-  }
-  // Large trees run one wave per SIMD and gain from issuing all input loads up
-  // front; small ones keep their occupancy instead (measured).
-  template <bool EXT>
-  static rbd_status fwd_dyn_t(const float* tab, int64_t batch, int64_t ld, const float* q, const float* qd,
-                              const float* tau, const float* fext, float* qdd, hipStream_t s) {
-    const Shape sh = heavy_shape(batch);
-    constexpr bool kPre = TP::NV > 16;
-    if (preload_inputs(kPre))
-      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_fwd_dyn<TP, true, EXT>), sh.grid, sh.block, 0, s, tab,
-                         batch, ld, q, qd, tau, fext, qdd);
-    else
-      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_fwd_dyn<TP, false, EXT>), sh.grid, sh.block, 0, s,
-                         tab, batch, ld, q, qd, tau, fext, qdd);
-    return check_launch("rbd_fwd_dyn");
-  }
-  template <bool EXT>
-  static rbd_status aba_t(const float* tab, int64_t batch, int64_t ld, const float* q, const float* qd,
-                          const float* tau, const float* fext, float* qdd, hipStream_t s) {
-    const Shape sh = heavy_shape(batch);
-    // with external forces the articulated-body sweep is faster loading its
-    // inputs in place (humanoid: 77.8 vs 81.6 us)
-    constexpr bool kPre = TP::NV > 16 && !EXT;
-    if (preload_inputs(kPre))
-      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_aba<TP, true, EXT>), sh.grid, sh.block, 0, s, tab,
-                         batch, ld, q, qd, tau, fext, qdd);
-    else
-      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_aba<TP, false, EXT>), sh.grid, sh.block, 0, s, tab,
-                         batch, ld, q, qd, tau, fext, qdd);
-    return check_launch("rbd_aba");
-  }
-  static rbd_status vjp(const float* tab, int64_t batch, int64_t ld, const float* q, const float* qd,
-                        const float* tau, const float* gqdd, float* gq, float* gqd, float* gtau, hipStream_t s) {
-    const Shape sh = heavy_shape(batch);
-    // Between the solve and the adjoint sweep, q-double-dot and lam park in
-    // output rows that the adjoint overwrites only after reading them: g_qd
-    // and g_tau, or, for a large tree missing one of those, g_q shifted by
-    // nq - nv rows, so that DoF k lands in the q slot of its own body (the
-    // adjoint reads a body's entries in its forward step and writes that
-    // body's g_q in its backward step).
-    constexpr bool kVjpParkInGq = TP::NV > 16;
-    float* const gq_shift = gq ? gq + (TP::NQ - TP::NV) * ld : nullptr;
-    if (gqd && gtau)
-      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_fwd_dyn_vjp<TP, 2>), sh.grid, sh.block, 0, s, tab,
-                         batch, ld, q, qd, tau, gqdd, gq, gqd, gtau, gqd, gtau);
-    else if (kVjpParkInGq && gq && (gqd || gtau))
-      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_fwd_dyn_vjp<TP, kVjpParkInGq ? 3 : 2>), sh.grid, sh.block, 0, s, tab,
-                         batch, ld, q, qd, tau, gqdd, gq, gqd, gtau, gqd ? gqd : gq_shift, gtau ? gtau : gq_shift);
-    else if (gq || gqd)
-      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_fwd_dyn_vjp<TP, 1>), sh.grid, sh.block, 0, s, tab,
-                         batch, ld, q, qd, tau, gqdd, gq, gqd, gtau, gqd, gtau);
-    else
-      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_fwd_dyn_vjp<TP, 0>), sh.grid, sh.block, 0, s, tab,
-                         batch, ld, q, qd, tau, gqdd, gq, gqd, gtau, gqd, gtau);
-    return check_launch("rbd_fwd_dyn_vjp");
-  }
-  static rbd_status jvp(const float* tab, int64_t batch, int64_t ld, const float* q, const float* qd,
-                        const float* tau, const float* dq, const float* dqd, const float* dtau, float* qdd,
-                        float* dqdd, hipStream_t s) {
-    const Shape sh = heavy_shape(batch);
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_fwd_dyn_jvp<TP>), sh.grid, sh.block, 0, s, tab, batch, ld,
-                       q, qd, tau, dq, dqd, dtau, qdd, dqdd);
-    return check_launch("rbd_fwd_dyn_jvp");
-  }
-  static rbd_status diff_ik(const float* tab, int64_t batch, int64_t ld, const float* q, const float* tgt, float gain,
-                            float lam2, float* qd, hipStream_t s) {
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_diff_ik<TP>), dim3(grid_for(batch)), dim3(kBlock), 0, s, tab, batch, ld, q,
-                       tgt, gain, lam2, qd);
-    return check_launch("rbd_diff_ik");
-  }
-  static rbd_status osc(const float* tab, int64_t batch, int64_t ld, const float* q, const float* qd,
-                        const float* tgt, float kp, float kd, float kn, float* tau, hipStream_t s) {
-    const Shape sh = heavy_shape(batch);
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_osc<TP>), sh.grid, sh.block, 0, s, tab, batch, ld, q, qd, tgt, kp, kd, kn,
-                       tau);
-    return check_launch("rbd_osc");
-  }
-  static rbd_status packed(int op, const float* tab, const void* table, int grid, hipStream_t s) {
-    const uint8_t* t = static_cast<const uint8_t*>(table);
-    if (op == RBD_OP_FWD_DYN)
-      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_packed<TP, RBD_OP_FWD_DYN>), dim3(grid), dim3(kBlock), 0, s, tab, t);
-    else
-      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_packed<TP, RBD_OP_RNEA>), dim3(grid), dim3(kBlock), 0, s, tab, t);
-    return check_launch("packed launch");
-  }
-  static rbd_status packed_vjp(int, const float* tab, const void* table, int grid, hipStream_t s) {
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_packed<TP, RBD_OP_FWD_DYN_VJP>), dim3(grid), dim3(kBlock), 0, s, tab,
-                       static_cast<const uint8_t*>(table));
-    return check_launch("packed launch");
-  }
-  // Part 1: kinematics, inverse dynamics, mass matrix. Part 2: forward dynamics
-  // and the packed forward-dynamics and inverse-dynamics launches. Part 3: the
-  // adjoint and its packed launch. Part 4: the articulated-body algorithm.
-  // Part 5: the external-force variants of inverse and forward dynamics. Part
-  // 6: the forward-mode derivative. Part 7: the controller workloads. Each part
-  // is its own translation unit and instantiates only its own kernels.
-  template <int K>
-  static LaunchTable part() {
-    LaunchTable t{};
-    if constexpr (K == 1) {
-      t.fk = &Launch::fk;
-      t.jacobian = &Launch::jacobian;
-      t.rnea = &Launch::rnea_t<false>;
-      t.crba = &Launch::crba;
-    } else if constexpr (K == 2) {
-      t.fwd_dyn = &Launch::fwd_dyn_t<false>;
-      t.packed = &Launch::packed;
-    } else if constexpr (K == 3) {
-      t.vjp = &Launch::vjp;
-      t.packed_vjp = &Launch::packed_vjp;
-    } else if constexpr (K == 4) {
-      t.aba = &Launch::aba_t<false>;
-    } else if constexpr (K == 5) {
-      t.rnea_ext = &Launch::rnea_t<true>;
-      t.fwd_dyn_ext = &Launch::fwd_dyn_t<true>;
-      t.aba_ext = &Launch::aba_t<true>;
-    } else if constexpr (K == 6) {
-      t.jvp = &Launch::jvp;
-    } else {
-      t.diff_ik = &Launch::diff_ik;
-      t.osc = &Launch::osc;
-    }
-    return t;
-  }
-};
 
 }  // namespace rbd

@@ -322,7 +322,9 @@ rbd_status launch_group(rbd_server* s, Group* g) {
   return RBD_OK;
 }
 
-void finish_group(rbd_server* s, Group* g, const Clock::time_point now) {
+// Delivers a group's results (or its failure) to its requests and frees its
+// block and slot; `inflight` says whether the group is in the in-flight list.
+void finish_group(rbd_server* s, Group* g, const Clock::time_point now, bool inflight = true) {
   // results -> client buffers (instance-major, as requested)
   if (g->status == RBD_OK) {
     const uint8_t* hb = s->h_stage + g->off;
@@ -346,8 +348,10 @@ void finish_group(rbd_server* s, Group* g, const Clock::time_point now) {
     s->n_inst += (uint64_t)rp->batch;
   }
   s->n_launch++;
-  s->inflight.erase(std::find(s->inflight.begin(), s->inflight.end(), g));
-  if (s->inflight.empty()) s->busy_s += std::chrono::duration<double>(now - s->busy_since).count();
+  if (inflight) {
+    s->inflight.erase(std::find(s->inflight.begin(), s->inflight.end(), g));
+    if (s->inflight.empty()) s->busy_s += std::chrono::duration<double>(now - s->busy_since).count();
+  }
   delete g;
   s->cv_done.notify_all();
   s->cv_work.notify_all();
@@ -384,18 +388,20 @@ void dispatcher_main(rbd_server* s) {
     s->slots[g->slot].busy = true;
     lk.unlock();
     g->status = launch_group(s, g);
+    if (g->status != RBD_OK) {
+      // A failed group never reaches the completion thread (which reads the
+      // groups in flight without the lock): copies queued before the failure
+      // may still run, so drain them, then fail this group's requests only
+      // and return its block to the arena.
+      (void)hipStreamSynchronize(s->slots[g->slot].stream);
+      finish_group(s, g, Clock::now(), false);
+      lk.lock();
+      continue;
+    }
     lk.lock();
     if (s->inflight.empty()) s->busy_since = Clock::now();
     s->inflight.push_back(g);
     s->cv_inflight.notify_all();
-    if (g->status != RBD_OK) {
-      lk.unlock();
-      // copies queued before the failure may still run: drain them before the
-      // block goes back to the arena
-      (void)hipStreamSynchronize(s->slots[g->slot].stream);
-      finish_group(s, g, Clock::now());
-      lk.lock();
-    }
   }
   s->dispatcher_done = true;
   s->cv_work.notify_all();
@@ -414,8 +420,7 @@ void completer_main(rbd_server* s) {
     std::vector<Group*> look(s->inflight.begin(), s->inflight.end());
     lk.unlock();
     bool any = false;
-    for (Group* g : look) {
-      if (g->status != RBD_OK) continue;  // failed groups are finished by the dispatcher
+    for (Group* g : look) {  // only this thread finishes (and frees) groups in flight
       const hipError_t e = hipEventQuery(s->slots[g->slot].done);
       if (e == hipErrorNotReady) continue;
       if (e != hipSuccess) g->status = fail(RBD_E_LAUNCH, "server: launch failed on the device");

@@ -5,6 +5,13 @@
 
 namespace rbd {
 
+// Threads per block of the kernels that run one instance per lane (the heavy
+// kernels choose their own block size, see the launchers).
+constexpr int kBlock = 256;
+
+// Operations of a packed serving launch (equal to rbd_op's values).
+constexpr int kOpFwdDyn = 0, kOpRnea = 1, kOpFwdDynVjp = 2;
+
 // Jacobian output frames grouped by body: output slots slot[beg[i] .. beg[i+1])
 // are frames of body i. Passed by value as a kernel argument.
 struct JacSlots {

@@ -23,13 +23,13 @@ LIB_PATH = os.path.join(PKG, "librbd.so")
 
 RBD_OK = 0
 STATUS = {0: "RBD_OK", 1: "RBD_E_INVAL", 2: "RBD_E_NOMEM", 3: "RBD_E_NODEVICE", 4: "RBD_E_LAUNCH",
-          5: "RBD_E_UNSUPPORTED", 6: "RBD_E_TIMEOUT", 7: "RBD_E_SHUTDOWN"}
+          5: "RBD_E_UNSUPPORTED", 6: "RBD_E_TIMEOUT", 7: "RBD_E_SHUTDOWN", 8: "RBD_E_COMPILE"}
 OP_FWD_DYN, OP_RNEA, OP_FWD_DYN_VJP = 0, 1, 2
 
 # Every symbol include/rbd.h declares.
 EXPORTS = ["rbd_model_create", "rbd_model_destroy", "rbd_model_dims", "rbd_model_topology", "rbd_fk",
            "rbd_jacobian", "rbd_rnea", "rbd_crba", "rbd_fwd_dyn", "rbd_aba", "rbd_fwd_dyn_jvp", "rbd_fwd_dyn_vjp", "rbd_diff_ik", "rbd_osc", "rbd_status_str",
-           "rbd_last_error", "rbd_device_count", "rbd_diag_fma_rate", "rbd_server_create", "rbd_server_submit", "rbd_server_wait",
+           "rbd_last_error", "rbd_device_count", "rbd_diag_fma_rate", "rbd_diag_hbm_rate", "rbd_precompile_topology", "rbd_server_create", "rbd_server_submit", "rbd_server_wait",
            "rbd_server_get_stats", "rbd_server_reset_stats", "rbd_server_destroy"]
 
 
@@ -98,6 +98,8 @@ def lib():
         L.rbd_last_error.restype = C.c_char_p
         L.rbd_device_count.argtypes = []
         L.rbd_diag_fma_rate.argtypes = [C.c_int, C.c_int, C.c_int, P(C.c_double)]
+        L.rbd_diag_hbm_rate.argtypes = [C.c_int, C.c_int64, C.c_int, C.c_int, P(C.c_double)]
+        L.rbd_precompile_topology.argtypes = [C.c_int32, P(C.c_int32), C.c_int, C.c_char_p, C.c_int32]
         L.rbd_server_create.argtypes = [P(ServerConfigC), P(vp)]
         L.rbd_server_submit.argtypes = [vp, vp, C.c_int, i64, P(vp), P(vp), P(C.c_uint64)]
         L.rbd_server_wait.argtypes = [vp, C.c_uint64, C.c_double, P(C.c_int)]
@@ -121,6 +123,23 @@ def fma_rate(blocks: int = 256, ilp: int = 16, device: int = 0) -> float:
     """Measured FP32 FMA TFLOP/s at a launch of `blocks` x 256 threads (diagnostic)."""
     out = C.c_double()
     check(lib().rbd_diag_fma_rate(int(device), int(blocks), int(ilp), C.byref(out)))
+    return out.value
+
+
+N_KERNELS = 27
+
+
+def precompile_topology(parent, floating: bool, cache_dir: Optional[str] = None, kernel: int = -1) -> None:
+    """Compile a tree topology's kernels (kernel -1: all of them) into a code-object cache (no GPU needed)."""
+    par = (C.c_int32 * len(parent))(*[int(p) for p in parent])
+    d = None if cache_dir is None else os.fsencode(cache_dir)
+    check(lib().rbd_precompile_topology(len(parent), par, int(bool(floating)), d, int(kernel)))
+
+
+def hbm_rate(nbytes: int = 1 << 30, mode: int = 0, blocks: int = 8192, device: int = 0) -> float:
+    """Measured streaming HBM GB/s: mode 0 writes nbytes, mode 1 copies them (diagnostic)."""
+    out = C.c_double()
+    check(lib().rbd_diag_hbm_rate(int(device), int(nbytes), int(mode), int(blocks), C.byref(out)))
     return out.value
 
 

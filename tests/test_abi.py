@@ -86,9 +86,57 @@ def test_null_desc(rbd):
     assert st == 1 and "NULL" in err
 
 
-def test_unsupported_topology(rbd):
+def test_new_topology_without_device(rbd):
+    """A valid tree outside the compiled list is accepted (its kernels are compiled at run time on a
+    device host); without a GPU the call stops at the device check, before compiling."""
     st, err = _create(rbd, W.random_tree([-1, 0, 0], False, 4))
-    assert st == 5 and "no compiled kernel" in err
+    if rbd.device_count() == 0:
+        assert st == 3, err
+
+
+def test_precompile_writes_every_kernel(rbd, tmp_path):
+    """Run-time compilation without a GPU: one kernel, then every kernel of a new topology into a
+    cache directory; a second call finds them all there and compiles nothing."""
+    import time
+    rbd.precompile_topology([-1, 0], False, str(tmp_path), kernel=7)
+    assert len([f for f in os.listdir(tmp_path) if f.endswith(".hsaco")]) == 1
+    rbd.precompile_topology([-1, 0], False, str(tmp_path))
+    files = sorted(f for f in os.listdir(tmp_path) if f.endswith(".hsaco"))
+    assert len(files) == 27
+    blobs = [open(os.path.join(tmp_path, f), "rb").read() for f in files]
+    t0 = time.time()
+    rbd.precompile_topology([-1, 0], False, str(tmp_path))
+    assert time.time() - t0 < 2.0  # cache hits only
+    assert sorted(f for f in os.listdir(tmp_path) if f.endswith(".hsaco")) == files
+    assert blobs == [open(os.path.join(tmp_path, f), "rb").read() for f in files]
+
+
+def test_precompile_rejects_bad_topologies(rbd, tmp_path):
+    with pytest.raises(rbd.RbdError):
+        rbd.precompile_topology([-1, 0, 0, 1], False, str(tmp_path))  # not depth-first
+    with pytest.raises(rbd.RbdError):
+        rbd.precompile_topology([0], False, str(tmp_path))
+    with pytest.raises(rbd.RbdError):
+        rbd.precompile_topology([-1] * 65, False, str(tmp_path))
+    with pytest.raises(rbd.RbdError):
+        rbd.precompile_topology([-1, 0], False, str(tmp_path), kernel=27)
+
+
+def test_prebuilt_topologies_are_new_and_installed(rbd):
+    """The shapes installed with run-time-compiled kernels are not compiled topologies, and build()
+    put all 27 kernels of each in the library's cache."""
+    from paper_2604_04310_amd.build import CSRC, JIT_DIR, PREBUILT
+    import workloads as W2
+    text = open(os.path.join(CSRC, "rbd_topologies.hpp")).read().replace("\\\n", " ")
+    compiled = {(fr == "true", tuple(int(x) for x in par.split(",")))
+                for fr, par in re.findall(r"X\(\w+, (true|false), ([-0-9, ]+)\)", text)}
+    assert len(compiled) == 11
+    assert not {(fl, tuple(par)) for fl, par in PREBUILT.values()} & compiled
+    assert PREBUILT["tree9"][1] == W2.random_dfs_parents(9, 2)
+    assert PREBUILT["tree20"][1] == W2.random_dfs_parents(20, 4)
+    assert PREBUILT["tree40f"][1] == W2.random_dfs_parents(40, 9)
+    assert PREBUILT["quadruped13f"][1] == W2.QUADRUPED_PARENT
+    assert len([f for f in os.listdir(JIT_DIR) if f.endswith(".hsaco")]) >= 27 * len(PREBUILT)
 
 
 def test_valid_model_without_device(rbd):

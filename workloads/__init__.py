@@ -182,6 +182,26 @@ def random_tree(parent, floating: bool, seed: int, rotated: bool = False, gravit
     return _random_bodies(rng, list(parent), jt, f"tree{len(parent)}{'f' if floating else ''}", rotated, gravity)
 
 
+def random_dfs_parents(n: int, seed: int, p_continue: float = 0.6) -> list:
+    """A random tree of n bodies numbered depth-first: body i hangs on body i-1
+    with probability p_continue, else on a uniformly chosen body of the path
+    from the root to body i-1 (the root itself when the path is short)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    parent = [-1]
+    for i in range(1, n):
+        path = []
+        k = i - 1
+        while k >= 0:
+            path.append(k)
+            k = parent[k]
+        parent.append(i - 1 if rng.random() < p_continue else int(path[rng.integers(len(path))]))
+    return parent
+
+
+# A quadruped: a free trunk and four 3-joint legs.
+QUADRUPED_PARENT = [-1, 0, 1, 2, 0, 4, 5, 0, 7, 8, 0, 10, 11]
+
+
 def tilted_gravity(seed: int) -> np.ndarray:
     """A gravity vector of magnitude 9.81 in a random direction (for models whose world z is not up)."""
     rng = np.random.Generator(np.random.PCG64(seed))
