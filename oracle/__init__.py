@@ -5,10 +5,11 @@ baseline leg use it; the GPU library never imports, links or calls it, and it
 imports nothing of the GPU library.
 
 ``rbd_oracle.cpp`` holds the recursive Featherstone algorithms (paper Sec. II,
-Eq. (1)-(2); the recursive forms of Alg. 1 and Alg. 2), ``paper_vectorized``
-restates Alg. 1 and Alg. 2 literally with the ancestor mask U, and
-``euler_lagrange`` derives M, c and g symbolically from the Lagrangian for
-small chains. Every array here is instance-major float64.
+Eq. (1)-(2); the quantities Alg. 1 and Alg. 2 compute), ``jacobian_form``
+computes M and inverse dynamics a second, independent way (centre-of-mass
+Jacobians in the world frame and Kane's equations), and ``euler_lagrange``
+derives M, c and g symbolically from the Lagrangian for small chains. Every
+array here is instance-major float64.
 """
 from __future__ import annotations
 

@@ -5,8 +5,7 @@
 // table or constant with the GPU library, and the GPU library never calls it.
 //
 // What it computes (paper: Sec. II, Eq. (1) and Eq. (2); Sec. III, Alg. 1 and
-// Alg. 2 define the same quantities in a vectorised form, which the NumPy
-// module paper_vectorized.py restates literally):
+// Alg. 2 define the same quantities in a vectorised form):
 //   * forward kinematics 0T_i(q) of every body frame (Sec. II);
 //   * the world-aligned geometric Jacobian of any body frame (Sec. IV, the
 //     analytical Jacobians the library provides);

@@ -14,7 +14,7 @@ from scipy.spatial.transform import Rotation
 import oracle as O
 import workloads as W
 from oracle import euler_lagrange as EL
-from oracle import paper_vectorized as PV
+from oracle import jacobian_form as JF
 from tests._helpers import base_rotation, com_world, inertia_matrix, rel_err, retract
 
 G = 9.81
@@ -250,17 +250,26 @@ def test_forward_dynamics_round_trip_and_three_methods(name):
     assert rel_err(q_ltl, ref) < 1e-11
 
 
-@pytest.mark.parametrize("name", ["chain7", "humanoid30", "tree12"])
-def test_paper_literal_vectorized_forms_match_recursive(name):
-    """Alg. 1 and Alg. 2 (ancestor mask U, root frame) agree with the recursive oracle."""
+@pytest.mark.parametrize("name", ["chain7", "humanoid30", "tree12", "humanoid30_rot"])
+def test_jacobian_form_matches_recursive(name):
+    """M and tau from body Jacobians and Kane's equations in the world frame (an independent
+    formulation) agree with the recursive body-frame oracle, with rotated joint origins and tilted
+    gravity too."""
     d = {"chain7": W.chain(7), "humanoid30": W.humanoid(),
-         "tree12": W.random_tree([-1, 0, 1, 1, 0, 4, 5, 5, 7, 0, 9, 10], True, 5)}[name]
+         "tree12": W.random_tree([-1, 0, 1, 1, 0, 4, 5, 5, 7, 0, 9, 10], True, 5),
+         "humanoid30_rot": W.humanoid(8, rotated=True, gravity=W.tilted_gravity(9))}[name]
+    # FP32 rounding leaves the origin rotations orthonormal only to ~6e-8; the two formulations
+    # read a non-orthonormal matrix differently (a transpose as the inverse, or not), so both are
+    # given its nearest rotation (polar factor) for an FP64-exact comparison
+    for i in range(d.n_bodies):
+        U_, _, Vt = np.linalg.svd(d.origin[i, :9].reshape(3, 3))
+        d.origin[i, :9] = (U_ @ Vt).reshape(-1)
     st = W.states(d, 32, 7)
     rng = np.random.Generator(np.random.PCG64(3))
     qdd = rng.normal(size=st.qd.shape)
-    assert rel_err(PV.crba(d, st.q), O.crba(d, st.q)) < 1e-12
-    assert rel_err(PV.rnea(d, st.q, st.qd, qdd), O.rnea(d, st.q, st.qd, qdd)) < 1e-12
-    assert rel_err(PV.rnea(d, st.q, st.qd), O.rnea(d, st.q, st.qd)) < 1e-12
+    assert rel_err(JF.mass_matrix(d, st.q), O.crba(d, st.q)) < 1e-12
+    assert rel_err(JF.inverse_dynamics(d, st.q, st.qd, qdd), O.rnea(d, st.q, st.qd, qdd)) < 1e-12
+    assert rel_err(JF.inverse_dynamics(d, st.q, st.qd), O.rnea(d, st.q, st.qd)) < 1e-12
 
 
 # ---------------------------------------------------------------- kinematics
