@@ -69,7 +69,8 @@ typedef enum {
   RBD_E_UNSUPPORTED = 5, /* valid model whose topology has no compiled kernel */
   RBD_E_TIMEOUT = 6,     /* rbd_server_wait: the request did not finish       */
   RBD_E_SHUTDOWN = 7,    /* rbd_server_*: the server is shutting down         */
-  RBD_E_COMPILE = 8      /* run-time compilation of a new topology failed     */
+  RBD_E_COMPILE = 8,     /* run-time compilation of a new topology failed     */
+  RBD_E_CANCELLED = 9    /* rbd_server_*: the request was cancelled           */
 } rbd_status;
 
 typedef enum { RBD_JOINT_REVOLUTE = 0, RBD_JOINT_FREE = 1 } rbd_joint;
@@ -114,7 +115,10 @@ typedef struct rbd_model rbd_model; /* opaque: device-resident tables */
  * subtree that is not a contiguous range, FREE joint not at body 0, unknown
  * joint type, zero axis, R not a rotation, mass <= 0, inertia not positive
  * definite or violating the triangle inequality), RBD_E_NODEVICE,
- * RBD_E_NOMEM. */
+ * RBD_E_NOMEM.
+ * device = -1 creates a host-only model: validated, with its tables on the
+ * host and no kernels; compute calls on it return RBD_E_NODEVICE. It serves a
+ * server with the host executor (scheduling without a GPU, see below). */
 rbd_status rbd_model_create(const rbd_tree_desc* desc, int device, rbd_model** out);
 rbd_status rbd_model_destroy(rbd_model* model);
 rbd_status rbd_model_dims(const rbd_model* model, int* nq, int* nv, int* n_bodies);
@@ -267,19 +271,34 @@ int rbd_device_count(void);       /* number of visible GPUs (0 without one)    *
  *   RBD_OP_FWD_DYN_VJP: in = {q, qd, tau, g_qdd},   out = {g_q, g_qd, g_tau}
  * The buffers, and the model, must stay valid until rbd_server_wait reports
  * completion. The server copies inputs into its device arena, runs the batch
- * and copies the results back. */
+ * and copies the results back. A launch group that fails (a failed copy or
+ * launch, a device error) fails its own requests only (RBD_E_LAUNCH); the
+ * other groups and later requests are unaffected. */
 typedef enum { RBD_OP_FWD_DYN = 0, RBD_OP_RNEA = 1, RBD_OP_FWD_DYN_VJP = 2 } rbd_op;
 
 typedef struct rbd_server rbd_server;
 
+typedef enum {
+  RBD_EXEC_DEVICE = 0, /* the GPU: copies, packed kernels, completion callbacks     */
+  RBD_EXEC_HOST = 1    /* no GPU: the same scheduler over host memory, for testing
+                          admission, packing, completion and failure handling; a
+                          group's "launch" writes, for output a of every instance i,
+                          out_a[i][c] = in_(a mod n_in)[i][c mod rows] + 1000 a
+                          (rows of that input); models must be host-only          */
+} rbd_executor;
+
 typedef struct {
-  int device;            /* GPU id                                                  */
+  int device;            /* GPU id (ignored by the host executor)                   */
   size_t arena_bytes;    /* device memory for staged requests (admission budget)    */
   int n_streams;         /* concurrent launch streams, 1..8                         */
   int max_batch_requests;/* most requests packed into one launch (1..4096)          */
   double max_wait_us;    /* how long a launch may wait to gather more requests      */
   int use_graphs;        /* 1: replay captured HIP graphs, 0: plain launches        */
   int per_request;       /* 1: one launch per request (baseline mode, no packing)   */
+  int executor;          /* rbd_executor                                            */
+  int64_t fail_group;    /* testing: the fail_group-th launch group (counted from 1)
+                            fails before anything of it is launched, as a failed
+                            launch would; 0 = never                                */
 } rbd_server_config;
 
 rbd_status rbd_server_create(const rbd_server_config* cfg, rbd_server** out);
@@ -290,6 +309,11 @@ rbd_status rbd_server_submit(rbd_server* s, const rbd_model* model, int op, int6
 /* Wait until the request finishes (timeout_s < 0: forever). On RBD_OK,
  * *req_status holds the request's own result. A ticket can be waited once. */
 rbd_status rbd_server_wait(rbd_server* s, uint64_t ticket, double timeout_s, rbd_status* req_status);
+/* Cancel a request that is still queued: it completes at once with status
+ * RBD_E_CANCELLED (rbd_server_wait reports it; its outputs are not written).
+ * RBD_E_INVAL if the ticket is unknown or its request already left the queue
+ * (it then completes normally). */
+rbd_status rbd_server_cancel(rbd_server* s, uint64_t ticket);
 /* Latency (submit -> results in host memory) and throughput counters since
  * the last reset. */
 typedef struct {

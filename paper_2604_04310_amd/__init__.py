@@ -7,4 +7,4 @@ from .rbd import (EXPORTS, LIB_PATH, Model, RbdError, aba, crba, desc_struct, de
                   hbm_rate, precompile_topology,
                   fk, fwd_dyn, osc,
                   fwd_dyn_autograd, fwd_dyn_jvp, fwd_dyn_vjp, jacobian, lib, rnea, Server, op_shapes,
-                  OP_FWD_DYN, OP_RNEA, OP_FWD_DYN_VJP)
+                  OP_FWD_DYN, OP_RNEA, OP_FWD_DYN_VJP, EXEC_DEVICE, EXEC_HOST)

@@ -8,6 +8,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <initializer_list>
 #include <vector>
 
 #include "rbd_internal.hpp"
@@ -184,15 +185,37 @@ std::vector<float> make_tables(const rbd_tree_desc* d) {
   return tab;
 }
 
-static rbd_status use_device(int device) {
-  int cur = -1;
-  if (hipGetDevice(&cur) != hipSuccess) return fail(RBD_E_NODEVICE, "no HIP device");
-  if (cur != device && hipSetDevice(device) != hipSuccess) return fail(RBD_E_NODEVICE, "cannot select device %d", device);
-  return RBD_OK;
-}
+
+// Makes the model's device current for one call and restores the caller's
+// current device afterwards (a call never changes it).
+struct DeviceScope {
+  int prev = -1, dev = -1;
+  rbd_status st = RBD_OK;
+  explicit DeviceScope(int device) : dev(device) {  // device < 0: nothing to select
+    if (dev < 0) return;
+    if (hipGetDevice(&prev) != hipSuccess) {
+      prev = -1;
+      st = fail(RBD_E_NODEVICE, "no HIP device");
+    } else if (prev != dev && hipSetDevice(dev) != hipSuccess) {
+      st = fail(RBD_E_NODEVICE, "cannot select device %d", dev);
+    }
+  }
+  ~DeviceScope() {
+    if (prev >= 0 && prev != dev) (void)hipSetDevice(prev);
+  }
+};
+
+// An output [out_rows][ld] that shares an element with one of the inputs.
+struct Arr {
+  const float* p;
+  int64_t rows;
+};
+static bool output_overlaps(const float* out, int64_t out_rows, std::initializer_list<Arr> ins, int64_t ld,
+                            int64_t batch);
 
 static rbd_status check_batch(const rbd_model* m, int64_t batch, int64_t ld, const char* what) {
   if (!m) return fail(RBD_E_INVAL, "%s: model is NULL", what);
+  if (m->device < 0) return fail(RBD_E_NODEVICE, "%s: the model is host-only (created with device -1)", what);
   if (batch < 0) return fail(RBD_E_INVAL, "%s: batch = %lld < 0", what, (long long)batch);
   if (batch > (int64_t(1) << 30))
     return fail(RBD_E_INVAL, "%s: batch = %lld exceeds 2^30 instances per call", what, (long long)batch);
@@ -214,6 +237,13 @@ static bool soa_overlap(const float* a, int64_t ra, const float* b, int64_t rb, 
   return (rows_q && r < batch) || (rows_q1 && ld - r < batch);
 }
 
+static bool output_overlaps(const float* out, int64_t out_rows, std::initializer_list<Arr> ins, int64_t ld,
+                            int64_t batch) {
+  for (const Arr& a : ins)
+    if (soa_overlap(out, out_rows, a.p, a.rows, ld, batch)) return true;
+  return false;
+}
+
 }  // namespace rbd
 
 using namespace rbd;
@@ -231,6 +261,7 @@ const char* rbd_status_str(rbd_status s) {
     case RBD_E_TIMEOUT: return "timed out";
     case RBD_E_SHUTDOWN: return "shutting down";
     case RBD_E_COMPILE: return "run-time compilation failed";
+    case RBD_E_CANCELLED: return "cancelled";
   }
   return "unknown status";
 }
@@ -251,11 +282,18 @@ rbd_status rbd_model_create(const rbd_tree_desc* desc, int device, rbd_model** o
   const int n = desc->n_bodies;
   const bool floating = desc->joint_type[0] == RBD_JOINT_FREE;
   const int topo = find_topology(floating, n, desc->parent);
-  const int ndev = rbd_device_count();
-  if (device < 0 || device >= ndev) return fail(RBD_E_NODEVICE, "device %d is not available (%d visible)", device, ndev);
-  if ((st = use_device(device)) != RBD_OK) return st;
-  const KernelSet* ks = topo >= 0 ? aot_kernels(topo) : nullptr;
-  if (!ks && (st = jit_kernels(floating, n, desc->parent, device, &ks)) != RBD_OK) return st;
+  const bool host_only = device == -1;
+  const KernelSet* ks = nullptr;
+  if (!host_only) {
+    const int ndev = rbd_device_count();
+    if (device < 0 || device >= ndev) return fail(RBD_E_NODEVICE, "device %d is not available (%d visible)", device, ndev);
+  }
+  DeviceScope ds(host_only ? -1 : device);
+  if (ds.st != RBD_OK) return ds.st;
+  if (!host_only) {
+    ks = topo >= 0 ? aot_kernels(topo) : nullptr;
+    if (!ks && (st = jit_kernels(floating, n, desc->parent, device, &ks)) != RBD_OK) return st;
+  }
   std::vector<float> tab = make_tables(desc);
   rbd_model* m = new (std::nothrow) rbd_model;
   if (!m) return fail(RBD_E_NOMEM, "host allocation failed");
@@ -269,6 +307,11 @@ rbd_status rbd_model_create(const rbd_tree_desc* desc, int device, rbd_model** o
   m->nq = n + (floating ? 6 : 0);
   m->nv = n + (floating ? 5 : 0);
   m->tab_floats = tab.size();
+  if (host_only) {  // tables kept on the host, no kernels
+    m->h_tab = std::move(tab);
+    *out = m;
+    return RBD_OK;
+  }
   if (hipMalloc(&m->d_tab, tab.size() * sizeof(float)) != hipSuccess) {
     delete m;
     return fail(RBD_E_NOMEM, "device allocation of %zu bytes failed", tab.size() * sizeof(float));
@@ -285,7 +328,7 @@ rbd_status rbd_model_create(const rbd_tree_desc* desc, int device, rbd_model** o
 rbd_status rbd_model_destroy(rbd_model* m) {
   if (!m) return RBD_OK;
   if (m->d_tab) {
-    (void)use_device(m->device);
+    DeviceScope ds(m->device);
     (void)hipFree(m->d_tab);
   }
   delete m;
@@ -301,8 +344,9 @@ rbd_status rbd_model_dims(const rbd_model* m, int* nq, int* nv, int* n_bodies) {
 }
 
 const char* rbd_model_topology(const rbd_model* m) {
-  if (!m || !m->ks) return "";
-  return m->ks->name;
+  if (!m) return "";
+  if (m->ks) return m->ks->name;
+  return m->topo >= 0 ? topology(m->topo).name : "host-only";
 }
 
 rbd_status rbd_precompile_topology(int32_t n_bodies, const int32_t* parent, int floating, const char* cache_dir,
@@ -321,7 +365,10 @@ rbd_status rbd_fk(const rbd_model* m, int64_t batch, int64_t ld, const float* q,
   rbd_status st = check_batch(m, batch, ld, "rbd_fk");
   if (st != RBD_OK) return st;
   if (batch > 0 && (!q || !T)) return fail(RBD_E_INVAL, "rbd_fk: NULL array");
-  if ((st = use_device(m->device)) != RBD_OK) return st;
+  if (output_overlaps(T, 12 * (int64_t)m->n, {{q, m->nq}}, ld, batch))
+    return fail(RBD_E_INVAL, "rbd_fk: the output overlaps an input");
+  DeviceScope ds(m->device);
+  if (ds.st != RBD_OK) return ds.st;
   return launch_fk(m, batch, ld, q, T, s);
 }
 
@@ -335,7 +382,10 @@ rbd_status rbd_jacobian(const rbd_model* m, int64_t batch, int64_t ld, const flo
     if (frames[f] < 0 || frames[f] >= m->n)
       return fail(RBD_E_INVAL, "rbd_jacobian: frames[%d] = %d is not a body id (0..%d)", f, frames[f], m->n - 1);
   if (batch > 0 && (!q || !J)) return fail(RBD_E_INVAL, "rbd_jacobian: NULL array");
-  if ((st = use_device(m->device)) != RBD_OK) return st;
+  if (output_overlaps(J, (int64_t)n_frames * 6 * m->nv, {{q, m->nq}}, ld, batch))
+    return fail(RBD_E_INVAL, "rbd_jacobian: the output overlaps an input");
+  DeviceScope ds(m->device);
+  if (ds.st != RBD_OK) return ds.st;
   return launch_jacobian(m, batch, ld, q, n_frames, frames, J, s);
 }
 
@@ -344,7 +394,10 @@ rbd_status rbd_rnea(const rbd_model* m, int64_t batch, int64_t ld, const float* 
   rbd_status st = check_batch(m, batch, ld, "rbd_rnea");
   if (st != RBD_OK) return st;
   if (batch > 0 && (!q || !qd || !tau)) return fail(RBD_E_INVAL, "rbd_rnea: NULL array");
-  if ((st = use_device(m->device)) != RBD_OK) return st;
+  if (output_overlaps(tau, m->nv, {{q, m->nq}, {qd, m->nv}, {qdd, m->nv}, {f_ext, 6 * (int64_t)m->n}}, ld, batch))
+    return fail(RBD_E_INVAL, "rbd_rnea: the output overlaps an input");
+  DeviceScope ds(m->device);
+  if (ds.st != RBD_OK) return ds.st;
   return launch_rnea(m, batch, ld, q, qd, qdd, f_ext, tau, s);
 }
 
@@ -352,7 +405,10 @@ rbd_status rbd_crba(const rbd_model* m, int64_t batch, int64_t ld, const float* 
   rbd_status st = check_batch(m, batch, ld, "rbd_crba");
   if (st != RBD_OK) return st;
   if (batch > 0 && (!q || !M)) return fail(RBD_E_INVAL, "rbd_crba: NULL array");
-  if ((st = use_device(m->device)) != RBD_OK) return st;
+  if (output_overlaps(M, (int64_t)m->nv * m->nv, {{q, m->nq}}, ld, batch))
+    return fail(RBD_E_INVAL, "rbd_crba: the output overlaps an input");
+  DeviceScope ds(m->device);
+  if (ds.st != RBD_OK) return ds.st;
   return launch_crba(m, batch, ld, q, M, s);
 }
 
@@ -361,7 +417,10 @@ rbd_status rbd_fwd_dyn(const rbd_model* m, int64_t batch, int64_t ld, const floa
   rbd_status st = check_batch(m, batch, ld, "rbd_fwd_dyn");
   if (st != RBD_OK) return st;
   if (batch > 0 && (!q || !qd || !tau || !qdd)) return fail(RBD_E_INVAL, "rbd_fwd_dyn: NULL array");
-  if ((st = use_device(m->device)) != RBD_OK) return st;
+  if (output_overlaps(qdd, m->nv, {{q, m->nq}, {qd, m->nv}, {tau, m->nv}, {f_ext, 6 * (int64_t)m->n}}, ld, batch))
+    return fail(RBD_E_INVAL, "rbd_fwd_dyn: the output overlaps an input");
+  DeviceScope ds(m->device);
+  if (ds.st != RBD_OK) return ds.st;
   return launch_fwd_dyn(m, batch, ld, q, qd, tau, f_ext, qdd, s);
 }
 
@@ -370,7 +429,10 @@ rbd_status rbd_aba(const rbd_model* m, int64_t batch, int64_t ld, const float* q
   rbd_status st = check_batch(m, batch, ld, "rbd_aba");
   if (st != RBD_OK) return st;
   if (batch > 0 && (!q || !qd || !tau || !qdd)) return fail(RBD_E_INVAL, "rbd_aba: NULL array");
-  if ((st = use_device(m->device)) != RBD_OK) return st;
+  if (output_overlaps(qdd, m->nv, {{q, m->nq}, {qd, m->nv}, {tau, m->nv}, {f_ext, 6 * (int64_t)m->n}}, ld, batch))
+    return fail(RBD_E_INVAL, "rbd_aba: the output overlaps an input");
+  DeviceScope ds(m->device);
+  if (ds.st != RBD_OK) return ds.st;
   return launch_aba(m, batch, ld, q, qd, tau, f_ext, qdd, s);
 }
 
@@ -384,7 +446,12 @@ rbd_status rbd_fwd_dyn_jvp(const rbd_model* m, int64_t batch, int64_t ld, const 
   // qdd is parked in one of the outputs between sweeps
   if (soa_overlap(qdd, m->nv, dqdd, m->nv, ld, batch))
     return fail(RBD_E_INVAL, "rbd_fwd_dyn_jvp: qdd and dqdd overlap");
-  if ((st = use_device(m->device)) != RBD_OK) return st;
+  for (const float* o : {static_cast<const float*>(qdd), static_cast<const float*>(dqdd)})
+    if (output_overlaps(o, m->nv, {{q, m->nq}, {qd, m->nv}, {tau, m->nv}, {dq, m->nq}, {dqd, m->nv}, {dtau, m->nv}},
+                        ld, batch))
+      return fail(RBD_E_INVAL, "rbd_fwd_dyn_jvp: an output overlaps an input");
+  DeviceScope ds(m->device);
+  if (ds.st != RBD_OK) return ds.st;
   return launch_fwd_dyn_jvp(m, batch, ld, q, qd, tau, dq, dqd, dtau, qdd, dqdd, s);
 }
 
@@ -406,7 +473,10 @@ rbd_status rbd_diff_ik(const rbd_model* m, int64_t batch, int64_t ld, const floa
   if (!std::isfinite(gain) || !std::isfinite(damping) || damping < 0.0f)
     return fail(RBD_E_INVAL, "rbd_diff_ik: gain must be finite and damping finite and >= 0");
   if (batch > 0 && (!q || !target || !qd)) return fail(RBD_E_INVAL, "rbd_diff_ik: NULL array");
-  if ((st = use_device(m->device)) != RBD_OK) return st;
+  if (output_overlaps(qd, m->nv, {{q, m->nq}, {target, 12}}, ld, batch))
+    return fail(RBD_E_INVAL, "rbd_diff_ik: the output overlaps an input");
+  DeviceScope ds(m->device);
+  if (ds.st != RBD_OK) return ds.st;
   return launch_diff_ik(m, batch, ld, q, target, gain, damping * damping, qd, s);
 }
 
@@ -418,7 +488,10 @@ rbd_status rbd_osc(const rbd_model* m, int64_t batch, int64_t ld, const float* q
   if (!std::isfinite(kp) || !std::isfinite(kd) || !std::isfinite(k_null))
     return fail(RBD_E_INVAL, "rbd_osc: gains must be finite");
   if (batch > 0 && (!q || !qd || !target || !tau)) return fail(RBD_E_INVAL, "rbd_osc: NULL array");
-  if ((st = use_device(m->device)) != RBD_OK) return st;
+  if (output_overlaps(tau, m->nv, {{q, m->nq}, {qd, m->nv}, {target, 12}}, ld, batch))
+    return fail(RBD_E_INVAL, "rbd_osc: the output overlaps an input");
+  DeviceScope ds(m->device);
+  if (ds.st != RBD_OK) return ds.st;
   return launch_osc(m, batch, ld, q, qd, target, kp, kd, k_null, tau, s);
 }
 
@@ -432,7 +505,11 @@ rbd_status rbd_fwd_dyn_vjp(const rbd_model* m, int64_t batch, int64_t ld, const 
   if (soa_overlap(g_q, m->nq, g_qd, m->nv, ld, batch) || soa_overlap(g_q, m->nq, g_tau, m->nv, ld, batch) ||
       soa_overlap(g_qd, m->nv, g_tau, m->nv, ld, batch))
     return fail(RBD_E_INVAL, "rbd_fwd_dyn_vjp: output arrays overlap");
-  if ((st = use_device(m->device)) != RBD_OK) return st;
+  for (const Arr& o : {Arr{g_q, m->nq}, Arr{g_qd, m->nv}, Arr{g_tau, m->nv}})
+    if (output_overlaps(o.p, o.rows, {{q, m->nq}, {qd, m->nv}, {tau, m->nv}, {g_qdd, m->nv}}, ld, batch))
+      return fail(RBD_E_INVAL, "rbd_fwd_dyn_vjp: an output overlaps an input");
+  DeviceScope ds(m->device);
+  if (ds.st != RBD_OK) return ds.st;
   return launch_fwd_dyn_vjp(m, batch, ld, q, qd, tau, g_qdd, g_q, g_qd, g_tau, s);
 }
 

@@ -34,6 +34,7 @@ struct rbd_model {
   int n = 0, nq = 0, nv = 0;
   bool floating = false;
   float* d_tab = nullptr;      // device tables (see rbd_lane.hpp)
+  std::vector<float> h_tab;    // the tables of a host-only model (device -1)
   size_t tab_floats = 0;
   uint64_t uid = 0;            // unique over the process (a new model never reuses one)
 };

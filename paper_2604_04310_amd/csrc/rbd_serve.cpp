@@ -12,9 +12,14 @@
 // (slot, class, grid size) replays it for any group. Up to n_streams groups
 // are in flight on their own streams, so requests that arrive while others run
 // are admitted as memory and slots free up, and their work overlaps on the GPU.
-// A completion thread polls the groups' events, copies the results into the
-// clients' buffers, frees the arena block and records each request's latency
-// (submit to results in host memory).
+// When a group's copy-back has run, a host callback enqueued behind it on the
+// stream hands the group to a completion thread (which sleeps until then),
+// which copies the results into the clients' buffers, frees the arena block and
+// records each request's latency (submit to results in host memory). A group
+// that fails fails only its own requests. The host executor runs the same
+// scheduler over host memory with a fixed stand-in computation, so admission,
+// packing, completion, cancellation and failure handling can be tested
+// without a GPU.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -120,6 +125,7 @@ class Arena {
 };
 
 struct Group {
+  rbd_server* srv = nullptr;
   int slot = -1;
   const rbd_model* model = nullptr;
   int op = 0;
@@ -152,7 +158,8 @@ using namespace rbd;
 
 struct rbd_server {
   rbd_server_config cfg{};
-  uint8_t* d_arena = nullptr;
+  bool host_exec = false;      // RBD_EXEC_HOST: arena and staging in host memory
+  uint8_t* d_arena = nullptr;  // device arena (host memory for the host executor)
   uint8_t* h_stage = nullptr;
   Arena arena;
   std::vector<Slot> slots;
@@ -161,7 +168,9 @@ struct rbd_server {
   std::deque<std::shared_ptr<Request>> pending;
   std::unordered_map<uint64_t, std::shared_ptr<Request>> tickets;
   std::vector<Group*> inflight;
+  std::deque<Group*> completed;  // groups in flight whose work has finished
   uint64_t next_ticket = 1;
+  int64_t n_groups = 0;          // launch groups formed so far
   bool stop = false, dispatcher_done = false;
   std::thread dispatcher, completer;
   // statistics
@@ -248,8 +257,42 @@ rbd_status capture_packed(const rbd_model* m, int op, const void* d_table, int g
   return RBD_OK;
 }
 
+// Host executor: the documented stand-in computation, straight from the
+// clients' inputs into the group's output block (host memory).
+void host_launch(rbd_server* s, Group* g) {
+  uint8_t* hb = s->h_stage + g->off;
+  size_t opos = g->out_off;
+  for (auto& rp : g->reqs) {
+    const Request& r = *rp;
+    int in_rows[4], out_rows[3], n_in, n_out;
+    shape_of(r.model, r.op, &n_in, in_rows, &n_out, out_rows);
+    for (int a = 0; a < r.n_out; ++a) {
+      float* o = reinterpret_cast<float*>(hb + opos);
+      const int src = a % r.n_in, rows = in_rows[src];
+      for (int64_t i = 0; i < r.batch; ++i)
+        for (int c = 0; c < out_rows[a]; ++c)
+          o[i * out_rows[a] + c] = r.in[src][i * rows + c % rows] + 1000.0f * (float)a;
+      opos += r.out_n[a] * sizeof(float);
+    }
+  }
+}
+
+// The stream reached the end of a group's work: hand it to the completion
+// thread (runs on the runtime's callback thread; no HIP calls here).
+void on_group_done(void* arg) {
+  Group* g = static_cast<Group*>(arg);
+  rbd_server* s = g->srv;
+  std::lock_guard<std::mutex> lk(s->mu);
+  s->completed.push_back(g);
+  s->cv_inflight.notify_all();
+}
+
 // Stage, launch and queue the copy-back of one group (dispatcher thread, no lock).
 rbd_status launch_group(rbd_server* s, Group* g) {
+  if (s->host_exec) {
+    host_launch(s, g);
+    return RBD_OK;
+  }
   Slot& sl = s->slots[g->slot];
   uint8_t* hb = s->h_stage + g->off;
   uint8_t* db = s->d_arena + g->off;
@@ -322,8 +365,6 @@ rbd_status launch_group(rbd_server* s, Group* g) {
   return RBD_OK;
 }
 
-// Delivers a group's results (or its failure) to its requests and frees its
-// block and slot; `inflight` says whether the group is in the in-flight list.
 void finish_group(rbd_server* s, Group* g, const Clock::time_point now, bool inflight = true) {
   // results -> client buffers (instance-major, as requested)
   if (g->status == RBD_OK) {
@@ -355,10 +396,11 @@ void finish_group(rbd_server* s, Group* g, const Clock::time_point now, bool inf
   delete g;
   s->cv_done.notify_all();
   s->cv_work.notify_all();
+  s->cv_inflight.notify_all();
 }
 
 void dispatcher_main(rbd_server* s) {
-  (void)hipSetDevice(s->cfg.device);
+  if (!s->host_exec) (void)hipSetDevice(s->cfg.device);
   std::unique_lock<std::mutex> lk(s->mu);
   for (;;) {
     if (s->pending.empty()) {
@@ -385,23 +427,43 @@ void dispatcher_main(rbd_server* s) {
       continue;
     }
     g->slot = free_slot(s);
+    g->srv = s;
     s->slots[g->slot].busy = true;
+    const bool injected = s->cfg.fail_group > 0 && ++s->n_groups == s->cfg.fail_group;
     lk.unlock();
-    g->status = launch_group(s, g);
+    g->status = injected ? fail(RBD_E_LAUNCH, "server: injected failure of launch group %lld",
+                                (long long)s->cfg.fail_group)
+                         : launch_group(s, g);
     if (g->status != RBD_OK) {
       // A failed group never reaches the completion thread (which reads the
       // groups in flight without the lock): copies queued before the failure
       // may still run, so drain them, then fail this group's requests only
       // and return its block to the arena.
-      (void)hipStreamSynchronize(s->slots[g->slot].stream);
+      if (!s->host_exec) (void)hipStreamSynchronize(s->slots[g->slot].stream);
       finish_group(s, g, Clock::now(), false);
       lk.lock();
       continue;
     }
+    const hipStream_t st = s->host_exec ? nullptr : s->slots[g->slot].stream;
     lk.lock();
     if (s->inflight.empty()) s->busy_since = Clock::now();
     s->inflight.push_back(g);
-    s->cv_inflight.notify_all();
+    if (s->host_exec) {  // its work is done already
+      s->completed.push_back(g);
+      s->cv_inflight.notify_all();
+      continue;
+    }
+    lk.unlock();
+    // the completion thread learns of the group from a host callback queued
+    // behind its work (g may be finished and freed as soon as it is queued)
+    if (hipLaunchHostFunc(st, on_group_done, g) != hipSuccess) {
+      (void)hipStreamSynchronize(st);  // no callback will come: wait here instead
+      lk.lock();
+      s->completed.push_back(g);
+      s->cv_inflight.notify_all();
+      continue;
+    }
+    lk.lock();
   }
   s->dispatcher_done = true;
   s->cv_work.notify_all();
@@ -409,25 +471,22 @@ void dispatcher_main(rbd_server* s) {
 }
 
 void completer_main(rbd_server* s) {
-  (void)hipSetDevice(s->cfg.device);
+  if (!s->host_exec) (void)hipSetDevice(s->cfg.device);
   std::unique_lock<std::mutex> lk(s->mu);
   for (;;) {
-    if (s->inflight.empty()) {
-      if (s->dispatcher_done) break;
+    if (s->completed.empty()) {
+      if (s->inflight.empty() && s->dispatcher_done) break;
       s->cv_inflight.wait(lk);
       continue;
     }
-    std::vector<Group*> look(s->inflight.begin(), s->inflight.end());
+    Group* g = s->completed.front();
+    s->completed.pop_front();
     lk.unlock();
-    bool any = false;
-    for (Group* g : look) {  // only this thread finishes (and frees) groups in flight
-      const hipError_t e = hipEventQuery(s->slots[g->slot].done);
-      if (e == hipErrorNotReady) continue;
-      if (e != hipSuccess) g->status = fail(RBD_E_LAUNCH, "server: launch failed on the device");
-      finish_group(s, g, Clock::now());
-      any = true;
-    }
-    if (!any) std::this_thread::yield();
+    // the callback runs once the stream got there; an error of the group's
+    // work shows in its event
+    if (!s->host_exec && hipEventQuery(s->slots[g->slot].done) != hipSuccess)
+      g->status = fail(RBD_E_LAUNCH, "server: launch failed on the device");
+    finish_group(s, g, Clock::now());
     lk.lock();
   }
 }
@@ -446,22 +505,35 @@ rbd_status rbd_server_create(const rbd_server_config* cfg, rbd_server** out) {
     return fail(RBD_E_INVAL, "max_batch_requests = %d, expected 1..%d", cfg->max_batch_requests, kMaxPacked);
   if (cfg->arena_bytes < (1u << 16)) return fail(RBD_E_INVAL, "arena_bytes must be at least 64 KiB");
   if (!(cfg->max_wait_us >= 0.0)) return fail(RBD_E_INVAL, "max_wait_us must be >= 0");
-  const int ndev = rbd_device_count();
-  if (cfg->device < 0 || cfg->device >= ndev) return fail(RBD_E_NODEVICE, "device %d is not available", cfg->device);
-  if (hipSetDevice(cfg->device) != hipSuccess) return fail(RBD_E_NODEVICE, "cannot select device %d", cfg->device);
+  if (cfg->executor != RBD_EXEC_DEVICE && cfg->executor != RBD_EXEC_HOST)
+    return fail(RBD_E_INVAL, "executor = %d is unknown", cfg->executor);
+  if (cfg->fail_group < 0) return fail(RBD_E_INVAL, "fail_group must be >= 0");
+  const bool host = cfg->executor == RBD_EXEC_HOST;
+  if (!host) {
+    const int ndev = rbd_device_count();
+    if (cfg->device < 0 || cfg->device >= ndev) return fail(RBD_E_NODEVICE, "device %d is not available", cfg->device);
+    if (hipSetDevice(cfg->device) != hipSuccess) return fail(RBD_E_NODEVICE, "cannot select device %d", cfg->device);
+  }
   auto* s = new (std::nothrow) rbd_server;
   if (!s) return fail(RBD_E_NOMEM, "host allocation failed");
   s->cfg = *cfg;
+  s->host_exec = host;
   s->arena.init(cfg->arena_bytes);
-  bool ok = hipMalloc(&s->d_arena, cfg->arena_bytes) == hipSuccess &&
-            hipHostMalloc(&s->h_stage, cfg->arena_bytes, hipHostMallocDefault) == hipSuccess;
   s->slots.resize(cfg->n_streams);
-  const size_t tcap = table_capacity(cfg->max_batch_requests);
-  for (auto& sl : s->slots) {
-    ok = ok && hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) == hipSuccess &&
-         hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) == hipSuccess &&
-         hipMalloc(&sl.d_table, tcap) == hipSuccess &&
-         hipHostMalloc(&sl.h_table, tcap, hipHostMallocDefault) == hipSuccess;
+  bool ok = true;
+  if (host) {
+    s->h_stage = new (std::nothrow) uint8_t[cfg->arena_bytes];
+    ok = s->h_stage != nullptr;
+  } else {
+    ok = hipMalloc(&s->d_arena, cfg->arena_bytes) == hipSuccess &&
+         hipHostMalloc(&s->h_stage, cfg->arena_bytes, hipHostMallocDefault) == hipSuccess;
+    const size_t tcap = table_capacity(cfg->max_batch_requests);
+    for (auto& sl : s->slots) {
+      ok = ok && hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) == hipSuccess &&
+           hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) == hipSuccess &&
+           hipMalloc(&sl.d_table, tcap) == hipSuccess &&
+           hipHostMalloc(&sl.h_table, tcap, hipHostMallocDefault) == hipSuccess;
+    }
   }
   if (!ok) {
     rbd_server_destroy(s);
@@ -479,7 +551,9 @@ rbd_status rbd_server_submit(rbd_server* s, const rbd_model* m, int op, int64_t 
   if (op < RBD_OP_FWD_DYN || op > RBD_OP_FWD_DYN_VJP) return fail(RBD_E_INVAL, "rbd_server_submit: unknown op %d", op);
   if (batch < 1 || batch > (int64_t)kMaxTilesPerGroup * kTileLanes)
     return fail(RBD_E_INVAL, "rbd_server_submit: batch = %lld out of range", (long long)batch);
-  if (m->device != s->cfg.device) return fail(RBD_E_INVAL, "rbd_server_submit: model lives on another device");
+  if (s->host_exec ? m->device != -1 : m->device != s->cfg.device)
+    return fail(RBD_E_INVAL, s->host_exec ? "rbd_server_submit: the host executor serves host-only models"
+                                          : "rbd_server_submit: model lives on another device");
   auto r = std::make_shared<Request>();
   int in_rows[4], out_rows[3];
   shape_of(m, op, &r->n_in, in_rows, &r->n_out, out_rows);
@@ -525,6 +599,22 @@ rbd_status rbd_server_wait(rbd_server* s, uint64_t ticket, double timeout_s, rbd
   }
   if (req_status) *req_status = r->status;
   s->tickets.erase(ticket);
+  return RBD_OK;
+}
+
+rbd_status rbd_server_cancel(rbd_server* s, uint64_t ticket) {
+  if (!s) return fail(RBD_E_INVAL, "rbd_server_cancel: server is NULL");
+  std::lock_guard<std::mutex> lk(s->mu);
+  auto it = s->tickets.find(ticket);
+  if (it == s->tickets.end()) return fail(RBD_E_INVAL, "rbd_server_cancel: unknown ticket %llu", (unsigned long long)ticket);
+  auto pos = std::find(s->pending.begin(), s->pending.end(), it->second);
+  if (pos == s->pending.end())
+    return fail(RBD_E_INVAL, "rbd_server_cancel: ticket %llu already left the queue", (unsigned long long)ticket);
+  s->pending.erase(pos);
+  it->second->status = RBD_E_CANCELLED;
+  it->second->done = true;
+  s->cv_done.notify_all();
+  s->cv_work.notify_all();
   return RBD_OK;
 }
 
@@ -578,6 +668,11 @@ rbd_status rbd_server_destroy(rbd_server* s) {
     s->cv_inflight.notify_all();
   }
   if (s->completer.joinable()) s->completer.join();
+  if (s->host_exec) {
+    delete[] s->h_stage;
+    delete s;
+    return RBD_OK;
+  }
   (void)hipSetDevice(s->cfg.device);
   for (auto& sl : s->slots) {
     for (auto& kv : sl.graphs) (void)hipGraphExecDestroy(kv.second);

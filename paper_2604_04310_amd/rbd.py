@@ -23,13 +23,14 @@ LIB_PATH = os.path.join(PKG, "librbd.so")
 
 RBD_OK = 0
 STATUS = {0: "RBD_OK", 1: "RBD_E_INVAL", 2: "RBD_E_NOMEM", 3: "RBD_E_NODEVICE", 4: "RBD_E_LAUNCH",
-          5: "RBD_E_UNSUPPORTED", 6: "RBD_E_TIMEOUT", 7: "RBD_E_SHUTDOWN", 8: "RBD_E_COMPILE"}
+          5: "RBD_E_UNSUPPORTED", 6: "RBD_E_TIMEOUT", 7: "RBD_E_SHUTDOWN", 8: "RBD_E_COMPILE",
+          9: "RBD_E_CANCELLED"}
 OP_FWD_DYN, OP_RNEA, OP_FWD_DYN_VJP = 0, 1, 2
 
 # Every symbol include/rbd.h declares.
 EXPORTS = ["rbd_model_create", "rbd_model_destroy", "rbd_model_dims", "rbd_model_topology", "rbd_fk",
            "rbd_jacobian", "rbd_rnea", "rbd_crba", "rbd_fwd_dyn", "rbd_aba", "rbd_fwd_dyn_jvp", "rbd_fwd_dyn_vjp", "rbd_diff_ik", "rbd_osc", "rbd_status_str",
-           "rbd_last_error", "rbd_device_count", "rbd_diag_fma_rate", "rbd_diag_hbm_rate", "rbd_precompile_topology", "rbd_server_create", "rbd_server_submit", "rbd_server_wait",
+           "rbd_last_error", "rbd_device_count", "rbd_diag_fma_rate", "rbd_diag_hbm_rate", "rbd_precompile_topology", "rbd_server_create", "rbd_server_submit", "rbd_server_wait", "rbd_server_cancel",
            "rbd_server_get_stats", "rbd_server_reset_stats", "rbd_server_destroy"]
 
 
@@ -56,7 +57,10 @@ class TreeDescC(C.Structure):
 class ServerConfigC(C.Structure):
     _fields_ = [("device", C.c_int), ("arena_bytes", C.c_size_t), ("n_streams", C.c_int),
                 ("max_batch_requests", C.c_int), ("max_wait_us", C.c_double), ("use_graphs", C.c_int),
-                ("per_request", C.c_int)]
+                ("per_request", C.c_int), ("executor", C.c_int), ("fail_group", C.c_int64)]
+
+
+EXEC_DEVICE, EXEC_HOST = 0, 1
 
 
 class ServerStatsC(C.Structure):
@@ -103,6 +107,7 @@ def lib():
         L.rbd_server_create.argtypes = [P(ServerConfigC), P(vp)]
         L.rbd_server_submit.argtypes = [vp, vp, C.c_int, i64, P(vp), P(vp), P(C.c_uint64)]
         L.rbd_server_wait.argtypes = [vp, C.c_uint64, C.c_double, P(C.c_int)]
+        L.rbd_server_cancel.argtypes = [vp, C.c_uint64]
         L.rbd_server_get_stats.argtypes = [vp, P(ServerStatsC)]
         L.rbd_server_reset_stats.argtypes = [vp]
         L.rbd_server_destroy.argtypes = [vp]
@@ -169,7 +174,8 @@ def desc_struct(desc) -> TreeDescC:
 
 
 class Model:
-    """A kinematic tree resident on one GPU (owns the device tables)."""
+    """A kinematic tree resident on one GPU (owns the device tables); device=-1 makes a host-only
+    model (no kernels) for a server with the host executor."""
 
     def __init__(self, desc, device: int = 0):
         self._h = C.c_void_p()
@@ -440,9 +446,10 @@ class Server:
 
     def __init__(self, device: int = 0, arena_bytes: int = 256 << 20, n_streams: int = 4,
                  max_batch_requests: int = 1024, max_wait_us: float = 0.0, use_graphs: bool = True,
-                 per_request: bool = False):
+                 per_request: bool = False, executor: int = EXEC_DEVICE, fail_group: int = 0):
         cfg = ServerConfigC(int(device), int(arena_bytes), int(n_streams), int(max_batch_requests),
-                            float(max_wait_us), int(bool(use_graphs)), int(bool(per_request)))
+                            float(max_wait_us), int(bool(use_graphs)), int(bool(per_request)), int(executor),
+                            int(fail_group))
         self._h = C.c_void_p()
         check(lib().rbd_server_create(C.byref(cfg), C.byref(self._h)))
         self._live = {}
@@ -472,6 +479,10 @@ class Server:
         check(lib().rbd_server_wait(self._h, C.c_uint64(ticket), float(timeout), C.byref(st)))
         self._live.pop(ticket, None)
         return st.value
+
+    def cancel(self, ticket: int) -> None:
+        """Cancel a request still in the queue (it then completes with RBD_E_CANCELLED)."""
+        check(lib().rbd_server_cancel(self._h, C.c_uint64(ticket)))
 
     def stats(self) -> dict:
         s = ServerStatsC()

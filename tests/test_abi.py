@@ -159,11 +159,12 @@ def test_null_model_calls(rbd):
 
 def _server_create(rbd, **kw):
     cfg = dict(device=0, arena_bytes=1 << 24, n_streams=2, max_batch_requests=64, max_wait_us=0.0,
-               use_graphs=1, per_request=0)
+               use_graphs=1, per_request=0, executor=0, fail_group=0)
     cfg.update(kw)
     from paper_2604_04310_amd import rbd as R
     c = R.ServerConfigC(cfg["device"], cfg["arena_bytes"], cfg["n_streams"], cfg["max_batch_requests"],
-                              cfg["max_wait_us"], cfg["use_graphs"], cfg["per_request"])
+                        cfg["max_wait_us"], cfg["use_graphs"], cfg["per_request"], cfg["executor"],
+                        cfg["fail_group"])
     h = C.c_void_p()
     st = rbd.lib().rbd_server_create(C.byref(c), C.byref(h))
     if st == 0:
