@@ -192,6 +192,112 @@ def kernel_rooflines(O, W, desc, chain, ops, cnt, hbm):
     }
 
 
+# ---------------------------------------------------------------- profile summaries
+def _topology_names():
+    """Tree<...> template arguments -> compiled topology name."""
+    import re
+    text = open(os.path.join(CSRC, "rbd_topologies.hpp")).read().replace("\\\n", " ")
+    return {re.sub(r"\s+", " ", f"{fr}, {par.strip()}"): name
+            for name, fr, par in re.findall(r"X\((\w+), (true|false), ([-0-9, \s]+)\)", text)}
+
+
+def _short_kernel(name, topo):
+    """'void rbd::k_fwd_dyn<rbd::Tree<true, -1, ...>, true, false>(...)' -> 'k_fwd_dyn<humanoid30, true, false>'."""
+    import re
+    name = name.replace("(anonymous namespace)::", "").split("(")[0].replace("void ", "").replace("rbd::", "")
+    m = re.search(r"Tree<([^>]*)>", name)
+    if m:
+        name = name.replace(m.group(0), topo.get(re.sub(r"\s+", " ", m.group(1).strip()), "tree"))
+    return name
+
+
+def _kernel_key(short):
+    """The bench's key of a kernel at its benchmark shape (None for kernels the bench does not rate)."""
+    base, _, rest = short.partition("<")
+    topo = rest.split(",")[0].rstrip(">").strip()
+    key = {"k_fwd_dyn": "fwd_dyn", "k_rnea": "rnea_bias", "k_aba": "aba", "k_crba": "crba", "k_fk": "fk",
+           "k_jacobian": "jacobian", "k_osc": "osc", "k_diff_ik": "diff_ik", "k_fwd_dyn_vjp": "fwd_dyn_vjp",
+           "k_fwd_dyn_jvp": "fwd_dyn_jvp"}.get(base)
+    return f"{key}_{topo}" if key and topo in ("humanoid30", "chain7") else None
+
+
+def summarize_profiles(out_dir):
+    """Writes the committed profile summaries from the rocprofv3 databases of one
+    run of gpu commands (kernel trace of the bench, and three counter passes of
+    bench.py --counters): profiles/bench_kernels_humanoid30_chain7_stats.txt and
+    profiles/kernel_counters_humanoid30_chain7.txt."""
+    import collections
+    import sqlite3
+    topo = _topology_names()
+
+    def db(sub):
+        return sqlite3.connect(os.path.join(out_dir, sub, "run_results.db")).cursor()
+
+    # kernel trace: calls and average duration per kernel
+    cur = db("prof_trace")
+    rows = list(cur.execute("select name, total_calls, average, total_duration, percentage from top_kernels"))
+    lines = ["# Kernel trace of bench.py on one MI355X (gfx950), rocprofv3 --kernel-trace --stats",
+             "#", "# command (run from /tmp with TMPDIR=/tmp):",
+             "#   rocprofv3 --kernel-trace --stats -d <out> -o run -- python3 <repo>/bench.py --steps 20 --warmup 5 "
+             "--no-serving --no-cpu",
+             "# Durations per dispatch in microseconds, over every dispatch of the run (warm-up, timed launches, "
+             "graph replays, single launches).",
+             f"# source_hash = {kernel_source_hash()}", "#",
+             f"{'kernel':70s} {'calls':>6s} {'avg_us':>10s} {'total_us':>11s} {'pct':>6s}"]
+    for name, calls, avg, total, pct in rows:
+        lines.append(f"{_short_kernel(name, topo)[:70]:70s} {calls:6d} {avg:10.3f} {total:11.1f} {pct:6.2f}")
+    with open(os.path.join(ROOT, "profiles", "bench_kernels_humanoid30_chain7_stats.txt"), "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+
+    # counters: summed over shader engines per dispatch, medians per kernel
+    def counters(sub):
+        agg, names = collections.defaultdict(float), {}
+        for did, kname, cname, val in db(sub).execute(
+                "select dispatch_id, kernel_name, counter_name, value from counters_collection"):
+            agg[(did, cname)] += val
+            names[did] = kname
+        per = collections.defaultdict(lambda: collections.defaultdict(list))
+        for (did, cname), v in agg.items():
+            per[names[did]][cname].append(v)
+        return per
+
+    fetch, write, sq = counters("pmc_FETCH_SIZE"), counters("pmc_WRITE_SIZE"), counters("pmc_SQ_INSTS_VALU_FLOPS_FP32")
+    med = lambda xs: float(np.median(xs))  # noqa: E731
+    copy = next(k for k in fetch if "copyBuffer" in k and med(fetch[k]["FETCH_SIZE"]) > 1e5)
+    copy_bytes = 512 << 20
+    fscale = copy_bytes / (med(fetch[copy]["FETCH_SIZE"]) * 1024.0)
+    wscale = copy_bytes / (med(write[copy]["WRITE_SIZE"]) * 1024.0)
+    out = ["# Hardware counters of the hot kernels at their benchmark shapes, one MI355X (gfx950)", "#",
+           "# commands (each its own run, from /tmp with TMPDIR=/tmp):",
+           "#   rocprofv3 --pmc FETCH_SIZE -d <out> -o run -- python3 <repo>/bench.py --counters",
+           "#   rocprofv3 --pmc WRITE_SIZE -d <out> -o run -- python3 <repo>/bench.py --counters",
+           "#   rocprofv3 --pmc SQ_INSTS_VALU_FLOPS_FP32 SQ_INSTS_VALU SQ_WAVES SQ_WAVE_CYCLES SQ_WAIT_ANY "
+           "SQ_WAIT_INST_ANY SQ_ACTIVE_INST_ANY -d <out> -o run -- python3 <repo>/bench.py --counters",
+           "# then: python3 bench.py --summarize-profiles <out dir> (this file and the kernel-trace summary).",
+           "# Counter values summed over shader engines per dispatch, median over the dispatches of a kernel.",
+           f"# Calibration on a plain 512 MiB device copy: FETCH_SIZE scale {fscale:.4f}, WRITE_SIZE scale "
+           f"{wscale:.4f} (bytes = KiB x 1024 x scale).",
+           "# flops_per_eval = SQ_INSTS_VALU_FLOPS_FP32 / SQ_WAVES (FP32 FLOPs of one lane, one instance per lane);",
+           "# valu_insts_per_wave = SQ_INSTS_VALU / SQ_WAVES; quad-cycles per wave: wave_cycles, wait_any "
+           "(dependency and memory waits), wait_inst_any (issue waits), active_inst_any (issuing).",
+           f"source_hash = {kernel_source_hash()}"]
+    for name in sq:
+        key = _kernel_key(_short_kernel(name, topo))
+        if key is None or name not in fetch or name not in write:
+            continue
+        c = {k: med(v) for k, v in sq[name].items()}
+        w = max(c.get("SQ_WAVES", 0.0), 1.0)
+        fb = med(fetch[name]["FETCH_SIZE"]) * 1024.0 * fscale
+        wb = med(write[name]["WRITE_SIZE"]) * 1024.0 * wscale
+        out.append(f"kernel={key} flops_per_eval={c['SQ_INSTS_VALU_FLOPS_FP32'] / w:.0f} "
+                   f"valu_insts_per_wave={c['SQ_INSTS_VALU'] / w:.0f} waves={w:.0f} fetch_bytes={fb:.0f} "
+                   f"write_bytes={wb:.0f} wave_cycles={c['SQ_WAVE_CYCLES'] / w:.0f} wait_any={c['SQ_WAIT_ANY'] / w:.0f} "
+                   f"wait_inst_any={c['SQ_WAIT_INST_ANY'] / w:.0f} active_inst_any={c['SQ_ACTIVE_INST_ANY'] / w:.0f}")
+    with open(COUNTERS_FILE, "w") as fh:
+        fh.write("\n".join(out) + "\n")
+    print("\n".join(out))
+
+
 def soa(x, torch):
     return torch.tensor(np.ascontiguousarray(x.T), dtype=torch.float32, device="cuda")
 
@@ -349,9 +455,13 @@ def main():
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--counters", action="store_true", help="only run the counter-collection driver")
+    ap.add_argument("--summarize-profiles", metavar="DIR", help="write profiles/ summaries from rocprofv3 output")
     args = ap.parse_args()
     if args.counters:
         counters_driver()
+        return
+    if args.summarize_profiles:
+        summarize_profiles(args.summarize_profiles)
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU: the dynamics of independent robot instances need no "
@@ -495,10 +605,11 @@ def main():
     ops = {k: round(v, 2) if "us" in k else float(f"{v:.4g}") for k, v in ops.items()}
     del cq, cqd, ctau
     torch.cuda.empty_cache()
-    hbm = {"write_gbs": round(max(rbd.hbm_rate(1 << 30, 0, b) for b in (4096, 16384)), 1),
-           "copy_gbs": round(max(rbd.hbm_rate(1 << 30, 1, b) for b in (4096, 16384)), 1),
+    hbm = {"write_gbs": round(max(rbd.hbm_rate(1 << 30, m, b) for m in (0, 2) for b in (0, 2048, 8192)), 1),
+           "copy_gbs": round(max(rbd.hbm_rate(1 << 30, 1, b) for b in (0, 2048, 8192)), 1),
            "spec_gbs": PEAK_HBM_GBS,
-           "how": "streaming kernel (16-byte non-temporal stores, grid-stride), best of 10 launches over 1 GiB"}
+           "how": "streaming kernels over 1 GiB (16-byte stores, non-temporal or plain; unrolled tiles or a "
+                  "grid-stride loop), the best configuration, best of 10 launches each"}
     kernels = kernel_rooflines(O, W, desc, chain, ops, cnt, hbm)
 
     serving = None if args.no_serving else serving_leg(rbd, torch, args.serve_seconds)

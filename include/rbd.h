@@ -242,14 +242,15 @@ rbd_status rbd_osc(const rbd_model* model, int64_t batch, int64_t ld, const floa
 rbd_status rbd_diag_fma_rate(int device, int blocks, int ilp, double* tflops);
 
 /* Diagnostic (not on the hot path): measured streaming HBM bandwidth in GB/s.
- * mode 0 writes `bytes` bytes (16-byte non-temporal stores, the way the pose,
- * mass-matrix and Jacobian outputs are written); mode 1 copies `bytes` bytes
- * (GB/s counts read + written bytes). A grid-stride kernel of `blocks` blocks
- * of 256 threads; the best of 10 timed launches after 3 warm-up launches.
- * bytes in [1 MiB, 16 GiB], blocks in [1, 2^20]. Synchronous; allocates and
- * frees its buffers (device memory of bytes, twice for a copy). It is the
- * achievable ceiling the memory-bound kernels are compared with, beside the
- * published 8 TB/s. */
+ * mode 0 writes `bytes` bytes with non-temporal 16-byte stores (the way the
+ * pose, mass-matrix and Jacobian outputs are written), mode 2 with plain
+ * stores; mode 1 copies `bytes` bytes (GB/s counts read + written bytes).
+ * blocks = 0: one block of 256 threads per 64 KiB, each thread 16 elements
+ * a block apart; blocks > 0: a grid-stride loop over that many blocks. The
+ * best of 10 timed launches after 3 warm-up launches. bytes in [1 MiB,
+ * 16 GiB], blocks in [0, 2^20]. Synchronous; allocates and frees its buffers
+ * (device memory of bytes, twice for a copy). It is the achievable ceiling
+ * the memory-bound kernels are compared with, beside the published 8 TB/s. */
 rbd_status rbd_diag_hbm_rate(int device, int64_t bytes, int mode, int blocks, double* gbs);
 
 const char* rbd_status_str(rbd_status s);

@@ -45,22 +45,34 @@ rbd_status time_rate(float* buf, int blocks, int fma_per_lane, hipStream_t s, hi
   return RBD_OK;
 }
 
-// Streaming HBM kernels over n float4 elements: a grid-stride loop of 16-byte
-// accesses, consecutive lanes on consecutive addresses. WRITE stores a value
-// with non-temporal stores (as the pose, mass-matrix and Jacobian outputs are
-// written); COPY reads src and writes dst.
-template <bool COPY>
-__global__ __launch_bounds__(256) void k_hbm_stream(const float4* __restrict__ src, float4* __restrict__ dst,
-                                                    int64_t n, float v) {
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-    float4 x;
+// Streaming HBM kernels over n float4 elements, consecutive lanes on
+// consecutive 16-byte elements. COPY reads src and writes dst, else a value
+// is written; NT selects non-temporal stores (as the pose, mass-matrix and
+// Jacobian outputs are written). With grid-stride = false each thread handles
+// kUnroll elements a block's width apart (one 64 KiB tile per block, no
+// loop); with grid-stride = true the grid strides over the whole array.
+constexpr int kUnroll = 16;
+typedef float f4 __attribute__((ext_vector_type(4)));
+template <bool COPY, bool NT, bool STRIDE>
+__global__ __launch_bounds__(256) void k_hbm_stream(const f4* __restrict__ src, f4* __restrict__ dst, int64_t n,
+                                                    float v) {
+  auto put = [&](int64_t i) __attribute__((always_inline)) {
+    f4 x;
     if constexpr (COPY) x = src[i];
-    else x = make_float4(v, v, v, v);
-    __builtin_nontemporal_store(x.x, &dst[i].x);
-    __builtin_nontemporal_store(x.y, &dst[i].y);
-    __builtin_nontemporal_store(x.z, &dst[i].z);
-    __builtin_nontemporal_store(x.w, &dst[i].w);
+    else x = f4{v, v, v, v};
+    if constexpr (NT) __builtin_nontemporal_store(x, &dst[i]);
+    else dst[i] = x;
+  };
+  if constexpr (STRIDE) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) put(i);
+  } else {
+    const int64_t base = (int64_t)blockIdx.x * kUnroll * blockDim.x + threadIdx.x;
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      const int64_t i = base + (int64_t)u * blockDim.x;
+      if (i < n) put(i);
+    }
   }
 }
 
@@ -68,19 +80,19 @@ __global__ __launch_bounds__(256) void k_hbm_stream(const float4* __restrict__ s
 }  // namespace rbd
 
 // Best of 10 timed launches (after 3 warm-up launches) of the streaming kernel
-// over `bytes` bytes (rounded down to 16), with 256-thread blocks, `blocks` of
-// them; GB/s counts the bytes moved to and from HBM (copy: read + write).
+// over `bytes` bytes (rounded down to 16), 256-thread blocks; GB/s counts the
+// bytes moved to and from HBM (copy: read + write).
 extern "C" rbd_status rbd_diag_hbm_rate(int device, int64_t bytes, int mode, int blocks, double* gbs) {
   using namespace rbd;
   if (!gbs) return fail(RBD_E_INVAL, "gbs is NULL");
-  if (mode != 0 && mode != 1) return fail(RBD_E_INVAL, "mode = %d, expected 0 (write) or 1 (copy)", mode);
+  if (mode < 0 || mode > 2) return fail(RBD_E_INVAL, "mode = %d, expected 0 (write), 1 (copy) or 2 (plain write)", mode);
   if (bytes < (1 << 20) || bytes > (int64_t(16) << 30))
     return fail(RBD_E_INVAL, "bytes = %lld, expected 1 MiB .. 16 GiB", (long long)bytes);
-  if (blocks < 1 || blocks > (1 << 20)) return fail(RBD_E_INVAL, "blocks = %d, expected 1..2^20", blocks);
+  if (blocks < 0 || blocks > (1 << 20)) return fail(RBD_E_INVAL, "blocks = %d, expected 0..2^20", blocks);
   if (device < 0 || device >= rbd_device_count()) return fail(RBD_E_NODEVICE, "device %d is not available", device);
   if (hipSetDevice(device) != hipSuccess) return fail(RBD_E_NODEVICE, "cannot select device %d", device);
   const int64_t n = bytes / 16;
-  float4 *src = nullptr, *dst = nullptr;
+  f4 *src = nullptr, *dst = nullptr;
   if (hipMalloc(&dst, n * 16) != hipSuccess) return fail(RBD_E_NOMEM, "allocation failed");
   if (mode == 1 && hipMalloc(&src, n * 16) != hipSuccess) {
     (void)hipFree(dst);
@@ -90,12 +102,18 @@ extern "C" rbd_status rbd_diag_hbm_rate(int device, int64_t bytes, int mode, int
   hipEvent_t e0 = nullptr, e1 = nullptr;
   (void)hipEventCreate(&e0);
   (void)hipEventCreate(&e1);
+  const unsigned tiles = (unsigned)((n + (int64_t)kUnroll * 256 - 1) / ((int64_t)kUnroll * 256));
+  const dim3 grid(blocks > 0 ? (unsigned)blocks : tiles), block(256);
   auto launch = [&]() {
-    if (mode == 1)
-      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_hbm_stream<true>), dim3(blocks), dim3(256), 0, nullptr, src, dst, n, 0.0f);
-    else
-      hipLaunchKernelGGL(HIP_KERNEL_NAME(k_hbm_stream<false>), dim3(blocks), dim3(256), 0, nullptr, src, dst, n,
-                         1.0f);
+    if (blocks > 0) {
+      if (mode == 1) hipLaunchKernelGGL(HIP_KERNEL_NAME(k_hbm_stream<true, true, true>), grid, block, 0, nullptr, src, dst, n, 0.0f);
+      else if (mode == 0) hipLaunchKernelGGL(HIP_KERNEL_NAME(k_hbm_stream<false, true, true>), grid, block, 0, nullptr, src, dst, n, 1.0f);
+      else hipLaunchKernelGGL(HIP_KERNEL_NAME(k_hbm_stream<false, false, true>), grid, block, 0, nullptr, src, dst, n, 1.0f);
+    } else {
+      if (mode == 1) hipLaunchKernelGGL(HIP_KERNEL_NAME(k_hbm_stream<true, true, false>), grid, block, 0, nullptr, src, dst, n, 0.0f);
+      else if (mode == 0) hipLaunchKernelGGL(HIP_KERNEL_NAME(k_hbm_stream<false, true, false>), grid, block, 0, nullptr, src, dst, n, 1.0f);
+      else hipLaunchKernelGGL(HIP_KERNEL_NAME(k_hbm_stream<false, false, false>), grid, block, 0, nullptr, src, dst, n, 1.0f);
+    }
   };
   rbd_status st = RBD_OK;
   float best = 0.0f;
