@@ -144,8 +144,11 @@ def kernel_rooflines(O, W, desc, chain, ops, cnt, hbm):
     B, Bv, Bc, Bw = BATCH, 32768, 1 << 20, 1 << 18
     nb = desc.n_bodies
 
-    def valu(key, us, batch, oracle_flops):
-        c = cnt.get(key, {})
+    def valu(key, us, batch, oracle_flops, counter_batch=None):
+        c = dict(cnt.get(key, {}))
+        if counter_batch is not None and counter_batch != batch:
+            c.pop("fetch_bytes", None)  # bytes per launch were counted at another batch
+            c.pop("write_bytes", None)
         exe = c.get("flops_per_eval")
         r = {"kernel_us": us, "batch": batch, "bound": "alu", "peak_tflops": PEAK_FP32_TFLOPS,
              "oracle_flops_per_eval": oracle_flops,
@@ -182,6 +185,10 @@ def kernel_rooflines(O, W, desc, chain, ops, cnt, hbm):
         "fwd_dyn_vjp_humanoid30": valu("fwd_dyn_vjp_humanoid30", ops["fwd_dyn_vjp_humanoid30_b32768_us"], Bv, None),
         "fwd_dyn_vjp_chain7": valu("fwd_dyn_vjp_chain7", ops["fwd_dyn_vjp_chain7_b262144_us"], Bw, None),
         "fwd_dyn_jvp_humanoid30": valu("fwd_dyn_jvp_humanoid30", ops["fwd_dyn_jvp_humanoid30_b32768_us"], Bv, None),
+        "fwd_dyn_vjp_humanoid30_b65536": valu("fwd_dyn_vjp_humanoid30", ops["fwd_dyn_vjp_humanoid30_b65536_us"], B,
+                                              None, counter_batch=Bv),
+        "fwd_dyn_jvp_humanoid30_b65536": valu("fwd_dyn_jvp_humanoid30", ops["fwd_dyn_jvp_humanoid30_b65536_us"], B,
+                                              None, counter_batch=Bv),
         "osc_humanoid30": valu("osc_humanoid30", ops["osc_humanoid30_b65536_us"], B, None),
         "crba_humanoid30": mem("crba_humanoid30", ops["crba_humanoid30_b65536_us"], B, 4 * (desc.nq + nv * nv)),
         "fk_humanoid30": mem("fk_humanoid30", ops["fk_humanoid30_b65536_us"], B, 4 * (desc.nq + 12 * nb)),
@@ -346,6 +353,8 @@ def cpu_baseline(desc, st, budget_s):
     except OSError:
         pass
     return {"value": done / dt, "unit": "evals/s", "cores": cores, "kind": "oracle", "cpu_model": model,
+            "build": "g++ -O2 -fopenmp, no -march (portable code, as committed)",
+            "parallelism": "OpenMP over states, one state per thread at a time, default affinity",
             "sample": f"{done} humanoid30 fwd_dyn evals (FP64, branch-sparse L^T L) = {done // n} passes over "
                       f"the first {n} states of the batch, {dt:.1f} s wall",
             "one_core_evals_per_s": done1 / dt1}
@@ -581,6 +590,15 @@ def main():
     ops["fwd_dyn_jvp_humanoid30_b32768_us"] = 1e3 * time_launches(
         lambda: rbd.fwd_dyn_jvp(model, vq, vqd, vtau, tq, tqd, ttau), n_t, torch)
     del tq, tqd, ttau
+    # the same two at batch 65536, where their waves fill every SIMD (32768 instances fill half)
+    g65 = soa(W.cotangent(desc.nv, BATCH, 9), torch)
+    ops["fwd_dyn_vjp_humanoid30_b65536_us"] = 1e3 * time_launches(
+        lambda: rbd.fwd_dyn_vjp(model, q, qd, tau, g65), n_t, torch)
+    tq, tqd, ttau = (soa(W._f32(np.random.default_rng(s).normal(size=(BATCH, r))), torch)
+                     for s, r in ((11, desc.nq), (12, desc.nv), (13, desc.nv)))
+    ops["fwd_dyn_jvp_humanoid30_b65536_us"] = 1e3 * time_launches(
+        lambda: rbd.fwd_dyn_jvp(model, q, qd, tau, tq, tqd, ttau), n_t, torch)
+    del tq, tqd, ttau, g65
     tg = soa(W._f32(targets(W, BATCH)), torch)
     ops["osc_humanoid30_b65536_us"] = 1e3 * time_launches(lambda: rbd.osc(model, q, qd, tg, 50.0, 10.0, 2.0), n_t, torch)
     ops["diff_ik_humanoid30_b65536_us"] = 1e3 * time_launches(lambda: rbd.diff_ik(model, q, tg, 2.0, 0.05), n_t, torch)

@@ -104,7 +104,8 @@ typedef struct rbd_model rbd_model; /* opaque: device-resident tables */
  * that kernel is launched on a device (so the first call of each operation on
  * a new topology is host-synchronous and takes seconds for small trees, up to
  * minutes for a 40-body tree; the first call must not be made during stream
- * capture). Code objects are cached on disk and looked up in $RBD_JIT_CACHE
+ * capture; controller kernels of other frames, see rbd_osc, are compiled the
+ * same way). Code objects are cached on disk and looked up in $RBD_JIT_CACHE
  * (if set), then in "_jit" beside librbd.so (code objects installed with the
  * library, see rbd_precompile_topology), then in $XDG_CACHE_HOME/rbd-jit or
  * ~/.cache/rbd-jit; new ones are written to $RBD_JIT_CACHE, else the user
@@ -130,12 +131,14 @@ const char* rbd_model_topology(const rbd_model* model);
  * depth-first, floating != 0 for a free body 0) into the code-object cache
  * directory cache_dir (created if missing; NULL = the default write directory
  * described at rbd_model_create): kernel = -1 compiles all RBD_N_KERNELS of
- * them, kernel in [0, RBD_N_KERNELS) that one only (separate processes can
+ * them, kernel in [0, RBD_N_KERNELS) that one only, RBD_N_KERNELS + 2 f the
+ * differential-IK and RBD_N_KERNELS + 2 f + 1 the operational-space-control
+ * kernel of frame f (0 <= f < n_bodies; separate processes can
  * compile a topology's kernels in parallel: hiprtc compiles one program at a
  * time per process). Kernels already in the directory are kept. Needs no GPU.
  * Synchronous. Used to install a robot's kernels before its first use.
  * Errors: RBD_E_INVAL, RBD_E_COMPILE. */
-#define RBD_N_KERNELS 27
+#define RBD_N_KERNELS 30
 rbd_status rbd_precompile_topology(int32_t n_bodies, const int32_t* parent, int floating, const char* cache_dir,
                                    int32_t kernel);
 
@@ -187,35 +190,43 @@ rbd_status rbd_fwd_dyn(const rbd_model* model, int64_t batch, int64_t ld, const 
 rbd_status rbd_aba(const rbd_model* model, int64_t batch, int64_t ld, const float* q, const float* qd,
                    const float* tau, const float* f_ext, float* qdd, hipStream_t stream);
 
-/* Jacobian-vector product of rbd_fwd_dyn without external forces (forward-mode
- * AD, Sec. IV-A and Fig. 2): for tangents dq [nq][ld] (raw quaternion
- * components included; a free base's position does not change qdd), dqd and
- * dtau [nv][ld], dqdd = dqdd/dq dq + dqdd/dqd dqd + M^-1 dtau [nv][ld]. Computed
- * as M^-1 (dtau - dID/dq dq - dID/dqd dqd) at qdd = FD(q, qd, tau): the fused
- * forward dynamics, a sweep of tangent inverse dynamics, then a solve with M,
- * all in one kernel. qdd (nullable) also receives the forward dynamics. All
- * inputs are required. The forward dynamics is kept in qdd (or in dqdd) between
- * the sweeps, so qdd and dqdd must not overlap (RBD_E_INVAL). */
+/* Jacobian-vector product of rbd_fwd_dyn (forward-mode AD, Sec. IV-A and
+ * Fig. 2): for tangents dq [nq][ld] (raw quaternion components included),
+ * dqd and dtau [nv][ld], and external-force tangents df_ext [n_bodies*6][ld]
+ * (nullable: zero), dqdd = dqdd/dq dq + dqdd/dqd dqd + M^-1 dtau + M^-1
+ * sum_i J_i^T dF_i [nv][ld], at the forward dynamics with external forces
+ * f_ext (nullable: none; layout as for rbd_rnea). Computed as
+ * M^-1 (dtau - dID/dq dq - dID/dqd dqd) at qdd = FD(q, qd, tau, F), with ID
+ * including -sum_i J_i(q)^T F_i: the fused forward dynamics, a sweep of
+ * tangent inverse dynamics, then a solve with M, all in one kernel. With
+ * forces, a free base's position tangent moves them relative to the robot.
+ * qdd (nullable) also receives the forward dynamics. The forward dynamics is
+ * kept in qdd (or in dqdd) between the sweeps, so qdd and dqdd must not
+ * overlap (RBD_E_INVAL). */
 rbd_status rbd_fwd_dyn_jvp(const rbd_model* model, int64_t batch, int64_t ld, const float* q, const float* qd,
-                           const float* tau, const float* dq, const float* dqd, const float* dtau, float* qdd,
-                           float* dqdd, hipStream_t stream);
+                           const float* tau, const float* f_ext, const float* dq, const float* dqd,
+                           const float* dtau, const float* df_ext, float* qdd, float* dqdd, hipStream_t stream);
 
-/* Vector-Jacobian product of rbd_fwd_dyn without external forces, for the
- * cotangent g_qdd [nv][ld]:
- * g_q = g_qdd^T dqdd/dq [nq][ld] (raw quaternion components included),
- * g_qd = g_qdd^T dqdd/dqd [nv][ld], g_tau = g_qdd^T dqdd/dtau = M^-1 g_qdd
- * [nv][ld]. Any of the three outputs may be NULL (not computed). Between the
- * kernel's two sweeps the requested outputs hold the forward dynamics and
+/* Vector-Jacobian product of rbd_fwd_dyn with external forces f_ext
+ * (nullable: none; layout as for rbd_rnea), for the cotangent g_qdd [nv][ld]:
+ * g_q = g_qdd^T dqdd/dq [nq][ld] (raw quaternion components included; with
+ * forces, a free base's position has a gradient too), g_qd = g_qdd^T
+ * dqdd/dqd [nv][ld], g_tau = M^-1 g_qdd [nv][ld], and g_f_ext = g_qdd^T
+ * dqdd/dF [n_bodies*6][ld]: for body i, J_i lam with lam = M^-1 g_qdd, the
+ * twist of body i in world axes at the world origin, [v_O; w] (it pairs with
+ * F_i = [f; n_O]). Any of the four outputs may be NULL (not computed). Between
+ * the kernel's two sweeps the requested outputs hold the forward dynamics and
  * M^-1 g_qdd, so they must not overlap one another (RBD_E_INVAL). */
 rbd_status rbd_fwd_dyn_vjp(const rbd_model* model, int64_t batch, int64_t ld, const float* q, const float* qd,
-                           const float* tau, const float* g_qdd, float* g_q, float* g_qd, float* g_tau,
-                           hipStream_t stream);
+                           const float* tau, const float* f_ext, const float* g_qdd, float* g_q, float* g_qd,
+                           float* g_tau, float* g_f_ext, hipStream_t stream);
 
 /* Controller workloads (Sec. IV, Sec. V and Table II: differential IK and
- * operational-space control), the plain textbook forms for one end-effector
- * frame, fused into one kernel each. frame must be the last body (n_bodies -
- * 1, a leaf: the end effector every topology is compiled for; another valid
- * body id gives RBD_E_UNSUPPORTED). target: [12][ld], the desired pose
+ * operational-space control), the plain textbook forms for one frame, fused
+ * into one kernel each. frame is any body id: the last body (n_bodies - 1)
+ * has kernels with the topology's others; for any other frame the kernel is
+ * compiled for that frame at run time on its first use (cached on disk like
+ * a new topology's kernels; RBD_E_COMPILE if that fails). target: [12][ld], the desired pose
  * [R* | p*] of the frame per instance in the layout of rbd_fk's output (R* in
  * the body's user axes). With the frame's pose (R_e, p_e) and its Jacobian J
  * as in rbd_jacobian:

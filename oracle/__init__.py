@@ -63,8 +63,8 @@ def lib():
         L.orc_fwd_dyn_ext.argtypes = [m, i64, d, d, d, d, d, C.c_int]
         L.orc_crba.argtypes = [m, i64, d, d]
         L.orc_fwd_dyn.argtypes = [m, i64, d, d, d, d, C.c_int]
-        L.orc_fwd_dyn_vjp_fd.argtypes = [m, i64, d, d, d, d, d, d, d, C.c_double, C.c_int]
-        L.orc_fwd_dyn_jvp_fd.argtypes = [m, i64, d, d, d, d, d, d, d, C.c_double, C.c_int]
+        L.orc_fwd_dyn_vjp_fd.argtypes = [m, i64, d, d, d, d, d, d, d, d, d, C.c_double, C.c_int]
+        L.orc_fwd_dyn_jvp_fd.argtypes = [m, i64, d, d, d, d, d, d, d, d, d, C.c_double, C.c_int]
         L.orc_count_ops.argtypes = [m, C.c_int, P(C.c_longlong)]
         L.orc_max_threads.argtypes = []
         L.orc_set_threads.argtypes = [C.c_int]
@@ -174,21 +174,30 @@ def fwd_dyn(desc, q, qd, tau, method=METHOD_LTL, fext=None):
     return qdd
 
 
-def fwd_dyn_vjp_fd(desc, q, qd, tau, gbar, h=1e-6, method=METHOD_LTL):
-    """(gq, gqd, gtau): gbar^T d qdd / d(q, qd, tau) by central differences of step h."""
+def fwd_dyn_vjp_fd(desc, q, qd, tau, gbar, h=1e-6, method=METHOD_LTL, fext=None):
+    """(gq, gqd, gtau) = gbar^T d qdd / d(q, qd, tau) by central differences of step h; with external
+    forces fext [B, n, 6] (or [B, 6n]) also gfext = gbar^T d qdd / dF, [B, 6n]."""
     q, qd, tau, gbar = _c(q), _c(qd), _c(tau), _c(gbar)
     gq, gqd, gtau = np.empty_like(q), np.empty_like(qd), np.empty_like(tau)
-    _check(lib().orc_fwd_dyn_vjp_fd(C.byref(_model(desc)), q.shape[0], _dp(q), _dp(qd), _dp(tau), _dp(gbar),
-                                    _dp(gq), _dp(gqd), _dp(gtau), h, method), "vjp")
-    return gq, gqd, gtau
+    fx = None if fext is None else _c(np.asarray(fext).reshape(q.shape[0], -1))
+    gf = None if fext is None else np.empty_like(fx)
+    _check(lib().orc_fwd_dyn_vjp_fd(C.byref(_model(desc)), q.shape[0], _dp(q), _dp(qd), _dp(tau),
+                                    None if fx is None else _dp(fx), _dp(gbar), _dp(gq), _dp(gqd), _dp(gtau),
+                                    None if gf is None else _dp(gf), h, method), "vjp")
+    return (gq, gqd, gtau) if fext is None else (gq, gqd, gtau, gf)
 
 
-def fwd_dyn_jvp_fd(desc, q, qd, tau, dq, dqd, dtau, h=1e-6, method=METHOD_LTL):
-    """d qdd along (dq, dqd, dtau): one central difference of step h of forward dynamics."""
+def fwd_dyn_jvp_fd(desc, q, qd, tau, dq, dqd, dtau, h=1e-6, method=METHOD_LTL, fext=None, dfext=None):
+    """d qdd along (dq, dqd, dtau[, dfext]): one central difference of step h of forward dynamics
+    (with external forces fext when given; either force array may be None)."""
     q, qd, tau, dq, dqd, dtau = _c(q), _c(qd), _c(tau), _c(dq), _c(dqd), _c(dtau)
+    B = q.shape[0]
+    fx = None if fext is None else _c(np.asarray(fext).reshape(B, -1))
+    dfx = None if dfext is None else _c(np.asarray(dfext).reshape(B, -1))
     dqdd = np.empty_like(qd)
-    _check(lib().orc_fwd_dyn_jvp_fd(C.byref(_model(desc)), q.shape[0], _dp(q), _dp(qd), _dp(tau), _dp(dq),
-                                    _dp(dqd), _dp(dtau), _dp(dqdd), h, method), "jvp")
+    _check(lib().orc_fwd_dyn_jvp_fd(C.byref(_model(desc)), B, _dp(q), _dp(qd), _dp(tau),
+                                    None if fx is None else _dp(fx), _dp(dq), _dp(dqd), _dp(dtau),
+                                    None if dfx is None else _dp(dfx), _dp(dqdd), h, method), "jvp")
     return dqdd
 
 

@@ -835,18 +835,21 @@ int orc_fwd_dyn_ext(const orc_model* d, int64_t B, const double* q, const double
   return 0;
 }
 
-// Jacobian-vector product of qdd = FD(q, qd, tau) along the tangent (dq, dqd,
-// dtau), the directional derivative by one central difference of step h:
-// [FD(x + h dx) - FD(x - h dx)] / 2h (raw quaternion components are moved
-// like any other coordinate).
+// Jacobian-vector product of qdd = FD(q, qd, tau, F) along the tangent (dq,
+// dqd, dtau, dF), the directional derivative by one central difference of
+// step h: [FD(x + h dx) - FD(x - h dx)] / 2h (raw quaternion components are
+// moved like any other coordinate). fext (external forces, [B][6n]) and dfext
+// may be null (none, and a zero tangent).
 int orc_fwd_dyn_jvp_fd(const orc_model* d, int64_t B, const double* q, const double* qd, const double* tau,
-                       const double* dq, const double* dqd, const double* dtau, double* dqdd, double h, int method) {
+                       const double* fext, const double* dq, const double* dqd, const double* dtau,
+                       const double* dfext, double* dqdd, double h, int method) {
   Model M;
   if (build_model(d, M) || method < 0 || method > 2) return 1;
-  const int nq = M.nq, nv = M.nv;
+  const int nq = M.nq, nv = M.nv, nf = 6 * M.n;
+  const bool ext = fext || dfext;
 #pragma omp parallel for schedule(static)
   for (int64_t b = 0; b < B; ++b) {
-    std::vector<double> xp(nq), xm(nq), yp(nv), ym(nv), zp(nv), zm(nv), ap(nv), am(nv);
+    std::vector<double> xp(nq), xm(nq), yp(nv), ym(nv), zp(nv), zm(nv), ap(nv), am(nv), fp(nf), fm(nf);
     for (int k = 0; k < nq; ++k) {
       xp[k] = q[b * nq + k] + h * dq[b * nq + k];
       xm[k] = q[b * nq + k] - h * dq[b * nq + k];
@@ -857,25 +860,34 @@ int orc_fwd_dyn_jvp_fd(const orc_model* d, int64_t B, const double* q, const dou
       zp[k] = tau[b * nv + k] + h * dtau[b * nv + k];
       zm[k] = tau[b * nv + k] - h * dtau[b * nv + k];
     }
-    fwd_dyn(M, xp.data(), yp.data(), zp.data(), ap.data(), method);
-    fwd_dyn(M, xm.data(), ym.data(), zm.data(), am.data(), method);
+    for (int k = 0; k < nf && ext; ++k) {
+      const double f0 = fext ? fext[b * nf + k] : 0.0, df = dfext ? dfext[b * nf + k] : 0.0;
+      fp[k] = f0 + h * df;
+      fm[k] = f0 - h * df;
+    }
+    fwd_dyn(M, xp.data(), yp.data(), zp.data(), ap.data(), method, ext ? fp.data() : nullptr);
+    fwd_dyn(M, xm.data(), ym.data(), zm.data(), am.data(), method, ext ? fm.data() : nullptr);
     for (int k = 0; k < nv; ++k) dqdd[b * nv + k] = (ap[k] - am[k]) / (2.0 * h);
   }
   return 0;
 }
 
-// Vector-Jacobian product of qdd = FD(q, qd, tau) with cotangent gbar, by
+// Vector-Jacobian product of qdd = FD(q, qd, tau, F) with cotangent gbar, by
 // central differences of step h on every coordinate (raw quaternion
-// components included). Any output may be null.
+// components and every external-force component included). fext may be null
+// (no forces); any output may be null.
 int orc_fwd_dyn_vjp_fd(const orc_model* d, int64_t B, const double* q, const double* qd, const double* tau,
-                       const double* gbar, double* gq, double* gqd, double* gtau, double h, int method) {
+                       const double* fext, const double* gbar, double* gq, double* gqd, double* gtau,
+                       double* gfext, double h, int method) {
   Model M;
   if (build_model(d, M) || method < 0 || method > 2) return 1;
-  const int nq = M.nq, nv = M.nv;
+  const int nq = M.nq, nv = M.nv, nf = 6 * M.n;
+  const bool ext = fext || gfext;
 #pragma omp parallel for schedule(static)
   for (int64_t b = 0; b < B; ++b) {
-    std::vector<double> x(nq), y(nv), z(nv), qp(nv), qm(nv);
+    std::vector<double> x(nq), y(nv), z(nv), f(nf, 0.0), qp(nv), qm(nv);
     const double* g = gbar + b * nv;
+    const double* F = ext ? f.data() : nullptr;
     auto contract = [&](void) {
       double s = 0.0;
       for (int k = 0; k < nv; ++k) s += g[k] * (qp[k] - qm[k]);
@@ -884,30 +896,22 @@ int orc_fwd_dyn_vjp_fd(const orc_model* d, int64_t B, const double* q, const dou
     std::memcpy(x.data(), q + b * nq, nq * sizeof(double));
     std::memcpy(y.data(), qd + b * nv, nv * sizeof(double));
     std::memcpy(z.data(), tau + b * nv, nv * sizeof(double));
+    if (fext) std::memcpy(f.data(), fext + b * nf, nf * sizeof(double));
+    auto diff = [&](double* v, int k) {
+      const double v0 = v[k];
+      v[k] = v0 + h; fwd_dyn(M, x.data(), y.data(), z.data(), qp.data(), method, F);
+      v[k] = v0 - h; fwd_dyn(M, x.data(), y.data(), z.data(), qm.data(), method, F);
+      v[k] = v0;
+      return contract();
+    };
     if (gq)
-      for (int k = 0; k < nq; ++k) {
-        const double x0 = x[k];
-        x[k] = x0 + h; fwd_dyn(M, x.data(), y.data(), z.data(), qp.data(), method);
-        x[k] = x0 - h; fwd_dyn(M, x.data(), y.data(), z.data(), qm.data(), method);
-        x[k] = x0;
-        gq[b * nq + k] = contract();
-      }
+      for (int k = 0; k < nq; ++k) gq[b * nq + k] = diff(x.data(), k);
     if (gqd)
-      for (int k = 0; k < nv; ++k) {
-        const double y0 = y[k];
-        y[k] = y0 + h; fwd_dyn(M, x.data(), y.data(), z.data(), qp.data(), method);
-        y[k] = y0 - h; fwd_dyn(M, x.data(), y.data(), z.data(), qm.data(), method);
-        y[k] = y0;
-        gqd[b * nv + k] = contract();
-      }
+      for (int k = 0; k < nv; ++k) gqd[b * nv + k] = diff(y.data(), k);
     if (gtau)
-      for (int k = 0; k < nv; ++k) {
-        const double z0 = z[k];
-        z[k] = z0 + h; fwd_dyn(M, x.data(), y.data(), z.data(), qp.data(), method);
-        z[k] = z0 - h; fwd_dyn(M, x.data(), y.data(), z.data(), qm.data(), method);
-        z[k] = z0;
-        gtau[b * nv + k] = contract();
-      }
+      for (int k = 0; k < nv; ++k) gtau[b * nv + k] = diff(z.data(), k);
+    if (gfext)
+      for (int k = 0; k < nf; ++k) gfext[b * nf + k] = diff(f.data(), k);
   }
   return 0;
 }

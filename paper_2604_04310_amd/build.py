@@ -39,8 +39,11 @@ PREBUILT = {
     "tree40f": (True, [-1, 0, 1, 0, 0, 0, 0, 6, 7, 8, 9, 10, 9, 0, 13, 0, 15, 16, 0, 0, 0, 0, 21, 0, 23, 24, 25, 0,
                        27, 28, 29, 30, 31, 32, 29, 34, 27, 0, 37, 38]),
 }
+# Controller kernels of frames other than the last body, installed the same
+# way: topology name (compiled or PREBUILT) -> frames.
+PREBUILT_FRAMES = {"humanoid30": [6, 22], "chain7": [3], "quadruped13f": [3]}
 JIT_DIR = os.path.join(PKG, "_jit")
-N_KERNELS = 27  # RBD_N_KERNELS
+N_KERNELS = 30  # RBD_N_KERNELS
 
 
 def _precompile_one(args):
@@ -64,6 +67,10 @@ def prebuild_jit(verbose: bool = False, jobs: int = 0) -> None:
     import multiprocessing as mp
     t0 = time.time()
     work = [(name, fl, par, k) for name, (fl, par) in PREBUILT.items() for k in range(N_KERNELS)]
+    shapes = {**compiled_topologies(), **PREBUILT}
+    for name, frames in PREBUILT_FRAMES.items():
+        fl, par = shapes[name]
+        work += [(f"{name} frame {f}", fl, par, N_KERNELS + 2 * f + osc) for f in frames for osc in (0, 1)]
     work.sort(key=lambda w: -len(w[2]))  # the largest trees first
     with ProcessPoolExecutor(max_workers=jobs or _jobs(), mp_context=mp.get_context("spawn")) as ex:
         for name, kernel, st, err in ex.map(_precompile_one, work):
@@ -77,6 +84,13 @@ def prebuild_jit(verbose: bool = False, jobs: int = 0) -> None:
     if verbose:
         print(f"jit cache: {len(work)} kernels of {len(PREBUILT)} topologies ready in {time.time() - t0:.1f}s",
               flush=True)
+
+
+def compiled_topologies():
+    """name -> (floating, parents) of every topology compiled ahead of time."""
+    text = open(os.path.join(CSRC, "rbd_topologies.hpp")).read().replace("\\\n", " ")
+    return {name: (fr == "true", [int(x) for x in par.split(",")])
+            for name, fr, par in re.findall(r"X\((\w+), (true|false), ([-0-9, \s]+)\)", text)}
 
 
 def topologies():
@@ -140,7 +154,7 @@ def build(verbose: bool = False, jobs: int = 0, resource_usage: bool = False, in
     work = []
     # the largest topologies first, so the longest compiles start early
     for name in reversed(topologies()):
-        for part in (2, 7, 4, 6, 5, 3, 1):
+        for part in (8, 2, 7, 4, 6, 5, 3, 1):
             obj = os.path.join(out_dir, f"kern_{name}_p{part}.o")
             cmd = [HIPCC, *DEVICE, *COMMON, f"-DRBD_TOPO={name}", f"-DRBD_PART={part}", "-c",
                    os.path.join(CSRC, TOPO_SOURCE), "-o", obj]

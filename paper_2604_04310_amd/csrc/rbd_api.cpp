@@ -302,6 +302,7 @@ rbd_status rbd_model_create(const rbd_tree_desc* desc, int device, rbd_model** o
   m->device = device;
   m->topo = topo;
   m->ks = ks;
+  m->parent.assign(desc->parent, desc->parent + n);
   m->n = n;
   m->floating = floating;
   m->nq = n + (floating ? 6 : 0);
@@ -354,8 +355,8 @@ rbd_status rbd_precompile_topology(int32_t n_bodies, const int32_t* parent, int 
   static_assert(KID_COUNT == RBD_N_KERNELS, "RBD_N_KERNELS differs from the kernel list");
   if (!parent) return fail(RBD_E_INVAL, "parent is NULL");
   if (n_bodies < 1 || n_bodies > 64) return fail(RBD_E_INVAL, "n_bodies = %d, expected 1..64", n_bodies);
-  if (kernel < -1 || kernel >= KID_COUNT)
-    return fail(RBD_E_INVAL, "kernel = %d, expected -1 or 0..%d", kernel, KID_COUNT - 1);
+  if (kernel < -1 || kernel >= KID_COUNT + 2 * n_bodies)
+    return fail(RBD_E_INVAL, "kernel = %d, expected -1 or 0..%d", kernel, KID_COUNT + 2 * n_bodies - 1);
   rbd_status st = validate_topology(n_bodies, parent);
   if (st != RBD_OK) return st;
   return jit_precompile(floating != 0, n_bodies, parent, cache_dir, kernel);
@@ -437,8 +438,8 @@ rbd_status rbd_aba(const rbd_model* m, int64_t batch, int64_t ld, const float* q
 }
 
 rbd_status rbd_fwd_dyn_jvp(const rbd_model* m, int64_t batch, int64_t ld, const float* q, const float* qd,
-                           const float* tau, const float* dq, const float* dqd, const float* dtau, float* qdd,
-                           float* dqdd, hipStream_t s) {
+                           const float* tau, const float* f_ext, const float* dq, const float* dqd, const float* dtau,
+                           const float* df_ext, float* qdd, float* dqdd, hipStream_t s) {
   rbd_status st = check_batch(m, batch, ld, "rbd_fwd_dyn_jvp");
   if (st != RBD_OK) return st;
   if (batch > 0 && (!q || !qd || !tau || !dq || !dqd || !dtau || !dqdd))
@@ -446,22 +447,20 @@ rbd_status rbd_fwd_dyn_jvp(const rbd_model* m, int64_t batch, int64_t ld, const 
   // qdd is parked in one of the outputs between sweeps
   if (soa_overlap(qdd, m->nv, dqdd, m->nv, ld, batch))
     return fail(RBD_E_INVAL, "rbd_fwd_dyn_jvp: qdd and dqdd overlap");
+  const int64_t nf = 6 * (int64_t)m->n;
   for (const float* o : {static_cast<const float*>(qdd), static_cast<const float*>(dqdd)})
-    if (output_overlaps(o, m->nv, {{q, m->nq}, {qd, m->nv}, {tau, m->nv}, {dq, m->nq}, {dqd, m->nv}, {dtau, m->nv}},
+    if (output_overlaps(o, m->nv, {{q, m->nq}, {qd, m->nv}, {tau, m->nv}, {f_ext, nf}, {dq, m->nq}, {dqd, m->nv},
+                                   {dtau, m->nv}, {df_ext, nf}},
                         ld, batch))
       return fail(RBD_E_INVAL, "rbd_fwd_dyn_jvp: an output overlaps an input");
   DeviceScope ds(m->device);
   if (ds.st != RBD_OK) return ds.st;
-  return launch_fwd_dyn_jvp(m, batch, ld, q, qd, tau, dq, dqd, dtau, qdd, dqdd, s);
+  return launch_fwd_dyn_jvp(m, batch, ld, q, qd, tau, f_ext, dq, dqd, dtau, df_ext, qdd, dqdd, s);
 }
 
-// The controller entry points serve the end effector each topology is compiled
-// for: the last body.
+// A controller frame is any body (the last one has ahead-of-time kernels).
 static rbd_status check_frame(const rbd_model* m, int32_t frame, const char* fn) {
   if (frame < 0 || frame >= m->n) return fail(RBD_E_INVAL, "%s: frame %d is not a body id (0..%d)", fn, frame, m->n - 1);
-  if (frame != m->n - 1)
-    return fail(RBD_E_UNSUPPORTED, "%s: frame %d: kernels are compiled for the end effector, body %d", fn, frame,
-                m->n - 1);
   return RBD_OK;
 }
 
@@ -477,7 +476,7 @@ rbd_status rbd_diff_ik(const rbd_model* m, int64_t batch, int64_t ld, const floa
     return fail(RBD_E_INVAL, "rbd_diff_ik: the output overlaps an input");
   DeviceScope ds(m->device);
   if (ds.st != RBD_OK) return ds.st;
-  return launch_diff_ik(m, batch, ld, q, target, gain, damping * damping, qd, s);
+  return launch_diff_ik(m, batch, ld, q, frame, target, gain, damping * damping, qd, s);
 }
 
 rbd_status rbd_osc(const rbd_model* m, int64_t batch, int64_t ld, const float* q, const float* qd, int32_t frame,
@@ -492,25 +491,28 @@ rbd_status rbd_osc(const rbd_model* m, int64_t batch, int64_t ld, const float* q
     return fail(RBD_E_INVAL, "rbd_osc: the output overlaps an input");
   DeviceScope ds(m->device);
   if (ds.st != RBD_OK) return ds.st;
-  return launch_osc(m, batch, ld, q, qd, target, kp, kd, k_null, tau, s);
+  return launch_osc(m, batch, ld, q, qd, frame, target, kp, kd, k_null, tau, s);
 }
 
 rbd_status rbd_fwd_dyn_vjp(const rbd_model* m, int64_t batch, int64_t ld, const float* q, const float* qd,
-                           const float* tau, const float* g_qdd, float* g_q, float* g_qd, float* g_tau,
-                           hipStream_t s) {
+                           const float* tau, const float* f_ext, const float* g_qdd, float* g_q, float* g_qd,
+                           float* g_tau, float* g_f_ext, hipStream_t s) {
   rbd_status st = check_batch(m, batch, ld, "rbd_fwd_dyn_vjp");
   if (st != RBD_OK) return st;
   if (batch > 0 && (!q || !qd || !tau || !g_qdd)) return fail(RBD_E_INVAL, "rbd_fwd_dyn_vjp: NULL input array");
   // the outputs hold intermediate values between the kernel's two sweeps
-  if (soa_overlap(g_q, m->nq, g_qd, m->nv, ld, batch) || soa_overlap(g_q, m->nq, g_tau, m->nv, ld, batch) ||
-      soa_overlap(g_qd, m->nv, g_tau, m->nv, ld, batch))
-    return fail(RBD_E_INVAL, "rbd_fwd_dyn_vjp: output arrays overlap");
-  for (const Arr& o : {Arr{g_q, m->nq}, Arr{g_qd, m->nv}, Arr{g_tau, m->nv}})
-    if (output_overlaps(o.p, o.rows, {{q, m->nq}, {qd, m->nv}, {tau, m->nv}, {g_qdd, m->nv}}, ld, batch))
+  const int64_t nf = 6 * (int64_t)m->n;
+  const Arr outs[4] = {{g_q, m->nq}, {g_qd, m->nv}, {g_tau, m->nv}, {g_f_ext, nf}};
+  for (int i = 0; i < 4; ++i)
+    for (int j = i + 1; j < 4; ++j)
+      if (soa_overlap(outs[i].p, outs[i].rows, outs[j].p, outs[j].rows, ld, batch))
+        return fail(RBD_E_INVAL, "rbd_fwd_dyn_vjp: output arrays overlap");
+  for (const Arr& o : outs)
+    if (output_overlaps(o.p, o.rows, {{q, m->nq}, {qd, m->nv}, {tau, m->nv}, {f_ext, nf}, {g_qdd, m->nv}}, ld, batch))
       return fail(RBD_E_INVAL, "rbd_fwd_dyn_vjp: an output overlaps an input");
   DeviceScope ds(m->device);
   if (ds.st != RBD_OK) return ds.st;
-  return launch_fwd_dyn_vjp(m, batch, ld, q, qd, tau, g_qdd, g_q, g_qd, g_tau, s);
+  return launch_fwd_dyn_vjp(m, batch, ld, q, qd, tau, f_ext, g_qdd, g_q, g_qd, g_tau, g_f_ext, s);
 }
 
 }  // extern "C"

@@ -22,7 +22,8 @@ static_assert(kOpFwdDyn == RBD_OP_FWD_DYN && kOpRnea == RBD_OP_RNEA && kOpFwdDyn
   void kernels_##name##_p4(const void**);                                                                    \
   void kernels_##name##_p5(const void**);                                                                    \
   void kernels_##name##_p6(const void**);                                                                    \
-  void kernels_##name##_p7(const void**);
+  void kernels_##name##_p7(const void**);                                                                    \
+  void kernels_##name##_p8(const void**);
 RBD_TOPOLOGIES(RBD_DECL)
 #undef RBD_DECL
 
@@ -40,7 +41,7 @@ using FillFn = void (*)(const void**);
 static const FillFn k_fill[][kParts] = {
 #define RBD_TAB(name, fr, ...)                                                                            \
   {&kernels_##name##_p1, &kernels_##name##_p2, &kernels_##name##_p3, &kernels_##name##_p4, \
-   &kernels_##name##_p5, &kernels_##name##_p6, &kernels_##name##_p7},
+   &kernels_##name##_p5, &kernels_##name##_p6, &kernels_##name##_p7, &kernels_##name##_p8},
     RBD_TOPOLOGIES(RBD_TAB)
 #undef RBD_TAB
 };
@@ -48,8 +49,8 @@ static const FillFn k_fill[][kParts] = {
 int n_topologies() { return (int)(sizeof(k_topos) / sizeof(k_topos[0])); }
 const TopoInfo& topology(int id) { return k_topos[id]; }
 
-// The kernel table of a compiled topology: its seven parts merged (built on
-// first use).
+// The kernel table of a compiled topology: its parts merged (built on first
+// use).
 const KernelSet* aot_kernels(int id) {
   static const std::vector<KernelSet> all = [] {
     std::vector<KernelSet> v(n_topologies());
@@ -198,28 +199,43 @@ rbd_status launch_aba(const rbd_model* m, int64_t batch, int64_t ld, const float
 }
 
 rbd_status launch_fwd_dyn_jvp(const rbd_model* m, int64_t batch, int64_t ld, const float* q, const float* qd,
-                              const float* tau, const float* dq, const float* dqd, const float* dtau, float* qdd,
-                              float* dqdd, hipStream_t s) {
+                              const float* tau, const float* fext, const float* dq, const float* dqd,
+                              const float* dtau, const float* dfext, float* qdd, float* dqdd, hipStream_t s) {
   if (batch == 0) return RBD_OK;
   const float* tab = m->d_tab;
-  void* a[] = {&tab, &batch, &ld, &q, &qd, &tau, &dq, &dqd, &dtau, &qdd, &dqdd};
-  return launch(m, KID_JVP, heavy_shape(batch), a, s, "rbd_fwd_dyn_jvp");
+  void* a[] = {&tab, &batch, &ld, &q, &qd, &tau, &dq, &dqd, &dtau, &qdd, &dqdd, &fext, &dfext};
+  return launch(m, (fext || dfext) ? KID_JVP_EXT : KID_JVP, heavy_shape(batch), a, s, "rbd_fwd_dyn_jvp");
 }
 
-rbd_status launch_diff_ik(const rbd_model* m, int64_t batch, int64_t ld, const float* q, const float* tgt,
+// The controller kernel of `frame`: the set's own for the last body, else one
+// compiled for that frame at run time on first use.
+static rbd_status launch_frame(const rbd_model* m, bool osc, int frame, Shape sh, void** args, hipStream_t s,
+                               const char* what) {
+  if (frame == m->n - 1) return launch(m, osc ? KID_OSC : KID_DIFF_IK, sh, args, s, what);
+  hipFunction_t f = nullptr;
+  const rbd_status st = jit_frame_function(m->floating, m->n, m->parent.data(), m->device, osc, frame, &f);
+  if (st != RBD_OK) return st;
+  hipError_t e = hipModuleLaunchKernel(f, sh.grid.x, sh.grid.y, sh.grid.z, sh.block.x, sh.block.y, sh.block.z, 0, s,
+                                       args, nullptr);
+  if (e == hipSuccess) e = hipGetLastError();
+  if (e != hipSuccess) return fail(RBD_E_LAUNCH, "%s: launch failed: %s", what, hipGetErrorString(e));
+  return RBD_OK;
+}
+
+rbd_status launch_diff_ik(const rbd_model* m, int64_t batch, int64_t ld, const float* q, int frame, const float* tgt,
                           float gain, float lam2, float* qd, hipStream_t s) {
   if (batch == 0) return RBD_OK;
   const float* tab = m->d_tab;
   void* a[] = {&tab, &batch, &ld, &q, &tgt, &gain, &lam2, &qd};
-  return launch(m, KID_DIFF_IK, plain_shape(batch), a, s, "rbd_diff_ik");
+  return launch_frame(m, false, frame, plain_shape(batch), a, s, "rbd_diff_ik");
 }
 
-rbd_status launch_osc(const rbd_model* m, int64_t batch, int64_t ld, const float* q, const float* qd,
+rbd_status launch_osc(const rbd_model* m, int64_t batch, int64_t ld, const float* q, const float* qd, int frame,
                       const float* tgt, float kp, float kd, float kn, float* tau, hipStream_t s) {
   if (batch == 0) return RBD_OK;
   const float* tab = m->d_tab;
   void* a[] = {&tab, &batch, &ld, &q, &qd, &tgt, &kp, &kd, &kn, &tau};
-  return launch(m, KID_OSC, heavy_shape(batch), a, s, "rbd_osc");
+  return launch_frame(m, true, frame, heavy_shape(batch), a, s, "rbd_osc");
 }
 
 // Between the solve and the adjoint sweep, q-double-dot and lam park in
@@ -227,15 +243,20 @@ rbd_status launch_osc(const rbd_model* m, int64_t batch, int64_t ld, const float
 // g_tau, or, for a large tree missing one of those, g_q shifted by nq - nv
 // rows, so that DoF k lands in the q slot of its own body (the adjoint reads a
 // body's entries in its forward step and writes that body's g_q in its
-// backward step).
+// backward step). With external forces they park in g_qd and g_tau or stay in
+// registers.
 rbd_status launch_fwd_dyn_vjp(const rbd_model* m, int64_t batch, int64_t ld, const float* q, const float* qd,
-                              const float* tau, const float* gqdd, float* gq, float* gqd, float* gtau,
-                              hipStream_t s) {
-  if (batch == 0 || (!gq && !gqd && !gtau)) return RBD_OK;
+                              const float* tau, const float* fext, const float* gqdd, float* gq, float* gqd,
+                              float* gtau, float* gfext, hipStream_t s) {
+  if (batch == 0 || (!gq && !gqd && !gtau && !gfext)) return RBD_OK;
   float* const gq_shift = gq ? gq + (int64_t)(m->nq - m->nv) * ld : nullptr;
   KernelId id;
   float *park_qdd = gqd, *park_lam = gtau;
-  if (gqd && gtau) {
+  // external forces matter to g_q and g_qd (through qdd) and the force
+  // cotangent; g_tau = M^-1 g_qdd does not depend on them
+  if (gfext || (fext && (gq || gqd))) {
+    id = (gqd && gtau) ? KID_VJP_EXT_PARK : KID_VJP_EXT_REGS;
+  } else if (gqd && gtau) {
     id = KID_VJP_PARK;
   } else if (large(m) && gq && (gqd || gtau)) {
     id = KID_VJP_PARK_GQ;
@@ -247,7 +268,7 @@ rbd_status launch_fwd_dyn_vjp(const rbd_model* m, int64_t batch, int64_t ld, con
     id = KID_VJP_TAU;
   }
   const float* tab = m->d_tab;
-  void* a[] = {&tab, &batch, &ld, &q, &qd, &tau, &gqdd, &gq, &gqd, &gtau, &park_qdd, &park_lam};
+  void* a[] = {&tab, &batch, &ld, &q, &qd, &tau, &gqdd, &gq, &gqd, &gtau, &park_qdd, &park_lam, &fext, &gfext};
   return launch(m, id, heavy_shape(batch), a, s, "rbd_fwd_dyn_vjp");
 }
 

@@ -35,6 +35,7 @@ struct rbd_model {
   bool floating = false;
   float* d_tab = nullptr;      // device tables (see rbd_lane.hpp)
   std::vector<float> h_tab;    // the tables of a host-only model (device -1)
+  std::vector<int32_t> parent; // topology (for run-time compiled per-frame kernels)
   size_t tab_floats = 0;
   uint64_t uid = 0;            // unique over the process (a new model never reuses one)
 };
@@ -72,7 +73,13 @@ const KernelSet* aot_kernels(int id);
 // its kernels on first use.
 rbd_status jit_kernels(bool floating, int n, const int32_t* parent, int device, const KernelSet** out);
 rbd_status jit_function(const KernelSet* ks, KernelId id, hipFunction_t* out);
-// Compiles kernel `kernel` of the topology (-1: every kernel) into the cache
+// The differential-IK (osc = false) or operational-space-control kernel of
+// one frame, compiled at run time for frames other than the last body (any
+// topology), loaded once per device.
+rbd_status jit_frame_function(bool floating, int n, const int32_t* parent, int device, bool osc, int frame,
+                              hipFunction_t* out);
+// Compiles kernel `kernel` of the topology (-1: every kernel of the list;
+// KID_COUNT + 2 f (+1): the diff-IK (OSC) kernel of frame f) into the cache
 // directory (NULL: the default one); needs no device.
 rbd_status jit_precompile(bool floating, int n, const int32_t* parent, const char* cache_dir, int kernel);
 
@@ -88,15 +95,15 @@ rbd_status launch_fwd_dyn(const rbd_model* m, int64_t batch, int64_t ld, const f
 rbd_status launch_aba(const rbd_model* m, int64_t batch, int64_t ld, const float* q, const float* qd,
                       const float* tau, const float* fext, float* qdd, hipStream_t s);
 rbd_status launch_fwd_dyn_jvp(const rbd_model* m, int64_t batch, int64_t ld, const float* q, const float* qd,
-                              const float* tau, const float* dq, const float* dqd, const float* dtau, float* qdd,
-                              float* dqdd, hipStream_t s);
-rbd_status launch_diff_ik(const rbd_model* m, int64_t batch, int64_t ld, const float* q, const float* tgt,
+                              const float* tau, const float* fext, const float* dq, const float* dqd,
+                              const float* dtau, const float* dfext, float* qdd, float* dqdd, hipStream_t s);
+rbd_status launch_diff_ik(const rbd_model* m, int64_t batch, int64_t ld, const float* q, int frame, const float* tgt,
                           float gain, float lam2, float* qd, hipStream_t s);
-rbd_status launch_osc(const rbd_model* m, int64_t batch, int64_t ld, const float* q, const float* qd,
+rbd_status launch_osc(const rbd_model* m, int64_t batch, int64_t ld, const float* q, const float* qd, int frame,
                       const float* tgt, float kp, float kd, float kn, float* tau, hipStream_t s);
 rbd_status launch_fwd_dyn_vjp(const rbd_model* m, int64_t batch, int64_t ld, const float* q, const float* qd,
-                              const float* tau, const float* gqdd, float* gq, float* gqd, float* gtau,
-                              hipStream_t s);
+                              const float* tau, const float* fext, const float* gqdd, float* gq, float* gqd,
+                              float* gtau, float* gfext, hipStream_t s);
 
 
 // Packed serving launch of one (model, op): d_table holds a PackedHdr-led

@@ -68,6 +68,15 @@ std::string program_source(const std::string& topo) {
          ">;\nstatic_assert(TP::depth_first(), \"topology is not depth-first\");\n";
 }
 
+// The kernel expression of kernel `kid`: one of the topology's kernel list, or,
+// from KID_COUNT on, the controller kernels of one frame: KID_COUNT + 2 f is
+// differential IK for body f, KID_COUNT + 2 f + 1 operational-space control.
+std::string kernel_expr(int kid) {
+  if (kid < KID_COUNT) return kKernelExpr[kid];
+  const int f = (kid - KID_COUNT) / 2;
+  return std::string((kid - KID_COUNT) % 2 ? "rbd::k_osc<TP, " : "rbd::k_diff_ik<TP, ") + std::to_string(f) + ">";
+}
+
 // Hash of everything that determines a kernel's code object.
 uint64_t kernel_key(const std::string& src, int kid) {
   uint64_t h = 1469598103934665603ull;
@@ -77,7 +86,7 @@ uint64_t kernel_key(const std::string& src, int kid) {
   }
   for (int i = 0; i < kNumOptions; ++i) h = fnv1a(h, std::string(kOptions[i]));
   h = fnv1a(h, src);
-  return fnv1a(h, std::string(kKernelExpr[kid]));
+  return fnv1a(h, kernel_expr(kid));
 }
 
 bool make_dirs(const std::string& d) {
@@ -178,7 +187,8 @@ bool compile(const std::string& src, int kid, CodeObject& out, std::string& err)
     err = "hiprtcCreateProgram failed";
     return false;
   }
-  bool ok = hiprtcAddNameExpression(p, kKernelExpr[kid]) == HIPRTC_SUCCESS;
+  const std::string expr = kernel_expr(kid);
+  bool ok = hiprtcAddNameExpression(p, expr.c_str()) == HIPRTC_SUCCESS;
   const hiprtcResult r = ok ? hiprtcCompileProgram(p, kNumOptions, kOptions) : HIPRTC_ERROR_INVALID_INPUT;
   if (r != HIPRTC_SUCCESS) {
     size_t n = 0;
@@ -189,7 +199,7 @@ bool compile(const std::string& src, int kid, CodeObject& out, std::string& err)
     ok = false;
   }
   const char* lowered = nullptr;
-  if (ok && (hiprtcGetLoweredName(p, kKernelExpr[kid], &lowered) != HIPRTC_SUCCESS || !lowered)) {
+  if (ok && (hiprtcGetLoweredName(p, expr.c_str(), &lowered) != HIPRTC_SUCCESS || !lowered)) {
     err = "no lowered name";
     ok = false;
   }
@@ -225,7 +235,7 @@ rbd_status code_object(const std::string& src, int kid, const CacheDirs& dirs, C
     }
   std::string err;
   if (!compile(src, kid, out, err))
-    return fail(RBD_E_COMPILE, "run-time compilation of %s failed: %s", kKernelExpr[kid], err.c_str());
+    return fail(RBD_E_COMPILE, "run-time compilation of %s failed: %s", kernel_expr(kid).c_str(), err.c_str());
   write_cached(dirs.write, file, out);
   return RBD_OK;
 }
@@ -235,6 +245,7 @@ struct JitTopo {
   std::string src;
   std::string name;
   std::map<int, std::unique_ptr<KernelSet>> per_device;
+  std::map<std::pair<int, int>, hipFunction_t> frame_fn;  // (device, kid >= KID_COUNT)
 };
 
 std::mutex g_reg_mu;
@@ -243,24 +254,44 @@ std::map<std::string, std::unique_ptr<JitTopo>>& registry() {
   return *r;
 }
 
+// The run-time state of a topology (created on first use, alive until exit).
+JitTopo* jit_topo(bool floating, int n, const int32_t* parent) {
+  const std::string topo = topology_text(floating, n, parent);
+  std::lock_guard<std::mutex> g(g_reg_mu);
+  std::unique_ptr<JitTopo>& slot = registry()[topo];
+  if (!slot) {
+    slot.reset(new JitTopo);
+    char name[48];
+    std::snprintf(name, sizeof(name), "jit_%d%s_%08llx", n, floating ? "f" : "",
+                  (unsigned long long)(fnv1a(1469598103934665603ull, topo) & 0xffffffffull));
+    slot->name = name;
+    slot->src = program_source(topo);
+  }
+  return slot.get();
+}
+
+// Compiles (or reads) and loads kernel kid of jt on `device`.
+rbd_status load_function(JitTopo* jt, int kid, int device, hipFunction_t* out) {
+  CodeObject co;
+  const rbd_status st = code_object(jt->src, kid, cache_dirs(nullptr), co);
+  if (st != RBD_OK) return st;
+  int cur = -1;
+  if (hipGetDevice(&cur) != hipSuccess || (cur != device && hipSetDevice(device) != hipSuccess))
+    return fail(RBD_E_NODEVICE, "cannot select device %d", device);
+  hipModule_t mod = nullptr;
+  hipError_t e = hipModuleLoadData(&mod, co.code.data());
+  if (e == hipSuccess) e = hipModuleGetFunction(out, mod, co.name.c_str());
+  if (cur != device) (void)hipSetDevice(cur);
+  if (e != hipSuccess)
+    return fail(RBD_E_LAUNCH, "loading the compiled kernel %s failed: %s", kernel_expr(kid).c_str(),
+                hipGetErrorString(e));
+  return RBD_OK;
+}
+
 }  // namespace
 
 rbd_status jit_kernels(bool floating, int n, const int32_t* parent, int device, const KernelSet** out) {
-  const std::string topo = topology_text(floating, n, parent);
-  JitTopo* jt;
-  {
-    std::lock_guard<std::mutex> g(g_reg_mu);
-    std::unique_ptr<JitTopo>& slot = registry()[topo];
-    if (!slot) {
-      slot.reset(new JitTopo);
-      char name[48];
-      std::snprintf(name, sizeof(name), "jit_%d%s_%08llx", n, floating ? "f" : "",
-                    (unsigned long long)(fnv1a(1469598103934665603ull, topo) & 0xffffffffull));
-      slot->name = name;
-      slot->src = program_source(topo);
-    }
-    jt = slot.get();
-  }
+  JitTopo* jt = jit_topo(floating, n, parent);
   std::lock_guard<std::mutex> g(jt->mu);
   std::unique_ptr<KernelSet>& ks = jt->per_device[device];
   if (!ks) {
@@ -284,20 +315,28 @@ rbd_status jit_function(const KernelSet* ks, KernelId id, hipFunction_t* out) {
   std::lock_guard<std::mutex> g(jt->mu);
   f = ks->jit[id].load(std::memory_order_acquire);
   if (!f) {
-    CodeObject co;
-    const rbd_status st = code_object(jt->src, id, cache_dirs(nullptr), co);
+    const rbd_status st = load_function(jt, id, ks->device, &f);
     if (st != RBD_OK) return st;
-    int cur = -1;
-    if (hipGetDevice(&cur) != hipSuccess || (cur != ks->device && hipSetDevice(ks->device) != hipSuccess))
-      return fail(RBD_E_NODEVICE, "cannot select device %d", ks->device);
-    hipModule_t mod = nullptr;
-    hipError_t e = hipModuleLoadData(&mod, co.code.data());
-    if (e == hipSuccess) e = hipModuleGetFunction(&f, mod, co.name.c_str());
-    if (cur != ks->device) (void)hipSetDevice(cur);
-    if (e != hipSuccess)
-      return fail(RBD_E_LAUNCH, "loading the compiled kernel %s failed: %s", kKernelExpr[id], hipGetErrorString(e));
     ks->jit[id].store(f, std::memory_order_release);
   }
+  *out = f;
+  return RBD_OK;
+}
+
+rbd_status jit_frame_function(bool floating, int n, const int32_t* parent, int device, bool osc, int frame,
+                              hipFunction_t* out) {
+  JitTopo* jt = jit_topo(floating, n, parent);
+  const int kid = KID_COUNT + 2 * frame + (osc ? 1 : 0);
+  std::lock_guard<std::mutex> g(jt->mu);
+  auto it = jt->frame_fn.find({device, kid});
+  if (it != jt->frame_fn.end()) {
+    *out = it->second;
+    return RBD_OK;
+  }
+  hipFunction_t f = nullptr;
+  const rbd_status st = load_function(jt, kid, device, &f);
+  if (st != RBD_OK) return st;
+  jt->frame_fn[{device, kid}] = f;
   *out = f;
   return RBD_OK;
 }
@@ -310,6 +349,10 @@ rbd_status jit_precompile(bool floating, int n, const int32_t* parent, const cha
     CodeObject co;
     const rbd_status st = code_object(src, k, dirs, co);
     if (st != RBD_OK) return st;
+  }
+  if (kernel >= KID_COUNT) {  // a frame's controller kernel
+    CodeObject co;
+    return code_object(src, kernel, dirs, co);
   }
   return RBD_OK;
 }

@@ -1,5 +1,5 @@
 // Kernels of one compiled topology. Built once per entry of RBD_TOPOLOGIES
-// and part (-DRBD_TOPO=<name> -DRBD_PART=1..7), so they compile in parallel.
+// and part (-DRBD_TOPO=<name> -DRBD_PART=1..8), so they compile in parallel.
 // The part's function stores the address of each of its kernels in its slot
 // of the topology's kernel table.
 #include <hip/hip_runtime.h>
@@ -9,7 +9,7 @@
 #include "rbd_topologies.hpp"
 
 #if !defined(RBD_TOPO) || !defined(RBD_PART)
-#error "RBD_TOPO must name a topology and RBD_PART a part (1..7)"
+#error "RBD_TOPO must name a topology and RBD_PART a part (1..8)"
 #endif
 
 #define RBD_CAT2(a, b) a##b

@@ -6,7 +6,7 @@
 // matrix; 2 forward dynamics and the packed forward / inverse dynamics
 // launches; 3 the adjoint and its packed launch; 4 the articulated-body
 // algorithm; 5 the external-force variants; 6 the forward-mode derivative;
-// 7 the controllers.
+// 7 the controllers; 8 the derivatives with external forces.
 #pragma once
 
 #define RBD_KERNELS(X)                                    \
@@ -36,7 +36,10 @@
   X(KID_ABA_PRE_EXT, 5, k_aba<TP, true, true>)            \
   X(KID_JVP, 6, k_fwd_dyn_jvp<TP>)                        \
   X(KID_DIFF_IK, 7, k_diff_ik<TP>)                        \
-  X(KID_OSC, 7, k_osc<TP>)
+  X(KID_OSC, 7, k_osc<TP>)                                \
+  X(KID_VJP_EXT_REGS, 8, k_fwd_dyn_vjp<TP, 1, true>)      \
+  X(KID_VJP_EXT_PARK, 8, k_fwd_dyn_vjp<TP, 2, true>)      \
+  X(KID_JVP_EXT, 8, k_fwd_dyn_jvp<TP, true>)
 
 namespace rbd {
 
@@ -47,6 +50,6 @@ enum KernelId : int {
   KID_COUNT
 };
 
-constexpr int kParts = 7;
+constexpr int kParts = 8;
 
 }  // namespace rbd

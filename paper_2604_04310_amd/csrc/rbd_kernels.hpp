@@ -241,29 +241,29 @@ struct SinkTwo {
   }
 };
 
-template <class TP, bool ADJ, class QI, class X, class GQ, class GQD, class GT>
+template <class TP, bool ADJ, class QI, class X, class GQ, class GQD, class GT, class FX = NoFext, class GF = NoGF>
 RBD_DI void vjp_lane(const float* __restrict__ tab, const QI& q, const X& qd, const X& tau, const X& gqdd,
-                     const GQ& gq, const GQD& gqd, const GT& gtau) {
+                     const GQ& gq, const GQD& gqd, const GT& gtau, const FX& fx = FX{}, const GF& gf = GF{}) {
   constexpr int NV = TP::NV;
   float qddv[NV], lam[NV];
-  fwd_dyn_lane<TP, 2>(tab, q, qd, RhsTwo<X>{tau, gqdd}, SinkRegs{qddv, lam});
+  fwd_dyn_lane<TP, 2>(tab, q, qd, RhsTwo<X>{tau, gqdd}, SinkRegs{qddv, lam}, fx);
   sfor<0, NV>([&](auto K_) __attribute__((always_inline)) {
     constexpr int K = decltype(K_)::value;
     gtau(K, lam[K]);
   });
-  if constexpr (ADJ) id_adjoint_lane<TP>(tab, q, qd, RegView{qddv}, RegView{lam}, gq, gqd);
+  if constexpr (ADJ) id_adjoint_lane<TP>(tab, q, qd, RegView{qddv}, RegView{lam}, gq, gqd, fx, gf);
 }
 
 // q-double-dot parked in g_qd and lam in g_tau between the solve and the
 // adjoint sweep, instead of 2 nv registers held across it. Every element is
 // read by its body's forward step before that body's backward step
 // overwrites g_qd.
-template <class TP, class QI, class X, class GQ, class P>
+template <class TP, class QI, class X, class GQ, class P, class FX = NoFext, class GF = NoGF>
 RBD_DI void vjp_lane_parked(const float* __restrict__ tab, const QI& q, const X& qd, const X& tau, const X& gqdd,
                             const GQ& gq, const P& gqd_out, const P& gtau_out, const typename P::In& gqd_in,
-                            const typename P::In& gtau_in) {
-  fwd_dyn_lane<TP, 2>(tab, q, qd, RhsTwo<X>{tau, gqdd}, SinkTwo<P>{gqd_out, gtau_out});
-  id_adjoint_lane<TP>(tab, q, qd, gqd_in, gtau_in, gq, gqd_out);
+                            const typename P::In& gtau_in, const FX& fx = FX{}, const GF& gf = GF{}) {
+  fwd_dyn_lane<TP, 2>(tab, q, qd, RhsTwo<X>{tau, gqdd}, SinkTwo<P>{gqd_out, gtau_out}, fx);
+  id_adjoint_lane<TP>(tab, q, qd, gqd_in, gtau_in, gq, gqd_out, fx, gf);
 }
 
 struct RowAlias {
@@ -278,19 +278,43 @@ struct RowAlias {
 // MODE 0: g_tau only; 1: adjoint with q-double-dot and lam in registers (some
 // output absent); 2: adjoint with both parked in g_qd and g_tau (passed again
 // as park_qdd and park_lam); 3 (large trees): as 2, parked where the launcher
-// chooses, g_qd optional.
-template <class TP, int MODE>
+// chooses, g_qd optional. EXT (modes 1 and 2): external forces fext
+// (nullable: zero) in the dynamics and the force cotangent g_fext (nullable).
+template <class TP, int MODE, bool EXT = false>
 __global__ __launch_bounds__(kBlock) void k_fwd_dyn_vjp(const float* __restrict__ tab, int64_t batch, int64_t ld,
                                                         const float* __restrict__ q, const float* __restrict__ qd,
                                                         const float* __restrict__ tau,
                                                         const float* __restrict__ gqdd, float* gq, float* gqd,
-                                                        float* gtau, float* park_qdd, float* park_lam) {
+                                                        float* gtau, float* park_qdd, float* park_lam,
+                                                        const float* __restrict__ fext, float* gfext) {
+  static_assert(!EXT || MODE == 1 || MODE == 2, "external forces: modes 1 and 2");
   RBD_LANE_IO(TP);
   const uint32_t b = lane_id();
   if (b >= batch) return;
   const In qi{q, ld, b}, qdi{qd, ld, b}, ti{tau, ld, b}, gi{gqdd, ld, b};
   const OutOpt<OutAlias> gqo{OutAlias{gq, ld, b}, gq != nullptr};
-  if constexpr (MODE >= 2 && TP::NV > 16) {
+  if constexpr (EXT) {
+    const FextOpt fx{{fext, ld, b}};
+    const GFOut gf{{gfext, ld, b}};
+    if constexpr (MODE == 2) {
+      const OutAliasP pd{{gqd, ld, b}}, pt{{gtau, ld, b}};
+      if constexpr (TP::NV > 16) {
+        // fresh views for the second sweep (as below)
+        fwd_dyn_lane<TP, 2>(tab, qi, qdi, RhsTwo<In>{ti, gi}, SinkTwo<OutAliasP>{pd, pt}, fx);
+        sweep_boundary();
+        const int64_t l2 = opaque(ld);
+        const OutOpt<OutAlias> gqo2{OutAlias{gq, l2, b}, gq != nullptr};
+        id_adjoint_lane<TP>(opaque(tab), In{opaque(q), l2, b}, In{opaque(qd), l2, b}, InAlias{gqd, l2, b},
+                            InAlias{gtau, l2, b}, gqo2, OutAlias{gqd, l2, b}, FextOpt{{opaque(fext), l2, b}},
+                            GFOut{{gfext, l2, b}});
+      } else {
+        vjp_lane_parked<TP>(tab, qi, qdi, ti, gi, gqo, pd, pt, InAlias{gqd, ld, b}, InAlias{gtau, ld, b}, fx, gf);
+      }
+    } else {
+      vjp_lane<TP, true>(tab, qi, qdi, ti, gi, gqo, OutOpt<OutAlias>{OutAlias{gqd, ld, b}, gqd != nullptr},
+                         OutOpt<OutAlias>{OutAlias{gtau, ld, b}, gtau != nullptr}, fx, gf);
+    }
+  } else if constexpr (MODE >= 2 && TP::NV > 16) {
     // the two sweeps of vjp_lane_parked, the second on fresh views (its own
     // table and input pointers and row stride): a large tree's first sweep
     // uses every register, and values kept for the second one spill
@@ -326,18 +350,25 @@ __global__ __launch_bounds__(kBlock) void k_fwd_dyn_vjp(const float* __restrict_
 // place (each right-hand-side entry is read when its subtree closes, every
 // result written after the sweep). Neither output is restrict-qualified, so
 // loads of parked values stay ordered with the stores.
-template <class TP>
+// EXT: external forces fext and their tangent dfext (each nullable: zero).
+template <class TP, bool EXT = false>
 __global__ __launch_bounds__(kBlock) void k_fwd_dyn_jvp(const float* __restrict__ tab, int64_t batch, int64_t ld,
                                                         const float* __restrict__ q, const float* __restrict__ qd,
                                                         const float* __restrict__ tau, const float* __restrict__ dq,
                                                         const float* __restrict__ dqd,
-                                                        const float* __restrict__ dtau, float* qdd, float* dqdd) {
+                                                        const float* __restrict__ dtau, float* qdd, float* dqdd,
+                                                        const float* __restrict__ fext,
+                                                        const float* __restrict__ dfext) {
   RBD_LANE_IO(TP);
   const uint32_t b = lane_id();
   if (b >= batch) return;
   float* park = qdd ? qdd : dqdd;
+  auto fx_view = [&](const float* p, int64_t l) __attribute__((always_inline)) {
+    if constexpr (EXT) return FextOpt{{p, l, b}};
+    else return NoFext{};
+  };
   fwd_dyn_lane<TP, 1>(tab, In{q, ld, b}, In{qd, ld, b}, RhsOne<In>{In{tau, ld, b}},
-                      SinkOne<OutAlias>{OutAlias{park, ld, b}});
+                      SinkOne<OutAlias>{OutAlias{park, ld, b}}, fx_view(fext, ld));
   // a large tree gives each sweep fresh views (see k_fwd_dyn_vjp)
   constexpr bool kFresh = TP::NV > 16;
   auto view = [](auto x) __attribute__((always_inline)) {
@@ -346,28 +377,30 @@ __global__ __launch_bounds__(kBlock) void k_fwd_dyn_jvp(const float* __restrict_
   };
   const int64_t ld2 = view(ld);
   id_tangent_lane<TP>(view(tab), In{view(q), ld2, b}, In{view(qd), ld2, b}, InAlias{park, ld2, b},
-                      In{dq, ld2, b}, In{dqd, ld2, b}, In{dtau, ld2, b}, OutAlias{dqdd, ld2, b});
+                      In{dq, ld2, b}, In{dqd, ld2, b}, In{dtau, ld2, b}, OutAlias{dqdd, ld2, b},
+                      fx_view(fext, ld2), fx_view(dfext, ld2));
   const int64_t ld3 = view(ld2);
   fwd_dyn_lane<TP, 1, In, In, RhsOne<InAlias>, SinkOne<OutAlias>, NoFext, false>(
       view(tab), In{view(q), ld3, b}, In{qd, ld3, b}, RhsOne<InAlias>{InAlias{dqdd, ld3, b}},
       SinkOne<OutAlias>{OutAlias{dqdd, ld3, b}});
 }
 
-// ---- controller workloads for the end effector E = the last body (a leaf).
-template <class TP>
+// ---- controller workloads for one frame E: the last body (a leaf) ahead of
+// time, any other body compiled at run time on its first use.
+template <class TP, int E = TP::N - 1>
 __global__ __launch_bounds__(kBlock) void k_diff_ik(const float* __restrict__ tab, int64_t batch, int64_t ld,
                                                     const float* __restrict__ q, const float* __restrict__ tgt,
                                                     float gain, float lam2, float* __restrict__ qd) {
   RBD_LANE_IO(TP);
   const uint32_t b = lane_id();
   if (b >= batch) return;
-  diff_ik_lane<TP, TP::N - 1>(tab, In{q, ld, b}, In{tgt, ld, b}, gain, lam2, Out{qd, ld, b});
+  diff_ik_lane<TP, E>(tab, In{q, ld, b}, In{tgt, ld, b}, gain, lam2, Out{qd, ld, b});
 }
 
 // Inputs are loaded where they are used: preloading them (as k_fwd_dyn does
 // for large trees) held 83 more registers across a sweep that already spills,
 // and measured 99 us against 81 us for the humanoid at batch 65536.
-template <class TP>
+template <class TP, int E = TP::N - 1>
 __global__ __launch_bounds__(kBlock) void k_osc(const float* __restrict__ tab, int64_t batch, int64_t ld,
                                                 const float* __restrict__ q, const float* __restrict__ qd,
                                                 const float* __restrict__ tgt, float kp, float kd, float kn,
@@ -375,7 +408,7 @@ __global__ __launch_bounds__(kBlock) void k_osc(const float* __restrict__ tab, i
   RBD_LANE_IO(TP);
   const uint32_t b = lane_id();
   if (b >= batch) return;
-  osc_lane<TP, TP::N - 1>(tab, In{q, ld, b}, In{qd, ld, b}, In{tgt, ld, b}, kp, kd, kn, Out{tau, ld, b});
+  osc_lane<TP, E>(tab, In{q, ld, b}, In{qd, ld, b}, In{tgt, ld, b}, kp, kd, kn, Out{tau, ld, b});
 }
 
 // ---- packed launch for the serving runtime. One launch serves many requests

@@ -425,6 +425,25 @@ struct NoFext {
 struct FextIn : In {
   static constexpr bool kOn = true;
 };
+// Forces that may be absent as a whole (a null array reads as zero): the
+// inputs of the derivative kernels, where the force cotangent or tangent is
+// wanted with or without forces.
+struct FextOpt : In {
+  static constexpr bool kOn = true;
+  RBD_DI float operator()(int c) const { return base ? In::operator()(c) : 0.0f; }
+};
+// The force cotangent output of the adjoint (g_F_i = J_i lam as [v_O; w], the
+// twist of body i in world axes at the world origin), or none.
+struct NoGF {
+  static constexpr bool kOn = false;
+  RBD_DI void operator()(int, float) const {}
+};
+struct GFOut : Out {
+  static constexpr bool kOn = true;
+  RBD_DI void operator()(int c, float v) const {
+    if (base) Out::operator()(c, v);
+  }
+};
 
 // World pose of body I's joint-aligned frame from its parent's (Rw, pw) and
 // the joint rotation RI (the base rotation for a free base).
@@ -920,10 +939,23 @@ RBD_DI void fwd_dyn_lane(const float* __restrict__ t, const QI& q, const QDI& qd
 // A free base contributes only through gravity a_0 = R^T (-g), whose
 // quaternion derivative follows the normalised Hamilton rotation; its position
 // does not enter body-frame dynamics.
-template <class TP, class QI, class QDI, class QDDI, class DQI, class DQDI, class DTI, class OUT>
+//
+// External forces F_i (fixed in the world, tangent dF_i) enter as -F_i in
+// body i's force balance; in body coordinates F_i moves with the body, so
+// with eta_i = X eta_parent + S dq_i the body's pose tangent (a free base
+// starts from [dtheta; R^T dp], dtheta = 2 vec(conj(quat) (x) dquat) / |quat|^2),
+// the body-frame force changes by -eta_i x* F_i plus dF_i in body coordinates.
+template <class TP, class QI, class QDI, class QDDI, class DQI, class DQDI, class DTI, class OUT, class FX = NoFext,
+          class DFX = NoFext>
 RBD_DI void id_tangent_lane(const float* __restrict__ t, const QI& q, const QDI& qd, const QDDI& qdd,
-                            const DQI& dq, const DQDI& dqd, const DTI& dtau, const OUT& out) {
+                            const DQI& dq, const DQDI& dqd, const DTI& dtau, const OUT& out, const FX& fx = FX{},
+                            const DFX& dfx = DFX{}) {
   constexpr int N = TP::N;
+  constexpr bool kExt = FX::kOn || DFX::kOn;
+  constexpr int NE = kExt ? N : 1;
+  M3 Rw[NE];
+  V3 pw[NE];
+  Mot eta[NE];
   M3 R[N];
   Mot v[N], a[N], dv[N], da[N];
   Frc f[N], df[N];
@@ -1028,6 +1060,27 @@ RBD_DI void id_tangent_lane(const float* __restrict__ t, const QI& q, const QDI&
     const Frc Iv = imul(Ib, v[I]);
     f[I] = imul(Ib, a[I]) + crf(v[I], Iv);
     df[I] = imul(Ib, da[I]) + crf(dv[I], Iv) + crf(v[I], imul(Ib, dv[I]));
+    if constexpr (kExt) {
+      world_pose<TP, I>(t, q, R[I], Rw, pw);
+      if constexpr (TP::free_body(I)) {
+        const float w = q(3), x = q(4), y = q(5), z = q(6);
+        const float dw = dq(3), dx = dq(4), dy = dq(5), dz = dq(6);
+        const float s2 = 2.0f * frcp(w * w + x * x + y * y + z * z);
+        // vec(conj(quat) (x) dquat) = w du - dw u - u x du
+        const V3 u = {x, y, z}, du = {dx, dy, dz};
+        const V3 th = s2 * (w * du - dw * u - cross(u, du));
+        eta[I] = {th, mulT(R[I], V3{dq(0), dq(1), dq(2)})};
+      } else {
+        constexpr int P = TP::parent(I);
+        if constexpr (P < 0) eta[I] = {{0.0f, 0.0f, 0.0f}, {0.0f, 0.0f, 0.0f}};
+        else eta[I] = xmot(R[I], load_r<I>(t), eta[P]);
+        eta[I].w.z = eta[I].w.z + dq(cidx<TP::qofs(I)>);
+      }
+      const Frc fe = fext_body<I>(fx, Rw[I], pw[I]);
+      const Frc dfe = fext_body<I>(dfx, Rw[I], pw[I]) - crf(eta[I], fe);
+      f[I] = f[I] - fe;
+      df[I] = df[I] - dfe;
+    }
     close_subtrees<TP, I, I>(backward);
   });
 }
@@ -1047,10 +1100,27 @@ RBD_DI void id_tangent_lane(const float* __restrict__ t, const QI& q, const QDI&
 //   dqd_i = S^T vbar - S^T (v x* abar).
 // For a free base only gravity a_0 = R^T (-g) depends on q (through the
 // quaternion); its position never enters body-frame dynamics.
-template <class TP, class QI, class QDI, class QDD, class LAM, class GQ, class GQD>
+//
+// External forces F_i (world axes, fixed in the world) add ID_ext(q) = -sum_i
+// J_i^T F_i. With mu_i the twist of body i under joint rates lam (as above),
+// lam^T ID_ext = -sum_i <mu_i, F_i>; its q-derivative at revolute joint k is
+//   -<S_k, Wsub_k - (X mu_parent) x* Fsub_k>,  Wsub_k = sum_{i in sub(k)} mu_i x* F_i,
+// Fsub_k = sum_{i in sub(k)} F_i (both carried up the tree like forces), since
+// turning joint k moves every F_i of its subtree in frame k by -(S dq) x* and
+// the part of mu_i below k with it. A free base moved by [dtheta; R^T dp]
+// (body frame) changes every F_i by -[dtheta; R^T dp] x* F_i, so the position
+// gets R Wsub_0.f and the quaternion Wsub_0.n . dtheta/dquat. (ID_0, the
+// dynamics without forces, is differentiated as above with forces excluded.)
+// The force cotangent g_F_i = J_i lam is mu_i in world axes at the world origin.
+template <class TP, class QI, class QDI, class QDD, class LAM, class GQ, class GQD, class FX = NoFext, class GF = NoGF>
 RBD_DI void id_adjoint_lane(const float* __restrict__ t, const QI& q, const QDI& qd, const QDD& qdd, const LAM& lam,
-                            const GQ& gq, const GQD& gqd) {
+                            const GQ& gq, const GQD& gqd, const FX& fx = FX{}, const GF& gf = GF{}) {
   constexpr int N = TP::N;
+  constexpr bool kExt = FX::kOn, kW = FX::kOn || GF::kOn;
+  constexpr int NE = kExt ? N : 1, NW = kW ? N : 1;
+  M3 Rw[NW];
+  V3 pw[NW];
+  Frc Fs[NE], Ws[NE];  // subtree sums of F_i and of mu_i x* F_i, in body coordinates
   // Only (cos q, sin q) of a body is kept between its forward and backward
   // step; R is rebuilt when needed, which keeps the live root path small.
   float cq[N], sq[N];
@@ -1082,11 +1152,21 @@ RBD_DI void id_adjoint_lane(const float* __restrict__ t, const QI& q, const QDI&
       const float dy = -2.0f * y * gA + 2.0f * g.y * uA + 2.0f * gu * A.y + 2.0f * w * axg.y;
       const float dz = -2.0f * z * gA + 2.0f * g.z * uA + 2.0f * gu * A.z + 2.0f * w * axg.z;
       // dPhi/dquat_k = -(g^T dN/dquat_k abar - 2 quat_k g^T R abar) / |quat|^2; output -dPhi
-      gq(0, 0.0f); gq(1, 0.0f); gq(2, 0.0f);
-      gq(3, (dw - 2.0f * w * gRA) * s);
-      gq(4, (dx - 2.0f * x * gRA) * s);
-      gq(5, (dy - 2.0f * y * gRA) * s);
-      gq(6, (dz - 2.0f * z * gRA) * s);
+      float g4[4] = {(dw - 2.0f * w * gRA) * s, (dx - 2.0f * x * gRA) * s, (dy - 2.0f * y * gRA) * s,
+                     (dz - 2.0f * z * gRA) * s};
+      V3 gp = {0.0f, 0.0f, 0.0f};
+      if constexpr (kExt) {
+        // position: R Wsub_0.f; quaternion: Wsub_0.n . (2 / |quat|^2) vec(conj(quat) (x) e_k)
+        gp = mul(R0, Ws[J].f);
+        const V3 n = Ws[J].n;
+        const float s2 = 2.0f * s;
+        g4[0] = __builtin_fmaf(s2, -x * n.x - y * n.y - z * n.z, g4[0]);
+        g4[1] = __builtin_fmaf(s2, w * n.x - z * n.y + y * n.z, g4[1]);
+        g4[2] = __builtin_fmaf(s2, z * n.x + w * n.y - x * n.z, g4[2]);
+        g4[3] = __builtin_fmaf(s2, -y * n.x + x * n.y + w * n.z, g4[3]);
+      }
+      gq(0, gp.x); gq(1, gp.y); gq(2, gp.z);
+      gq(3, g4[0]); gq(4, g4[1]); gq(5, g4[2]); gq(6, g4[3]);
     } else {
       const float w = qd(cidx<TP::vofs(J)>);
       // (S qd) x* abar = w [(-n_y, n_x, 0); (-f_y, f_x, 0)]
@@ -1100,6 +1180,12 @@ RBD_DI void id_adjoint_lane(const float* __restrict__ t, const QI& q, const QDI&
       // <vbar, -S x (X v_p)>: (X v_p) has the x, y parts of v
       float dq = vbar.n.x * v[J].w.y - vbar.n.y * v[J].w.x + vbar.f.x * v[J].v.y - vbar.f.y * v[J].v.x;
       dq = dq + abar.n.x * ap[J][1] - abar.n.y * ap[J][0] + abar.f.x * ap[J][3] - abar.f.y * ap[J][2];
+      float dq_ext = 0.0f;
+      if constexpr (kExt) {
+        // <S, Wsub - (X mu_p) x* Fsub>: (X mu_p) has the x, y parts of mu
+        const Frc& Fsj = Fs[J];
+        dq_ext = Ws[J].n.z - (mu[J].w.x * Fsj.n.y - mu[J].w.y * Fsj.n.x + mu[J].v.x * Fsj.f.y - mu[J].v.y * Fsj.f.x);
+      }
       if constexpr (P >= 0) {
         // <X mu_p, S x* f>: (X mu_p) has the x, y parts of mu
         dq = dq - mu[J].w.x * f[J].n.y + mu[J].w.y * f[J].n.x - mu[J].v.x * f[J].f.y + mu[J].v.y * f[J].f.x;
@@ -1108,8 +1194,12 @@ RBD_DI void id_adjoint_lane(const float* __restrict__ t, const QI& q, const QDI&
         xfrc_acc(RJ, r, f[J], f[P]);
         xfrc_acc(RJ, r, abar, ab[P]);
         xfrc_acc(RJ, r, vbar, vb[P]);
+        if constexpr (kExt) {
+          xfrc_acc(RJ, r, Fs[J], Fs[P]);
+          xfrc_acc(RJ, r, Ws[J], Ws[P]);
+        }
       }
-      gq(cidx<TP::qofs(J)>, -dq);
+      gq(cidx<TP::qofs(J)>, dq_ext - dq);
     }
   };
 
@@ -1150,6 +1240,21 @@ RBD_DI void id_adjoint_lane(const float* __restrict__ t, const QI& q, const QDI&
     f[I] = imul(Ib, a[I]) + crf(v[I], imul(Ib, v[I]));
     ab[I] = Frc{{0.0f, 0.0f, 0.0f}, {0.0f, 0.0f, 0.0f}};
     vb[I] = Frc{{0.0f, 0.0f, 0.0f}, {0.0f, 0.0f, 0.0f}};
+    if constexpr (kW) {
+      if constexpr (TP::free_body(I)) world_pose<TP, I>(t, q, R0, Rw, pw);
+      else world_pose<TP, I>(t, q, joint_rot_cs<I>(t, cq[I], sq[I]), Rw, pw);
+    }
+    if constexpr (kExt) {
+      Fs[I] = fext_body<I>(fx, Rw[I], pw[I]);
+      Ws[I] = crf(mu[I], Fs[I]);
+    }
+    if constexpr (GF::kOn) {
+      // g_F = [v_O; w] in world axes: w = R mu.w, v_O = R mu.v + p x w
+      const V3 wv = mul(Rw[I], mu[I].w);
+      const V3 vo = cross_add(pw[I], wv, mul(Rw[I], mu[I].v));
+      gf(6 * I, vo.x); gf(6 * I + 1, vo.y); gf(6 * I + 2, vo.z);
+      gf(6 * I + 3, wv.x); gf(6 * I + 4, wv.y); gf(6 * I + 5, wv.z);
+    }
     close_subtrees<TP, I, I>(backward);
   });
 }

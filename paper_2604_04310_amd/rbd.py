@@ -91,8 +91,8 @@ def lib():
         L.rbd_crba.argtypes = [vp, i64, i64, vp, vp, vp]
         L.rbd_fwd_dyn.argtypes = [vp, i64, i64, vp, vp, vp, vp, vp, vp]
         L.rbd_aba.argtypes = [vp, i64, i64, vp, vp, vp, vp, vp, vp]
-        L.rbd_fwd_dyn_vjp.argtypes = [vp, i64, i64, vp, vp, vp, vp, vp, vp, vp, vp]
-        L.rbd_fwd_dyn_jvp.argtypes = [vp, i64, i64, vp, vp, vp, vp, vp, vp, vp, vp]
+        L.rbd_fwd_dyn_vjp.argtypes = [vp, i64, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+        L.rbd_fwd_dyn_jvp.argtypes = [vp, i64, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
         f32 = C.c_float
         L.rbd_diff_ik.argtypes = [vp, i64, i64, vp, C.c_int32, vp, f32, f32, vp, vp]
         L.rbd_osc.argtypes = [vp, i64, i64, vp, vp, C.c_int32, vp, f32, f32, f32, vp, vp]
@@ -131,7 +131,7 @@ def fma_rate(blocks: int = 256, ilp: int = 16, device: int = 0) -> float:
     return out.value
 
 
-N_KERNELS = 27
+N_KERNELS = 30
 
 
 def precompile_topology(parent, floating: bool, cache_dir: Optional[str] = None, kernel: int = -1) -> None:
@@ -320,44 +320,58 @@ def aba(model: Model, q, qd, tau, out=None, fext=None):
     return _fd(lib().rbd_aba, model, q, qd, tau, out, fext)
 
 
-def fwd_dyn_vjp(model: Model, q, qd, tau, g_qdd, want=(True, True, True)):
-    """(g_q [nq, B], g_qd [nv, B], g_tau [nv, B]) = g_qdd^T d qdd / d(q, qd, tau); None where not wanted."""
+def fwd_dyn_vjp(model: Model, q, qd, tau, g_qdd, want=(True, True, True), fext=None, want_fext=False):
+    """(g_q [nq, B], g_qd [nv, B], g_tau [nv, B]) = g_qdd^T d qdd / d(q, qd, tau); None where not wanted.
+    fext: optional [6 * n_bodies, B] external forces (as for rnea); want_fext adds g_fext [6 * n_bodies, B],
+    the cotangent of the forces (returned fourth)."""
     qp, B, l1 = _soa(q, model.nq, "q")
     qdp, _, l2 = _soa(qd, model.nv, "qd", B)
     taup, _, l3 = _soa(tau, model.nv, "tau", B)
     gp, _, l4 = _soa(g_qdd, model.nv, "g_qdd", B)
-    ld = _same_ld(l1, l2, l3, l4)
+    lds = [l1, l2, l3, l4]
+    fp = None
+    nf = 6 * model.n_bodies
+    if fext is not None:
+        fp, _, l5 = _soa(fext, nf, "fext", B)
+        lds.append(l5)
+    ld = _same_ld(*lds)
     if B > 0 and ld != B:
         raise ValueError("fwd_dyn_vjp: inputs must be contiguous")
     outs = [_out(model.nq, B, q) if want[0] else None, _out(model.nv, B, q) if want[1] else None,
-            _out(model.nv, B, q) if want[2] else None]
+            _out(model.nv, B, q) if want[2] else None, _out(nf, B, q) if want_fext else None]
     ptrs = [C.c_void_p(o.data_ptr()) if o is not None else None for o in outs]
-    check(lib().rbd_fwd_dyn_vjp(model.handle, B, ld, qp, qdp, taup, gp, ptrs[0], ptrs[1], ptrs[2], _stream()))
-    return tuple(outs)
+    check(lib().rbd_fwd_dyn_vjp(model.handle, B, ld, qp, qdp, taup, fp, gp, ptrs[0], ptrs[1], ptrs[2], ptrs[3],
+                                _stream()))
+    return tuple(outs) if want_fext else tuple(outs[:3])
 
 
-def fwd_dyn_jvp(model: Model, q, qd, tau, dq, dqd, dtau, want_qdd=False):
-    """d qdd [nv, B] along the tangent (dq [nq, B], dqd, dtau [nv, B]); with want_qdd also returns qdd."""
+def fwd_dyn_jvp(model: Model, q, qd, tau, dq, dqd, dtau, want_qdd=False, fext=None, dfext=None):
+    """d qdd [nv, B] along the tangent (dq [nq, B], dqd, dtau [nv, B], and optionally dfext [6 * n_bodies, B]),
+    with external forces fext [6 * n_bodies, B] when given; with want_qdd also returns qdd."""
     ins = [_soa(x, r, n, None) for x, r, n in ((q, model.nq, "q"), (qd, model.nv, "qd"), (tau, model.nv, "tau"),
                                                (dq, model.nq, "dq"), (dqd, model.nv, "dqd"),
                                                (dtau, model.nv, "dtau"))]
+    nf = 6 * model.n_bodies
+    fx = [None if x is None else _soa(x, nf, n, None) for x, n in ((fext, "fext"), (dfext, "dfext"))]
     B = ins[0][1]
-    if any(i[1] != B for i in ins):
+    if any(i[1] != B for i in ins + [f for f in fx if f is not None]):
         raise ValueError("fwd_dyn_jvp: batch sizes differ")
-    ld = _same_ld(*[i[2] for i in ins])
+    ld = _same_ld(*[i[2] for i in ins + [f for f in fx if f is not None]])
     if B > 0 and ld != B:
         raise ValueError("fwd_dyn_jvp: inputs must be contiguous")
     dqdd = _out(model.nv, B, q)
     qdd = _out(model.nv, B, q) if want_qdd else None
-    check(lib().rbd_fwd_dyn_jvp(model.handle, B, ld, *[i[0] for i in ins],
+    p = [i[0] for i in ins]
+    check(lib().rbd_fwd_dyn_jvp(model.handle, B, ld, p[0], p[1], p[2], None if fx[0] is None else fx[0][0],
+                                p[3], p[4], p[5], None if fx[1] is None else fx[1][0],
                                 C.c_void_p(qdd.data_ptr()) if qdd is not None else None,
                                 C.c_void_p(dqdd.data_ptr()), _stream()))
     return (qdd, dqdd) if want_qdd else dqdd
 
 
 def diff_ik(model: Model, q, target, gain: float, damping: float, frame: Optional[int] = None, out=None):
-    """Damped least-squares joint velocity [nv, B] toward target [12, B] ([R* | p*] row-major) for the
-    end effector (the last body)."""
+    """Damped least-squares joint velocity [nv, B] toward target [12, B] ([R* | p*] row-major) for a frame
+    (the last body by default; other frames compile their kernel on first use)."""
     qp, B, l1 = _soa(q, model.nq, "q")
     tp, _, l2 = _soa(target, 12, "target", B)
     qd = _out(model.nv, B, q) if out is None else out
@@ -369,7 +383,8 @@ def diff_ik(model: Model, q, target, gain: float, damping: float, frame: Optiona
 
 
 def osc(model: Model, q, qd, target, kp: float, kd: float, k_null: float, frame: Optional[int] = None, out=None):
-    """Operational-space control torques [nv, B] for the end effector (the last body)."""
+    """Operational-space control torques [nv, B] for a frame (the last body by default; other frames compile
+    their kernel on first use)."""
     qp, B, l1 = _soa(q, model.nq, "q")
     qdp, _, l2 = _soa(qd, model.nv, "qd", B)
     tp, _, l3 = _soa(target, 12, "target", B)
@@ -385,35 +400,43 @@ def _make_autograd():
     torch = _torch()
 
     class FwdDyn(torch.autograd.Function):
-        """qdd = FD(q, qd, tau) with the hand-written adjoint kernel as backward and the tangent
-        kernel as the forward-mode rule (torch.autograd.forward_ad dual tensors; torch.func
+        """qdd = FD(q, qd, tau[, fext]) with the hand-written adjoint kernel as backward and the
+        tangent kernel as the forward-mode rule (torch.autograd.forward_ad dual tensors; torch.func
         transforms hand the rules storage-less wrappers, which a kernel call cannot take).
-        Inputs must be contiguous [rows, B] tensors."""
+        Inputs must be contiguous [rows, B] tensors; fext may be None."""
 
         @staticmethod
-        def forward(model, q, qd, tau):
-            return fwd_dyn(model, q, qd, tau)
+        def forward(model, q, qd, tau, fext):
+            return fwd_dyn(model, q, qd, tau, fext=fext)
 
         @staticmethod
         def setup_context(ctx, inputs, output):
-            model, q, qd, tau = inputs
+            model, q, qd, tau, fext = inputs
             ctx.model = model
-            ctx.save_for_backward(q, qd, tau)
-            ctx.save_for_forward(q, qd, tau)
+            ctx.has_fext = fext is not None
+            saved = (q, qd, tau) + ((fext,) if fext is not None else ())
+            ctx.save_for_backward(*saved)
+            ctx.save_for_forward(*saved)
 
         @staticmethod
         def backward(ctx, g):
-            q, qd, tau = ctx.saved_tensors
+            q, qd, tau, *rest = ctx.saved_tensors
+            fext = rest[0] if ctx.has_fext else None
             want = ctx.needs_input_grad[1:4]
-            gq, gqd, gtau = fwd_dyn_vjp(ctx.model, q, qd, tau, g.contiguous(), want=tuple(bool(w) for w in want))
-            return None, gq, gqd, gtau
+            want_f = ctx.has_fext and ctx.needs_input_grad[4]
+            outs = fwd_dyn_vjp(ctx.model, q, qd, tau, g.contiguous(), want=tuple(bool(w) for w in want),
+                               fext=fext, want_fext=want_f)
+            gf = outs[3] if want_f else None
+            return None, outs[0], outs[1], outs[2], gf
 
         @staticmethod
-        def jvp(ctx, _model_t, q_t, qd_t, tau_t):
-            q, qd, tau = ctx.saved_tensors
+        def jvp(ctx, _model_t, q_t, qd_t, tau_t, f_t):
+            q, qd, tau, *rest = ctx.saved_tensors
+            fext = rest[0] if ctx.has_fext else None
             tangents = [torch.zeros_like(x) if t is None else t.contiguous()
                         for x, t in ((q, q_t), (qd, qd_t), (tau, tau_t))]
-            return fwd_dyn_jvp(ctx.model, q, qd, tau, *tangents)
+            df = f_t.contiguous() if (ctx.has_fext and f_t is not None) else None
+            return fwd_dyn_jvp(ctx.model, q, qd, tau, *tangents, fext=fext, dfext=df)
 
     return FwdDyn
 
@@ -421,12 +444,14 @@ def _make_autograd():
 _FwdDyn = None
 
 
-def fwd_dyn_autograd(model: Model, q, qd, tau):
-    """Differentiable forward dynamics: backward runs rbd_fwd_dyn_vjp, forward-mode AD rbd_fwd_dyn_jvp."""
+def fwd_dyn_autograd(model: Model, q, qd, tau, fext=None):
+    """Differentiable forward dynamics: backward runs rbd_fwd_dyn_vjp, forward-mode AD rbd_fwd_dyn_jvp;
+    fext (optional [6 * n_bodies, B] external forces) is differentiable too."""
     global _FwdDyn
     if _FwdDyn is None:
         _FwdDyn = _make_autograd()
-    return _FwdDyn.apply(model, q.contiguous(), qd.contiguous(), tau.contiguous())
+    return _FwdDyn.apply(model, q.contiguous(), qd.contiguous(), tau.contiguous(),
+                         None if fext is None else fext.contiguous())
 
 
 # ---------------------------------------------------------------- serving

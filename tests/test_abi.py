@@ -102,7 +102,7 @@ def test_precompile_writes_every_kernel(rbd, tmp_path):
     assert len([f for f in os.listdir(tmp_path) if f.endswith(".hsaco")]) == 1
     rbd.precompile_topology([-1, 0], False, str(tmp_path))
     files = sorted(f for f in os.listdir(tmp_path) if f.endswith(".hsaco"))
-    assert len(files) == 27
+    assert len(files) == 30
     blobs = [open(os.path.join(tmp_path, f), "rb").read() for f in files]
     t0 = time.time()
     rbd.precompile_topology([-1, 0], False, str(tmp_path))
@@ -119,12 +119,14 @@ def test_precompile_rejects_bad_topologies(rbd, tmp_path):
     with pytest.raises(rbd.RbdError):
         rbd.precompile_topology([-1] * 65, False, str(tmp_path))
     with pytest.raises(rbd.RbdError):
-        rbd.precompile_topology([-1, 0], False, str(tmp_path), kernel=27)
+        rbd.precompile_topology([-1, 0], False, str(tmp_path), kernel=rbd.N_KERNELS + 4)  # 2 bodies
+    with pytest.raises(rbd.RbdError):
+        rbd.precompile_topology([-1, 0], False, str(tmp_path), kernel=-2)
 
 
 def test_prebuilt_topologies_are_new_and_installed(rbd):
     """The shapes installed with run-time-compiled kernels are not compiled topologies, and build()
-    put all 27 kernels of each in the library's cache."""
+    put all 30 kernels of each in the library's cache."""
     from paper_2604_04310_amd.build import CSRC, JIT_DIR, PREBUILT
     import workloads as W2
     text = open(os.path.join(CSRC, "rbd_topologies.hpp")).read().replace("\\\n", " ")
@@ -136,7 +138,7 @@ def test_prebuilt_topologies_are_new_and_installed(rbd):
     assert PREBUILT["tree20"][1] == W2.random_dfs_parents(20, 4)
     assert PREBUILT["tree40f"][1] == W2.random_dfs_parents(40, 9)
     assert PREBUILT["quadruped13f"][1] == W2.QUADRUPED_PARENT
-    assert len([f for f in os.listdir(JIT_DIR) if f.endswith(".hsaco")]) >= 27 * len(PREBUILT)
+    assert len([f for f in os.listdir(JIT_DIR) if f.endswith(".hsaco")]) >= 30 * len(PREBUILT)
 
 
 def test_valid_model_without_device(rbd):
@@ -153,7 +155,9 @@ def test_null_model_calls(rbd):
     assert b"model is NULL" in L.rbd_last_error()
     assert L.rbd_aba(None, 1, 1, None, None, None, None, None, None) == 1
     assert L.rbd_rnea(None, 1, 1, None, None, None, None, None, None) == 1
-    assert L.rbd_fwd_dyn_jvp(None, 1, 1, None, None, None, None, None, None, None, None, None) == 1
+    assert L.rbd_fwd_dyn_jvp(None, 1, 1, *([None] * 11)) == 1
+    assert b"model is NULL" in L.rbd_last_error()
+    assert L.rbd_fwd_dyn_vjp(None, 1, 1, *([None] * 10)) == 1
     assert b"model is NULL" in L.rbd_last_error()
 
 

@@ -146,6 +146,30 @@ def test_jvp_full_batch(rbd, name, B):
     assert vjp_err([cols(dqdd, idx)], [ref]) < 1e-3
 
 
+def test_derivatives_with_external_forces_at_batch_32768(rbd):
+    """The adjoint and the tangent of the humanoid's forward dynamics under external forces at the
+    derivatives' benchmark size: finite everywhere, 256 states against central differences."""
+    desc = W.humanoid()
+    m = rbd.Model(desc, 0)
+    B = 32768
+    st = W.states(desc, B, 111)
+    rng = np.random.Generator(np.random.PCG64(112))
+    fext = W._f32(rng.normal(0.0, 5.0, size=(B, desc.n_bodies * 6)))
+    gbar = W.cotangent(desc.nv, B, 113)
+    q, qd, tau, fx = gpu(st.q), gpu(st.qd), gpu(st.tau), gpu(fext)
+    outs = rbd.fwd_dyn_vjp(m, q, qd, tau, gpu(gbar), fext=fx, want_fext=True)
+    dq, dqd, dtau, df = (W._f32(rng.normal(size=x.shape)) for x in (st.q, st.qd, st.tau, fext))
+    dqdd = rbd.fwd_dyn_jvp(m, q, qd, tau, gpu(dq), gpu(dqd), gpu(dtau), fext=fx, dfext=gpu(df))
+    torch.cuda.synchronize()
+    assert all(torch.isfinite(o).all() for o in outs) and torch.isfinite(dqdd).all()
+    idx = np.linspace(0, B - 1, 256).astype(int)
+    ref = O.fwd_dyn_vjp_fd(desc, st.q[idx], st.qd[idx], st.tau[idx], gbar[idx], fext=fext[idx])
+    assert vjp_err([cols(o, idx) for o in outs], list(ref)) < 1e-3
+    refj = O.fwd_dyn_jvp_fd(desc, st.q[idx], st.qd[idx], st.tau[idx], dq[idx], dqd[idx], dtau[idx], fext=fext[idx],
+                            dfext=df[idx])
+    assert vjp_err([cols(dqdd, idx)], [refj]) < 1e-3
+
+
 def test_external_forces_at_batch_65536(rbd):
     """fwd_dyn and rnea with external forces on the humanoid batch: a strided sample against the oracle."""
     desc = W.humanoid()

@@ -79,6 +79,15 @@ def check_every_row(rbd, m, desc, seed, B=300):
     dx = [W._f32(rng.normal(size=x[:Bd].shape)) for x in (st.q, st.qd, st.tau)]
     dqdd = host(rbd.fwd_dyn_jvp(m, *args, *[gpu(x) for x in dx]))
     assert vjp_err([dqdd], [O.fwd_dyn_jvp_fd(desc, st.q[:Bd], st.qd[:Bd], st.tau[:Bd], *dx)]) < TOL_VJP
+    # the derivatives with external forces
+    fb = fext[:Bd].reshape(Bd, -1)
+    outs = rbd.fwd_dyn_vjp(m, *args, gpu(gbar), fext=gpu(fb), want_fext=True)
+    ref = O.fwd_dyn_vjp_fd(desc, st.q[:Bd], st.qd[:Bd], st.tau[:Bd], gbar, fext=fb)
+    assert vjp_err([host(x) for x in outs], list(ref)) < TOL_VJP
+    df = W._f32(rng.normal(size=fb.shape))
+    dqdd = host(rbd.fwd_dyn_jvp(m, *args, *[gpu(x) for x in dx], fext=gpu(fb), dfext=gpu(df)))
+    refj = O.fwd_dyn_jvp_fd(desc, st.q[:Bd], st.qd[:Bd], st.tau[:Bd], *dx, fext=fb, dfext=df)
+    assert vjp_err([dqdd], [refj]) < TOL_VJP
     # controllers of the last body, against the oracle's plain forms with the FP32 error floor of the
     # controller tests (conditioning of the task-space solve)
     from tests.test_gpu_controllers import DAMP, GAIN, KD, KN, KP, floor_ik, floor_osc, within_bar
@@ -121,6 +130,6 @@ def test_compiled_on_the_device_host(rbd, tmp_path, monkeypatch):
     assert rel_err(qdd, O.fwd_dyn(desc, st.q, st.qd, st.tau)) < TOL_QDD
     assert n_code_objects() == 1
     check_every_row(rbd, m, desc, 90)
-    assert 10 <= n_code_objects() <= 27
+    assert 10 <= n_code_objects() <= 30
     m2 = rbd.Model(desc_of(False, [-1, 0, 0], 91), 0)
     assert m2.topology == m.topology

@@ -212,6 +212,63 @@ def test_fwd_dyn_jvp_parity(rbd, name):
     assert np.array_equal(host(rbd.fwd_dyn_jvp(m, *args)), host(dqdd))
 
 
+@pytest.mark.parametrize("name", list(ALL))
+def test_derivatives_with_external_forces(rbd, name):
+    """The adjoint (g_q, g_qd, g_tau and the force cotangent g_fext) and the tangent (with force
+    tangents) of forward dynamics under external forces, against central differences of the
+    oracle; the outputs of every subset agree with the full call."""
+    desc, m = model_of(rbd, name)
+    B = 128
+    st = draw(name, desc, B, 260)
+    rng = np.random.Generator(np.random.PCG64(261))
+    fext = W._f32(rng.normal(0.0, 5.0, size=(B, desc.n_bodies * 6)))
+    gbar = W.cotangent(desc.nv, B, 262)
+    args = [gpu(x) for x in (st.q, st.qd, st.tau, gbar)]
+    fx = gpu(fext)
+    outs = rbd.fwd_dyn_vjp(m, *args, fext=fx, want_fext=True)
+    ref = O.fwd_dyn_vjp_fd(desc, st.q, st.qd, st.tau, gbar, fext=fext)
+    assert vjp_err([host(o) for o in outs], list(ref)) < TOL_VJP
+    full = [host(o) for o in outs]
+    for want in [(1, 0, 0, 0), (0, 1, 0, 0), (1, 1, 0, 0), (1, 0, 1, 0), (0, 0, 0, 1), (1, 1, 1, 0)]:
+        sub = rbd.fwd_dyn_vjp(m, *args, want=tuple(bool(w) for w in want[:3]), fext=fx, want_fext=bool(want[3]))
+        for w, o, f in zip(want, sub, full):
+            assert (o is not None) == bool(w)
+            if w:
+                assert rel_err(host(o), f) < 1e-4, want
+    dx = [W._f32(rng.normal(size=x.shape)) for x in (st.q, st.qd, st.tau)]
+    df = W._f32(rng.normal(size=fext.shape))
+    dqdd = host(rbd.fwd_dyn_jvp(m, *args[:3], *[gpu(x) for x in dx], fext=fx, dfext=gpu(df)))
+    refj = O.fwd_dyn_jvp_fd(desc, st.q, st.qd, st.tau, *dx, fext=fext, dfext=df)
+    assert vjp_err([dqdd], [refj]) < TOL_VJP
+    # force tangent alone, without forces: M^-1 sum J^T dF
+    dz = [np.zeros_like(x) for x in dx]
+    d2 = host(rbd.fwd_dyn_jvp(m, *args[:3], *[gpu(x) for x in dz], dfext=gpu(df)))
+    assert vjp_err([d2], [O.fwd_dyn_jvp_fd(desc, st.q, st.qd, st.tau, *dz, dfext=df)]) < TOL_VJP
+
+
+def test_autograd_with_external_forces(rbd):
+    """Backward through fwd_dyn_autograd reaches the forces; forward-mode carries a force tangent."""
+    from torch.autograd import forward_ad as fwAD
+    desc, m = model_of(rbd, "tree12f_rot")
+    B = 64
+    st = draw("tree12f_rot", desc, B, 263)
+    rng = np.random.Generator(np.random.PCG64(264))
+    fext = W._f32(rng.normal(0.0, 5.0, size=(B, desc.n_bodies * 6)))
+    gbar = W.cotangent(desc.nv, B, 265)
+    q = gpu(st.q).requires_grad_(True)
+    f = gpu(fext).requires_grad_(True)
+    qdd = rbd.fwd_dyn_autograd(m, q, gpu(st.qd), gpu(st.tau), fext=f)
+    (qdd * gpu(gbar)).sum().backward()
+    ref = O.fwd_dyn_vjp_fd(desc, st.q, st.qd, st.tau, gbar, fext=fext)
+    assert vjp_err([host(q.grad), host(f.grad)], [ref[0], ref[3]]) < TOL_VJP
+    df = W._f32(rng.normal(size=fext.shape))
+    with fwAD.dual_level():
+        out = rbd.fwd_dyn_autograd(m, gpu(st.q), gpu(st.qd), gpu(st.tau), fext=fwAD.make_dual(gpu(fext), gpu(df)))
+        t = fwAD.unpack_dual(out).tangent
+    z = [np.zeros_like(x) for x in (st.q, st.qd, st.tau)]
+    assert vjp_err([host(t)], [O.fwd_dyn_jvp_fd(desc, st.q, st.qd, st.tau, *z, fext=fext, dfext=df)]) < TOL_VJP
+
+
 # The remaining compiled chains, each with its own random inertial parameters. Together with MODELS
 # they cover every topology in the library (a CPU test checks that the two lists stay complete).
 EXTRA_TOPOLOGIES = {f"chain{n}": (n, 40 + n) for n in (3, 4, 5, 6, 8)}
@@ -390,18 +447,23 @@ def test_overlapping_derivative_outputs_are_rejected(rbd):
     desc, m = model_of(rbd, "humanoid30")
     L = rbd.lib()
     p, o = C.c_void_p(1 << 20), C.c_void_p((1 << 20) + 4 * 3)
-    assert L.rbd_fwd_dyn_vjp(m.handle, 8, 8, p, p, p, p, None, p, o, None) == 1
+    i = C.c_void_p(1 << 30)  # inputs elsewhere
+    assert L.rbd_fwd_dyn_vjp(m.handle, 8, 8, i, i, i, None, i, None, p, o, None, None) == 1
     assert b"overlap" in L.rbd_last_error()
-    assert L.rbd_fwd_dyn_vjp(m.handle, 8, 8, p, p, p, p, o, p, None, None) == 1
-    assert L.rbd_fwd_dyn_jvp(m.handle, 8, 8, p, p, p, p, p, p, o, o, None) == 1
+    assert L.rbd_fwd_dyn_vjp(m.handle, 8, 8, i, i, i, None, i, o, p, None, None, None) == 1
+    assert L.rbd_fwd_dyn_vjp(m.handle, 8, 8, i, i, i, None, i, None, p, None, o, None) == 1  # g_f_ext too
+    assert L.rbd_fwd_dyn_jvp(m.handle, 8, 8, i, i, i, None, i, i, i, None, o, o, None) == 1
+    assert L.rbd_fwd_dyn_vjp(m.handle, 8, 8, p, i, i, None, i, None, o, None, None, None) == 1  # output on q
+    assert b"overlaps an input" in L.rbd_last_error()
     B, ld = 8, 16
     st = W.states(desc, B, 217)
     gbar = W.cotangent(desc.nv, B, 218)
     ins = [gpu(x, ld) for x in (st.q, st.qd, st.tau, gbar)]
     buf = torch.full((desc.nv, ld), float("nan"), dtype=torch.float32, device="cuda")
     ptr = buf.data_ptr()
-    rc = L.rbd_fwd_dyn_vjp(m.handle, B, ld, *[C.c_void_p(x.data_ptr()) for x in ins], None, C.c_void_p(ptr),
-                           C.c_void_p(ptr + 4 * B), C.c_void_p(torch.cuda.current_stream().cuda_stream))
+    ip = [C.c_void_p(x.data_ptr()) for x in ins]
+    rc = L.rbd_fwd_dyn_vjp(m.handle, B, ld, ip[0], ip[1], ip[2], None, ip[3], None, C.c_void_p(ptr),
+                           C.c_void_p(ptr + 4 * B), None, C.c_void_p(torch.cuda.current_stream().cuda_stream))
     assert rc == 0
     _, gqd, gtau = rbd.fwd_dyn_vjp(m, *[gpu(x) for x in (st.q, st.qd, st.tau, gbar)], want=(False, True, True))
     got = host(buf)  # [ld, nv]: rows 0..B-1 hold g_qd, rows B..2B-1 hold g_tau

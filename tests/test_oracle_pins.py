@@ -527,6 +527,49 @@ def test_jvp_tau_direction_is_inverse_mass_matrix():
     assert rel_err(jv, np.linalg.solve(O.crba(desc, st.q), dtau[..., None])[..., 0]) < 1e-7
 
 
+# ---------------------------------------------------------------- derivatives with external forces
+@pytest.mark.parametrize("name", ["chain7", "tree12f"])
+def test_vjp_with_forces_closed_form_blocks(name):
+    """With external forces: g_tau = M^-1 gbar still (forward dynamics is affine in tau, forces
+    aside), and g_F_i = J_i M^-1 gbar exactly, J_i the Jacobian of body i's twist at the world
+    origin, [v_O; w] = [v_p + p x w; w] (qdd is affine in F with slope M^-1 J^T)."""
+    desc = W.chain(7) if name == "chain7" else W.random_tree([-1, 0, 1, 1, 0, 4, 5, 5, 7, 0, 9, 10], True, 34)
+    B = 6
+    st = W.states(desc, B, 60)
+    fext = _random_fext(desc, B, 61)
+    gbar = W.cotangent(desc.nv, B, 62)
+    gq, gqd, gtau, gf = O.fwd_dyn_vjp_fd(desc, st.q, st.qd, st.tau, gbar, fext=fext)
+    lam = np.linalg.solve(O.crba(desc, st.q), gbar[..., None])[..., 0]
+    assert rel_err(gtau, lam) < 1e-7
+    J = O.jacobian(desc, st.q)  # [B, n, 6, nv], rows [v; w] at the body origin p
+    p = O.fk(desc, st.q)[..., :, 3]
+    tw = np.einsum("bnrc,bc->bnr", J, lam)
+    ref = np.concatenate([tw[..., :3] + np.cross(p, tw[..., 3:]), tw[..., 3:]], axis=2).reshape(B, -1)
+    assert rel_err(gf, ref) < 1e-7
+    # without forces the q and qd blocks are the force-free ones
+    g0 = O.fwd_dyn_vjp_fd(desc, st.q, st.qd, st.tau, gbar, fext=np.zeros_like(fext))
+    r0 = O.fwd_dyn_vjp_fd(desc, st.q, st.qd, st.tau, gbar)
+    assert rel_err(g0[0], r0[0]) < 1e-12 and rel_err(g0[1], r0[1]) < 1e-12
+
+
+@pytest.mark.parametrize("name", ["chain7", "humanoid30"])
+def test_jvp_is_dual_to_vjp_with_forces(name):
+    """<gbar, J dx> = <J^T gbar, dx> with forces and force tangents (both difference formulas)."""
+    desc = W.chain(7) if name == "chain7" else W.humanoid()
+    B = 6
+    st = W.states(desc, B, 63)
+    rng = np.random.Generator(np.random.PCG64(64))
+    fext = _random_fext(desc, B, 65)
+    dq, dqd, dtau = rng.normal(size=st.q.shape), rng.normal(size=st.qd.shape), rng.normal(size=st.tau.shape)
+    df = rng.normal(size=(B, 6 * desc.n_bodies))
+    gbar = W.cotangent(desc.nv, B, 66)
+    jv = O.fwd_dyn_jvp_fd(desc, st.q, st.qd, st.tau, dq, dqd, dtau, fext=fext, dfext=df)
+    gq, gqd, gtau, gf = O.fwd_dyn_vjp_fd(desc, st.q, st.qd, st.tau, gbar, fext=fext)
+    lhs = np.einsum("bk,bk->b", gbar, jv)
+    rhs = sum(np.einsum("bk,bk->b", g, x) for g, x in ((gq, dq), (gqd, dqd), (gtau, dtau), (gf, df)))
+    assert np.allclose(lhs, rhs, rtol=1e-6, atol=1e-6 * np.abs(rhs).max())
+
+
 # ---------------------------------------------------------------- controller workloads (Sec. IV, Table II)
 from oracle import controllers as CT  # noqa: E402
 
