@@ -16,7 +16,6 @@ import hashlib
 import json
 import os
 import sys
-import threading
 import time
 
 import numpy as np
@@ -303,6 +302,67 @@ def summarize_profiles(out_dir):
     with open(COUNTERS_FILE, "w") as fh:
         fh.write("\n".join(out) + "\n")
     print("\n".join(out))
+    if os.path.exists(os.path.join(out_dir, "prof_serving", "run_results.db")):
+        summarize_serving_trace(os.path.join(out_dir, "prof_serving", "run_results.db"), topo)
+
+
+def _union(iv):
+    """Total length of the union of [start, end) intervals."""
+    tot, cur_s, cur_e = 0, None, None
+    for s0, e0 in sorted(iv):
+        if cur_e is None or s0 > cur_e:
+            if cur_e is not None:
+                tot += cur_e - cur_s
+            cur_s, cur_e = s0, e0
+        else:
+            cur_e = max(cur_e, e0)
+    return tot + (cur_e - cur_s if cur_e is not None else 0)
+
+
+def summarize_serving_trace(path, topo):
+    """profiles/serving_overlap_chain7_humanoid30.txt: from a kernel and memory-copy trace of the
+    serving leg, how the packed launches and copies of different launch slots overlap in time."""
+    import collections
+    import sqlite3
+    cur = sqlite3.connect(path).cursor()
+    ks = [(n, st, q, s0, e0) for n, st, q, s0, e0 in
+          cur.execute("select name, stream_id, queue_id, start, end from kernels") if "k_packed" in n]
+    cps = list(cur.execute("select start, end from memory_copies"))
+    t0 = min(min(k[3] for k in ks), min(c[0] for c in cps))
+    t1 = max(max(k[4] for k in ks), max(c[1] for c in cps))
+    k_iv = [(k[3], k[4]) for k in ks]
+    k_sum, k_union = sum(e - s for s, e in k_iv), _union(k_iv)
+    ev = sorted([(s, 1) for s, _ in k_iv] + [(e, -1) for _, e in k_iv])
+    conc, last, multi = 0, None, 0
+    for t, d in ev:
+        if conc >= 2 and last is not None:
+            multi += t - last
+        conc += d
+        last = t
+    per = collections.defaultdict(list)
+    for n, st, q, s0, e0 in ks:
+        per[_short_kernel(n, topo)].append(e0 - s0)
+    lines = ["# Serving leg under a kernel and copy trace, one MI355X (gfx950)", "#",
+             "# command (run from /tmp with TMPDIR=/tmp):",
+             "#   rocprofv3 --kernel-trace --memory-copy-trace -d <out>/prof_serving -o run -- python3 "
+             "<repo>/bench.py --serving-only --serve-seconds 2",
+             "# then: python3 bench.py --summarize-profiles <out> (with the other profile runs)",
+             f"# source_hash = {kernel_source_hash()}",
+             f"span_ms = {(t1 - t0) / 1e6:.1f}",
+             f"packed_launches = {len(ks)} on {len({k[1] for k in ks})} streams, {len({k[2] for k in ks})} hardware queues",
+             f"packed_kernel_time_ms = {k_sum / 1e6:.2f} (sum of durations)",
+             f"packed_kernel_busy_ms = {k_union / 1e6:.2f} (union: time with at least one packed kernel running)",
+             f"gpu_kernel_busy_frac = {k_union / (t1 - t0):.3f} (union over the span)",
+             f"time_with_two_or_more_packed_kernels_ms = {multi / 1e6:.2f} "
+             f"({multi / max(k_union, 1):.3f} of the busy time)",
+             f"copies = {len(cps)}, copy_busy_ms = {_union(cps) / 1e6:.2f}, "
+             f"kernel_or_copy_busy_frac = {_union(k_iv + cps) / (t1 - t0):.3f}",
+             "", f"{'kernel':70s} {'calls':>7s} {'avg_us':>9s} {'p99_us':>9s}"]
+    for name, d in sorted(per.items(), key=lambda kv: -sum(kv[1])):
+        lines.append(f"{name[:70]:70s} {len(d):7d} {np.mean(d) / 1e3:9.2f} {np.percentile(d, 99) / 1e3:9.2f}")
+    with open(os.path.join(ROOT, "profiles", "serving_overlap_chain7_humanoid30.txt"), "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
 
 
 def soa(x, torch):
@@ -360,7 +420,7 @@ def cpu_baseline(desc, st, budget_s):
             "one_core_evals_per_s": done1 / dt1}
 
 
-def serving_leg(rbd, torch, seconds, seed=7):
+def serving_leg(rbd, torch, seconds, seed=7, n_streams=4):
     """Poisson mix of chain7/humanoid30 requests (ops 60/25/15 fwd_dyn/rnea/vjp,
     batch log-uniform in [1, 4096]) at half and at 80 % of the measured
     closed-loop capacity."""
@@ -381,75 +441,57 @@ def serving_leg(rbd, torch, seconds, seed=7):
             ins = ins + [W.cotangent(d.nv, B, 77 + k)]
         pool.append((name, op, B, [x.astype(np.float32) for x in ins]))
 
-    def run(srv, n_req, rate):
-        """Open loop when rate > 0 (exponential gaps), else all at once; returns (stats, wall)."""
-        tickets = []
-        waiter_err = []
-        lock = threading.Condition()
-
-        def waiter():
-            k = 0
-            while k < n_req:
-                with lock:
-                    while len(tickets) <= k:
-                        lock.wait()
-                    t = tickets[k]
-                if srv.wait(t, 120.0) != 0:
-                    waiter_err.append(t)
-                k += 1
-
-        th = threading.Thread(target=waiter)
-        th.start()
+    def run_python(srv, n_req):
+        """Closed loop from Python (submit all, then wait in order): the binding's own overhead."""
         srv.reset_stats()
         t0 = time.perf_counter()
-        next_t = t0
-        for k in range(n_req):
-            if rate > 0:
-                next_t += rng.exponential(1.0 / rate)
-                while time.perf_counter() < next_t:
-                    pass
-            name, op, B, ins = pool[k % len(pool)]
-            t, _ = srv.submit(models[name], op, ins)
-            with lock:
-                tickets.append(t)
-                lock.notify()
-        th.join()
-        wall = time.perf_counter() - t0
-        if waiter_err:
-            raise RuntimeError(f"{len(waiter_err)} served requests failed")
+        tickets = [srv.submit(models[pool[k % len(pool)][0]], pool[k % len(pool)][1], pool[k % len(pool)][3])[0]
+                   for k in range(n_req)]
+        bad = sum(srv.wait(t, 120.0) != 0 for t in tickets)
+        if bad:
+            raise RuntimeError(f"{bad} served requests failed")
+        return n_req / (time.perf_counter() - t0)
+
+    specs = [(models[name], op, ins) for name, op, _, ins in pool]
+
+    def run(srv, n_req, rate, seed):
+        """Native open-loop client (Poisson at `rate`, 0 = closed loop); returns (stats, wall)."""
+        srv.reset_stats()
+        wall, failed = srv.load(specs, n_req, rate=rate, window=4 * len(specs), seed=seed)
+        if failed:
+            raise RuntimeError(f"{failed} served requests failed")
         return srv.stats(), wall
 
+    def leg(st, wall, rate):
+        return {"offered_req_per_s": round(rate, 1), "requests": st["requests"], "launches": st["launches"],
+                "evals_per_s": st["instances"] / wall, "p50_us": st["p50_us"], "p99_us": st["p99_us"],
+                "max_us": st["max_us"], "groups_in_flight_frac": round(st["busy_s"] / wall, 3)}
+
     out = {}
-    srv = rbd.Server(arena_bytes=1 << 30, n_streams=4, max_batch_requests=1024, use_graphs=True)
-    run(srv, 512, 0.0)  # warm: graphs, pools
-    st, wall = run(srv, 2048, 0.0)
+    srv = rbd.Server(arena_bytes=1 << 30, n_streams=n_streams, max_batch_requests=1024, use_graphs=True)
+    run(srv, 1024, 0.0, 1)  # warm: graphs, pools
+    st, wall = run(srv, 8192, 0.0, 2)
     cap = st["requests"] / wall
-    run(srv, 4000, 0.5 * cap)  # open-loop warm-up, not reported
-    n_open = int(max(512, min(20000, cap * 0.5 * seconds)))
-    st, wall = run(srv, n_open, 0.5 * cap)
-    out["batched"] = {"offered_req_per_s": round(0.5 * cap, 1), "requests": st["requests"],
-                      "launches": st["launches"], "evals_per_s": st["instances"] / wall,
-                      "p50_us": st["p50_us"], "p99_us": st["p99_us"], "max_us": st["max_us"],
-                      "closed_loop_capacity_req_per_s": round(cap, 1),
-                      "groups_in_flight_frac": round(st["busy_s"] / wall, 3)}
-    n80 = int(max(512, min(20000, cap * 0.8 * seconds)))
-    st, wall = run(srv, n80, 0.8 * cap)
-    out["batched_at_80pct"] = {"offered_req_per_s": round(0.8 * cap, 1), "requests": st["requests"],
-                               "launches": st["launches"], "evals_per_s": st["instances"] / wall,
-                               "p50_us": st["p50_us"], "p99_us": st["p99_us"], "max_us": st["max_us"],
-                               "groups_in_flight_frac": round(st["busy_s"] / wall, 3)}
+    run(srv, 4000, 0.5 * cap, 3)  # open-loop warm-up, not reported
+    st, wall = run(srv, int(max(512, min(200000, cap * 0.5 * seconds))), 0.5 * cap, 4)
+    out["batched"] = dict(leg(st, wall, 0.5 * cap), closed_loop_capacity_req_per_s=round(cap, 1),
+                          closed_loop_evals_per_s=None)
+    st, wall = run(srv, int(max(512, min(200000, cap * 0.8 * seconds))), 0.8 * cap, 5)
+    out["batched_at_80pct"] = leg(st, wall, 0.8 * cap)
+    st, wall = run(srv, 8192, 0.0, 6)
+    out["batched"]["closed_loop_evals_per_s"] = st["instances"] / wall
+    out["python_client_closed_loop_req_per_s"] = round(run_python(srv, 2048), 1)
     srv.close()
     base = rbd.Server(arena_bytes=1 << 30, n_streams=1, per_request=True, use_graphs=False)
-    run(base, 256, 0.0)
-    st, wall = run(base, 2048, 0.0)
+    run(base, 256, 0.0, 7)
+    st, wall = run(base, 2048, 0.0, 8)
     bcap = st["requests"] / wall
-    n_b = int(max(256, min(20000, min(0.5 * cap, 0.9 * bcap) * seconds)))
-    st, wall = run(base, n_b, min(0.5 * cap, 0.9 * bcap))
-    out["one_launch_per_request"] = {"offered_req_per_s": round(min(0.5 * cap, 0.9 * bcap), 1),
-                                     "requests": st["requests"], "evals_per_s": st["instances"] / wall,
-                                     "p50_us": st["p50_us"], "p99_us": st["p99_us"], "max_us": st["max_us"],
-                                     "closed_loop_capacity_req_per_s": round(bcap, 1)}
+    rate = min(0.5 * cap, 0.9 * bcap)
+    st, wall = run(base, int(max(256, min(50000, rate * seconds))), rate, 9)
+    out["one_launch_per_request"] = dict(leg(st, wall, rate), closed_loop_capacity_req_per_s=round(bcap, 1))
     base.close()
+    out["client"] = ("native open-loop generator (rbd_diag_serve_load): Poisson arrivals from one submitting "
+                     f"thread, one waiting thread; {n_streams} launch slots (stream + worker thread each)")
     out["mix"] = "Poisson arrivals, chain7/humanoid30 50/50, fwd_dyn/rnea/fwd_dyn_vjp 60/25/15, batch log-uniform 1..4096, host I/O included"
     return out
 
@@ -462,6 +504,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--serve-seconds", type=float, default=6.0)
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--serving-only", action="store_true", help="only the serving leg (for a trace of it)")
+    ap.add_argument("--serve-streams", type=int, default=4)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--counters", action="store_true", help="only run the counter-collection driver")
     ap.add_argument("--summarize-profiles", metavar="DIR", help="write profiles/ summaries from rocprofv3 output")
@@ -485,6 +529,9 @@ def main():
     import workloads as W
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.serving_only:
+        print(json.dumps(serving_leg(rbd, torch, args.serve_seconds, n_streams=args.serve_streams)), flush=True)
+        return
     desc = W.humanoid()
     model = rbd.Model(desc, 0)
     st = W.states(desc, BATCH, 103)
@@ -630,7 +677,7 @@ def main():
                   "grid-stride loop), the best configuration, best of 10 launches each"}
     kernels = kernel_rooflines(O, W, desc, chain, ops, cnt, hbm)
 
-    serving = None if args.no_serving else serving_leg(rbd, torch, args.serve_seconds)
+    serving = None if args.no_serving else serving_leg(rbd, torch, args.serve_seconds, n_streams=args.serve_streams)
     cpu = None if args.no_cpu else cpu_baseline(desc, st, args.cpu_seconds)
 
     line = {

@@ -338,6 +338,29 @@ rbd_status rbd_server_reset_stats(rbd_server* s);
 /* Drain outstanding requests, then free everything. */
 rbd_status rbd_server_destroy(rbd_server* s);
 
+/* Diagnostic (a measurement client, not on the hot path): an open-loop load
+ * generator for a server, so that its capacity and latency are measured
+ * without the overhead of a scripting-language client. Request j
+ * (0 <= j < n_requests) is spec[j mod n_spec], submitted from the calling
+ * thread; arrivals are Poisson at rate_per_s (exponential gaps drawn from
+ * SplitMix64 seeded with `seed`), or as fast as the window allows when
+ * rate_per_s is 0 (closed loop). At most `window` requests (rounded up to a
+ * multiple of n_spec) are outstanding; their outputs go to buffers the
+ * generator allocates and frees (host memory). One extra thread waits for
+ * the tickets in order. Blocks until every request completed; *wall_s is the
+ * time from the first submit to the last completion and *failed counts
+ * requests whose own status was not RBD_OK. The spec's input buffers must
+ * stay valid during the call. Read the server's latency figures with
+ * rbd_server_get_stats (reset them before). */
+typedef struct {
+  const rbd_model* model;
+  int op;               /* rbd_op                                 */
+  int64_t batch;
+  const float* in[4];   /* host inputs as for rbd_server_submit   */
+} rbd_load_request;
+rbd_status rbd_diag_serve_load(rbd_server* s, int n_spec, const rbd_load_request* spec, int64_t n_requests,
+                               double rate_per_s, int window, uint64_t seed, double* wall_s, int64_t* failed);
+
 #ifdef __cplusplus
 }
 #endif

@@ -1,6 +1,7 @@
 """Build librbd.so (HIP for gfx950 + host C++) in-tree with hipcc."""
 from __future__ import annotations
 
+import hashlib
 import os
 import re
 import subprocess
@@ -14,7 +15,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "librbd.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-HOST_SOURCES = ["rbd_api.cpp", "rbd_dispatch.cpp", "rbd_serve.cpp", "rbd_jit.cpp"]
+HOST_SOURCES = ["rbd_api.cpp", "rbd_dispatch.cpp", "rbd_serve.cpp", "rbd_jit.cpp", "rbd_loadgen.cpp"]
 DEVICE_SOURCES = ["rbd_diag.hip"]
 TOPO_SOURCE = "rbd_kern_topo.hip"
 # Device headers the run-time compiler instantiates for a new topology; their
@@ -56,6 +57,71 @@ def _precompile_one(args):
     par = (C.c_int32 * len(parent))(*parent)
     st = lib.rbd_precompile_topology(len(parent), par, int(floating), JIT_DIR.encode(), kernel)
     return name, kernel, st, (lib.rbd_last_error().decode() if st else "")
+
+
+def _elf_symbols(data: bytes):
+    """Names of the symbols in an ELF64 little-endian image's .symtab."""
+    import struct
+    shoff, = struct.unpack_from("<Q", data, 0x28)
+    shentsize, shnum, shstrndx = struct.unpack_from("<HHH", data, 0x3A)
+    secs = [struct.unpack_from("<IIQQQQIIQQ", data, shoff + k * shentsize) for k in range(shnum)]
+    names = []
+    for sec in secs:
+        if sec[1] != 2:  # SHT_SYMTAB
+            continue
+        strtab = secs[sec[6]]
+        for off in range(sec[4], sec[4] + sec[5], sec[9]):
+            name_off, = struct.unpack_from("<I", data, off)
+            start = strtab[4] + name_off
+            names.append(data[start:data.index(b"\0", start)].decode())
+    return names
+
+
+def _section(data: bytes, wanted: str) -> bytes:
+    import struct
+    shoff, = struct.unpack_from("<Q", data, 0x28)
+    shentsize, shnum, shstrndx = struct.unpack_from("<HHH", data, 0x3A)
+    secs = [struct.unpack_from("<IIQQQQIIQQ", data, shoff + k * shentsize) for k in range(shnum)]
+    shstr = secs[shstrndx][4]
+    for sec in secs:
+        start = shstr + sec[0]
+        if data[start:data.index(b"\0", start)].decode() == wanted:
+            return data[sec[4]:sec[4] + sec[5]]
+    raise ValueError(f"no section {wanted}")
+
+
+def check_kernel_names(lib: str = LIB) -> int:
+    """Every kernel the library registers on the host side (its __device_stub__ symbols) must exist,
+    under the same name, in the gfx950 code objects embedded in the library; a launch of a
+    registered kernel missing from its code object cannot be resolved. Returns the kernel count."""
+    import struct
+    data = open(lib, "rb").read()
+    fat = _section(data, ".hip_fatbin")
+    magic = b"__CLANG_OFFLOAD_BUNDLE__"
+    device = set()
+    pos = fat.find(magic)
+    while pos >= 0:
+        n, = struct.unpack_from("<Q", fat, pos + len(magic))
+        q = pos + len(magic) + 8
+        for _ in range(n):
+            off, size, tlen = struct.unpack_from("<QQQ", fat, q)
+            triple = fat[q + 24:q + 24 + tlen].decode()
+            q += 24 + tlen
+            if "gfx950" in triple and size:
+                device.update(x[:-3] for x in _elf_symbols(fat[pos + off:pos + off + size]) if x.endswith(".kd"))
+        pos = fat.find(magic, q)
+    stubs = set()
+    for sym in _elf_symbols(data):
+        m = re.match(r"_ZN3rbd(\d+)__device_stub__(\w+)", sym)
+        if m:
+            name = sym[m.start(2):m.start(2) + int(m.group(1)) - len("__device_stub__")]
+            rest = sym[m.start(2) + len(name):]
+            stubs.add(f"_ZN3rbd{len(name)}{name}{rest}")
+    missing = sorted(stubs - device)
+    if missing or not stubs:
+        raise RuntimeError(f"{lib}: {len(missing)} registered kernels are missing from the device code, e.g. "
+                           f"{missing[:2]}" if missing else f"{lib}: no kernels registered")
+    return len(stubs)
 
 
 def prebuild_jit(verbose: bool = False, jobs: int = 0) -> None:
@@ -110,8 +176,17 @@ DEVICE_DEPS = [TOPO_SOURCE, "rbd_kernels.hpp", "rbd_kernel_ids.hpp", "rbd_lane.h
 HOST_HEADERS = ["rbd_internal.hpp", "rbd_shared.hpp", "rbd_kernel_ids.hpp", "rbd_topologies.hpp"]
 
 
-def _newest(paths) -> float:
-    return max(os.path.getmtime(p) for p in paths)
+def _inputs_hash(obj: str, cmd) -> str:
+    """Hash of an object's compile command and the text of every file it is compiled from, taken
+    before the compile starts. An incremental build reuses an object only if the hash recorded
+    with it matches: a file edited while its compile ran (hipcc reads the headers once for the
+    device pass and again for the host pass, so such an object can pair a host stub with device
+    code of another version) leaves a stale hash, and the object is compiled again."""
+    h = hashlib.sha256(" ".join(cmd).encode())
+    for path in _deps(obj, cmd):
+        with open(path, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
 
 
 def _deps(obj: str, cmd) -> list:
@@ -172,8 +247,15 @@ def build(verbose: bool = False, jobs: int = 0, resource_usage: bool = False, in
     work.append((obj, [HIPCC, *COMMON, "-c", jit_src, "-o", obj]))
     t0 = time.time()
     running, logs, objs = [], [], []
+    def recorded(o):
+        try:
+            with open(o + ".inputs") as fh:
+                return fh.read().strip()
+        except OSError:
+            return None
+
     if incremental and not resource_usage:
-        fresh = [(o, c) for o, c in work if os.path.exists(o) and os.path.getmtime(o) > _newest(_deps(o, c))]
+        fresh = [(o, c) for o, c in work if os.path.exists(o) and recorded(o) == _inputs_hash(o, c)]
         objs = [o for o, _ in fresh]
         work = [(o, c) for o, c in work if (o, c) not in fresh]
     pending = list(work)
@@ -182,19 +264,24 @@ def build(verbose: bool = False, jobs: int = 0, resource_usage: bool = False, in
             obj, cmd = pending.pop(0)
             if verbose:
                 print(" ".join(cmd), flush=True)
-            running.append((obj, cmd, subprocess.Popen(cmd, stderr=subprocess.PIPE)))
+            if os.path.exists(obj + ".inputs"):
+                os.remove(obj + ".inputs")
+            digest = _inputs_hash(obj, cmd)
+            running.append((obj, cmd, digest, subprocess.Popen(cmd, stderr=subprocess.PIPE)))
         time.sleep(0.1)
         for item in list(running):
-            obj, cmd, p = item
+            obj, cmd, digest, p = item
             if p.poll() is None:
                 continue
             running.remove(item)
             err = p.stderr.read().decode()
             if p.returncode != 0:
-                for _, _, q in running:
+                for _, _, _, q in running:
                     q.kill()
                 sys.stderr.write(err)
                 raise RuntimeError(f"compilation failed: {' '.join(cmd)}")
+            with open(obj + ".inputs", "w") as fh:
+                fh.write(digest + "\n")
             logs.append(err)
             objs.append(obj)
     tmp = LIB + ".tmp"
@@ -203,6 +290,7 @@ def build(verbose: bool = False, jobs: int = 0, resource_usage: bool = False, in
     if verbose:
         print(" ".join(link), flush=True)
     subprocess.run(link, check=True)
+    check_kernel_names(tmp)
     os.replace(tmp, LIB)
     if verbose:
         print(f"built {LIB} in {time.time() - t0:.1f}s", flush=True)

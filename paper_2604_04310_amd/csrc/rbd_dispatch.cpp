@@ -272,8 +272,20 @@ rbd_status launch_fwd_dyn_vjp(const rbd_model* m, int64_t batch, int64_t ld, con
   return launch(m, id, heavy_shape(batch), a, s, "rbd_fwd_dyn_vjp");
 }
 
+static KernelId packed_id(int op) {
+  return op == kOpFwdDynVjp ? KID_PACKED_VJP : (op == kOpFwdDyn ? KID_PACKED_FWD_DYN : KID_PACKED_RNEA);
+}
+
+rbd_status prepare_packed(const rbd_model* m, int op) {
+  const KernelSet* ks = m->ks;
+  if (!ks) return fail(RBD_E_UNSUPPORTED, "packed launch: the model has no kernels");
+  if (!ks->is_jit) return RBD_OK;
+  hipFunction_t f = nullptr;
+  return jit_function(ks, packed_id(op), &f);
+}
+
 rbd_status launch_packed(const rbd_model* m, int op, const void* d_table, int grid, hipStream_t s) {
-  const KernelId id = op == kOpFwdDynVjp ? KID_PACKED_VJP : (op == kOpFwdDyn ? KID_PACKED_FWD_DYN : KID_PACKED_RNEA);
+  const KernelId id = packed_id(op);
   const float* tab = m->d_tab;
   const uint8_t* t = static_cast<const uint8_t*>(d_table);
   void* a[] = {&tab, &t};

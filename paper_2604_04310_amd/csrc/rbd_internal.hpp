@@ -110,5 +110,8 @@ rbd_status launch_fwd_dyn_vjp(const rbd_model* m, int64_t batch, int64_t ld, con
 // descriptor table in device memory; grid blocks of 256 threads stride over it.
 constexpr int kMaxPacked = 4096;
 rbd_status launch_packed(const rbd_model* m, int op, const void* d_table, int grid, hipStream_t s);
+// Loads the packed kernel of `op` (compiling it if the model's kernels are
+// compiled at run time), so that a later launch does nothing but launch.
+rbd_status prepare_packed(const rbd_model* m, int op);
 
 }  // namespace rbd

@@ -3,23 +3,24 @@
 // Requests (model, operation, batch, host buffers) queue in arrival order. A
 // dispatcher thread forms a launch group from the oldest request's (model,
 // operation) class: as many queued requests of that class as fit the largest
-// free block of the device arena (admission by device memory) and the free
-// launch slots. A group is one block of the arena holding all of its inputs,
-// then all of its outputs; it costs one host-to-device copy, one packed launch
-// (every request of the group at once, tiles of 64 instances) and one
+// free block of the device arena (admission by device memory), and hands it to
+// a free launch slot. A group is one block of the arena holding all of its
+// inputs, then all of its outputs; it costs one host-to-device copy, one packed
+// launch (every request of the group at once, tiles of 64 instances) and one
 // device-to-host copy. The packed launch has a fixed grid of persistent waves
 // that read the tile table from device memory, so one captured HIP graph per
-// (slot, class, grid size) replays it for any group. Up to n_streams groups
-// are in flight on their own streams, so requests that arrive while others run
-// are admitted as memory and slots free up, and their work overlaps on the GPU.
-// When a group's copy-back has run, a host callback enqueued behind it on the
-// stream hands the group to a completion thread (which sleeps until then),
-// which copies the results into the clients' buffers, frees the arena block and
-// records each request's latency (submit to results in host memory). A group
-// that fails fails only its own requests. The host executor runs the same
-// scheduler over host memory with a fixed stand-in computation, so admission,
-// packing, completion, cancellation and failure handling can be tested
-// without a GPU.
+// (slot, class, grid size) replays it for any group. Each slot is a stream and
+// a worker thread: the worker stages the group's inputs into pinned memory,
+// queues the copies and the launch, sleeps until a host callback queued behind
+// the copy-back wakes it, copies the results into the clients' buffers, frees
+// the arena block and records each request's latency (submit to results in
+// host memory). Up to n_streams groups are in flight at once, so requests that
+// arrive while others run are admitted as memory and slots free up, their work
+// overlaps on the GPU, and the host copies of different groups run in
+// parallel. A group that fails fails only its own requests. The host executor
+// runs the same scheduler over host memory with a fixed stand-in computation,
+// so admission, packing, completion, cancellation and failure handling can be
+// tested without a GPU.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -141,10 +142,18 @@ struct Slot {
   hipEvent_t done = nullptr;
   uint8_t* d_table = nullptr;
   uint8_t* h_table = nullptr;
-  bool busy = false;
-  // captured launches by (model uid, op, grid): a graph holds its model's
-  // table address, so the key must not be the model's (reusable) address
+  bool busy = false;  // guarded by the server's mutex
+  // captured launches by (model uid, op, grid), used by this slot's worker
+  // only: a graph holds its model's table address, so the key must not be the
+  // model's (reusable) address
   std::map<std::tuple<uint64_t, int, int>, hipGraphExec_t> graphs;
+  // hand-off between the dispatcher, the worker and the stream callback
+  std::mutex mu;
+  std::condition_variable cv;
+  Group* job = nullptr;    // the next group to run (guarded by mu)
+  bool work_done = false;  // the stream reached the end of the job (guarded by mu)
+  bool quit = false;       // guarded by mu
+  std::thread worker;
 };
 
 size_t table_capacity(int max_req) {
@@ -162,17 +171,17 @@ struct rbd_server {
   uint8_t* d_arena = nullptr;  // device arena (host memory for the host executor)
   uint8_t* h_stage = nullptr;
   Arena arena;
-  std::vector<Slot> slots;
+  std::vector<std::unique_ptr<Slot>> slots;
   std::mutex mu;
-  std::condition_variable cv_work, cv_done, cv_inflight;
+  std::mutex capture_mu;  // one graph capture at a time
+  std::condition_variable cv_work, cv_done;
   std::deque<std::shared_ptr<Request>> pending;
   std::unordered_map<uint64_t, std::shared_ptr<Request>> tickets;
-  std::vector<Group*> inflight;
-  std::deque<Group*> completed;  // groups in flight whose work has finished
+  int n_busy = 0;                // slots with a group (guarded by mu)
   uint64_t next_ticket = 1;
   int64_t n_groups = 0;          // launch groups formed so far
-  bool stop = false, dispatcher_done = false;
-  std::thread dispatcher, completer;
+  bool stop = false;
+  std::thread dispatcher;
   // statistics
   std::vector<double> lat_us;
   uint64_t n_req = 0, n_inst = 0, n_launch = 0;
@@ -185,7 +194,7 @@ namespace {
 
 int free_slot(rbd_server* s) {
   for (size_t i = 0; i < s->slots.size(); ++i)
-    if (!s->slots[i].busy) return (int)i;
+    if (!s->slots[i]->busy) return (int)i;
   return -1;
 }
 
@@ -277,23 +286,22 @@ void host_launch(rbd_server* s, Group* g) {
   }
 }
 
-// The stream reached the end of a group's work: hand it to the completion
-// thread (runs on the runtime's callback thread; no HIP calls here).
+// The stream reached the end of a slot's job: wake its worker (runs on the
+// runtime's callback thread; no HIP calls here).
 void on_group_done(void* arg) {
-  Group* g = static_cast<Group*>(arg);
-  rbd_server* s = g->srv;
-  std::lock_guard<std::mutex> lk(s->mu);
-  s->completed.push_back(g);
-  s->cv_inflight.notify_all();
+  Slot* sl = static_cast<Slot*>(arg);
+  std::lock_guard<std::mutex> lk(sl->mu);
+  sl->work_done = true;
+  sl->cv.notify_all();
 }
 
-// Stage, launch and queue the copy-back of one group (dispatcher thread, no lock).
+// Stage, launch and queue the copy-back of one group (its slot's worker, no lock).
 rbd_status launch_group(rbd_server* s, Group* g) {
   if (s->host_exec) {
     host_launch(s, g);
     return RBD_OK;
   }
-  Slot& sl = s->slots[g->slot];
+  Slot& sl = *s->slots[g->slot];
   uint8_t* hb = s->h_stage + g->off;
   uint8_t* db = s->d_arena + g->off;
   // pack inputs (instance-major, as given) and the tile table
@@ -336,23 +344,23 @@ rbd_status launch_group(rbd_server* s, Group* g) {
     auto key = std::make_tuple(g->model->uid, g->op, grid);
     auto it = sl.graphs.find(key);
     if (it == sl.graphs.end()) {
-      // first request of this model: capture its graphs for every slot,
+      // first group of this model on this slot: capture its graphs for every
       // operation and grid size now, so that none is captured mid-stream later
-      // (a capture costs about a millisecond of dispatcher time)
-      for (auto& other : s->slots)
-        for (int op = RBD_OP_FWD_DYN; op <= RBD_OP_FWD_DYN_VJP; ++op)
-          for (int gc : kGridClasses) {
-            if (&other == &sl && op == g->op && gc == grid) continue;
-            auto k2 = std::make_tuple(g->model->uid, op, gc);
-            if (other.graphs.count(k2)) continue;
-            hipGraphExec_t e2 = nullptr;
-            if (capture_packed(g->model, op, other.d_table, gc, other.stream, &e2) == RBD_OK)
-              other.graphs.emplace(k2, e2);
-          }
-      hipGraphExec_t exec = nullptr;
-      rs = capture_packed(g->model, g->op, sl.d_table, grid, st, &exec);
-      if (rs != RBD_OK) return rs;
-      it = sl.graphs.emplace(key, exec).first;
+      // (a capture costs about a millisecond of this worker's time)
+      std::lock_guard<std::mutex> cap(s->capture_mu);
+      for (int op = RBD_OP_FWD_DYN; op <= RBD_OP_FWD_DYN_VJP; ++op) {
+        rs = prepare_packed(g->model, op);  // a run-time-compiled kernel is loaded outside the capture
+        if (rs != RBD_OK) return rs;
+        for (int gc : kGridClasses) {
+          auto k2 = std::make_tuple(g->model->uid, op, gc);
+          if (sl.graphs.count(k2)) continue;
+          hipGraphExec_t exec = nullptr;
+          rs = capture_packed(g->model, op, sl.d_table, gc, st, &exec);
+          if (rs != RBD_OK) return rs;
+          sl.graphs.emplace(k2, exec);
+        }
+      }
+      it = sl.graphs.find(key);
     }
     if (hipGraphLaunch(it->second, st) != hipSuccess) return fail(RBD_E_LAUNCH, "server: graph launch failed");
   } else {
@@ -365,7 +373,7 @@ rbd_status launch_group(rbd_server* s, Group* g) {
   return RBD_OK;
 }
 
-void finish_group(rbd_server* s, Group* g, const Clock::time_point now, bool inflight = true) {
+void finish_group(rbd_server* s, Group* g, const Clock::time_point now) {
   // results -> client buffers (instance-major, as requested)
   if (g->status == RBD_OK) {
     const uint8_t* hb = s->h_stage + g->off;
@@ -380,7 +388,8 @@ void finish_group(rbd_server* s, Group* g, const Clock::time_point now, bool inf
   }
   std::lock_guard<std::mutex> lk(s->mu);
   s->arena.release(g->off, g->bytes);
-  s->slots[g->slot].busy = false;
+  s->slots[g->slot]->busy = false;
+  if (--s->n_busy == 0) s->busy_s += std::chrono::duration<double>(now - s->busy_since).count();
   for (auto& rp : g->reqs) {
     rp->status = g->status;
     rp->done = true;
@@ -389,18 +398,51 @@ void finish_group(rbd_server* s, Group* g, const Clock::time_point now, bool inf
     s->n_inst += (uint64_t)rp->batch;
   }
   s->n_launch++;
-  if (inflight) {
-    s->inflight.erase(std::find(s->inflight.begin(), s->inflight.end(), g));
-    if (s->inflight.empty()) s->busy_s += std::chrono::duration<double>(now - s->busy_since).count();
-  }
   delete g;
   s->cv_done.notify_all();
   s->cv_work.notify_all();
-  s->cv_inflight.notify_all();
+}
+
+// One group on one slot, start to finish (the slot's worker thread).
+void run_group(rbd_server* s, Slot& sl, Group* g) {
+  if (g->status == RBD_OK) g->status = launch_group(s, g);
+  if (!s->host_exec) {
+    if (g->status != RBD_OK) {
+      // copies queued before the failure may still run: drain them before the
+      // block returns to the arena
+      (void)hipStreamSynchronize(sl.stream);
+    } else {
+      if (hipLaunchHostFunc(sl.stream, on_group_done, &sl) == hipSuccess) {
+        std::unique_lock<std::mutex> lk(sl.mu);
+        sl.cv.wait(lk, [&] { return sl.work_done; });
+      } else {
+        (void)hipStreamSynchronize(sl.stream);  // no callback will come: wait here instead
+      }
+      // an error of the group's device work shows in its event
+      if (hipEventQuery(sl.done) != hipSuccess) g->status = fail(RBD_E_LAUNCH, "server: launch failed on the device");
+    }
+  }
+  finish_group(s, g, Clock::now());
+}
+
+void worker_main(rbd_server* s, int k) {
+  Slot& sl = *s->slots[k];
+  if (!s->host_exec) (void)hipSetDevice(s->cfg.device);
+  for (;;) {
+    Group* g = nullptr;
+    {
+      std::unique_lock<std::mutex> lk(sl.mu);
+      sl.cv.wait(lk, [&] { return sl.job != nullptr || sl.quit; });
+      if (!sl.job) return;  // asked to quit with nothing left to run
+      g = sl.job;
+      sl.job = nullptr;
+      sl.work_done = false;
+    }
+    run_group(s, sl, g);
+  }
 }
 
 void dispatcher_main(rbd_server* s) {
-  if (!s->host_exec) (void)hipSetDevice(s->cfg.device);
   std::unique_lock<std::mutex> lk(s->mu);
   for (;;) {
     if (s->pending.empty()) {
@@ -428,65 +470,17 @@ void dispatcher_main(rbd_server* s) {
     }
     g->slot = free_slot(s);
     g->srv = s;
-    s->slots[g->slot].busy = true;
-    const bool injected = s->cfg.fail_group > 0 && ++s->n_groups == s->cfg.fail_group;
+    Slot& sl = *s->slots[g->slot];
+    sl.busy = true;
+    if (s->n_busy++ == 0) s->busy_since = Clock::now();
+    if (s->cfg.fail_group > 0 && ++s->n_groups == s->cfg.fail_group)
+      g->status = fail(RBD_E_LAUNCH, "server: injected failure of launch group %lld", (long long)s->cfg.fail_group);
     lk.unlock();
-    g->status = injected ? fail(RBD_E_LAUNCH, "server: injected failure of launch group %lld",
-                                (long long)s->cfg.fail_group)
-                         : launch_group(s, g);
-    if (g->status != RBD_OK) {
-      // A failed group never reaches the completion thread (which reads the
-      // groups in flight without the lock): copies queued before the failure
-      // may still run, so drain them, then fail this group's requests only
-      // and return its block to the arena.
-      if (!s->host_exec) (void)hipStreamSynchronize(s->slots[g->slot].stream);
-      finish_group(s, g, Clock::now(), false);
-      lk.lock();
-      continue;
+    {
+      std::lock_guard<std::mutex> sk(sl.mu);
+      sl.job = g;
     }
-    const hipStream_t st = s->host_exec ? nullptr : s->slots[g->slot].stream;
-    lk.lock();
-    if (s->inflight.empty()) s->busy_since = Clock::now();
-    s->inflight.push_back(g);
-    if (s->host_exec) {  // its work is done already
-      s->completed.push_back(g);
-      s->cv_inflight.notify_all();
-      continue;
-    }
-    lk.unlock();
-    // the completion thread learns of the group from a host callback queued
-    // behind its work (g may be finished and freed as soon as it is queued)
-    if (hipLaunchHostFunc(st, on_group_done, g) != hipSuccess) {
-      (void)hipStreamSynchronize(st);  // no callback will come: wait here instead
-      lk.lock();
-      s->completed.push_back(g);
-      s->cv_inflight.notify_all();
-      continue;
-    }
-    lk.lock();
-  }
-  s->dispatcher_done = true;
-  s->cv_work.notify_all();
-  s->cv_inflight.notify_all();
-}
-
-void completer_main(rbd_server* s) {
-  if (!s->host_exec) (void)hipSetDevice(s->cfg.device);
-  std::unique_lock<std::mutex> lk(s->mu);
-  for (;;) {
-    if (s->completed.empty()) {
-      if (s->inflight.empty() && s->dispatcher_done) break;
-      s->cv_inflight.wait(lk);
-      continue;
-    }
-    Group* g = s->completed.front();
-    s->completed.pop_front();
-    lk.unlock();
-    // the callback runs once the stream got there; an error of the group's
-    // work shows in its event
-    if (!s->host_exec && hipEventQuery(s->slots[g->slot].done) != hipSuccess)
-      g->status = fail(RBD_E_LAUNCH, "server: launch failed on the device");
-    finish_group(s, g, Clock::now());
+    sl.cv.notify_all();
     lk.lock();
   }
 }
@@ -519,7 +513,7 @@ rbd_status rbd_server_create(const rbd_server_config* cfg, rbd_server** out) {
   s->cfg = *cfg;
   s->host_exec = host;
   s->arena.init(cfg->arena_bytes);
-  s->slots.resize(cfg->n_streams);
+  for (int k = 0; k < cfg->n_streams; ++k) s->slots.push_back(std::make_unique<Slot>());
   bool ok = true;
   if (host) {
     s->h_stage = new (std::nothrow) uint8_t[cfg->arena_bytes];
@@ -529,18 +523,18 @@ rbd_status rbd_server_create(const rbd_server_config* cfg, rbd_server** out) {
          hipHostMalloc(&s->h_stage, cfg->arena_bytes, hipHostMallocDefault) == hipSuccess;
     const size_t tcap = table_capacity(cfg->max_batch_requests);
     for (auto& sl : s->slots) {
-      ok = ok && hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) == hipSuccess &&
-           hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) == hipSuccess &&
-           hipMalloc(&sl.d_table, tcap) == hipSuccess &&
-           hipHostMalloc(&sl.h_table, tcap, hipHostMallocDefault) == hipSuccess;
+      ok = ok && hipStreamCreateWithFlags(&sl->stream, hipStreamNonBlocking) == hipSuccess &&
+           hipEventCreateWithFlags(&sl->done, hipEventDisableTiming) == hipSuccess &&
+           hipMalloc(&sl->d_table, tcap) == hipSuccess &&
+           hipHostMalloc(&sl->h_table, tcap, hipHostMallocDefault) == hipSuccess;
     }
   }
   if (!ok) {
     rbd_server_destroy(s);
     return fail(RBD_E_NOMEM, "server: allocation of %zu arena bytes failed", cfg->arena_bytes);
   }
+  for (int k = 0; k < cfg->n_streams; ++k) s->slots[k]->worker = std::thread(worker_main, s, k);
   s->dispatcher = std::thread(dispatcher_main, s);
-  s->completer = std::thread(completer_main, s);
   *out = s;
   return RBD_OK;
 }
@@ -660,14 +654,15 @@ rbd_status rbd_server_destroy(rbd_server* s) {
     s->stop = true;
     s->cv_work.notify_all();
   }
-  if (s->dispatcher.joinable()) s->dispatcher.join();
-  {
-    std::lock_guard<std::mutex> lk(s->mu);
-    s->dispatcher_done = true;
-    s->cv_work.notify_all();
-    s->cv_inflight.notify_all();
+  if (s->dispatcher.joinable()) s->dispatcher.join();  // every request has a slot now
+  for (auto& sl : s->slots) {
+    {
+      std::lock_guard<std::mutex> lk(sl->mu);
+      sl->quit = true;
+    }
+    sl->cv.notify_all();
+    if (sl->worker.joinable()) sl->worker.join();  // after its last group
   }
-  if (s->completer.joinable()) s->completer.join();
   if (s->host_exec) {
     delete[] s->h_stage;
     delete s;
@@ -675,12 +670,12 @@ rbd_status rbd_server_destroy(rbd_server* s) {
   }
   (void)hipSetDevice(s->cfg.device);
   for (auto& sl : s->slots) {
-    for (auto& kv : sl.graphs) (void)hipGraphExecDestroy(kv.second);
-    if (sl.stream) (void)hipStreamSynchronize(sl.stream);
-    if (sl.done) (void)hipEventDestroy(sl.done);
-    if (sl.stream) (void)hipStreamDestroy(sl.stream);
-    if (sl.d_table) (void)hipFree(sl.d_table);
-    if (sl.h_table) (void)hipHostFree(sl.h_table);
+    for (auto& kv : sl->graphs) (void)hipGraphExecDestroy(kv.second);
+    if (sl->stream) (void)hipStreamSynchronize(sl->stream);
+    if (sl->done) (void)hipEventDestroy(sl->done);
+    if (sl->stream) (void)hipStreamDestroy(sl->stream);
+    if (sl->d_table) (void)hipFree(sl->d_table);
+    if (sl->h_table) (void)hipHostFree(sl->h_table);
   }
   if (s->d_arena) (void)hipFree(s->d_arena);
   if (s->h_stage) (void)hipHostFree(s->h_stage);

@@ -31,7 +31,7 @@ OP_FWD_DYN, OP_RNEA, OP_FWD_DYN_VJP = 0, 1, 2
 EXPORTS = ["rbd_model_create", "rbd_model_destroy", "rbd_model_dims", "rbd_model_topology", "rbd_fk",
            "rbd_jacobian", "rbd_rnea", "rbd_crba", "rbd_fwd_dyn", "rbd_aba", "rbd_fwd_dyn_jvp", "rbd_fwd_dyn_vjp", "rbd_diff_ik", "rbd_osc", "rbd_status_str",
            "rbd_last_error", "rbd_device_count", "rbd_diag_fma_rate", "rbd_diag_hbm_rate", "rbd_precompile_topology", "rbd_server_create", "rbd_server_submit", "rbd_server_wait", "rbd_server_cancel",
-           "rbd_server_get_stats", "rbd_server_reset_stats", "rbd_server_destroy"]
+           "rbd_server_get_stats", "rbd_server_reset_stats", "rbd_server_destroy", "rbd_diag_serve_load"]
 
 
 class RbdError(RuntimeError):
@@ -61,6 +61,10 @@ class ServerConfigC(C.Structure):
 
 
 EXEC_DEVICE, EXEC_HOST = 0, 1
+
+
+class LoadRequestC(C.Structure):
+    _fields_ = [("model", C.c_void_p), ("op", C.c_int), ("batch", C.c_int64), ("inp", C.c_void_p * 4)]
 
 
 class ServerStatsC(C.Structure):
@@ -111,6 +115,8 @@ def lib():
         L.rbd_server_get_stats.argtypes = [vp, P(ServerStatsC)]
         L.rbd_server_reset_stats.argtypes = [vp]
         L.rbd_server_destroy.argtypes = [vp]
+        L.rbd_diag_serve_load.argtypes = [vp, C.c_int, P(LoadRequestC), i64, C.c_double, C.c_int, C.c_uint64,
+                                          P(C.c_double), P(i64)]
         _lib = L
     return _lib
 
@@ -508,6 +514,26 @@ class Server:
     def cancel(self, ticket: int) -> None:
         """Cancel a request still in the queue (it then completes with RBD_E_CANCELLED)."""
         check(lib().rbd_server_cancel(self._h, C.c_uint64(ticket)))
+
+    def load(self, requests, n_requests: int, rate: float = 0.0, window: int = 1024, seed: int = 0):
+        """Native open-loop load (rbd_diag_serve_load): request j is requests[j % len(requests)], each a
+        (model, op, inputs) triple of instance-major float32 arrays; Poisson arrivals at `rate` per second
+        (0: closed loop). Returns (wall seconds, failed requests)."""
+        keep, spec = [], (LoadRequestC * len(requests))()
+        for k, (model, op, inputs) in enumerate(requests):
+            in_rows, _ = op_shapes(model, op)
+            batch = int(inputs[0].shape[0])
+            xs = [np.ascontiguousarray(x, dtype=np.float32) for x in inputs]
+            if len(xs) != len(in_rows) or any(x.shape != (batch, r) for x, r in zip(xs, in_rows)):
+                raise ValueError(f"request {k}: inputs do not match op {op}")
+            keep.append(xs)
+            spec[k].model, spec[k].op, spec[k].batch = model.handle.value, int(op), batch
+            for a, x in enumerate(xs):
+                spec[k].inp[a] = x.ctypes.data
+        wall, failed = C.c_double(), C.c_int64()
+        check(lib().rbd_diag_serve_load(self._h, len(requests), spec, int(n_requests), float(rate), int(window),
+                                        int(seed), C.byref(wall), C.byref(failed)))
+        return wall.value, failed.value
 
     def stats(self) -> dict:
         s = ServerStatsC()

@@ -208,3 +208,11 @@ def test_parity_tests_cover_every_compiled_topology():
     from tests.test_gpu_parity import EXTRA_TOPOLOGIES, MODELS
     assert set(MODELS) | set(EXTRA_TOPOLOGIES) == set(topologies())
     assert not set(MODELS) & set(EXTRA_TOPOLOGIES)
+
+
+def test_registered_kernels_exist_in_device_code(rbd):
+    """Every kernel the library registers on the host side exists under the same name in its
+    embedded gfx950 code objects (a stale object pairing a host stub of one header version with
+    device code of another would make its launches unresolvable)."""
+    from paper_2604_04310_amd.build import check_kernel_names
+    assert check_kernel_names(rbd.LIB_PATH) >= 11 * rbd.N_KERNELS

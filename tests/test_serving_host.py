@@ -58,7 +58,10 @@ def test_host_only_model_has_no_kernels(rbd, models):
 def test_every_request_gets_its_own_results(rbd, models):
     """A mix of robots, operations and batch sizes from two client threads: every ticket completes
     once, with its own inputs' results, across many packed groups."""
-    srv = rbd.Server(executor=rbd.EXEC_HOST, arena_bytes=4 << 20, n_streams=3, max_batch_requests=64)
+    # a gather window makes packing certain: without one, three workers can keep up with two
+    # Python clients and every request may run alone
+    srv = rbd.Server(executor=rbd.EXEC_HOST, arena_bytes=4 << 20, n_streams=3, max_batch_requests=64,
+                     max_wait_us=3000.0)
     rng = np.random.Generator(np.random.PCG64(1))
     plan = [(list(models)[int(rng.integers(2))], int(rng.choice([rbd.OP_FWD_DYN, rbd.OP_RNEA, rbd.OP_FWD_DYN_VJP])),
              int(np.clip(round(np.exp(rng.uniform(0, np.log(2048)))), 1, 2048))) for _ in range(400)]
@@ -168,3 +171,33 @@ def test_host_executor_validation(rbd, models):
         rbd.Server(executor=7)
     with pytest.raises(rbd.RbdError):
         rbd.Server(executor=rbd.EXEC_HOST, fail_group=-1)
+
+
+def test_native_load_generator(rbd, models):
+    """rbd_diag_serve_load drives a server from native threads: closed loop and Poisson arrivals
+    both complete every request, the server's counters see each of them once, and a bad spec or an
+    injected group failure is reported."""
+    srv = rbd.Server(executor=rbd.EXEC_HOST, arena_bytes=8 << 20, n_streams=4, max_batch_requests=64)
+    specs = []
+    for k in range(6):
+        name = "chain7" if k % 2 else "humanoid30"
+        op = [rbd.OP_FWD_DYN, rbd.OP_RNEA, rbd.OP_FWD_DYN_VJP][k % 3]
+        specs.append((models[name], op, make_request(rbd, models[name], op, 7 + 60 * k, 600 + k)))
+    n_inst = sum(s[2][0].shape[0] for s in specs)
+    srv.reset_stats()
+    wall, failed = srv.load(specs, 600, rate=0.0, window=16, seed=3)
+    st = srv.stats()
+    assert failed == 0 and wall > 0
+    assert st["requests"] == 600 and st["instances"] == 100 * n_inst and st["launches"] <= 600
+    srv.reset_stats()
+    wall, failed = srv.load(specs, 300, rate=20000.0, window=64, seed=4)
+    assert failed == 0 and srv.stats()["requests"] == 300
+    assert wall >= 0.5 * 300 / 20000.0  # arrivals are paced, not sent at once
+    with pytest.raises(ValueError):
+        srv.load([(models["chain7"], rbd.OP_FWD_DYN, [np.zeros((4, 7), np.float32)])], 1)
+    srv.close()
+    bad = rbd.Server(executor=rbd.EXEC_HOST, arena_bytes=8 << 20, n_streams=1, max_batch_requests=1,
+                     fail_group=5)
+    wall, failed = bad.load(specs[:1], 20, window=4)
+    assert failed == 1  # one request per group, the fifth group fails
+    bad.close()
