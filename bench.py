@@ -63,7 +63,8 @@ def read_counters():
             continue
         fields = dict(f.split("=", 1) for f in line.split() if "=" in f)
         if "kernel" in fields:
-            out[fields.pop("kernel")] = {k: float(v) for k, v in fields.items()}
+            key = fields.pop("kernel")
+            out[key] = {k: float(v) for k, v in fields.items()}
     return out if src == kernel_source_hash() else {}
 
 
@@ -637,6 +638,12 @@ def main():
     ops["fwd_dyn_jvp_humanoid30_b32768_us"] = 1e3 * time_launches(
         lambda: rbd.fwd_dyn_jvp(model, vq, vqd, vtau, tq, tqd, ttau), n_t, torch)
     del tq, tqd, ttau
+    # every output subset of the adjoint (what autograd asks for when only some inputs need grads)
+    for want in ((True, False, False), (False, True, False), (False, False, True), (True, True, False),
+                 (True, False, True), (False, True, True)):
+        tag = "".join(n for n, w in zip(("q", "qd", "tau"), want) if w)
+        ops[f"fwd_dyn_vjp_{tag}_humanoid30_b32768_us"] = 1e3 * time_launches(
+            lambda: rbd.fwd_dyn_vjp(model, vq, vqd, vtau, gq, want=want), n_t, torch)
     # the same two at batch 65536, where their waves fill every SIMD (32768 instances fill half)
     g65 = soa(W.cotangent(desc.nv, BATCH, 9), torch)
     ops["fwd_dyn_vjp_humanoid30_b65536_us"] = 1e3 * time_launches(
