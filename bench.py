@@ -464,9 +464,16 @@ def serving_leg(rbd, torch, seconds, seed=7, n_streams=4):
         return srv.stats(), wall
 
     def leg(st, wall, rate):
+        ks = max(st["gpu_kernel_s"], 1e-12)
         return {"offered_req_per_s": round(rate, 1), "requests": st["requests"], "launches": st["launches"],
                 "evals_per_s": st["instances"] / wall, "p50_us": st["p50_us"], "p99_us": st["p99_us"],
-                "max_us": st["max_us"], "groups_in_flight_frac": round(st["busy_s"] / wall, 3)}
+                "max_us": st["max_us"], "groups_in_flight_frac": round(st["busy_s"] / wall, 3),
+                # device timeline from the server's own per-group timing events
+                "gpu_kernel_busy_frac": round(st["gpu_kernel_s"] / wall, 3),
+                "gpu_kernel_overlap_frac": round(st["gpu_kernel_overlap_s"] / ks, 3),
+                "gpu_copy_busy_frac": round(st["gpu_copy_s"] / wall, 3),
+                "gpu_active_frac": round(st["gpu_active_s"] / wall, 3),
+                "mean_kernel_us": round(1e6 * st["gpu_kernel_sum_s"] / max(st["groups_timed"], 1), 1)}
 
     out = {}
     srv = rbd.Server(arena_bytes=1 << 30, n_streams=n_streams, max_batch_requests=1024, use_graphs=True)
@@ -479,6 +486,8 @@ def serving_leg(rbd, torch, seconds, seed=7, n_streams=4):
                           closed_loop_evals_per_s=None)
     st, wall = run(srv, int(max(512, min(200000, cap * 0.8 * seconds))), 0.8 * cap, 5)
     out["batched_at_80pct"] = leg(st, wall, 0.8 * cap)
+    st, wall = run(srv, int(max(512, min(200000, cap * 0.25 * seconds))), 0.25 * cap, 10)
+    out["batched_at_25pct"] = leg(st, wall, 0.25 * cap)
     st, wall = run(srv, 8192, 0.0, 6)
     out["batched"]["closed_loop_evals_per_s"] = st["instances"] / wall
     out["python_client_closed_loop_req_per_s"] = round(run_python(srv, 2048), 1)

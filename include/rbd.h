@@ -138,7 +138,7 @@ const char* rbd_model_topology(const rbd_model* model);
  * time per process). Kernels already in the directory are kept. Needs no GPU.
  * Synchronous. Used to install a robot's kernels before its first use.
  * Errors: RBD_E_INVAL, RBD_E_COMPILE. */
-#define RBD_N_KERNELS 30
+#define RBD_N_KERNELS 31
 rbd_status rbd_precompile_topology(int32_t n_bodies, const int32_t* parent, int floating, const char* cache_dir,
                                    int32_t kernel);
 
@@ -327,13 +327,23 @@ rbd_status rbd_server_wait(rbd_server* s, uint64_t ticket, double timeout_s, rbd
  * (it then completes normally). */
 rbd_status rbd_server_cancel(rbd_server* s, uint64_t ticket);
 /* Latency (submit -> results in host memory) and throughput counters since
- * the last reset. */
+ * the last reset, and the device timeline of the launch groups finished since
+ * then, from timing events each group records on its stream (before and after
+ * its input copy, after its packed launch, after its copy-back). */
 typedef struct {
   uint64_t requests, instances, launches;
   double p50_us, p99_us, max_us, mean_us;
-  double busy_s; /* wall time with at least one launch in flight */
+  double busy_s;               /* wall time with at least one launch group in flight    */
+  uint64_t groups_timed;       /* groups on the device timeline (device executor only)  */
+  double gpu_kernel_s;         /* time with at least one packed launch running          */
+  double gpu_kernel_overlap_s; /* time with two or more running (on different streams)  */
+  double gpu_kernel_sum_s;     /* sum of the packed launches' durations                 */
+  double gpu_copy_s;           /* time with at least one input or result copy running   */
+  double gpu_active_s;         /* time with any copy or launch of a group running       */
 } rbd_server_stats;
 rbd_status rbd_server_get_stats(rbd_server* s, rbd_server_stats* out);
+/* Clears the counters and starts a new device timeline (synchronises with
+ * the GPU for a moment to record its origin). */
 rbd_status rbd_server_reset_stats(rbd_server* s);
 /* Drain outstanding requests, then free everything. */
 rbd_status rbd_server_destroy(rbd_server* s);

@@ -262,6 +262,10 @@ rbd_status launch_fwd_dyn_vjp(const rbd_model* m, int64_t batch, int64_t ld, con
     id = KID_VJP_PARK_GQ;
     park_qdd = gqd ? gqd : gq_shift;
     park_lam = gtau ? gtau : gq_shift;
+  } else if (large(m) && (gq || gqd)) {  // one of g_q and g_qd: q-double-dot parks there, lam in registers
+    id = KID_VJP_PARK_QDD;
+    park_qdd = gqd ? gqd : gq_shift;
+    park_lam = nullptr;
   } else if (gq || gqd) {
     id = KID_VJP_REGS;
   } else {

@@ -240,6 +240,15 @@ struct SinkTwo {
     if (r == 0) qdd(k, v); else lam(k, v);
   }
 };
+// q-double-dot parked in an output, lam kept in registers.
+template <class Y>
+struct SinkParkReg {
+  Y qdd;
+  float* lam;
+  RBD_DI void operator()(int r, int k, float v) const {
+    if (r == 0) qdd(k, v); else lam[k] = v;
+  }
+};
 
 template <class TP, bool ADJ, class QI, class X, class GQ, class GQD, class GT, class FX = NoFext, class GF = NoGF>
 RBD_DI void vjp_lane(const float* __restrict__ tab, const QI& q, const X& qd, const X& tau, const X& gqdd,
@@ -278,8 +287,10 @@ struct RowAlias {
 // MODE 0: g_tau only; 1: adjoint with q-double-dot and lam in registers (some
 // output absent); 2: adjoint with both parked in g_qd and g_tau (passed again
 // as park_qdd and park_lam); 3 (large trees): as 2, parked where the launcher
-// chooses, g_qd optional. EXT (modes 1 and 2): external forces fext
-// (nullable: zero) in the dynamics and the force cotangent g_fext (nullable).
+// chooses, g_qd optional; 4 (large trees, one of g_q and g_qd, no g_tau):
+// q-double-dot parked in park_qdd, lam in registers, the adjoint on fresh
+// views. EXT (modes 1 and 2): external forces fext (nullable: zero) in the
+// dynamics and the force cotangent g_fext (nullable).
 template <class TP, int MODE, bool EXT = false>
 __global__ __launch_bounds__(kBlock) void k_fwd_dyn_vjp(const float* __restrict__ tab, int64_t batch, int64_t ld,
                                                         const float* __restrict__ q, const float* __restrict__ qd,
@@ -314,6 +325,18 @@ __global__ __launch_bounds__(kBlock) void k_fwd_dyn_vjp(const float* __restrict_
       vjp_lane<TP, true>(tab, qi, qdi, ti, gi, gqo, OutOpt<OutAlias>{OutAlias{gqd, ld, b}, gqd != nullptr},
                          OutOpt<OutAlias>{OutAlias{gtau, ld, b}, gtau != nullptr}, fx, gf);
     }
+  } else if constexpr (MODE == 4) {
+    // one output to park in: q-double-dot goes there (the adjoint reads each
+    // entry in its body's forward step, before that body's backward step
+    // writes the output), lam stays in registers across the sweep boundary
+    float lam[TP::NV];
+    const OutAliasP pd{{park_qdd, ld, b}};
+    fwd_dyn_lane<TP, 2>(tab, qi, qdi, RhsTwo<In>{ti, gi}, SinkParkReg<OutAliasP>{pd, lam});
+    sweep_boundary();
+    const int64_t l2 = opaque(ld);
+    id_adjoint_lane<TP>(opaque(tab), In{opaque(q), l2, b}, In{opaque(qd), l2, b}, InAlias{park_qdd, l2, b},
+                        RegView{lam}, OutOpt<OutAlias>{OutAlias{gq, l2, b}, gq != nullptr},
+                        OutOpt<OutAlias>{OutAlias{gqd, l2, b}, gqd != nullptr});
   } else if constexpr (MODE >= 2 && TP::NV > 16) {
     // the two sweeps of vjp_lane_parked, the second on fresh views (its own
     // table and input pointers and row stride): a large tree's first sweep
@@ -441,8 +464,17 @@ __global__ __launch_bounds__(kBlock) void k_packed(const float* __restrict__ tab
     } else {
       float* gqd = R.out[1] + i * NV;
       float* gtau = R.out[2] + i * NV;
-      vjp_lane_parked<TP>(tab, q, qd, x2, InRow{R.in[3] + i * NV}, OutRow{R.out[0] + i * NQ}, RowAlias{gqd},
-                          RowAlias{gtau}, RowAlias::In{gqd}, RowAlias::In{gtau});
+      if constexpr (NV > 16) {
+        // the two sweeps on fresh views, as in k_fwd_dyn_vjp
+        fwd_dyn_lane<TP, 2>(tab, q, qd, RhsTwo<InRow>{x2, InRow{R.in[3] + i * NV}},
+                            SinkTwo<RowAlias>{RowAlias{gqd}, RowAlias{gtau}});
+        sweep_boundary();
+        id_adjoint_lane<TP>(opaque(tab), InRow{opaque(R.in[0]) + i * NQ}, InRow{opaque(R.in[1]) + i * NV},
+                            RowAlias::In{gqd}, RowAlias::In{gtau}, OutRow{R.out[0] + i * NQ}, RowAlias{gqd});
+      } else {
+        vjp_lane_parked<TP>(tab, q, qd, x2, InRow{R.in[3] + i * NV}, OutRow{R.out[0] + i * NQ}, RowAlias{gqd},
+                            RowAlias{gtau}, RowAlias::In{gqd}, RowAlias::In{gtau});
+      }
     }
   }
 }

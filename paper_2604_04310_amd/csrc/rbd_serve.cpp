@@ -24,6 +24,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <chrono>
 #include <condition_variable>
 #include <cstring>
@@ -132,6 +133,7 @@ struct Group {
   int op = 0;
   std::vector<std::shared_ptr<Request>> reqs;
   size_t off = 0, bytes = 0, in_bytes = 0, out_off = 0, out_bytes = 0;
+  bool timed = false;  // its timeline events were recorded
   std::vector<size_t> in_pos, out_pos;  // per request, offsets inside the block
   int n_tiles = 0;
   rbd_status status = RBD_OK;
@@ -139,7 +141,9 @@ struct Group {
 
 struct Slot {
   hipStream_t stream = nullptr;
-  hipEvent_t done = nullptr;
+  // device timeline of the slot's current group: before the input copy,
+  // after it (the packed launch starts), after the launch, after the copy-back
+  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
   uint8_t* d_table = nullptr;
   uint8_t* h_table = nullptr;
   bool busy = false;  // guarded by the server's mutex
@@ -187,6 +191,11 @@ struct rbd_server {
   uint64_t n_req = 0, n_inst = 0, n_launch = 0;
   double busy_s = 0.0;
   Clock::time_point busy_since;
+  // device timeline since the last reset: per group, the times (ms after
+  // `ref`) of its four slot events
+  hipStream_t ref_stream = nullptr;
+  hipEvent_t ref = nullptr;
+  std::vector<std::array<float, 4>> timeline;
 };
 
 namespace rbd {
@@ -335,8 +344,10 @@ rbd_status launch_group(rbd_server* s, Group* g) {
   hdr->pad = 0;
   const size_t table_bytes = req_off + sizeof(PackedReq) * g->reqs.size();
   hipStream_t st = sl.stream;
-  if (hipMemcpyAsync(db, hb, g->in_bytes, hipMemcpyHostToDevice, st) != hipSuccess ||
-      hipMemcpyAsync(sl.d_table, sl.h_table, table_bytes, hipMemcpyHostToDevice, st) != hipSuccess)
+  if (hipEventRecord(sl.ev[0], st) != hipSuccess ||
+      hipMemcpyAsync(db, hb, g->in_bytes, hipMemcpyHostToDevice, st) != hipSuccess ||
+      hipMemcpyAsync(sl.d_table, sl.h_table, table_bytes, hipMemcpyHostToDevice, st) != hipSuccess ||
+      hipEventRecord(sl.ev[1], st) != hipSuccess)
     return fail(RBD_E_LAUNCH, "server: input copy failed");
   const int grid = s->cfg.per_request ? std::max(1, (g->n_tiles * kTileLanes + 255) / 256) : grid_class(g->n_tiles);
   rbd_status rs = RBD_OK;
@@ -367,9 +378,11 @@ rbd_status launch_group(rbd_server* s, Group* g) {
     rs = launch_packed(g->model, g->op, sl.d_table, grid, st);
     if (rs != RBD_OK) return rs;
   }
-  if (hipMemcpyAsync(hb + g->out_off, db + g->out_off, g->out_bytes, hipMemcpyDeviceToHost, st) != hipSuccess ||
-      hipEventRecord(sl.done, st) != hipSuccess)
+  if (hipEventRecord(sl.ev[2], st) != hipSuccess ||
+      hipMemcpyAsync(hb + g->out_off, db + g->out_off, g->out_bytes, hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipEventRecord(sl.ev[3], st) != hipSuccess)
     return fail(RBD_E_LAUNCH, "server: result copy failed");
+  g->timed = true;
   return RBD_OK;
 }
 
@@ -387,6 +400,13 @@ void finish_group(rbd_server* s, Group* g, const Clock::time_point now) {
     }
   }
   std::lock_guard<std::mutex> lk(s->mu);
+  if (g->status == RBD_OK && g->timed) {
+    const Slot& sl = *s->slots[g->slot];
+    std::array<float, 4> t{};
+    bool ok = true;
+    for (int k = 0; k < 4; ++k) ok = ok && hipEventElapsedTime(&t[k], s->ref, sl.ev[k]) == hipSuccess;
+    if (ok) s->timeline.push_back(t);
+  }
   s->arena.release(g->off, g->bytes);
   s->slots[g->slot]->busy = false;
   if (--s->n_busy == 0) s->busy_s += std::chrono::duration<double>(now - s->busy_since).count();
@@ -419,7 +439,7 @@ void run_group(rbd_server* s, Slot& sl, Group* g) {
         (void)hipStreamSynchronize(sl.stream);  // no callback will come: wait here instead
       }
       // an error of the group's device work shows in its event
-      if (hipEventQuery(sl.done) != hipSuccess) g->status = fail(RBD_E_LAUNCH, "server: launch failed on the device");
+      if (hipEventQuery(sl.ev[3]) != hipSuccess) g->status = fail(RBD_E_LAUNCH, "server: launch failed on the device");
     }
   }
   finish_group(s, g, Clock::now());
@@ -524,10 +544,14 @@ rbd_status rbd_server_create(const rbd_server_config* cfg, rbd_server** out) {
     const size_t tcap = table_capacity(cfg->max_batch_requests);
     for (auto& sl : s->slots) {
       ok = ok && hipStreamCreateWithFlags(&sl->stream, hipStreamNonBlocking) == hipSuccess &&
-           hipEventCreateWithFlags(&sl->done, hipEventDisableTiming) == hipSuccess &&
+           hipEventCreate(&sl->ev[0]) == hipSuccess && hipEventCreate(&sl->ev[1]) == hipSuccess &&
+           hipEventCreate(&sl->ev[2]) == hipSuccess && hipEventCreate(&sl->ev[3]) == hipSuccess &&
            hipMalloc(&sl->d_table, tcap) == hipSuccess &&
            hipHostMalloc(&sl->h_table, tcap, hipHostMallocDefault) == hipSuccess;
     }
+    ok = ok && hipStreamCreateWithFlags(&s->ref_stream, hipStreamNonBlocking) == hipSuccess &&
+         hipEventCreate(&s->ref) == hipSuccess && hipEventRecord(s->ref, s->ref_stream) == hipSuccess &&
+         hipEventSynchronize(s->ref) == hipSuccess;
   }
   if (!ok) {
     rbd_server_destroy(s);
@@ -634,6 +658,32 @@ rbd_status rbd_server_get_stats(rbd_server* s, rbd_server_stats* out) {
     for (double x : s->lat_us) sum += x;
     out->mean_us = sum / (double)s->lat_us.size();
   }
+  // device timeline: kernel intervals [t1, t2], copies [t0, t1] and [t2, t3]
+  std::vector<std::pair<float, int>> kev, cev, aev;
+  for (const auto& t : s->timeline) {
+    kev.push_back({t[1], 1}); kev.push_back({t[2], -1});
+    cev.push_back({t[0], 1}); cev.push_back({t[1], -1}); cev.push_back({t[2], 1}); cev.push_back({t[3], -1});
+    aev.push_back({t[0], 1}); aev.push_back({t[3], -1});
+  }
+  // time (s) covered by at least `k` of the intervals
+  auto covered = [](std::vector<std::pair<float, int>>& ev, int k) {
+    std::sort(ev.begin(), ev.end());
+    double tot = 0.0;
+    int depth = 0;
+    for (size_t i = 0; i < ev.size(); ++i) {
+      if (i > 0 && depth >= k) tot += (double)(ev[i].first - ev[i - 1].first);
+      depth += ev[i].second;
+    }
+    return tot * 1e-3;
+  };
+  double ksum = 0.0;
+  for (const auto& t : s->timeline) ksum += (double)(t[2] - t[1]) * 1e-3;
+  out->groups_timed = s->timeline.size();
+  out->gpu_kernel_s = covered(kev, 1);
+  out->gpu_kernel_overlap_s = covered(kev, 2);
+  out->gpu_kernel_sum_s = ksum;
+  out->gpu_copy_s = covered(cev, 1);
+  out->gpu_active_s = covered(aev, 1);
   return RBD_OK;
 }
 
@@ -644,6 +694,12 @@ rbd_status rbd_server_reset_stats(rbd_server* s) {
   s->n_req = s->n_inst = s->n_launch = 0;
   s->busy_s = 0.0;
   s->busy_since = Clock::now();
+  s->timeline.clear();
+  if (!s->host_exec) {  // a new origin for the device timeline
+    (void)hipSetDevice(s->cfg.device);
+    if (hipEventRecord(s->ref, s->ref_stream) != hipSuccess || hipEventSynchronize(s->ref) != hipSuccess)
+      return fail(RBD_E_LAUNCH, "rbd_server_reset_stats: timeline origin could not be recorded");
+  }
   return RBD_OK;
 }
 
@@ -672,11 +728,14 @@ rbd_status rbd_server_destroy(rbd_server* s) {
   for (auto& sl : s->slots) {
     for (auto& kv : sl->graphs) (void)hipGraphExecDestroy(kv.second);
     if (sl->stream) (void)hipStreamSynchronize(sl->stream);
-    if (sl->done) (void)hipEventDestroy(sl->done);
+    for (hipEvent_t e : sl->ev)
+      if (e) (void)hipEventDestroy(e);
     if (sl->stream) (void)hipStreamDestroy(sl->stream);
     if (sl->d_table) (void)hipFree(sl->d_table);
     if (sl->h_table) (void)hipHostFree(sl->h_table);
   }
+  if (s->ref) (void)hipEventDestroy(s->ref);
+  if (s->ref_stream) (void)hipStreamDestroy(s->ref_stream);
   if (s->d_arena) (void)hipFree(s->d_arena);
   if (s->h_stage) (void)hipHostFree(s->h_stage);
   delete s;

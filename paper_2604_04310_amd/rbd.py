@@ -70,7 +70,9 @@ class LoadRequestC(C.Structure):
 class ServerStatsC(C.Structure):
     _fields_ = [("requests", C.c_uint64), ("instances", C.c_uint64), ("launches", C.c_uint64),
                 ("p50_us", C.c_double), ("p99_us", C.c_double), ("max_us", C.c_double), ("mean_us", C.c_double),
-                ("busy_s", C.c_double)]
+                ("busy_s", C.c_double), ("groups_timed", C.c_uint64), ("gpu_kernel_s", C.c_double),
+                ("gpu_kernel_overlap_s", C.c_double), ("gpu_kernel_sum_s", C.c_double), ("gpu_copy_s", C.c_double),
+                ("gpu_active_s", C.c_double)]
 
 
 _lib = None
@@ -137,7 +139,7 @@ def fma_rate(blocks: int = 256, ilp: int = 16, device: int = 0) -> float:
     return out.value
 
 
-N_KERNELS = 30
+N_KERNELS = 31
 
 
 def precompile_topology(parent, floating: bool, cache_dir: Optional[str] = None, kernel: int = -1) -> None:

@@ -130,6 +130,6 @@ def test_compiled_on_the_device_host(rbd, tmp_path, monkeypatch):
     assert rel_err(qdd, O.fwd_dyn(desc, st.q, st.qd, st.tau)) < TOL_QDD
     assert n_code_objects() == 1
     check_every_row(rbd, m, desc, 90)
-    assert 10 <= n_code_objects() <= 30
+    assert 10 <= n_code_objects() <= rbd.N_KERNELS + 6  # a controller frame or two may add its own
     m2 = rbd.Model(desc_of(False, [-1, 0, 0], 91), 0)
     assert m2.topology == m.topology

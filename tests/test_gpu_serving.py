@@ -179,3 +179,26 @@ def test_a_new_model_never_replays_a_destroyed_models_graphs(env):
         assert np.array_equal(outs[0], direct)
         m.close()
     srv.close()
+
+
+def test_native_load_generator_on_the_device(env):
+    """rbd_diag_serve_load against the device executor: closed loop and Poisson arrivals complete
+    every request with status OK, and the server counts each request once."""
+    rbd, descs, models = env
+    reqs = make_requests(rbd, descs, 12, 7)
+    specs = [(models[n], op, ins) for n, op, ins in reqs]
+    srv = rbd.Server(arena_bytes=64 << 20, n_streams=3, max_batch_requests=64)
+    srv.reset_stats()
+    wall, failed = srv.load(specs, 240, rate=0.0, window=48, seed=1)
+    st = srv.stats()
+    assert failed == 0 and st["requests"] == 240 and 0 < st["launches"] <= 240 and wall > 0
+    # the device timeline: every group timed, kernels inside the active time, overlap inside kernel time
+    assert st["groups_timed"] == st["launches"]
+    assert 0 < st["gpu_kernel_s"] <= st["gpu_kernel_sum_s"] + 1e-9
+    assert st["gpu_kernel_overlap_s"] <= st["gpu_kernel_s"] + 1e-9
+    assert st["gpu_kernel_s"] <= st["gpu_active_s"] + 1e-9 and st["gpu_active_s"] <= 1.05 * wall + 1e-3
+    assert 0 < st["gpu_copy_s"] <= st["gpu_active_s"] + 1e-9
+    srv.reset_stats()
+    wall, failed = srv.load(specs, 120, rate=5000.0, window=24, seed=2)
+    assert failed == 0 and srv.stats()["requests"] == 120
+    srv.close()

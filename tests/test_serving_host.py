@@ -189,6 +189,7 @@ def test_native_load_generator(rbd, models):
     st = srv.stats()
     assert failed == 0 and wall > 0
     assert st["requests"] == 600 and st["instances"] == 100 * n_inst and st["launches"] <= 600
+    assert st["groups_timed"] == 0 and st["gpu_kernel_s"] == 0.0  # no device timeline without a device
     srv.reset_stats()
     wall, failed = srv.load(specs, 300, rate=20000.0, window=64, seed=4)
     assert failed == 0 and srv.stats()["requests"] == 300
