@@ -97,6 +97,7 @@ static inline unsigned grid_for(int64_t batch) { return (unsigned)((batch + kBlo
 constexpr int64_t kOneWavePerSimd = 256 * 4 * 64;
 struct Shape {
   dim3 grid, block;
+  unsigned lds = 0;  // dynamic LDS bytes per block
 };
 static inline Shape heavy_shape(int64_t batch) {
   const unsigned blk = batch <= kOneWavePerSimd ? 64 : kBlock;
@@ -118,11 +119,11 @@ static rbd_status launch(const rbd_model* m, KernelId id, Shape sh, void** args,
     hipFunction_t f = nullptr;
     const rbd_status st = jit_function(ks, id, &f);
     if (st != RBD_OK) return st;
-    e = hipModuleLaunchKernel(f, sh.grid.x, sh.grid.y, sh.grid.z, sh.block.x, sh.block.y, sh.block.z, 0, s, args,
-                              nullptr);
+    e = hipModuleLaunchKernel(f, sh.grid.x, sh.grid.y, sh.grid.z, sh.block.x, sh.block.y, sh.block.z, sh.lds, s,
+                              args, nullptr);
   } else {
     if (!ks->aot[id]) return fail(RBD_E_UNSUPPORTED, "%s: kernel %d was not compiled", what, (int)id);
-    e = hipLaunchKernel(ks->aot[id], sh.grid, sh.block, args, 0, s);
+    e = hipLaunchKernel(ks->aot[id], sh.grid, sh.block, args, sh.lds, s);
   }
   if (e == hipSuccess) e = hipGetLastError();
   if (e != hipSuccess) return fail(RBD_E_LAUNCH, "%s: launch failed: %s", what, hipGetErrorString(e));
@@ -238,12 +239,10 @@ rbd_status launch_osc(const rbd_model* m, int64_t batch, int64_t ld, const float
   return launch_frame(m, true, frame, heavy_shape(batch), a, s, "rbd_osc");
 }
 
-// Between the solve and the adjoint sweep, q-double-dot and lam park in
-// output rows that the adjoint overwrites only after reading them: g_qd and
-// g_tau, or, for a large tree missing one of those, g_q shifted by nq - nv
-// rows, so that DoF k lands in the q slot of its own body (the adjoint reads a
-// body's entries in its forward step and writes that body's g_q in its
-// backward step). With external forces they park in g_qd and g_tau or stay in
+// Between the solve and the adjoint sweep, q-double-dot and lam park: for a
+// large tree in LDS (any output set); for a small tree in the g_qd and g_tau
+// rows, which the adjoint overwrites only after reading them, or in
+// registers. With external forces they park in g_qd and g_tau or stay in
 // registers.
 rbd_status launch_fwd_dyn_vjp(const rbd_model* m, int64_t batch, int64_t ld, const float* q, const float* qd,
                               const float* tau, const float* fext, const float* gqdd, float* gq, float* gqd,
@@ -256,16 +255,19 @@ rbd_status launch_fwd_dyn_vjp(const rbd_model* m, int64_t batch, int64_t ld, con
   // cotangent; g_tau = M^-1 g_qdd does not depend on them
   if (gfext || (fext && (gq || gqd))) {
     id = (gqd && gtau) ? KID_VJP_EXT_PARK : KID_VJP_EXT_REGS;
+  } else if (large(m) && (gq || gqd)) {
+    // q-double-dot and lam park in LDS: 64-lane blocks (one wave each), 2 nv floats per lane
+    const float* tab = m->d_tab;
+    void* a[] = {&tab, &batch, &ld, &q, &qd, &tau, &gqdd, &gq, &gqd, &gtau, &park_qdd, &park_lam, &fext, &gfext};
+    Shape sh{dim3((unsigned)((batch + kTileLanes - 1) / kTileLanes)), dim3(kTileLanes),
+             (unsigned)(2 * m->nv * kTileLanes * sizeof(float))};
+    return launch(m, KID_VJP_LDS, sh, a, s, "rbd_fwd_dyn_vjp");
   } else if (gqd && gtau) {
     id = KID_VJP_PARK;
   } else if (large(m) && gq && (gqd || gtau)) {
     id = KID_VJP_PARK_GQ;
     park_qdd = gqd ? gqd : gq_shift;
     park_lam = gtau ? gtau : gq_shift;
-  } else if (large(m) && (gq || gqd)) {  // one of g_q and g_qd: q-double-dot parks there, lam in registers
-    id = KID_VJP_PARK_QDD;
-    park_qdd = gqd ? gqd : gq_shift;
-    park_lam = nullptr;
   } else if (gq || gqd) {
     id = KID_VJP_REGS;
   } else {

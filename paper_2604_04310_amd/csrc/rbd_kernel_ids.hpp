@@ -40,7 +40,7 @@
   X(KID_VJP_EXT_REGS, 8, k_fwd_dyn_vjp<TP, 1, true>)      \
   X(KID_VJP_EXT_PARK, 8, k_fwd_dyn_vjp<TP, 2, true>)      \
   X(KID_JVP_EXT, 8, k_fwd_dyn_jvp<TP, true>)            \
-  X(KID_VJP_PARK_QDD, 3, k_fwd_dyn_vjp<TP, 4>)
+  X(KID_VJP_LDS, 3, k_fwd_dyn_vjp<TP, 4>)
 
 namespace rbd {
 

@@ -19,9 +19,18 @@ RBD_DI uint32_t lane_id() { return blockIdx.x * blockDim.x + threadIdx.x; }
 // so model constants, inputs, row addresses and what is computed from them
 // (joint sines and cosines) are reloaded and recomputed in each sweep instead
 // of being held in registers across all of them.
+// The asm operand keeps the pointer's address space (global for inputs,
+// constant for the model table), so loads through the copy stay global loads
+// with a scalar base, and table reads stay scalar loads.
 RBD_DI const float* opaque(const float* p) {
-  asm volatile("" : "+s"(p));
-  return p;
+  auto g = (const __attribute__((address_space(1))) float*)p;
+  asm volatile("" : "+s"(g));
+  return (const float*)g;
+}
+RBD_DI const float* opaque_table(const float* p) {
+  auto c = (const __attribute__((address_space(4))) float*)p;
+  asm volatile("" : "+s"(c));
+  return (const float*)c;
 }
 RBD_DI int64_t opaque(int64_t x) {
   asm volatile("" : "+s"(x));
@@ -240,14 +249,16 @@ struct SinkTwo {
     if (r == 0) qdd(k, v); else lam(k, v);
   }
 };
-// q-double-dot parked in an output, lam kept in registers.
-template <class Y>
-struct SinkParkReg {
-  Y qdd;
-  float* lam;
-  RBD_DI void operator()(int r, int k, float v) const {
-    if (r == 0) qdd(k, v); else lam[k] = v;
-  }
+// A per-lane row parked in LDS: entry c of lane l of a wave at
+// p[c * 64 + l] (consecutive lanes in consecutive banks; the entry offset is
+// a compile-time immediate).
+struct LdsRow {
+  float* p;
+  RBD_DI void operator()(int c, float v) const { p[c * kTileLanes] = v; }
+  struct In {
+    const float* p;
+    RBD_DI float operator()(int c) const { return p[c * kTileLanes]; }
+  };
 };
 
 template <class TP, bool ADJ, class QI, class X, class GQ, class GQD, class GT, class FX = NoFext, class GF = NoGF>
@@ -276,10 +287,12 @@ RBD_DI void vjp_lane_parked(const float* __restrict__ tab, const QI& q, const X&
 }
 
 struct RowAlias {
-  float* p;
+  GlobalF* p;
+  RBD_DI RowAlias(float* q) : p((GlobalF*)q) {}
   RBD_DI void operator()(int c, float v) const { p[c] = v; }
   struct In {
-    const float* p;
+    const GlobalF* p;
+    RBD_DI In(const float* q) : p((const GlobalF*)q) {}
     RBD_DI float operator()(int c) const { return p[c]; }
   };
 };
@@ -287,10 +300,10 @@ struct RowAlias {
 // MODE 0: g_tau only; 1: adjoint with q-double-dot and lam in registers (some
 // output absent); 2: adjoint with both parked in g_qd and g_tau (passed again
 // as park_qdd and park_lam); 3 (large trees): as 2, parked where the launcher
-// chooses, g_qd optional; 4 (large trees, one of g_q and g_qd, no g_tau):
-// q-double-dot parked in park_qdd, lam in registers, the adjoint on fresh
-// views. EXT (modes 1 and 2): external forces fext (nullable: zero) in the
-// dynamics and the force cotangent g_fext (nullable).
+// chooses, g_qd optional; 4 (large trees, any outputs): q-double-dot and lam
+// parked in LDS (dynamic shared memory, 2 NV floats per lane), the adjoint on
+// fresh views. EXT (modes 1 and 2): external forces fext (nullable: zero) in
+// the dynamics and the force cotangent g_fext (nullable).
 template <class TP, int MODE, bool EXT = false>
 __global__ __launch_bounds__(kBlock) void k_fwd_dyn_vjp(const float* __restrict__ tab, int64_t batch, int64_t ld,
                                                         const float* __restrict__ q, const float* __restrict__ qd,
@@ -315,7 +328,7 @@ __global__ __launch_bounds__(kBlock) void k_fwd_dyn_vjp(const float* __restrict_
         sweep_boundary();
         const int64_t l2 = opaque(ld);
         const OutOpt<OutAlias> gqo2{OutAlias{gq, l2, b}, gq != nullptr};
-        id_adjoint_lane<TP>(opaque(tab), In{opaque(q), l2, b}, In{opaque(qd), l2, b}, InAlias{gqd, l2, b},
+        id_adjoint_lane<TP>(opaque_table(tab), In{opaque(q), l2, b}, In{opaque(qd), l2, b}, InAlias{gqd, l2, b},
                             InAlias{gtau, l2, b}, gqo2, OutAlias{gqd, l2, b}, FextOpt{{opaque(fext), l2, b}},
                             GFOut{{gfext, l2, b}});
       } else {
@@ -326,16 +339,21 @@ __global__ __launch_bounds__(kBlock) void k_fwd_dyn_vjp(const float* __restrict_
                          OutOpt<OutAlias>{OutAlias{gtau, ld, b}, gtau != nullptr}, fx, gf);
     }
   } else if constexpr (MODE == 4) {
-    // one output to park in: q-double-dot goes there (the adjoint reads each
-    // entry in its body's forward step, before that body's backward step
-    // writes the output), lam stays in registers across the sweep boundary
-    float lam[TP::NV];
-    const OutAliasP pd{{park_qdd, ld, b}};
-    fwd_dyn_lane<TP, 2>(tab, qi, qdi, RhsTwo<In>{ti, gi}, SinkParkReg<OutAliasP>{pd, lam});
+    // each wave's region of the block's dynamic LDS: [qdd rows | lam rows]
+    extern __shared__ float lds_park[];
+    constexpr int NV = TP::NV;
+    float* const w = lds_park + (threadIdx.x / kTileLanes) * (2 * NV * kTileLanes) + (threadIdx.x % kTileLanes);
+    fwd_dyn_lane<TP, 2>(tab, qi, qdi, RhsTwo<In>{ti, gi}, SinkTwo<LdsRow>{LdsRow{w}, LdsRow{w + NV * kTileLanes}});
+    if (gtau) {
+      sfor<0, NV>([&](auto K_) __attribute__((always_inline)) {
+        constexpr int K = decltype(K_)::value;
+        Out{gtau, ld, b}(K, w[(NV + K) * kTileLanes]);
+      });
+    }
     sweep_boundary();
     const int64_t l2 = opaque(ld);
-    id_adjoint_lane<TP>(opaque(tab), In{opaque(q), l2, b}, In{opaque(qd), l2, b}, InAlias{park_qdd, l2, b},
-                        RegView{lam}, OutOpt<OutAlias>{OutAlias{gq, l2, b}, gq != nullptr},
+    id_adjoint_lane<TP>(opaque_table(tab), In{opaque(q), l2, b}, In{opaque(qd), l2, b}, LdsRow::In{w},
+                        LdsRow::In{w + NV * kTileLanes}, OutOpt<OutAlias>{OutAlias{gq, l2, b}, gq != nullptr},
                         OutOpt<OutAlias>{OutAlias{gqd, l2, b}, gqd != nullptr});
   } else if constexpr (MODE >= 2 && TP::NV > 16) {
     // the two sweeps of vjp_lane_parked, the second on fresh views (its own
@@ -353,10 +371,10 @@ __global__ __launch_bounds__(kBlock) void k_fwd_dyn_vjp(const float* __restrict_
     const int64_t l2 = opaque(ld);
     const OutOpt<OutAlias> gqo2{OutAlias{gq, l2, b}, gq != nullptr};
     if constexpr (MODE == 2)
-      id_adjoint_lane<TP>(opaque(tab), In{opaque(q), l2, b}, In{opaque(qd), l2, b}, InAlias{pq, l2, b},
+      id_adjoint_lane<TP>(opaque_table(tab), In{opaque(q), l2, b}, In{opaque(qd), l2, b}, InAlias{pq, l2, b},
                           InAlias{pl, l2, b}, gqo2, OutAlias{gqd, l2, b});
     else
-      id_adjoint_lane<TP>(opaque(tab), In{opaque(q), l2, b}, In{opaque(qd), l2, b}, InAlias{pq, l2, b},
+      id_adjoint_lane<TP>(opaque_table(tab), In{opaque(q), l2, b}, In{opaque(qd), l2, b}, InAlias{pq, l2, b},
                           InAlias{pl, l2, b}, gqo2, OutOpt<OutAlias>{OutAlias{gqd, l2, b}, gqd != nullptr});
   } else if constexpr (MODE == 2) {
     const OutAliasP pd{{gqd, ld, b}}, pt{{gtau, ld, b}};
@@ -398,13 +416,17 @@ __global__ __launch_bounds__(kBlock) void k_fwd_dyn_jvp(const float* __restrict_
     if constexpr (kFresh) return opaque(x);
     else return x;
   };
+  auto view_table = [](const float* x) __attribute__((always_inline)) {
+    if constexpr (kFresh) return opaque_table(x);
+    else return x;
+  };
   const int64_t ld2 = view(ld);
-  id_tangent_lane<TP>(view(tab), In{view(q), ld2, b}, In{view(qd), ld2, b}, InAlias{park, ld2, b},
+  id_tangent_lane<TP>(view_table(tab), In{view(q), ld2, b}, In{view(qd), ld2, b}, InAlias{park, ld2, b},
                       In{dq, ld2, b}, In{dqd, ld2, b}, In{dtau, ld2, b}, OutAlias{dqdd, ld2, b},
                       fx_view(fext, ld2), fx_view(dfext, ld2));
   const int64_t ld3 = view(ld2);
   fwd_dyn_lane<TP, 1, In, In, RhsOne<InAlias>, SinkOne<OutAlias>, NoFext, false>(
-      view(tab), In{view(q), ld3, b}, In{qd, ld3, b}, RhsOne<InAlias>{InAlias{dqdd, ld3, b}},
+      view_table(tab), In{view(q), ld3, b}, In{qd, ld3, b}, RhsOne<InAlias>{InAlias{dqdd, ld3, b}},
       SinkOne<OutAlias>{OutAlias{dqdd, ld3, b}});
 }
 
@@ -469,7 +491,7 @@ __global__ __launch_bounds__(kBlock) void k_packed(const float* __restrict__ tab
         fwd_dyn_lane<TP, 2>(tab, q, qd, RhsTwo<InRow>{x2, InRow{R.in[3] + i * NV}},
                             SinkTwo<RowAlias>{RowAlias{gqd}, RowAlias{gtau}});
         sweep_boundary();
-        id_adjoint_lane<TP>(opaque(tab), InRow{opaque(R.in[0]) + i * NQ}, InRow{opaque(R.in[1]) + i * NV},
+        id_adjoint_lane<TP>(opaque_table(tab), InRow{opaque(R.in[0]) + i * NQ}, InRow{opaque(R.in[1]) + i * NV},
                             RowAlias::In{gqd}, RowAlias::In{gtau}, OutRow{R.out[0] + i * NQ}, RowAlias{gqd});
       } else {
         vjp_lane_parked<TP>(tab, q, qd, x2, InRow{R.in[3] + i * NV}, OutRow{R.out[0] + i * NQ}, RowAlias{gqd},

@@ -404,13 +404,18 @@ struct OutNT {
   uint32_t lane;
   RBD_DI void operator()(int c, float v) const { __builtin_nontemporal_store(v, lane_ptr(base + c * ld, lane)); }
 };
-// A lane's own row of an instance-major array (coordinate c at p[c]).
+// A lane's own row of an instance-major array (coordinate c at p[c]). The
+// row pointers come from a table in memory, so they are typed as global
+// memory here: loads and stores through them are global, not flat.
+using GlobalF = __attribute__((address_space(1))) float;
 struct InRow {
-  const float* __restrict__ p;
+  const GlobalF* __restrict__ p;
+  RBD_DI InRow(const float* q) : p((const GlobalF*)q) {}
   RBD_DI float operator()(int c) const { return p[c]; }
 };
 struct OutRow {
-  float* __restrict__ p;
+  GlobalF* __restrict__ p;
+  RBD_DI OutRow(float* q) : p((GlobalF*)q) {}
   RBD_DI void operator()(int c, float v) const { p[c] = v; }
 };
 
