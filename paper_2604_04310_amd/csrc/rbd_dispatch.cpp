@@ -240,41 +240,29 @@ rbd_status launch_osc(const rbd_model* m, int64_t batch, int64_t ld, const float
 }
 
 // Between the solve and the adjoint sweep, q-double-dot and lam park: for a
-// large tree in LDS (any output set); for a small tree in the g_qd and g_tau
-// rows, which the adjoint overwrites only after reading them, or in
-// registers. With external forces they park in g_qd and g_tau or stay in
-// registers.
+// large tree in LDS, whatever outputs are requested (64-lane blocks, one wave
+// each, 2 nv floats per lane); for a small tree in the g_qd and g_tau rows
+// when both are requested (the adjoint overwrites them only after reading
+// them), else in registers.
 rbd_status launch_fwd_dyn_vjp(const rbd_model* m, int64_t batch, int64_t ld, const float* q, const float* qd,
                               const float* tau, const float* fext, const float* gqdd, float* gq, float* gqd,
                               float* gtau, float* gfext, hipStream_t s) {
   if (batch == 0 || (!gq && !gqd && !gtau && !gfext)) return RBD_OK;
-  float* const gq_shift = gq ? gq + (int64_t)(m->nq - m->nv) * ld : nullptr;
-  KernelId id;
-  float *park_qdd = gqd, *park_lam = gtau;
   // external forces matter to g_q and g_qd (through qdd) and the force
   // cotangent; g_tau = M^-1 g_qdd does not depend on them
-  if (gfext || (fext && (gq || gqd))) {
-    id = (gqd && gtau) ? KID_VJP_EXT_PARK : KID_VJP_EXT_REGS;
-  } else if (large(m) && (gq || gqd)) {
-    // q-double-dot and lam park in LDS: 64-lane blocks (one wave each), 2 nv floats per lane
-    const float* tab = m->d_tab;
-    void* a[] = {&tab, &batch, &ld, &q, &qd, &tau, &gqdd, &gq, &gqd, &gtau, &park_qdd, &park_lam, &fext, &gfext};
-    Shape sh{dim3((unsigned)((batch + kTileLanes - 1) / kTileLanes)), dim3(kTileLanes),
-             (unsigned)(2 * m->nv * kTileLanes * sizeof(float))};
-    return launch(m, KID_VJP_LDS, sh, a, s, "rbd_fwd_dyn_vjp");
-  } else if (gqd && gtau) {
-    id = KID_VJP_PARK;
-  } else if (large(m) && gq && (gqd || gtau)) {
-    id = KID_VJP_PARK_GQ;
-    park_qdd = gqd ? gqd : gq_shift;
-    park_lam = gtau ? gtau : gq_shift;
-  } else if (gq || gqd) {
-    id = KID_VJP_REGS;
-  } else {
-    id = KID_VJP_TAU;
-  }
+  const bool ext = gfext || (fext && (gq || gqd));
   const float* tab = m->d_tab;
-  void* a[] = {&tab, &batch, &ld, &q, &qd, &tau, &gqdd, &gq, &gqd, &gtau, &park_qdd, &park_lam, &fext, &gfext};
+  void* a[] = {&tab, &batch, &ld, &q, &qd, &tau, &gqdd, &gq, &gqd, &gtau, &fext, &gfext};
+  if (large(m) && (gq || gqd || gfext)) {
+    const Shape sh{dim3((unsigned)((batch + kTileLanes - 1) / kTileLanes)), dim3(kTileLanes),
+                   (unsigned)(2 * m->nv * kTileLanes * sizeof(float))};
+    return launch(m, ext ? KID_VJP_EXT_LDS : KID_VJP_LDS, sh, a, s, "rbd_fwd_dyn_vjp");
+  }
+  KernelId id;
+  if (ext) id = (gqd && gtau) ? KID_VJP_EXT_PARK : KID_VJP_EXT_REGS;
+  else if (gqd && gtau) id = KID_VJP_PARK;
+  else if (gq || gqd) id = KID_VJP_REGS;
+  else id = KID_VJP_TAU;
   return launch(m, id, heavy_shape(batch), a, s, "rbd_fwd_dyn_vjp");
 }
 

@@ -24,7 +24,6 @@
   X(KID_VJP_TAU, 3, k_fwd_dyn_vjp<TP, 0>)                 \
   X(KID_VJP_REGS, 3, k_fwd_dyn_vjp<TP, 1>)                \
   X(KID_VJP_PARK, 3, k_fwd_dyn_vjp<TP, 2>)                \
-  X(KID_VJP_PARK_GQ, 3, k_fwd_dyn_vjp<TP, 3>)             \
   X(KID_PACKED_VJP, 3, k_packed<TP, 2>)                   \
   X(KID_ABA, 4, k_aba<TP, false, false>)                  \
   X(KID_ABA_PRE, 4, k_aba<TP, true, false>)               \
@@ -40,7 +39,8 @@
   X(KID_VJP_EXT_REGS, 8, k_fwd_dyn_vjp<TP, 1, true>)      \
   X(KID_VJP_EXT_PARK, 8, k_fwd_dyn_vjp<TP, 2, true>)      \
   X(KID_JVP_EXT, 8, k_fwd_dyn_jvp<TP, true>)            \
-  X(KID_VJP_LDS, 3, k_fwd_dyn_vjp<TP, 4>)
+  X(KID_VJP_LDS, 3, k_fwd_dyn_vjp<TP, 3>)                 \
+  X(KID_VJP_EXT_LDS, 8, k_fwd_dyn_vjp<TP, 3, true>)
 
 namespace rbd {
 

@@ -298,52 +298,43 @@ struct RowAlias {
 };
 
 // MODE 0: g_tau only; 1: adjoint with q-double-dot and lam in registers (some
-// output absent); 2: adjoint with both parked in g_qd and g_tau (passed again
-// as park_qdd and park_lam); 3 (large trees): as 2, parked where the launcher
-// chooses, g_qd optional; 4 (large trees, any outputs): q-double-dot and lam
-// parked in LDS (dynamic shared memory, 2 NV floats per lane), the adjoint on
-// fresh views. EXT (modes 1 and 2): external forces fext (nullable: zero) in
-// the dynamics and the force cotangent g_fext (nullable).
+// output absent); 2: adjoint with both parked in g_qd and g_tau (both
+// requested); 3 (large trees, any outputs): both parked in LDS (dynamic shared
+// memory, 2 NV floats per lane), the adjoint on fresh views. EXT (modes 1 to
+// 3): external forces fext (nullable: zero) in the dynamics and the force
+// cotangent g_fext (nullable).
 template <class TP, int MODE, bool EXT = false>
 __global__ __launch_bounds__(kBlock) void k_fwd_dyn_vjp(const float* __restrict__ tab, int64_t batch, int64_t ld,
                                                         const float* __restrict__ q, const float* __restrict__ qd,
                                                         const float* __restrict__ tau,
                                                         const float* __restrict__ gqdd, float* gq, float* gqd,
-                                                        float* gtau, float* park_qdd, float* park_lam,
-                                                        const float* __restrict__ fext, float* gfext) {
-  static_assert(!EXT || MODE == 1 || MODE == 2, "external forces: modes 1 and 2");
+                                                        float* gtau, const float* __restrict__ fext, float* gfext) {
+  static_assert(!EXT || MODE >= 1, "external forces: modes 1 to 3");
   RBD_LANE_IO(TP);
   const uint32_t b = lane_id();
   if (b >= batch) return;
   const In qi{q, ld, b}, qdi{qd, ld, b}, ti{tau, ld, b}, gi{gqdd, ld, b};
   const OutOpt<OutAlias> gqo{OutAlias{gq, ld, b}, gq != nullptr};
-  if constexpr (EXT) {
-    const FextOpt fx{{fext, ld, b}};
-    const GFOut gf{{gfext, ld, b}};
-    if constexpr (MODE == 2) {
-      const OutAliasP pd{{gqd, ld, b}}, pt{{gtau, ld, b}};
-      if constexpr (TP::NV > 16) {
-        // fresh views for the second sweep (as below)
-        fwd_dyn_lane<TP, 2>(tab, qi, qdi, RhsTwo<In>{ti, gi}, SinkTwo<OutAliasP>{pd, pt}, fx);
-        sweep_boundary();
-        const int64_t l2 = opaque(ld);
-        const OutOpt<OutAlias> gqo2{OutAlias{gq, l2, b}, gq != nullptr};
-        id_adjoint_lane<TP>(opaque_table(tab), In{opaque(q), l2, b}, In{opaque(qd), l2, b}, InAlias{gqd, l2, b},
-                            InAlias{gtau, l2, b}, gqo2, OutAlias{gqd, l2, b}, FextOpt{{opaque(fext), l2, b}},
-                            GFOut{{gfext, l2, b}});
-      } else {
-        vjp_lane_parked<TP>(tab, qi, qdi, ti, gi, gqo, pd, pt, InAlias{gqd, ld, b}, InAlias{gtau, ld, b}, fx, gf);
-      }
-    } else {
-      vjp_lane<TP, true>(tab, qi, qdi, ti, gi, gqo, OutOpt<OutAlias>{OutAlias{gqd, ld, b}, gqd != nullptr},
-                         OutOpt<OutAlias>{OutAlias{gtau, ld, b}, gtau != nullptr}, fx, gf);
-    }
-  } else if constexpr (MODE == 4) {
-    // each wave's region of the block's dynamic LDS: [qdd rows | lam rows]
+  // the external-force views (nothing without EXT)
+  auto fx_view = [&](const float* p, int64_t l) __attribute__((always_inline)) {
+    if constexpr (EXT) return FextOpt{{p, l, b}};
+    else return NoFext{};
+  };
+  auto gf_view = [&](int64_t l) __attribute__((always_inline)) {
+    if constexpr (EXT) return GFOut{{gfext, l, b}};
+    else return NoGF{};
+  };
+  if constexpr (MODE == 3) {
+    // the two sweeps, the second on fresh views (its own table and input
+    // pointers and row stride): a large tree's first sweep uses every
+    // register, and values kept for the second one spill (measured: 1028 ->
+    // 400 B/lane of scratch, 126 -> 108 us for the humanoid). Each wave parks
+    // in its region of the block's dynamic LDS: [qdd rows | lam rows].
     extern __shared__ float lds_park[];
     constexpr int NV = TP::NV;
     float* const w = lds_park + (threadIdx.x / kTileLanes) * (2 * NV * kTileLanes) + (threadIdx.x % kTileLanes);
-    fwd_dyn_lane<TP, 2>(tab, qi, qdi, RhsTwo<In>{ti, gi}, SinkTwo<LdsRow>{LdsRow{w}, LdsRow{w + NV * kTileLanes}});
+    fwd_dyn_lane<TP, 2>(tab, qi, qdi, RhsTwo<In>{ti, gi}, SinkTwo<LdsRow>{LdsRow{w}, LdsRow{w + NV * kTileLanes}},
+                        fx_view(fext, ld));
     if (gtau) {
       sfor<0, NV>([&](auto K_) __attribute__((always_inline)) {
         constexpr int K = decltype(K_)::value;
@@ -354,34 +345,16 @@ __global__ __launch_bounds__(kBlock) void k_fwd_dyn_vjp(const float* __restrict_
     const int64_t l2 = opaque(ld);
     id_adjoint_lane<TP>(opaque_table(tab), In{opaque(q), l2, b}, In{opaque(qd), l2, b}, LdsRow::In{w},
                         LdsRow::In{w + NV * kTileLanes}, OutOpt<OutAlias>{OutAlias{gq, l2, b}, gq != nullptr},
-                        OutOpt<OutAlias>{OutAlias{gqd, l2, b}, gqd != nullptr});
-  } else if constexpr (MODE >= 2 && TP::NV > 16) {
-    // the two sweeps of vjp_lane_parked, the second on fresh views (its own
-    // table and input pointers and row stride): a large tree's first sweep
-    // uses every register, and values kept for the second one spill
-    // (measured: 1028 -> 400 B/lane of scratch, 126 -> 108 us for the
-    // humanoid; a small tree is faster keeping them)
-    // q-double-dot and lam park in g_qd and g_tau (MODE 2) or in park_qdd and
-    // park_lam (MODE 3, see the launcher)
-    float* const pq = MODE == 2 ? gqd : park_qdd;
-    float* const pl = MODE == 2 ? gtau : park_lam;
-    const OutAliasP pd{{pq, ld, b}}, pt{{pl, ld, b}};
-    fwd_dyn_lane<TP, 2>(tab, qi, qdi, RhsTwo<In>{ti, gi}, SinkTwo<OutAliasP>{pd, pt});
-    sweep_boundary();
-    const int64_t l2 = opaque(ld);
-    const OutOpt<OutAlias> gqo2{OutAlias{gq, l2, b}, gq != nullptr};
-    if constexpr (MODE == 2)
-      id_adjoint_lane<TP>(opaque_table(tab), In{opaque(q), l2, b}, In{opaque(qd), l2, b}, InAlias{pq, l2, b},
-                          InAlias{pl, l2, b}, gqo2, OutAlias{gqd, l2, b});
-    else
-      id_adjoint_lane<TP>(opaque_table(tab), In{opaque(q), l2, b}, In{opaque(qd), l2, b}, InAlias{pq, l2, b},
-                          InAlias{pl, l2, b}, gqo2, OutOpt<OutAlias>{OutAlias{gqd, l2, b}, gqd != nullptr});
+                        OutOpt<OutAlias>{OutAlias{gqd, l2, b}, gqd != nullptr}, fx_view(opaque(fext), l2),
+                        gf_view(l2));
   } else if constexpr (MODE == 2) {
     const OutAliasP pd{{gqd, ld, b}}, pt{{gtau, ld, b}};
-    vjp_lane_parked<TP>(tab, qi, qdi, ti, gi, gqo, pd, pt, InAlias{gqd, ld, b}, InAlias{gtau, ld, b});
+    vjp_lane_parked<TP>(tab, qi, qdi, ti, gi, gqo, pd, pt, InAlias{gqd, ld, b}, InAlias{gtau, ld, b},
+                        fx_view(fext, ld), gf_view(ld));
   } else {
     vjp_lane<TP, MODE == 1>(tab, qi, qdi, ti, gi, gqo, OutOpt<OutAlias>{OutAlias{gqd, ld, b}, gqd != nullptr},
-                            OutOpt<OutAlias>{OutAlias{gtau, ld, b}, gtau != nullptr});
+                            OutOpt<OutAlias>{OutAlias{gtau, ld, b}, gtau != nullptr}, fx_view(fext, ld),
+                            gf_view(ld));
   }
 }
 
