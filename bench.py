@@ -413,7 +413,12 @@ def cpu_baseline(desc, st, budget_s):
             model = next((ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name")), model)
     except OSError:
         pass
+    try:
+        affinity = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        affinity = None
     return {"value": done / dt, "unit": "evals/s", "cores": cores, "kind": "oracle", "cpu_model": model,
+            "affinity_cpus": affinity, "logical_cpus": os.cpu_count(),
             "build": "g++ -O2 -fopenmp, no -march (portable code, as committed)",
             "parallelism": "OpenMP over states, one state per thread at a time, default affinity",
             "sample": f"{done} humanoid30 fwd_dyn evals (FP64, branch-sparse L^T L) = {done // n} passes over "
