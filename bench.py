@@ -458,15 +458,12 @@ def serving_leg(rbd, torch, seconds, seed=7, n_streams=4):
             raise RuntimeError(f"{bad} served requests failed")
         return n_req / (time.perf_counter() - t0)
 
-    pageable = [(models[name], op, ins) for name, op, _, ins in pool]
-    pinned = [(m, op, [rbd.pinned_copy(x) for x in ins]) for m, op, ins in pageable]
+    specs = [(models[name], op, ins) for name, op, _, ins in pool]
 
-    def run(srv, n_req, rate, seed, pin=True):
-        """Native open-loop client (Poisson at `rate`, 0 = closed loop), request and result arrays in
-        pinned host memory (or pageable); returns (stats, wall)."""
+    def run(srv, n_req, rate, seed):
+        """Native open-loop client (Poisson at `rate`, 0 = closed loop); returns (stats, wall)."""
         srv.reset_stats()
-        wall, failed = srv.load(pinned if pin else pageable, n_req, rate=rate, window=4 * len(pool), seed=seed,
-                                pinned_outputs=pin)
+        wall, failed = srv.load(specs, n_req, rate=rate, window=4 * len(specs), seed=seed)
         if failed:
             raise RuntimeError(f"{failed} served requests failed")
         return srv.stats(), wall
@@ -498,8 +495,6 @@ def serving_leg(rbd, torch, seconds, seed=7, n_streams=4):
     out["batched_at_25pct"] = leg(st, wall, 0.25 * cap)
     st, wall = run(srv, 8192, 0.0, 6)
     out["batched"]["closed_loop_evals_per_s"] = st["instances"] / wall
-    st, wall = run(srv, 8192, 0.0, 11, pin=False)
-    out["pageable_client_closed_loop_req_per_s"] = round(st["requests"] / wall, 1)
     out["python_client_closed_loop_req_per_s"] = round(run_python(srv, 2048), 1)
     srv.close()
     base = rbd.Server(arena_bytes=1 << 30, n_streams=1, per_request=True, use_graphs=False)
@@ -511,8 +506,7 @@ def serving_leg(rbd, torch, seconds, seed=7, n_streams=4):
     out["one_launch_per_request"] = dict(leg(st, wall, rate), closed_loop_capacity_req_per_s=round(bcap, 1))
     base.close()
     out["client"] = ("native open-loop generator (rbd_diag_serve_load): Poisson arrivals from one submitting "
-                     "thread, one waiting thread, request and result arrays in pinned host memory (large arrays "
-                     f"skip the staging copy); {n_streams} launch slots (stream + worker thread each)")
+                     f"thread, one waiting thread; {n_streams} launch slots (stream + worker thread each)")
     out["mix"] = "Poisson arrivals, chain7/humanoid30 50/50, fwd_dyn/rnea/fwd_dyn_vjp 60/25/15, batch log-uniform 1..4096, host I/O included"
     return out
 

@@ -315,10 +315,7 @@ typedef struct {
 
 rbd_status rbd_server_create(const rbd_server_config* cfg, rbd_server** out);
 /* Queue one request; returns a ticket immediately. RBD_E_INVAL if it can never
- * fit the arena or names a bad op, size or pointer. An array of at least
- * 64 KiB that lives in pinned host memory (hipHostMalloc, or a pinned torch
- * tensor) is copied by DMA straight between it and the device, skipping the
- * staging copy; other arrays go through the server's pinned staging block. */
+ * fit the arena or names a bad op, size or pointer. */
 rbd_status rbd_server_submit(rbd_server* s, const rbd_model* model, int op, int64_t batch,
                              const float* const* host_in, float* const* host_out, uint64_t* ticket);
 /* Wait until the request finishes (timeout_s < 0: forever). On RBD_OK,
@@ -359,8 +356,7 @@ rbd_status rbd_server_destroy(rbd_server* s);
  * SplitMix64 seeded with `seed`), or as fast as the window allows when
  * rate_per_s is 0 (closed loop). At most `window` requests (rounded up to a
  * multiple of n_spec) are outstanding; their outputs go to buffers the
- * generator allocates and frees (host memory, pinned if pinned_outputs is
- * nonzero). One extra thread waits for
+ * generator allocates and frees (host memory). One extra thread waits for
  * the tickets in order. Blocks until every request completed; *wall_s is the
  * time from the first submit to the last completion and *failed counts
  * requests whose own status was not RBD_OK. The spec's input buffers must
@@ -373,8 +369,7 @@ typedef struct {
   const float* in[4];   /* host inputs as for rbd_server_submit   */
 } rbd_load_request;
 rbd_status rbd_diag_serve_load(rbd_server* s, int n_spec, const rbd_load_request* spec, int64_t n_requests,
-                               double rate_per_s, int window, uint64_t seed, int pinned_outputs, double* wall_s,
-                               int64_t* failed);
+                               double rate_per_s, int window, uint64_t seed, double* wall_s, int64_t* failed);
 
 #ifdef __cplusplus
 }

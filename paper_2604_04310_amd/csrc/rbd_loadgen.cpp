@@ -42,7 +42,7 @@ using namespace rbd;
 
 extern "C" rbd_status rbd_diag_serve_load(rbd_server* s, int n_spec, const rbd_load_request* spec,
                                           int64_t n_requests, double rate_per_s, int window, uint64_t seed,
-                                          int pinned_outputs, double* wall_s, int64_t* failed) {
+                                          double* wall_s, int64_t* failed) {
   if (!s || !spec || !wall_s || !failed) return fail(RBD_E_INVAL, "rbd_diag_serve_load: NULL argument");
   if (n_spec < 1 || n_requests < 1 || window < 1 || !(rate_per_s >= 0.0))
     return fail(RBD_E_INVAL, "rbd_diag_serve_load: n_spec, n_requests and window must be >= 1, rate >= 0");
@@ -55,32 +55,11 @@ extern "C" rbd_status rbd_diag_serve_load(rbd_server* s, int n_spec, const rbd_l
   // (copies * n_spec), which no other outstanding request uses
   const int copies = (window + n_spec - 1) / n_spec;
   const int64_t n_buf = (int64_t)copies * n_spec;
-  // one allocation holds every output buffer: pageable, or pinned (then the
-  // server copies large results straight into it)
-  std::vector<size_t> off((size_t)n_buf * 3, 0);
-  size_t total = 0;
+  std::vector<std::vector<float>> bufs((size_t)n_buf * 3);
   for (int64_t b = 0; b < n_buf; ++b) {
     const rbd_load_request& r = spec[b % n_spec];
-    for (int a = 0; a < out_count(r.op); ++a) {
-      off[(size_t)b * 3 + a] = total;
-      total += (size_t)(out_rows(r.model, r.op, a) * r.batch);
-    }
+    for (int a = 0; a < out_count(r.op); ++a) bufs[(size_t)b * 3 + a].resize((size_t)(out_rows(r.model, r.op, a) * r.batch));
   }
-  std::vector<float> pageable;
-  float* out_base = nullptr;
-  if (pinned_outputs) {
-    if (hipHostMalloc((void**)&out_base, total * sizeof(float), hipHostMallocDefault) != hipSuccess)
-      return fail(RBD_E_NOMEM, "rbd_diag_serve_load: %zu bytes of pinned memory", total * sizeof(float));
-  } else {
-    pageable.resize(total);
-    out_base = pageable.data();
-  }
-  struct PinnedFree {
-    float* p;
-    ~PinnedFree() {
-      if (p) (void)hipHostFree(p);
-    }
-  } pinned_guard{pinned_outputs ? out_base : nullptr};
   std::vector<uint64_t> tickets((size_t)n_requests);
   std::atomic<int64_t> submitted{0}, completed{0}, n_failed{0};
   std::atomic<bool> abort{false};
@@ -114,7 +93,7 @@ extern "C" rbd_status rbd_diag_serve_load(rbd_server* s, int n_spec, const rbd_l
     const rbd_load_request& r = spec[j % n_spec];
     const int64_t b = j % n_buf;
     float* outs[3] = {nullptr, nullptr, nullptr};
-    for (int a = 0; a < out_count(r.op); ++a) outs[a] = out_base + off[(size_t)b * 3 + a];
+    for (int a = 0; a < out_count(r.op); ++a) outs[a] = bufs[(size_t)b * 3 + a].data();
     result = rbd_server_submit(s, r.model, r.op, r.batch, r.in, outs, &tickets[(size_t)j]);
     if (result != RBD_OK) {
       abort = true;

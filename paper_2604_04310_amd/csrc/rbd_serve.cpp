@@ -52,9 +52,6 @@ constexpr int kMaxTilesPerGroup = 16384;  // 1 M instances per launch
 // 40 000 humanoid or 140 000 seven-joint instances, enough to fill the GPU.
 constexpr size_t kMaxGroupBytes = size_t(16) << 20;
 constexpr int kGridClasses[] = {4, 32, 256, 1024};
-// Arrays of at least this many bytes in pinned client memory skip the staging
-// copy (below it, one copy into the staging block is cheaper than a DMA call).
-constexpr size_t kDirectBytes = size_t(64) << 10;
 inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 struct Request {
@@ -68,10 +65,6 @@ struct Request {
   size_t in_n[4] = {0, 0, 0, 0};  // floats per array
   size_t out_n[3] = {0, 0, 0};
   size_t in_bytes = 0, out_bytes = 0;
-  // arrays large enough for a DMA of their own that the client holds in
-  // pinned memory: copied straight between the client's buffer and the arena
-  bool in_direct[4] = {false, false, false, false};
-  bool out_direct[3] = {false, false, false};
   Clock::time_point t_submit;
   bool done = false;
   rbd_status status = RBD_OK;
@@ -141,8 +134,7 @@ struct Group {
   std::vector<std::shared_ptr<Request>> reqs;
   size_t off = 0, bytes = 0, in_bytes = 0, out_off = 0, out_bytes = 0;
   bool timed = false;  // its timeline events were recorded
-  size_t staged_in = 0, staged_out = 0;  // bytes that go through the staging block
-  std::vector<size_t> out_pos;  // per request and output array, offset inside the block
+  std::vector<size_t> in_pos, out_pos;  // per request, offsets inside the block
   int n_tiles = 0;
   rbd_status status = RBD_OK;
 };
@@ -321,63 +313,40 @@ rbd_status launch_group(rbd_server* s, Group* g) {
   Slot& sl = *s->slots[g->slot];
   uint8_t* hb = s->h_stage + g->off;
   uint8_t* db = s->d_arena + g->off;
-  // pack the inputs (instance-major, as given): staged arrays first (copied
-  // here into the pinned staging block, one host-to-device copy for all), then
-  // arrays in pinned client memory (one DMA each, straight from the client);
-  // the outputs the same way; and the tile table
+  // pack inputs (instance-major, as given) and the tile table
   PackedHdr* hdr = reinterpret_cast<PackedHdr*>(sl.h_table);
   int32_t* tile_req = reinterpret_cast<int32_t*>(sl.h_table + sizeof(PackedHdr));
   const int32_t req_off = (int32_t)align_up(sizeof(PackedHdr) + sizeof(int32_t) * g->n_tiles);
   PackedReq* reqs = reinterpret_cast<PackedReq*>(sl.h_table + req_off);
-  const size_t nr = g->reqs.size();
-  for (size_t k = 0; k < nr; ++k) reqs[k] = PackedReq{};
-  g->out_pos.assign(nr * 3, 0);
   size_t ipos = 0, opos = g->out_off;
-  for (int pass = 0; pass < 2; ++pass) {
-    for (size_t k = 0; k < nr; ++k) {
-      const Request& r = *g->reqs[k];
-      for (int a = 0; a < r.n_in; ++a) {
-        if (r.in_direct[a] != (pass == 1)) continue;
-        if (pass == 0) std::memcpy(hb + ipos, r.in[a], r.in_n[a] * sizeof(float));
-        reqs[k].in[a] = reinterpret_cast<const float*>(db + ipos);
-        ipos += r.in_n[a] * sizeof(float);
-      }
-      for (int a = 0; a < r.n_out; ++a) {
-        if (r.out_direct[a] != (pass == 1)) continue;
-        reqs[k].out[a] = reinterpret_cast<float*>(db + opos);
-        g->out_pos[k * 3 + a] = opos;
-        opos += r.out_n[a] * sizeof(float);
-      }
-    }
-    if (pass == 0) {
-      g->staged_in = ipos;
-      g->staged_out = opos - g->out_off;
-    }
-  }
   int tile = 0;
-  for (size_t k = 0; k < nr; ++k) {
+  for (size_t k = 0; k < g->reqs.size(); ++k) {
     const Request& r = *g->reqs[k];
-    reqs[k].batch = (int32_t)r.batch;
-    reqs[k].first_tile = tile;
+    PackedReq pr{};
+    for (int a = 0; a < r.n_in; ++a) {
+      std::memcpy(hb + ipos, r.in[a], r.in_n[a] * sizeof(float));
+      pr.in[a] = reinterpret_cast<const float*>(db + ipos);
+      ipos += r.in_n[a] * sizeof(float);
+    }
+    for (int a = 0; a < r.n_out; ++a) {
+      pr.out[a] = reinterpret_cast<float*>(db + opos);
+      opos += r.out_n[a] * sizeof(float);
+    }
+    pr.batch = (int32_t)r.batch;
+    pr.first_tile = tile;
     const int rt = (int)((r.batch + kTileLanes - 1) / kTileLanes);
     for (int t = 0; t < rt; ++t) tile_req[tile++] = (int32_t)k;
+    reqs[k] = pr;
   }
   hdr->n_tiles = g->n_tiles;
-  hdr->n_req = (int32_t)nr;
+  hdr->n_req = (int32_t)g->reqs.size();
   hdr->req_offset = req_off;
   hdr->pad = 0;
-  const size_t table_bytes = req_off + sizeof(PackedReq) * nr;
+  const size_t table_bytes = req_off + sizeof(PackedReq) * g->reqs.size();
   hipStream_t st = sl.stream;
-  bool ok = hipEventRecord(sl.ev[0], st) == hipSuccess &&
-            (g->staged_in == 0 || hipMemcpyAsync(db, hb, g->staged_in, hipMemcpyHostToDevice, st) == hipSuccess);
-  for (size_t k = 0; k < nr && ok; ++k) {
-    const Request& r = *g->reqs[k];
-    for (int a = 0; a < r.n_in && ok; ++a)
-      if (r.in_direct[a])
-        ok = hipMemcpyAsync((void*)reqs[k].in[a], r.in[a], r.in_n[a] * sizeof(float), hipMemcpyHostToDevice, st) ==
-             hipSuccess;
-  }
-  if (!ok || hipMemcpyAsync(sl.d_table, sl.h_table, table_bytes, hipMemcpyHostToDevice, st) != hipSuccess ||
+  if (hipEventRecord(sl.ev[0], st) != hipSuccess ||
+      hipMemcpyAsync(db, hb, g->in_bytes, hipMemcpyHostToDevice, st) != hipSuccess ||
+      hipMemcpyAsync(sl.d_table, sl.h_table, table_bytes, hipMemcpyHostToDevice, st) != hipSuccess ||
       hipEventRecord(sl.ev[1], st) != hipSuccess)
     return fail(RBD_E_LAUNCH, "server: input copy failed");
   const int grid = s->cfg.per_request ? std::max(1, (g->n_tiles * kTileLanes + 255) / 256) : grid_class(g->n_tiles);
@@ -409,31 +378,17 @@ rbd_status launch_group(rbd_server* s, Group* g) {
     rs = launch_packed(g->model, g->op, sl.d_table, grid, st);
     if (rs != RBD_OK) return rs;
   }
-  ok = hipEventRecord(sl.ev[2], st) == hipSuccess &&
-       (g->staged_out == 0 ||
-        hipMemcpyAsync(hb + g->out_off, db + g->out_off, g->staged_out, hipMemcpyDeviceToHost, st) == hipSuccess);
-  for (size_t k = 0; k < nr && ok; ++k) {
-    const Request& r = *g->reqs[k];
-    for (int a = 0; a < r.n_out && ok; ++a)
-      if (r.out_direct[a])
-        ok = hipMemcpyAsync(r.out[a], db + g->out_pos[k * 3 + a], r.out_n[a] * sizeof(float), hipMemcpyDeviceToHost,
-                            st) == hipSuccess;
-  }
-  if (!ok || hipEventRecord(sl.ev[3], st) != hipSuccess) return fail(RBD_E_LAUNCH, "server: result copy failed");
+  if (hipEventRecord(sl.ev[2], st) != hipSuccess ||
+      hipMemcpyAsync(hb + g->out_off, db + g->out_off, g->out_bytes, hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipEventRecord(sl.ev[3], st) != hipSuccess)
+    return fail(RBD_E_LAUNCH, "server: result copy failed");
   g->timed = true;
   return RBD_OK;
 }
 
 void finish_group(rbd_server* s, Group* g, const Clock::time_point now) {
   // results -> client buffers (instance-major, as requested)
-  if (g->status == RBD_OK && !s->host_exec) {
-    const uint8_t* hb = s->h_stage + g->off;
-    for (size_t k = 0; k < g->reqs.size(); ++k) {
-      Request& r = *g->reqs[k];
-      for (int a = 0; a < r.n_out; ++a)
-        if (!r.out_direct[a]) std::memcpy(r.out[a], hb + g->out_pos[k * 3 + a], r.out_n[a] * sizeof(float));
-    }
-  } else if (g->status == RBD_OK) {  // host executor: outputs in order after out_off
+  if (g->status == RBD_OK) {
     const uint8_t* hb = s->h_stage + g->off;
     size_t opos = g->out_off;
     for (auto& rp : g->reqs) {
@@ -631,17 +586,6 @@ rbd_status rbd_server_submit(rbd_server* s, const rbd_model* m, int op, int64_t 
     r->out[a] = host_out[a];
     r->out_n[a] = (size_t)out_rows[a] * (size_t)batch;
     r->out_bytes += r->out_n[a] * sizeof(float);
-  }
-  if (!s->host_exec) {
-    auto pinned = [](const void* p) {
-      hipPointerAttribute_t at{};
-      const bool yes = hipPointerGetAttributes(&at, p) == hipSuccess && at.type == hipMemoryTypeHost;
-      (void)hipGetLastError();  // pageable memory is reported as an invalid value: clear it
-      return yes;
-    };
-    for (int a = 0; a < r->n_in; ++a) r->in_direct[a] = r->in_n[a] * sizeof(float) >= kDirectBytes && pinned(r->in[a]);
-    for (int a = 0; a < r->n_out; ++a)
-      r->out_direct[a] = r->out_n[a] * sizeof(float) >= kDirectBytes && pinned(r->out[a]);
   }
   if (align_up(r->in_bytes) + r->out_bytes > s->cfg.arena_bytes)
     return fail(RBD_E_INVAL, "rbd_server_submit: request needs %zu bytes, more than the arena holds",

@@ -118,7 +118,7 @@ def lib():
         L.rbd_server_reset_stats.argtypes = [vp]
         L.rbd_server_destroy.argtypes = [vp]
         L.rbd_diag_serve_load.argtypes = [vp, C.c_int, P(LoadRequestC), i64, C.c_double, C.c_int, C.c_uint64,
-                                          C.c_int, P(C.c_double), P(i64)]
+                                          P(C.c_double), P(i64)]
         _lib = L
     return _lib
 
@@ -473,22 +473,6 @@ def op_shapes(model: Model, op: int):
     raise ValueError(f"unknown op {op}")
 
 
-def pinned_empty(shape, dtype=np.float32):
-    """A numpy array in pinned host memory (a pinned torch tensor's storage, kept alive by the array):
-    the server copies such arrays of 64 KiB or more straight between them and the device."""
-    import torch
-    n = int(np.prod(shape))
-    t = torch.empty(n, dtype=torch.from_numpy(np.empty(0, dtype=dtype)).dtype, pin_memory=True)
-    return t.numpy().reshape(shape)
-
-
-def pinned_copy(x: np.ndarray) -> np.ndarray:
-    """A copy of x in pinned host memory."""
-    y = pinned_empty(x.shape, x.dtype)
-    y[...] = x
-    return y
-
-
 class Server:
     """Continuous-batching service (rbd_server_*). Requests carry host arrays,
     instance-major float32 [batch, rows]; results land in host arrays."""
@@ -503,9 +487,8 @@ class Server:
         check(lib().rbd_server_create(C.byref(cfg), C.byref(self._h)))
         self._live = {}
 
-    def submit(self, model: Model, op: int, inputs: Sequence[np.ndarray], outputs=None):
-        """Queue one request; returns (ticket, outputs) with outputs filled once waited. outputs: optional
-        arrays to write into (e.g. from pinned_empty), else new ones."""
+    def submit(self, model: Model, op: int, inputs: Sequence[np.ndarray]):
+        """Queue one request; returns (ticket, outputs) with outputs filled once waited."""
         in_rows, out_rows = op_shapes(model, op)
         if len(inputs) != len(in_rows):
             raise ValueError(f"op {op} takes {len(in_rows)} inputs")
@@ -516,14 +499,7 @@ class Server:
             if x.shape != (batch, r):
                 raise ValueError(f"input of shape {x.shape}, expected {(batch, r)}")
             ins.append(x)
-        if outputs is None:
-            outs = [np.empty((batch, r), dtype=np.float32) for r in out_rows]
-        else:
-            outs = list(outputs)
-            if len(outs) != len(out_rows) or any(
-                    o.dtype != np.float32 or o.shape != (batch, r) or not o.flags.c_contiguous
-                    for o, r in zip(outs, out_rows)):
-                raise ValueError("outputs do not match the operation")
+        outs = [np.empty((batch, r), dtype=np.float32) for r in out_rows]
         pin = (C.c_void_p * 4)(*[C.c_void_p(x.ctypes.data) for x in ins] + [None] * (4 - len(ins)))
         pout = (C.c_void_p * 3)(*[C.c_void_p(x.ctypes.data) for x in outs] + [None] * (3 - len(outs)))
         t = C.c_uint64()
@@ -541,12 +517,10 @@ class Server:
         """Cancel a request still in the queue (it then completes with RBD_E_CANCELLED)."""
         check(lib().rbd_server_cancel(self._h, C.c_uint64(ticket)))
 
-    def load(self, requests, n_requests: int, rate: float = 0.0, window: int = 1024, seed: int = 0,
-             pinned_outputs: bool = False):
+    def load(self, requests, n_requests: int, rate: float = 0.0, window: int = 1024, seed: int = 0):
         """Native open-loop load (rbd_diag_serve_load): request j is requests[j % len(requests)], each a
         (model, op, inputs) triple of instance-major float32 arrays; Poisson arrivals at `rate` per second
-        (0: closed loop); outputs in pinned host memory if pinned_outputs. Returns (wall seconds, failed
-        requests)."""
+        (0: closed loop). Returns (wall seconds, failed requests)."""
         keep, spec = [], (LoadRequestC * len(requests))()
         for k, (model, op, inputs) in enumerate(requests):
             in_rows, _ = op_shapes(model, op)
@@ -560,7 +534,7 @@ class Server:
                 spec[k].inp[a] = x.ctypes.data
         wall, failed = C.c_double(), C.c_int64()
         check(lib().rbd_diag_serve_load(self._h, len(requests), spec, int(n_requests), float(rate), int(window),
-                                        int(seed), int(bool(pinned_outputs)), C.byref(wall), C.byref(failed)))
+                                        int(seed), C.byref(wall), C.byref(failed)))
         return wall.value, failed.value
 
     def stats(self) -> dict:

@@ -201,44 +201,4 @@ def test_native_load_generator_on_the_device(env):
     srv.reset_stats()
     wall, failed = srv.load(specs, 120, rate=5000.0, window=24, seed=2)
     assert failed == 0 and srv.stats()["requests"] == 120
-    pinned = [(m, op, [rbd.pinned_copy(x) for x in ins]) for m, op, ins in specs]
-    wall, failed = srv.load(pinned, 120, rate=0.0, window=24, seed=3, pinned_outputs=True)
-    assert failed == 0
-    srv.close()
-
-
-def test_pinned_client_buffers_take_the_direct_path(env):
-    """Requests whose large arrays live in pinned host memory are copied by DMA straight between
-    them and the arena (no staging copy): their results equal, bit for bit, those of the same
-    requests in pageable memory, in a mix where some arrays are pinned and some are not."""
-    rbd, descs, models = env
-    rng = np.random.Generator(np.random.PCG64(31))
-    reqs = []
-    for k in range(12):
-        name = ["chain7", "humanoid30"][k % 2]
-        op = [rbd.OP_FWD_DYN, rbd.OP_RNEA, rbd.OP_FWD_DYN_VJP][k % 3]
-        B = int(rng.integers(3000, 5000))  # humanoid rows are >= 64 KiB from B = 456, chain7 from B = 2341
-        d = descs[name]
-        st = W.states(d, B, 700 + k)
-        ins = [st.q, st.qd, st.tau] if op != rbd.OP_RNEA else [st.q, st.qd, W.cotangent(d.nv, B, k)]
-        if op == rbd.OP_FWD_DYN_VJP:
-            ins = ins + [W.cotangent(d.nv, B, 50 + k)]
-        reqs.append((name, op, [x.astype(np.float32) for x in ins]))
-    srv = rbd.Server(arena_bytes=256 << 20, n_streams=3, max_batch_requests=8)
-    ref = [srv.submit(models[n], op, ins) for n, op, ins in reqs]
-    for t, _ in ref:
-        assert srv.wait(t, 60.0) == 0
-    got = []
-    for k, (n, op, ins) in enumerate(reqs):
-        pin_in = [rbd.pinned_copy(x) if (k + a) % 3 else x for a, x in enumerate(ins)]  # some arrays pinned
-        _, out_rows = rbd.op_shapes(models[n], op)
-        outs = [rbd.pinned_empty((ins[0].shape[0], r)) if (k + a) % 2 else np.empty((ins[0].shape[0], r), np.float32)
-                for a, r in enumerate(out_rows)]
-        for o in outs:
-            o[...] = np.nan
-        got.append((srv.submit(models[n], op, pin_in, outputs=outs), pin_in))
-    for k, (((t, outs), _), (_, ref_outs)) in enumerate(zip(got, ref)):
-        assert srv.wait(t, 60.0) == 0
-        for a, (o, r) in enumerate(zip(outs, ref_outs)):
-            assert np.array_equal(o, r), (k, a)
     srv.close()
