@@ -426,7 +426,7 @@ def cpu_baseline(desc, st, budget_s):
             "one_core_evals_per_s": done1 / dt1}
 
 
-def serving_leg(rbd, torch, seconds, seed=7, n_streams=4):
+def serving_leg(rbd, torch, seconds, seed=7, n_streams=4, group_bytes=0):
     """Poisson mix of chain7/humanoid30 requests (ops 60/25/15 fwd_dyn/rnea/vjp,
     batch log-uniform in [1, 4096]) at half and at 80 % of the measured
     closed-loop capacity."""
@@ -481,7 +481,8 @@ def serving_leg(rbd, torch, seconds, seed=7, n_streams=4):
                 "mean_kernel_us": round(1e6 * st["gpu_kernel_sum_s"] / max(st["groups_timed"], 1), 1)}
 
     out = {}
-    srv = rbd.Server(arena_bytes=1 << 30, n_streams=n_streams, max_batch_requests=1024, use_graphs=True)
+    srv = rbd.Server(arena_bytes=1 << 30, n_streams=n_streams, max_batch_requests=1024, use_graphs=True,
+                     max_group_bytes=group_bytes)
     run(srv, 1024, 0.0, 1)  # warm: graphs, pools
     st, wall = run(srv, 8192, 0.0, 2)
     cap = st["requests"] / wall
@@ -521,6 +522,7 @@ def main():
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--serving-only", action="store_true", help="only the serving leg (for a trace of it)")
     ap.add_argument("--serve-streams", type=int, default=4)
+    ap.add_argument("--serve-group-mib", type=float, default=0.0, help="launch-group byte cap (0: default)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--counters", action="store_true", help="only run the counter-collection driver")
     ap.add_argument("--summarize-profiles", metavar="DIR", help="write profiles/ summaries from rocprofv3 output")
@@ -545,7 +547,8 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     if args.serving_only:
-        print(json.dumps(serving_leg(rbd, torch, args.serve_seconds, n_streams=args.serve_streams)), flush=True)
+        print(json.dumps(serving_leg(rbd, torch, args.serve_seconds, n_streams=args.serve_streams,
+                                     group_bytes=int(args.serve_group_mib * (1 << 20)))), flush=True)
         return
     desc = W.humanoid()
     model = rbd.Model(desc, 0)

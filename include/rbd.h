@@ -311,6 +311,9 @@ typedef struct {
   int64_t fail_group;    /* testing: the fail_group-th launch group (counted from 1)
                             fails before anything of it is launched, as a failed
                             launch would; 0 = never                                */
+  size_t max_group_bytes;/* a launch group stops growing at this many bytes of
+                            staged inputs and outputs (a larger single request
+                            still forms a group of its own); 0 = 16 MiB           */
 } rbd_server_config;
 
 rbd_status rbd_server_create(const rbd_server_config* cfg, rbd_server** out);

@@ -45,11 +45,12 @@ namespace {
 using Clock = std::chrono::steady_clock;
 constexpr size_t kAlign = 256;
 constexpr int kMaxTilesPerGroup = 16384;  // 1 M instances per launch
-// A launch group stops growing at this many bytes of staged inputs and outputs
-// (a single request larger than it still forms a group of its own). Host
-// staging and the two copies dominate a group's latency, so a cap keeps a
-// small request from waiting behind hundreds of megabytes; 16 MiB is about
-// 40 000 humanoid or 140 000 seven-joint instances, enough to fill the GPU.
+// By default a launch group stops growing at this many bytes of staged inputs
+// and outputs (a single request larger than it still forms a group of its
+// own). Host staging and the two copies dominate a group's latency, so a cap
+// keeps a small request from waiting behind hundreds of megabytes; 16 MiB is
+// about 40 000 humanoid or 140 000 seven-joint instances, enough to fill the
+// GPU. rbd_server_config.max_group_bytes overrides it.
 constexpr size_t kMaxGroupBytes = size_t(16) << 20;
 constexpr int kGridClasses[] = {4, 32, 256, 1024};
 inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
@@ -172,6 +173,7 @@ using namespace rbd;
 struct rbd_server {
   rbd_server_config cfg{};
   bool host_exec = false;      // RBD_EXEC_HOST: arena and staging in host memory
+  size_t group_cap = 0;        // bytes at which a launch group stops growing
   uint8_t* d_arena = nullptr;  // device arena (host memory for the host executor)
   uint8_t* h_stage = nullptr;
   Arena arena;
@@ -226,7 +228,7 @@ Group* form_group(rbd_server* s) {
     if (tiles + rt > kMaxTilesPerGroup) break;
     const size_t grown = align_up(in_total + r->in_bytes) + out_total + r->out_bytes;
     if (grown > budget) break;
-    if (!g->reqs.empty() && grown > kMaxGroupBytes) break;
+    if (!g->reqs.empty() && grown > s->group_cap) break;
     in_total += r->in_bytes;
     out_total += r->out_bytes;
     tiles += rt;
@@ -532,6 +534,7 @@ rbd_status rbd_server_create(const rbd_server_config* cfg, rbd_server** out) {
   if (!s) return fail(RBD_E_NOMEM, "host allocation failed");
   s->cfg = *cfg;
   s->host_exec = host;
+  s->group_cap = cfg->max_group_bytes ? cfg->max_group_bytes : kMaxGroupBytes;
   s->arena.init(cfg->arena_bytes);
   for (int k = 0; k < cfg->n_streams; ++k) s->slots.push_back(std::make_unique<Slot>());
   bool ok = true;

@@ -57,7 +57,8 @@ class TreeDescC(C.Structure):
 class ServerConfigC(C.Structure):
     _fields_ = [("device", C.c_int), ("arena_bytes", C.c_size_t), ("n_streams", C.c_int),
                 ("max_batch_requests", C.c_int), ("max_wait_us", C.c_double), ("use_graphs", C.c_int),
-                ("per_request", C.c_int), ("executor", C.c_int), ("fail_group", C.c_int64)]
+                ("per_request", C.c_int), ("executor", C.c_int), ("fail_group", C.c_int64),
+                ("max_group_bytes", C.c_size_t)]
 
 
 EXEC_DEVICE, EXEC_HOST = 0, 1
@@ -479,10 +480,11 @@ class Server:
 
     def __init__(self, device: int = 0, arena_bytes: int = 256 << 20, n_streams: int = 4,
                  max_batch_requests: int = 1024, max_wait_us: float = 0.0, use_graphs: bool = True,
-                 per_request: bool = False, executor: int = EXEC_DEVICE, fail_group: int = 0):
+                 per_request: bool = False, executor: int = EXEC_DEVICE, fail_group: int = 0,
+                 max_group_bytes: int = 0):
         cfg = ServerConfigC(int(device), int(arena_bytes), int(n_streams), int(max_batch_requests),
                             float(max_wait_us), int(bool(use_graphs)), int(bool(per_request)), int(executor),
-                            int(fail_group))
+                            int(fail_group), int(max_group_bytes))
         self._h = C.c_void_p()
         check(lib().rbd_server_create(C.byref(cfg), C.byref(self._h)))
         self._live = {}

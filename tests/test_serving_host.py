@@ -202,3 +202,21 @@ def test_native_load_generator(rbd, models):
     wall, failed = bad.load(specs[:1], 20, window=4)
     assert failed == 1  # one request per group, the fifth group fails
     bad.close()
+
+
+def test_group_byte_cap(rbd, models):
+    """max_group_bytes bounds a launch group: requests of 144 KiB under a 256 KiB cap run one per
+    group even when a gather window has all of them queued, and each still gets its own results."""
+    m = models["humanoid30"]
+    B = 256  # (nq + 2 nv + nv) floats per instance: 144 KiB per request
+    srv = rbd.Server(executor=rbd.EXEC_HOST, arena_bytes=64 << 20, n_streams=1, max_batch_requests=64,
+                     max_wait_us=20000.0, max_group_bytes=256 << 10)
+    reqs = []
+    for k in range(10):
+        ins = make_request(rbd, m, rbd.OP_FWD_DYN, B, 800 + k)
+        reqs.append((*srv.submit(m, rbd.OP_FWD_DYN, ins), ins))
+    for t, outs, ins in reqs:
+        assert srv.wait(t, 30.0) == OK
+        assert np.array_equal(outs[0], expected(rbd, m, rbd.OP_FWD_DYN, ins)[0])
+    assert srv.stats()["launches"] == 10
+    srv.close()
