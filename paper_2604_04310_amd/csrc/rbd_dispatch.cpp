@@ -205,7 +205,15 @@ rbd_status launch_fwd_dyn_jvp(const rbd_model* m, int64_t batch, int64_t ld, con
   if (batch == 0) return RBD_OK;
   const float* tab = m->d_tab;
   void* a[] = {&tab, &batch, &ld, &q, &qd, &tau, &dq, &dqd, &dtau, &qdd, &dqdd, &fext, &dfext};
-  return launch(m, (fext || dfext) ? KID_JVP_EXT : KID_JVP, heavy_shape(batch), a, s, "rbd_fwd_dyn_jvp");
+  const bool ext = fext || dfext;
+  if (large(m) && batch <= kOneWavePerSimd / 2) {
+    // two waves per 64 instances: the factor of M on its own wave, in
+    // parallel with the solve for qdd and the tangent
+    const Shape sh{dim3((unsigned)((batch + kTileLanes - 1) / kTileLanes)), dim3(2 * kTileLanes),
+                   (unsigned)(2 * m->nv * kTileLanes * sizeof(float))};
+    return launch(m, ext ? KID_JVP_EXT_SPLIT : KID_JVP_SPLIT, sh, a, s, "rbd_fwd_dyn_jvp");
+  }
+  return launch(m, ext ? KID_JVP_EXT : KID_JVP, heavy_shape(batch), a, s, "rbd_fwd_dyn_jvp");
 }
 
 // The controller kernel of `frame`: the set's own for the last body, else one

@@ -403,6 +403,58 @@ __global__ __launch_bounds__(kBlock) void k_fwd_dyn_jvp(const float* __restrict_
       SinkOne<OutAlias>{OutAlias{dqdd, ld3, b}});
 }
 
+// ---- the same tangent on two waves per 64 instances (a block of 128 lanes),
+// for batches small enough that one wave per 64 instances leaves SIMDs idle:
+// wave 0 runs the fused solve for qdd and the tangent of inverse dynamics and
+// hands the right-hand side to wave 1 through LDS; wave 1 factors M in the
+// meantime, then solves with it. Dynamic LDS per block: [rhs rows | qdd rows],
+// 64 lanes each. Every lane of the block reaches the one barrier.
+template <class TP, bool EXT = false>
+__global__ __launch_bounds__(2 * kTileLanes) void k_fwd_dyn_jvp_split(
+    const float* __restrict__ tab, int64_t batch, int64_t ld, const float* __restrict__ q,
+    const float* __restrict__ qd, const float* __restrict__ tau, const float* __restrict__ dq,
+    const float* __restrict__ dqd, const float* __restrict__ dtau, float* qdd, float* dqdd,
+    const float* __restrict__ fext, const float* __restrict__ dfext) {
+  RBD_LANE_IO(TP);
+  constexpr int NV = TP::NV;
+  extern __shared__ float lds_jvp[];
+  const uint32_t lane = threadIdx.x % kTileLanes;
+  const bool solver = threadIdx.x >= kTileLanes;
+  const uint32_t b = blockIdx.x * kTileLanes + lane;
+  const bool valid = b < batch;
+  float* const rhs = lds_jvp + lane;
+  float* const qpark = lds_jvp + NV * kTileLanes + lane;
+  auto fx_view = [&](const float* p, int64_t l) __attribute__((always_inline)) {
+    if constexpr (EXT) return FextOpt{{p, l, b}};
+    else return NoFext{};
+  };
+  Ltl<TP, 1> F;
+  if (!solver) {
+    if (valid) {
+      fwd_dyn_lane<TP, 1>(tab, In{q, ld, b}, In{qd, ld, b}, RhsOne<In>{In{tau, ld, b}},
+                          SinkOne<LdsRow>{LdsRow{qpark}}, fx_view(fext, ld));
+      if (qdd) {
+        sfor<0, NV>([&](auto K_) __attribute__((always_inline)) {
+          constexpr int K = decltype(K_)::value;
+          Out{qdd, ld, b}(K, qpark[K * kTileLanes]);
+        });
+      }
+      sweep_boundary();
+      const int64_t l2 = opaque(ld);
+      id_tangent_lane<TP>(opaque_table(tab), In{opaque(q), l2, b}, In{opaque(qd), l2, b}, LdsRow::In{qpark},
+                          In{dq, l2, b}, In{dqd, l2, b}, In{dtau, l2, b}, LdsRow{rhs}, fx_view(opaque(fext), l2),
+                          fx_view(opaque(dfext), l2));
+    }
+  } else if (valid) {
+    ltl_factor_lane<TP>(tab, In{q, ld, b}, F);
+  }
+  __syncthreads();
+  if (solver && valid) {
+    ltl_solve_y<TP>(F, LdsRow::In{rhs});
+    ltl_back<TP, 1>(F, [&](int, int k, float v) __attribute__((always_inline)) { Out{dqdd, ld, b}(k, v); });
+  }
+}
+
 // ---- controller workloads for one frame E: the last body (a leaf) ahead of
 // time, any other body compiled at run time on its first use.
 template <class TP, int E = TP::N - 1>

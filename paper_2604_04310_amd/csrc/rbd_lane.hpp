@@ -743,6 +743,10 @@ struct Ltl {
 struct AllRhs {
   static constexpr bool on(int, int) { return true; }
 };
+// No right-hand side at all: the factor alone.
+struct NoRhs {
+  static constexpr bool on(int, int) { return false; }
+};
 
 // Row K given row K of M (Mr[j] for ancestors j, Mkk) and b_K.
 template <class TP, int K, int NRHS, class MASK = AllRhs>
@@ -812,6 +816,23 @@ RBD_DI void ltl_back(const Ltl<TP, NRHS>& F, const SINK& sink) {
       x[K] = acc * F.Linv[K];
       sink(r, K, x[K]);
     });
+  });
+}
+
+// y of L^T y = b for a factor computed without right-hand side (b(k) gives
+// entry k): leaves first, each entry from its descendants', the same
+// arithmetic as the fused sweep does while it factors.
+template <class TP, class B>
+RBD_DI void ltl_solve_y(Ltl<TP, 1>& F, const B& b) {
+  constexpr int NV = TP::NV;
+  sfor_rev<0, NV>([&](auto K_) __attribute__((always_inline)) {
+    constexpr int K = decltype(K_)::value;
+    float acc = b(K);
+    sfor<K + 1, NV>([&](auto D_) __attribute__((always_inline)) {
+      constexpr int Dd = decltype(D_)::value;
+      if constexpr (TP::is_danc(K, Dd)) acc = acc - F.L[cidx<TP::lidx(Dd, K)>] * F.y[0][Dd];
+    });
+    F.y[0][K] = acc * F.Linv[K];
   });
 }
 
@@ -925,6 +946,36 @@ RBD_DI void fwd_dyn_lane(const float* __restrict__ t, const QI& q, const QDI& qd
   });
 
   ltl_back<TP, NRHS>(F, sink);
+}
+
+// The branch-sparse L^T L factor of M(q) alone: the bias-free sweep of
+// fwd_dyn_lane (joint rotations down, CRBA rows and factor rows as subtrees
+// close) without right-hand sides and without the solve.
+template <class TP, class QI>
+RBD_DI void ltl_factor_lane(const float* __restrict__ t, const QI& q, Ltl<TP, 1>& F) {
+  constexpr int N = TP::N, NV = TP::NV;
+  M3 R[N];
+  Inr Ic[N];
+  auto backward = [&](auto J_) __attribute__((always_inline)) {
+    constexpr int J = decltype(J_)::value;
+    constexpr int P = TP::parent(J);
+    if constexpr (TP::free_body(J)) {
+      ltl_base_rows<TP, 1>(F, Ic[J], [](int, int) __attribute__((always_inline)) { return 0.0f; }, NoRhs{});
+    } else {
+      float Mr[NV > 1 ? NV : 1];
+      crba_row<TP, J>(t, R, Ic[J], Mr);
+      const float bk[1] = {0.0f};
+      ltl_row<TP, TP::vofs(J), 1, NoRhs>(F, Mr, Ic[J].zz, bk);
+      if constexpr (P >= 0) xinr_acc(R[J], load_r<J>(t), Ic[J], Ic[P]);
+    }
+  };
+  sfor<0, N>([&](auto I_) __attribute__((always_inline)) {
+    constexpr int I = decltype(I_)::value;
+    if constexpr (TP::free_body(I)) R[I] = quat_rot(q(3), q(4), q(5), q(6));
+    else R[I] = joint_rot<I>(t, q(cidx<TP::qofs(I)>));
+    Ic[I] = load_inr<I>(t);
+    close_subtrees<TP, I, I>(backward);
+  });
 }
 
 // =================================================================== fwd_dyn tangent

@@ -115,7 +115,7 @@ def test_rotated_humanoid_batch_65536(rbd):
     del J
 
 
-@pytest.mark.parametrize("name,B", [("chain7", 1 << 18), ("humanoid30", 32768)])
+@pytest.mark.parametrize("name,B", [("chain7", 1 << 18), ("humanoid30", 32768), ("humanoid30", 65536)])
 def test_vjp_full_batch(rbd, name, B):
     desc = W.chain(7) if name == "chain7" else W.humanoid()
     m = rbd.Model(desc, 0)
@@ -129,10 +129,12 @@ def test_vjp_full_batch(rbd, name, B):
     assert vjp_err([cols(gq, idx), cols(gqd, idx), cols(gtau, idx)], [rq, rqd, rtau]) < 1e-3
 
 
-@pytest.mark.parametrize("name,B", [("chain7", 1 << 18), ("humanoid30", 32768)])
+@pytest.mark.parametrize("name,B", [("chain7", 1 << 18), ("humanoid30", 32768), ("humanoid30", 65536),
+                                    ("humanoid30", 32768 + 37)])
 def test_jvp_full_batch(rbd, name, B):
-    """The forward-mode derivative at the adjoint's benchmark sizes: finite everywhere, 256 states
-    against central differences of the oracle along the same tangent."""
+    """The forward-mode derivative at the adjoint's benchmark sizes (the humanoid on two waves per 64
+    instances up to 32768, one wave above): finite everywhere, 256 states against central
+    differences of the oracle along the same tangent."""
     desc = W.chain(7) if name == "chain7" else W.humanoid()
     m = rbd.Model(desc, 0)
     st = W.states(desc, B, 106)

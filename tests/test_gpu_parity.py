@@ -357,6 +357,15 @@ def test_batch_edges(rbd, B):
         return
     qdd = rbd.fwd_dyn(m, gpu(st.q), gpu(st.qd), gpu(st.tau))
     assert rel_err(host(qdd), O.fwd_dyn(desc, st.q, st.qd, st.tau)) < TOL_QDD
+    # the derivatives on a ragged last block (the tangent on two waves per 64 instances, the adjoint
+    # parked in LDS)
+    rng = np.random.Generator(np.random.PCG64(213))
+    dx = [W._f32(rng.normal(size=x.shape)) for x in (st.q, st.qd, st.tau)]
+    dqdd = host(rbd.fwd_dyn_jvp(m, gpu(st.q), gpu(st.qd), gpu(st.tau), *[gpu(x) for x in dx]))
+    assert vjp_err([dqdd], [O.fwd_dyn_jvp_fd(desc, st.q, st.qd, st.tau, *dx)]) < TOL_VJP
+    gbar = W.cotangent(desc.nv, B, 214)
+    g = [host(x) for x in rbd.fwd_dyn_vjp(m, gpu(st.q), gpu(st.qd), gpu(st.tau), gpu(gbar))]
+    assert vjp_err(g, list(O.fwd_dyn_vjp_fd(desc, st.q, st.qd, st.tau, gbar))) < TOL_VJP
 
 
 def test_special_states(rbd):
