@@ -198,11 +198,14 @@ rbd_status rbd_aba(const rbd_model* model, int64_t batch, int64_t ld, const floa
  * f_ext (nullable: none; layout as for rbd_rnea). Computed as
  * M^-1 (dtau - dID/dq dq - dID/dqd dqd) at qdd = FD(q, qd, tau, F), with ID
  * including -sum_i J_i(q)^T F_i: the fused forward dynamics, a sweep of
- * tangent inverse dynamics, then a solve with M, all in one kernel. With
- * forces, a free base's position tangent moves them relative to the robot.
- * qdd (nullable) also receives the forward dynamics. The forward dynamics is
- * kept in qdd (or in dqdd) between the sweeps, so qdd and dqdd must not
- * overlap (RBD_E_INVAL). */
+ * tangent inverse dynamics, then a solve with M, all in one kernel (for a
+ * tree of more than 16 DoFs at a batch of at most 32768, on two waves per 64
+ * instances: one runs the first two sweeps while the other factors M, and
+ * the right-hand side passes between them through LDS). With forces, a free
+ * base's position tangent moves them relative to the robot. qdd (nullable)
+ * also receives the forward dynamics. The forward dynamics may be kept in qdd
+ * (or in dqdd) between the sweeps, so qdd and dqdd must not overlap
+ * (RBD_E_INVAL). */
 rbd_status rbd_fwd_dyn_jvp(const rbd_model* model, int64_t batch, int64_t ld, const float* q, const float* qd,
                            const float* tau, const float* f_ext, const float* dq, const float* dqd,
                            const float* dtau, const float* df_ext, float* qdd, float* dqdd, hipStream_t stream);
@@ -214,9 +217,11 @@ rbd_status rbd_fwd_dyn_jvp(const rbd_model* model, int64_t batch, int64_t ld, co
  * dqdd/dqd [nv][ld], g_tau = M^-1 g_qdd [nv][ld], and g_f_ext = g_qdd^T
  * dqdd/dF [n_bodies*6][ld]: for body i, J_i lam with lam = M^-1 g_qdd, the
  * twist of body i in world axes at the world origin, [v_O; w] (it pairs with
- * F_i = [f; n_O]). Any of the four outputs may be NULL (not computed). Between
- * the kernel's two sweeps the requested outputs hold the forward dynamics and
- * M^-1 g_qdd, so they must not overlap one another (RBD_E_INVAL). */
+ * F_i = [f; n_O]). Any of the four outputs may be NULL (not computed). One
+ * kernel: a solve for the forward dynamics and M^-1 g_qdd with one factor,
+ * then an adjoint sweep of inverse dynamics; between the two the solutions
+ * are kept in LDS (trees of more than 16 DoFs) or in the requested g_qd and
+ * g_tau outputs, so the outputs must not overlap one another (RBD_E_INVAL). */
 rbd_status rbd_fwd_dyn_vjp(const rbd_model* model, int64_t batch, int64_t ld, const float* q, const float* qd,
                            const float* tau, const float* f_ext, const float* g_qdd, float* g_q, float* g_qd,
                            float* g_tau, float* g_f_ext, hipStream_t stream);
