@@ -489,8 +489,9 @@ class Server:
         check(lib().rbd_server_create(C.byref(cfg), C.byref(self._h)))
         self._live = {}
 
-    def submit(self, model: Model, op: int, inputs: Sequence[np.ndarray]):
-        """Queue one request; returns (ticket, outputs) with outputs filled once waited."""
+    def submit(self, model: Model, op: int, inputs: Sequence[np.ndarray], outputs=None):
+        """Queue one request; returns (ticket, outputs) with outputs filled once waited. outputs: optional
+        C-contiguous float32 arrays [batch, rows] to write the results into, else new ones."""
         in_rows, out_rows = op_shapes(model, op)
         if len(inputs) != len(in_rows):
             raise ValueError(f"op {op} takes {len(in_rows)} inputs")
@@ -501,7 +502,14 @@ class Server:
             if x.shape != (batch, r):
                 raise ValueError(f"input of shape {x.shape}, expected {(batch, r)}")
             ins.append(x)
-        outs = [np.empty((batch, r), dtype=np.float32) for r in out_rows]
+        if outputs is None:
+            outs = [np.empty((batch, r), dtype=np.float32) for r in out_rows]
+        else:
+            outs = list(outputs)
+            if len(outs) != len(out_rows) or any(
+                    o.dtype != np.float32 or o.shape != (batch, r) or not o.flags.c_contiguous
+                    for o, r in zip(outs, out_rows)):
+                raise ValueError("outputs do not match the operation")
         pin = (C.c_void_p * 4)(*[C.c_void_p(x.ctypes.data) for x in ins] + [None] * (4 - len(ins)))
         pout = (C.c_void_p * 3)(*[C.c_void_p(x.ctypes.data) for x in outs] + [None] * (3 - len(outs)))
         t = C.c_uint64()

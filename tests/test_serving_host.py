@@ -104,8 +104,8 @@ def test_a_failed_group_fails_only_its_own_requests(rbd, models):
     reqs = []
     for k in range(40):
         ins = make_request(rbd, m, rbd.OP_FWD_DYN, 16 + k, 100 + k)
-        t, outs = srv.submit(m, rbd.OP_FWD_DYN, ins)
-        outs[0][:] = -7.0  # sentinel: a failed request's outputs are not written
+        # sentinel: a failed request's outputs are not written
+        t, outs = srv.submit(m, rbd.OP_FWD_DYN, ins, outputs=[np.full((16 + k, m.nv), -7.0, np.float32)])
         reqs.append((t, ins, outs))
     status = [srv.wait(t, 30.0) for t, _, _ in reqs]
     failed = [k for k, s in enumerate(status) if s != OK]
@@ -129,8 +129,7 @@ def test_cancel_a_queued_request(rbd, models):
     reqs = []
     for k in range(6):
         ins = make_request(rbd, m, rbd.OP_RNEA, 32, 200 + k)
-        t, outs = srv.submit(m, rbd.OP_RNEA, ins)
-        outs[0][:] = -7.0
+        t, outs = srv.submit(m, rbd.OP_RNEA, ins, outputs=[np.full((32, m.nv), -7.0, np.float32)])
         reqs.append((t, ins, outs))
     srv.cancel(reqs[2][0])
     assert srv.wait(reqs[2][0], 0.0) == CANCELLED
@@ -220,3 +219,60 @@ def test_group_byte_cap(rbd, models):
         assert np.array_equal(outs[0], expected(rbd, m, rbd.OP_FWD_DYN, ins)[0])
     assert srv.stats()["launches"] == 10
     srv.close()
+
+
+def test_many_clients_cancels_and_shutdown(rbd, models):
+    """Eight client threads submit a random mix while one of them cancels some of its queued
+    requests: every request completes exactly once, either cancelled (outputs untouched) or with
+    its own results, the counters match, and destroying the server with requests still queued
+    drains them."""
+    srv = rbd.Server(executor=rbd.EXEC_HOST, arena_bytes=2 << 20, n_streams=4, max_batch_requests=16,
+                     max_wait_us=200.0)
+    names = list(models)
+    done, errors = [], []
+    lock = threading.Lock()
+
+    def client(c):
+        rng = np.random.Generator(np.random.PCG64(900 + c))
+        mine = []
+        for k in range(60):
+            name = names[int(rng.integers(2))]
+            op = int(rng.choice([rbd.OP_FWD_DYN, rbd.OP_RNEA, rbd.OP_FWD_DYN_VJP]))
+            B = int(rng.integers(1, 300))
+            ins = make_request(rbd, models[name], op, B, 10000 * c + k)
+            outs = [np.full((B, r), -7.0, np.float32) for r in rbd.op_shapes(models[name], op)[1]]
+            t, outs = srv.submit(models[name], op, ins, outputs=outs)
+            mine.append((t, name, op, ins, outs))
+            if c == 0 and k % 3 == 0:
+                try:
+                    srv.cancel(t)
+                except rbd.RbdError:
+                    pass  # already left the queue
+        for t, name, op, ins, outs in mine:
+            st = srv.wait(t, 60.0)
+            try:
+                if st == CANCELLED:
+                    assert all(np.all(o == -7.0) for o in outs)
+                else:
+                    assert st == OK
+                    for got, ref in zip(outs, expected(rbd, models[name], op, ins)):
+                        assert np.array_equal(got, ref)
+            except AssertionError as e:
+                errors.append((c, t, str(e)))
+            with lock:
+                done.append((t, st))
+
+    srv.reset_stats()
+    threads = [threading.Thread(target=client, args=(c,)) for c in range(8)]
+    for th in threads:
+        th.start()
+    for th in threads:
+        th.join()
+    assert not errors, errors[:3]
+    assert len(done) == 480 and len({t for t, _ in done}) == 480
+    n_ok = sum(st == OK for _, st in done)
+    assert srv.stats()["requests"] == n_ok and n_ok >= 480 - 20
+    late = [srv.submit(models["chain7"], rbd.OP_FWD_DYN, make_request(rbd, models["chain7"], rbd.OP_FWD_DYN, 50, k))
+            for k in range(30)]
+    srv.close()  # drains the queue before freeing
+    assert all(np.isfinite(outs[0]).all() for _, outs in late)
