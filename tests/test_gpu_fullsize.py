@@ -148,12 +148,13 @@ def test_jvp_full_batch(rbd, name, B):
     assert vjp_err([cols(dqdd, idx)], [ref]) < 1e-3
 
 
-def test_derivatives_with_external_forces_at_batch_32768(rbd):
+@pytest.mark.parametrize("B", [32768, 65536])
+def test_derivatives_with_external_forces_full_batch(rbd, B):
     """The adjoint and the tangent of the humanoid's forward dynamics under external forces at the
-    derivatives' benchmark size: finite everywhere, 256 states against central differences."""
+    derivatives' benchmark size (two waves per 64 instances) and at 65536 (one): finite
+    everywhere, 256 states against central differences."""
     desc = W.humanoid()
     m = rbd.Model(desc, 0)
-    B = 32768
     st = W.states(desc, B, 111)
     rng = np.random.Generator(np.random.PCG64(112))
     fext = W._f32(rng.normal(0.0, 5.0, size=(B, desc.n_bodies * 6)))
