@@ -210,7 +210,7 @@ rbd_status launch_fwd_dyn_jvp(const rbd_model* m, int64_t batch, int64_t ld, con
     // two waves per 64 instances: the factor of M on its own wave, in
     // parallel with the solve for qdd and the tangent
     const Shape sh{dim3((unsigned)((batch + kTileLanes - 1) / kTileLanes)), dim3(2 * kTileLanes),
-                   (unsigned)(3 * m->nv * kTileLanes * sizeof(float))};
+                   (unsigned)(2 * m->nv * kTileLanes * sizeof(float))};
     return launch(m, ext ? KID_JVP_EXT_SPLIT : KID_JVP_SPLIT, sh, a, s, "rbd_fwd_dyn_jvp");
   }
   return launch(m, ext ? KID_JVP_EXT : KID_JVP, heavy_shape(batch), a, s, "rbd_fwd_dyn_jvp");
@@ -261,13 +261,6 @@ rbd_status launch_fwd_dyn_vjp(const rbd_model* m, int64_t batch, int64_t ld, con
   const bool ext = gfext || (fext && (gq || gqd));
   const float* tab = m->d_tab;
   void* a[] = {&tab, &batch, &ld, &q, &qd, &tau, &gqdd, &gq, &gqd, &gtau, &fext, &gfext};
-  if (large(m) && (gq || gqd || gfext) && batch <= kOneWavePerSimd / 2) {
-    // two waves per 64 instances: h and the factor of M at once, then the
-    // solves on one wave and the adjoint sweep on the other
-    const Shape sh{dim3((unsigned)((batch + kTileLanes - 1) / kTileLanes)), dim3(2 * kTileLanes),
-                   (unsigned)(3 * m->nv * kTileLanes * sizeof(float))};
-    return launch(m, ext ? KID_VJP_EXT_SPLIT : KID_VJP_SPLIT, sh, a, s, "rbd_fwd_dyn_vjp");
-  }
   if (large(m) && (gq || gqd || gfext)) {
     const Shape sh{dim3((unsigned)((batch + kTileLanes - 1) / kTileLanes)), dim3(kTileLanes),
                    (unsigned)(2 * m->nv * kTileLanes * sizeof(float))};

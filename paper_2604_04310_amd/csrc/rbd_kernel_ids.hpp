@@ -42,9 +42,7 @@
   X(KID_VJP_LDS, 3, k_fwd_dyn_vjp<TP, 3>)                 \
   X(KID_VJP_EXT_LDS, 8, k_fwd_dyn_vjp<TP, 3, true>)       \
   X(KID_JVP_SPLIT, 6, k_fwd_dyn_jvp_split<TP>)            \
-  X(KID_JVP_EXT_SPLIT, 8, k_fwd_dyn_jvp_split<TP, true>) \
-  X(KID_VJP_SPLIT, 3, k_fwd_dyn_vjp_split<TP>)            \
-  X(KID_VJP_EXT_SPLIT, 8, k_fwd_dyn_vjp_split<TP, true>)
+  X(KID_JVP_EXT_SPLIT, 8, k_fwd_dyn_jvp_split<TP, true>)
 
 namespace rbd {
 

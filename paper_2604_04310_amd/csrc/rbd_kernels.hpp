@@ -403,30 +403,12 @@ __global__ __launch_bounds__(kBlock) void k_fwd_dyn_jvp(const float* __restrict_
       SinkOne<OutAlias>{OutAlias{dqdd, ld3, b}});
 }
 
-// ---- the derivatives of a large tree on two waves per 64 instances (a block
-// of 128 lanes), for batches small enough that one wave per 64 instances
-// leaves SIMDs idle. Wave 0 computes the bias force h while wave 1 factors M;
-// wave 1 solves for qdd (and, for the adjoint, lam = M^-1 g_qdd); wave 0 runs
-// the tangent or adjoint sweep of inverse dynamics; for the tangent, wave 1
-// solves once more. Values pass between the waves through the block's dynamic
-// LDS, rows of 64 lanes: [h, then the tangent's right-hand side | qdd | lam].
-// Every lane of the block reaches every barrier.
-struct SplitLanes {
-  uint32_t lane, b;
-  bool solver, valid;
-  float* row[3];
-  template <int NV>
-  RBD_DI static SplitLanes make(float* lds, int64_t batch) {
-    SplitLanes s;
-    s.lane = threadIdx.x % kTileLanes;
-    s.solver = threadIdx.x >= kTileLanes;
-    s.b = blockIdx.x * kTileLanes + s.lane;
-    s.valid = s.b < batch;
-    for (int r = 0; r < 3; ++r) s.row[r] = lds + r * NV * kTileLanes + s.lane;
-    return s;
-  }
-};
-
+// ---- the same tangent on two waves per 64 instances (a block of 128 lanes),
+// for batches small enough that one wave per 64 instances leaves SIMDs idle:
+// wave 0 runs the fused solve for qdd and the tangent of inverse dynamics and
+// hands the right-hand side to wave 1 through LDS; wave 1 factors M in the
+// meantime, then solves with it. Dynamic LDS per block: [rhs rows | qdd rows],
+// 64 lanes each. Every lane of the block reaches the one barrier.
 template <class TP, bool EXT = false>
 __global__ __launch_bounds__(2 * kTileLanes) void k_fwd_dyn_jvp_split(
     const float* __restrict__ tab, int64_t batch, int64_t ld, const float* __restrict__ q,
@@ -434,94 +416,42 @@ __global__ __launch_bounds__(2 * kTileLanes) void k_fwd_dyn_jvp_split(
     const float* __restrict__ dqd, const float* __restrict__ dtau, float* qdd, float* dqdd,
     const float* __restrict__ fext, const float* __restrict__ dfext) {
   RBD_LANE_IO(TP);
-  extern __shared__ float lds_split[];
-  const SplitLanes L = SplitLanes::make<TP::NV>(lds_split, batch);
-  const uint32_t b = L.b;
+  constexpr int NV = TP::NV;
+  extern __shared__ float lds_jvp[];
+  const uint32_t lane = threadIdx.x % kTileLanes;
+  const bool solver = threadIdx.x >= kTileLanes;
+  const uint32_t b = blockIdx.x * kTileLanes + lane;
+  const bool valid = b < batch;
+  float* const rhs = lds_jvp + lane;
+  float* const qpark = lds_jvp + NV * kTileLanes + lane;
   auto fx_view = [&](const float* p, int64_t l) __attribute__((always_inline)) {
     if constexpr (EXT) return FextOpt{{p, l, b}};
     else return NoFext{};
   };
   Ltl<TP, 1> F;
-  // 1: h (wave 0) and the factor of M (wave 1) at once
-  if (!L.solver) {
-    if (L.valid)
-      rnea_lane<TP, false>(tab, In{q, ld, b}, In{qd, ld, b}, In{qd, ld, b}, LdsRow{L.row[0]}, fx_view(fext, ld));
-  } else if (L.valid) {
+  if (!solver) {
+    if (valid) {
+      fwd_dyn_lane<TP, 1>(tab, In{q, ld, b}, In{qd, ld, b}, RhsOne<In>{In{tau, ld, b}},
+                          SinkOne<LdsRow>{LdsRow{qpark}}, fx_view(fext, ld));
+      if (qdd) {
+        sfor<0, NV>([&](auto K_) __attribute__((always_inline)) {
+          constexpr int K = decltype(K_)::value;
+          Out{qdd, ld, b}(K, qpark[K * kTileLanes]);
+        });
+      }
+      sweep_boundary();
+      const int64_t l2 = opaque(ld);
+      id_tangent_lane<TP>(opaque_table(tab), In{opaque(q), l2, b}, In{opaque(qd), l2, b}, LdsRow::In{qpark},
+                          In{dq, l2, b}, In{dqd, l2, b}, In{dtau, l2, b}, LdsRow{rhs}, fx_view(opaque(fext), l2),
+                          fx_view(opaque(dfext), l2));
+    }
+  } else if (valid) {
     ltl_factor_lane<TP>(tab, In{q, ld, b}, F);
   }
   __syncthreads();
-  // 2: qdd = M^-1 (tau - h)
-  if (L.solver && L.valid) {
-    const In ti{tau, ld, b};
-    const float* h = L.row[0];
-    ltl_solve_y<TP>(F, [&](int k) __attribute__((always_inline)) { return ti(k) - h[k * kTileLanes]; });
-    ltl_back<TP, 1>(F, [&](int, int k, float v) __attribute__((always_inline)) {
-      L.row[1][k * kTileLanes] = v;
-      if (qdd) Out{qdd, ld, b}(k, v);
-    });
-  }
-  __syncthreads();
-  // 3: the tangent of inverse dynamics at (q, qd, qdd): dtau - d(ID)
-  if (!L.solver && L.valid) {
-    const int64_t l2 = opaque(ld);
-    id_tangent_lane<TP>(opaque_table(tab), In{opaque(q), l2, b}, In{opaque(qd), l2, b}, LdsRow::In{L.row[1]},
-                        In{dq, l2, b}, In{dqd, l2, b}, In{dtau, l2, b}, LdsRow{L.row[0]}, fx_view(opaque(fext), l2),
-                        fx_view(opaque(dfext), l2));
-  }
-  __syncthreads();
-  // 4: dqdd = M^-1 (dtau - d(ID))
-  if (L.solver && L.valid) {
-    ltl_solve_y<TP>(F, LdsRow::In{L.row[0]});
+  if (solver && valid) {
+    ltl_solve_y<TP>(F, LdsRow::In{rhs});
     ltl_back<TP, 1>(F, [&](int, int k, float v) __attribute__((always_inline)) { Out{dqdd, ld, b}(k, v); });
-  }
-}
-
-template <class TP, bool EXT = false>
-__global__ __launch_bounds__(2 * kTileLanes) void k_fwd_dyn_vjp_split(
-    const float* __restrict__ tab, int64_t batch, int64_t ld, const float* __restrict__ q,
-    const float* __restrict__ qd, const float* __restrict__ tau, const float* __restrict__ gqdd, float* gq,
-    float* gqd, float* gtau, const float* __restrict__ fext, float* gfext) {
-  RBD_LANE_IO(TP);
-  extern __shared__ float lds_split[];
-  const SplitLanes L = SplitLanes::make<TP::NV>(lds_split, batch);
-  const uint32_t b = L.b;
-  auto fx_view = [&](const float* p, int64_t l) __attribute__((always_inline)) {
-    if constexpr (EXT) return FextOpt{{p, l, b}};
-    else return NoFext{};
-  };
-  auto gf_view = [&](int64_t l) __attribute__((always_inline)) {
-    if constexpr (EXT) return GFOut{{gfext, l, b}};
-    else return NoGF{};
-  };
-  Ltl<TP, 1> F;
-  // 1: h (wave 0) and the factor of M (wave 1) at once
-  if (!L.solver) {
-    if (L.valid)
-      rnea_lane<TP, false>(tab, In{q, ld, b}, In{qd, ld, b}, In{qd, ld, b}, LdsRow{L.row[0]}, fx_view(fext, ld));
-  } else if (L.valid) {
-    ltl_factor_lane<TP>(tab, In{q, ld, b}, F);
-  }
-  __syncthreads();
-  // 2: qdd = M^-1 (tau - h) and lam = M^-1 g_qdd (g_tau = lam)
-  if (L.solver && L.valid) {
-    const In ti{tau, ld, b}, gi{gqdd, ld, b};
-    const float* h = L.row[0];
-    ltl_solve_y<TP>(F, [&](int k) __attribute__((always_inline)) { return ti(k) - h[k * kTileLanes]; });
-    ltl_back<TP, 1>(F, [&](int, int k, float v) __attribute__((always_inline)) { L.row[1][k * kTileLanes] = v; });
-    ltl_solve_y<TP>(F, gi);
-    ltl_back<TP, 1>(F, [&](int, int k, float v) __attribute__((always_inline)) {
-      L.row[2][k * kTileLanes] = v;
-      if (gtau) Out{gtau, ld, b}(k, v);
-    });
-  }
-  __syncthreads();
-  // 3: the adjoint sweep of inverse dynamics at (q, qd, qdd) with cotangent lam
-  if (!L.solver && L.valid) {
-    const int64_t l2 = opaque(ld);
-    id_adjoint_lane<TP>(opaque_table(tab), In{opaque(q), l2, b}, In{opaque(qd), l2, b}, LdsRow::In{L.row[1]},
-                        LdsRow::In{L.row[2]}, OutOpt<OutAlias>{OutAlias{gq, l2, b}, gq != nullptr},
-                        OutOpt<OutAlias>{OutAlias{gqd, l2, b}, gqd != nullptr}, fx_view(opaque(fext), l2),
-                        gf_view(l2));
   }
 }
 
