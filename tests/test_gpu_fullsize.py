@@ -151,8 +151,8 @@ def test_jvp_full_batch(rbd, name, B):
 @pytest.mark.parametrize("B", [32768, 65536])
 def test_derivatives_with_external_forces_full_batch(rbd, B):
     """The adjoint and the tangent of the humanoid's forward dynamics under external forces at the
-    derivatives' benchmark size (two waves per 64 instances) and at 65536 (one): finite
-    everywhere, 256 states against central differences."""
+    derivatives' benchmark size and at 65536 (the tangent on two waves per 64 instances, then on
+    one): finite everywhere, 256 states against central differences."""
     desc = W.humanoid()
     m = rbd.Model(desc, 0)
     st = W.states(desc, B, 111)
