@@ -19,15 +19,19 @@ RBD_DI uint32_t lane_id() { return blockIdx.x * blockDim.x + threadIdx.x; }
 // so model constants, inputs, row addresses and what is computed from them
 // (joint sines and cosines) are reloaded and recomputed in each sweep instead
 // of being held in registers across all of them.
-// The asm operand keeps the pointer's address space (global for inputs; the
-// table's copy, opaque_table, is in the lane header), so loads through the
-// copy stay global loads with a scalar base.
+// The asm operand keeps the pointer's address space (global for inputs,
+// constant for the model table), so loads through the copy stay global loads
+// with a scalar base, and table reads stay scalar loads.
 RBD_DI const float* opaque(const float* p) {
   auto g = (const __attribute__((address_space(1))) float*)p;
   asm volatile("" : "+s"(g));
   return (const float*)g;
 }
-
+RBD_DI const float* opaque_table(const float* p) {
+  auto c = (const __attribute__((address_space(4))) float*)p;
+  asm volatile("" : "+s"(c));
+  return (const float*)c;
+}
 RBD_DI int64_t opaque(int64_t x) {
   asm volatile("" : "+s"(x));
   return x;

@@ -474,18 +474,6 @@ RBD_DI Frc fext_body(const FX& fx, const M3& Rw, V3 pw) {
   return {mulT(Rw, cross_add(f, pw, n)), mulT(Rw, f)};
 }
 
-// The model table's pointer, hidden from the optimiser (an empty asm on its
-// scalar register, typed as constant memory so reads through it stay scalar
-// loads). Loads through such a copy are not merged with earlier loads of the
-// same constants, so a constant is not held in a register from a body's
-// forward step until its backward step (or a descendant's), where it is read
-// again.
-RBD_DI const float* opaque_table(const float* p) {
-  auto c = (const __attribute__((address_space(4))) float*)p;
-  asm volatile("" : "+s"(c));
-  return (const float*)c;
-}
-
 // =================================================================== FK
 // World pose of every body in the user's body axes: [R | p] row-major.
 template <class TP, class QI, class TO>
@@ -876,7 +864,7 @@ RBD_DI void crba_row(const float* __restrict__ t, const M3* R, const Inr& IcJ, f
 // and a final root-to-leaves sweep solves L x = y.
 // BIAS = false solves M x = rhs alone (no bias force, qd unused).
 template <class TP, int NRHS, class QI, class QDI, class RHS, class SINK, class FX = NoFext, bool BIAS = true>
-RBD_DI void fwd_dyn_lane(const float* __restrict__ t0, const QI& q, const QDI& qd, const RHS& rhs, const SINK& sink,
+RBD_DI void fwd_dyn_lane(const float* __restrict__ t, const QI& q, const QDI& qd, const RHS& rhs, const SINK& sink,
                          const FX& fx = FX{}) {
   constexpr int N = TP::N, NV = TP::NV;
   constexpr int NW = FX::kOn ? N : 1;
@@ -887,18 +875,12 @@ RBD_DI void fwd_dyn_lane(const float* __restrict__ t0, const QI& q, const QDI& q
   Frc f[N];
   Inr Ic[N];
   Ltl<TP, NRHS> F;
-  const float* __restrict__ t = t0;
   const V3 g = load_g<TP>(t);
   const V3 mg = {-g.x, -g.y, -g.z};
 
   auto backward = [&](auto J_) __attribute__((always_inline)) {
     constexpr int J = decltype(J_)::value;
     constexpr int P = TP::parent(J);
-    // a large tree's backward step reads its constants (the CRBA walk's
-    // ancestor offsets, its own offset) afresh: merged with the forward
-    // step's loads they were held in registers across whole subtrees (SGPR
-    // spills: 1 176 lane moves per wave for the humanoid, 224 this way)
-    const float* t = TP::NV > 16 ? opaque_table(t0) : t0;
     if constexpr (TP::free_body(J)) {
       if constexpr (BIAS) {
         const float hb[6] = {f[J].f.x, f[J].f.y, f[J].f.z, f[J].n.x, f[J].n.y, f[J].n.z};
