@@ -65,6 +65,7 @@ def lib():
         L.orc_fwd_dyn.argtypes = [m, i64, d, d, d, d, C.c_int]
         L.orc_fwd_dyn_vjp_fd.argtypes = [m, i64, d, d, d, d, d, d, d, d, d, C.c_double, C.c_int]
         L.orc_fwd_dyn_jvp_fd.argtypes = [m, i64, d, d, d, d, d, d, d, d, d, C.c_double, C.c_int]
+        L.orc_rnea_jvp_fd.argtypes = [m, i64, d, d, d, d, d, d, d, d, d, C.c_double]
         L.orc_count_ops.argtypes = [m, C.c_int, P(C.c_longlong)]
         L.orc_max_threads.argtypes = []
         L.orc_set_threads.argtypes = [C.c_int]
@@ -199,6 +200,21 @@ def fwd_dyn_jvp_fd(desc, q, qd, tau, dq, dqd, dtau, h=1e-6, method=METHOD_LTL, f
                                     None if fx is None else _dp(fx), _dp(dq), _dp(dqd), _dp(dtau),
                                     None if dfx is None else _dp(dfx), _dp(dqdd), h, method), "jvp")
     return dqdd
+
+
+def rnea_jvp_fd(desc, q, qd, qdd, dq, dqd, dqdd, h=1e-6, fext=None, dfext=None):
+    """d tau along (dq, dqd, dqdd[, dfext]) of inverse dynamics tau = ID(q, qd, qdd, F), Eq. (1): one
+    central difference of step h (with external forces fext when given; either force array may be
+    None)."""
+    q, qd, qdd, dq, dqd, dqdd = _c(q), _c(qd), _c(qdd), _c(dq), _c(dqd), _c(dqdd)
+    B = q.shape[0]
+    fx = None if fext is None else _c(np.asarray(fext).reshape(B, -1))
+    dfx = None if dfext is None else _c(np.asarray(dfext).reshape(B, -1))
+    dtau = np.empty_like(qd)
+    _check(lib().orc_rnea_jvp_fd(C.byref(_model(desc)), B, _dp(q), _dp(qd), _dp(qdd),
+                                 None if fx is None else _dp(fx), _dp(dq), _dp(dqd), _dp(dqdd),
+                                 None if dfx is None else _dp(dfx), _dp(dtau), h), "rnea jvp")
+    return dtau
 
 
 OPS = {"fk": 0, "jacobian": 1, "rnea": 2, "rnea_bias": 3, "crba": 4, "fwd_dyn_llt": 5, "fwd_dyn_ltl": 6, "aba": 7}

@@ -872,6 +872,41 @@ int orc_fwd_dyn_jvp_fd(const orc_model* d, int64_t B, const double* q, const dou
   return 0;
 }
 
+// Jacobian-vector product of inverse dynamics tau = ID(q, qd, qdd, F) along
+// (dq, dqd, dqdd, dF): one central difference of step h (raw quaternion
+// components perturbed like any other coordinate). fext and dfext may be null.
+int orc_rnea_jvp_fd(const orc_model* d, int64_t B, const double* q, const double* qd, const double* qdd,
+                    const double* fext, const double* dq, const double* dqd, const double* dqdd,
+                    const double* dfext, double* dtau, double h) {
+  Model M;
+  if (build_model(d, M)) return 1;
+  const int nq = M.nq, nv = M.nv, nf = 6 * M.n;
+  const bool ext = fext || dfext;
+#pragma omp parallel for schedule(static)
+  for (int64_t b = 0; b < B; ++b) {
+    std::vector<double> xp(nq), xm(nq), yp(nv), ym(nv), zp(nv), zm(nv), tp(nv), tm(nv), fp(nf), fm(nf);
+    for (int k = 0; k < nq; ++k) {
+      xp[k] = q[b * nq + k] + h * dq[b * nq + k];
+      xm[k] = q[b * nq + k] - h * dq[b * nq + k];
+    }
+    for (int k = 0; k < nv; ++k) {
+      yp[k] = qd[b * nv + k] + h * dqd[b * nv + k];
+      ym[k] = qd[b * nv + k] - h * dqd[b * nv + k];
+      zp[k] = qdd[b * nv + k] + h * dqdd[b * nv + k];
+      zm[k] = qdd[b * nv + k] - h * dqdd[b * nv + k];
+    }
+    for (int k = 0; k < nf && ext; ++k) {
+      const double f0 = fext ? fext[b * nf + k] : 0.0, df = dfext ? dfext[b * nf + k] : 0.0;
+      fp[k] = f0 + h * df;
+      fm[k] = f0 - h * df;
+    }
+    rnea(M, xp.data(), yp.data(), zp.data(), tp.data(), ext ? fp.data() : (const double*)nullptr);
+    rnea(M, xm.data(), ym.data(), zm.data(), tm.data(), ext ? fm.data() : (const double*)nullptr);
+    for (int k = 0; k < nv; ++k) dtau[b * nv + k] = (tp[k] - tm[k]) / (2.0 * h);
+  }
+  return 0;
+}
+
 // Vector-Jacobian product of qdd = FD(q, qd, tau, F) with cotangent gbar, by
 // central differences of step h on every coordinate (raw quaternion
 // components and every external-force component included). fext may be null

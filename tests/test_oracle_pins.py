@@ -631,3 +631,53 @@ def test_osc_commands_exactly_the_task_acceleration(name):
     tau0 = CT.osc(desc, st.q, st.qd, e, tgt, kp, kd, 0.0) - O.rnea(desc, st.q, st.qd)
     F, *_ = np.linalg.lstsq(np.swapaxes(J[0], 0, 1), tau0[0], rcond=None)
     assert np.allclose(np.swapaxes(J[0], 0, 1) @ F, tau0[0], rtol=1e-9, atol=1e-9 * np.abs(tau0[0]).max())
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_rnea_jvp_single_pendulum(seed):
+    """The tangent of one revolute joint's inverse dynamics in closed form: tau = M qdd + dV/dq, so
+    d tau = M dqdd + (d2V/dq2) dq with d(a x R c)/dq = a x (a x R c), and qd enters nowhere."""
+    d, rng = _single_body(seed)
+    a = d.axis[0] / np.linalg.norm(d.axis[0])
+    c, m = d.com[0], d.mass[0]
+    Ic = inertia_matrix(d, 0)
+    Rf = d.origin[0, :9].reshape(3, 3)
+    B = 16
+    q = rng.uniform(-np.pi, np.pi, size=(B, 1))
+    qd, qdd, dq, dqd, dqdd = (rng.normal(size=(B, 1)) for _ in range(5))
+    M_ref = a @ Ic @ a + m * np.dot(np.cross(a, c), np.cross(a, c))
+    Rq = Rotation.from_rotvec(a[None, :] * q).as_matrix()
+    lever = np.einsum("bij,j->bi", Rq, c)
+    d2V = -m * np.einsum("i,ij,bj->b", d.gravity, Rf, np.cross(a[None, :], np.cross(a[None, :], lever)))
+    ref = M_ref * dqdd[:, 0] + d2V * dq[:, 0]
+    got = O.rnea_jvp_fd(d, q, qd, qdd, dq, dqd, dqdd)[:, 0]
+    assert np.allclose(got, ref, rtol=1e-7, atol=1e-8)
+
+
+@pytest.mark.parametrize("name", ["chain7", "humanoid30"])
+def test_rnea_jvp_along_qdd_is_M(name):
+    """Inverse dynamics is affine in qdd: its tangent along (0, 0, dqdd) is M(q) dqdd."""
+    desc = W.chain(7) if name == "chain7" else W.humanoid()
+    st = W.states(desc, 8, 41)
+    rng = np.random.Generator(np.random.PCG64(42))
+    qdd, dqdd = rng.normal(size=st.qd.shape), rng.normal(size=st.qd.shape)
+    z = np.zeros_like
+    got = O.rnea_jvp_fd(desc, st.q, st.qd, qdd, z(st.q), z(st.qd), dqdd)
+    ref = np.einsum("bij,bj->bi", O.crba(desc, st.q), dqdd)
+    assert np.abs(got - ref).max() < 1e-7 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("forces", [False, True])
+def test_rnea_jvp_inverts_fwd_dyn_jvp(forces):
+    """ID(q, qd, FD(q, qd, tau, F), F) = tau, so along any (dq, dqd, dtau, dF) the tangent of
+    inverse dynamics at dqdd = the tangent of forward dynamics returns dtau."""
+    desc = W.humanoid()
+    st = W.states(desc, 8, 43)
+    rng = np.random.Generator(np.random.PCG64(44))
+    dq, dqd, dtau = (rng.normal(size=x.shape) for x in (st.q, st.qd, st.tau))
+    fx = rng.normal(0.0, 5.0, size=(8, desc.n_bodies * 6)) if forces else None
+    dfx = rng.normal(size=(8, desc.n_bodies * 6)) if forces else None
+    qdd = O.fwd_dyn(desc, st.q, st.qd, st.tau, fext=None if fx is None else fx.reshape(8, -1, 6))
+    dqdd = O.fwd_dyn_jvp_fd(desc, st.q, st.qd, st.tau, dq, dqd, dtau, fext=fx, dfext=dfx)
+    got = O.rnea_jvp_fd(desc, st.q, st.qd, qdd, dq, dqd, dqdd, fext=fx, dfext=dfx)
+    assert np.abs(got - dtau).max() < 1e-5 * np.abs(dtau).max()
