@@ -108,6 +108,7 @@ def counters_driver():
     tq, tqd, ttau = (soa(W._f32(np.random.default_rng(s).normal(size=(Bv, r))), torch)
                      for s, r in ((11, desc.nq), (12, desc.nv), (13, desc.nv)))
     step("fwd_dyn_jvp humanoid30 32768", lambda: rbd.fwd_dyn_jvp(m, vq, vqd, vtau, tq, tqd, ttau))
+    step("rnea_jvp humanoid30 32768", lambda: rbd.rnea_jvp(m, vq, vqd, vtau, tq, tqd, ttau))
     del q, qd, tau, out, vq, vqd, vtau, gq, tq, tqd, ttau
     torch.cuda.empty_cache()
     chain = W.chain(7)
@@ -189,6 +190,8 @@ def kernel_rooflines(O, W, desc, chain, ops, cnt, hbm):
                                               None, counter_batch=Bv),
         "fwd_dyn_jvp_humanoid30_b65536": valu("fwd_dyn_jvp_humanoid30", ops["fwd_dyn_jvp_humanoid30_b65536_us"], B,
                                               None, counter_batch=Bv),
+        "rnea_jvp_humanoid30_b65536": valu("rnea_jvp_humanoid30", ops["rnea_jvp_humanoid30_b65536_us"], B, None,
+                                           counter_batch=Bv),
         "osc_humanoid30": valu("osc_humanoid30", ops["osc_humanoid30_b65536_us"], B, None),
         "crba_humanoid30": mem("crba_humanoid30", ops["crba_humanoid30_b65536_us"], B, 4 * (desc.nq + nv * nv)),
         "fk_humanoid30": mem("fk_humanoid30", ops["fk_humanoid30_b65536_us"], B, 4 * (desc.nq + 12 * nb)),
@@ -224,7 +227,8 @@ def _kernel_key(short):
     topo = rest.split(",")[0].rstrip(">").strip()
     key = {"k_fwd_dyn": "fwd_dyn", "k_rnea": "rnea_bias", "k_aba": "aba", "k_crba": "crba", "k_fk": "fk",
            "k_jacobian": "jacobian", "k_osc": "osc", "k_diff_ik": "diff_ik", "k_fwd_dyn_vjp": "fwd_dyn_vjp",
-           "k_fwd_dyn_jvp": "fwd_dyn_jvp", "k_fwd_dyn_jvp_split": "fwd_dyn_jvp"}.get(base)
+           "k_fwd_dyn_jvp": "fwd_dyn_jvp", "k_fwd_dyn_jvp_split": "fwd_dyn_jvp",
+           "k_rnea_jvp": "rnea_jvp"}.get(base)
     return f"{key}_{topo}" if key and topo in ("humanoid30", "chain7") else None
 
 
@@ -672,7 +676,10 @@ def main():
                      for s, r in ((11, desc.nq), (12, desc.nv), (13, desc.nv)))
     ops["fwd_dyn_jvp_humanoid30_b65536_us"] = 1e3 * time_launches(
         lambda: rbd.fwd_dyn_jvp(model, q, qd, tau, tq, tqd, ttau), n_t, torch)
-    del tq, tqd, ttau, g65
+    acc = soa(W._f32(np.random.default_rng(15).normal(size=(BATCH, desc.nv))), torch)
+    ops["rnea_jvp_humanoid30_b65536_us"] = 1e3 * time_launches(
+        lambda: rbd.rnea_jvp(model, q, qd, acc, tq, tqd, ttau), n_t, torch)
+    del tq, tqd, ttau, g65, acc
     tg = soa(W._f32(targets(W, BATCH)), torch)
     ops["osc_humanoid30_b65536_us"] = 1e3 * time_launches(lambda: rbd.osc(model, q, qd, tg, 50.0, 10.0, 2.0), n_t, torch)
     ops["diff_ik_humanoid30_b65536_us"] = 1e3 * time_launches(lambda: rbd.diff_ik(model, q, tg, 2.0, 0.05), n_t, torch)

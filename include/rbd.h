@@ -17,6 +17,7 @@
  *                    algorithm, O(n), no mass matrix (Sec. II names it among
  *                    Featherstone's algorithms; Sec. VI-A, future work)
  *   rbd_fwd_dyn_jvp  forward-mode derivative of rbd_fwd_dyn (Sec. IV-A, Fig. 2)
+ *   rbd_rnea_jvp     forward-mode derivative of rbd_rnea (Sec. IV-A, Fig. 2)
  *   rbd_diff_ik      differential IK for an end effector (Sec. IV, Table II)
  *   rbd_osc          operational-space control torques (Sec. IV, Table II)
  *   rbd_fwd_dyn_vjp  reverse-mode derivative of rbd_fwd_dyn (Sec. I, AD)
@@ -138,7 +139,7 @@ const char* rbd_model_topology(const rbd_model* model);
  * time per process). Kernels already in the directory are kept. Needs no GPU.
  * Synchronous. Used to install a robot's kernels before its first use.
  * Errors: RBD_E_INVAL, RBD_E_COMPILE. */
-#define RBD_N_KERNELS 33
+#define RBD_N_KERNELS 35
 rbd_status rbd_precompile_topology(int32_t n_bodies, const int32_t* parent, int floating, const char* cache_dir,
                                    int32_t kernel);
 
@@ -209,6 +210,17 @@ rbd_status rbd_aba(const rbd_model* model, int64_t batch, int64_t ld, const floa
 rbd_status rbd_fwd_dyn_jvp(const rbd_model* model, int64_t batch, int64_t ld, const float* q, const float* qd,
                            const float* tau, const float* f_ext, const float* dq, const float* dqd,
                            const float* dtau, const float* df_ext, float* qdd, float* dqdd, hipStream_t stream);
+
+/* Jacobian-vector product of rbd_rnea (forward-mode AD of Eq. (1)): for
+ * tangents dq [nq][ld] (raw quaternion components included), dqd and dqdd
+ * [nv][ld], and external-force tangents df_ext [n_bodies*6][ld] (nullable:
+ * zero), dtau = dID/dq dq + dID/dqd dqd + M dqdd - sum_i (J_i^T F_i)' [nv][ld]
+ * at (q, qd, qdd) with external forces f_ext (nullable: none; layout as for
+ * rbd_rnea). One sweep of tangent inverse dynamics; dtau must not overlap an
+ * input (RBD_E_INVAL). */
+rbd_status rbd_rnea_jvp(const rbd_model* model, int64_t batch, int64_t ld, const float* q, const float* qd,
+                        const float* qdd, const float* f_ext, const float* dq, const float* dqd, const float* dqdd,
+                        const float* df_ext, float* dtau, hipStream_t stream);
 
 /* Vector-Jacobian product of rbd_fwd_dyn with external forces f_ext
  * (nullable: none; layout as for rbd_rnea), for the cotangent g_qdd [nv][ld]:

@@ -458,6 +458,23 @@ rbd_status rbd_fwd_dyn_jvp(const rbd_model* m, int64_t batch, int64_t ld, const 
   return launch_fwd_dyn_jvp(m, batch, ld, q, qd, tau, f_ext, dq, dqd, dtau, df_ext, qdd, dqdd, s);
 }
 
+rbd_status rbd_rnea_jvp(const rbd_model* m, int64_t batch, int64_t ld, const float* q, const float* qd,
+                        const float* qdd, const float* f_ext, const float* dq, const float* dqd, const float* dqdd,
+                        const float* df_ext, float* dtau, hipStream_t s) {
+  rbd_status st = check_batch(m, batch, ld, "rbd_rnea_jvp");
+  if (st != RBD_OK) return st;
+  if (batch > 0 && (!q || !qd || !qdd || !dq || !dqd || !dqdd || !dtau))
+    return fail(RBD_E_INVAL, "rbd_rnea_jvp: NULL array");
+  const int64_t nf = 6 * (int64_t)m->n;
+  if (output_overlaps(dtau, m->nv, {{q, m->nq}, {qd, m->nv}, {qdd, m->nv}, {f_ext, nf}, {dq, m->nq}, {dqd, m->nv},
+                                    {dqdd, m->nv}, {df_ext, nf}},
+                      ld, batch))
+    return fail(RBD_E_INVAL, "rbd_rnea_jvp: the output overlaps an input");
+  DeviceScope ds(m->device);
+  if (ds.st != RBD_OK) return ds.st;
+  return launch_rnea_jvp(m, batch, ld, q, qd, qdd, f_ext, dq, dqd, dqdd, df_ext, dtau, s);
+}
+
 // A controller frame is any body (the last one has ahead-of-time kernels).
 static rbd_status check_frame(const rbd_model* m, int32_t frame, const char* fn) {
   if (frame < 0 || frame >= m->n) return fail(RBD_E_INVAL, "%s: frame %d is not a body id (0..%d)", fn, frame, m->n - 1);

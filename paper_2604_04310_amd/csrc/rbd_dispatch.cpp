@@ -216,6 +216,15 @@ rbd_status launch_fwd_dyn_jvp(const rbd_model* m, int64_t batch, int64_t ld, con
   return launch(m, ext ? KID_JVP_EXT : KID_JVP, heavy_shape(batch), a, s, "rbd_fwd_dyn_jvp");
 }
 
+rbd_status launch_rnea_jvp(const rbd_model* m, int64_t batch, int64_t ld, const float* q, const float* qd,
+                           const float* qdd, const float* fext, const float* dq, const float* dqd, const float* dqdd,
+                           const float* dfext, float* dtau, hipStream_t s) {
+  if (batch == 0) return RBD_OK;
+  const float* tab = m->d_tab;
+  void* a[] = {&tab, &batch, &ld, &q, &qd, &qdd, &dq, &dqd, &dqdd, &dtau, &fext, &dfext};
+  return launch(m, (fext || dfext) ? KID_RNEA_JVP_EXT : KID_RNEA_JVP, heavy_shape(batch), a, s, "rbd_rnea_jvp");
+}
+
 // The controller kernel of `frame`: the set's own for the last body, else one
 // compiled for that frame at run time on first use.
 static rbd_status launch_frame(const rbd_model* m, bool osc, int frame, Shape sh, void** args, hipStream_t s,

@@ -42,7 +42,9 @@
   X(KID_VJP_LDS, 3, k_fwd_dyn_vjp<TP, 3>)                 \
   X(KID_VJP_EXT_LDS, 8, k_fwd_dyn_vjp<TP, 3, true>)       \
   X(KID_JVP_SPLIT, 6, k_fwd_dyn_jvp_split<TP>)            \
-  X(KID_JVP_EXT_SPLIT, 8, k_fwd_dyn_jvp_split<TP, true>)
+  X(KID_JVP_EXT_SPLIT, 8, k_fwd_dyn_jvp_split<TP, true>) \
+  X(KID_RNEA_JVP, 6, k_rnea_jvp<TP>)                      \
+  X(KID_RNEA_JVP_EXT, 8, k_rnea_jvp<TP, true>)
 
 namespace rbd {
 

@@ -455,6 +455,37 @@ __global__ __launch_bounds__(2 * kTileLanes) void k_fwd_dyn_jvp_split(
   }
 }
 
+// ---- tangent of inverse dynamics, Eq. (1), along (dq, dqd, dqdd[, dF]): one
+// sweep of id_tangent_lane with the acceleration tangent; the sweep writes
+// 0 - d(ID), stored negated as d(ID) (both steps exact).
+template <class V>
+struct On : V {  // a view whose entries are used (kOn)
+  static constexpr bool kOn = true;
+};
+template <class O>
+struct Neg {
+  O o;
+  RBD_DI void operator()(int c, float v) const { o(c, -v); }
+};
+
+template <class TP, bool EXT = false>
+__global__ __launch_bounds__(kBlock) void k_rnea_jvp(const float* __restrict__ tab, int64_t batch, int64_t ld,
+                                                     const float* __restrict__ q, const float* __restrict__ qd,
+                                                     const float* __restrict__ qdd, const float* __restrict__ dq,
+                                                     const float* __restrict__ dqd, const float* __restrict__ dqdd,
+                                                     float* __restrict__ dtau, const float* __restrict__ fext,
+                                                     const float* __restrict__ dfext) {
+  RBD_LANE_IO(TP);
+  const uint32_t b = lane_id();
+  if (b >= batch) return;
+  auto fx_view = [&](const float* p) __attribute__((always_inline)) {
+    if constexpr (EXT) return FextOpt{{p, ld, b}};
+    else return NoFext{};
+  };
+  id_tangent_lane<TP>(tab, In{q, ld, b}, In{qd, ld, b}, In{qdd, ld, b}, In{dq, ld, b}, In{dqd, ld, b}, NoFext{},
+                      Neg<Out>{Out{dtau, ld, b}}, fx_view(fext), fx_view(dfext), On<In>{In{dqdd, ld, b}});
+}
+
 // ---- controller workloads for one frame E: the last body (a leaf) ahead of
 // time, any other body compiled at run time on its first use.
 template <class TP, int E = TP::N - 1>

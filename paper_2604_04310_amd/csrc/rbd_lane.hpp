@@ -1001,11 +1001,13 @@ RBD_DI void ltl_factor_lane(const float* __restrict__ t, const QI& q, Ltl<TP, 1>
 // with eta_i = X eta_parent + S dq_i the body's pose tangent (a free base
 // starts from [dtheta; R^T dp], dtheta = 2 vec(conj(quat) (x) dquat) / |quat|^2),
 // the body-frame force changes by -eta_i x* F_i plus dF_i in body coordinates.
+// A tangent dqdd of the accelerations (DQDD with kOn) adds S dqdd_i to da_i:
+// then the sweep is the full tangent of inverse dynamics.
 template <class TP, class QI, class QDI, class QDDI, class DQI, class DQDI, class DTI, class OUT, class FX = NoFext,
-          class DFX = NoFext>
+          class DFX = NoFext, class DQDD = NoFext>
 RBD_DI void id_tangent_lane(const float* __restrict__ t, const QI& q, const QDI& qd, const QDDI& qdd,
                             const DQI& dq, const DQDI& dqd, const DTI& dtau, const OUT& out, const FX& fx = FX{},
-                            const DFX& dfx = DFX{}) {
+                            const DFX& dfx = DFX{}, const DQDD& dqdd = DQDD{}) {
   constexpr int N = TP::N;
   constexpr bool kExt = FX::kOn || DFX::kOn;
   constexpr int NE = kExt ? N : 1;
@@ -1069,6 +1071,7 @@ RBD_DI void id_tangent_lane(const float* __restrict__ t, const QI& q, const QDI&
       a[I] = {{qdd(3), qdd(4), qdd(5)}, ag + V3{qdd(0), qdd(1), qdd(2)}};
       dv[I] = {{dqd(3), dqd(4), dqd(5)}, {dqd(0), dqd(1), dqd(2)}};
       da[I] = {{0.0f, 0.0f, 0.0f}, dag};
+      if constexpr (DQDD::kOn) da[I] = da[I] + Mot{{dqdd(3), dqdd(4), dqdd(5)}, {dqdd(0), dqdd(1), dqdd(2)}};
     } else {
       R[I] = joint_rot<I>(t, q(cidx<TP::qofs(I)>));
       const float w = qd(cidx<TP::vofs(I)>);
@@ -1111,6 +1114,7 @@ RBD_DI void id_tangent_lane(const float* __restrict__ t, const QI& q, const QDI&
       da[I].w.y = __builtin_fmaf(-w, dv[I].w.x, __builtin_fmaf(-dw, v[I].w.x, da[I].w.y));
       da[I].v.x = __builtin_fmaf(w, dv[I].v.y, __builtin_fmaf(dw, v[I].v.y, da[I].v.x));
       da[I].v.y = __builtin_fmaf(-w, dv[I].v.x, __builtin_fmaf(-dw, v[I].v.x, da[I].v.y));
+      if constexpr (DQDD::kOn) da[I].w.z = da[I].w.z + dqdd(cidx<TP::vofs(I)>);
     }
     const Inr Ib = load_inr<I>(t);
     const Frc Iv = imul(Ib, v[I]);

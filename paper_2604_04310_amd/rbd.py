@@ -29,7 +29,7 @@ OP_FWD_DYN, OP_RNEA, OP_FWD_DYN_VJP = 0, 1, 2
 
 # Every symbol include/rbd.h declares.
 EXPORTS = ["rbd_model_create", "rbd_model_destroy", "rbd_model_dims", "rbd_model_topology", "rbd_fk",
-           "rbd_jacobian", "rbd_rnea", "rbd_crba", "rbd_fwd_dyn", "rbd_aba", "rbd_fwd_dyn_jvp", "rbd_fwd_dyn_vjp", "rbd_diff_ik", "rbd_osc", "rbd_status_str",
+           "rbd_jacobian", "rbd_rnea", "rbd_crba", "rbd_fwd_dyn", "rbd_aba", "rbd_fwd_dyn_jvp", "rbd_rnea_jvp", "rbd_fwd_dyn_vjp", "rbd_diff_ik", "rbd_osc", "rbd_status_str",
            "rbd_last_error", "rbd_device_count", "rbd_diag_fma_rate", "rbd_diag_hbm_rate", "rbd_precompile_topology", "rbd_server_create", "rbd_server_submit", "rbd_server_wait", "rbd_server_cancel",
            "rbd_server_get_stats", "rbd_server_reset_stats", "rbd_server_destroy", "rbd_diag_serve_load"]
 
@@ -100,6 +100,7 @@ def lib():
         L.rbd_aba.argtypes = [vp, i64, i64, vp, vp, vp, vp, vp, vp]
         L.rbd_fwd_dyn_vjp.argtypes = [vp, i64, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
         L.rbd_fwd_dyn_jvp.argtypes = [vp, i64, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+        L.rbd_rnea_jvp.argtypes = [vp, i64, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
         f32 = C.c_float
         L.rbd_diff_ik.argtypes = [vp, i64, i64, vp, C.c_int32, vp, f32, f32, vp, vp]
         L.rbd_osc.argtypes = [vp, i64, i64, vp, vp, C.c_int32, vp, f32, f32, f32, vp, vp]
@@ -140,7 +141,7 @@ def fma_rate(blocks: int = 256, ilp: int = 16, device: int = 0) -> float:
     return out.value
 
 
-N_KERNELS = 33
+N_KERNELS = 35
 
 
 def precompile_topology(parent, floating: bool, cache_dir: Optional[str] = None, kernel: int = -1) -> None:
@@ -352,6 +353,27 @@ def fwd_dyn_vjp(model: Model, q, qd, tau, g_qdd, want=(True, True, True), fext=N
     check(lib().rbd_fwd_dyn_vjp(model.handle, B, ld, qp, qdp, taup, fp, gp, ptrs[0], ptrs[1], ptrs[2], ptrs[3],
                                 _stream()))
     return tuple(outs) if want_fext else tuple(outs[:3])
+
+
+def rnea_jvp(model: Model, q, qd, qdd, dq, dqd, dqdd, fext=None, dfext=None):
+    """d tau [nv, B] of inverse dynamics along the tangent (dq [nq, B], dqd, dqdd [nv, B], and optionally dfext
+    [6 * n_bodies, B]), with external forces fext [6 * n_bodies, B] when given."""
+    ins = [_soa(x, r, n, None) for x, r, n in ((q, model.nq, "q"), (qd, model.nv, "qd"), (qdd, model.nv, "qdd"),
+                                               (dq, model.nq, "dq"), (dqd, model.nv, "dqd"),
+                                               (dqdd, model.nv, "dqdd"))]
+    nf = 6 * model.n_bodies
+    fx = [None if x is None else _soa(x, nf, n, None) for x, n in ((fext, "fext"), (dfext, "dfext"))]
+    B = ins[0][1]
+    if any(i[1] != B for i in ins + [f for f in fx if f is not None]):
+        raise ValueError("rnea_jvp: batch sizes differ")
+    ld = _same_ld(*[i[2] for i in ins + [f for f in fx if f is not None]])
+    if B > 0 and ld != B:
+        raise ValueError("rnea_jvp: inputs must be contiguous")
+    dtau = _out(model.nv, B, q)
+    p = [i[0] for i in ins]
+    check(lib().rbd_rnea_jvp(model.handle, B, ld, p[0], p[1], p[2], fx[0][0] if fx[0] else None, p[3], p[4], p[5],
+                             fx[1][0] if fx[1] else None, C.c_void_p(dtau.data_ptr()) if B else None, _stream()))
+    return dtau
 
 
 def fwd_dyn_jvp(model: Model, q, qd, tau, dq, dqd, dtau, want_qdd=False, fext=None, dfext=None):

@@ -159,6 +159,8 @@ def test_null_model_calls(rbd):
     assert b"model is NULL" in L.rbd_last_error()
     assert L.rbd_fwd_dyn_vjp(None, 1, 1, *([None] * 10)) == 1
     assert b"model is NULL" in L.rbd_last_error()
+    assert L.rbd_rnea_jvp(None, 1, 1, *([None] * 10)) == 1
+    assert b"model is NULL" in L.rbd_last_error()
 
 
 def _server_create(rbd, **kw):

@@ -148,6 +148,25 @@ def test_jvp_full_batch(rbd, name, B):
     assert vjp_err([cols(dqdd, idx)], [ref]) < 1e-3
 
 
+def test_rnea_jvp_full_batch(rbd):
+    """The tangent of the humanoid's inverse dynamics at 65536 with external forces: finite
+    everywhere, 256 states against central differences of the oracle."""
+    desc = W.humanoid()
+    m = rbd.Model(desc, 0)
+    B = 65536
+    st = W.states(desc, B, 114)
+    rng = np.random.Generator(np.random.PCG64(115))
+    qdd, dq, dqd, dqdd = (W._f32(rng.normal(size=x.shape)) for x in (st.qd, st.q, st.qd, st.qd))
+    fext = W._f32(rng.normal(0.0, 5.0, size=(B, desc.n_bodies * 6)))
+    df = W._f32(rng.normal(size=fext.shape))
+    dtau = rbd.rnea_jvp(m, *[gpu(x) for x in (st.q, st.qd, qdd, dq, dqd, dqdd)], fext=gpu(fext), dfext=gpu(df))
+    torch.cuda.synchronize()
+    assert torch.isfinite(dtau).all()
+    idx = np.linspace(0, B - 1, 256).astype(int)
+    ref = O.rnea_jvp_fd(desc, *[x[idx] for x in (st.q, st.qd, qdd, dq, dqd, dqdd)], fext=fext[idx], dfext=df[idx])
+    assert vjp_err([cols(dtau, idx)], [ref]) < 1e-3
+
+
 @pytest.mark.parametrize("B", [32768, 65536])
 def test_derivatives_with_external_forces_full_batch(rbd, B):
     """The adjoint and the tangent of the humanoid's forward dynamics under external forces at the

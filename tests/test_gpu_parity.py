@@ -196,6 +196,53 @@ def test_external_weight_support_on_gpu(rbd):
 
 
 @pytest.mark.parametrize("name", list(ALL))
+def test_rnea_jvp_parity(rbd, name):
+    """Tangent of inverse dynamics along (dq, dqd, dqdd) against the oracle's central differences."""
+    desc, m = model_of(rbd, name)
+    B = 256 + 17  # a ragged last block
+    st = draw(name, desc, B, 250)
+    rng = np.random.Generator(np.random.PCG64(251))
+    qdd = W._f32(rng.normal(size=st.qd.shape))
+    dq, dqd, dqdd = (W._f32(rng.normal(size=x.shape)) for x in (st.q, st.qd, st.qd))
+    dtau = host(rbd.rnea_jvp(m, gpu(st.q), gpu(st.qd), gpu(qdd), gpu(dq), gpu(dqd), gpu(dqdd)))
+    assert vjp_err([dtau], [O.rnea_jvp_fd(desc, st.q, st.qd, qdd, dq, dqd, dqdd)]) < TOL_VJP
+
+
+@pytest.mark.parametrize("name", ["chain7", "tree12f", "humanoid30", "humanoid30_rot"])
+def test_rnea_jvp_with_external_forces(rbd, name):
+    """The same with external forces and their tangent, and with the force tangent alone."""
+    desc, m = model_of(rbd, name)
+    B = 256
+    st = draw(name, desc, B, 252)
+    rng = np.random.Generator(np.random.PCG64(253))
+    qdd = W._f32(rng.normal(size=st.qd.shape))
+    dq, dqd, dqdd = (W._f32(rng.normal(size=x.shape)) for x in (st.q, st.qd, st.qd))
+    fext = W._f32(rng.normal(0.0, 5.0, size=(B, 6 * desc.n_bodies)))
+    dfext = W._f32(rng.normal(size=fext.shape))
+    args = [gpu(x) for x in (st.q, st.qd, qdd, dq, dqd, dqdd)]
+    dtau = host(rbd.rnea_jvp(m, *args, fext=gpu(fext), dfext=gpu(dfext)))
+    ref = O.rnea_jvp_fd(desc, st.q, st.qd, qdd, dq, dqd, dqdd, fext=fext, dfext=dfext)
+    assert vjp_err([dtau], [ref]) < TOL_VJP
+    z = [np.zeros_like(x) for x in (dq, dqd, dqdd)]
+    only_f = host(rbd.rnea_jvp(m, *args[:3], *[gpu(x) for x in z], dfext=gpu(dfext)))
+    assert vjp_err([only_f], [O.rnea_jvp_fd(desc, st.q, st.qd, qdd, *z, dfext=dfext)]) < TOL_VJP
+
+
+def test_rnea_jvp_inverts_fwd_dyn_jvp_on_gpu(rbd):
+    """ID(q, qd, FD(q, qd, tau)) = tau: the GPU's tangent of inverse dynamics at the GPU's tangent
+    of forward dynamics gives back dtau."""
+    desc, m = model_of(rbd, "humanoid30")
+    B = 512
+    st = W.states(desc, B, 254)
+    rng = np.random.Generator(np.random.PCG64(255))
+    dq, dqd, dtau = (W._f32(rng.normal(size=x.shape)) for x in (st.q, st.qd, st.tau))
+    q, qd = gpu(st.q), gpu(st.qd)
+    qdd, dqdd = rbd.fwd_dyn_jvp(m, q, qd, gpu(st.tau), gpu(dq), gpu(dqd), gpu(dtau), want_qdd=True)
+    back = host(rbd.rnea_jvp(m, q, qd, qdd, gpu(dq), gpu(dqd), dqdd))
+    assert vjp_err([back], [dtau]) < TOL_VJP
+
+
+@pytest.mark.parametrize("name", list(ALL))
 def test_fwd_dyn_jvp_parity(rbd, name):
     """Forward-mode derivative against the oracle's central differences along the same tangent."""
     desc, m = model_of(rbd, name)
