@@ -391,6 +391,30 @@ typedef struct {
 rbd_status rbd_diag_serve_load(rbd_server* s, int n_spec, const rbd_load_request* spec, int64_t n_requests,
                                double rate_per_s, int window, uint64_t seed, double* wall_s, int64_t* failed);
 
+/* ------------------------------------------------------------------ no allocation
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the packed
+ * launch of the serving runtime over requests whose arrays are already in
+ * device memory, instance-major FP32 ([batch][n]) with the inputs and outputs
+ * of rbd_server_submit for `op` (unused in/out slots are ignored). The
+ * descriptor table that the server keeps in memory it allocates is written,
+ * by a kernel on `stream`, into a static array of 196 624 bytes that each GPU
+ * holds until the process ends; the call allocates nothing and copies nothing
+ * from the host. Limits per call: 1024 requests and 32768 tiles of 64
+ * instances (sum over requests of ceil(batch / 64)), else RBD_E_INVAL. A
+ * model whose kernels are compiled at run time must have run `op` once
+ * through rbd_server_submit first (loading its code allocates), else
+ * RBD_E_INVAL. Asynchronous on `stream`; the table is rewritten by every call,
+ * so calls that overlap on one GPU (on different streams, or from several
+ * threads) race: serialise them. Results equal those of rbd_server_submit. */
+typedef struct {
+  const float* in[4];  /* device inputs, as for rbd_server_submit  */
+  float* out[3];       /* device outputs, as for rbd_server_submit */
+  int64_t batch;
+} rbd_packed_request;
+rbd_status rbd_packed_static(const rbd_model* model, int op, int n_req, const rbd_packed_request* reqs,
+                             hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -16,7 +16,7 @@ LIB = os.path.join(PKG, "librbd.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 HOST_SOURCES = ["rbd_api.cpp", "rbd_dispatch.cpp", "rbd_serve.cpp", "rbd_jit.cpp", "rbd_loadgen.cpp"]
-DEVICE_SOURCES = ["rbd_diag.hip"]
+DEVICE_SOURCES = ["rbd_diag.hip", "rbd_noalloc.hip"]
 TOPO_SOURCE = "rbd_kern_topo.hip"
 # Device headers the run-time compiler instantiates for a new topology; their
 # text is embedded in the library.

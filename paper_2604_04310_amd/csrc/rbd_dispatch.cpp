@@ -295,6 +295,13 @@ rbd_status prepare_packed(const rbd_model* m, int op) {
   return jit_function(ks, packed_id(op), &f);
 }
 
+bool packed_ready(const rbd_model* m, int op) {
+  const KernelSet* ks = m->ks;
+  if (!ks) return false;
+  if (!ks->is_jit) return ks->aot[packed_id(op)] != nullptr;
+  return ks->jit[packed_id(op)].load(std::memory_order_acquire) != nullptr;
+}
+
 rbd_status launch_packed(const rbd_model* m, int op, const void* d_table, int grid, hipStream_t s) {
   const KernelId id = packed_id(op);
   const float* tab = m->d_tab;

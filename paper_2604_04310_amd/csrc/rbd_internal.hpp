@@ -116,5 +116,8 @@ rbd_status launch_packed(const rbd_model* m, int op, const void* d_table, int gr
 // Loads the packed kernel of `op` (compiling it if the model's kernels are
 // compiled at run time), so that a later launch does nothing but launch.
 rbd_status prepare_packed(const rbd_model* m, int op);
+// Whether a launch of the packed kernel of `op` loads nothing first (a
+// topology compiled ahead of time, or a run-time one whose kernel is loaded).
+bool packed_ready(const rbd_model* m, int op);
 
 }  // namespace rbd

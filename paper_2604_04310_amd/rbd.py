@@ -31,7 +31,8 @@ OP_FWD_DYN, OP_RNEA, OP_FWD_DYN_VJP = 0, 1, 2
 EXPORTS = ["rbd_model_create", "rbd_model_destroy", "rbd_model_dims", "rbd_model_topology", "rbd_fk",
            "rbd_jacobian", "rbd_rnea", "rbd_crba", "rbd_fwd_dyn", "rbd_aba", "rbd_fwd_dyn_jvp", "rbd_rnea_jvp", "rbd_fwd_dyn_vjp", "rbd_diff_ik", "rbd_osc", "rbd_status_str",
            "rbd_last_error", "rbd_device_count", "rbd_diag_fma_rate", "rbd_diag_hbm_rate", "rbd_precompile_topology", "rbd_server_create", "rbd_server_submit", "rbd_server_wait", "rbd_server_cancel",
-           "rbd_server_get_stats", "rbd_server_reset_stats", "rbd_server_destroy", "rbd_diag_serve_load"]
+           "rbd_server_get_stats", "rbd_server_reset_stats", "rbd_server_destroy", "rbd_diag_serve_load",
+           "rbd_packed_static"]
 
 
 class RbdError(RuntimeError):
@@ -66,6 +67,10 @@ EXEC_DEVICE, EXEC_HOST = 0, 1
 
 class LoadRequestC(C.Structure):
     _fields_ = [("model", C.c_void_p), ("op", C.c_int), ("batch", C.c_int64), ("inp", C.c_void_p * 4)]
+
+
+class PackedRequestC(C.Structure):
+    _fields_ = [("inp", C.c_void_p * 4), ("out", C.c_void_p * 3), ("batch", C.c_int64)]
 
 
 class ServerStatsC(C.Structure):
@@ -121,6 +126,7 @@ def lib():
         L.rbd_server_destroy.argtypes = [vp]
         L.rbd_diag_serve_load.argtypes = [vp, C.c_int, P(LoadRequestC), i64, C.c_double, C.c_int, C.c_uint64,
                                           P(C.c_double), P(i64)]
+        L.rbd_packed_static.argtypes = [vp, C.c_int, C.c_int, P(PackedRequestC), vp]
         _lib = L
     return _lib
 
@@ -494,6 +500,29 @@ def op_shapes(model: Model, op: int):
     if op == OP_FWD_DYN_VJP:
         return [nq, nv, nv, nv], [nq, nv, nv]
     raise ValueError(f"unknown op {op}")
+
+
+def packed_static(model: Model, op: int, requests) -> None:
+    """rbd_packed_static on the current stream: `requests` is a list of (inputs, outputs), each a list of
+    contiguous CUDA float32 tensors [batch, rows] with the rows of op_shapes(model, op); the outputs are
+    written in place. Allocates no device memory."""
+    torch = _torch()
+    in_rows, out_rows = op_shapes(model, op)
+    arr = (PackedRequestC * max(1, len(requests)))()
+    for k, (ins, outs) in enumerate(requests):
+        if len(ins) != len(in_rows) or len(outs) != len(out_rows):
+            raise ValueError(f"request {k}: op {op} takes {len(in_rows)} inputs and {len(out_rows)} outputs")
+        batch = int(ins[0].shape[0])
+        for x, r in list(zip(ins, in_rows)) + list(zip(outs, out_rows)):
+            if (not isinstance(x, torch.Tensor) or not x.is_cuda or x.dtype != torch.float32
+                    or tuple(x.shape) != (batch, r) or not x.is_contiguous()):
+                raise ValueError(f"request {k}: expected contiguous CUDA float32 [{batch}, {r}] arrays")
+        for a, x in enumerate(ins):
+            arr[k].inp[a] = x.data_ptr() if batch else None
+        for a, x in enumerate(outs):
+            arr[k].out[a] = x.data_ptr() if batch else None
+        arr[k].batch = batch
+    check(lib().rbd_packed_static(model.handle, int(op), len(requests), arr, _stream()))
 
 
 class Server:
