@@ -139,7 +139,7 @@ const char* rbd_model_topology(const rbd_model* model);
  * time per process). Kernels already in the directory are kept. Needs no GPU.
  * Synchronous. Used to install a robot's kernels before its first use.
  * Errors: RBD_E_INVAL, RBD_E_COMPILE. */
-#define RBD_N_KERNELS 35
+#define RBD_N_KERNELS 36
 rbd_status rbd_precompile_topology(int32_t n_bodies, const int32_t* parent, int floating, const char* cache_dir,
                                    int32_t kernel);
 

@@ -222,7 +222,9 @@ rbd_status launch_rnea_jvp(const rbd_model* m, int64_t batch, int64_t ld, const 
   if (batch == 0) return RBD_OK;
   const float* tab = m->d_tab;
   void* a[] = {&tab, &batch, &ld, &q, &qd, &qdd, &dq, &dqd, &dqdd, &dtau, &fext, &dfext};
-  return launch(m, (fext || dfext) ? KID_RNEA_JVP_EXT : KID_RNEA_JVP, heavy_shape(batch), a, s, "rbd_rnea_jvp");
+  const bool ext = fext || dfext;
+  const KernelId id = ext ? KID_RNEA_JVP_EXT : (preload_inputs(large(m)) ? KID_RNEA_JVP_PRE : KID_RNEA_JVP);
+  return launch(m, id, heavy_shape(batch), a, s, "rbd_rnea_jvp");
 }
 
 // The controller kernel of `frame`: the set's own for the last body, else one

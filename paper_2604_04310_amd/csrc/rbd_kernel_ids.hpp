@@ -44,7 +44,8 @@
   X(KID_JVP_SPLIT, 6, k_fwd_dyn_jvp_split<TP>)            \
   X(KID_JVP_EXT_SPLIT, 8, k_fwd_dyn_jvp_split<TP, true>) \
   X(KID_RNEA_JVP, 6, k_rnea_jvp<TP>)                      \
-  X(KID_RNEA_JVP_EXT, 8, k_rnea_jvp<TP, true>)
+  X(KID_RNEA_JVP_EXT, 8, k_rnea_jvp<TP, true>)           \
+  X(KID_RNEA_JVP_PRE, 6, k_rnea_jvp<TP, false, true>)
 
 namespace rbd {
 

@@ -468,7 +468,9 @@ struct Neg {
   RBD_DI void operator()(int c, float v) const { o(c, -v); }
 };
 
-template <class TP, bool EXT = false>
+// PRE (no external forces): every input load is issued at entry, as in
+// k_fwd_dyn.
+template <class TP, bool EXT = false, bool PRE = false>
 __global__ __launch_bounds__(kBlock) void k_rnea_jvp(const float* __restrict__ tab, int64_t batch, int64_t ld,
                                                      const float* __restrict__ q, const float* __restrict__ qd,
                                                      const float* __restrict__ qdd, const float* __restrict__ dq,
@@ -482,8 +484,28 @@ __global__ __launch_bounds__(kBlock) void k_rnea_jvp(const float* __restrict__ t
     if constexpr (EXT) return FextOpt{{p, ld, b}};
     else return NoFext{};
   };
-  id_tangent_lane<TP>(tab, In{q, ld, b}, In{qd, ld, b}, In{qdd, ld, b}, In{dq, ld, b}, In{dqd, ld, b}, NoFext{},
-                      Neg<Out>{Out{dtau, ld, b}}, fx_view(fext), fx_view(dfext), On<In>{In{dqdd, ld, b}});
+  if constexpr (PRE && !EXT) {
+    constexpr int NQ = TP::NQ, NV = TP::NV;
+    float qv[NQ], qdv[NV], qddv[NV], dqv[NQ], dqdv[NV], dqddv[NV];
+    const In qi{q, ld, b}, qdi{qd, ld, b}, qddi{qdd, ld, b}, dqi{dq, ld, b}, dqdi{dqd, ld, b}, dqddi{dqdd, ld, b};
+    sfor<0, NQ>([&](auto K_) __attribute__((always_inline)) {
+      constexpr int K = decltype(K_)::value;
+      qv[K] = qi(K);
+      dqv[K] = dqi(K);
+    });
+    sfor<0, NV>([&](auto K_) __attribute__((always_inline)) {
+      constexpr int K = decltype(K_)::value;
+      qdv[K] = qdi(K);
+      qddv[K] = qddi(K);
+      dqdv[K] = dqdi(K);
+      dqddv[K] = dqddi(K);
+    });
+    id_tangent_lane<TP>(tab, RegView{qv}, RegView{qdv}, RegView{qddv}, RegView{dqv}, RegView{dqdv}, NoFext{},
+                        Neg<Out>{Out{dtau, ld, b}}, NoFext{}, NoFext{}, On<RegView>{RegView{dqddv}});
+  } else {
+    id_tangent_lane<TP>(tab, In{q, ld, b}, In{qd, ld, b}, In{qdd, ld, b}, In{dq, ld, b}, In{dqd, ld, b}, NoFext{},
+                        Neg<Out>{Out{dtau, ld, b}}, fx_view(fext), fx_view(dfext), On<In>{In{dqdd, ld, b}});
+  }
 }
 
 // ---- controller workloads for one frame E: the last body (a leaf) ahead of

@@ -147,7 +147,7 @@ def fma_rate(blocks: int = 256, ilp: int = 16, device: int = 0) -> float:
     return out.value
 
 
-N_KERNELS = 35
+N_KERNELS = 36
 
 
 def precompile_topology(parent, floating: bool, cache_dir: Optional[str] = None, kernel: int = -1) -> None:

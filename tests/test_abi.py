@@ -220,3 +220,25 @@ def test_registered_kernels_exist_in_device_code(rbd):
     device code of another would make its launches unresolvable)."""
     from paper_2604_04310_amd.build import check_kernel_names
     assert check_kernel_names(rbd.LIB_PATH) >= 11 * rbd.N_KERNELS
+
+
+def test_plain_c_program_uses_the_boundary(rbd, tmp_path):
+    """include/rbd.h compiles as C11 and librbd.so links and runs from a C program with no Python in
+    the loop: a host-only model (dimensions, a compute call refused without kernels, an invalid tree
+    rejected with a message) and a server with the host executor (submit, wait, statistics)."""
+    import shutil
+    import subprocess
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        pytest.skip("no C compiler")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    lib_dir = os.path.dirname(rbd.LIB_PATH)
+    rocm = os.environ.get("ROCM_PATH", "/opt/rocm")
+    exe = str(tmp_path / "c_abi_host")
+    subprocess.run([gcc, "-std=c11", "-Wall", "-Wextra", "-Werror", "-D__HIP_PLATFORM_AMD__",
+                    "-I" + os.path.join(root, "include"), "-I" + os.path.join(rocm, "include"),
+                    os.path.join(root, "tests", "c_abi_host.c"), "-o", exe, rbd.LIB_PATH,
+                    "-Wl,-rpath," + lib_dir], check=True, capture_output=True, timeout=120)
+    out = subprocess.run([exe], capture_output=True, text=True, timeout=60)
+    assert out.returncode == 0, out.stderr
+    assert out.stdout.strip() == "c abi ok"
