@@ -66,6 +66,7 @@ def lib():
         L.orc_fwd_dyn_vjp_fd.argtypes = [m, i64, d, d, d, d, d, d, d, d, d, C.c_double, C.c_int]
         L.orc_fwd_dyn_jvp_fd.argtypes = [m, i64, d, d, d, d, d, d, d, d, d, C.c_double, C.c_int]
         L.orc_rnea_jvp_fd.argtypes = [m, i64, d, d, d, d, d, d, d, d, d, C.c_double]
+        L.orc_rnea_vjp_fd.argtypes = [m, i64, d, d, d, d, d, d, d, d, d, C.c_double]
         L.orc_count_ops.argtypes = [m, C.c_int, P(C.c_longlong)]
         L.orc_max_threads.argtypes = []
         L.orc_set_threads.argtypes = [C.c_int]
@@ -215,6 +216,21 @@ def rnea_jvp_fd(desc, q, qd, qdd, dq, dqd, dqdd, h=1e-6, fext=None, dfext=None):
                                  None if fx is None else _dp(fx), _dp(dq), _dp(dqd), _dp(dqdd),
                                  None if dfx is None else _dp(dfx), _dp(dtau), h), "rnea jvp")
     return dtau
+
+
+def rnea_vjp_fd(desc, q, qd, qdd, lam, h=1e-6, fext=None, want_fext=False):
+    """Cotangents (g_q, g_qd, g_qdd[, g_fext]) = lam^T dID/d(q, qd, qdd[, F]) of inverse dynamics
+    tau = ID(q, qd, qdd, F), Eq. (1), by central differences of step h on every coordinate (with external
+    forces fext when given)."""
+    q, qd, qdd, lam = _c(q), _c(qd), _c(qdd), _c(lam)
+    B = q.shape[0]
+    fx = None if fext is None else _c(np.asarray(fext).reshape(B, -1))
+    gq, gqd, gqdd = np.empty_like(q), np.empty_like(qd), np.empty_like(qd)
+    gf = np.empty((B, 6 * desc.n_bodies)) if want_fext else None
+    _check(lib().orc_rnea_vjp_fd(C.byref(_model(desc)), B, _dp(q), _dp(qd), _dp(qdd),
+                                 None if fx is None else _dp(fx), _dp(lam), _dp(gq), _dp(gqd), _dp(gqdd),
+                                 None if gf is None else _dp(gf), h), "rnea vjp")
+    return (gq, gqd, gqdd, gf) if want_fext else (gq, gqd, gqdd)
 
 
 OPS = {"fk": 0, "jacobian": 1, "rnea": 2, "rnea_bias": 3, "crba": 4, "fwd_dyn_llt": 5, "fwd_dyn_ltl": 6, "aba": 7}

@@ -907,6 +907,48 @@ int orc_rnea_jvp_fd(const orc_model* d, int64_t B, const double* q, const double
   return 0;
 }
 
+// Vector-Jacobian product of inverse dynamics tau = ID(q, qd, qdd, F) with
+// cotangent lam: g_x = lam^T dID/dx for x = q, qd, qdd and F, by central
+// differences of step h on every coordinate (raw quaternion components and
+// every external-force component included). fext may be null (no forces); any
+// output may be null.
+int orc_rnea_vjp_fd(const orc_model* d, int64_t B, const double* q, const double* qd, const double* qdd,
+                    const double* fext, const double* lam, double* gq, double* gqd, double* gqdd, double* gfext,
+                    double h) {
+  Model M;
+  if (build_model(d, M)) return 1;
+  const int nq = M.nq, nv = M.nv, nf = 6 * M.n;
+  const bool ext = fext || gfext;
+#pragma omp parallel for schedule(static)
+  for (int64_t b = 0; b < B; ++b) {
+    std::vector<double> x(nq), y(nv), z(nv), f(nf, 0.0), tp(nv), tm(nv);
+    const double* l = lam + b * nv;
+    const double* F = ext ? f.data() : nullptr;
+    std::memcpy(x.data(), q + b * nq, nq * sizeof(double));
+    std::memcpy(y.data(), qd + b * nv, nv * sizeof(double));
+    std::memcpy(z.data(), qdd + b * nv, nv * sizeof(double));
+    if (fext) std::memcpy(f.data(), fext + b * nf, nf * sizeof(double));
+    auto diff = [&](double* v, int k) {
+      const double v0 = v[k];
+      v[k] = v0 + h; rnea(M, x.data(), y.data(), z.data(), tp.data(), F);
+      v[k] = v0 - h; rnea(M, x.data(), y.data(), z.data(), tm.data(), F);
+      v[k] = v0;
+      double s = 0.0;
+      for (int c = 0; c < nv; ++c) s += l[c] * (tp[c] - tm[c]);
+      return s / (2.0 * h);
+    };
+    if (gq)
+      for (int k = 0; k < nq; ++k) gq[b * nq + k] = diff(x.data(), k);
+    if (gqd)
+      for (int k = 0; k < nv; ++k) gqd[b * nv + k] = diff(y.data(), k);
+    if (gqdd)
+      for (int k = 0; k < nv; ++k) gqdd[b * nv + k] = diff(z.data(), k);
+    if (gfext)
+      for (int k = 0; k < nf; ++k) gfext[b * nf + k] = diff(f.data(), k);
+  }
+  return 0;
+}
+
 // Vector-Jacobian product of qdd = FD(q, qd, tau, F) with cotangent gbar, by
 // central differences of step h on every coordinate (raw quaternion
 // components and every external-force component included). fext may be null

@@ -667,6 +667,95 @@ def test_rnea_jvp_along_qdd_is_M(name):
     assert np.abs(got - ref).max() < 1e-7 * np.abs(ref).max()
 
 
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_rnea_vjp_single_pendulum(seed):
+    """The cotangents of one revolute joint's inverse dynamics tau = M qdd + dV/dq in closed form:
+    g_q = lam d2V/dq2, g_qd = 0 (no velocity dependence), g_qdd = M lam."""
+    d, rng = _single_body(seed)
+    a = d.axis[0] / np.linalg.norm(d.axis[0])
+    c, m = d.com[0], d.mass[0]
+    Ic = inertia_matrix(d, 0)
+    Rf = d.origin[0, :9].reshape(3, 3)
+    B = 16
+    q = rng.uniform(-np.pi, np.pi, size=(B, 1))
+    qd, qdd, lam = (rng.normal(size=(B, 1)) for _ in range(3))
+    M_ref = a @ Ic @ a + m * np.dot(np.cross(a, c), np.cross(a, c))
+    Rq = Rotation.from_rotvec(a[None, :] * q).as_matrix()
+    lever = np.einsum("bij,j->bi", Rq, c)
+    d2V = -m * np.einsum("i,ij,bj->b", d.gravity, Rf, np.cross(a[None, :], np.cross(a[None, :], lever)))
+    gq, gqd, gqdd = O.rnea_vjp_fd(d, q, qd, qdd, lam)
+    assert np.allclose(gq[:, 0], lam[:, 0] * d2V, rtol=1e-7, atol=1e-8)
+    assert np.abs(gqd).max() < 1e-8
+    assert np.allclose(gqdd[:, 0], M_ref * lam[:, 0], rtol=1e-7, atol=1e-8)
+
+
+@pytest.mark.parametrize("name", ["chain7", "humanoid30"])
+def test_rnea_vjp_qdd_block_is_M(name):
+    """Inverse dynamics is affine in qdd with slope M(q), which is symmetric: g_qdd = M lam."""
+    desc = W.chain(7) if name == "chain7" else W.humanoid()
+    st = W.states(desc, 6, 45)
+    rng = np.random.Generator(np.random.PCG64(46))
+    qdd, lam = rng.normal(size=st.qd.shape), rng.normal(size=st.qd.shape)
+    gqdd = O.rnea_vjp_fd(desc, st.q, st.qd, qdd, lam)[2]
+    ref = np.einsum("bij,bj->bi", O.crba(desc, st.q), lam)
+    assert np.abs(gqdd - ref).max() < 1e-7 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("name", ["chain7", "tree12f"])
+def test_rnea_vjp_force_cotangent_and_force_free_blocks(name):
+    """ID carries -sum_i J_i^T F_i (Eq. (1)), so g_F_i = -J_i lam exactly, J_i the Jacobian of body
+    i's twist at the world origin, [v_O; w] = [v_p + p x w; w]; with zero forces the other blocks are
+    the force-free ones."""
+    desc = W.chain(7) if name == "chain7" else W.random_tree([-1, 0, 1, 1, 0, 4, 5, 5, 7, 0, 9, 10], True, 34)
+    B = 6
+    st = W.states(desc, B, 67)
+    fext = _random_fext(desc, B, 68)
+    rng = np.random.Generator(np.random.PCG64(69))
+    qdd, lam = rng.normal(size=st.qd.shape), rng.normal(size=st.qd.shape)
+    gq, gqd, gqdd, gf = O.rnea_vjp_fd(desc, st.q, st.qd, qdd, lam, fext=fext, want_fext=True)
+    J = O.jacobian(desc, st.q)  # [B, n, 6, nv], rows [v; w] at the body origin p
+    p = O.fk(desc, st.q)[..., :, 3]
+    tw = np.einsum("bnrc,bc->bnr", J, lam)
+    ref = -np.concatenate([tw[..., :3] + np.cross(p, tw[..., 3:]), tw[..., 3:]], axis=2).reshape(B, -1)
+    assert rel_err(gf, ref) < 1e-7
+    g0 = O.rnea_vjp_fd(desc, st.q, st.qd, qdd, lam, fext=np.zeros_like(fext))
+    r0 = O.rnea_vjp_fd(desc, st.q, st.qd, qdd, lam)
+    assert all(rel_err(x, y) < 1e-12 for x, y in zip(g0, r0))
+
+
+@pytest.mark.parametrize("name", ["chain7", "humanoid30"])
+def test_rnea_vjp_is_dual_to_rnea_jvp(name):
+    """<lam, J dx> = <J^T lam, dx> for inverse dynamics, forces and force tangents included."""
+    desc = W.chain(7) if name == "chain7" else W.humanoid()
+    B = 6
+    st = W.states(desc, B, 70)
+    rng = np.random.Generator(np.random.PCG64(71))
+    fext = _random_fext(desc, B, 72)
+    qdd = rng.normal(size=st.qd.shape)
+    dq, dqd, dqdd = rng.normal(size=st.q.shape), rng.normal(size=st.qd.shape), rng.normal(size=st.qd.shape)
+    df = rng.normal(size=(B, 6 * desc.n_bodies))
+    lam = W.cotangent(desc.nv, B, 73)
+    jv = O.rnea_jvp_fd(desc, st.q, st.qd, qdd, dq, dqd, dqdd, fext=fext, dfext=df)
+    gq, gqd, gqdd, gf = O.rnea_vjp_fd(desc, st.q, st.qd, qdd, lam, fext=fext, want_fext=True)
+    lhs = np.einsum("bk,bk->b", lam, jv)
+    rhs = sum(np.einsum("bk,bk->b", g, x) for g, x in ((gq, dq), (gqd, dqd), (gqdd, dqdd), (gf, df)))
+    assert np.allclose(lhs, rhs, rtol=1e-6, atol=1e-6 * np.abs(rhs).max())
+
+
+def test_rnea_vjp_composes_with_fwd_dyn_vjp():
+    """Implicit differentiation of ID(q, qd, FD(q, qd, tau)) = tau: at qdd = FD(...) and lam =
+    M^-1 gbar, the fwd_dyn cotangents are (g_q, g_qd) = -(ID's g_q, g_qd) and g_tau = lam."""
+    desc = W.humanoid()
+    B = 4
+    st = W.states(desc, B, 74)
+    gbar = W.cotangent(desc.nv, B, 75)
+    qdd = O.fwd_dyn(desc, st.q, st.qd, st.tau)
+    lam = np.linalg.solve(O.crba(desc, st.q), gbar[..., None])[..., 0]
+    gq, gqd, _ = O.rnea_vjp_fd(desc, st.q, st.qd, qdd, lam)
+    fq, fqd, ftau = O.fwd_dyn_vjp_fd(desc, st.q, st.qd, st.tau, gbar)
+    assert rel_err(-gq, fq) < 1e-5 and rel_err(-gqd, fqd) < 1e-5 and rel_err(lam, ftau) < 1e-7
+
+
 @pytest.mark.parametrize("forces", [False, True])
 def test_rnea_jvp_inverts_fwd_dyn_jvp(forces):
     """ID(q, qd, FD(q, qd, tau, F), F) = tau, so along any (dq, dqd, dtau, dF) the tangent of
