@@ -109,6 +109,7 @@ def counters_driver():
                      for s, r in ((11, desc.nq), (12, desc.nv), (13, desc.nv)))
     step("fwd_dyn_jvp humanoid30 32768", lambda: rbd.fwd_dyn_jvp(m, vq, vqd, vtau, tq, tqd, ttau))
     step("rnea_jvp humanoid30 32768", lambda: rbd.rnea_jvp(m, vq, vqd, vtau, tq, tqd, ttau))
+    step("rnea_vjp humanoid30 32768", lambda: rbd.rnea_vjp(m, vq, vqd, vtau, gq))
     del q, qd, tau, out, vq, vqd, vtau, gq, tq, tqd, ttau
     torch.cuda.empty_cache()
     chain = W.chain(7)
@@ -192,6 +193,8 @@ def kernel_rooflines(O, W, desc, chain, ops, cnt, hbm):
                                               None, counter_batch=Bv),
         "rnea_jvp_humanoid30_b65536": valu("rnea_jvp_humanoid30", ops["rnea_jvp_humanoid30_b65536_us"], B, None,
                                            counter_batch=Bv),
+        "rnea_vjp_humanoid30_b65536": valu("rnea_vjp_humanoid30", ops["rnea_vjp_humanoid30_b65536_us"], B, None,
+                                           counter_batch=Bv),
         "osc_humanoid30": valu("osc_humanoid30", ops["osc_humanoid30_b65536_us"], B, None),
         "crba_humanoid30": mem("crba_humanoid30", ops["crba_humanoid30_b65536_us"], B, 4 * (desc.nq + nv * nv)),
         "fk_humanoid30": mem("fk_humanoid30", ops["fk_humanoid30_b65536_us"], B, 4 * (desc.nq + 12 * nb)),
@@ -228,7 +231,7 @@ def _kernel_key(short):
     key = {"k_fwd_dyn": "fwd_dyn", "k_rnea": "rnea_bias", "k_aba": "aba", "k_crba": "crba", "k_fk": "fk",
            "k_jacobian": "jacobian", "k_osc": "osc", "k_diff_ik": "diff_ik", "k_fwd_dyn_vjp": "fwd_dyn_vjp",
            "k_fwd_dyn_jvp": "fwd_dyn_jvp", "k_fwd_dyn_jvp_split": "fwd_dyn_jvp",
-           "k_rnea_jvp": "rnea_jvp"}.get(base)
+           "k_rnea_jvp": "rnea_jvp", "k_rnea_vjp": "rnea_vjp"}.get(base)
     return f"{key}_{topo}" if key and topo in ("humanoid30", "chain7") else None
 
 
@@ -679,6 +682,8 @@ def main():
     acc = soa(W._f32(np.random.default_rng(15).normal(size=(BATCH, desc.nv))), torch)
     ops["rnea_jvp_humanoid30_b65536_us"] = 1e3 * time_launches(
         lambda: rbd.rnea_jvp(model, q, qd, acc, tq, tqd, ttau), n_t, torch)
+    ops["rnea_vjp_humanoid30_b65536_us"] = 1e3 * time_launches(
+        lambda: rbd.rnea_vjp(model, q, qd, acc, g65), n_t, torch)
     del tq, tqd, ttau, g65, acc
     tg = soa(W._f32(targets(W, BATCH)), torch)
     ops["osc_humanoid30_b65536_us"] = 1e3 * time_launches(lambda: rbd.osc(model, q, qd, tg, 50.0, 10.0, 2.0), n_t, torch)

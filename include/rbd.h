@@ -18,6 +18,7 @@
  *                    Featherstone's algorithms; Sec. VI-A, future work)
  *   rbd_fwd_dyn_jvp  forward-mode derivative of rbd_fwd_dyn (Sec. IV-A, Fig. 2)
  *   rbd_rnea_jvp     forward-mode derivative of rbd_rnea (Sec. IV-A, Fig. 2)
+ *   rbd_rnea_vjp     reverse-mode derivative of rbd_rnea (Sec. I, AD)
  *   rbd_diff_ik      differential IK for an end effector (Sec. IV, Table II)
  *   rbd_osc          operational-space control torques (Sec. IV, Table II)
  *   rbd_fwd_dyn_vjp  reverse-mode derivative of rbd_fwd_dyn (Sec. I, AD)
@@ -139,7 +140,7 @@ const char* rbd_model_topology(const rbd_model* model);
  * time per process). Kernels already in the directory are kept. Needs no GPU.
  * Synchronous. Used to install a robot's kernels before its first use.
  * Errors: RBD_E_INVAL, RBD_E_COMPILE. */
-#define RBD_N_KERNELS 36
+#define RBD_N_KERNELS 38
 rbd_status rbd_precompile_topology(int32_t n_bodies, const int32_t* parent, int floating, const char* cache_dir,
                                    int32_t kernel);
 
@@ -221,6 +222,20 @@ rbd_status rbd_fwd_dyn_jvp(const rbd_model* model, int64_t batch, int64_t ld, co
 rbd_status rbd_rnea_jvp(const rbd_model* model, int64_t batch, int64_t ld, const float* q, const float* qd,
                         const float* qdd, const float* f_ext, const float* dq, const float* dqd, const float* dqdd,
                         const float* df_ext, float* dtau, hipStream_t stream);
+
+/* Vector-Jacobian product of rbd_rnea (reverse-mode AD of Eq. (1)) for the
+ * cotangent lam [nv][ld], at (q, qd, qdd) with external forces f_ext
+ * (nullable: none; layout as for rbd_rnea): g_q = lam^T dID/dq [nq][ld] (raw
+ * quaternion components included), g_qd = lam^T dID/dqd [nv][ld], g_qdd =
+ * lam^T dID/dqdd = M lam [nv][ld], and g_f_ext = lam^T dID/dF = -J_i lam
+ * [n_bodies*6][ld] (layout of f_ext: [v_O; w] of body i's twist under joint
+ * rates lam, in world axes at the world origin, negated). Every output is
+ * nullable (not computed); with none the call does nothing. One sweep of the
+ * adjoint of inverse dynamics. Outputs must not overlap an input or each
+ * other (RBD_E_INVAL). */
+rbd_status rbd_rnea_vjp(const rbd_model* model, int64_t batch, int64_t ld, const float* q, const float* qd,
+                        const float* qdd, const float* f_ext, const float* lam, float* g_q, float* g_qd, float* g_qdd,
+                        float* g_f_ext, hipStream_t stream);
 
 /* Vector-Jacobian product of rbd_fwd_dyn with external forces f_ext
  * (nullable: none; layout as for rbd_rnea), for the cotangent g_qdd [nv][ld]:

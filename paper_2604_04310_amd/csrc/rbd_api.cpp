@@ -475,6 +475,26 @@ rbd_status rbd_rnea_jvp(const rbd_model* m, int64_t batch, int64_t ld, const flo
   return launch_rnea_jvp(m, batch, ld, q, qd, qdd, f_ext, dq, dqd, dqdd, df_ext, dtau, s);
 }
 
+rbd_status rbd_rnea_vjp(const rbd_model* m, int64_t batch, int64_t ld, const float* q, const float* qd,
+                        const float* qdd, const float* f_ext, const float* lam, float* g_q, float* g_qd, float* g_qdd,
+                        float* g_f_ext, hipStream_t s) {
+  rbd_status st = check_batch(m, batch, ld, "rbd_rnea_vjp");
+  if (st != RBD_OK) return st;
+  if (batch > 0 && (!q || !qd || !qdd || !lam)) return fail(RBD_E_INVAL, "rbd_rnea_vjp: NULL input array");
+  const int64_t nf = 6 * (int64_t)m->n;
+  const Arr outs[4] = {{g_q, m->nq}, {g_qd, m->nv}, {g_qdd, m->nv}, {g_f_ext, nf}};
+  for (int i = 0; i < 4; ++i)
+    for (int j = i + 1; j < 4; ++j)
+      if (soa_overlap(outs[i].p, outs[i].rows, outs[j].p, outs[j].rows, ld, batch))
+        return fail(RBD_E_INVAL, "rbd_rnea_vjp: output arrays overlap");
+  for (const Arr& o : outs)
+    if (output_overlaps(o.p, o.rows, {{q, m->nq}, {qd, m->nv}, {qdd, m->nv}, {f_ext, nf}, {lam, m->nv}}, ld, batch))
+      return fail(RBD_E_INVAL, "rbd_rnea_vjp: an output overlaps an input");
+  DeviceScope ds(m->device);
+  if (ds.st != RBD_OK) return ds.st;
+  return launch_rnea_vjp(m, batch, ld, q, qd, qdd, f_ext, lam, g_q, g_qd, g_qdd, g_f_ext, s);
+}
+
 // A controller frame is any body (the last one has ahead-of-time kernels).
 static rbd_status check_frame(const rbd_model* m, int32_t frame, const char* fn) {
   if (frame < 0 || frame >= m->n) return fail(RBD_E_INVAL, "%s: frame %d is not a body id (0..%d)", fn, frame, m->n - 1);

@@ -227,6 +227,17 @@ rbd_status launch_rnea_jvp(const rbd_model* m, int64_t batch, int64_t ld, const 
   return launch(m, id, heavy_shape(batch), a, s, "rbd_rnea_jvp");
 }
 
+rbd_status launch_rnea_vjp(const rbd_model* m, int64_t batch, int64_t ld, const float* q, const float* qd,
+                           const float* qdd, const float* fext, const float* lam, float* gq, float* gqd, float* gqdd,
+                           float* gfext, hipStream_t s) {
+  if (batch == 0 || (!gq && !gqd && !gqdd && !gfext)) return RBD_OK;
+  // external forces matter to g_q and the force cotangent only
+  const bool ext = gfext || (fext && gq);
+  const float* tab = m->d_tab;
+  void* a[] = {&tab, &batch, &ld, &q, &qd, &qdd, &lam, &gq, &gqd, &gqdd, &fext, &gfext};
+  return launch(m, ext ? KID_RNEA_VJP_EXT : KID_RNEA_VJP, heavy_shape(batch), a, s, "rbd_rnea_vjp");
+}
+
 // The controller kernel of `frame`: the set's own for the last body, else one
 // compiled for that frame at run time on first use.
 static rbd_status launch_frame(const rbd_model* m, bool osc, int frame, Shape sh, void** args, hipStream_t s,

@@ -97,6 +97,9 @@ rbd_status launch_aba(const rbd_model* m, int64_t batch, int64_t ld, const float
 rbd_status launch_rnea_jvp(const rbd_model* m, int64_t batch, int64_t ld, const float* q, const float* qd,
                            const float* qdd, const float* fext, const float* dq, const float* dqd, const float* dqdd,
                            const float* dfext, float* dtau, hipStream_t s);
+rbd_status launch_rnea_vjp(const rbd_model* m, int64_t batch, int64_t ld, const float* q, const float* qd,
+                           const float* qdd, const float* fext, const float* lam, float* gq, float* gqd, float* gqdd,
+                           float* gfext, hipStream_t s);
 rbd_status launch_fwd_dyn_jvp(const rbd_model* m, int64_t batch, int64_t ld, const float* q, const float* qd,
                               const float* tau, const float* fext, const float* dq, const float* dqd,
                               const float* dtau, const float* dfext, float* qdd, float* dqdd, hipStream_t s);

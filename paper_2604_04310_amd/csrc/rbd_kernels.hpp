@@ -463,8 +463,9 @@ struct On : V {  // a view whose entries are used (kOn)
   static constexpr bool kOn = true;
 };
 template <class O>
-struct Neg {
+struct Neg {  // an output written negated
   O o;
+  static constexpr bool kOn = true;
   RBD_DI void operator()(int c, float v) const { o(c, -v); }
 };
 
@@ -506,6 +507,33 @@ __global__ __launch_bounds__(kBlock) void k_rnea_jvp(const float* __restrict__ t
     id_tangent_lane<TP>(tab, In{q, ld, b}, In{qd, ld, b}, In{qdd, ld, b}, In{dq, ld, b}, In{dqd, ld, b}, NoFext{},
                         Neg<Out>{Out{dtau, ld, b}}, fx_view(fext), fx_view(dfext), On<In>{In{dqdd, ld, b}});
   }
+}
+
+// ---- adjoint of inverse dynamics, Eq. (1), for the cotangent lam: one sweep
+// of id_adjoint_lane at the given qdd. That sweep writes the cotangents of
+// forward dynamics, -lam^T dID/d(q, qd) and J_i lam, which are stored negated
+// (exact), and g_qdd = M lam. Every output may be absent (null).
+template <class TP, bool EXT = false>
+__global__ __launch_bounds__(kBlock) void k_rnea_vjp(const float* __restrict__ tab, int64_t batch, int64_t ld,
+                                                     const float* __restrict__ q, const float* __restrict__ qd,
+                                                     const float* __restrict__ qdd, const float* __restrict__ lam,
+                                                     float* __restrict__ gq, float* __restrict__ gqd,
+                                                     float* __restrict__ gqdd, const float* __restrict__ fext,
+                                                     float* __restrict__ gfext) {
+  RBD_LANE_IO(TP);
+  const uint32_t b = lane_id();
+  if (b >= batch) return;
+  auto opt = [&](float* p) __attribute__((always_inline)) { return OutOpt<Out>{Out{p, ld, b}, p != nullptr}; };
+  auto fx_view = [&]() __attribute__((always_inline)) {
+    if constexpr (EXT) return FextOpt{{fext, ld, b}};
+    else return NoFext{};
+  };
+  auto gf_view = [&]() __attribute__((always_inline)) {
+    if constexpr (EXT) return Neg<GFOut>{GFOut{{gfext, ld, b}}};
+    else return NoGF{};
+  };
+  id_adjoint_lane<TP>(tab, In{q, ld, b}, In{qd, ld, b}, In{qdd, ld, b}, In{lam, ld, b}, Neg<OutOpt<Out>>{opt(gq)},
+                      Neg<OutOpt<Out>>{opt(gqd)}, fx_view(), gf_view(), On<OutOpt<Out>>{opt(gqdd)});
 }
 
 // ---- controller workloads for one frame E: the last body (a leaf) ahead of

@@ -1172,9 +1172,13 @@ RBD_DI void id_tangent_lane(const float* __restrict__ t, const QI& q, const QDI&
 // gets R Wsub_0.f and the quaternion Wsub_0.n . dtheta/dquat. (ID_0, the
 // dynamics without forces, is differentiated as above with forces excluded.)
 // The force cotangent g_F_i = J_i lam is mu_i in world axes at the world origin.
-template <class TP, class QI, class QDI, class QDD, class LAM, class GQ, class GQD, class FX = NoFext, class GF = NoGF>
+// With GQDD (kOn), S^T abar = M lam is written too: abar is the composite
+// force of the accelerations mu (no velocity, no gravity).
+template <class TP, class QI, class QDI, class QDD, class LAM, class GQ, class GQD, class FX = NoFext, class GF = NoGF,
+          class GQDD = NoGF>
 RBD_DI void id_adjoint_lane(const float* __restrict__ t, const QI& q, const QDI& qd, const QDD& qdd, const LAM& lam,
-                            const GQ& gq, const GQD& gqd, const FX& fx = FX{}, const GF& gf = GF{}) {
+                            const GQ& gq, const GQD& gqd, const FX& fx = FX{}, const GF& gf = GF{},
+                            const GQDD& gqdd = GQDD{}) {
   constexpr int N = TP::N;
   constexpr bool kExt = FX::kOn, kW = FX::kOn || GF::kOn;
   constexpr int NE = kExt ? N : 1, NW = kW ? N : 1;
@@ -1197,6 +1201,14 @@ RBD_DI void id_adjoint_lane(const float* __restrict__ t, const QI& q, const QDI&
     const Inr Ib = load_inr<J>(t);
     const Frc abar = imul(Ib, mu[J]) + ab[J];
     Frc vbar = imul(Ib, crm(mu[J], v[J])) - crf(mu[J], imul(Ib, v[J])) + vb[J];
+    if constexpr (GQDD::kOn) {
+      if constexpr (TP::free_body(J)) {
+        gqdd(0, abar.f.x); gqdd(1, abar.f.y); gqdd(2, abar.f.z);
+        gqdd(3, abar.n.x); gqdd(4, abar.n.y); gqdd(5, abar.n.z);
+      } else {
+        gqdd(cidx<TP::vofs(J)>, abar.n.z);
+      }
+    }
     if constexpr (TP::free_body(J)) {
       gqd(0, -vbar.f.x); gqd(1, -vbar.f.y); gqd(2, -vbar.f.z);
       gqd(3, -vbar.n.x); gqd(4, -vbar.n.y); gqd(5, -vbar.n.z);

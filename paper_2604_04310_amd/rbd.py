@@ -29,7 +29,7 @@ OP_FWD_DYN, OP_RNEA, OP_FWD_DYN_VJP = 0, 1, 2
 
 # Every symbol include/rbd.h declares.
 EXPORTS = ["rbd_model_create", "rbd_model_destroy", "rbd_model_dims", "rbd_model_topology", "rbd_fk",
-           "rbd_jacobian", "rbd_rnea", "rbd_crba", "rbd_fwd_dyn", "rbd_aba", "rbd_fwd_dyn_jvp", "rbd_rnea_jvp", "rbd_fwd_dyn_vjp", "rbd_diff_ik", "rbd_osc", "rbd_status_str",
+           "rbd_jacobian", "rbd_rnea", "rbd_crba", "rbd_fwd_dyn", "rbd_aba", "rbd_fwd_dyn_jvp", "rbd_rnea_jvp", "rbd_rnea_vjp", "rbd_fwd_dyn_vjp", "rbd_diff_ik", "rbd_osc", "rbd_status_str",
            "rbd_last_error", "rbd_device_count", "rbd_diag_fma_rate", "rbd_diag_hbm_rate", "rbd_precompile_topology", "rbd_server_create", "rbd_server_submit", "rbd_server_wait", "rbd_server_cancel",
            "rbd_server_get_stats", "rbd_server_reset_stats", "rbd_server_destroy", "rbd_diag_serve_load",
            "rbd_packed_static"]
@@ -106,6 +106,7 @@ def lib():
         L.rbd_fwd_dyn_vjp.argtypes = [vp, i64, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
         L.rbd_fwd_dyn_jvp.argtypes = [vp, i64, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
         L.rbd_rnea_jvp.argtypes = [vp, i64, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+        L.rbd_rnea_vjp.argtypes = [vp, i64, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
         f32 = C.c_float
         L.rbd_diff_ik.argtypes = [vp, i64, i64, vp, C.c_int32, vp, f32, f32, vp, vp]
         L.rbd_osc.argtypes = [vp, i64, i64, vp, vp, C.c_int32, vp, f32, f32, f32, vp, vp]
@@ -147,7 +148,7 @@ def fma_rate(blocks: int = 256, ilp: int = 16, device: int = 0) -> float:
     return out.value
 
 
-N_KERNELS = 36
+N_KERNELS = 38
 
 
 def precompile_topology(parent, floating: bool, cache_dir: Optional[str] = None, kernel: int = -1) -> None:
@@ -361,6 +362,28 @@ def fwd_dyn_vjp(model: Model, q, qd, tau, g_qdd, want=(True, True, True), fext=N
     return tuple(outs) if want_fext else tuple(outs[:3])
 
 
+def rnea_vjp(model: Model, q, qd, qdd, lam, want=(True, True, True), fext=None, want_fext=False):
+    """(g_q [nq, B], g_qd [nv, B], g_qdd [nv, B]) = lam^T dID/d(q, qd, qdd) of inverse dynamics (g_qdd = M lam);
+    None where not wanted. fext: optional [6 * n_bodies, B] external forces; want_fext adds g_fext
+    [6 * n_bodies, B] = -J_i lam (returned fourth)."""
+    ins = [_soa(x, r, n, None) for x, r, n in ((q, model.nq, "q"), (qd, model.nv, "qd"), (qdd, model.nv, "qdd"),
+                                               (lam, model.nv, "lam"))]
+    nf = 6 * model.n_bodies
+    fx = None if fext is None else _soa(fext, nf, "fext", None)
+    B = ins[0][1]
+    if any(i[1] != B for i in ins + ([fx] if fx else [])):
+        raise ValueError("rnea_vjp: batch sizes differ")
+    ld = _same_ld(*[i[2] for i in ins + ([fx] if fx else [])])
+    if B > 0 and ld != B:
+        raise ValueError("rnea_vjp: inputs must be contiguous")
+    outs = [_out(model.nq, B, q) if want[0] else None, _out(model.nv, B, q) if want[1] else None,
+            _out(model.nv, B, q) if want[2] else None, _out(nf, B, q) if want_fext else None]
+    ptrs = [C.c_void_p(o.data_ptr()) if (o is not None and B) else None for o in outs]
+    p = [i[0] for i in ins]
+    check(lib().rbd_rnea_vjp(model.handle, B, ld, p[0], p[1], p[2], fx[0] if fx else None, p[3], *ptrs, _stream()))
+    return tuple(outs) if want_fext else tuple(outs[:3])
+
+
 def rnea_jvp(model: Model, q, qd, qdd, dq, dqd, dqdd, fext=None, dfext=None):
     """d tau [nv, B] of inverse dynamics along the tangent (dq [nq, B], dqd, dqdd [nv, B], and optionally dfext
     [6 * n_bodies, B]), with external forces fext [6 * n_bodies, B] when given."""
@@ -479,6 +502,59 @@ def _make_autograd():
 
 
 _FwdDyn = None
+_InvDyn = None
+
+
+def _make_rnea_autograd():
+    torch = _torch()
+
+    class InvDyn(torch.autograd.Function):
+        """tau = ID(q, qd, qdd[, fext]) with the adjoint kernel (rbd_rnea_vjp) as backward and the
+        tangent kernel (rbd_rnea_jvp) as the forward-mode rule. Inputs must be contiguous [rows, B]
+        tensors; fext may be None."""
+
+        @staticmethod
+        def forward(model, q, qd, qdd, fext):
+            return rnea(model, q, qd, qdd, fext=fext)
+
+        @staticmethod
+        def setup_context(ctx, inputs, output):
+            model, q, qd, qdd, fext = inputs
+            ctx.model = model
+            ctx.has_fext = fext is not None
+            saved = (q, qd, qdd) + ((fext,) if fext is not None else ())
+            ctx.save_for_backward(*saved)
+            ctx.save_for_forward(*saved)
+
+        @staticmethod
+        def backward(ctx, g):
+            q, qd, qdd, *rest = ctx.saved_tensors
+            fext = rest[0] if ctx.has_fext else None
+            want = tuple(bool(w) for w in ctx.needs_input_grad[1:4])
+            want_f = ctx.has_fext and ctx.needs_input_grad[4]
+            outs = rnea_vjp(ctx.model, q, qd, qdd, g.contiguous(), want=want, fext=fext, want_fext=want_f)
+            return None, outs[0], outs[1], outs[2], outs[3] if want_f else None
+
+        @staticmethod
+        def jvp(ctx, _model_t, q_t, qd_t, qdd_t, f_t):
+            q, qd, qdd, *rest = ctx.saved_tensors
+            fext = rest[0] if ctx.has_fext else None
+            tangents = [torch.zeros_like(x) if t is None else t.contiguous()
+                        for x, t in ((q, q_t), (qd, qd_t), (qdd, qdd_t))]
+            df = f_t.contiguous() if (ctx.has_fext and f_t is not None) else None
+            return rnea_jvp(ctx.model, q, qd, qdd, *tangents, fext=fext, dfext=df)
+
+    return InvDyn
+
+
+def rnea_autograd(model: Model, q, qd, qdd, fext=None):
+    """Differentiable inverse dynamics: backward runs rbd_rnea_vjp, forward-mode AD rbd_rnea_jvp; fext
+    (optional [6 * n_bodies, B] external forces) is differentiable too."""
+    global _InvDyn
+    if _InvDyn is None:
+        _InvDyn = _make_rnea_autograd()
+    return _InvDyn.apply(model, q.contiguous(), qd.contiguous(), qdd.contiguous(),
+                         None if fext is None else fext.contiguous())
 
 
 def fwd_dyn_autograd(model: Model, q, qd, tau, fext=None):

@@ -161,6 +161,8 @@ def test_null_model_calls(rbd):
     assert b"model is NULL" in L.rbd_last_error()
     assert L.rbd_rnea_jvp(None, 1, 1, *([None] * 10)) == 1
     assert b"model is NULL" in L.rbd_last_error()
+    assert L.rbd_rnea_vjp(None, 1, 1, *([None] * 10)) == 1
+    assert b"model is NULL" in L.rbd_last_error()
     assert L.rbd_packed_static(None, 0, 1, None, None) == 1
     assert b"model is NULL" in L.rbd_last_error()
 

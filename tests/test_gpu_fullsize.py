@@ -167,6 +167,25 @@ def test_rnea_jvp_full_batch(rbd):
     assert vjp_err([cols(dtau, idx)], [ref]) < 1e-3
 
 
+def test_rnea_vjp_full_batch(rbd):
+    """The adjoint of the humanoid's inverse dynamics at 65536 with external forces: finite
+    everywhere, 256 states against central differences of the oracle."""
+    desc = W.humanoid()
+    m = rbd.Model(desc, 0)
+    B = 65536
+    st = W.states(desc, B, 116)
+    rng = np.random.Generator(np.random.PCG64(117))
+    qdd = W._f32(rng.normal(size=st.qd.shape))
+    fext = W._f32(rng.normal(0.0, 5.0, size=(B, desc.n_bodies * 6)))
+    lam = W.cotangent(desc.nv, B, 118)
+    outs = rbd.rnea_vjp(m, *[gpu(x) for x in (st.q, st.qd, qdd, lam)], fext=gpu(fext), want_fext=True)
+    torch.cuda.synchronize()
+    assert all(torch.isfinite(o).all() for o in outs)
+    idx = np.linspace(0, B - 1, 256).astype(int)
+    ref = O.rnea_vjp_fd(desc, st.q[idx], st.qd[idx], qdd[idx], lam[idx], fext=fext[idx], want_fext=True)
+    assert vjp_err([cols(o, idx) for o in outs], list(ref)) < 1e-3
+
+
 @pytest.mark.parametrize("B", [32768, 65536])
 def test_derivatives_with_external_forces_full_batch(rbd, B):
     """The adjoint and the tangent of the humanoid's forward dynamics under external forces at the

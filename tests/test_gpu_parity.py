@@ -228,6 +228,89 @@ def test_rnea_jvp_with_external_forces(rbd, name):
     assert vjp_err([only_f], [O.rnea_jvp_fd(desc, st.q, st.qd, qdd, *z, dfext=dfext)]) < TOL_VJP
 
 
+@pytest.mark.parametrize("name", list(ALL))
+def test_rnea_vjp_parity(rbd, name):
+    """Adjoint of inverse dynamics (g_q, g_qd, g_qdd) against the oracle's central differences."""
+    desc, m = model_of(rbd, name)
+    B = 256 + 17  # a ragged last block
+    st = draw(name, desc, B, 256)
+    rng = np.random.Generator(np.random.PCG64(257))
+    qdd = W._f32(rng.normal(size=st.qd.shape))
+    lam = W.cotangent(desc.nv, B, 258)
+    outs = rbd.rnea_vjp(m, gpu(st.q), gpu(st.qd), gpu(qdd), gpu(lam))
+    assert vjp_err([host(o) for o in outs], list(O.rnea_vjp_fd(desc, st.q, st.qd, qdd, lam))) < TOL_VJP
+
+
+@pytest.mark.parametrize("name", ["chain7", "tree12f", "humanoid30", "humanoid30_rot"])
+def test_rnea_vjp_with_external_forces(rbd, name):
+    """With external forces and the force cotangent; every output subset equals the full call's."""
+    desc, m = model_of(rbd, name)
+    B = 256
+    st = draw(name, desc, B, 259)
+    rng = np.random.Generator(np.random.PCG64(260))
+    qdd = W._f32(rng.normal(size=st.qd.shape))
+    fext = W._f32(rng.normal(0.0, 5.0, size=(B, 6 * desc.n_bodies)))
+    lam = W.cotangent(desc.nv, B, 261)
+    args = [gpu(x) for x in (st.q, st.qd, qdd, lam)]
+    full = [host(o) for o in rbd.rnea_vjp(m, *args, fext=gpu(fext), want_fext=True)]
+    ref = O.rnea_vjp_fd(desc, st.q, st.qd, qdd, lam, fext=fext, want_fext=True)
+    assert vjp_err(full, list(ref)) < TOL_VJP
+    for k in range(3):
+        want = tuple(i == k for i in range(3))
+        part = rbd.rnea_vjp(m, *args, want=want, fext=gpu(fext))
+        assert all((p is None) == (not w) for p, w in zip(part, want))
+        got = host(part[k])
+        assert np.abs(got - full[k]).max() <= 1e-6 * max(np.abs(full[k]).max(), 1e-30)
+
+
+def test_rnea_vjp_on_gpu_is_dual_to_rnea_jvp_and_its_qdd_block_is_M(rbd):
+    """<lam, J dx> = <J^T lam, dx> between the two GPU kernels (forces and force tangents included),
+    and g_qdd = M lam with M from the GPU's CRBA."""
+    desc, m = model_of(rbd, "humanoid30_rot")
+    B = 512
+    st = draw("humanoid30_rot", desc, B, 262)
+    rng = np.random.Generator(np.random.PCG64(263))
+    qdd = W._f32(rng.normal(size=st.qd.shape))
+    fext = W._f32(rng.normal(0.0, 5.0, size=(B, 6 * desc.n_bodies)))
+    dq, dqd, dqdd, df = (W._f32(rng.normal(size=x.shape)) for x in (st.q, st.qd, st.qd, fext))
+    lam = W.cotangent(desc.nv, B, 264)
+    q, qd, a, fx = gpu(st.q), gpu(st.qd), gpu(qdd), gpu(fext)
+    jv = host(rbd.rnea_jvp(m, q, qd, a, gpu(dq), gpu(dqd), gpu(dqdd), fext=fx, dfext=gpu(df)))
+    g = [host(o) for o in rbd.rnea_vjp(m, q, qd, a, gpu(lam), fext=fx, want_fext=True)]
+    terms_l = lam * jv
+    terms_r = [gk * xk for gk, xk in zip(g, (dq, dqd, dqdd, df))]
+    lhs, rhs = terms_l.sum(1), sum(t.sum(1) for t in terms_r)
+    scale = np.abs(terms_l).sum(1) + sum(np.abs(t).sum(1) for t in terms_r)
+    assert (np.abs(lhs - rhs) / scale).max() < 1e-4
+    M = host(rbd.crba(m, q)).reshape(B, desc.nv, desc.nv)
+    Ml = np.einsum("bij,bj->bi", M, lam)
+    assert (np.abs(g[2] - Ml).max(1) / np.abs(Ml).max(1)).max() < 1e-5
+
+
+def test_rnea_autograd(rbd):
+    """Backward through rnea_autograd runs the adjoint kernel (forces included); forward-mode AD runs
+    the tangent kernel."""
+    from torch.autograd import forward_ad as fwAD
+    desc, m = model_of(rbd, "tree12f_rot")
+    B = 64
+    st = draw("tree12f_rot", desc, B, 265)
+    rng = np.random.Generator(np.random.PCG64(266))
+    qdd = W._f32(rng.normal(size=st.qd.shape))
+    fext = W._f32(rng.normal(0.0, 5.0, size=(B, desc.n_bodies * 6)))
+    lam = W.cotangent(desc.nv, B, 267)
+    xs = [gpu(x).requires_grad_(True) for x in (st.q, st.qd, qdd, fext)]
+    tau = rbd.rnea_autograd(m, *xs[:3], fext=xs[3])
+    (tau * gpu(lam)).sum().backward()
+    ref = O.rnea_vjp_fd(desc, st.q, st.qd, qdd, lam, fext=fext, want_fext=True)
+    assert vjp_err([host(x.grad) for x in xs], list(ref)) < TOL_VJP
+    dq, dqd, dqdd = (W._f32(rng.normal(size=x.shape)) for x in (st.q, st.qd, st.qd))
+    with fwAD.dual_level():
+        out = rbd.rnea_autograd(m, fwAD.make_dual(gpu(st.q), gpu(dq)), fwAD.make_dual(gpu(st.qd), gpu(dqd)),
+                                fwAD.make_dual(gpu(qdd), gpu(dqdd)), fext=gpu(fext))
+        t = fwAD.unpack_dual(out).tangent
+    assert vjp_err([host(t)], [O.rnea_jvp_fd(desc, st.q, st.qd, qdd, dq, dqd, dqdd, fext=fext)]) < TOL_VJP
+
+
 def test_rnea_jvp_inverts_fwd_dyn_jvp_on_gpu(rbd):
     """ID(q, qd, FD(q, qd, tau)) = tau: the GPU's tangent of inverse dynamics at the GPU's tangent
     of forward dynamics gives back dtau. That dtau is the sum of the state part (dq, dqd) and the
