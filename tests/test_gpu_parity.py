@@ -491,6 +491,8 @@ def test_batch_edges(rbd, B):
         z = torch.zeros((desc.nq, 0), dtype=torch.float32, device="cuda")
         zv = torch.zeros((desc.nv, 0), dtype=torch.float32, device="cuda")
         assert rbd.fwd_dyn(m, z, zv, zv).shape == (desc.nv, 0)
+        assert rbd.rnea_jvp(m, z, zv, zv, z, zv, zv).shape == (desc.nv, 0)
+        assert [o.shape for o in rbd.rnea_vjp(m, z, zv, zv, zv)] == [(desc.nq, 0), (desc.nv, 0), (desc.nv, 0)]
         return
     qdd = rbd.fwd_dyn(m, gpu(st.q), gpu(st.qd), gpu(st.tau))
     assert rel_err(host(qdd), O.fwd_dyn(desc, st.q, st.qd, st.tau)) < TOL_QDD
@@ -503,6 +505,38 @@ def test_batch_edges(rbd, B):
     gbar = W.cotangent(desc.nv, B, 214)
     g = [host(x) for x in rbd.fwd_dyn_vjp(m, gpu(st.q), gpu(st.qd), gpu(st.tau), gpu(gbar))]
     assert vjp_err(g, list(O.fwd_dyn_vjp_fd(desc, st.q, st.qd, st.tau, gbar))) < TOL_VJP
+    # the tangent and adjoint of inverse dynamics (tau standing in for an acceleration)
+    jv = host(rbd.rnea_jvp(m, gpu(st.q), gpu(st.qd), gpu(st.tau), *[gpu(x) for x in dx]))
+    assert vjp_err([jv], [O.rnea_jvp_fd(desc, st.q, st.qd, st.tau, *dx)]) < TOL_VJP
+    g = [host(x) for x in rbd.rnea_vjp(m, gpu(st.q), gpu(st.qd), gpu(st.tau), gpu(gbar))]
+    assert vjp_err(g, list(O.rnea_vjp_fd(desc, st.q, st.qd, st.tau, gbar))) < TOL_VJP
+
+
+def test_inverse_dynamics_derivatives_with_leading_dimension_larger_than_batch(rbd):
+    """rbd_rnea_jvp and rbd_rnea_vjp through the C ABI on [rows, ld] arrays with ld > batch: the
+    results match the contiguous call and the padding columns are untouched."""
+    import ctypes as C
+    desc, m = model_of(rbd, "tree12f")
+    B, ld = 300, 448
+    st = W.states(desc, B, 215)
+    rng = np.random.Generator(np.random.PCG64(216))
+    qdd, dqdd, lam = (W._f32(rng.normal(size=st.qd.shape)) for _ in range(3))
+    dq, dqd = W._f32(rng.normal(size=st.q.shape)), W._f32(rng.normal(size=st.qd.shape))
+    ins = [gpu(x, ld) for x in (st.q, st.qd, qdd, dq, dqd, dqdd, lam)]
+    p = [C.c_void_p(x.data_ptr()) for x in ins]
+    outs = [torch.full((r, ld), 7.0, dtype=torch.float32, device="cuda") for r in (desc.nv, desc.nq, desc.nv, desc.nv)]
+    o = [C.c_void_p(x.data_ptr()) for x in outs]
+    s = C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    L = rbd.lib()
+    assert L.rbd_rnea_jvp(m.handle, B, ld, p[0], p[1], p[2], None, p[3], p[4], p[5], None, o[0], s) == 0
+    assert L.rbd_rnea_vjp(m.handle, B, ld, p[0], p[1], p[2], None, p[6], o[1], o[2], o[3], None, s) == 0
+    torch.cuda.synchronize()
+    for x in outs:
+        assert torch.all(x[:, B:] == 7.0)
+    ref_j = rbd.rnea_jvp(m, *[gpu(x) for x in (st.q, st.qd, qdd, dq, dqd, dqdd)])
+    ref_v = rbd.rnea_vjp(m, *[gpu(x) for x in (st.q, st.qd, qdd, lam)])
+    for got, ref in zip(outs, [ref_j, *ref_v]):
+        assert torch.equal(got[:, :B], ref)
 
 
 def test_special_states(rbd):
