@@ -1839,6 +1839,12 @@ RBD_DI void diff_ik_lane(const float* __restrict__ t, const QI& q, const TGT& tg
 // close, so L is never used again and no back substitution is needed. Then a
 // 6x6 solve gives the task wrench z, and J^T z is z applied at E and carried
 // down E's path like a body force.
+// The task space is expressed in E's own frame: the backward sweep carries
+// one transform up E's path, the rotation A_J = R_{E<-J} and the origin o_J of
+// body J in E's frame (A_E = I, o_E = 0; A_P = A_J R_J^T, o_P = o_J - A_P r_J),
+// and J's column is [o_J x z_J; z_J] with z_J = A_J e_z. World poses are then
+// needed only on the way down to E (for the pose error), not held for the
+// backward sweep.
 template <class TP, int E, class QI, class QDI, class TGT, class TO>
 RBD_DI void osc_lane(const float* __restrict__ t, const QI& q, const QDI& qd, const TGT& tgt, float kp, float kd,
                      float kn, const TO& tau) {
@@ -1857,8 +1863,8 @@ RBD_DI void osc_lane(const float* __restrict__ t, const QI& q, const QDI& qd, co
 #pragma unroll
     for (int j = 0; j < 6; ++j) G[i][j] = 0.0f;
   }
-  M3 RwE;
-  V3 pE;
+  M3 At = {{1.0f, 0.0f, 0.0f, 0.0f, 1.0f, 0.0f, 0.0f, 0.0f, 1.0f}};  // A_J of the next path body to close
+  V3 ot = {0.0f, 0.0f, 0.0f};                                         // o_J
   float astar[6];
   const V3 g = load_g<TP>(t);
   const V3 mg = {-g.x, -g.y, -g.z};
@@ -1878,9 +1884,16 @@ RBD_DI void osc_lane(const float* __restrict__ t, const QI& q, const QDI& qd, co
     constexpr int P = TP::parent(J);
     constexpr bool kPath = TP::is_anc(J, E);
     if constexpr (TP::free_body(J)) {
+      // E-frame columns of the base DoFs: [A e_c; 0] (linear), [o x A e_c; A e_c] (angular)
       float cols[6][6];
 #pragma unroll
-      for (int c = 0; c < 6; ++c) base_jcol(Rw[J], pw[J], pE, c, cols[c]);
+      for (int c = 0; c < 3; ++c) {
+        const V3 ax = {At.a[c], At.a[3 + c], At.a[6 + c]};
+        const V3 lin = cross(ot, ax);
+        cols[c][0] = ax.x; cols[c][1] = ax.y; cols[c][2] = ax.z; cols[c][3] = 0.0f; cols[c][4] = 0.0f; cols[c][5] = 0.0f;
+        cols[c + 3][0] = lin.x; cols[c + 3][1] = lin.y; cols[c + 3][2] = lin.z;
+        cols[c + 3][3] = ax.x; cols[c + 3][4] = ax.y; cols[c + 3][5] = ax.z;
+      }
       ltl_base_rows<TP, 7>(F, Ic[J], [&](int r, int K) __attribute__((always_inline)) {
         return r < 6 ? cols[K][r] : -kn * qd(K);
       }, MK{});
@@ -1896,10 +1909,9 @@ RBD_DI void osc_lane(const float* __restrict__ t, const QI& q, const QDI& qd, co
       crba_row<TP, J>(t, R, Ic[J], Mr);
       float bk[7];
       if constexpr (kPath) {
-        float col[6];
-        rev_jcol(Rw[J], pw[J], pE, col);
-#pragma unroll
-        for (int r = 0; r < 6; ++r) bk[r] = col[r];
+        const V3 z = {At.a[2], At.a[5], At.a[8]};
+        const V3 lin = cross(ot, z);
+        bk[0] = lin.x; bk[1] = lin.y; bk[2] = lin.z; bk[3] = z.x; bk[4] = z.y; bk[5] = z.z;
       }
       const float tn = -kn * qd(k);
       bk[6] = tn;
@@ -1914,6 +1926,10 @@ RBD_DI void osc_lane(const float* __restrict__ t, const QI& q, const QDI& qd, co
         const V3 r = load_r<J>(t);
         xfrc_acc(R[J], r, f[J], f[P]);
         xinr_acc(R[J], r, Ic[J], Ic[P]);
+        if constexpr (kPath) {
+          At = mulMMT(At, R[J]);
+          ot = ot - mul(At, r);
+        }
       }
     }
   };
@@ -1944,15 +1960,14 @@ RBD_DI void osc_lane(const float* __restrict__ t, const QI& q, const QDI& qd, co
     }
     if constexpr (TP::is_anc(I, E)) world_pose<TP, I>(t, q, R[I], Rw, pw);
     if constexpr (I == E) {
-      RwE = Rw[E];
-      pE = pw[E];
       float err[6];
-      pose_error<TP, E>(t, RwE, pE, tgt, err);
-      // world twist of E: the body velocity turned into world axes
-      const V3 vl = mul(RwE, v[E].v), vw = mul(RwE, v[E].w);
-      const float tw[6] = {vl.x, vl.y, vl.z, vw.x, vw.y, vw.z};
+      pose_error<TP, E>(t, Rw[E], pw[E], tgt, err);
+      // the world-axes error turned into E's axes; E's twist in its own axes is its body velocity
+      const V3 el = mulT(Rw[E], V3{err[0], err[1], err[2]}), ea = mulT(Rw[E], V3{err[3], err[4], err[5]});
+      const float e6[6] = {el.x, el.y, el.z, ea.x, ea.y, ea.z};
+      const float tw[6] = {v[E].v.x, v[E].v.y, v[E].v.z, v[E].w.x, v[E].w.y, v[E].w.z};
 #pragma unroll
-      for (int i = 0; i < 6; ++i) astar[i] = kp * err[i] - kd * tw[i];
+      for (int i = 0; i < 6; ++i) astar[i] = kp * e6[i] - kd * tw[i];
     }
     const Inr Ib = load_inr<I>(t);
     f[I] = imul(Ib, a[I]) + crf(v[I], imul(Ib, v[I]));
@@ -1965,8 +1980,8 @@ RBD_DI void osc_lane(const float* __restrict__ t, const QI& q, const QDI& qd, co
 #pragma unroll
   for (int i = 0; i < 6; ++i) rhs[i] = astar[i] - c6[i];
   chol6_solve(G, rhs, z);
-  // J^T z: the wrench [z_lin; z_ang] at E's origin, carried down E's path
-  Frc w = {mulT(RwE, V3{z[3], z[4], z[5]}), mulT(RwE, V3{z[0], z[1], z[2]})};
+  // J^T z: the wrench [z_lin; z_ang] at E's origin (E's axes), carried down E's path
+  Frc w = {V3{z[3], z[4], z[5]}, V3{z[0], z[1], z[2]}};
   sfor_rev<0, E + 1>([&](auto K_) __attribute__((always_inline)) {
     constexpr int K = decltype(K_)::value;
     constexpr int P = TP::parent(K);
