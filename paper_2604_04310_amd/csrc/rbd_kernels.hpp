@@ -548,18 +548,28 @@ __global__ __launch_bounds__(kBlock) void k_diff_ik(const float* __restrict__ ta
   diff_ik_lane<TP, E>(tab, In{q, ld, b}, In{tgt, ld, b}, gain, lam2, Out{qd, ld, b});
 }
 
-// Inputs are loaded where they are used: preloading them (as k_fwd_dyn does
-// for large trees) held 83 more registers across a sweep that already spills,
-// and measured 99 us against 81 us for the humanoid at batch 65536.
+// Two sweeps (bias force with the null-space solve, then the task-space
+// solve), the second on fresh views; the torques written by the first are read
+// back by the second, so tau is not restrict-qualified. Inputs are loaded
+// where they are used (preloading them, as k_fwd_dyn does for large trees,
+// held 83 more registers and measured 99 us against 81 us for the humanoid at
+// batch 65536 with the sweeps fused).
 template <class TP, int E = TP::N - 1>
 __global__ __launch_bounds__(kBlock) void k_osc(const float* __restrict__ tab, int64_t batch, int64_t ld,
                                                 const float* __restrict__ q, const float* __restrict__ qd,
                                                 const float* __restrict__ tgt, float kp, float kd, float kn,
-                                                float* __restrict__ tau) {
+                                                float* tau) {
   RBD_LANE_IO(TP);
   const uint32_t b = lane_id();
   if (b >= batch) return;
-  osc_lane<TP, E>(tab, In{q, ld, b}, In{qd, ld, b}, In{tgt, ld, b}, kp, kd, kn, Out{tau, ld, b});
+  float ypath[TP::NV], astar[6];
+  osc_sweep_bias<TP, E>(tab, In{q, ld, b}, In{qd, ld, b}, In{tgt, ld, b}, kp, kd, kn, OutAlias{tau, ld, b}, ypath,
+                        astar);
+  sweep_boundary();
+  // the second sweep on fresh views (see k_fwd_dyn_vjp)
+  const int64_t l2 = opaque(ld);
+  osc_sweep_task<TP, E>(opaque_table(tab), In{opaque(q), l2, b}, ypath, astar, OutAlias{tau, l2, b},
+                        InAlias{tau, l2, b});
 }
 
 // ---- packed launch for the serving runtime. One launch serves many requests

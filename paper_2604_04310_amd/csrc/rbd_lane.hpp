@@ -1832,104 +1832,59 @@ RBD_DI void diff_ik_lane(const float* __restrict__ t, const QI& q, const TGT& tg
 // Operational-space control (Khatib's form, the Jdot qd term omitted):
 //   a* = kp err - kd J qd,  tau_null = -k_null qd,
 //   tau = J^T Lambda (a* - J M^-1 tau_null) + tau_null + h,  Lambda^-1 = J M^-1 J^T.
-// One depth-first sweep as in fwd_dyn_lane (bias force h, world poses, CRBA
-// rows, branch-sparse M = L^T L) runs the first solve for seven right-hand
-// sides: the six rows of J and tau_null. With Y = L^-T J^T and y = L^-T tau_null,
-// Lambda^-1 = Y^T Y and J M^-1 tau_null = Y^T y accumulate as the path's DoFs
-// close, so L is never used again and no back substitution is needed. Then a
-// 6x6 solve gives the task wrench z, and J^T z is z applied at E and carried
-// down E's path like a body force.
-// The task space is expressed in E's own frame: the backward sweep carries
-// one transform up E's path, the rotation A_J = R_{E<-J} and the origin o_J of
+// Two depth-first sweeps over the branch-sparse factor M = L^T L (as in
+// fwd_dyn_lane); L is never used after its sweep, so no back substitution is
+// needed. One sweep carrying all seven right-hand sides holds more than the
+// register file and spills; two sweeps each hold about what forward dynamics
+// holds.
+//   osc_sweep_bias: bias force h and the factor with one right-hand side,
+//     y = L^-T tau_null. It writes h + tau_null for every DoF and returns y on
+//     E's path and a* (pose error and twist of E, in E's axes).
+//   osc_sweep_task: the factor again with the six rows of J as right-hand
+//     sides, Y = L^-T J^T. Lambda^-1 = Y^T Y and J M^-1 tau_null = Y^T y
+//     accumulate as the path's DoFs close; a 6x6 solve gives the task wrench
+//     z, and J^T z (z applied at E and carried down E's path like a body
+//     force) is added to the torques the first sweep wrote.
+// The task space is expressed in E's own frame: the second sweep carries one
+// transform up E's path, the rotation A_J = R_{E<-J} and the origin o_J of
 // body J in E's frame (A_E = I, o_E = 0; A_P = A_J R_J^T, o_P = o_J - A_P r_J),
-// and J's column is [o_J x z_J; z_J] with z_J = A_J e_z. World poses are then
-// needed only on the way down to E (for the pose error), not held for the
-// backward sweep.
+// and J's column is [o_J x z_J; z_J] with z_J = A_J e_z.
 template <class TP, int E, class QI, class QDI, class TGT, class TO>
-RBD_DI void osc_lane(const float* __restrict__ t, const QI& q, const QDI& qd, const TGT& tgt, float kp, float kd,
-                     float kn, const TO& tau) {
+RBD_DI void osc_sweep_bias(const float* __restrict__ t, const QI& q, const QDI& qd, const TGT& tgt, float kp,
+                           float kd, float kn, const TO& tau, float (&ypath)[TP::NV], float (&astar)[6]) {
   constexpr int N = TP::N, NV = TP::NV;
-  using MK = PathRhs<TP, E>;
   M3 R[N], Rw[N];
   V3 pw[N];
   Mot v[N], a[N];
   Frc f[N];
   Inr Ic[N];
-  Ltl<TP, 7> F;
-  float G[6][6], c6[6], hn[NV];
-#pragma unroll
-  for (int i = 0; i < 6; ++i) {
-    c6[i] = 0.0f;
-#pragma unroll
-    for (int j = 0; j < 6; ++j) G[i][j] = 0.0f;
-  }
-  M3 At = {{1.0f, 0.0f, 0.0f, 0.0f, 1.0f, 0.0f, 0.0f, 0.0f, 1.0f}};  // A_J of the next path body to close
-  V3 ot = {0.0f, 0.0f, 0.0f};                                         // o_J
-  float astar[6];
+  Ltl<TP, 1> F;
   const V3 g = load_g<TP>(t);
   const V3 mg = {-g.x, -g.y, -g.z};
-
-  auto accumulate = [&](auto K_) __attribute__((always_inline)) {
-    constexpr int K = decltype(K_)::value;
-#pragma unroll
-    for (int i = 0; i < 6; ++i) {
-      c6[i] = __builtin_fmaf(F.y[i][K], F.y[6][K], c6[i]);
-#pragma unroll
-      for (int j = 0; j <= i; ++j) G[i][j] = __builtin_fmaf(F.y[i][K], F.y[j][K], G[i][j]);
-    }
-  };
 
   auto backward = [&](auto J_) __attribute__((always_inline)) {
     constexpr int J = decltype(J_)::value;
     constexpr int P = TP::parent(J);
-    constexpr bool kPath = TP::is_anc(J, E);
     if constexpr (TP::free_body(J)) {
-      // E-frame columns of the base DoFs: [A e_c; 0] (linear), [o x A e_c; A e_c] (angular)
-      float cols[6][6];
-#pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        const V3 ax = {At.a[c], At.a[3 + c], At.a[6 + c]};
-        const V3 lin = cross(ot, ax);
-        cols[c][0] = ax.x; cols[c][1] = ax.y; cols[c][2] = ax.z; cols[c][3] = 0.0f; cols[c][4] = 0.0f; cols[c][5] = 0.0f;
-        cols[c + 3][0] = lin.x; cols[c + 3][1] = lin.y; cols[c + 3][2] = lin.z;
-        cols[c + 3][3] = ax.x; cols[c + 3][4] = ax.y; cols[c + 3][5] = ax.z;
-      }
-      ltl_base_rows<TP, 7>(F, Ic[J], [&](int r, int K) __attribute__((always_inline)) {
-        return r < 6 ? cols[K][r] : -kn * qd(K);
-      }, MK{});
+      ltl_base_rows<TP, 1>(F, Ic[J], [&](int, int K) __attribute__((always_inline)) { return -kn * qd(K); });
       const float hb[6] = {f[J].f.x, f[J].f.y, f[J].f.z, f[J].n.x, f[J].n.y, f[J].n.z};
       sfor<0, 6>([&](auto K_) __attribute__((always_inline)) {
         constexpr int K = decltype(K_)::value;
-        accumulate(K_);
-        hn[K] = __builtin_fmaf(-kn, qd(K), hb[K]);
+        ypath[K] = F.y[0][K];
+        tau(K, __builtin_fmaf(-kn, qd(K), hb[K]));
       });
     } else {
       constexpr int k = TP::vofs(J);
       float Mr[NV > 1 ? NV : 1];
       crba_row<TP, J>(t, R, Ic[J], Mr);
-      float bk[7];
-      if constexpr (kPath) {
-        const V3 z = {At.a[2], At.a[5], At.a[8]};
-        const V3 lin = cross(ot, z);
-        bk[0] = lin.x; bk[1] = lin.y; bk[2] = lin.z; bk[3] = z.x; bk[4] = z.y; bk[5] = z.z;
-      }
-      const float tn = -kn * qd(k);
-      bk[6] = tn;
-      ltl_row<TP, k, 7, MK>(F, Mr, Ic[J].zz, bk);
-      if constexpr (kPath) {
-        accumulate(ic<k>{});
-        hn[k] = f[J].n.z + tn;
-      } else {
-        tau(k, f[J].n.z + tn);
-      }
+      const float bk[1] = {-kn * qd(k)};
+      ltl_row<TP, k, 1>(F, Mr, Ic[J].zz, bk);
+      if constexpr (TP::is_anc(J, E)) ypath[k] = F.y[0][k];
+      tau(k, f[J].n.z + bk[0]);
       if constexpr (P >= 0) {
         const V3 r = load_r<J>(t);
         xfrc_acc(R[J], r, f[J], f[P]);
         xinr_acc(R[J], r, Ic[J], Ic[P]);
-        if constexpr (kPath) {
-          At = mulMMT(At, R[J]);
-          ot = ot - mul(At, r);
-        }
       }
     }
   };
@@ -1974,6 +1929,84 @@ RBD_DI void osc_lane(const float* __restrict__ t, const QI& q, const QDI& qd, co
     Ic[I] = Ib;
     close_subtrees<TP, I, I>(backward);
   });
+}
+
+// TI reads back what TO wrote in the first sweep.
+template <class TP, int E, class QI, class TO, class TI>
+RBD_DI void osc_sweep_task(const float* __restrict__ t, const QI& q, const float (&ypath)[TP::NV],
+                           const float (&astar)[6], const TO& tau, const TI& tau_in) {
+  constexpr int N = TP::N, NV = TP::NV;
+  using MK = PathRhs<TP, E>;
+  M3 R[N];
+  Inr Ic[N];
+  Ltl<TP, 6> F;
+  float G[6][6], c6[6];
+#pragma unroll
+  for (int i = 0; i < 6; ++i) {
+    c6[i] = 0.0f;
+#pragma unroll
+    for (int j = 0; j < 6; ++j) G[i][j] = 0.0f;
+  }
+  M3 At = {{1.0f, 0.0f, 0.0f, 0.0f, 1.0f, 0.0f, 0.0f, 0.0f, 1.0f}};  // A_J of the next path body to close
+  V3 ot = {0.0f, 0.0f, 0.0f};                                         // o_J
+
+  auto accumulate = [&](auto K_) __attribute__((always_inline)) {
+    constexpr int K = decltype(K_)::value;
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+      c6[i] = __builtin_fmaf(F.y[i][K], ypath[K], c6[i]);
+#pragma unroll
+      for (int j = 0; j <= i; ++j) G[i][j] = __builtin_fmaf(F.y[i][K], F.y[j][K], G[i][j]);
+    }
+  };
+
+  auto backward = [&](auto J_) __attribute__((always_inline)) {
+    constexpr int J = decltype(J_)::value;
+    constexpr int P = TP::parent(J);
+    constexpr bool kPath = TP::is_anc(J, E);
+    if constexpr (TP::free_body(J)) {
+      // E-frame columns of the base DoFs: [A e_c; 0] (linear), [o x A e_c; A e_c] (angular)
+      float cols[6][6];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const V3 ax = {At.a[c], At.a[3 + c], At.a[6 + c]};
+        const V3 lin = cross(ot, ax);
+        cols[c][0] = ax.x; cols[c][1] = ax.y; cols[c][2] = ax.z; cols[c][3] = 0.0f; cols[c][4] = 0.0f; cols[c][5] = 0.0f;
+        cols[c + 3][0] = lin.x; cols[c + 3][1] = lin.y; cols[c + 3][2] = lin.z;
+        cols[c + 3][3] = ax.x; cols[c + 3][4] = ax.y; cols[c + 3][5] = ax.z;
+      }
+      ltl_base_rows<TP, 6>(F, Ic[J], [&](int r, int K) __attribute__((always_inline)) { return cols[K][r]; }, MK{});
+      sfor<0, 6>([&](auto K_) __attribute__((always_inline)) { accumulate(K_); });
+    } else {
+      constexpr int k = TP::vofs(J);
+      float Mr[NV > 1 ? NV : 1];
+      crba_row<TP, J>(t, R, Ic[J], Mr);
+      float bk[6];
+      if constexpr (kPath) {
+        const V3 z = {At.a[2], At.a[5], At.a[8]};
+        const V3 lin = cross(ot, z);
+        bk[0] = lin.x; bk[1] = lin.y; bk[2] = lin.z; bk[3] = z.x; bk[4] = z.y; bk[5] = z.z;
+      }
+      ltl_row<TP, k, 6, MK>(F, Mr, Ic[J].zz, bk);
+      if constexpr (kPath) accumulate(ic<k>{});
+      if constexpr (P >= 0) {
+        const V3 r = load_r<J>(t);
+        xinr_acc(R[J], r, Ic[J], Ic[P]);
+        if constexpr (kPath) {
+          At = mulMMT(At, R[J]);
+          ot = ot - mul(At, r);
+        }
+      }
+    }
+  };
+
+  sfor<0, N>([&](auto I_) __attribute__((always_inline)) {
+    constexpr int I = decltype(I_)::value;
+    if constexpr (TP::free_body(I)) R[I] = quat_rot(q(3), q(4), q(5), q(6));
+    else R[I] = joint_rot<I>(t, q(cidx<TP::qofs(I)>));
+    Ic[I] = load_inr<I>(t);
+    close_subtrees<TP, I, I>(backward);
+  });
 
   // task wrench z = Lambda (a* - J M^-1 tau_null)
   float rhs[6], z[6];
@@ -1989,10 +2022,10 @@ RBD_DI void osc_lane(const float* __restrict__ t, const QI& q, const QDI& qd, co
       if constexpr (TP::free_body(K)) {
         const float wb[6] = {w.f.x, w.f.y, w.f.z, w.n.x, w.n.y, w.n.z};
 #pragma unroll
-        for (int c = 0; c < 6; ++c) tau(c, hn[c] + wb[c]);
+        for (int c = 0; c < 6; ++c) tau(c, tau_in(c) + wb[c]);
       } else {
         constexpr int k = TP::vofs(K);
-        tau(k, hn[k] + w.n.z);
+        tau(k, tau_in(k) + w.n.z);
         if constexpr (P >= 0) w = xfrc(joint_rot<K>(t, q(cidx<TP::qofs(K)>)), load_r<K>(t), w);
       }
     }
