@@ -86,6 +86,19 @@ struct RegView {
   const float* x;
   RBD_DI float operator()(int k) const { return x[k]; }
 };
+// Loads entries 0..n-1 of input views into registers.
+template <int n, class A>
+RBD_DI void preload_inputs(float (&x)[n], const A& a) {
+  sfor<0, n>([&](auto K_) __attribute__((always_inline)) { x[decltype(K_)::value] = a(decltype(K_)::value); });
+}
+template <int n, class A, class B>
+RBD_DI void preload_inputs(float (&x)[n], float (&y)[n], const A& a, const B& b) {
+  sfor<0, n>([&](auto K_) __attribute__((always_inline)) {
+    constexpr int K = decltype(K_)::value;
+    x[K] = a(K);
+    y[K] = b(K);
+  });
+}
 
 template <class TP>
 __global__ __launch_bounds__(kBlock) void k_fk(const float* __restrict__ tab, int64_t batch, int64_t ld,
@@ -394,9 +407,20 @@ __global__ __launch_bounds__(kBlock) void k_fwd_dyn_jvp(const float* __restrict_
     else return x;
   };
   const int64_t ld2 = view(ld);
-  id_tangent_lane<TP>(view_table(tab), In{view(q), ld2, b}, In{view(qd), ld2, b}, InAlias{park, ld2, b},
-                      In{dq, ld2, b}, In{dqd, ld2, b}, In{dtau, ld2, b}, OutAlias{dqdd, ld2, b},
-                      fx_view(fext, ld2), fx_view(dfext, ld2));
+  if constexpr (kFresh && !EXT) {
+    // every input load of the tangent sweep issued at its start, as in k_rnea_jvp
+    constexpr int NQ = TP::NQ, NV = TP::NV;
+    float qv[NQ], qdv[NV], dqv[NQ], dqdv[NV], dtv[NV];
+    preload_inputs<NQ>(qv, dqv, In{view(q), ld2, b}, In{dq, ld2, b});
+    preload_inputs<NV>(qdv, dqdv, In{view(qd), ld2, b}, In{dqd, ld2, b});
+    preload_inputs<NV>(dtv, In{dtau, ld2, b});
+    id_tangent_lane<TP>(view_table(tab), RegView{qv}, RegView{qdv}, InAlias{park, ld2, b}, RegView{dqv},
+                        RegView{dqdv}, RegView{dtv}, OutAlias{dqdd, ld2, b});
+  } else {
+    id_tangent_lane<TP>(view_table(tab), In{view(q), ld2, b}, In{view(qd), ld2, b}, InAlias{park, ld2, b},
+                        In{dq, ld2, b}, In{dqd, ld2, b}, In{dtau, ld2, b}, OutAlias{dqdd, ld2, b},
+                        fx_view(fext, ld2), fx_view(dfext, ld2));
+  }
   const int64_t ld3 = view(ld2);
   fwd_dyn_lane<TP, 1, In, In, RhsOne<InAlias>, SinkOne<OutAlias>, NoFext, false>(
       view_table(tab), In{view(q), ld3, b}, In{qd, ld3, b}, RhsOne<InAlias>{InAlias{dqdd, ld3, b}},
@@ -441,9 +465,20 @@ __global__ __launch_bounds__(2 * kTileLanes) void k_fwd_dyn_jvp_split(
       }
       sweep_boundary();
       const int64_t l2 = opaque(ld);
-      id_tangent_lane<TP>(opaque_table(tab), In{opaque(q), l2, b}, In{opaque(qd), l2, b}, LdsRow::In{qpark},
-                          In{dq, l2, b}, In{dqd, l2, b}, In{dtau, l2, b}, LdsRow{rhs}, fx_view(opaque(fext), l2),
-                          fx_view(opaque(dfext), l2));
+      if constexpr (!EXT) {
+        // every input load of the tangent sweep issued at its start, as in k_rnea_jvp
+        constexpr int NQ = TP::NQ;
+        float qv[NQ], qdv[NV], dqv[NQ], dqdv[NV], dtv[NV];
+        preload_inputs<NQ>(qv, dqv, In{opaque(q), l2, b}, In{dq, l2, b});
+        preload_inputs<NV>(qdv, dqdv, In{opaque(qd), l2, b}, In{dqd, l2, b});
+        preload_inputs<NV>(dtv, In{dtau, l2, b});
+        id_tangent_lane<TP>(opaque_table(tab), RegView{qv}, RegView{qdv}, LdsRow::In{qpark}, RegView{dqv},
+                            RegView{dqdv}, RegView{dtv}, LdsRow{rhs});
+      } else {
+        id_tangent_lane<TP>(opaque_table(tab), In{opaque(q), l2, b}, In{opaque(qd), l2, b}, LdsRow::In{qpark},
+                            In{dq, l2, b}, In{dqd, l2, b}, In{dtau, l2, b}, LdsRow{rhs}, fx_view(opaque(fext), l2),
+                            fx_view(opaque(dfext), l2));
+      }
     }
   } else if (valid) {
     ltl_factor_lane<TP>(tab, In{q, ld, b}, F);
