@@ -102,3 +102,43 @@ def test_packed_static_tree_compiled_at_run_time(env):
     assert srv.wait(t, 120.0) == 0
     compare_with_server(rbd, srv, m, desc, rbd.OP_RNEA, [100, 3, 64], 78)
     compare_with_server(rbd, srv, m, desc, rbd.OP_RNEA, [9], 79)
+
+
+def test_packed_static_in_a_captured_graph(env):
+    """What the entry point is for: captured once into a HIP graph (torch.cuda.graph), then replayed
+    with new inputs copied into the same buffers between replays (eager work and synchronisation in
+    between); every replay equals an eager call on the same inputs, bit for bit."""
+    rbd, descs, models, srv = env
+    m, d = models["humanoid30"], descs["humanoid30"]
+    op = rbd.OP_FWD_DYN_VJP
+    batches = [300, 64, 5]
+    in_rows, out_rows = rbd.op_shapes(m, op)
+    dev = [([torch.empty((B, r), device="cuda") for r in in_rows],
+            [torch.empty((B, r), device="cuda") for r in out_rows]) for B in batches]
+
+    def fill(seed):
+        for k, (B, (di, _)) in enumerate(zip(batches, dev)):
+            for x, h in zip(di, host_inputs(rbd, d, op, B, seed + 10 * k)):
+                x.copy_(torch.from_numpy(h))
+        torch.cuda.synchronize()
+
+    fill(500)
+    rbd.packed_static(m, op, dev)  # eager first: the static table's address is looked up here
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        rbd.packed_static(m, op, dev)
+    for rep in range(3):
+        fill(600 + 100 * rep)
+        g.replay()
+        torch.cuda.synchronize()
+        replayed = [[o.clone() for o in outs] for _, outs in dev]
+        for _, outs in dev:
+            for o in outs:
+                o.fill_(float("nan"))
+        rbd.packed_static(m, op, dev)
+        torch.cuda.synchronize()
+        for got, (_, outs) in zip(replayed, dev):
+            for a, b in zip(got, outs):
+                assert torch.isfinite(b).all()
+                assert torch.equal(a, b)
