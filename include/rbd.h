@@ -421,7 +421,9 @@ rbd_status rbd_diag_serve_load(rbd_server* s, int n_spec, const rbd_load_request
  * through rbd_server_submit first (loading its code allocates), else
  * RBD_E_INVAL. Asynchronous on `stream`; the table is rewritten by every call,
  * so calls that overlap on one GPU (on different streams, or from several
- * threads) race: serialise them. Results equal those of rbd_server_submit. */
+ * threads) race: serialise them. Results equal those of rbd_server_submit.
+ * Pointers are not dereferenced on the host and overlaps are not checked: an
+ * output must not overlap an input or another request's output. */
 typedef struct {
   const float* in[4];  /* device inputs, as for rbd_server_submit  */
   float* out[3];       /* device outputs, as for rbd_server_submit */
