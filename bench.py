@@ -230,7 +230,7 @@ def _kernel_key(short):
     topo = rest.split(",")[0].rstrip(">").strip()
     key = {"k_fwd_dyn": "fwd_dyn", "k_rnea": "rnea_bias", "k_aba": "aba", "k_crba": "crba", "k_fk": "fk",
            "k_jacobian": "jacobian", "k_osc": "osc", "k_diff_ik": "diff_ik", "k_fwd_dyn_vjp": "fwd_dyn_vjp",
-           "k_fwd_dyn_jvp": "fwd_dyn_jvp", "k_fwd_dyn_jvp_split": "fwd_dyn_jvp",
+           "k_fwd_dyn_jvp": "fwd_dyn_jvp", "k_fwd_dyn_jvp_split": "fwd_dyn_jvp", "k_fwd_dyn_vjp_split": "fwd_dyn_vjp",
            "k_rnea_jvp": "rnea_jvp", "k_rnea_vjp": "rnea_vjp"}.get(base)
     return f"{key}_{topo}" if key and topo in ("humanoid30", "chain7") else None
 
@@ -292,7 +292,7 @@ def summarize_profiles(out_dir):
            f"# Calibration on a plain 512 MiB device copy: FETCH_SIZE scale {fscale:.4f}, WRITE_SIZE scale "
            f"{wscale:.4f} (bytes = KiB x 1024 x scale).",
            "# flops_per_eval = SQ_INSTS_VALU_FLOPS_FP32 / SQ_WAVES (FP32 FLOPs of one lane, one instance per lane;",
-           "# twice that for the tangent of the 35-DoF tree, which runs two waves per 64 instances);",
+           "# twice that for the tangent and the adjoint of the 35-DoF tree at batch 32768, which run two waves per 64 instances);",
            "# valu_insts_per_wave = SQ_INSTS_VALU / SQ_WAVES; quad-cycles per wave: wave_cycles, wait_any "
            "(dependency and memory waits), wait_inst_any (issue waits), active_inst_any (issuing).",
            f"source_hash = {kernel_source_hash()}"]
@@ -303,7 +303,7 @@ def summarize_profiles(out_dir):
         c = {k: med(v) for k, v in sq[name].items()}
         w = max(c.get("SQ_WAVES", 0.0), 1.0)
         # waves per 64 instances: two for the tangent split over two waves
-        per = 2.0 if _short_kernel(name, topo).startswith("k_fwd_dyn_jvp_split") else 1.0
+        per = 2.0 if _short_kernel(name, topo).startswith(("k_fwd_dyn_jvp_split", "k_fwd_dyn_vjp_split")) else 1.0
         fb = med(fetch[name]["FETCH_SIZE"]) * 1024.0 * fscale
         wb = med(write[name]["WRITE_SIZE"]) * 1024.0 * wscale
         out.append(f"kernel={key} flops_per_eval={c['SQ_INSTS_VALU_FLOPS_FP32'] * per / w:.0f} "

@@ -140,7 +140,7 @@ const char* rbd_model_topology(const rbd_model* model);
  * time per process). Kernels already in the directory are kept. Needs no GPU.
  * Synchronous. Used to install a robot's kernels before its first use.
  * Errors: RBD_E_INVAL, RBD_E_COMPILE. */
-#define RBD_N_KERNELS 38
+#define RBD_N_KERNELS 40
 rbd_status rbd_precompile_topology(int32_t n_bodies, const int32_t* parent, int floating, const char* cache_dir,
                                    int32_t kernel);
 
@@ -248,7 +248,11 @@ rbd_status rbd_rnea_vjp(const rbd_model* model, int64_t batch, int64_t ld, const
  * kernel: a solve for the forward dynamics and M^-1 g_qdd with one factor,
  * then an adjoint sweep of inverse dynamics; between the two the solutions
  * are kept in LDS (trees of more than 16 DoFs) or in the requested g_qd and
- * g_tau outputs, so the outputs must not overlap one another (RBD_E_INVAL). */
+ * g_tau outputs, so the outputs must not overlap one another (RBD_E_INVAL).
+ * For a tree of more than 16 DoFs at a batch of at most 32768 the two solves
+ * run on two waves per 64 instances, each with its own factor, and meet in
+ * LDS before the adjoint sweep (the environment variable RBD_VJP_SPLIT=0
+ * turns this off, for measurement). */
 rbd_status rbd_fwd_dyn_vjp(const rbd_model* model, int64_t batch, int64_t ld, const float* q, const float* qd,
                            const float* tau, const float* f_ext, const float* g_qdd, float* g_q, float* g_qd,
                            float* g_tau, float* g_f_ext, hipStream_t stream);

@@ -44,7 +44,7 @@ PREBUILT = {
 # way: topology name (compiled or PREBUILT) -> frames.
 PREBUILT_FRAMES = {"humanoid30": [6, 22], "chain7": [3], "quadruped13f": [3]}
 JIT_DIR = os.path.join(PKG, "_jit")
-N_KERNELS = 38  # RBD_N_KERNELS
+N_KERNELS = 40  # RBD_N_KERNELS
 
 
 def _precompile_one(args):

@@ -83,6 +83,17 @@ bool preload_inputs(bool topology_default) {
   return env < 0 ? topology_default : env == 1;
 }
 
+// Whether the adjoint of a large tree at a batch up to half the chip runs on
+// two waves per 64 instances: yes, unless the environment variable
+// RBD_VJP_SPLIT is 0 (for measurement).
+static bool split_adjoint() {
+  static const bool on = [] {
+    const char* e = std::getenv("RBD_VJP_SPLIT");
+    return !(e && std::strcmp(e, "0") == 0);
+  }();
+  return on;
+}
+
 // ------------------------------------------------------------------ launch
 static inline unsigned grid_for(int64_t batch) { return (unsigned)((batch + kBlock - 1) / kBlock); }
 
@@ -284,9 +295,16 @@ rbd_status launch_fwd_dyn_vjp(const rbd_model* m, int64_t batch, int64_t ld, con
   const float* tab = m->d_tab;
   void* a[] = {&tab, &batch, &ld, &q, &qd, &tau, &gqdd, &gq, &gqd, &gtau, &fext, &gfext};
   if (large(m) && (gq || gqd || gfext)) {
-    const Shape sh{dim3((unsigned)((batch + kTileLanes - 1) / kTileLanes)), dim3(kTileLanes),
-                   (unsigned)(2 * m->nv * kTileLanes * sizeof(float))};
-    return launch(m, ext ? KID_VJP_EXT_LDS : KID_VJP_LDS, sh, a, s, "rbd_fwd_dyn_vjp");
+    const unsigned grid = (unsigned)((batch + kTileLanes - 1) / kTileLanes);
+    const unsigned lds = (unsigned)(2 * m->nv * kTileLanes * sizeof(float));
+    if (batch <= kOneWavePerSimd / 2 && split_adjoint()) {
+      // two waves per 64 instances: lam = M^-1 g_qdd on its own wave, in
+      // parallel with the solve for qdd
+      return launch(m, ext ? KID_VJP_EXT_SPLIT : KID_VJP_SPLIT, Shape{dim3(grid), dim3(2 * kTileLanes), lds}, a, s,
+                    "rbd_fwd_dyn_vjp");
+    }
+    return launch(m, ext ? KID_VJP_EXT_LDS : KID_VJP_LDS, Shape{dim3(grid), dim3(kTileLanes), lds}, a, s,
+                  "rbd_fwd_dyn_vjp");
   }
   KernelId id;
   if (ext) id = (gqd && gtau) ? KID_VJP_EXT_PARK : KID_VJP_EXT_REGS;

@@ -47,7 +47,9 @@
   X(KID_RNEA_JVP_EXT, 8, k_rnea_jvp<TP, true>)           \
   X(KID_RNEA_JVP_PRE, 6, k_rnea_jvp<TP, false, true>)    \
   X(KID_RNEA_VJP, 3, k_rnea_vjp<TP>)                      \
-  X(KID_RNEA_VJP_EXT, 8, k_rnea_vjp<TP, true>)
+  X(KID_RNEA_VJP_EXT, 8, k_rnea_vjp<TP, true>)            \
+  X(KID_VJP_SPLIT, 3, k_fwd_dyn_vjp_split<TP>)            \
+  X(KID_VJP_EXT_SPLIT, 8, k_fwd_dyn_vjp_split<TP, true>)
 
 namespace rbd {
 

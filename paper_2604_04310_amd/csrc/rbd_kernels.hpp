@@ -373,6 +373,70 @@ __global__ __launch_bounds__(kBlock) void k_fwd_dyn_vjp(const float* __restrict_
   }
 }
 
+// ---- the adjoint on two waves per 64 instances (a block of 128 lanes), for
+// large trees at batches small enough that one wave per 64 instances leaves
+// SIMDs idle: wave 0 solves for qdd (the fused sweep) while wave 1 factors M
+// on its own and solves lam = M^-1 g_qdd (the bias-free sweep; g_tau = lam).
+// Nothing but qdd and lam crosses the block's one barrier, parked in LDS
+// ([qdd rows | lam rows], 64 lanes each); then wave 0 runs the adjoint sweep
+// on fresh views. Every lane of the block reaches the barrier.
+template <class TP, bool EXT = false>
+__global__ __launch_bounds__(2 * kTileLanes) void k_fwd_dyn_vjp_split(
+    const float* __restrict__ tab, int64_t batch, int64_t ld, const float* __restrict__ q,
+    const float* __restrict__ qd, const float* __restrict__ tau, const float* __restrict__ gqdd, float* gq,
+    float* gqd, float* gtau, const float* __restrict__ fext, float* gfext) {
+  RBD_LANE_IO(TP);
+  constexpr int NQ = TP::NQ, NV = TP::NV;
+  extern __shared__ float lds_vjp[];
+  const uint32_t lane = threadIdx.x % kTileLanes;
+  const bool solver = threadIdx.x >= kTileLanes;
+  const uint32_t b = blockIdx.x * kTileLanes + lane;
+  const bool valid = b < batch;
+  float* const qpark = lds_vjp + lane;
+  float* const lpark = lds_vjp + NV * kTileLanes + lane;
+  auto fx_view = [&](const float* p, int64_t l) __attribute__((always_inline)) {
+    if constexpr (EXT) return FextOpt{{p, l, b}};
+    else return NoFext{};
+  };
+  auto gf_view = [&](int64_t l) __attribute__((always_inline)) {
+    if constexpr (EXT) return GFOut{{gfext, l, b}};
+    else return NoGF{};
+  };
+  if (!solver) {
+    if (valid) {
+      if constexpr (EXT) {
+        fwd_dyn_lane<TP, 1>(tab, In{q, ld, b}, In{qd, ld, b}, RhsOne<In>{In{tau, ld, b}},
+                            SinkOne<LdsRow>{LdsRow{qpark}}, fx_view(fext, ld));
+      } else {
+        // every input load at entry, as in k_fwd_dyn for large trees
+        float qv[NQ], qdv[NV], tv[NV];
+        preload_inputs<NQ>(qv, In{q, ld, b});
+        preload_inputs<NV>(qdv, tv, In{qd, ld, b}, In{tau, ld, b});
+        fwd_dyn_lane<TP, 1>(tab, RegView{qv}, RegView{qdv}, RhsOne<RegView>{RegView{tv}},
+                            SinkOne<LdsRow>{LdsRow{qpark}});
+      }
+    }
+  } else if (valid) {
+    fwd_dyn_lane<TP, 1, In, In, RhsOne<In>, SinkOne<LdsRow>, NoFext, false>(
+        tab, In{q, ld, b}, In{qd, ld, b}, RhsOne<In>{In{gqdd, ld, b}}, SinkOne<LdsRow>{LdsRow{lpark}});
+    if (gtau) {
+      sfor<0, NV>([&](auto K_) __attribute__((always_inline)) {
+        constexpr int K = decltype(K_)::value;
+        Out{gtau, ld, b}(K, lpark[K * kTileLanes]);
+      });
+    }
+  }
+  __syncthreads();
+  if (!solver && valid) {
+    sweep_boundary();
+    const int64_t l2 = opaque(ld);
+    id_adjoint_lane<TP>(opaque_table(tab), In{opaque(q), l2, b}, In{opaque(qd), l2, b}, LdsRow::In{qpark},
+                        LdsRow::In{lpark}, OutOpt<OutAlias>{OutAlias{gq, l2, b}, gq != nullptr},
+                        OutOpt<OutAlias>{OutAlias{gqd, l2, b}, gqd != nullptr}, fx_view(opaque(fext), l2),
+                        gf_view(l2));
+  }
+}
+
 // ---- fwd_dyn tangent, three sweeps of one lane: qdd by the fused solve
 // (parked in the qdd output when one is given, else in dqdd), the tangent of
 // inverse dynamics writing dtau - d(ID) into dqdd, and the solve with M in

@@ -148,7 +148,7 @@ def fma_rate(blocks: int = 256, ilp: int = 16, device: int = 0) -> float:
     return out.value
 
 
-N_KERNELS = 38
+N_KERNELS = 40
 
 
 def precompile_topology(parent, floating: bool, cache_dir: Optional[str] = None, kernel: int = -1) -> None:
