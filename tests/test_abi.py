@@ -244,3 +244,15 @@ def test_plain_c_program_uses_the_boundary(rbd, tmp_path):
     out = subprocess.run([exe], capture_output=True, text=True, timeout=60)
     assert out.returncode == 0, out.stderr
     assert out.stdout.strip() == "c abi ok"
+
+
+def test_kernel_count_is_the_same_everywhere(rbd):
+    """The kernel list (csrc/rbd_kernel_ids.hpp), RBD_N_KERNELS in include/rbd.h, the binding and the
+    build all count the same kernels."""
+    from paper_2604_04310_amd import build as B
+    ids = open(os.path.join(ROOT, "paper_2604_04310_amd", "csrc", "rbd_kernel_ids.hpp")).read()
+    listed = re.findall(r"^\s*X\((KID_\w+),", ids, flags=re.M)
+    assert len(listed) == len(set(listed))
+    header = open(os.path.join(ROOT, "include", "rbd.h")).read()
+    declared = int(re.search(r"#define RBD_N_KERNELS (\d+)", header).group(1))
+    assert len(listed) == declared == rbd.N_KERNELS == B.N_KERNELS
