@@ -256,3 +256,20 @@ def test_kernel_count_is_the_same_everywhere(rbd):
     header = open(os.path.join(ROOT, "include", "rbd.h")).read()
     declared = int(re.search(r"#define RBD_N_KERNELS (\d+)", header).group(1))
     assert len(listed) == declared == rbd.N_KERNELS == B.N_KERNELS
+
+
+def test_packed_static_rejects_host_only_models_and_bad_arguments(rbd):
+    """rbd_packed_static's host-side checks that need no GPU: a null model and a host-only model
+    (device -1) are refused before anything is launched."""
+    L = rbd.lib()
+    s = rbd.desc_struct(W.chain(3))
+    h = C.c_void_p()
+    assert L.rbd_model_create(C.byref(s), -1, C.byref(h)) == 0
+    try:
+        req = (rbd.rbd.PackedRequestC * 1)()
+        assert L.rbd_packed_static(h, 0, 1, req, None) == 1
+        assert b"host-only" in L.rbd_last_error()
+    finally:
+        L.rbd_model_destroy(h)
+    assert L.rbd_packed_static(None, 0, 0, None, None) == 1  # the model is checked first
+    assert b"model is NULL" in L.rbd_last_error()
